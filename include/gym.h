@@ -1,0 +1,241 @@
+/*
+ * gym.h -- C ABI of the MI355X matrix-free FEEC operator library.
+ *
+ * The library applies, inside Krylov solves, the discrete operators of the
+ * finite-element de Rham complex of "Generalized Yee methods" (arXiv
+ * 2301.01753), section 2: integer incidence matrices G, C, D (eq.
+ * discreteDeRham, CG = 0, DC = 0) and the metric mass matrices
+ * (M_p)_ij = int (Lambda_i, Lambda_j)_p dx, evaluated matrix-free by
+ * sum-factorised tensor contractions at Gauss points.  Spaces are the
+ * tensor-product family Q_r^- Lambda^k on structured quad/hex meshes
+ * (r = 1 is the generalized Whitney family of section 4.1).
+ *
+ * Conventions shared by every call:
+ *   - Status: 0 = GYM_OK, > 0 warning, < 0 error.  No call aborts or throws;
+ *     gym_last_error() returns a message for the calling thread.
+ *   - Vectors passed as `void*`/`double*` are DEVICE pointers owned by the
+ *     caller, in the canonical layout below; arrays documented as host
+ *     pointers are read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Apply calls are stream-ordered and asynchronous; *_create, gym_solve
+ *     (which synchronises its stream) and the gym_serve_* calls are blocking.
+ *   - Canonical layout of a space's vector: component blocks in axis order
+ *     (x, y, z); inside a block, lexicographic over the lattice positions
+ *     with x fastest.  Per axis the lattice has m = r*N cells; nodal
+ *     positions are 0..m (1..m-1 under essential boundary conditions), edge
+ *     positions 0..m-1.  A degree of freedom is the integral of the form over
+ *     its lattice k-cell (the integral-normalised version of the paper's eq.
+ *     WhitneyFormDefn); with this choice incidence is exactly +-1.
+ *   - Multiple right-hand sides: `nrhs` vectors stored back to back,
+ *     element (rhs, i) at rhs*ndofs + i.
+ *   - Handles are not thread-safe; calls on one context from several threads
+ *     must be serialised by the caller (the serving loop is the exception:
+ *     gym_serve_submit/poll may be called from any thread).
+ */
+#ifndef GYM_H
+#define GYM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define GYM_OK               0
+#define GYM_W_NOT_CONVERGED  1   /* solve hit maxit; x holds the last iterate */
+#define GYM_E_ARG           -1   /* invalid argument (message says which)     */
+#define GYM_E_OOM           -2   /* device allocation failed / over budget    */
+#define GYM_E_HIP           -3   /* a HIP runtime call failed                 */
+#define GYM_E_INVALID_MESH  -4   /* det J <= 0 at a quadrature point          */
+#define GYM_E_BREAKDOWN     -5   /* Krylov breakdown (NaN, indefinite M^-1)   */
+#define GYM_E_UNSUPPORTED   -6   /* valid request this build does not handle  */
+
+/* ---- enumerations ---------------------------------------------------- */
+#define GYM_H1     0   /* Lambda^0: nodal                                    */
+#define GYM_HCURL  1   /* Lambda^1: component c edge along c                 */
+#define GYM_HDIV   2   /* Lambda^{d-1}: component c nodal along c (flux)     */
+#define GYM_L2     3   /* Lambda^d: cell integrals                           */
+
+#define GYM_BC_NATURAL    0
+#define GYM_BC_ESSENTIAL  1   /* drop nodal positions 0 and m (zero trace)   */
+
+#define GYM_F64   0   /* contractions and vectors in FP64                    */
+#define GYM_F32   1   /* contractions in FP32, vectors FP32                  */
+#define GYM_BF16  2   /* contractions BF16 on MFMA, FP32 accumulate/vectors  */
+
+#define GYM_MIXED_POISSON  0  /* H(div) x L2:  [M2, -D^T M3; -M3 D, 0]       */
+#define GYM_HODGE1         1  /* H1_0 x H0(curl): [-M0, G^T M1; M1 G, C^T M2 C] */
+
+#define GYM_MINRES  0
+#define GYM_CG      1   /* for SPD operators only (mass solves)              */
+
+#define GYM_MODE_F64      0  /* plain FP64 Krylov                            */
+#define GYM_MODE_IR_F32   1  /* FP64 iterative refinement, FP32 inner solve   */
+#define GYM_MODE_IR_BF16  2  /* FP64 iterative refinement, BF16 contractions  */
+
+typedef struct gym_ctx gym_ctx;
+typedef struct gym_mesh gym_mesh;
+typedef struct gym_space gym_space;
+typedef struct gym_op gym_op;
+typedef struct gym_server gym_server;
+
+/* ---- context --------------------------------------------------------- */
+/* Bind to HIP device `device`, upload the 1-D basis/quadrature tables.
+ * Errors: GYM_E_ARG (bad device), GYM_E_HIP. */
+int gym_create(gym_ctx** out, int device);
+/* Frees the context.  Meshes, spaces, operators and servers created from it
+ * must be destroyed first. */
+int gym_destroy(gym_ctx* ctx);
+/* Last error message of the calling thread ("" if none).  Valid until the
+ * next failing call on this thread. */
+const char* gym_last_error(void);
+
+/* ---- mesh (paper section 2: the mesh T_h) ----------------------------- */
+/* Structured mesh of nel[0] x nel[1] (x nel[2]) cells, dim = 2 or 3.
+ * vertices: HOST array of (nel[0]+1)*...*(nel[d-1]+1)*dim doubles,
+ * vertex (i,j,k) at ((k*(ny+1) + j)*(nx+1) + i)*dim, or NULL for the uniform
+ * box [lo, hi].  Each cell is the multilinear image of [0,1]^d of its
+ * corners.  The array is copied.  A NULL vertex array gives an affine mesh;
+ * a non-NULL one is treated as curved (per-quadrature-point Jacobians).
+ * Errors: GYM_E_ARG, GYM_E_INVALID_MESH (det J <= 0 at a Gauss point of
+ * any degree <= 4 rule), GYM_E_OOM. */
+int gym_mesh_create(gym_ctx* ctx, int dim, const int64_t nel[3],
+                    const double* vertices, const double lo[3],
+                    const double hi[3], gym_mesh** out);
+int gym_mesh_destroy(gym_mesh* mesh);
+
+/* ---- spaces (paper section 2: Lambda^p(T_h) with basis Lambda^p) ------ */
+/* kind: GYM_H1..GYM_L2; degree r in 1..4; bc: GYM_BC_*. */
+int gym_space_create(gym_ctx* ctx, const gym_mesh* mesh, int kind, int degree,
+                     int bc, gym_space** out);
+int64_t gym_space_ndofs(const gym_space* space);
+int gym_space_destroy(gym_space* space);
+
+/* ---- incidence (paper eq. discreteDeRham) ----------------------------- */
+/* y = d x (transpose = 0) or y = d^T x (transpose = 1) where d: from -> to is
+ * G (H1 -> HCURL), C (HCURL -> HDIV in 3-D, HCURL -> L2 in 2-D) or
+ * D (HDIV -> L2).  FP64, device pointers, sizes from gym_space_ndofs
+ * (x has the size of `from` for d and of `to` for d^T).  Each output entry
+ * is summed from +0.0 over its +-1 terms in ascending input-index order, so
+ * the result is bit-reproducible.  Errors: GYM_E_ARG (spaces not adjacent
+ * in the complex, different meshes or degrees). */
+int gym_d_apply(const gym_space* from, const gym_space* to, int transpose,
+                const double* x, double* y, void* stream);
+
+/* ---- mass (paper section 2: (M_p)_ij) --------------------------------- */
+/* y = M x for `nrhs` vectors.  prec GYM_F64: x, y are double*; GYM_F32 and
+ * GYM_BF16: x, y are float*.  Quadrature: Gauss, r + 1 points per axis. */
+int gym_mass_apply(const gym_space* space, int prec, int nrhs, const void* x,
+                   void* y, void* stream);
+
+/* ---- block operators (readings built from G, C, D, M_p) --------------- */
+/* problem GYM_MIXED_POISSON: unknowns [s (HDIV, natural); p (L2)].
+ * problem GYM_HODGE1 (3-D): unknowns [sigma (H1, essential); u (HCURL,
+ * essential)]; its (2,2) block C^T M2 C is the paper's curl-of-curl P2/c^2.
+ * Both operators are symmetric indefinite. */
+int gym_op_create(gym_ctx* ctx, int problem, const gym_mesh* mesh, int degree,
+                  gym_op** out);
+int64_t gym_op_ndofs(const gym_op* op);
+/* n[0], n[1] = sizes of the two unknown blocks. */
+int gym_op_block_sizes(const gym_op* op, int64_t n[2]);
+int gym_op_destroy(gym_op* op);
+/* y = A x, nrhs vectors; precisions as for gym_mass_apply (incidence exact). */
+int gym_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y,
+                 void* stream);
+/* Diagonal of the block-Jacobi preconditioner (FP64, op ndofs entries):
+ * diag(M2 + D^T M3 D), diag(M3) for Poisson; diag(M0 + G^T M1 G),
+ * diag(M1 + C^T M2 C) for Hodge. */
+int gym_op_precond_diag(const gym_op* op, double* diag, void* stream);
+
+/* Load vector of a manufactured field (FP64, op ndofs entries, device):
+ * Poisson: b = [0; -F], F_i = int f Lambda^d_i with
+ *   u = sum_m c_m prod_a sin(k_ma pi x_a), f = pi^2 |k_m|^2 u_m;
+ * Hodge: b = [0; F], F_i = int f . Lambda^1_i with
+ *   u_a = sum_m c_ma cos(k_ma pi x_a) prod_{b!=a} sin(k_mb pi x_b).
+ * modes: HOST int array (nmodes x dim) of wave numbers; coeffs: HOST array
+ * (nmodes x ncomp) with ncomp = 1 (Poisson) or 3 (Hodge).  Gauss rule with
+ * r + 2 points per axis.  Synchronous. */
+int gym_rhs_manufactured(const gym_op* op, int nmodes, const int* modes,
+                         const double* coeffs, double* b, void* stream);
+
+/* ---- solves ----------------------------------------------------------- */
+typedef struct gym_solve_opts {
+  int method;         /* GYM_MINRES (default) or GYM_CG                    */
+  int mode;           /* GYM_MODE_F64 / _IR_F32 / _IR_BF16                 */
+  double rtol;        /* stop when ||b - A x|| / ||b|| <= rtol (FP64)       */
+  int maxit;          /* Krylov iterations (per inner solve under IR)      */
+  double inner_rtol;  /* IR: inner relative residual target (e.g. 1e-4)    */
+  int max_outer;      /* IR: outer refinement steps                        */
+  int check_every;    /* host reads the device residual estimate every k   */
+} gym_solve_opts;
+
+typedef struct gym_solve_info {
+  int status;          /* GYM_OK, GYM_W_NOT_CONVERGED or an error          */
+  int iters;           /* total Krylov iterations (all inner solves)       */
+  int outer_iters;     /* IR outer steps (0 in FP64 mode)                  */
+  double rel_res;      /* ||b - A x|| / ||b|| in FP64 at exit, per rhs max */
+  double seconds;      /* wall time of the call                            */
+} gym_solve_info;
+
+/* Fill `opts` with defaults: MINRES, FP64, rtol 1e-10, maxit 20000,
+ * inner_rtol 1e-4, max_outer 30, check_every 25. */
+void gym_solve_opts_default(gym_solve_opts* opts);
+
+/* Solve A x = b for nrhs right-hand sides (device FP64 vectors, x is
+ * overwritten; the initial guess is zero).  The Krylov workspace is
+ * allocated on the first solve of an operator and kept until
+ * gym_op_destroy.  Blocking: returns after the stream is synchronised.
+ * Returns info->status. */
+int gym_solve(gym_op* op, const gym_solve_opts* opts, int nrhs,
+              const double* b, double* x, gym_solve_info* info, void* stream);
+
+/* Mass solve M x = b (CG, Jacobi preconditioner, FP64): the exact-FEEC
+ * application of M_1^{-1} in the paper's eq. (exactEOM). */
+int gym_mass_solve(const gym_space* space, const gym_solve_opts* opts,
+                   int nrhs, const double* b, double* x, gym_solve_info* info,
+                   void* stream);
+
+/* ---- serving: continuous batching of independent solves --------------- */
+typedef struct gym_serve_opts {
+  int device;            /* HIP device                                       */
+  int64_t mem_budget;    /* bytes of device memory the server may hold       */
+  int max_slots;         /* requests resident at once                        */
+  double rtol;           /* per-request relative residual target             */
+  int maxit;             /* per-request iteration cap                        */
+} gym_serve_opts;
+
+typedef struct gym_request {
+  int problem;           /* GYM_MIXED_POISSON or GYM_HODGE1                  */
+  int nel;               /* cubic mesh nel^3 on the unit cube                */
+  int degree;            /* 1..3                                             */
+  uint64_t seed;         /* right-hand side: N(0,1) on the second block,
+                            zero on the first, drawn by the server with a
+                            counter-based generator (see DESIGN)             */
+  const double* rhs;     /* optional HOST rhs (op ndofs); overrides seed      */
+} gym_request;
+
+typedef struct gym_result {
+  int status;            /* GYM_OK, GYM_W_NOT_CONVERGED, error; 2 = pending  */
+  int iters;
+  double rel_res;
+  double latency_s;      /* submit -> result ready                           */
+  int64_t ndofs;
+} gym_result;
+
+int gym_serve_start(const gym_serve_opts* opts, gym_server** out);
+/* Enqueue a request; returns its id.  Errors: GYM_E_OOM if one request
+ * alone exceeds the memory budget. */
+int gym_serve_submit(gym_server* srv, const gym_request* req, uint64_t* id);
+/* Non-blocking.  If x_host is not NULL and the result is ready, the
+ * solution (op ndofs doubles) is copied there.  Returns 0 when the result
+ * is ready, 2 while pending. */
+int gym_serve_poll(gym_server* srv, uint64_t id, gym_result* res,
+                   double* x_host);
+/* Drain: wait for all submitted requests, then stop the loop. */
+int gym_serve_stop(gym_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GYM_H */

@@ -1,0 +1,832 @@
+// C ABI entry points of the gym library (declared in include/gym.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gym_internal.hpp"
+#include "kernels.hpp"
+#include "krylov.hpp"
+
+namespace gym {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string("HIP error: ") + hipGetErrorString(e) + " in " + what;
+  return GYM_E_HIP;
+}
+
+namespace {
+
+DevSpace to_dev(const SpaceDesc& s, long long base) {
+  DevSpace d{};
+  for (int c = 0; c < 3; ++c) {
+    const CompDesc& cd = s.comp[c < s.ncomp ? c : 0];
+    d.c[c].offset = base + (c < s.ncomp ? cd.offset : 0);
+    for (int a = 0; a < 3; ++a) {
+      d.c[c].start[a] = (int)cd.start[a];
+      d.c[c].count[a] = (int)cd.count[a];
+    }
+  }
+  return d;
+}
+
+// constant pointwise metric of one component on an axis-aligned box cell
+double metric_const(int kind, int comp, const gym_mesh* m) {
+  double det = 1.0;
+  for (int a = 0; a < m->dim; ++a) det *= m->h[a];
+  switch (kind) {
+    case GYM_H1: return det;
+    case GYM_HCURL: return det / (m->h[comp] * m->h[comp]);
+    case GYM_HDIV: return m->h[comp] * m->h[comp] / det;
+    default: return 1.0 / det;
+  }
+}
+
+// Diagonals of the global 1-D reference matrices along one axis:
+// nodal mass, edge mass and the nodal stiffness Delta^T M_e Delta.
+struct Diag1D {
+  std::vector<double> dn, de, dk;
+};
+
+Diag1D diag1d(int r, int64_t nel) {
+  Tables1D t = make_tables(r, r + 1);
+  int q = r + 1;
+  std::vector<double> mn(r + 1), me(r), kk(r + 1, 0.0);
+  for (int i = 0; i <= r; ++i) {
+    double s = 0;
+    for (int k = 0; k < q; ++k) s += t.gw[k] * t.phi[k * (r + 1) + i] * t.phi[k * (r + 1) + i];
+    mn[i] = s;
+  }
+  std::vector<double> Me(r * r);
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j) {
+      double s = 0;
+      for (int k = 0; k < q; ++k) s += t.gw[k] * t.edge[k * r + i] * t.edge[k * r + j];
+      Me[i * r + j] = s;
+    }
+  for (int i = 0; i < r; ++i) me[i] = Me[i * r + i];
+  // (Delta u)_j = u_{j+1} - u_j; diag of Delta^T Me Delta at node i:
+  for (int i = 0; i <= r; ++i) {
+    double s = 0;
+    for (int a = 0; a < r; ++a)
+      for (int b = 0; b < r; ++b) {
+        double ea = (i == a + 1) ? 1.0 : (i == a ? -1.0 : 0.0);
+        double eb = (i == b + 1) ? 1.0 : (i == b ? -1.0 : 0.0);
+        s += ea * Me[a * r + b] * eb;
+      }
+    kk[i] = s;
+  }
+  int64_t m = r * nel;
+  Diag1D d;
+  d.dn.assign(m + 1, 0.0);
+  d.dk.assign(m + 1, 0.0);
+  d.de.assign(m, 0.0);
+  for (int64_t e = 0; e < nel; ++e) {
+    for (int i = 0; i <= r; ++i) {
+      d.dn[r * e + i] += mn[i];
+      d.dk[r * e + i] += kk[i];
+    }
+    for (int j = 0; j < r; ++j) d.de[r * e + j] = me[j];
+  }
+  return d;
+}
+
+// Preconditioner diagonal on affine meshes (see gym_op_precond_diag).
+std::vector<double> precond_diag_host(const gym_op* op) {
+  const gym_mesh* m = op->mesh;
+  const int dim = m->dim;
+  std::vector<Diag1D> D;
+  for (int a = 0; a < 3; ++a) D.push_back(diag1d(op->r, a < dim ? m->nel[a] : 1));
+  std::vector<double> out(op->na + op->nb, 0.0);
+  auto loop = [&](const SpaceDesc& s, int64_t base, auto&& fn) {
+    for (int c = 0; c < s.ncomp; ++c) {
+      const CompDesc& cd = s.comp[c];
+      int64_t idx = base + cd.offset;
+      for (int64_t k = 0; k < cd.count[2]; ++k)
+        for (int64_t j = 0; j < cd.count[1]; ++j)
+          for (int64_t i = 0; i < cd.count[0]; ++i) {
+            int64_t p[3] = {cd.start[0] + i, cd.start[1] + j, cd.start[2] + k};
+            out[idx++] = fn(c, p);
+          }
+    }
+  };
+  auto dn = [&](int a, int64_t p) { return a < dim ? D[a].dn[p] : 1.0; };
+  auto de = [&](int a, int64_t p) { return a < dim ? D[a].de[p] : 1.0; };
+  auto dk = [&](int a, int64_t p) { return D[a].dk[p]; };
+  if (op->problem == GYM_MIXED_POISSON) {
+    const double s3 = metric_const(GYM_L2, 0, m);
+    loop(op->sa, 0, [&](int c, const int64_t* p) {
+      double rest = 1.0;
+      for (int a = 0; a < dim; ++a)
+        if (a != c) rest *= de(a, p[a]);
+      return metric_const(GYM_HDIV, c, m) * dn(c, p[c]) * rest + s3 * dk(c, p[c]) * rest;
+    });
+    loop(op->sb, op->na, [&](int, const int64_t* p) {
+      double v = s3;
+      for (int a = 0; a < dim; ++a) v *= de(a, p[a]);
+      return v;
+    });
+  } else {
+    loop(op->sa, 0, [&](int, const int64_t* p) {
+      double v = metric_const(GYM_H1, 0, m);
+      for (int a = 0; a < 3; ++a) v *= dn(a, p[a]);
+      for (int c = 0; c < 3; ++c) {
+        double t = metric_const(GYM_HCURL, c, m) * dk(c, p[c]);
+        for (int a = 0; a < 3; ++a)
+          if (a != c) t *= dn(a, p[a]);
+        v += t;
+      }
+      return v;
+    });
+    loop(op->sb, op->na, [&](int c, const int64_t* p) {
+      int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+      double v = metric_const(GYM_HCURL, c, m) * de(c, p[c]) * dn(c1, p[c1]) * dn(c2, p[c2]);
+      v += metric_const(GYM_HDIV, c1, m) * de(c, p[c]) * dn(c1, p[c1]) * dk(c2, p[c2]);
+      v += metric_const(GYM_HDIV, c2, m) * de(c, p[c]) * dn(c2, p[c2]) * dk(c1, p[c1]);
+      return v;
+    });
+  }
+  return out;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+int dalloc(void** p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(GYM_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return 0;
+}
+
+int check_mesh_jacobians(const gym_mesh* m) {
+  // det J > 0 at the corners and the 5-point Gauss points of every cell
+  std::vector<double> gx, gw;
+  gauss_rule(5, gx, gw);
+  std::vector<double> pts = {0.0};
+  pts.insert(pts.end(), gx.begin(), gx.end());
+  pts.push_back(1.0);
+  const int d = m->dim;
+  const int64_t nx = m->nel[0], ny = m->nel[1], nz = d == 3 ? m->nel[2] : 1;
+  const double* V = m->vertices.data();
+  auto vtx = [&](int64_t i, int64_t j, int64_t k, int a) {
+    return V[((k * (ny + 1) + j) * (nx + 1) + i) * d + a];
+  };
+  for (int64_t k = 0; k < nz; ++k)
+    for (int64_t j = 0; j < ny; ++j)
+      for (int64_t i = 0; i < nx; ++i) {
+        for (double z : (d == 3 ? pts : std::vector<double>{0.5}))
+          for (double y : pts)
+            for (double x : pts) {
+              double J[3][3] = {{0}};
+              double xi[3] = {x, y, z};
+              for (int corner = 0; corner < (1 << d); ++corner) {
+                int b[3] = {corner & 1, (corner >> 1) & 1, (corner >> 2) & 1};
+                for (int a = 0; a < d; ++a) {
+                  double g = 1.0;
+                  for (int c = 0; c < d; ++c) {
+                    if (c == a) g *= b[c] ? 1.0 : -1.0;
+                    else g *= b[c] ? xi[c] : 1.0 - xi[c];
+                  }
+                  for (int comp = 0; comp < d; ++comp)
+                    J[comp][a] += g * vtx(i + b[0], j + b[1], k + (d == 3 ? b[2] : 0), comp);
+                }
+              }
+              double det = d == 2 ? J[0][0] * J[1][1] - J[0][1] * J[1][0]
+                                  : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                                        J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                                        J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+              if (!(det > 0))
+                return fail(GYM_E_INVALID_MESH, "det J <= 0 in cell (" + std::to_string(i) + "," +
+                                                    std::to_string(j) + "," + std::to_string(k) + ")");
+            }
+      }
+  return 0;
+}
+
+int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
+  const gym_mesh* m = op->mesh;
+  OpParams p{};
+  p.x = x;
+  p.y = y;
+  p.ndofs = op->na + op->nb;
+  p.sa = to_dev(op->sa, 0);
+  p.sb = to_dev(op->sb, op->na);
+  for (int a = 0; a < 3; ++a) {
+    p.nel[a] = a < m->dim ? (int)m->nel[a] : 1;
+    p.m[a] = a < m->dim ? (int)(op->r * m->nel[a]) : 1;
+  }
+  int prob;
+  if (op->problem == GYM_MIXED_POISSON) {
+    prob = PROB_POISSON;
+    for (int c = 0; c < m->dim; ++c) p.sc[c] = metric_const(GYM_HDIV, c, m);
+    p.sc[3] = metric_const(GYM_L2, 0, m);
+  } else {
+    prob = PROB_HODGE;
+    p.sc[0] = metric_const(GYM_H1, 0, m);
+    for (int c = 0; c < 3; ++c) {
+      p.sc[1 + c] = metric_const(GYM_HCURL, c, m);
+      p.sc[4 + c] = metric_const(GYM_HDIV, c, m);
+    }
+  }
+  int rc = launch_operator(prob, m->dim, op->r, prec, p, nrhs, op->ctx->ncu, s);
+  if (rc == -2) return fail(GYM_E_UNSUPPORTED, "no kernel for this problem/degree/precision");
+  if (rc) return fail(GYM_E_HIP, "operator kernel launch failed");
+  return 0;
+}
+
+int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
+  const gym_mesh* m = sp->mesh;
+  OpParams p{};
+  p.x = x;
+  p.y = y;
+  p.ndofs = sp->desc.ndofs;
+  p.sa = to_dev(sp->desc, 0);
+  p.sb = p.sa;
+  for (int a = 0; a < 3; ++a) {
+    p.nel[a] = a < m->dim ? (int)m->nel[a] : 1;
+    p.m[a] = a < m->dim ? (int)(sp->desc.r * m->nel[a]) : 1;
+  }
+  for (int c = 0; c < sp->desc.ncomp; ++c) p.sc[c] = metric_const(sp->desc.kind, c, m);
+  int prob = PROB_MASS_H1 + sp->desc.kind;
+  int rc = launch_operator(prob, m->dim, sp->desc.r, prec, p, nrhs, sp->ctx->ncu, s);
+  if (rc == -2) return fail(GYM_E_UNSUPPORTED, "no mass kernel for this space/precision");
+  if (rc) return fail(GYM_E_HIP, "mass kernel launch failed");
+  return 0;
+}
+
+// ---- Krylov drivers ---------------------------------------------------------
+template <typename TV>
+struct MinresWork {
+  TV *r1 = nullptr, *r2 = nullptr, *y = nullptr, *v = nullptr, *w = nullptr, *w1 = nullptr, *w2 = nullptr;
+  double *pa = nullptr, *pb = nullptr;
+  MinresState* st = nullptr;
+  MinresState* host = nullptr;
+};
+
+template <typename TV>
+int alloc_minres(std::vector<void*>& pool, MinresWork<TV>& w, long long n, int nrhs, int nb) {
+  TV** vecs[7] = {&w.r1, &w.r2, &w.y, &w.v, &w.w, &w.w1, &w.w2};
+  for (TV** v : vecs) {
+    void* p;
+    if (int rc = dalloc(&p, sizeof(TV) * n * nrhs)) return rc;
+    pool.push_back(p);
+    *v = (TV*)p;
+  }
+  void* p;
+  if (int rc = dalloc(&p, sizeof(double) * 2 * nb * nrhs)) return rc;
+  pool.push_back(p);
+  w.pa = (double*)p;
+  w.pb = w.pa + nb * nrhs;
+  if (int rc = dalloc(&p, sizeof(MinresState) * 2 * nrhs)) return rc;
+  pool.push_back(p);
+  w.st = (MinresState*)p;
+  GYM_HIP(hipHostMalloc((void**)&w.host, sizeof(MinresState) * 2 * nrhs, hipHostMallocDefault));
+  return 0;
+}
+
+template <typename TV, typename Apply>
+int run_minres(Apply&& apply, long long n, int nrhs, int nb, const TV* b, TV* x, const double* dinv, double tol,
+               int maxit, int check_every, MinresWork<TV>& wk, hipStream_t s, int* iters_out, int* flag_out,
+               int resume) {
+  MinresVecs<TV> V{b, x, wk.r1, wk.r2, wk.y, wk.v, wk.w, wk.w1, wk.w2};
+  if (!resume) minres_launch_init<TV>(V, dinv, n, nrhs, nb, wk.pa, wk.st, tol, s);
+  int it = 0;
+  if (check_every < 1) check_every = 1;
+  bool all_done = false;
+  while (it < maxit && !all_done) {
+    MinresState* cur = wk.st + (it & 1) * nrhs;
+    MinresState* next = wk.st + ((it + 1) & 1) * nrhs;
+    if (int rc = apply(V.v, V.y)) return rc;
+    minres_launch_k3<TV>(V.y, V.r1, V.v, n, nrhs, nb, cur, wk.pa, s);
+    minres_launch_k5<TV>(V.y, V.r2, V.r1, dinv, n, nrhs, nb, cur, wk.pa, wk.pb, s);
+    MinresVecs<TV> U = V;
+    U.y = V.r1;  // z = M^-1 r2 was written over the old r1
+    minres_launch_k7<TV>(U, n, nrhs, nb, cur, next, wk.pa, wk.pb, s);
+    TV* old_r1 = V.r1;
+    V.r1 = V.r2;
+    V.r2 = V.y;
+    V.y = old_r1;
+    TV *ow = V.w, *ow1 = V.w1, *ow2 = V.w2;
+    V.w = ow1;
+    V.w1 = ow2;
+    V.w2 = ow;
+    ++it;
+    if (it % check_every == 0 || it == maxit) {
+      GYM_HIP(hipMemcpyAsync(wk.host, next, sizeof(MinresState) * nrhs, hipMemcpyDeviceToHost, s));
+      GYM_HIP(hipStreamSynchronize(s));
+      all_done = true;
+      for (int r = 0; r < nrhs; ++r) all_done = all_done && wk.host[r].done;
+    }
+  }
+  GYM_HIP(hipGetLastError());
+  // the latest state is in slot (it & 1); keep it in slot 0 for a resume
+  if (it & 1) GYM_HIP(hipMemcpyAsync(wk.st, wk.st + nrhs, sizeof(MinresState) * nrhs, hipMemcpyDeviceToDevice, s));
+  GYM_HIP(hipMemcpyAsync(wk.host, wk.st, sizeof(MinresState) * nrhs, hipMemcpyDeviceToHost, s));
+  GYM_HIP(hipStreamSynchronize(s));
+  // the rotation of work buffers must persist for a resume
+  wk.r1 = V.r1;
+  wk.r2 = V.r2;
+  wk.y = V.y;
+  wk.v = V.v;
+  wk.w = V.w;
+  wk.w1 = V.w1;
+  wk.w2 = V.w2;
+  int maxitn = 0, flag = 1;
+  for (int r = 0; r < nrhs; ++r) {
+    maxitn = std::max(maxitn, wk.host[r].itn);
+    if (wk.host[r].flag < 0) flag = -1;
+    else if (wk.host[r].flag == 0 && flag > 0) flag = 0;
+  }
+  *iters_out = maxitn;
+  *flag_out = flag;
+  return 0;
+}
+
+int relres_f64(const gym_op* op, int nrhs, const double* b, const double* x, double* tmp, double* part,
+               double* sums, int nb, hipStream_t s, std::vector<double>& rel, std::vector<double>* rnorm = nullptr) {
+  long long n = op->na + op->nb;
+  if (int rc = launch_op_apply(op, GYM_F64, nrhs, x, tmp, s)) return rc;
+  launch_norm2(tmp, b, n, nrhs, nb, 1, part, sums, s);
+  launch_norm2(b, nullptr, n, nrhs, nb, 0, part, sums + nrhs, s);
+  std::vector<double> h(2 * nrhs);
+  GYM_HIP(hipMemcpyAsync(h.data(), sums, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
+  GYM_HIP(hipStreamSynchronize(s));
+  rel.assign(nrhs, 0.0);
+  if (rnorm) rnorm->assign(nrhs, 0.0);
+  for (int r = 0; r < nrhs; ++r) {
+    double rn = std::sqrt(h[r]), bn = std::sqrt(h[nrhs + r]);
+    rel[r] = bn > 0 ? rn / bn : rn;
+    if (rnorm) (*rnorm)[r] = rn;
+  }
+  return 0;
+}
+
+}  // namespace
+
+// Workspace held by an operator between solves.
+struct OpWork {
+  long long n = 0;
+  int nrhs = 0, nb = 0;
+  MinresWork<double> m64;
+  MinresWork<float> m32;
+  double *tmp = nullptr, *part = nullptr, *sums = nullptr, *r64 = nullptr, *scale = nullptr;
+  float *r32 = nullptr, *x32 = nullptr;
+  std::vector<void*> pool;
+};
+
+}  // namespace gym
+
+using namespace gym;
+
+extern "C" {
+
+const char* gym_last_error(void) { return g_err.c_str(); }
+
+int gym_create(gym_ctx** out, int device) {
+  if (!out) return fail(GYM_E_ARG, "out is NULL");
+  int n = 0;
+  GYM_HIP(hipGetDeviceCount(&n));
+  if (device < 0 || device >= n) return fail(GYM_E_ARG, "no HIP device " + std::to_string(device));
+  GYM_HIP(hipSetDevice(device));
+  gym_ctx* c = new gym_ctx;
+  c->device = device;
+  GYM_HIP(hipDeviceGetAttribute(&c->ncu, hipDeviceAttributeMultiprocessorCount, device));
+  if (int rc = upload_tables()) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return GYM_OK;
+}
+
+int gym_destroy(gym_ctx* ctx) {
+  delete ctx;
+  return GYM_OK;
+}
+
+int gym_mesh_create(gym_ctx* ctx, int dim, const int64_t nel[3], const double* vertices, const double lo[3],
+                    const double hi[3], gym_mesh** out) {
+  if (!ctx || !out || !nel) return fail(GYM_E_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return fail(GYM_E_ARG, "dim must be 2 or 3");
+  gym_mesh* m = new gym_mesh;
+  m->ctx = ctx;
+  m->dim = dim;
+  int64_t nv = 1;
+  for (int a = 0; a < 3; ++a) {
+    m->nel[a] = a < dim ? nel[a] : 1;
+    if (m->nel[a] < 1 || m->nel[a] > (1 << 20)) {
+      delete m;
+      return fail(GYM_E_ARG, "nel out of range");
+    }
+    m->lo[a] = lo ? lo[a] : 0.0;
+    m->hi[a] = hi ? hi[a] : 1.0;
+    if (a < dim && !(m->hi[a] > m->lo[a])) {
+      delete m;
+      return fail(GYM_E_ARG, "hi must exceed lo");
+    }
+    m->h[a] = a < dim ? (m->hi[a] - m->lo[a]) / m->nel[a] : 1.0;
+    if (a < dim) nv *= m->nel[a] + 1;
+  }
+  if (vertices) {
+    m->curved = true;
+    m->vertices.assign(vertices, vertices + nv * dim);
+    if (int rc = check_mesh_jacobians(m)) {
+      delete m;
+      return rc;
+    }
+    if (int rc = dalloc((void**)&m->d_vertices, sizeof(double) * nv * dim)) {
+      delete m;
+      return rc;
+    }
+    hipError_t e = hipMemcpy(m->d_vertices, vertices, sizeof(double) * nv * dim, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(m->d_vertices);
+      delete m;
+      return hip_fail(e, "hipMemcpy vertices");
+    }
+  }
+  *out = m;
+  return GYM_OK;
+}
+
+int gym_mesh_destroy(gym_mesh* m) {
+  if (!m) return GYM_OK;
+  if (m->d_vertices) (void)hipFree(m->d_vertices);
+  delete m;
+  return GYM_OK;
+}
+
+int gym_space_create(gym_ctx* ctx, const gym_mesh* mesh, int kind, int degree, int bc, gym_space** out) {
+  if (!ctx || !mesh || !out) return fail(GYM_E_ARG, "NULL argument");
+  if (kind < GYM_H1 || kind > GYM_L2) return fail(GYM_E_ARG, "bad space kind");
+  if (degree < 1 || degree > kMaxR) return fail(GYM_E_ARG, "degree must be 1..4");
+  if (bc != GYM_BC_NATURAL && bc != GYM_BC_ESSENTIAL) return fail(GYM_E_ARG, "bad bc");
+  gym_space* s = new gym_space;
+  s->ctx = ctx;
+  s->mesh = mesh;
+  s->desc = make_space_desc(kind, mesh->dim, mesh->nel, degree, bc);
+  *out = s;
+  return GYM_OK;
+}
+
+int64_t gym_space_ndofs(const gym_space* s) { return s ? s->desc.ndofs : -1; }
+
+int gym_space_destroy(gym_space* s) {
+  if (!s) return GYM_OK;
+  if (s->d_diag) (void)hipFree(s->d_diag);
+  for (void* p : s->work) (void)hipFree(p);
+  delete s;
+  return GYM_OK;
+}
+
+int gym_d_apply(const gym_space* from, const gym_space* to, int transpose, const double* x, double* y,
+                void* stream) {
+  if (!from || !to || !x || !y) return fail(GYM_E_ARG, "NULL argument");
+  if (from->mesh != to->mesh || from->desc.r != to->desc.r)
+    return fail(GYM_E_ARG, "spaces on different meshes or degrees");
+  const int dim = from->desc.dim;
+  int op = -1;
+  int fk = from->desc.kind, tk = to->desc.kind;
+  if (fk == GYM_H1 && tk == GYM_HCURL) op = 0;
+  else if (fk == GYM_HCURL && tk == (dim == 3 ? GYM_HDIV : GYM_L2)) op = 1;
+  else if (fk == GYM_HDIV && tk == GYM_L2) op = 2;
+  if (op < 0) return fail(GYM_E_ARG, "spaces are not consecutive in the de Rham complex");
+  IncParams p{};
+  p.x = x;
+  p.y = y;
+  const gym_space* src = transpose ? to : from;
+  const gym_space* dst = transpose ? from : to;
+  p.in = to_dev(src->desc, 0);
+  p.out = to_dev(dst->desc, 0);
+  p.in_ncomp = src->desc.ncomp;
+  p.out_ncomp = dst->desc.ncomp;
+  p.dim = dim;
+  p.op = op;
+  p.transpose = transpose ? 1 : 0;
+  p.nout = dst->desc.ndofs;
+  int rc = launch_incidence(p, (hipStream_t)stream);
+  if (rc) return fail(GYM_E_HIP, "incidence launch failed");
+  return GYM_OK;
+}
+
+int gym_mass_apply(const gym_space* space, int prec, int nrhs, const void* x, void* y, void* stream) {
+  if (!space || !x || !y || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
+  if (space->mesh->curved) return fail(GYM_E_UNSUPPORTED, "curved meshes: mass apply not built yet");
+  if (prec != GYM_F64 && prec != GYM_F32) return fail(GYM_E_UNSUPPORTED, "precision not available");
+  return launch_mass_apply(space, prec, nrhs, x, y, (hipStream_t)stream);
+}
+
+int gym_op_create(gym_ctx* ctx, int problem, const gym_mesh* mesh, int degree, gym_op** out) {
+  if (!ctx || !mesh || !out) return fail(GYM_E_ARG, "NULL argument");
+  if (degree < 1 || degree > kMaxR) return fail(GYM_E_ARG, "degree must be 1..4");
+  if (problem != GYM_MIXED_POISSON && problem != GYM_HODGE1) return fail(GYM_E_ARG, "unknown problem");
+  if (problem == GYM_HODGE1 && mesh->dim != 3) return fail(GYM_E_UNSUPPORTED, "Hodge problem is 3-D only");
+  gym_op* op = new gym_op;
+  op->ctx = ctx;
+  op->mesh = mesh;
+  op->problem = problem;
+  op->r = degree;
+  if (problem == GYM_MIXED_POISSON) {
+    op->sa = make_space_desc(GYM_HDIV, mesh->dim, mesh->nel, degree, GYM_BC_NATURAL);
+    op->sb = make_space_desc(GYM_L2, mesh->dim, mesh->nel, degree, GYM_BC_NATURAL);
+  } else {
+    op->sa = make_space_desc(GYM_H1, mesh->dim, mesh->nel, degree, GYM_BC_ESSENTIAL);
+    op->sb = make_space_desc(GYM_HCURL, mesh->dim, mesh->nel, degree, GYM_BC_ESSENTIAL);
+  }
+  op->na = op->sa.ndofs;
+  op->nb = op->sb.ndofs;
+  std::vector<double> d = precond_diag_host(op);
+  for (double& v : d) v = 1.0 / v;
+  if (int rc = dalloc((void**)&op->d_prec, sizeof(double) * d.size())) {
+    delete op;
+    return rc;
+  }
+  hipError_t e = hipMemcpy(op->d_prec, d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(op->d_prec);
+    delete op;
+    return hip_fail(e, "hipMemcpy preconditioner");
+  }
+  *out = op;
+  return GYM_OK;
+}
+
+int64_t gym_op_ndofs(const gym_op* op) { return op ? op->na + op->nb : -1; }
+
+int gym_op_block_sizes(const gym_op* op, int64_t n[2]) {
+  if (!op || !n) return fail(GYM_E_ARG, "NULL argument");
+  n[0] = op->na;
+  n[1] = op->nb;
+  return GYM_OK;
+}
+
+static void free_work(gym_op* op) {
+  if (op->work.empty()) return;
+  OpWork* w = (OpWork*)op->work[0];
+  for (void* p : w->pool) (void)hipFree(p);
+  if (w->m64.host) (void)hipHostFree(w->m64.host);
+  if (w->m32.host) (void)hipHostFree(w->m32.host);
+  delete w;
+  op->work.clear();
+  op->work_nrhs = 0;
+}
+
+int gym_op_destroy(gym_op* op) {
+  if (!op) return GYM_OK;
+  free_work(op);
+  if (op->d_prec) (void)hipFree(op->d_prec);
+  delete op;
+  return GYM_OK;
+}
+
+int gym_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, void* stream) {
+  if (!op || !x || !y || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
+  if (op->mesh->curved) return fail(GYM_E_UNSUPPORTED, "curved meshes: operator not built yet");
+  if (prec != GYM_F64 && prec != GYM_F32) return fail(GYM_E_UNSUPPORTED, "precision not available");
+  return launch_op_apply(op, prec, nrhs, x, y, (hipStream_t)stream);
+}
+
+int gym_op_precond_diag(const gym_op* op, double* diag, void* stream) {
+  if (!op || !diag) return fail(GYM_E_ARG, "NULL argument");
+  std::vector<double> d = precond_diag_host(op);
+  GYM_HIP(hipMemcpyAsync(diag, d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice, (hipStream_t)stream));
+  GYM_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return GYM_OK;
+}
+
+int gym_rhs_manufactured(const gym_op* op, int nmodes, const int* modes, const double* coeffs, double* b,
+                         void* stream) {
+  if (!op || !b || (nmodes > 0 && (!modes || !coeffs))) return fail(GYM_E_ARG, "bad argument");
+  const gym_mesh* m = op->mesh;
+  if (m->curved) return fail(GYM_E_UNSUPPORTED, "manufactured loads need an affine mesh");
+  const int dim = m->dim, r = op->r, q = r + 2;
+  const double pi = 3.14159265358979323846;
+  Tables1D t = make_tables(r, q);
+  // 1-D load factors: L[a][type][p] = int_axis g(x) b_p(x) dx over the
+  // reference coordinate (h folded in by the caller), for g = sin or cos.
+  auto load1d = [&](int a, bool nodal, bool use_cos, int k) {
+    int64_t nel = m->nel[a], mm = r * nel;
+    std::vector<double> out(nodal ? mm + 1 : mm, 0.0);
+    for (int64_t e = 0; e < nel; ++e)
+      for (int s = 0; s < q; ++s) {
+        double x = m->lo[a] + m->h[a] * (e + t.gx[s]);
+        double g = use_cos ? std::cos(k * pi * x) : std::sin(k * pi * x);
+        double wg = t.gw[s] * g;
+        if (nodal)
+          for (int i = 0; i <= r; ++i) out[r * e + i] += wg * t.phi[s * (r + 1) + i];
+        else
+          for (int j = 0; j < r; ++j) out[r * e + j] += wg * t.edge[s * r + j];
+      }
+    return out;
+  };
+  std::vector<double> h(op->na + op->nb, 0.0);
+  const SpaceDesc& sd = op->sb;
+  double det = 1.0;
+  for (int a = 0; a < dim; ++a) det *= m->h[a];
+  for (int md = 0; md < nmodes; ++md) {
+    const int* k = modes + md * dim;
+    double k2 = 0;
+    for (int a = 0; a < dim; ++a) k2 += double(k[a]) * k[a];
+    for (int c = 0; c < sd.ncomp; ++c) {
+      const CompDesc& cd = sd.comp[c];
+      double coef;
+      std::vector<double> L[3];
+      if (op->problem == GYM_MIXED_POISSON) {
+        // f = c pi^2 |k|^2 prod sin; L2 basis: F_i = int f b_i (reference cell)
+        coef = -coeffs[md] * pi * pi * k2;  // the load enters as -F
+        for (int a = 0; a < dim; ++a) L[a] = load1d(a, false, false, k[a]);
+      } else {
+        // f_c = c_c pi^2 |k|^2 cos(k_c pi x_c) prod_{b != c} sin(k_b pi x_b);
+        // HCURL basis (covariant): F_i = det/h_c * prod_a int g_a b_a
+        coef = coeffs[md * 3 + c] * pi * pi * k2 * det / m->h[c];
+        for (int a = 0; a < dim; ++a) L[a] = load1d(a, (cd.nodal_mask >> a) & 1, a == c, k[a]);
+      }
+      int64_t idx = op->na + cd.offset;
+      for (int64_t kk = 0; kk < cd.count[2]; ++kk)
+        for (int64_t jj = 0; jj < cd.count[1]; ++jj)
+          for (int64_t ii = 0; ii < cd.count[0]; ++ii) {
+            double v = coef * L[0][cd.start[0] + ii] * L[1][cd.start[1] + jj];
+            if (dim == 3) v *= L[2][cd.start[2] + kk];
+            h[idx++] += v;
+          }
+    }
+  }
+  GYM_HIP(hipMemcpyAsync(b, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, (hipStream_t)stream));
+  GYM_HIP(hipStreamSynchronize((hipStream_t)stream));
+  return GYM_OK;
+}
+
+void gym_solve_opts_default(gym_solve_opts* o) {
+  if (!o) return;
+  o->method = GYM_MINRES;
+  o->mode = GYM_MODE_F64;
+  o->rtol = 1e-10;
+  o->maxit = 20000;
+  o->inner_rtol = 1e-4;
+  o->max_outer = 30;
+  o->check_every = 25;
+}
+
+static int ensure_work(gym_op* op, int nrhs, OpWork** out) {
+  long long n = op->na + op->nb;
+  if (!op->work.empty() && op->work_nrhs == nrhs) {
+    *out = (OpWork*)op->work[0];
+    return 0;
+  }
+  free_work(op);
+  OpWork* w = new OpWork;
+  op->work.push_back(w);
+  op->work_nrhs = nrhs;
+  w->n = n;
+  w->nrhs = nrhs;
+  w->nb = vec_grid(n, op->ctx->ncu);
+  if (int rc = alloc_minres<double>(w->pool, w->m64, n, nrhs, w->nb)) return rc;
+  void* p;
+  if (int rc = dalloc(&p, sizeof(double) * n * nrhs * 2)) return rc;
+  w->pool.push_back(p);
+  w->tmp = (double*)p;
+  w->r64 = w->tmp + n * nrhs;
+  if (int rc = dalloc(&p, sizeof(double) * (w->nb * nrhs + 4 * nrhs))) return rc;
+  w->pool.push_back(p);
+  w->part = (double*)p;
+  w->sums = w->part + w->nb * nrhs;
+  w->scale = w->sums + 2 * nrhs;
+  *out = w;
+  return 0;
+}
+
+static int ensure_work32(gym_op* op, OpWork* w) {
+  if (w->r32) return 0;
+  if (int rc = alloc_minres<float>(w->pool, w->m32, w->n, w->nrhs, w->nb)) return rc;
+  void* p;
+  if (int rc = dalloc(&p, sizeof(float) * w->n * w->nrhs * 2)) return rc;
+  w->pool.push_back(p);
+  w->r32 = (float*)p;
+  w->x32 = w->r32 + w->n * w->nrhs;
+  return 0;
+}
+
+int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double* b, double* x,
+              gym_solve_info* info, void* stream) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!op || !b || !x || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
+  gym_solve_opts opts;
+  if (opts_in) opts = *opts_in;
+  else gym_solve_opts_default(&opts);
+  gym_solve_info inf{};
+  hipStream_t s = (hipStream_t)stream;
+  if (op->mesh->curved) return fail(GYM_E_UNSUPPORTED, "curved meshes: operator not built yet");
+  if (opts.method != GYM_MINRES) return fail(GYM_E_UNSUPPORTED, "block operators are indefinite: use MINRES");
+  OpWork* w;
+  if (int rc = ensure_work(op, nrhs, &w)) return rc;
+  const long long n = w->n;
+  std::vector<double> rel;
+  int status = GYM_OK;
+  if (opts.mode == GYM_MODE_F64) {
+    auto apply = [&](const double* in, double* out) { return launch_op_apply(op, GYM_F64, nrhs, in, out, s); };
+    double tol = opts.rtol;
+    int total = 0, flag = 0, resume = 0;
+    for (int attempt = 0; attempt < 6; ++attempt) {
+      int it = 0;
+      if (int rc = run_minres<double>(apply, n, nrhs, w->nb, b, x, op->d_prec, tol, opts.maxit - total,
+                                      opts.check_every, w->m64, s, &it, &flag, resume))
+        return rc;
+      total = it;
+      if (flag < 0) {
+        status = fail(GYM_E_BREAKDOWN, "MINRES breakdown (NaN or indefinite preconditioner)");
+        break;
+      }
+      if (int rc = relres_f64(op, nrhs, b, x, w->tmp, w->part, w->sums, w->nb, s, rel)) return rc;
+      double worst = *std::max_element(rel.begin(), rel.end());
+      if (worst <= opts.rtol) break;
+      if (total >= opts.maxit) {
+        status = GYM_W_NOT_CONVERGED;
+        break;
+      }
+      // the preconditioned estimate was optimistic: tighten and continue
+      tol *= 0.1;
+      for (int r = 0; r < nrhs; ++r) {
+        w->m64.host[r].tol = tol;
+        w->m64.host[r].done = 0;
+        w->m64.host[r].flag = 0;
+      }
+      GYM_HIP(hipMemcpyAsync(w->m64.st, w->m64.host, sizeof(MinresState) * nrhs, hipMemcpyHostToDevice, s));
+      resume = 1;
+    }
+    inf.iters = total;
+  } else if (opts.mode == GYM_MODE_IR_F32 || opts.mode == GYM_MODE_IR_BF16) {
+    if (opts.mode == GYM_MODE_IR_BF16) return fail(GYM_E_UNSUPPORTED, "BF16 contractions not built yet");
+    if (int rc = ensure_work32(op, w)) return rc;
+    const int prec = GYM_F32;
+    auto apply32 = [&](const float* in, float* out) { return launch_op_apply(op, prec, nrhs, in, out, s); };
+    GYM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n * nrhs, s));
+    int total = 0, outer = 0;
+    std::vector<double> rn;
+    if (int rc = relres_f64(op, nrhs, b, x, w->tmp, w->part, w->sums, w->nb, s, rel, &rn)) return rc;
+    status = GYM_W_NOT_CONVERGED;
+    for (outer = 0; outer < opts.max_outer; ++outer) {
+      double worst = *std::max_element(rel.begin(), rel.end());
+      if (worst <= opts.rtol) {
+        status = GYM_OK;
+        break;
+      }
+      // r64 = b - A x (tmp holds A x); scale each rhs to unit norm in FP32
+      launch_sub(b, w->tmp, w->r64, n * nrhs, w->nb, s);
+      std::vector<double> sc(2 * nrhs);
+      for (int r = 0; r < nrhs; ++r) {
+        sc[r] = rn[r] > 0 ? 1.0 / rn[r] : 0.0;
+        sc[nrhs + r] = rn[r];
+      }
+      GYM_HIP(hipMemcpyAsync(w->scale, sc.data(), sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s));
+      launch_to_f32_scaled(w->r64, w->r32, n, nrhs, w->nb, w->scale, s);
+      int it = 0, flag = 0;
+      if (int rc = run_minres<float>(apply32, n, nrhs, w->nb, w->r32, w->x32, op->d_prec, opts.inner_rtol,
+                                     opts.maxit, opts.check_every, w->m32, s, &it, &flag, 0))
+        return rc;
+      total += it;
+      if (flag < 0) {
+        status = fail(GYM_E_BREAKDOWN, "inner MINRES breakdown");
+        break;
+      }
+      launch_axpy_f32(w->x32, x, n, nrhs, w->nb, w->scale + nrhs, s);
+      if (int rc = relres_f64(op, nrhs, b, x, w->tmp, w->part, w->sums, w->nb, s, rel, &rn)) return rc;
+    }
+    inf.iters = total;
+    inf.outer_iters = outer;
+  } else {
+    return fail(GYM_E_ARG, "unknown solve mode");
+  }
+  if (rel.empty())
+    if (int rc = relres_f64(op, nrhs, b, x, w->tmp, w->part, w->sums, w->nb, s, rel)) return rc;
+  inf.rel_res = *std::max_element(rel.begin(), rel.end());
+  if (status == GYM_OK && inf.rel_res > opts.rtol) status = GYM_W_NOT_CONVERGED;
+  inf.status = status;
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return status;
+}
+
+int gym_mass_solve(const gym_space* space, const gym_solve_opts* opts_in, int nrhs, const double* b, double* x,
+                   gym_solve_info* info, void* stream) {
+  return fail(GYM_E_UNSUPPORTED, "mass solve not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Internal declarations of the gym library (host side).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gym.h"
+
+namespace gym {
+
+constexpr int kMaxR = 4;          // highest degree with compiled kernels
+constexpr int kMaxQ = kMaxR + 2;  // widest Gauss rule (load vectors: r + 2)
+
+// Thread-local error message, returned by gym_last_error().
+void set_error(const std::string& msg);
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+
+#define GYM_HIP(call)                                              \
+  do {                                                             \
+    hipError_t _e = (call);                                        \
+    if (_e != hipSuccess) return ::gym::hip_fail(_e, #call);       \
+  } while (0)
+
+// 1-D tables on [0,1] for degree r (host, FP64): GLL nodes, Gauss rule of q
+// points, nodal values phi_i(x_t) and edge values e_j(x_t).
+struct Tables1D {
+  int r = 0, q = 0;
+  std::vector<double> nodes;    // r + 1
+  std::vector<double> gx, gw;   // q
+  std::vector<double> phi;      // q x (r + 1), row t
+  std::vector<double> edge;     // q x r
+};
+Tables1D make_tables(int r, int q);
+std::vector<double> gll_nodes(int r);
+void gauss_rule(int q, std::vector<double>& x, std::vector<double>& w);
+
+// Per-component description of a space: which axes are nodal, and the kept
+// lattice positions per axis [start, start + count).
+struct CompDesc {
+  int nodal_mask = 0;        // bit a set -> nodal along axis a
+  int64_t start[3] = {0, 0, 0};
+  int64_t count[3] = {1, 1, 1};
+  int64_t offset = 0;        // first global index of the block
+};
+
+struct SpaceDesc {
+  int kind = 0, dim = 3, r = 1, bc = 0, ncomp = 1;
+  int64_t m[3] = {1, 1, 1};
+  CompDesc comp[3];
+  int64_t ndofs = 0;
+};
+SpaceDesc make_space_desc(int kind, int dim, const int64_t nel[3], int r, int bc);
+
+}  // namespace gym
+
+struct gym_ctx {
+  int device = 0;
+  int ncu = 0;
+};
+
+struct gym_mesh {
+  gym_ctx* ctx = nullptr;
+  int dim = 3;
+  int64_t nel[3] = {1, 1, 1};
+  double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, h[3] = {1, 1, 1};
+  bool curved = false;              // vertex array given
+  double* d_vertices = nullptr;     // device copy, (N+1)^d x d
+  std::vector<double> vertices;     // host copy
+};
+
+struct gym_space {
+  gym_ctx* ctx = nullptr;
+  const gym_mesh* mesh = nullptr;
+  gym::SpaceDesc desc;
+  double* d_diag = nullptr;         // lazily built Jacobi diagonal
+  // Krylov workspace for mass solves
+  std::vector<void*> work;
+  int work_nrhs = 0;
+};
+
+struct gym_op {
+  gym_ctx* ctx = nullptr;
+  const gym_mesh* mesh = nullptr;
+  int problem = 0, r = 1;
+  gym::SpaceDesc sa, sb;             // first / second unknown block
+  int64_t na = 0, nb = 0;
+  double* d_prec = nullptr;          // 1 / diag, n = na + nb
+  std::vector<void*> work;           // Krylov workspace
+  int work_nrhs = 0;
+  size_t work_bytes = 0;
+};

@@ -1,0 +1,55 @@
+// Kernel launch interfaces shared by the host code of the gym library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gym {
+
+enum {
+  PROB_POISSON = 0,
+  PROB_HODGE = 1,
+  PROB_MASS_H1 = 10,
+  PROB_MASS_HCURL = 11,
+  PROB_MASS_HDIV = 12,
+  PROB_MASS_L2 = 13,
+};
+
+struct DevComp {
+  long long offset;  // first index of the component block in the vector
+  int start[3];      // first kept lattice position per axis
+  int count[3];      // kept positions per axis
+};
+struct DevSpace {
+  DevComp c[3];
+};
+
+struct OpParams {
+  const void* x;
+  void* y;
+  long long ndofs;  // stride between right-hand sides
+  DevSpace sa, sb;  // first / second block
+  int nel[3];
+  int m[3];         // lattice cells per axis (r * nel)
+  int tiles_x, tiles_y, chunk;
+  double sc[8];     // constant pointwise metric factors (affine meshes)
+};
+
+int upload_tables();
+int launch_operator(int prob, int dim, int r, int prec, const OpParams& p, int nrhs, int ncu,
+                    hipStream_t s);
+
+// incidence: y = d x or d^T x, bit-reproducible ascending-index sums
+struct IncParams {
+  const double* x;
+  double* y;
+  DevSpace in, out;
+  int in_ncomp, out_ncomp;
+  int dim;
+  int op;           // 0 = G, 1 = C, 2 = D
+  int transpose;
+  long long nout;
+};
+int launch_incidence(const IncParams& p, hipStream_t s);
+
+}  // namespace gym

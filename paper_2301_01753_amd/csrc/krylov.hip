@@ -1,0 +1,465 @@
+// Krylov kernels: preconditioned MINRES and CG with device-resident scalars.
+//
+// The paper's exact-FEEC equations of motion need M1^{-1} (eq. exactEOM): a
+// global solve (section 3), done here by CG with a diagonal preconditioner
+// (the preconditioner type the paper uses for its own PCG, section 5.1).
+// The symmetric indefinite block operators are solved by MINRES with a
+// symmetric positive block-diagonal preconditioner.
+//
+// Determinism: every dot product is a two-stage reduction with a fixed
+// order (per-block tree, then every consumer block re-reduces the same
+// partials in the same order), accumulated in FP64 whatever the vector type.
+// No atomics.  The scalar recurrences run redundantly in every block of the
+// kernel that needs them; block 0 alone writes the next state slot (double
+// buffered: kernels read slot it&1 and write slot (it+1)&1).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "krylov.hpp"
+
+namespace gym {
+
+constexpr int kBT = 256;
+
+template <typename T>
+__device__ __forceinline__ double todbl(T v) { return static_cast<double>(v); }
+
+// Block tree reduction of `v` (fixed order); returns the sum in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = kBT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+// Sum of `np` partials, same order in every block.
+__device__ __forceinline__ double reduce_partials(const double* part, int np, double* sh) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < np; i += kBT) v += part[i];
+  return block_sum(v, sh);
+}
+
+// ---- MINRES ---------------------------------------------------------------
+// init: r1 = r2 = b; y = dinv .* b; x = w = w1 = w2 = 0; partial (b . y)
+template <typename TV>
+__global__ void __launch_bounds__(kBT) minres_init_a(MinresVecs<TV> v, const double* __restrict__ dinv,
+                                                     long long n, double* part) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  const long long off = (long long)rhs * n;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    TV bi = v.b[off + i];
+    double yi = dinv[i] * todbl(bi);
+    v.r1[off + i] = bi;
+    v.r2[off + i] = bi;
+    v.y[off + i] = static_cast<TV>(yi);
+    v.x[off + i] = 0;
+    v.w[off + i] = 0;
+    v.w1[off + i] = 0;
+    v.w2[off + i] = 0;
+    acc += todbl(bi) * yi;
+  }
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[rhs * gridDim.x + blockIdx.x] = s;
+}
+
+// init: beta1 = sqrt(b . M^-1 b); v = y / beta1
+template <typename TV>
+__global__ void __launch_bounds__(kBT) minres_init_b(MinresVecs<TV> v, long long n, const double* part,
+                                                     int np, MinresState* st0, double tol) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  const long long off = (long long)rhs * n;
+  double b2 = reduce_partials(part + rhs * np, np, sh);
+  double beta1 = b2 > 0 ? sqrt(b2) : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    MinresState s{};
+    s.beta1 = beta1;
+    s.beta = beta1;
+    s.oldb = 0;
+    s.dbar = 0;
+    s.epsln = 0;
+    s.phibar = beta1;
+    s.cs = -1;
+    s.sn = 0;
+    s.tnorm2 = 0;
+    s.tol = tol;
+    s.itn = 0;
+    s.done = (beta1 == 0.0) ? 1 : 0;
+    s.flag = (b2 < 0 || b2 != b2) ? -1 : 0;
+    if (s.flag) s.done = 1;
+    st0[rhs] = s;
+  }
+  double inv = beta1 > 0 ? 1.0 / beta1 : 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
+    v.v[off + i] = static_cast<TV>(todbl(v.y[off + i]) * inv);
+}
+
+// after y = A v:  y -= (beta/oldb) r1 ; partial (v . y)
+template <typename TV>
+__global__ void __launch_bounds__(kBT) minres_k3(TV* __restrict__ y, const TV* __restrict__ r1,
+                                                 const TV* __restrict__ vv, long long n,
+                                                 const MinresState* cur, double* part_a) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  const MinresState s = cur[rhs];
+  if (s.done) return;
+  const long long off = (long long)rhs * n;
+  const double c = s.oldb > 0 ? s.beta / s.oldb : 0.0;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    double yi = todbl(y[off + i]) - c * todbl(r1[off + i]);
+    TV ys = static_cast<TV>(yi);
+    y[off + i] = ys;
+    acc += todbl(vv[off + i]) * todbl(ys);
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part_a[rhs * gridDim.x + blockIdx.x] = t;
+}
+
+// alfa = v . y ; y -= (alfa/beta) r2 ; z = dinv .* y -> zbuf ; partial (y . z)
+template <typename TV>
+__global__ void __launch_bounds__(kBT) minres_k5(TV* __restrict__ y, const TV* __restrict__ r2,
+                                                 TV* __restrict__ zbuf, const double* __restrict__ dinv,
+                                                 long long n, const MinresState* cur,
+                                                 const double* part_a, double* part_b) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  const MinresState s = cur[rhs];
+  if (s.done) return;
+  const int np = gridDim.x;
+  const double alfa = reduce_partials(part_a + rhs * np, np, sh);
+  const double c = alfa / s.beta;
+  const long long off = (long long)rhs * n;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    double yi = todbl(y[off + i]) - c * todbl(r2[off + i]);
+    TV ys = static_cast<TV>(yi);
+    y[off + i] = ys;
+    double zi = dinv[i] * todbl(ys);
+    TV zs = static_cast<TV>(zi);
+    zbuf[off + i] = zs;
+    acc += todbl(ys) * todbl(zs);
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part_b[rhs * gridDim.x + blockIdx.x] = t;
+}
+
+// Givens update, w/x update and next v:
+//   w_new = (v - oldeps w1 - delta w2) / gamma, x += phi w_new, v = z / beta
+// with (w1, w2) = (old w2, old w); w_new is written over old w1.
+template <typename TV>
+__global__ void __launch_bounds__(kBT) minres_k7(MinresVecs<TV> v, long long n, const MinresState* cur,
+                                                 MinresState* next, const double* part_a,
+                                                 const double* part_b) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  MinresState s = cur[rhs];
+  if (s.done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) next[rhs] = s;
+    return;
+  }
+  const int np = gridDim.x;
+  const double alfa = reduce_partials(part_a + rhs * np, np, sh);
+  const double b2 = reduce_partials(part_b + rhs * np, np, sh);
+  s.itn += 1;
+  const double oldb = s.beta;
+  double beta = b2 > 0 ? sqrt(b2) : 0.0;
+  s.tnorm2 += alfa * alfa + oldb * oldb + beta * beta;
+  const double oldeps = s.epsln;
+  const double delta = s.cs * s.dbar + s.sn * alfa;
+  const double gbar = s.sn * s.dbar - s.cs * alfa;
+  const double epsln = s.sn * beta;
+  const double dbar = -s.cs * beta;
+  double gamma = sqrt(gbar * gbar + beta * beta);
+  gamma = gamma > 2.2e-308 ? gamma : 2.2e-308;
+  const double cs = gbar / gamma, sn = beta / gamma;
+  const double phi = cs * s.phibar;
+  const double phibar = sn * s.phibar;
+  const double denom = 1.0 / gamma;
+  s.oldb = oldb;
+  s.beta = beta;
+  s.epsln = epsln;
+  s.dbar = dbar;
+  s.cs = cs;
+  s.sn = sn;
+  s.phibar = phibar;
+  s.alfa = alfa;
+  if (b2 < 0 || !(b2 == b2) || !(phibar == phibar)) {
+    s.flag = -1;
+    s.done = 1;
+  } else if (phibar <= s.tol * s.beta1 || beta == 0.0) {
+    s.flag = 1;
+    s.done = 1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) next[rhs] = s;
+  const long long off = (long long)rhs * n;
+  const double vinv = beta > 0 ? 1.0 / beta : 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    double w1 = todbl(v.w2[off + i]);
+    double w2 = todbl(v.w[off + i]);
+    double wn = (todbl(v.v[off + i]) - oldeps * w1 - delta * w2) * denom;
+    TV ws = static_cast<TV>(wn);
+    v.w1[off + i] = ws;  // old w1 buffer becomes the new w
+    v.x[off + i] = static_cast<TV>(todbl(v.x[off + i]) + phi * todbl(ws));
+    v.v[off + i] = static_cast<TV>(todbl(v.y[off + i]) * vinv);
+  }
+}
+
+// ---- CG (SPD mass solves) -------------------------------------------------
+template <typename TV>
+__global__ void __launch_bounds__(kBT) cg_init(CgVecs<TV> v, const double* __restrict__ dinv, long long n,
+                                               double* part) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  const long long off = (long long)rhs * n;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    TV bi = v.b[off + i];
+    double zi = dinv[i] * todbl(bi);
+    v.r[off + i] = bi;
+    v.p[off + i] = static_cast<TV>(zi);
+    v.x[off + i] = 0;
+    acc += todbl(bi) * zi;
+  }
+  double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[rhs * gridDim.x + blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBT) cg_init_b(const double* part, int np, CgState* st0, double tol) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  double rz = reduce_partials(part + rhs * np, np, sh);
+  if (threadIdx.x == 0) {
+    CgState s{};
+    s.rz = rz;
+    s.rz0 = rz;
+    s.tol = tol;
+    s.done = rz == 0.0 ? 1 : 0;
+    s.flag = (rz < 0 || rz != rz) ? -1 : 0;
+    if (s.flag) s.done = 1;
+    st0[rhs] = s;
+  }
+}
+
+// partial (p . q) after q = A p
+template <typename TV>
+__global__ void __launch_bounds__(kBT) cg_pq(const TV* __restrict__ p, const TV* __restrict__ q, long long n,
+                                             const CgState* cur, double* part_a) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  if (cur[rhs].done) return;
+  const long long off = (long long)rhs * n;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
+    acc += todbl(p[off + i]) * todbl(q[off + i]);
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part_a[rhs * gridDim.x + blockIdx.x] = t;
+}
+
+// alpha = rz / (p.q); x += alpha p; r -= alpha q; z = dinv r (into q);
+// partial (r . z)
+template <typename TV>
+__global__ void __launch_bounds__(kBT) cg_update(CgVecs<TV> v, const double* __restrict__ dinv, long long n,
+                                                 const CgState* cur, const double* part_a, double* part_b) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  const CgState s = cur[rhs];
+  if (s.done) return;
+  const int np = gridDim.x;
+  const double pq = reduce_partials(part_a + rhs * np, np, sh);
+  const double alpha = s.rz / pq;
+  const long long off = (long long)rhs * n;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    v.x[off + i] = static_cast<TV>(todbl(v.x[off + i]) + alpha * todbl(v.p[off + i]));
+    double ri = todbl(v.r[off + i]) - alpha * todbl(v.q[off + i]);
+    TV rs = static_cast<TV>(ri);
+    v.r[off + i] = rs;
+    double zi = dinv[i] * todbl(rs);
+    TV zs = static_cast<TV>(zi);
+    v.q[off + i] = zs;
+    acc += todbl(rs) * todbl(zs);
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part_b[rhs * gridDim.x + blockIdx.x] = t;
+}
+
+// beta = rz_new / rz; p = z + beta p; state update
+template <typename TV>
+__global__ void __launch_bounds__(kBT) cg_dir(CgVecs<TV> v, long long n, const CgState* cur, CgState* next,
+                                              const double* part_b) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  CgState s = cur[rhs];
+  if (s.done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) next[rhs] = s;
+    return;
+  }
+  const int np = gridDim.x;
+  const double rz = reduce_partials(part_b + rhs * np, np, sh);
+  const double beta = rz / s.rz;
+  s.itn += 1;
+  s.rz = rz;
+  if (rz < 0 || !(rz == rz)) {
+    s.flag = -1;
+    s.done = 1;
+  } else if (rz <= s.tol * s.tol * s.rz0) {
+    s.flag = 1;
+    s.done = 1;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) next[rhs] = s;
+  const long long off = (long long)rhs * n;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
+    v.p[off + i] = static_cast<TV>(todbl(v.q[off + i]) + beta * todbl(v.p[off + i]));
+}
+
+// ---- small vector utilities -------------------------------------------------
+// partial sums of (a - b)^2 style norms: mode 0: a.a, mode 1: (a-b).(a-b)
+template <typename TA>
+__global__ void __launch_bounds__(kBT) norm2_partial(const TA* __restrict__ a, const double* __restrict__ b,
+                                                     long long n, int mode, double* part) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.y;
+  const long long off = (long long)rhs * n;
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    double d = todbl(a[off + i]) - (mode ? b[off + i] : 0.0);
+    acc += d * d;
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) part[rhs * gridDim.x + blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(kBT) finish_sums(const double* part, int np, double* out) {
+  __shared__ double sh[kBT];
+  const int rhs = blockIdx.x;
+  double s = reduce_partials(part + rhs * np, np, sh);
+  if (threadIdx.x == 0) out[rhs] = s;
+}
+
+// y = a - b (all FP64)
+__global__ void __launch_bounds__(kBT) sub_kernel(const double* a, const double* b, double* y, long long n) {
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
+    y[i] = a[i] - b[i];
+}
+
+// y32 = scale[rhs] * a64 (rhs-wise scaling)
+__global__ void __launch_bounds__(kBT) to_f32_scaled(const double* a, float* y, long long n, const double* scale) {
+  const int rhs = blockIdx.y;
+  const long long off = (long long)rhs * n;
+  const double s = scale[rhs];
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
+    y[off + i] = static_cast<float>(a[off + i] * s);
+}
+
+// x64 += scale[rhs] * d32
+__global__ void __launch_bounds__(kBT) axpy_f32(const float* d, double* x, long long n, const double* scale) {
+  const int rhs = blockIdx.y;
+  const long long off = (long long)rhs * n;
+  const double s = scale[rhs];
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
+    x[off + i] += s * static_cast<double>(d[off + i]);
+}
+
+// ---- host launchers ---------------------------------------------------------
+int vec_grid(long long n, int ncu) {
+  long long b = (n + kBT * 4 - 1) / (kBT * 4);
+  long long cap = 4LL * ncu;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+#define GYM_LAUNCH(k, g, s, ...) hipLaunchKernelGGL(k, g, dim3(kBT), 0, s, __VA_ARGS__)
+
+template <typename TV>
+void minres_launch_init(const MinresVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, double* part,
+                        MinresState* st0, double tol, hipStream_t s) {
+  GYM_LAUNCH(minres_init_a<TV>, dim3(nb, nrhs), s, v, dinv, n, part);
+  GYM_LAUNCH(minres_init_b<TV>, dim3(nb, nrhs), s, v, n, part, nb, st0, tol);
+}
+
+template <typename TV>
+void minres_launch_k3(TV* y, const TV* r1, const TV* vv, long long n, int nrhs, int nb, const MinresState* cur,
+                      double* pa, hipStream_t s) {
+  GYM_LAUNCH(minres_k3<TV>, dim3(nb, nrhs), s, y, r1, vv, n, cur, pa);
+}
+
+template <typename TV>
+void minres_launch_k5(TV* y, const TV* r2, TV* z, const double* dinv, long long n, int nrhs, int nb,
+                      const MinresState* cur, const double* pa, double* pb, hipStream_t s) {
+  GYM_LAUNCH(minres_k5<TV>, dim3(nb, nrhs), s, y, r2, z, dinv, n, cur, pa, pb);
+}
+
+template <typename TV>
+void minres_launch_k7(const MinresVecs<TV>& v, long long n, int nrhs, int nb, const MinresState* cur,
+                      MinresState* next, const double* pa, const double* pb, hipStream_t s) {
+  GYM_LAUNCH(minres_k7<TV>, dim3(nb, nrhs), s, v, n, cur, next, pa, pb);
+}
+
+template <typename TV>
+void cg_launch_init(const CgVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, double* part,
+                    CgState* st0, double tol, hipStream_t s) {
+  GYM_LAUNCH(cg_init<TV>, dim3(nb, nrhs), s, v, dinv, n, part);
+  GYM_LAUNCH(cg_init_b, dim3(1, nrhs), s, part, nb, st0, tol);
+}
+
+template <typename TV>
+void cg_launch_iter_tail(const CgVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb,
+                         const CgState* cur, CgState* next, double* pa, double* pb, hipStream_t s) {
+  GYM_LAUNCH(cg_pq<TV>, dim3(nb, nrhs), s, v.p, v.q, n, cur, pa);
+  GYM_LAUNCH(cg_update<TV>, dim3(nb, nrhs), s, v, dinv, n, cur, pa, pb);
+  GYM_LAUNCH(cg_dir<TV>, dim3(nb, nrhs), s, v, n, cur, next, pb);
+}
+
+void launch_norm2(const double* a, const double* b, long long n, int nrhs, int nb, int mode, double* part,
+                  double* out, hipStream_t s) {
+  GYM_LAUNCH(norm2_partial<double>, dim3(nb, nrhs), s, a, b, n, mode, part);
+  GYM_LAUNCH(finish_sums, dim3(nrhs), s, part, nb, out);
+}
+
+void launch_sub(const double* a, const double* b, double* y, long long n, int nb, hipStream_t s) {
+  GYM_LAUNCH(sub_kernel, dim3(nb), s, a, b, y, n);
+}
+
+void launch_to_f32_scaled(const double* a, float* y, long long n, int nrhs, int nb, const double* scale,
+                          hipStream_t s) {
+  GYM_LAUNCH(to_f32_scaled, dim3(nb, nrhs), s, a, y, n, scale);
+}
+
+void launch_axpy_f32(const float* d, double* x, long long n, int nrhs, int nb, const double* scale,
+                     hipStream_t s) {
+  GYM_LAUNCH(axpy_f32, dim3(nb, nrhs), s, d, x, n, scale);
+}
+
+template void minres_launch_init<double>(const MinresVecs<double>&, const double*, long long, int, int, double*,
+                                         MinresState*, double, hipStream_t);
+template void minres_launch_init<float>(const MinresVecs<float>&, const double*, long long, int, int, double*,
+                                        MinresState*, double, hipStream_t);
+template void minres_launch_k3<double>(double*, const double*, const double*, long long, int, int,
+                                       const MinresState*, double*, hipStream_t);
+template void minres_launch_k3<float>(float*, const float*, const float*, long long, int, int,
+                                      const MinresState*, double*, hipStream_t);
+template void minres_launch_k5<double>(double*, const double*, double*, const double*, long long, int, int,
+                                       const MinresState*, const double*, double*, hipStream_t);
+template void minres_launch_k5<float>(float*, const float*, float*, const double*, long long, int, int,
+                                      const MinresState*, const double*, double*, hipStream_t);
+template void minres_launch_k7<double>(const MinresVecs<double>&, long long, int, int, const MinresState*,
+                                       MinresState*, const double*, const double*, hipStream_t);
+template void minres_launch_k7<float>(const MinresVecs<float>&, long long, int, int, const MinresState*,
+                                      MinresState*, const double*, const double*, hipStream_t);
+template void cg_launch_init<double>(const CgVecs<double>&, const double*, long long, int, int, double*,
+                                     CgState*, double, hipStream_t);
+template void cg_launch_iter_tail<double>(const CgVecs<double>&, const double*, long long, int, int,
+                                          const CgState*, CgState*, double*, double*, hipStream_t);
+
+}  // namespace gym

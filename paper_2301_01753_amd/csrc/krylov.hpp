@@ -1,0 +1,58 @@
+// Krylov kernel interfaces (see krylov.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace gym {
+
+struct MinresState {
+  double beta, oldb, dbar, epsln, phibar, cs, sn, tnorm2, beta1, alfa, tol;
+  int itn, done, flag, pad;  // flag: 0 running, 1 converged, -1 breakdown
+};
+
+struct CgState {
+  double rz, rz0, tol;
+  int itn, done, flag, pad;
+};
+
+template <typename TV>
+struct MinresVecs {
+  const TV* b;
+  TV *x, *r1, *r2, *y, *v, *w, *w1, *w2;
+};
+
+template <typename TV>
+struct CgVecs {
+  const TV* b;
+  TV *x, *r, *p, *q;  // q holds A p, then z = M^-1 r
+};
+
+int vec_grid(long long n, int ncu);
+
+template <typename TV>
+void minres_launch_init(const MinresVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, double* part,
+                        MinresState* st0, double tol, hipStream_t s);
+template <typename TV>
+void minres_launch_k3(TV* y, const TV* r1, const TV* vv, long long n, int nrhs, int nb, const MinresState* cur,
+                      double* pa, hipStream_t s);
+template <typename TV>
+void minres_launch_k5(TV* y, const TV* r2, TV* z, const double* dinv, long long n, int nrhs, int nb,
+                      const MinresState* cur, const double* pa, double* pb, hipStream_t s);
+template <typename TV>
+void minres_launch_k7(const MinresVecs<TV>& v, long long n, int nrhs, int nb, const MinresState* cur,
+                      MinresState* next, const double* pa, const double* pb, hipStream_t s);
+template <typename TV>
+void cg_launch_init(const CgVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, double* part,
+                    CgState* st0, double tol, hipStream_t s);
+template <typename TV>
+void cg_launch_iter_tail(const CgVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb,
+                         const CgState* cur, CgState* next, double* pa, double* pb, hipStream_t s);
+
+void launch_norm2(const double* a, const double* b, long long n, int nrhs, int nb, int mode, double* part,
+                  double* out, hipStream_t s);
+void launch_sub(const double* a, const double* b, double* y, long long n, int nb, hipStream_t s);
+void launch_to_f32_scaled(const double* a, float* y, long long n, int nrhs, int nb, const double* scale,
+                          hipStream_t s);
+void launch_axpy_f32(const float* d, double* x, long long n, int nrhs, int nb, const double* scale,
+                     hipStream_t s);
+
+}  // namespace gym
