@@ -1,0 +1,261 @@
+"""Benchmark of the matrix-free FEEC hot path on one MI355X.
+
+Workload (default): 3-D unit cube, 32^3 hexahedra, degree-2 Hodge Laplacian
+on 1-forms (sigma in H1_0, u in H0(curl)), right-hand side = load vector of
+an 8-mode Fourier field with N(0, 1) coefficients (seed 0), FP64
+matrix-free operator inside block-Jacobi preconditioned MINRES.
+
+A step is one whole solve (every Krylov iteration: incidence, sum-factorised
+masses, transposed incidence, deterministic reductions, vector updates) to a
+relative residual of 1e-10, starting from x = 0 with b already in HBM.
+
+value = operator-apply throughput inside the solve:
+        (DoFs x MINRES iterations) summed over the timed solves / wall time,
+in GDoF/s.  Also printed: solves/s, the pure operator-apply rate, the
+relative error of each result against an FP64 reference solve (rtol 1e-13),
+the mixed-precision mode (FP32 inner solve inside FP64 refinement) and the
+batched mode (8 right-hand sides per launch) on the same operator.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "operator-apply GDoF/s and solves/s to 1e-8 rel. err: FP64 vs mixed vs batched"
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+PEAK_FP64_TFLOPS = 78.6        # 256 CU x 64 FP64 FMA lanes x 2 x 2.4 GHz
+PEAK_FP32_TFLOPS = 157.3
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def comp_flops(n, q):
+    """Sum-factorised flops of one component: 3 forward contractions
+    (coefficients -> Gauss points), 3 transposed ones, per element."""
+    nx, ny, nz = n
+    fwd = 2 * (q * ny * nz * nx + q * q * nz * ny + q ** 3 * nz)
+    bwd = 2 * (q * q * nz * q + q * ny * nz * q + nx * ny * nz * q)
+    return fwd + bwd
+
+
+def algorithmic_flops_per_element(problem, r):
+    """Flops per element of one operator apply as the kernel's algorithm
+    defines them (Gauss points q = r + 1, no halo recomputation)."""
+    q, N, E = r + 1, r + 1, r
+    h1 = comp_flops((N, N, N), q)
+    hcurl = sum(comp_flops(tuple(E if a == c else N for a in range(3)), q) for c in range(3))
+    hdiv = sum(comp_flops(tuple(N if a == c else E for a in range(3)), q) for c in range(3))
+    l2 = comp_flops((E, E, E), q)
+    if problem == "hodge":
+        return h1 + 2 * hcurl + hdiv       # M0 sigma, M1 u, M1 G sigma, M2 C u
+    return hdiv + 2 * l2                   # M2 s, M3 p, M3 D s
+
+
+def cpu_baseline(nel, r, rtol):
+    """The CPU oracle (SciPy MINRES on the assembled operator) on a reduced
+    mesh of the same workload, single-threaded."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import synth
+    from oracle import problems
+    from oracle.lattice import Mesh
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        P = problems.Hodge1(Mesh(synth.uniform_vertices(nel)), r)
+        coeffs = synth.fourier_coeffs(0, 8, 3)
+        _, _, f = problems.hodge_fields(coeffs, synth.modes_3d())
+        b = P.rhs(f)
+        t_asm = time.perf_counter() - t0
+        its = [0]
+
+        def cb(_):
+            its[0] += 1
+
+        import scipy.sparse as sp
+        import scipy.sparse.linalg as spla
+        Minv = sp.diags(1.0 / P.precond_diag())
+        t0 = time.perf_counter()
+        # SciPy's stopping test is looser than a true relative residual;
+        # a tighter internal tolerance brings the true residual near `rtol`
+        x, info = spla.minres(P.A, b, M=Minv, rtol=rtol * 1e-4, maxiter=20000, callback=cb)
+        t_solve = time.perf_counter() - t0
+    n = P.A.shape[0]
+    rel = float(np.linalg.norm(P.A @ x - b) / np.linalg.norm(b))
+    return {
+        "value": n * its[0] / t_solve / 1e9,
+        "unit": "GDoF/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"SciPy MINRES on the assembled {nel[0]}x{nel[1]}x{nel[2]} degree-{r} Hodge system "
+                   f"({n} DoFs, {its[0]} iterations, rel. residual {rel:.1e}) in {t_solve:.2f} s; "
+                   f"assembly {t_asm:.2f} s not counted; 1 thread of {os.cpu_count()} host cores"),
+        "solves_per_s_at_sample": 1.0 / t_solve,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--nel", type=int, default=32)
+    ap.add_argument("--degree", type=int, default=2)
+    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-modes", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the operator would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2301_01753_amd import gym
+
+    dev = torch.device("cuda:0")
+    nel, r = (args.nel,) * 3, args.degree
+    ctx = gym.gym_create(0)
+    mesh = gym.gym_mesh_create(ctx, 3, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, r)
+    n = gym.gym_op_ndofs(op)
+    modes = synth.modes_3d()
+    b = torch.empty(n, dtype=torch.float64, device=dev)
+    gym.gym_rhs_manufactured(op, modes, synth.fourier_coeffs(0, 8, 3), b)
+    log(f"workload: {nel} degree {r} Hodge, {n} DoFs")
+
+    # FP64 reference (untimed), tight tolerance
+    xref = torch.empty_like(b)
+    o = gym.gym_solve_opts_default()
+    o.rtol = 1e-13
+    info = gym.gym_solve(op, o, 1, b, xref)
+    log(f"reference solve: {info.iters} iterations, rel_res {info.rel_res:.2e}")
+
+    def run_mode(mode, nrhs, bvec, steps, warmup):
+        x = torch.empty_like(bvec)
+        o = gym.gym_solve_opts_default()
+        o.rtol = args.rtol
+        o.mode = mode
+        o.inner_rtol = 1e-4
+        o.timing = 1
+        for _ in range(warmup):
+            gym.gym_solve(op, o, nrhs, bvec, x)
+        torch.cuda.synchronize()
+        iters, applies, apply_ms, worst = 0, 0, 0.0, 0.0
+        t0 = time.perf_counter()
+        infos = []
+        for k in range(steps):
+            inf = gym.gym_solve(op, o, nrhs, bvec, x)
+            infos.append((inf.iters, inf.outer_iters, inf.rel_res, inf.applies, inf.apply_ms, inf.status))
+            log(f"  mode {mode} nrhs {nrhs} step {k}: {inf.iters} it, rel_res {inf.rel_res:.2e}")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        for it, _, rr, na, ms, st in infos:
+            iters += it
+            applies += na
+            apply_ms += ms
+            worst = max(worst, rr)
+        return x, wall, iters, applies, apply_ms, worst, infos
+
+    def rel_err(x, ref):
+        return float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
+
+    # ---- FP64 (the headline) ----
+    torch.cuda.synchronize()
+    x, wall, iters, applies, apply_ms, worst, infos = run_mode(gym.GYM_MODE_F64, 1, b, args.steps, args.warmup)
+    err64 = rel_err(x, xref)
+    value = n * iters / wall / 1e9
+    ms_per_step = wall / args.steps * 1e3
+    apply_avg_s = apply_ms / applies / 1e3
+    flops = algorithmic_flops_per_element("hodge", r) * int(np.prod(nel))
+    bytes_ = 16.0 * n
+    ai = flops / bytes_
+    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
+    if ai > ridge:
+        roof = {"bound": "alu", "achieved": flops / apply_avg_s / 1e12, "peak": PEAK_FP64_TFLOPS,
+                "unit": "TFLOP/s"}
+    else:
+        roof = {"bound": "hbm", "achieved": bytes_ / apply_avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = "op_kernel<Hodge, r=%d, FP64>" % r
+    roof["avg_launch_us"] = apply_avg_s * 1e6
+    roof["algorithmic_flops"] = flops
+    roof["algorithmic_bytes"] = bytes_
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3-D unit cube {nel[0]}^3 hex, degree-{r} Hodge Laplacian on 1-forms "
+                        f"(H1_0 x H0(curl)), FP64 matrix-free apply + block-Jacobi MINRES to rel. residual "
+                        f"{args.rtol:g}, 8-mode manufactured field (seed 0)",
+            "ndofs": n,
+            "parallelism": "single GPU",
+        },
+        "solves_per_s": args.steps / wall,
+        "iters_per_solve": iters / args.steps,
+        "rel_err_vs_fp64_ref": err64,
+        "apply_gdof_s": n / apply_avg_s / 1e9,
+        "roofline": roof,
+    }
+
+    if not args.no_modes:
+        # ---- mixed precision: FP32 inner MINRES inside FP64 refinement ----
+        xm, wall_m, it_m, ap_m, ms_m, worst_m, inf_m = run_mode(gym.GYM_MODE_IR_F32, 1, b, args.steps, 1)
+        out["mixed_ir_f32"] = {
+            "solves_per_s": args.steps / wall_m, "gdof_s": n * it_m / wall_m / 1e9,
+            "inner_iters_per_solve": it_m / args.steps, "outer_iters": inf_m[-1][1],
+            "rel_err_vs_fp64_ref": rel_err(xm, xref), "rel_res": worst_m,
+            "apply_gdof_s_f32": n / (ms_m / ap_m / 1e3) / 1e9,
+            "speedup_vs_fp64": (args.steps / wall_m) / (args.steps / wall),
+        }
+        # ---- batched: 8 right-hand sides per launch ----
+        nb = 8
+        B = torch.empty(nb * n, dtype=torch.float64, device=dev)
+        for k in range(nb):
+            gym.gym_rhs_manufactured(op, modes, synth.fourier_coeffs(k, 8, 3), B[k * n:(k + 1) * n])
+        xb, wall_b, it_b, ap_b, ms_b, worst_b, inf_b = run_mode(gym.GYM_MODE_F64, nb, B, max(2, args.steps // 4), 1)
+        steps_b = max(2, args.steps // 4)
+        out["batched_8rhs"] = {
+            "solves_per_s": nb * steps_b / wall_b, "gdof_s": nb * n * it_b / wall_b / 1e9,
+            "iters_per_solve": it_b / steps_b, "rel_res": worst_b,
+            "apply_gdof_s": nb * n / (ms_b / ap_b / 1e3) / 1e9,
+            "speedup_vs_fp64": (nb * steps_b / wall_b) / (args.steps / wall),
+        }
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline((10, 10, 10), r, args.rtol)
+
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+    gym.gym_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

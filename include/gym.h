@@ -91,6 +91,18 @@ int gym_destroy(gym_ctx* ctx);
  * next failing call on this thread. */
 const char* gym_last_error(void);
 
+/* Context options (apply to every later call on the context).
+ * GYM_OPT_MASS_FORM: 0 = automatic (Kronecker form of the element masses
+ *   on affine meshes, Gauss-point form otherwise), 1 = always evaluate at
+ *   Gauss points (the paper's mass-matrix definition, quadrature r + 1).
+ *   Both forms compute the same operator up to rounding.
+ * GYM_OPT_TILE: 0 = automatic, 1 = large tiles (one workgroup per CU),
+ *   2 = small tiles (several workgroups per CU).
+ * Errors: GYM_E_ARG for an unknown option or value. */
+#define GYM_OPT_MASS_FORM 0
+#define GYM_OPT_TILE      1
+int gym_ctx_set(gym_ctx* ctx, int option, int value);
+
 /* ---- mesh (paper section 2: the mesh T_h) ----------------------------- */
 /* Structured mesh of nel[0] x nel[1] (x nel[2]) cells, dim = 2 or 3.
  * vertices: HOST array of (nel[0]+1)*...*(nel[d-1]+1)*dim doubles,
@@ -168,6 +180,7 @@ typedef struct gym_solve_opts {
   double inner_rtol;  /* IR: inner relative residual target (e.g. 1e-4)    */
   int max_outer;      /* IR: outer refinement steps                        */
   int check_every;    /* host reads the device residual estimate every k   */
+  int timing;         /* 1: bracket every operator apply with HIP events   */
 } gym_solve_opts;
 
 typedef struct gym_solve_info {
@@ -176,10 +189,12 @@ typedef struct gym_solve_info {
   int outer_iters;     /* IR outer steps (0 in FP64 mode)                  */
   double rel_res;      /* ||b - A x|| / ||b|| in FP64 at exit, per rhs max */
   double seconds;      /* wall time of the call                            */
+  int applies;         /* operator applies timed (opts.timing = 1)         */
+  double apply_ms;     /* summed HIP-event time of those applies, ms       */
 } gym_solve_info;
 
 /* Fill `opts` with defaults: MINRES, FP64, rtol 1e-10, maxit 20000,
- * inner_rtol 1e-4, max_outer 30, check_every 25. */
+ * inner_rtol 1e-4, max_outer 30, check_every 25, timing 0. */
 void gym_solve_opts_default(gym_solve_opts* opts);
 
 /* Solve A x = b for nrhs right-hand sides (device FP64 vectors, x is

@@ -221,9 +221,15 @@ int check_mesh_jacobians(const gym_mesh* m) {
   return 0;
 }
 
+void set_form(OpParams& p, const gym_ctx* ctx, const gym_mesh* m) {
+  p.kron = (ctx->mass_form == 0 && !m->curved) ? 1 : 0;
+  p.tile_budget = ctx->tile == 1 ? 0 : 1;
+}
+
 int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
   const gym_mesh* m = op->mesh;
   OpParams p{};
+  set_form(p, op->ctx, m);
   p.x = x;
   p.y = y;
   p.ndofs = op->na + op->nb;
@@ -255,6 +261,7 @@ int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y
 int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
   const gym_mesh* m = sp->mesh;
   OpParams p{};
+  set_form(p, sp->ctx, m);
   p.x = x;
   p.y = y;
   p.ndofs = sp->desc.ndofs;
@@ -379,6 +386,48 @@ int relres_f64(const gym_op* op, int nrhs, const double* b, const double* x, dou
   return 0;
 }
 
+// Brackets operator applies with HIP event pairs (pre-created pool) and sums
+// their elapsed times once the stream has been synchronised.
+struct ApplyTimer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  size_t used = 0;
+  ~ApplyTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  int begin(hipStream_t s) {
+    if (!on) return 0;
+    if (used + 2 > ev.size()) {
+      for (int k = 0; k < 256; ++k) {
+        hipEvent_t e;
+        GYM_HIP(hipEventCreate(&e));
+        ev.push_back(e);
+      }
+    }
+    GYM_HIP(hipEventRecord(ev[used], s));
+    return 0;
+  }
+  int end(hipStream_t s) {
+    if (!on) return 0;
+    GYM_HIP(hipEventRecord(ev[used + 1], s));
+    used += 2;
+    return 0;
+  }
+  // call after the stream is synchronised
+  int collect(int* n, double* ms) {
+    double tot = 0;
+    for (size_t k = 0; k + 1 < used; k += 2) {
+      float t = 0;
+      GYM_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
+      tot += t;
+    }
+    *n = (int)(used / 2);
+    *ms = tot;
+    used = 0;
+    return 0;
+  }
+};
+
 }  // namespace
 
 // Workspace held by an operator between solves.
@@ -420,6 +469,19 @@ int gym_create(gym_ctx** out, int device) {
 int gym_destroy(gym_ctx* ctx) {
   delete ctx;
   return GYM_OK;
+}
+
+int gym_ctx_set(gym_ctx* ctx, int option, int value) {
+  if (!ctx) return fail(GYM_E_ARG, "NULL context");
+  if (option == GYM_OPT_MASS_FORM && (value == 0 || value == 1)) {
+    ctx->mass_form = value;
+    return GYM_OK;
+  }
+  if (option == GYM_OPT_TILE && value >= 0 && value <= 2) {
+    ctx->tile = value;
+    return GYM_OK;
+  }
+  return fail(GYM_E_ARG, "unknown option or value");
 }
 
 int gym_mesh_create(gym_ctx* ctx, int dim, const int64_t nel[3], const double* vertices, const double lo[3],
@@ -683,6 +745,7 @@ void gym_solve_opts_default(gym_solve_opts* o) {
   o->inner_rtol = 1e-4;
   o->max_outer = 30;
   o->check_every = 25;
+  o->timing = 0;
 }
 
 static int ensure_work(gym_op* op, int nrhs, OpWork** out) {
@@ -740,8 +803,14 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
   const long long n = w->n;
   std::vector<double> rel;
   int status = GYM_OK;
+  ApplyTimer timer;
+  timer.on = opts.timing != 0;
   if (opts.mode == GYM_MODE_F64) {
-    auto apply = [&](const double* in, double* out) { return launch_op_apply(op, GYM_F64, nrhs, in, out, s); };
+    auto apply = [&](const double* in, double* out) {
+      if (int rc = timer.begin(s)) return rc;
+      if (int rc = launch_op_apply(op, GYM_F64, nrhs, in, out, s)) return rc;
+      return timer.end(s);
+    };
     double tol = opts.rtol;
     int total = 0, flag = 0, resume = 0;
     for (int attempt = 0; attempt < 6; ++attempt) {
@@ -776,7 +845,11 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
     if (opts.mode == GYM_MODE_IR_BF16) return fail(GYM_E_UNSUPPORTED, "BF16 contractions not built yet");
     if (int rc = ensure_work32(op, w)) return rc;
     const int prec = GYM_F32;
-    auto apply32 = [&](const float* in, float* out) { return launch_op_apply(op, prec, nrhs, in, out, s); };
+    auto apply32 = [&](const float* in, float* out) {
+      if (int rc = timer.begin(s)) return rc;
+      if (int rc = launch_op_apply(op, prec, nrhs, in, out, s)) return rc;
+      return timer.end(s);
+    };
     GYM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n * nrhs, s));
     int total = 0, outer = 0;
     std::vector<double> rn;
@@ -818,6 +891,8 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
     if (int rc = relres_f64(op, nrhs, b, x, w->tmp, w->part, w->sums, w->nb, s, rel)) return rc;
   inf.rel_res = *std::max_element(rel.begin(), rel.end());
   if (status == GYM_OK && inf.rel_res > opts.rtol) status = GYM_W_NOT_CONVERGED;
+  GYM_HIP(hipStreamSynchronize(s));
+  if (int rc = timer.collect(&inf.applies, &inf.apply_ms)) return rc;
   inf.status = status;
   inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (info) *info = inf;

@@ -59,6 +59,8 @@ SpaceDesc make_space_desc(int kind, int dim, const int64_t nel[3], int r, int bc
 struct gym_ctx {
   int device = 0;
   int ncu = 0;
+  int mass_form = 0;  // GYM_OPT_MASS_FORM
+  int tile = 0;       // GYM_OPT_TILE
 };
 
 struct gym_mesh {

@@ -32,6 +32,8 @@ struct OpParams {
   int nel[3];
   int m[3];         // lattice cells per axis (r * nel)
   int tiles_x, tiles_y, chunk;
+  int kron;         // 1: Kronecker (1-D element matrix) form of the masses
+  int tile_budget;  // 0: one 160 KB workgroup per CU, 1: 40 KB workgroups
   double sc[8];     // constant pointwise metric factors (affine meshes)
 };
 

@@ -117,7 +117,7 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 }
 
 // ---- LDS layout ------------------------------------------------------------
-template <class C, class F>
+template <class C, class F, bool KRON>
 struct Layout {
   static constexpr int lat(int f) { return C::lat(F::tm[f]); }
   static constexpr bool carries(int f) { return C::DIM == 3 && (F::tm[f] & 4); }
@@ -132,14 +132,14 @@ struct Layout {
     for (int g = 0; g < f; ++g) o += carries(g) ? C::plane(F::tm[g]) : 0;
     return o;
   }
-  static constexpr int A_off() { return car_off(F::NF); }
-  static constexpr int B_off() { return A_off() + C::tmpA(); }
   static constexpr int maxlat() {
     int m = 0;
     for (int t = 0; t < 8; ++t) m = C::lat(t) > m ? C::lat(t) : m;
     return m;
   }
-  static constexpr int L1_off() { return B_off() + C::tmpB(); }
+  static constexpr int A_off() { return car_off(F::NF); }
+  static constexpr int B_off() { return A_off() + (KRON ? maxlat() : C::tmpA()); }
+  static constexpr int L1_off() { return B_off() + (KRON ? maxlat() : C::tmpB()); }
   static constexpr int L2_off() { return L1_off() + maxlat(); }
   static constexpr int total() { return L2_off() + maxlat(); }
 };
@@ -151,10 +151,10 @@ __device__ __forceinline__ int ext(int a) {
 }
 
 // ---- the kernel ------------------------------------------------------------
-template <class C, int PROB, typename TV, typename TC>
+template <class C, int PROB, bool KRON, typename TV, typename TC>
 __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
   using F = Fields<PROB, C::DIM>;
-  using L = Layout<C, F>;
+  using L = Layout<C, F, KRON>;
   constexpr int R = C::R;
   __shared__ TC smem[L::total()];
   TC* A = smem + L::A_off();
@@ -219,12 +219,12 @@ __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
 
     if constexpr (PROB == PROB_HODGE) {
       // -M0 sigma
-      mass_uniform<C, 7, true>(in0, out0, (TC)-p.sc[0], A, B, er);
+      mass<C, 7, true, KRON>(in0, out0, (TC)-p.sc[0], A, B, er);
       // G^T (M1 u): v_c = M1_c u_c on the closure, then y_sigma(q) += v_c(q-e_c) - v_c(q)
       static_for<0, 3>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         constexpr int TE = 7 & ~(1 << c);
-        mass_uniform<C, TE, false>(smem + L::in_off(1 + c), L1, (TC)p.sc[1 + c], A, B, er);
+        mass<C, TE, false, KRON>(smem + L::in_off(1 + c), L1, (TC)p.sc[1 + c], A, B, er);
         for (int i = threadIdx.x; i < C::lat(7); i += kNT) {
           int q[3];
           lpos<C, 7>(i, q[0], q[1], q[2]);
@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
           L1[i] = g;
         }
         __syncthreads();
-        mass_uniform<C, TE, true>(L1, smem + L::out_off(1 + c), (TC)p.sc[1 + c], A, B, er);
+        mass<C, TE, true, KRON>(L1, smem + L::out_off(1 + c), (TC)p.sc[1 + c], A, B, er);
       });
       // C^T M2 C u
       static_for<0, 3>([&](auto cc) {
@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
           L1[i] = v;
         }
         __syncthreads();
-        mass_uniform<C, TF, false>(L1, L2, (TC)p.sc[4 + c], A, B, er);
+        mass<C, TF, false, KRON>(L1, L2, (TC)p.sc[4 + c], A, B, er);
         // (C^T z)_c2(q) = z_c(q - e_c1) - z_c(q); (C^T z)_c1(q) = z_c(q) - z_c(q - e_c2)
         TC* o2 = smem + L::out_off(1 + c2);
         for (int i = threadIdx.x; i < C::lat(T2); i += kNT) {
@@ -316,10 +316,10 @@ __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
       // M2 s
       static_for<0, NS>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        mass_uniform<C, F::tm[c], true>(smem + L::in_off(c), smem + L::out_off(c), (TC)p.sc[c], A, B, er);
+        mass<C, F::tm[c], true, KRON>(smem + L::in_off(c), smem + L::out_off(c), (TC)p.sc[c], A, B, er);
       });
       // -D^T (M3 p): y_s_c(q) += w(q) - w(q - e_c)
-      mass_uniform<C, 0, false>(inp, L1, (TC)p.sc[3], A, B, er);
+      mass<C, 0, false, KRON>(inp, L1, (TC)p.sc[3], A, B, er);
       static_for<0, NS>([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         constexpr int TF = F::tm[c];
@@ -355,11 +355,11 @@ __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
         L1[i] = v;
       }
       __syncthreads();
-      mass_uniform<C, 0, true>(L1, outp, (TC)-p.sc[3], A, B, er);
+      mass<C, 0, true, KRON>(L1, outp, (TC)-p.sc[3], A, B, er);
     } else {
       static_for<0, F::NF>([&](auto fc) {
         constexpr int f = decltype(fc)::value;
-        mass_uniform<C, F::tm[f], true>(smem + L::in_off(f), smem + L::out_off(f), (TC)p.sc[f], A, B, er);
+        mass<C, F::tm[f], true, KRON>(smem + L::in_off(f), smem + L::out_off(f), (TC)p.sc[f], A, B, er);
       });
     }
 
@@ -407,27 +407,30 @@ __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
 }
 
 // ---- tile-size selection ----------------------------------------------------
-template <int DIM, int R, int PROB, typename TC>
+// Largest square tile whose LDS footprint fits `budget` bytes (2..8 per side;
+// up to 16 in 2-D).  Two budgets are compiled: the whole 160 KB of a CU (one
+// workgroup per CU, least halo recomputation) and 40 KB (four workgroups per
+// CU, more waves to hide LDS latency).
+template <int DIM, int R, int PROB, bool KRON, typename TC, int BUDGET>
 struct TileSel {
   template <int B>
   static constexpr int bytes() {
     using C = Cfg<R, B, B, DIM>;
-    return Layout<C, Fields<PROB, DIM>>::total() * (int)sizeof(TC);
+    return Layout<C, Fields<PROB, DIM>, KRON>::total() * (int)sizeof(TC);
   }
-  static constexpr int kLimit = 160 * 1024;
-  static constexpr int B = DIM == 2 ? (bytes<16>() <= kLimit ? 16 : (bytes<8>() <= kLimit ? 8 : 4))
-                           : bytes<8>() <= kLimit ? 8
-                           : bytes<6>() <= kLimit ? 6
-                           : bytes<4>() <= kLimit ? 4
-                           : bytes<3>() <= kLimit ? 3
+  static constexpr int B = DIM == 2 ? (bytes<16>() <= BUDGET ? 16 : (bytes<8>() <= BUDGET ? 8 : (bytes<4>() <= BUDGET ? 4 : 2)))
+                           : bytes<8>() <= BUDGET ? 8
+                           : bytes<6>() <= BUDGET ? 6
+                           : bytes<4>() <= BUDGET ? 4
+                           : bytes<3>() <= BUDGET ? 3
                                                   : 2;
 };
 
-template <int DIM, int R, int PROB, typename TV, typename TC>
-int launch_op(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
-  constexpr int B = TileSel<DIM, R, PROB, TC>::B;
+template <int DIM, int R, int PROB, bool KRON, typename TV, typename TC, int BUDGET>
+int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
+  constexpr int B = TileSel<DIM, R, PROB, KRON, TC, BUDGET>::B;
   using C = Cfg<R, B, B, DIM>;
-  static_assert(Layout<C, Fields<PROB, DIM>>::total() * sizeof(TC) <= 160 * 1024, "LDS");
+  static_assert(Layout<C, Fields<PROB, DIM>, KRON>::total() * sizeof(TC) <= 160 * 1024, "LDS");
   OpParams p = p0;
   p.tiles_x = (p.nel[0] + B - 1) / B;
   p.tiles_y = (p.nel[1] + B - 1) / B;
@@ -435,16 +438,29 @@ int launch_op(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
   int nchunks = 1;
   p.chunk = 1;
   if (DIM == 3) {
+    // enough workgroups for two per CU, but chunks of at least 4 layers so
+    // that the recomputed halo layer costs at most a quarter
     const int target = 2 * ncu;
     nchunks = (target + nt * nrhs - 1) / (nt * nrhs);
+    int maxch = p.nel[2] / 4;
+    if (nchunks > maxch) nchunks = maxch;
     if (nchunks < 1) nchunks = 1;
-    if (nchunks > p.nel[2]) nchunks = p.nel[2];
     p.chunk = (p.nel[2] + nchunks - 1) / nchunks;
     nchunks = (p.nel[2] + p.chunk - 1) / p.chunk;
   }
   dim3 grid(nt, nchunks, nrhs);
-  hipLaunchKernelGGL((op_kernel<C, PROB, TV, TC>), grid, dim3(kNT), 0, stream, p);
+  hipLaunchKernelGGL((op_kernel<C, PROB, KRON, TV, TC>), grid, dim3(kNT), 0, stream, p);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int DIM, int R, int PROB, typename TV, typename TC>
+int launch_op(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
+  if (p.kron) {
+    if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, true, TV, TC, 160 * 1024>(p, nrhs, ncu, stream);
+    return launch_op_b<DIM, R, PROB, true, TV, TC, 40 * 1024>(p, nrhs, ncu, stream);
+  }
+  if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, false, TV, TC, 160 * 1024>(p, nrhs, ncu, stream);
+  return launch_op_b<DIM, R, PROB, false, TV, TC, 40 * 1024>(p, nrhs, ncu, stream);
 }
 
 template <int DIM, int PROB, typename TV, typename TC>
@@ -508,6 +524,18 @@ int upload_tables() {
           d.edgew[s][j] = t.gw[s] * t.edge[s * r + j];
         }
       }
+      for (int i = 0; i <= r; ++i)
+        for (int j = 0; j <= r; ++j) {
+          double acc = 0;
+          for (int s = 0; s < q; ++s) acc += t.gw[s] * t.phi[s * (r + 1) + i] * t.phi[s * (r + 1) + j];
+          d.mn[i][j] = acc;
+        }
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) {
+          double acc = 0;
+          for (int s = 0; s < q; ++s) acc += t.gw[s] * t.edge[s * r + i] * t.edge[s * r + j];
+          d.me[i][j] = acc;
+        }
     }
     TabSet<float>& f = hf[r - 1];
     const TabSet<double>& d = hd[r - 1];
@@ -517,6 +545,10 @@ int upload_tables() {
       for (int i = 0; i < 5; ++i) f.phi[s][i] = (float)d.phi[s][i], f.phiw[s][i] = (float)d.phiw[s][i];
       for (int j = 0; j < 4; ++j) f.edge[s][j] = (float)d.edge[s][j], f.edgew[s][j] = (float)d.edgew[s][j];
     }
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) f.mn[i][j] = (float)d.mn[i][j];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) f.me[i][j] = (float)d.me[i][j];
   }
   GYM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tab_d), hd, sizeof(hd)));
   GYM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tabL_d), hl, sizeof(hl)));

@@ -35,6 +35,8 @@ struct TabSet {
   T edgew[6][4];  // w_t * edge values
   T w[6];
   T gx[6];
+  T mn[5][5];     // 1-D element mass of the nodal functions (Gauss, q = r + 1)
+  T me[4][4];     // 1-D element mass of the edge functions
 };
 
 extern __constant__ TabSet<double> c_tab_d[4];   // q = r + 1
@@ -235,6 +237,85 @@ __device__ __forceinline__ void mass_uniform(const TC* in, TC* out, TC scale, TC
   __syncthreads();
   bwd_x<C, TM, ADD>(A, out, scale);
   __syncthreads();
+}
+
+// Kronecker form of the same mass apply on affine, axis-aligned cells: with a
+// constant metric the element matrix factors into 1-D element matrices
+// M_a = B_a^T W B_a (evaluated once from the same Gauss rule), so
+//   out (=|+=) scale * (M_x (x) M_y (x) M_z) in
+// assembled over the tile's valid elements.  Three banded lattice stages
+// replace the six Gauss-point stages; the result equals mass_uniform up to
+// rounding.  A, B: lattice-sized temporaries.
+template <typename TC, bool NODAL>
+__device__ __forceinline__ TC kmat(const TabSet<TC>& t, int i, int j) {
+  if constexpr (NODAL) return t.mn[i][j];
+  else return t.me[i][j];
+}
+
+template <class C, int TM, bool ADD, typename TC>
+__device__ __forceinline__ void mass_kron(const TC* in, TC* out, TC scale, TC* A, TC* B, const ElemRange& er) {
+  constexpr int NX = C::nx(TM), NY = C::ny(TM), NZ = C::nz(TM);
+  constexpr int R = C::R;
+  const TabSet<TC>& T = tabs<TC>(R);
+  {
+    constexpr bool N = TM & 1;
+    constexpr int n = N ? R + 1 : R;
+    for (int idx = threadIdx.x; idx < NX * NY * NZ; idx += kNT) {
+      int j = idx % NX;
+      const TC* s = in + (idx - j);
+      A[idx] = gather1d<R, C::EX, N>(j, [&](int e, int i) {
+        TC acc = 0;
+        if (e >= er.xlo && e < er.xhi) {
+#pragma unroll
+          for (int k = 0; k < n; ++k) acc += kmat<TC, N>(T, i, k) * s[R * e + k];
+        }
+        return acc;
+      });
+    }
+  }
+  __syncthreads();
+  {
+    constexpr bool N = TM & 2;
+    constexpr int n = N ? R + 1 : R;
+    for (int idx = threadIdx.x; idx < NX * NY * NZ; idx += kNT) {
+      int x = idx % NX, r2 = idx / NX;
+      int j = r2 % NY, k = r2 / NY;
+      const TC* s = A + x + NX * NY * k;
+      B[idx] = gather1d<R, C::EY, N>(j, [&](int e, int i) {
+        TC acc = 0;
+        if (e >= er.ylo && e < er.yhi) {
+#pragma unroll
+          for (int m = 0; m < n; ++m) acc += kmat<TC, N>(T, i, m) * s[NX * (R * e + m)];
+        }
+        return acc;
+      });
+    }
+  }
+  __syncthreads();
+  {
+    constexpr int P = NX * NY;
+    for (int idx = threadIdx.x; idx < P * NZ; idx += kNT) {
+      TC v;
+      if constexpr (C::DIM == 2) {
+        v = B[idx];
+      } else {
+        constexpr bool N = TM & 4;
+        int p = idx % P, k = idx / P;
+        v = 0;
+#pragma unroll
+        for (int m = 0; m < NZ; ++m) v += kmat<TC, N>(T, k, m) * B[p + P * m];
+      }
+      if constexpr (ADD) out[idx] += scale * v;
+      else out[idx] = scale * v;
+    }
+  }
+  __syncthreads();
+}
+
+template <class C, int TM, bool ADD, bool KRON, typename TC>
+__device__ __forceinline__ void mass(const TC* in, TC* out, TC scale, TC* A, TC* B, const ElemRange& er) {
+  if constexpr (KRON) mass_kron<C, TM, ADD>(in, out, scale, A, B, er);
+  else mass_uniform<C, TM, ADD>(in, out, scale, A, B, er);
 }
 
 // Lattice index inside the layer closure.

@@ -42,12 +42,13 @@ class GymError(RuntimeError):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("mode", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("check_every", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("timing", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("outer_iters", ctypes.c_int),
-                ("rel_res", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_res", ctypes.c_double), ("seconds", ctypes.c_double), ("applies", ctypes.c_int),
+                ("apply_ms", ctypes.c_double)]
 
 
 class ServeOpts(ctypes.Structure):
@@ -73,6 +74,7 @@ SIGNATURES = {
     "gym_create": (_I, [ctypes.POINTER(_P), _I]),
     "gym_destroy": (_I, [_P]),
     "gym_last_error": (ctypes.c_char_p, []),
+    "gym_ctx_set": (_I, [_P, _I, _I]),
     "gym_mesh_create": (_I, [_P, _I, ctypes.POINTER(_I64), _P, _P, _P, ctypes.POINTER(_P)]),
     "gym_mesh_destroy": (_I, [_P]),
     "gym_space_create": (_I, [_P, _P, _I, _I, _I, ctypes.POINTER(_P)]),
@@ -148,6 +150,13 @@ def gym_create(device=0):
 
 def gym_destroy(ctx):
     _check(lib().gym_destroy(ctx))
+
+
+GYM_OPT_MASS_FORM, GYM_OPT_TILE = 0, 1
+
+
+def gym_ctx_set(ctx, option, value):
+    _check(lib().gym_ctx_set(ctx, option, value))
 
 
 def gym_mesh_create(ctx, dim, nel, vertices=None, lo=None, hi=None):

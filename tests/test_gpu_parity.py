@@ -130,8 +130,21 @@ def _rel(got, ref):
     return np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-300)
 
 
+FORMS = [(0, 1), (0, 2), (1, 1), (1, 2)]   # (mass form, tile option)
+
+
+@pytest.fixture(params=FORMS, ids=["kron-large", "kron-small", "gauss-large", "gauss-small"])
+def form(request, g):
+    gym, ctx = g
+    gym.gym_ctx_set(ctx, gym.GYM_OPT_MASS_FORM, request.param[0])
+    gym.gym_ctx_set(ctx, gym.GYM_OPT_TILE, request.param[1])
+    yield request.param
+    gym.gym_ctx_set(ctx, gym.GYM_OPT_MASS_FORM, 0)
+    gym.gym_ctx_set(ctx, gym.GYM_OPT_TILE, 0)
+
+
 @pytest.mark.parametrize("kind,nel,r,bc", MASS_CASES)
-def test_mass_apply_3d(g, kind, nel, r, bc):
+def test_mass_apply_3d(g, form, kind, nel, r, bc):
     gym, ctx = g
     hi = (1.0, 1.7, 0.6)
     mesh = _mesh(gym, ctx, nel, hi=hi)
@@ -157,7 +170,7 @@ def test_mass_apply_3d(g, kind, nel, r, bc):
 
 @pytest.mark.parametrize("kind", ["H1", "HCURL", "HDIV", "L2"])
 @pytest.mark.parametrize("r", [1, 2, 4])
-def test_mass_apply_2d(g, kind, r):
+def test_mass_apply_2d(g, form, kind, r):
     gym, ctx = g
     nel = (19, 6)
     mesh = _mesh(gym, ctx, nel, hi=(2.0, 0.5))
@@ -186,7 +199,7 @@ def _oracle_problem(which, nel, r):
 
 
 @pytest.mark.parametrize("which,nel,r", OP_CASES)
-def test_operator_apply(g, which, nel, r):
+def test_operator_apply(g, form, which, nel, r):
     gym, ctx = g
     mesh = _mesh(gym, ctx, nel)
     op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON if which == "poisson" else gym.GYM_HODGE1, mesh, r)
