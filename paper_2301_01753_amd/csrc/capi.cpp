@@ -223,7 +223,17 @@ int check_mesh_jacobians(const gym_mesh* m) {
 
 void set_form(OpParams& p, const gym_ctx* ctx, const gym_mesh* m) {
   p.kron = (ctx->mass_form == 0 && !m->curved) ? 1 : 0;
-  p.tile_budget = ctx->tile == 1 ? 0 : 1;
+  // auto: small tiles on affine cells (latency hiding), large ones on curved
+  // cells where the per-Gauss-point work outweighs the LDS latency
+  p.tile_budget = (ctx->tile == 1 || (ctx->tile == 0 && m->curved)) ? 0 : 1;
+  p.curved = m->curved ? 1 : 0;
+  p.verts = m->d_vertices;
+}
+
+// On curved cells the metric is evaluated per Gauss point; the per-block
+// factors only carry signs.
+void curved_scales(OpParams& p) {
+  for (double& v : p.sc) v = 1.0;
 }
 
 int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
@@ -252,6 +262,7 @@ int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y
       p.sc[4 + c] = metric_const(GYM_HDIV, c, m);
     }
   }
+  if (m->curved) curved_scales(p);
   int rc = launch_operator(prob, m->dim, op->r, prec, p, nrhs, op->ctx->ncu, s);
   if (rc == -2) return fail(GYM_E_UNSUPPORTED, "no kernel for this problem/degree/precision");
   if (rc) return fail(GYM_E_HIP, "operator kernel launch failed");
@@ -272,6 +283,7 @@ int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, vo
     p.m[a] = a < m->dim ? (int)(sp->desc.r * m->nel[a]) : 1;
   }
   for (int c = 0; c < sp->desc.ncomp; ++c) p.sc[c] = metric_const(sp->desc.kind, c, m);
+  if (m->curved) curved_scales(p);
   int prob = PROB_MASS_H1 + sp->desc.kind;
   int rc = launch_operator(prob, m->dim, sp->desc.r, prec, p, nrhs, sp->ctx->ncu, s);
   if (rc == -2) return fail(GYM_E_UNSUPPORTED, "no mass kernel for this space/precision");
@@ -591,7 +603,6 @@ int gym_d_apply(const gym_space* from, const gym_space* to, int transpose, const
 
 int gym_mass_apply(const gym_space* space, int prec, int nrhs, const void* x, void* y, void* stream) {
   if (!space || !x || !y || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
-  if (space->mesh->curved) return fail(GYM_E_UNSUPPORTED, "curved meshes: mass apply not built yet");
   if (prec != GYM_F64 && prec != GYM_F32) return fail(GYM_E_UNSUPPORTED, "precision not available");
   return launch_mass_apply(space, prec, nrhs, x, y, (hipStream_t)stream);
 }
@@ -661,7 +672,6 @@ int gym_op_destroy(gym_op* op) {
 
 int gym_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, void* stream) {
   if (!op || !x || !y || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
-  if (op->mesh->curved) return fail(GYM_E_UNSUPPORTED, "curved meshes: operator not built yet");
   if (prec != GYM_F64 && prec != GYM_F32) return fail(GYM_E_UNSUPPORTED, "precision not available");
   return launch_op_apply(op, prec, nrhs, x, y, (hipStream_t)stream);
 }
@@ -796,7 +806,6 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
   else gym_solve_opts_default(&opts);
   gym_solve_info inf{};
   hipStream_t s = (hipStream_t)stream;
-  if (op->mesh->curved) return fail(GYM_E_UNSUPPORTED, "curved meshes: operator not built yet");
   if (opts.method != GYM_MINRES) return fail(GYM_E_UNSUPPORTED, "block operators are indefinite: use MINRES");
   OpWork* w;
   if (int rc = ensure_work(op, nrhs, &w)) return rc;

@@ -33,6 +33,8 @@ struct OpParams {
   int m[3];         // lattice cells per axis (r * nel)
   int tiles_x, tiles_y, chunk;
   int kron;         // 1: Kronecker (1-D element matrix) form of the masses
+  int curved;       // 1: per-Gauss-point metric from the vertex array
+  const double* verts;  // (nel+1)^3 x 3 vertex coordinates (curved only)
   int tile_budget;  // 0: one 160 KB workgroup per CU, 1: 40 KB workgroups
   double sc[8];     // constant pointwise metric factors (affine meshes)
 };
@@ -40,6 +42,13 @@ struct OpParams {
 int upload_tables();
 int launch_operator(int prob, int dim, int r, int prec, const OpParams& p, int nrhs, int ncu,
                     hipStream_t s);
+// per-unit entry points (op_hodge.hip, op_poisson.hip, op_mass.hip)
+int launch_hodge(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
+int launch_poisson(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
+int launch_mass(int prob, int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
+int upload_tables_hodge();
+int upload_tables_poisson();
+int upload_tables_mass();
 
 // incidence: y = d x or d^T x, bit-reproducible ascending-index sums
 struct IncParams {

@@ -1,0 +1,70 @@
+// Shared host code of the operator kernels: table construction and the
+// problem dispatch across the per-problem translation units.
+#include <hip/hip_runtime.h>
+
+#include "gym_internal.hpp"
+#include "kernels.hpp"
+#include "tile.hpp"
+
+namespace gym {
+
+void fill_tables(TabSet<double>* hd, TabSet<double>* hl, TabSet<float>* hf) {
+  for (int r = 1; r <= 4; ++r) {
+    for (int which = 0; which < 2; ++which) {
+      int q = r + 1 + which;
+      Tables1D t = make_tables(r, q);
+      TabSet<double>& d = which == 0 ? hd[r - 1] : hl[r - 1];
+      for (int s = 0; s < q; ++s) {
+        d.w[s] = t.gw[s];
+        d.gx[s] = t.gx[s];
+        for (int i = 0; i <= r; ++i) {
+          d.phi[s][i] = t.phi[s * (r + 1) + i];
+          d.phiw[s][i] = t.gw[s] * t.phi[s * (r + 1) + i];
+        }
+        for (int j = 0; j < r; ++j) {
+          d.edge[s][j] = t.edge[s * r + j];
+          d.edgew[s][j] = t.gw[s] * t.edge[s * r + j];
+        }
+      }
+      for (int i = 0; i <= r; ++i)
+        for (int j = 0; j <= r; ++j) {
+          double acc = 0;
+          for (int s = 0; s < q; ++s) acc += t.gw[s] * t.phi[s * (r + 1) + i] * t.phi[s * (r + 1) + j];
+          d.mn[i][j] = acc;
+        }
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) {
+          double acc = 0;
+          for (int s = 0; s < q; ++s) acc += t.gw[s] * t.edge[s * r + i] * t.edge[s * r + j];
+          d.me[i][j] = acc;
+        }
+    }
+    TabSet<float>& f = hf[r - 1];
+    const TabSet<double>& d = hd[r - 1];
+    for (int s = 0; s < 6; ++s) {
+      f.w[s] = (float)d.w[s];
+      f.gx[s] = (float)d.gx[s];
+      for (int i = 0; i < 5; ++i) f.phi[s][i] = (float)d.phi[s][i], f.phiw[s][i] = (float)d.phiw[s][i];
+      for (int j = 0; j < 4; ++j) f.edge[s][j] = (float)d.edge[s][j], f.edgew[s][j] = (float)d.edgew[s][j];
+    }
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) f.mn[i][j] = (float)d.mn[i][j];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) f.me[i][j] = (float)d.me[i][j];
+  }
+}
+
+
+int upload_tables() {
+  if (int rc = upload_tables_hodge()) return rc;
+  if (int rc = upload_tables_poisson()) return rc;
+  return upload_tables_mass();
+}
+
+int launch_operator(int prob, int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s) {
+  if (prob == PROB_HODGE) return launch_hodge(dim, r, prec, p, nrhs, ncu, s);
+  if (prob == PROB_POISSON) return launch_poisson(dim, r, prec, p, nrhs, ncu, s);
+  return launch_mass(prob, dim, r, prec, p, nrhs, ncu, s);
+}
+
+}  // namespace gym

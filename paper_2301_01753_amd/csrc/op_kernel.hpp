@@ -1,0 +1,705 @@
+// Fused matrix-free operator kernel (included by the op_*.hip units).
+//
+// Problems (unknown blocks in canonical layout, paper section 2 objects):
+//   POISSON : [s in HDIV; p in L2]      y_s = M2 s - D^T M3 p,  y_p = -M3 D s
+//   HODGE   : [sigma in H1_0; u in H0(curl)]
+//             y_sigma = -M0 sigma + G^T M1 u,  y_u = M1 G sigma + C^T M2 C u
+//   MASS_k  : y = M_k x for one space
+// Per element layer of a tile (see tile.hpp) the incidence is applied on the
+// closure (+-1 sums), each mass block by sum factorisation, and the
+// transposed incidence on the closure; this equals the sum over elements of
+// the element-local operators because incidence commutes with restriction
+// to an element.
+//
+// Mass forms (template FORM):
+//   FORM_GAUSS  Gauss-point contractions, constant metric (affine cells)
+//   FORM_KRON   Kronecker product of 1-D element masses (affine cells)
+//   FORM_CURVED Gauss-point contractions with the metric of the multilinear
+//               cell map evaluated at every Gauss point (curved cells)
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "gym_internal.hpp"
+#include "kernels.hpp"
+#include "tile.hpp"
+
+namespace gym {
+
+enum { FORM_GAUSS = 0, FORM_KRON = 1, FORM_CURVED = 2 };
+
+// ---- field lists ---------------------------------------------------------
+// tm: nodal mask of the field's lattice; sp: 0 = first block, 1 = second
+// block of the operator vector; cp: component within its space.
+template <int PROB, int DIM>
+struct Fields;
+
+template <>
+struct Fields<PROB_HODGE, 3> {
+  static constexpr int NF = 4;
+  static constexpr int tm[4] = {7, 6, 5, 3};
+  static constexpr int sp[4] = {0, 1, 1, 1};
+  static constexpr int cp[4] = {0, 0, 1, 2};
+};
+template <>
+struct Fields<PROB_POISSON, 3> {
+  static constexpr int NF = 4;
+  static constexpr int tm[4] = {1, 2, 4, 0};
+  static constexpr int sp[4] = {0, 0, 0, 1};
+  static constexpr int cp[4] = {0, 1, 2, 0};
+};
+template <>
+struct Fields<PROB_POISSON, 2> {
+  static constexpr int NF = 3;
+  static constexpr int tm[3] = {1, 2, 0};
+  static constexpr int sp[3] = {0, 0, 1};
+  static constexpr int cp[3] = {0, 1, 0};
+};
+template <>
+struct Fields<PROB_MASS_H1, 3> {
+  static constexpr int NF = 1;
+  static constexpr int tm[1] = {7};
+  static constexpr int sp[1] = {0};
+  static constexpr int cp[1] = {0};
+};
+template <>
+struct Fields<PROB_MASS_H1, 2> {
+  static constexpr int NF = 1;
+  static constexpr int tm[1] = {3};
+  static constexpr int sp[1] = {0};
+  static constexpr int cp[1] = {0};
+};
+template <>
+struct Fields<PROB_MASS_HCURL, 3> {
+  static constexpr int NF = 3;
+  static constexpr int tm[3] = {6, 5, 3};
+  static constexpr int sp[3] = {0, 0, 0};
+  static constexpr int cp[3] = {0, 1, 2};
+};
+template <>
+struct Fields<PROB_MASS_HCURL, 2> {
+  static constexpr int NF = 2;
+  static constexpr int tm[2] = {2, 1};
+  static constexpr int sp[2] = {0, 0};
+  static constexpr int cp[2] = {0, 1};
+};
+template <>
+struct Fields<PROB_MASS_HDIV, 3> {
+  static constexpr int NF = 3;
+  static constexpr int tm[3] = {1, 2, 4};
+  static constexpr int sp[3] = {0, 0, 0};
+  static constexpr int cp[3] = {0, 1, 2};
+};
+template <>
+struct Fields<PROB_MASS_HDIV, 2> {
+  static constexpr int NF = 2;
+  static constexpr int tm[2] = {1, 2};
+  static constexpr int sp[2] = {0, 0};
+  static constexpr int cp[2] = {0, 1};
+};
+template <>
+struct Fields<PROB_MASS_L2, 3> {
+  static constexpr int NF = 1;
+  static constexpr int tm[1] = {0};
+  static constexpr int sp[1] = {0};
+  static constexpr int cp[1] = {0};
+};
+template <>
+struct Fields<PROB_MASS_L2, 2> {
+  static constexpr int NF = 1;
+  static constexpr int tm[1] = {0};
+  static constexpr int sp[1] = {0};
+  static constexpr int cp[1] = {0};
+};
+
+template <int I, int N, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (I < N) {
+    fn(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(fn);
+  }
+}
+
+// ---- LDS layout ------------------------------------------------------------
+template <class C, class F, int FORM>
+struct Layout {
+  static constexpr int lat(int f) { return C::lat(F::tm[f]); }
+  static constexpr bool carries(int f) { return C::DIM == 3 && (F::tm[f] & 4); }
+  static constexpr int in_off(int f) {
+    int o = 0;
+    for (int g = 0; g < f; ++g) o += lat(g);
+    return o;
+  }
+  static constexpr int out_off(int f) { return in_off(F::NF) + in_off(f); }
+  static constexpr int car_off(int f) {
+    int o = 2 * in_off(F::NF);
+    for (int g = 0; g < f; ++g) o += carries(g) ? C::plane(F::tm[g]) : 0;
+    return o;
+  }
+  static constexpr int maxlat() {
+    int m = 0;
+    for (int t = 0; t < 8; ++t) m = C::lat(t) > m ? C::lat(t) : m;
+    return m;
+  }
+  static constexpr int nq() { return C::QX * C::QY * C::QZ; }
+  static constexpr int A_off() { return car_off(F::NF); }
+  static constexpr int B_off() { return A_off() + (FORM == FORM_KRON ? maxlat() : C::tmpA()); }
+  static constexpr int L_off(int k) { return B_off() + (FORM == FORM_KRON ? maxlat() : C::tmpB()) + k * maxlat(); }
+  // curved form: three Gauss-point arrays and the layer's vertex block
+  static constexpr int Q_off(int k) { return L_off(3) + k * nq(); }
+  static constexpr int nvert() { return 2 * (C::EX + 1) * (C::EY + 1) * 3; }
+  static constexpr int V_off() { return Q_off(3); }
+  static constexpr int total() { return FORM == FORM_CURVED ? V_off() + nvert() : L_off(3); }
+};
+
+// extent of the lattice of mask TM along axis a
+template <class C, int TM>
+__device__ __forceinline__ int ext(int a) {
+  return a == 0 ? C::nx(TM) : (a == 1 ? C::ny(TM) : C::nz(TM));
+}
+
+// ---- curved cells: Jacobian of the multilinear map at a Gauss point ----------
+// V: the layer's vertex block [2][EY+1][EX+1][3] (local element e spans
+// vertices e, e+1).  J[i][a] = dx_i / dxi_a.
+template <class C, typename TC>
+__device__ __forceinline__ void jac_at(const TC* V, int ex, int ey, TC xi, TC eta, TC zeta, TC J[3][3]) {
+  constexpr int SX = 3, SY = 3 * (C::EX + 1), SZ = 3 * (C::EX + 1) * (C::EY + 1);
+  const TC* v = V + ex * SX + ey * SY;
+  const TC wx[2] = {1 - xi, xi}, wy[2] = {1 - eta, eta}, wz[2] = {1 - zeta, zeta};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    TC dx = 0, dy = 0, dz = 0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        // derivative along x: (X(1,b,c) - X(0,b,c)) weighted by the other two
+        dx += wy[b] * wz[c] * (v[SX + b * SY + c * SZ + i] - v[b * SY + c * SZ + i]);
+        dy += wx[b] * wz[c] * (v[b * SX + SY + c * SZ + i] - v[b * SX + c * SZ + i]);
+        dz += wx[b] * wy[c] * (v[b * SX + c * SY + SZ + i] - v[b * SX + c * SY + i]);
+      }
+    J[i][0] = dx;
+    J[i][1] = dy;
+    J[i][2] = dz;
+  }
+}
+
+// Pointwise metric of the mass of `KIND` applied in place to the Gauss-point
+// values (vector kinds: Q0..Q2 are the three reference components).  The
+// Gauss weights are already in the transposed tables.
+//   H1: det J   L2: 1/det J   HCURL: det J J^-1 J^-T = adj adj^T / det
+//   HDIV: J^T J / det J
+template <class C, int KIND, typename TC>
+__device__ __forceinline__ void pointwise_curved(TC* Q0, TC* Q1, TC* Q2, const TC* V, TC sign,
+                                                 const ElemRange& er) {
+  const TabSet<TC>& T = tabs<TC>(C::R);
+  constexpr int N = C::QX * C::QY * C::QZ;
+  for (int idx = threadIdx.x; idx < N; idx += kNT) {
+    int qx = idx % C::QX, r = idx / C::QX;
+    int qy = r % C::QY, qz = r / C::QY;
+    int ex = qx / C::Q, ey = qy / C::Q;
+    if (ex < er.xlo || ex >= er.xhi || ey < er.ylo || ey >= er.yhi) {
+      Q0[idx] = 0;
+      if constexpr (KIND == GYM_HCURL || KIND == GYM_HDIV) {
+        Q1[idx] = 0;
+        Q2[idx] = 0;
+      }
+      continue;
+    }
+    TC J[3][3];
+    jac_at<C, TC>(V, ex, ey, T.gx[qx - ex * C::Q], T.gx[qy - ey * C::Q], T.gx[qz], J);
+    // cofactors: adj[a][i] = cof(J)[i][a], det = sum_i J[i][0] cof[i][0]
+    TC adj[3][3];
+    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const TC det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+    if constexpr (KIND == GYM_H1) {
+      Q0[idx] *= sign * det;
+    } else if constexpr (KIND == GYM_L2) {
+      Q0[idx] *= sign / det;
+    } else {
+      TC G[3][3];
+      const TC s = sign / det;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          TC acc = 0;
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc += KIND == GYM_HCURL ? adj[a][i] * adj[b][i] : J[i][a] * J[i][b];
+          G[a][b] = acc * s;
+        }
+      const TC u0 = Q0[idx], u1 = Q1[idx], u2 = Q2[idx];
+      Q0[idx] = G[0][0] * u0 + G[0][1] * u1 + G[0][2] * u2;
+      Q1[idx] = G[1][0] * u0 + G[1][1] * u1 + G[1][2] * u2;
+      Q2[idx] = G[2][0] * u0 + G[2][1] * u1 + G[2][2] * u2;
+    }
+  }
+}
+
+template <class C, int TM, typename TC>
+__device__ __forceinline__ void to_gauss(const TC* in, TC* Q, TC* A, TC* B, const ElemRange& er) {
+  fwd_x<C, TM>(in, A, er);
+  __syncthreads();
+  fwd_y<C, TM>(A, B, er);
+  __syncthreads();
+  fwd_z<C, TM>(B, Q);
+  __syncthreads();
+}
+
+template <class C, int TM, bool ADD, typename TC>
+__device__ __forceinline__ void from_gauss(const TC* Q, TC* out, TC* A, TC* B) {
+  bwd_z<C, TM>(Q, B);
+  __syncthreads();
+  bwd_y<C, TM>(B, A);
+  __syncthreads();
+  bwd_x<C, TM, ADD>(A, out, TC(1));
+  __syncthreads();
+}
+
+// Work buffers of one layer.
+template <typename TC>
+struct Work {
+  TC *A, *B, *L[3], *Q[3], *V;
+  ElemRange er;
+};
+
+// Scalar mass apply of kind KIND on a field of mask TM.
+template <class C, int TM, int KIND, bool ADD, int FORM, typename TC>
+__device__ __forceinline__ void smass(const TC* in, TC* out, TC scale, const Work<TC>& w) {
+  if constexpr (FORM == FORM_CURVED) {
+    to_gauss<C, TM>(in, w.Q[0], w.A, w.B, w.er);
+    pointwise_curved<C, KIND>(w.Q[0], w.Q[1], w.Q[2], w.V, scale, w.er);
+    __syncthreads();
+    from_gauss<C, TM, ADD>(w.Q[0], out, w.A, w.B);
+  } else {
+    mass<C, TM, ADD, FORM == FORM_KRON>(in, out, scale, w.A, w.B, w.er);
+  }
+}
+
+// Vector mass apply (three components of masks T0, T1, T2).  On affine
+// cells the metric is diagonal and the components decouple; on curved
+// cells all three reach the Gauss points before the metric mixes them.
+// in == out is allowed: inputs are consumed before outputs are written.
+template <class C, int KIND, int T0, int T1, int T2, bool ADD, int FORM, typename TC>
+__device__ __forceinline__ void vmass(TC* const in[3], TC* const out[3], const TC sc[3], const Work<TC>& w) {
+  if constexpr (FORM == FORM_CURVED) {
+    to_gauss<C, T0>(in[0], w.Q[0], w.A, w.B, w.er);
+    to_gauss<C, T1>(in[1], w.Q[1], w.A, w.B, w.er);
+    to_gauss<C, T2>(in[2], w.Q[2], w.A, w.B, w.er);
+    pointwise_curved<C, KIND>(w.Q[0], w.Q[1], w.Q[2], w.V, sc[0], w.er);
+    __syncthreads();
+    from_gauss<C, T0, ADD>(w.Q[0], out[0], w.A, w.B);
+    from_gauss<C, T1, ADD>(w.Q[1], out[1], w.A, w.B);
+    from_gauss<C, T2, ADD>(w.Q[2], out[2], w.A, w.B);
+  } else {
+    mass<C, T0, ADD, FORM == FORM_KRON>(in[0], out[0], sc[0], w.A, w.B, w.er);
+    mass<C, T1, ADD, FORM == FORM_KRON>(in[1], out[1], sc[1], w.A, w.B, w.er);
+    mass<C, T2, ADD, FORM == FORM_KRON>(in[2], out[2], sc[2], w.A, w.B, w.er);
+  }
+}
+
+// 2-D vector mass (affine forms only)
+template <class C, int T0, int T1, bool ADD, int FORM, typename TC>
+__device__ __forceinline__ void vmass2(TC* const in[2], TC* const out[2], const TC sc[2], const Work<TC>& w) {
+  mass<C, T0, ADD, FORM == FORM_KRON>(in[0], out[0], sc[0], w.A, w.B, w.er);
+  mass<C, T1, ADD, FORM == FORM_KRON>(in[1], out[1], sc[1], w.A, w.B, w.er);
+}
+
+// ---- the kernel ------------------------------------------------------------
+template <class C, int PROB, int FORM, typename TV, typename TC>
+__global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
+  using F = Fields<PROB, C::DIM>;
+  using L = Layout<C, F, FORM>;
+  constexpr int R = C::R;
+  static_assert(FORM != FORM_CURVED || C::DIM == 3, "curved cells are 3-D");
+  __shared__ TC smem[L::total()];
+
+  // XCD-aware tile order: consecutive hardware block ids go round-robin over
+  // the 8 XCDs; remap so that each XCD receives a contiguous run of tiles.
+  const int nt = p.tiles_x * p.tiles_y;
+  int b = blockIdx.x;
+  if (nt % 8 == 0) b = (b % 8) * (nt / 8) + b / 8;
+  const int tx = b % p.tiles_x, ty = b / p.tiles_x;
+  const int X0 = tx * C::BX, Y0 = ty * C::BY;
+  const int rhs = blockIdx.z;
+  const TV* __restrict__ xin = reinterpret_cast<const TV*>(p.x) + (long long)rhs * p.ndofs;
+  TV* __restrict__ yout = reinterpret_cast<TV*>(p.y) + (long long)rhs * p.ndofs;
+  const int gx0 = R * (X0 - 1), gy0 = R * (Y0 - 1);
+
+  Work<TC> w;
+  w.A = smem + L::A_off();
+  w.B = smem + L::B_off();
+  for (int k = 0; k < 3; ++k) w.L[k] = smem + L::L_off(k);
+  if constexpr (FORM == FORM_CURVED) {
+    for (int k = 0; k < 3; ++k) w.Q[k] = smem + L::Q_off(k);
+    w.V = smem + L::V_off();
+  } else {
+    for (int k = 0; k < 3; ++k) w.Q[k] = nullptr;
+    w.V = nullptr;
+  }
+  // local element e <-> global X0 - 1 + e
+  w.er = ElemRange{max(0, 1 - X0), min(C::EX, p.nel[0] - X0 + 1), max(0, 1 - Y0), min(C::EY, p.nel[1] - Y0 + 1)};
+
+  int zfirst = 0, zbeg = 0, zend = 1;
+  if constexpr (C::DIM == 3) {
+    zfirst = blockIdx.y * p.chunk;
+    zend = min(zfirst + p.chunk, p.nel[2]);
+    zbeg = zfirst > 0 ? zfirst - 1 : 0;
+  }
+
+  static_for<0, F::NF>([&](auto fc) {
+    constexpr int f = decltype(fc)::value;
+    if constexpr (L::carries(f)) {
+      TC* car = smem + L::car_off(f);
+      for (int i = threadIdx.x; i < C::plane(F::tm[f]); i += kNT) car[i] = 0;
+    }
+  });
+
+  auto IN = [&](int f) { return smem + L::in_off(f); };
+  auto OUT = [&](int f) { return smem + L::out_off(f); };
+
+  for (int ez = zbeg; ez < zend; ++ez) {
+    const int gz0 = C::DIM == 3 ? R * ez : 0;
+    // ---- load inputs, zero outputs (and the cell vertices when curved)
+    static_for<0, F::NF>([&](auto fc) {
+      constexpr int f = decltype(fc)::value;
+      constexpr int TM = F::tm[f];
+      const DevComp& cd = (F::sp[f] == 0 ? p.sa : p.sb).c[F::cp[f]];
+      TC* in = smem + L::in_off(f);
+      TC* out = smem + L::out_off(f);
+      for (int i = threadIdx.x; i < C::lat(TM); i += kNT) {
+        int lx, ly, lz;
+        lpos<C, TM>(i, lx, ly, lz);
+        int g0 = gx0 + lx - cd.start[0], g1 = gy0 + ly - cd.start[1], g2 = gz0 + lz - cd.start[2];
+        TC v = 0;
+        if (g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2])
+          v = static_cast<TC>(xin[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)]);
+        in[i] = v;
+        out[i] = 0;
+      }
+    });
+    if constexpr (FORM == FORM_CURVED) {
+      // vertices of the layer, clamped into the mesh (cells outside it are
+      // masked, their clamped geometry only has to stay finite)
+      constexpr int NVX = C::EX + 1, NVY = C::EY + 1;
+      for (int i = threadIdx.x; i < 2 * NVX * NVY * 3; i += kNT) {
+        int a = i % 3, r = i / 3;
+        int lx = r % NVX, r2 = r / NVX;
+        int ly = r2 % NVY, lz = r2 / NVY;
+        int vx = min(max(X0 - 1 + lx, 0), p.nel[0]);
+        int vy = min(max(Y0 - 1 + ly, 0), p.nel[1]);
+        int vz = min(ez + lz, p.nel[2]);
+        w.V[i] = static_cast<TC>(p.verts[(((long long)vz * (p.nel[1] + 1) + vy) * (p.nel[0] + 1) + vx) * 3 + a]);
+      }
+    }
+    __syncthreads();
+
+    if constexpr (PROB == PROB_HODGE) {
+      TC* in_u[3] = {IN(1), IN(2), IN(3)};
+      TC* out_u[3] = {OUT(1), OUT(2), OUT(3)};
+      TC* Lb[3] = {w.L[0], w.L[1], w.L[2]};
+      const TC s1[3] = {(TC)p.sc[1], (TC)p.sc[2], (TC)p.sc[3]};
+      const TC s2[3] = {(TC)p.sc[4], (TC)p.sc[5], (TC)p.sc[6]};
+      // -M0 sigma
+      smass<C, 7, GYM_H1, true, FORM>(IN(0), OUT(0), (TC)-p.sc[0], w);
+      // G^T (M1 u): v = M1 u on the closure, y_sigma(q) += sum_c v_c(q-e_c) - v_c(q)
+      vmass<C, GYM_HCURL, 6, 5, 3, false, FORM>(in_u, Lb, s1, w);
+      for (int i = threadIdx.x; i < C::lat(7); i += kNT) {
+        int q[3];
+        lpos<C, 7>(i, q[0], q[1], q[2]);
+        TC acc = 0;
+        static_for<0, 3>([&](auto cc) {
+          constexpr int c = decltype(cc)::value;
+          constexpr int TE = 7 & ~(1 << c);
+          if (q[c] >= 1) {
+            int s[3] = {q[0], q[1], q[2]};
+            s[c] -= 1;
+            acc += Lb[c][lidx<C, TE>(s[0], s[1], s[2])];
+          }
+          if (q[c] < ext<C, TE>(c)) acc -= Lb[c][lidx<C, TE>(q[0], q[1], q[2])];
+        });
+        OUT(0)[i] += acc;
+      }
+      __syncthreads();
+      // M1 G sigma: g_c(q) = sigma(q + e_c) - sigma(q)
+      static_for<0, 3>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        constexpr int TE = 7 & ~(1 << c);
+        const TC* sg = IN(0);
+        for (int i = threadIdx.x; i < C::lat(TE); i += kNT) {
+          int q[3];
+          lpos<C, TE>(i, q[0], q[1], q[2]);
+          int s[3] = {q[0], q[1], q[2]};
+          s[c] += 1;
+          TC g = -sg[lidx<C, 7>(q[0], q[1], q[2])];
+          g += sg[lidx<C, 7>(s[0], s[1], s[2])];
+          Lb[c][i] = g;
+        }
+      });
+      __syncthreads();
+      vmass<C, GYM_HCURL, 6, 5, 3, true, FORM>(Lb, out_u, s1, w);
+      // C^T M2 C u: b_c(p) = a_c2(p + e_c1) - a_c2(p) - a_c1(p + e_c2) + a_c1(p)
+      static_for<0, 3>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        constexpr int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        constexpr int TF = 1 << c;
+        constexpr int T1 = 7 & ~(1 << c1), T2 = 7 & ~(1 << c2);
+        const TC* a1 = in_u[c1];
+        const TC* a2 = in_u[c2];
+        for (int i = threadIdx.x; i < C::lat(TF); i += kNT) {
+          int q[3];
+          lpos<C, TF>(i, q[0], q[1], q[2]);
+          int t1[3] = {q[0], q[1], q[2]}, t2[3] = {q[0], q[1], q[2]};
+          t1[c1] += 1;
+          t2[c2] += 1;
+          TC v = a2[lidx<C, T2>(t1[0], t1[1], t1[2])];
+          v -= a2[lidx<C, T2>(q[0], q[1], q[2])];
+          v -= a1[lidx<C, T1>(t2[0], t2[1], t2[2])];
+          v += a1[lidx<C, T1>(q[0], q[1], q[2])];
+          Lb[c][i] = v;
+        }
+      });
+      __syncthreads();
+      vmass<C, GYM_HDIV, 1, 2, 4, false, FORM>(Lb, Lb, s2, w);  // z = M2 c in place
+      // (C^T z)_e(q) = [z_{e1}(q - e_{e2}) - z_{e1}(q)] + [z_{e2}(q) - z_{e2}(q - e_{e1})]
+      // with (e1, e2) the cyclic successors of edge component e
+      static_for<0, 3>([&](auto ce) {
+        constexpr int e = decltype(ce)::value;
+        constexpr int e1 = (e + 1) % 3, e2 = (e + 2) % 3;
+        constexpr int TE = 7 & ~(1 << e);
+        constexpr int TF1 = 1 << e1, TF2 = 1 << e2;
+        TC* o = out_u[e];
+        for (int i = threadIdx.x; i < C::lat(TE); i += kNT) {
+          int q[3];
+          lpos<C, TE>(i, q[0], q[1], q[2]);
+          TC acc = 0;
+          // face component e1 (nodal along e1, edge along e and e2)
+          if (q[e2] >= 1) {
+            int s[3] = {q[0], q[1], q[2]};
+            s[e2] -= 1;
+            acc += Lb[e1][lidx<C, TF1>(s[0], s[1], s[2])];
+          }
+          if (q[e2] < ext<C, TF1>(e2)) acc -= Lb[e1][lidx<C, TF1>(q[0], q[1], q[2])];
+          // face component e2 (nodal along e2, edge along e and e1)
+          if (q[e1] < ext<C, TF2>(e1)) acc += Lb[e2][lidx<C, TF2>(q[0], q[1], q[2])];
+          if (q[e1] >= 1) {
+            int s[3] = {q[0], q[1], q[2]};
+            s[e1] -= 1;
+            acc -= Lb[e2][lidx<C, TF2>(s[0], s[1], s[2])];
+          }
+          o[i] += acc;
+        }
+      });
+      __syncthreads();
+    } else if constexpr (PROB == PROB_POISSON) {
+      constexpr int D = C::DIM;
+      constexpr int NS = D;  // flux components
+      TC* L1 = w.L[0];
+      // M2 s
+      if constexpr (D == 3) {
+        TC* in_s[3] = {IN(0), IN(1), IN(2)};
+        TC* out_s[3] = {OUT(0), OUT(1), OUT(2)};
+        const TC s2[3] = {(TC)p.sc[0], (TC)p.sc[1], (TC)p.sc[2]};
+        vmass<C, GYM_HDIV, 1, 2, 4, true, FORM>(in_s, out_s, s2, w);
+      } else {
+        TC* in_s[2] = {IN(0), IN(1)};
+        TC* out_s[2] = {OUT(0), OUT(1)};
+        const TC s2[2] = {(TC)p.sc[0], (TC)p.sc[1]};
+        vmass2<C, 1, 2, true, FORM>(in_s, out_s, s2, w);
+      }
+      // -D^T (M3 p): y_s_c(q) += w(q) - w(q - e_c)
+      smass<C, 0, GYM_L2, false, FORM>(IN(NS), L1, (TC)p.sc[3], w);
+      static_for<0, NS>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        constexpr int TF = F::tm[c];
+        TC* o = OUT(c);
+        for (int i = threadIdx.x; i < C::lat(TF); i += kNT) {
+          int q[3];
+          lpos<C, TF>(i, q[0], q[1], q[2]);
+          TC acc = 0;
+          if (q[c] < ext<C, 0>(c)) acc += L1[lidx<C, 0>(q[0], q[1], q[2])];
+          if (q[c] >= 1) {
+            int s[3] = {q[0], q[1], q[2]};
+            s[c] -= 1;
+            acc -= L1[lidx<C, 0>(s[0], s[1], s[2])];
+          }
+          o[i] += acc;
+        }
+      });
+      __syncthreads();
+      // -M3 (D s): div(p) = sum_c s_c(p + e_c) - s_c(p)
+      for (int i = threadIdx.x; i < C::lat(0); i += kNT) {
+        int q[3];
+        lpos<C, 0>(i, q[0], q[1], q[2]);
+        TC v = 0;
+        static_for<0, NS>([&](auto cc) {
+          constexpr int c = decltype(cc)::value;
+          constexpr int TF = F::tm[c];
+          const TC* s = IN(c);
+          int t[3] = {q[0], q[1], q[2]};
+          t[c] += 1;
+          v -= s[lidx<C, TF>(q[0], q[1], q[2])];
+          v += s[lidx<C, TF>(t[0], t[1], t[2])];
+        });
+        L1[i] = v;
+      }
+      __syncthreads();
+      smass<C, 0, GYM_L2, true, FORM>(L1, OUT(NS), (TC)-p.sc[3], w);
+    } else {
+      constexpr int KIND = PROB - PROB_MASS_H1;
+      if constexpr (F::NF == 1) {
+        smass<C, F::tm[0], KIND, true, FORM>(IN(0), OUT(0), (TC)p.sc[0], w);
+      } else if constexpr (F::NF == 3) {
+        TC* in_v[3] = {IN(0), IN(1), IN(2)};
+        TC* out_v[3] = {OUT(0), OUT(1), OUT(2)};
+        const TC sv[3] = {(TC)p.sc[0], (TC)p.sc[1], (TC)p.sc[2]};
+        vmass<C, KIND, F::tm[0], F::tm[1], F::tm[2], true, FORM>(in_v, out_v, sv, w);
+      } else {
+        TC* in_v[2] = {IN(0), IN(1)};
+        TC* out_v[2] = {OUT(0), OUT(1)};
+        const TC sv[2] = {(TC)p.sc[0], (TC)p.sc[1]};
+        vmass2<C, F::tm[0], F::tm[1], true, FORM>(in_v, out_v, sv, w);
+      }
+    }
+
+    // ---- carry the shared top plane to the next layer
+    if constexpr (C::DIM == 3) {
+      static_for<0, F::NF>([&](auto fc) {
+        constexpr int f = decltype(fc)::value;
+        if constexpr (L::carries(f)) {
+          constexpr int PL = C::plane(F::tm[f]);
+          TC* out = smem + L::out_off(f);
+          TC* car = smem + L::car_off(f);
+          for (int i = threadIdx.x; i < PL; i += kNT) {
+            out[i] += car[i];
+            car[i] = out[i + R * PL];
+          }
+        }
+      });
+      __syncthreads();
+    }
+
+    // ---- write owned positions
+    if (ez >= zfirst) {
+      static_for<0, F::NF>([&](auto fc) {
+        constexpr int f = decltype(fc)::value;
+        constexpr int TM = F::tm[f];
+        const DevComp& cd = (F::sp[f] == 0 ? p.sa : p.sb).c[F::cp[f]];
+        const TC* out = smem + L::out_off(f);
+        for (int i = threadIdx.x; i < C::lat(TM); i += kNT) {
+          int lx, ly, lz;
+          lpos<C, TM>(i, lx, ly, lz);
+          int G0 = gx0 + lx, G1 = gy0 + ly, G2 = gz0 + lz;
+          bool own = G0 >= R * X0 && (G0 < R * (X0 + C::BX) || G0 == p.m[0]) && G1 >= R * Y0 &&
+                     (G1 < R * (Y0 + C::BY) || G1 == p.m[1]);
+          if constexpr (C::DIM == 3) own = own && (G2 < gz0 + R || G2 == p.m[2]);
+          int g0 = G0 - cd.start[0], g1 = G1 - cd.start[1], g2 = G2 - cd.start[2];
+          if (own && g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2])
+            yout[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)] =
+                static_cast<TV>(out[i]);
+        }
+      });
+    }
+    __syncthreads();
+  }
+}
+
+// ---- tile-size selection ----------------------------------------------------
+// Largest square tile whose LDS footprint fits `budget` bytes (2..8 per side;
+// up to 16 in 2-D).  Two budgets are compiled: the whole 160 KB of a CU (one
+// workgroup per CU, least halo recomputation) and 40 KB (several workgroups
+// per CU, more waves to hide LDS latency).
+template <int DIM, int R, int PROB, int FORM, typename TC, int BUDGET>
+struct TileSel {
+  template <int B>
+  static constexpr int bytes() {
+    using C = Cfg<R, B, B, DIM>;
+    return Layout<C, Fields<PROB, DIM>, FORM>::total() * (int)sizeof(TC);
+  }
+  static constexpr int B = DIM == 2 ? (bytes<16>() <= BUDGET ? 16 : (bytes<8>() <= BUDGET ? 8 : (bytes<4>() <= BUDGET ? 4 : 2)))
+                           : bytes<8>() <= BUDGET ? 8
+                           : bytes<6>() <= BUDGET ? 6
+                           : bytes<4>() <= BUDGET ? 4
+                           : bytes<3>() <= BUDGET ? 3
+                           : bytes<2>() <= BUDGET ? 2
+                                                  : 1;
+};
+
+template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, int BUDGET>
+int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
+  constexpr int B = TileSel<DIM, R, PROB, FORM, TC, BUDGET>::B;
+  using C = Cfg<R, B, B, DIM>;
+  static_assert(Layout<C, Fields<PROB, DIM>, FORM>::total() * sizeof(TC) <= 160 * 1024, "LDS");
+  OpParams p = p0;
+  p.tiles_x = (p.nel[0] + B - 1) / B;
+  p.tiles_y = (p.nel[1] + B - 1) / B;
+  const int nt = p.tiles_x * p.tiles_y;
+  int nchunks = 1;
+  p.chunk = 1;
+  if (DIM == 3) {
+    // enough workgroups for two per CU, but chunks of at least 4 layers so
+    // that the recomputed halo layer costs at most a quarter
+    const int target = 2 * ncu;
+    nchunks = (target + nt * nrhs - 1) / (nt * nrhs);
+    int maxch = p.nel[2] / 4;
+    if (nchunks > maxch) nchunks = maxch;
+    if (nchunks < 1) nchunks = 1;
+    p.chunk = (p.nel[2] + nchunks - 1) / nchunks;
+    nchunks = (p.nel[2] + p.chunk - 1) / p.chunk;
+  }
+  dim3 grid(nt, nchunks, nrhs);
+  hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC>), grid, dim3(kNT), 0, stream, p);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int DIM, int R, int PROB, typename TV, typename TC>
+int launch_op(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
+  constexpr int kBig = 160 * 1024, kSmall = 40 * 1024;
+  if (p.curved) {
+    if constexpr (DIM == 3) {
+      if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_CURVED, TV, TC, kBig>(p, nrhs, ncu, stream);
+      return launch_op_b<DIM, R, PROB, FORM_CURVED, TV, TC, kSmall>(p, nrhs, ncu, stream);
+    }
+    return -2;
+  }
+  if (p.kron) {
+    if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_KRON, TV, TC, kBig>(p, nrhs, ncu, stream);
+    return launch_op_b<DIM, R, PROB, FORM_KRON, TV, TC, kSmall>(p, nrhs, ncu, stream);
+  }
+  if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_GAUSS, TV, TC, kBig>(p, nrhs, ncu, stream);
+  return launch_op_b<DIM, R, PROB, FORM_GAUSS, TV, TC, kSmall>(p, nrhs, ncu, stream);
+}
+
+template <int DIM, int PROB, typename TV, typename TC>
+int dispatch_r(int r, const OpParams& p, int nrhs, int ncu, hipStream_t s) {
+  switch (r) {
+    case 1: return launch_op<DIM, 1, PROB, TV, TC>(p, nrhs, ncu, s);
+    case 2: return launch_op<DIM, 2, PROB, TV, TC>(p, nrhs, ncu, s);
+    case 3: return launch_op<DIM, 3, PROB, TV, TC>(p, nrhs, ncu, s);
+    case 4: return launch_op<DIM, 4, PROB, TV, TC>(p, nrhs, ncu, s);
+  }
+  return -2;
+}
+
+// Each translation unit owns a private copy of the constant tables; the
+// definitions below give every unit its own and the upload helper fills it.
+static int upload_tables_unit() {
+  TabSet<double> hd[4] = {}, hl[4] = {};
+  TabSet<float> hf[4] = {};
+  fill_tables(hd, hl, hf);
+  GYM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tab_d), hd, sizeof(hd)));
+  GYM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tabL_d), hl, sizeof(hl)));
+  GYM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tab_f), hf, sizeof(hf)));
+  return 0;
+}
+
+}  // namespace gym

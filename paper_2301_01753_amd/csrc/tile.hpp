@@ -39,9 +39,14 @@ struct TabSet {
   T me[4][4];     // 1-D element mass of the edge functions
 };
 
-extern __constant__ TabSet<double> c_tab_d[4];   // q = r + 1
-extern __constant__ TabSet<float> c_tab_f[4];
-extern __constant__ TabSet<double> c_tabL_d[4];  // q = r + 2 (load vectors)
+// Every translation unit that launches kernels holds its own copy of the
+// tables (no relocatable device code); see upload_tables_unit().
+static __constant__ TabSet<double> c_tab_d[4];   // q = r + 1
+static __constant__ TabSet<float> c_tab_f[4];
+static __constant__ TabSet<double> c_tabL_d[4];  // q = r + 2 (load vectors)
+
+// Host: fill the table sets for r = 1..4 (op_common.hip).
+void fill_tables(TabSet<double>* hd, TabSet<double>* hl, TabSet<float>* hf);
 
 template <typename T>
 __device__ __forceinline__ const TabSet<T>& tabs(int r);

@@ -339,3 +339,88 @@ def test_errors_are_reported(g):
     bad[1, 1, 1] = [2.0, 2.0, 2.0]          # folds the cells
     with pytest.raises(gym.GymError):
         gym.gym_mesh_create(ctx, 3, (2, 2, 2), vertices=bad)
+
+
+# ---- curved (perturbed, non-affine) cells -----------------------------------------
+CURVED_MASS = [("H1", (5, 4, 6), 1), ("HCURL", (4, 5, 3), 2), ("HDIV", (3, 4, 5), 3), ("L2", (4, 3, 4), 2),
+               ("HCURL", (3, 3, 4), 3), ("HDIV", (6, 5, 4), 1), ("H1", (3, 4, 3), 4)]
+
+
+@pytest.mark.parametrize("tile", [1, 2], ids=["large", "small"])
+@pytest.mark.parametrize("kind,nel,r", CURVED_MASS)
+def test_mass_apply_curved(g, tile, kind, nel, r):
+    gym, ctx = g
+    gym.gym_ctx_set(ctx, gym.GYM_OPT_TILE, tile)
+    verts = synth.perturbed_vertices(nel, 0.15, seed=21)
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts)
+    sp = gym.gym_space_create(ctx, mesh, KINDS[kind], r, 0)
+    so = Space(kind, nel, r)
+    M = assembly.mass_matrix(so, Mesh(verts))
+    x = synth.random_vector(so.ndofs, seed=4, nrhs=2)
+    y = torch.empty(2 * so.ndofs, dtype=torch.float64, device=DEV)
+    gym.gym_mass_apply(sp, gym.GYM_F64, 2, _t(x), y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().reshape(2, -1)
+    for k in range(2):
+        assert _rel(got[k], M @ x.reshape(2, -1)[k]) < 1e-13
+    gym.gym_ctx_set(ctx, gym.GYM_OPT_TILE, 0)
+    gym.gym_space_destroy(sp)
+    gym.gym_mesh_destroy(mesh)
+
+
+CURVED_OPS = [("hodge", (5, 4, 4), 1), ("hodge", (4, 5, 3), 2), ("hodge", (3, 3, 4), 3),
+              ("poisson", (5, 4, 4), 1), ("poisson", (4, 3, 5), 2), ("poisson", (3, 4, 3), 4)]
+
+
+@pytest.mark.parametrize("tile", [1, 2], ids=["large", "small"])
+@pytest.mark.parametrize("which,nel,r", CURVED_OPS)
+def test_operator_apply_curved(g, tile, which, nel, r):
+    gym, ctx = g
+    gym.gym_ctx_set(ctx, gym.GYM_OPT_TILE, tile)
+    verts = synth.perturbed_vertices(nel, 0.15, seed=8)
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON if which == "poisson" else gym.GYM_HODGE1, mesh, r)
+    mo = Mesh(verts)
+    P = problems.MixedPoisson(mo, r) if which == "poisson" else problems.Hodge1(mo, r)
+    n = gym.gym_op_ndofs(op)
+    x = synth.random_vector(n, seed=6, nrhs=2)
+    y = torch.empty(2 * n, dtype=torch.float64, device=DEV)
+    gym.gym_op_apply(op, gym.GYM_F64, 2, _t(x), y)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy().reshape(2, -1)
+    for k in range(2):
+        assert _rel(got[k], P.A @ x.reshape(2, -1)[k]) < 1e-13, f"rhs {k}"
+    y32 = torch.empty(2 * n, dtype=torch.float32, device=DEV)
+    gym.gym_op_apply(op, gym.GYM_F32, 2, torch.tensor(x, dtype=torch.float32, device=DEV), y32)
+    torch.cuda.synchronize()
+    assert _rel(y32.cpu().numpy().reshape(2, -1)[1].astype(np.float64), P.A @ x.reshape(2, -1)[1]) < 5e-5
+    gym.gym_ctx_set(ctx, gym.GYM_OPT_TILE, 0)
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
+@pytest.mark.parametrize("mode", ["f64", "ir_f32"])
+def test_solve_curved_hodge(g, mode):
+    gym, ctx = g
+    nel, r = (3, 4, 3), 3
+    verts = synth.perturbed_vertices(nel, 0.15, seed=0)
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts)
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, r)
+    P = problems.Hodge1(Mesh(verts), r)
+    n = P.A.shape[0]
+    nrhs = 3
+    b = synth.random_vector(n, seed=31, nrhs=nrhs)
+    x = torch.empty(nrhs * n, dtype=torch.float64, device=DEV)
+    opts = gym.gym_solve_opts_default()
+    opts.rtol = 1e-13 if mode == "f64" else 1e-12
+    if mode == "ir_f32":
+        opts.mode = gym.GYM_MODE_IR_F32
+    info = gym.gym_solve(op, opts, nrhs, _t(b), x)
+    got = x.cpu().numpy().reshape(nrhs, -1)
+    tol = 1e-10 if mode == "f64" else 1e-8
+    for k in range(nrhs):
+        ref = problems.solve_direct(P.A, b.reshape(nrhs, -1)[k])
+        err = np.linalg.norm(got[k] - ref) / np.linalg.norm(ref)
+        assert err < tol, f"rhs {k}: {err} (iters {info.iters}, outer {info.outer_iters})"
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
