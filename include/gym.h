@@ -225,9 +225,12 @@ typedef struct gym_request {
   int nel;               /* cubic mesh nel^3 on the unit cube                */
   int degree;            /* 1..3                                             */
   uint64_t seed;         /* right-hand side: N(0,1) on the second block,
-                            zero on the first, drawn by the server with a
-                            counter-based generator (see DESIGN)             */
-  const double* rhs;     /* optional HOST rhs (op ndofs); overrides seed      */
+                            zero on the first: SplitMix64 words
+                            z_k = mix(seed + (k+1) 0x9E3779B97F4A7C15),
+                            u = (z >> 11) 2^-53, Box-Muller on pairs        */
+  const double* rhs;     /* optional HOST rhs (op ndofs); overrides seed;
+                            copied at submit                                */
+  int want_solution;     /* 1: keep x on the host until polled             */
 } gym_request;
 
 typedef struct gym_result {
@@ -238,13 +241,19 @@ typedef struct gym_result {
   int64_t ndofs;
 } gym_result;
 
+/* Start the serving loop on opts->device: a host thread that admits
+ * requests while fewer than max_slots are active and their device memory
+ * (vectors + operator) fits mem_budget, runs one batched MINRES step of all
+ * active requests per turn, and retires converged ones (rel. residual <=
+ * rtol, true FP64 residual) so that queued requests enter the mix. */
 int gym_serve_start(const gym_serve_opts* opts, gym_server** out);
 /* Enqueue a request; returns its id.  Errors: GYM_E_OOM if one request
  * alone exceeds the memory budget. */
 int gym_serve_submit(gym_server* srv, const gym_request* req, uint64_t* id);
-/* Non-blocking.  If x_host is not NULL and the result is ready, the
- * solution (op ndofs doubles) is copied there.  Returns 0 when the result
- * is ready, 2 while pending. */
+/* Non-blocking.  If x_host is not NULL, the result is ready and the request
+ * asked for its solution, the solution (op ndofs doubles) is copied there.
+ * Returns 0 when the result is ready (the result is then released), 2 while
+ * pending.  res->status carries the request's own status. */
 int gym_serve_poll(gym_server* srv, uint64_t id, gym_result* res,
                    double* x_host);
 /* Drain: wait for all submitted requests, then stop the loop. */

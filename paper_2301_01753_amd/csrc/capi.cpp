@@ -236,9 +236,12 @@ void curved_scales(OpParams& p) {
   for (double& v : p.sc) v = 1.0;
 }
 
-int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
+}  // namespace
+
+// Kernel parameters of a block operator apply (shared with the server).
+void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int& prob) {
   const gym_mesh* m = op->mesh;
-  OpParams p{};
+  p = OpParams{};
   set_form(p, op->ctx, m);
   p.x = x;
   p.y = y;
@@ -249,7 +252,6 @@ int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y
     p.nel[a] = a < m->dim ? (int)m->nel[a] : 1;
     p.m[a] = a < m->dim ? (int)(op->r * m->nel[a]) : 1;
   }
-  int prob;
   if (op->problem == GYM_MIXED_POISSON) {
     prob = PROB_POISSON;
     for (int c = 0; c < m->dim; ++c) p.sc[c] = metric_const(GYM_HDIV, c, m);
@@ -263,11 +265,19 @@ int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y
     }
   }
   if (m->curved) curved_scales(p);
-  int rc = launch_operator(prob, m->dim, op->r, prec, p, nrhs, op->ctx->ncu, s);
+}
+
+int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
+  OpParams p;
+  int prob;
+  build_op_params(op, x, y, p, prob);
+  int rc = launch_operator(prob, op->mesh->dim, op->r, prec, p, nrhs, op->ctx->ncu, s);
   if (rc == -2) return fail(GYM_E_UNSUPPORTED, "no kernel for this problem/degree/precision");
   if (rc) return fail(GYM_E_HIP, "operator kernel launch failed");
   return 0;
 }
+
+namespace {
 
 int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
   const gym_mesh* m = sp->mesh;
@@ -453,6 +463,85 @@ struct OpWork {
   std::vector<void*> pool;
 };
 
+// Workspace of CG mass solves, cached on the space.
+struct MassWork {
+  int nrhs = 0, nb = 0;
+  double *r = nullptr, *p = nullptr, *q = nullptr, *pa = nullptr, *pb = nullptr, *sums = nullptr;
+  CgState* st = nullptr;
+  CgState* host = nullptr;
+  std::vector<void*> pool;
+};
+
+// Diagonal of M_k on an affine box (Kronecker product of 1-D diagonals);
+// on curved cells it is the diagonal of the box with the same spacing,
+// which only serves as the Jacobi preconditioner.
+std::vector<double> mass_diag_host(const gym_space* sp) {
+  const gym_mesh* m = sp->mesh;
+  const SpaceDesc& s = sp->desc;
+  std::vector<Diag1D> D;
+  for (int a = 0; a < 3; ++a) D.push_back(diag1d(s.r, a < m->dim ? m->nel[a] : 1));
+  std::vector<double> out(s.ndofs);
+  for (int c = 0; c < s.ncomp; ++c) {
+    const CompDesc& cd = s.comp[c];
+    const double sc = metric_const(s.kind, c, m);
+    int64_t idx = cd.offset;
+    for (int64_t k = 0; k < cd.count[2]; ++k)
+      for (int64_t j = 0; j < cd.count[1]; ++j)
+        for (int64_t i = 0; i < cd.count[0]; ++i) {
+          int64_t p[3] = {cd.start[0] + i, cd.start[1] + j, cd.start[2] + k};
+          double v = sc;
+          for (int a = 0; a < m->dim; ++a) v *= (cd.nodal_mask >> a & 1) ? D[a].dn[p[a]] : D[a].de[p[a]];
+          out[idx++] = v;
+        }
+  }
+  return out;
+}
+
+int ensure_mass_work(gym_space* sp, int nrhs, MassWork** out) {
+  if (!sp->work.empty() && sp->work_nrhs == nrhs) {
+    *out = (MassWork*)sp->work[0];
+    return 0;
+  }
+  if (!sp->work.empty()) {
+    MassWork* old = (MassWork*)sp->work[0];
+    for (void* p : old->pool) (void)hipFree(p);
+    if (old->host) (void)hipHostFree(old->host);
+    delete old;
+    sp->work.clear();
+  }
+  const long long n = sp->desc.ndofs;
+  MassWork* w = new MassWork;
+  sp->work.push_back(w);
+  sp->work_nrhs = nrhs;
+  w->nrhs = nrhs;
+  w->nb = vec_grid(n, sp->ctx->ncu);
+  double** vecs[3] = {&w->r, &w->p, &w->q};
+  for (double** v : vecs) {
+    void* p;
+    if (int rc = dalloc(&p, sizeof(double) * n * nrhs)) return rc;
+    w->pool.push_back(p);
+    *v = (double*)p;
+  }
+  void* p;
+  if (int rc = dalloc(&p, sizeof(double) * (2 * w->nb * nrhs + 2 * nrhs))) return rc;
+  w->pool.push_back(p);
+  w->pa = (double*)p;
+  w->pb = w->pa + w->nb * nrhs;
+  w->sums = w->pb + w->nb * nrhs;
+  if (int rc = dalloc(&p, sizeof(CgState) * 2 * nrhs)) return rc;
+  w->pool.push_back(p);
+  w->st = (CgState*)p;
+  GYM_HIP(hipHostMalloc((void**)&w->host, sizeof(CgState) * 2 * nrhs, hipHostMallocDefault));
+  if (!sp->d_diag) {
+    std::vector<double> d = mass_diag_host(sp);
+    for (double& v : d) v = 1.0 / v;
+    if (int rc = dalloc((void**)&sp->d_diag, sizeof(double) * n)) return rc;
+    GYM_HIP(hipMemcpy(sp->d_diag, d.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+  }
+  *out = w;
+  return 0;
+}
+
 }  // namespace gym
 
 using namespace gym;
@@ -566,7 +655,12 @@ int64_t gym_space_ndofs(const gym_space* s) { return s ? s->desc.ndofs : -1; }
 int gym_space_destroy(gym_space* s) {
   if (!s) return GYM_OK;
   if (s->d_diag) (void)hipFree(s->d_diag);
-  for (void* p : s->work) (void)hipFree(p);
+  if (!s->work.empty()) {
+    MassWork* w = (MassWork*)s->work[0];
+    for (void* p : w->pool) (void)hipFree(p);
+    if (w->host) (void)hipHostFree(w->host);
+    delete w;
+  }
   delete s;
   return GYM_OK;
 }
@@ -908,9 +1002,77 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
   return status;
 }
 
-int gym_mass_solve(const gym_space* space, const gym_solve_opts* opts_in, int nrhs, const double* b, double* x,
+int gym_mass_solve(const gym_space* space_c, const gym_solve_opts* opts_in, int nrhs, const double* b, double* x,
                    gym_solve_info* info, void* stream) {
-  return fail(GYM_E_UNSUPPORTED, "mass solve not built yet");
+  auto t0 = std::chrono::steady_clock::now();
+  if (!space_c || !b || !x || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
+  gym_space* space = const_cast<gym_space*>(space_c);  // workspace cache only
+  gym_solve_opts opts;
+  if (opts_in) opts = *opts_in;
+  else gym_solve_opts_default(&opts);
+  if (opts.mode != GYM_MODE_F64) return fail(GYM_E_UNSUPPORTED, "mass solves run in FP64");
+  hipStream_t s = (hipStream_t)stream;
+  const long long n = space->desc.ndofs;
+  MassWork* w;
+  if (int rc = ensure_mass_work(space, nrhs, &w)) return rc;
+  auto apply = [&](const double* in, double* out) { return launch_mass_apply(space, GYM_F64, nrhs, in, out, s); };
+  CgVecs<double> V{b, x, w->r, w->p, w->q};
+  cg_launch_init<double>(V, space->d_diag, n, nrhs, w->nb, w->pa, w->st, opts.rtol, s);
+  int it = 0;
+  const int every = opts.check_every < 1 ? 1 : opts.check_every;
+  gym_solve_info inf{};
+  int flag = 1;
+  std::vector<double> h(2 * nrhs);
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    bool all_done = false;
+    while (it < opts.maxit && !all_done) {
+      CgState* cur = w->st + (it & 1) * nrhs;
+      CgState* next = w->st + ((it + 1) & 1) * nrhs;
+      if (int rc = apply(V.p, V.q)) return rc;
+      cg_launch_iter_tail<double>(V, space->d_diag, n, nrhs, w->nb, cur, next, w->pa, w->pb, s);
+      ++it;
+      if (it % every == 0 || it == opts.maxit) {
+        GYM_HIP(hipMemcpyAsync(w->host, next, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, s));
+        GYM_HIP(hipStreamSynchronize(s));
+        all_done = true;
+        for (int r = 0; r < nrhs; ++r) all_done = all_done && w->host[r].done;
+      }
+    }
+    GYM_HIP(hipGetLastError());
+    // true relative residual ||b - M x|| / ||b|| (q is scratch here: the next
+    // iteration overwrites it with M p)
+    if (int rc = apply(x, w->q)) return rc;
+    launch_norm2(w->q, b, n, nrhs, w->nb, 1, w->pa, w->sums, s);
+    launch_norm2(b, nullptr, n, nrhs, w->nb, 0, w->pa, w->sums + nrhs, s);
+    GYM_HIP(hipMemcpyAsync(h.data(), w->sums, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, s));
+    GYM_HIP(hipStreamSynchronize(s));
+    inf.rel_res = 0;
+    flag = 1;
+    for (int r = 0; r < nrhs; ++r) {
+      double bn = std::sqrt(h[nrhs + r]);
+      double rel = bn > 0 ? std::sqrt(h[r]) / bn : std::sqrt(h[r]);
+      inf.rel_res = std::max(inf.rel_res, rel);
+      if (w->host[r].flag < 0) flag = -1;
+    }
+    if (flag < 0 || inf.rel_res <= opts.rtol || it >= opts.maxit) break;
+    // the preconditioned criterion was optimistic: tighten, resume (the
+    // latest state is in slot it & 1)
+    CgState* latest = w->st + (it & 1) * nrhs;
+    GYM_HIP(hipMemcpyAsync(w->host, latest, sizeof(CgState) * nrhs, hipMemcpyDeviceToHost, s));
+    GYM_HIP(hipStreamSynchronize(s));
+    for (int r = 0; r < nrhs; ++r) {
+      w->host[r].tol *= 0.1;
+      w->host[r].done = 0;
+      w->host[r].flag = 0;
+    }
+    GYM_HIP(hipMemcpyAsync(latest, w->host, sizeof(CgState) * nrhs, hipMemcpyHostToDevice, s));
+  }
+  inf.iters = it;
+  inf.status = flag < 0 ? GYM_E_BREAKDOWN : (inf.rel_res <= opts.rtol ? GYM_OK : GYM_W_NOT_CONVERGED);
+  if (flag < 0) fail(GYM_E_BREAKDOWN, "CG breakdown (NaN or non-positive curvature)");
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return inf.status;
 }
 
 }  // extern "C"

@@ -56,6 +56,14 @@ SpaceDesc make_space_desc(int kind, int dim, const int64_t nel[3], int r, int bc
 
 }  // namespace gym
 
+struct gym_op;
+namespace gym {
+struct OpParams;
+// Parameters of one block-operator apply (capi.cpp), and the apply itself.
+void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int& prob);
+int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s);
+}  // namespace gym
+
 struct gym_ctx {
   int device = 0;
   int ncu = 0;

@@ -31,10 +31,11 @@ struct OpParams {
   DevSpace sa, sb;  // first / second block
   int nel[3];
   int m[3];         // lattice cells per axis (r * nel)
-  int tiles_x, tiles_y, chunk;
+  int tiles_x, tiles_y, chunk, nchunks;
   int kron;         // 1: Kronecker (1-D element matrix) form of the masses
   int curved;       // 1: per-Gauss-point metric from the vertex array
   const double* verts;  // (nel+1)^3 x 3 vertex coordinates (curved only)
+  const int* gate;      // batched launches: skip when *gate != 0 (a solve's done flag)
   int tile_budget;  // 0: one 160 KB workgroup per CU, 1: 40 KB workgroups
   double sc[8];     // constant pointwise metric factors (affine meshes)
 };
@@ -46,6 +47,11 @@ int launch_operator(int prob, int dim, int r, int prec, const OpParams& p, int n
 int launch_hodge(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
 int launch_poisson(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
 int launch_mass(int prob, int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
+// ragged batch of affine operators of one problem and degree (FP64)
+int launch_op_batch(int prob, int dim, int r, OpParams* plist_host, int* bstart_host, int nreq,
+                    OpParams* plist_dev, int* bstart_dev, int ncu, hipStream_t s);
+int launch_hodge_batch(int r, OpParams* ph, int* bh, int n, OpParams* pd, int* bd, int ncu, hipStream_t s);
+int launch_poisson_batch(int r, OpParams* ph, int* bh, int n, OpParams* pd, int* bd, int ncu, hipStream_t s);
 int upload_tables_hodge();
 int upload_tables_poisson();
 int upload_tables_mass();

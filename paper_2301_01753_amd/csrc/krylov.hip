@@ -47,6 +47,43 @@ __device__ __forceinline__ double reduce_partials(const double* part, int np, do
 }
 
 // ---- MINRES ---------------------------------------------------------------
+// Lanczos/Givens scalar recurrence of one MINRES step (Paige & Saunders),
+// given alfa = v.(A v - ...) and b2 = r2 . M^-1 r2; returns the update
+// coefficients and marks convergence (phibar <= tol beta1) or breakdown.
+__device__ __forceinline__ void minres_scalar_update(MinresState& s, double alfa, double b2, double& phi,
+                                                     double& denom, double& oldeps, double& delta, double& vinv) {
+  s.itn += 1;
+  const double oldb = s.beta;
+  const double beta = b2 > 0 ? sqrt(b2) : 0.0;
+  s.tnorm2 += alfa * alfa + oldb * oldb + beta * beta;
+  oldeps = s.epsln;
+  delta = s.cs * s.dbar + s.sn * alfa;
+  const double gbar = s.sn * s.dbar - s.cs * alfa;
+  const double epsln = s.sn * beta;
+  const double dbar = -s.cs * beta;
+  double gamma = sqrt(gbar * gbar + beta * beta);
+  gamma = gamma > 2.2e-308 ? gamma : 2.2e-308;
+  const double cs = gbar / gamma, sn = beta / gamma;
+  phi = cs * s.phibar;
+  const double phibar = sn * s.phibar;
+  denom = 1.0 / gamma;
+  s.oldb = oldb;
+  s.beta = beta;
+  s.epsln = epsln;
+  s.dbar = dbar;
+  s.cs = cs;
+  s.sn = sn;
+  s.phibar = phibar;
+  s.alfa = alfa;
+  if (b2 < 0 || !(b2 == b2) || !(phibar == phibar)) {
+    s.flag = -1;
+    s.done = 1;
+  } else if (phibar <= s.tol * s.beta1 || beta == 0.0) {
+    s.flag = 1;
+    s.done = 1;
+  }
+  vinv = beta > 0 ? 1.0 / beta : 0.0;
+}
 // init: r1 = r2 = b; y = dinv .* b; x = w = w1 = w2 = 0; partial (b . y)
 template <typename TV>
 __global__ void __launch_bounds__(kBT) minres_init_a(MinresVecs<TV> v, const double* __restrict__ dinv,
@@ -170,39 +207,10 @@ __global__ void __launch_bounds__(kBT) minres_k7(MinresVecs<TV> v, long long n, 
   const int np = gridDim.x;
   const double alfa = reduce_partials(part_a + rhs * np, np, sh);
   const double b2 = reduce_partials(part_b + rhs * np, np, sh);
-  s.itn += 1;
-  const double oldb = s.beta;
-  double beta = b2 > 0 ? sqrt(b2) : 0.0;
-  s.tnorm2 += alfa * alfa + oldb * oldb + beta * beta;
-  const double oldeps = s.epsln;
-  const double delta = s.cs * s.dbar + s.sn * alfa;
-  const double gbar = s.sn * s.dbar - s.cs * alfa;
-  const double epsln = s.sn * beta;
-  const double dbar = -s.cs * beta;
-  double gamma = sqrt(gbar * gbar + beta * beta);
-  gamma = gamma > 2.2e-308 ? gamma : 2.2e-308;
-  const double cs = gbar / gamma, sn = beta / gamma;
-  const double phi = cs * s.phibar;
-  const double phibar = sn * s.phibar;
-  const double denom = 1.0 / gamma;
-  s.oldb = oldb;
-  s.beta = beta;
-  s.epsln = epsln;
-  s.dbar = dbar;
-  s.cs = cs;
-  s.sn = sn;
-  s.phibar = phibar;
-  s.alfa = alfa;
-  if (b2 < 0 || !(b2 == b2) || !(phibar == phibar)) {
-    s.flag = -1;
-    s.done = 1;
-  } else if (phibar <= s.tol * s.beta1 || beta == 0.0) {
-    s.flag = 1;
-    s.done = 1;
-  }
+  double phi, denom, oldeps, delta, vinv;
+  minres_scalar_update(s, alfa, b2, phi, denom, oldeps, delta, vinv);
   if (blockIdx.x == 0 && threadIdx.x == 0) next[rhs] = s;
   const long long off = (long long)rhs * n;
-  const double vinv = beta > 0 ? 1.0 / beta : 0.0;
   for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
     double w1 = todbl(v.w2[off + i]);
     double w2 = todbl(v.w[off + i]);
@@ -461,5 +469,123 @@ template void cg_launch_init<double>(const CgVecs<double>&, const double*, long 
                                      CgState*, double, hipStream_t);
 template void cg_launch_iter_tail<double>(const CgVecs<double>&, const double*, long long, int, int,
                                           const CgState*, CgState*, double*, double*, hipStream_t);
+
+}  // namespace gym
+
+// ---- ragged batches (serving) ------------------------------------------------
+// One launch covers one MINRES step of several independent solves; every
+// request keeps its own block count, partial sums and state, so its result
+// is the same whether it runs alone or in a batch.
+namespace gym {
+
+__device__ __forceinline__ int find_item(const int* bstart, int nitem, int blk) {
+  int lo = 0, hi = nitem;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (bstart[mid] <= blk) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kBT) batch_k3(const MinresItem* items, const int* bstart, int nitem) {
+  __shared__ double sh[kBT];
+  const int i = find_item(bstart, nitem, blockIdx.x);
+  const MinresItem it = items[i];
+  const int blk = blockIdx.x - bstart[i];
+  const MinresState s = *it.cur;
+  if (s.done) return;
+  const double c = s.oldb > 0 ? s.beta / s.oldb : 0.0;
+  double acc = 0.0;
+  for (long long k = (long long)blk * kBT + threadIdx.x; k < it.n; k += (long long)it.nb * kBT) {
+    double yi = it.y[k] - c * it.r1[k];
+    it.y[k] = yi;
+    acc += it.v[k] * yi;
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) it.pa[blk] = t;
+}
+
+__global__ void __launch_bounds__(kBT) batch_k5(const MinresItem* items, const int* bstart, int nitem) {
+  __shared__ double sh[kBT];
+  const int i = find_item(bstart, nitem, blockIdx.x);
+  const MinresItem it = items[i];
+  const int blk = blockIdx.x - bstart[i];
+  const MinresState s = *it.cur;
+  if (s.done) return;
+  const double alfa = reduce_partials(it.pa, it.nb, sh);
+  const double c = alfa / s.beta;
+  double acc = 0.0;
+  for (long long k = (long long)blk * kBT + threadIdx.x; k < it.n; k += (long long)it.nb * kBT) {
+    double yi = it.y[k] - c * it.r2[k];
+    it.y[k] = yi;
+    double zi = it.dinv[k] * yi;
+    it.r1[k] = zi;  // z over the old r1
+    acc += yi * zi;
+  }
+  double t = block_sum(acc, sh);
+  if (threadIdx.x == 0) it.pb[blk] = t;
+}
+
+__global__ void __launch_bounds__(kBT) batch_k7(const MinresItem* items, const int* bstart, int nitem) {
+  __shared__ double sh[kBT];
+  const int i = find_item(bstart, nitem, blockIdx.x);
+  const MinresItem it = items[i];
+  const int blk = blockIdx.x - bstart[i];
+  MinresState s = *it.cur;
+  if (s.done) {
+    if (blk == 0 && threadIdx.x == 0) *it.next = s;
+    return;
+  }
+  const double alfa = reduce_partials(it.pa, it.nb, sh);
+  const double b2 = reduce_partials(it.pb, it.nb, sh);
+  double phi, denom, oldeps, delta, vinv;
+  minres_scalar_update(s, alfa, b2, phi, denom, oldeps, delta, vinv);
+  if (blk == 0 && threadIdx.x == 0) *it.next = s;
+  for (long long k = (long long)blk * kBT + threadIdx.x; k < it.n; k += (long long)it.nb * kBT) {
+    double wn = (it.v[k] - oldeps * it.w2[k] - delta * it.w[k]) * denom;
+    it.w1[k] = wn;
+    it.x[k] += phi * wn;
+    it.v[k] = it.r1[k] * vinv;  // next v from z (in the old r1 buffer)
+  }
+}
+
+// N(0,1) right-hand side from a counter-based generator: SplitMix64
+// (Steele, Lea & Flood 2014) gives 64-bit words z_k = mix(seed + (k+1) g),
+// g = 0x9E3779B97F4A7C15; u = (z >> 11) 2^-53; Box-Muller on (u_{2i}, u_{2i+1}):
+// b_i = sqrt(-2 log(1 - u_{2i})) cos(2 pi u_{2i+1}).  Entries below `first`
+// are zero (the first unknown block).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long seed, unsigned long long k) {
+  unsigned long long z = seed + (k + 1ULL) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+
+__global__ void __launch_bounds__(kBT) rhs_normal(double* b, long long first, long long n, unsigned long long seed) {
+  for (long long k = (long long)blockIdx.x * kBT + threadIdx.x; k < n; k += (long long)gridDim.x * kBT) {
+    if (k < first) {
+      b[k] = 0.0;
+      continue;
+    }
+    unsigned long long i = (unsigned long long)(k - first);
+    double u1 = (double)(splitmix64(seed, 2 * i) >> 11) * 0x1.0p-53;
+    double u2 = (double)(splitmix64(seed, 2 * i + 1) >> 11) * 0x1.0p-53;
+    b[k] = sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
+void launch_batch_step(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(batch_k3, dim3(nblocks), dim3(kBT), 0, s, items_dev, bstart_dev, nitem);
+}
+void launch_batch_k5(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(batch_k5, dim3(nblocks), dim3(kBT), 0, s, items_dev, bstart_dev, nitem);
+}
+void launch_batch_k7(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(batch_k7, dim3(nblocks), dim3(kBT), 0, s, items_dev, bstart_dev, nitem);
+}
+void launch_rhs_normal(double* b, long long first, long long n, unsigned long long seed, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(rhs_normal, dim3(nb), dim3(kBT), 0, s, b, first, n, seed);
+}
 
 }  // namespace gym

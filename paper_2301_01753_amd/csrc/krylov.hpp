@@ -26,6 +26,22 @@ struct CgVecs {
   TV *x, *r, *p, *q;  // q holds A p, then z = M^-1 r
 };
 
+// One request of a ragged MINRES batch (FP64); pointers follow the same
+// rotation as the single-request driver.
+struct MinresItem {
+  long long n;
+  int nb, pad;
+  double *x, *r1, *r2, *y, *v, *w, *w1, *w2;
+  const double* dinv;
+  double *pa, *pb;
+  MinresState *cur, *next;
+};
+
+void launch_batch_step(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s);
+void launch_batch_k5(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s);
+void launch_batch_k7(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s);
+void launch_rhs_normal(double* b, long long first, long long n, unsigned long long seed, int nb, hipStream_t s);
+
 int vec_grid(long long n, int ncu);
 
 template <typename TV>

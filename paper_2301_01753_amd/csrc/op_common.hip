@@ -61,6 +61,15 @@ int upload_tables() {
   return upload_tables_mass();
 }
 
+int launch_op_batch(int prob, int dim, int r, OpParams* plist_host, int* bstart_host, int nreq, OpParams* plist_dev,
+                    int* bstart_dev, int ncu, hipStream_t s) {
+  if (dim != 3) return -2;
+  if (prob == PROB_HODGE) return launch_hodge_batch(r, plist_host, bstart_host, nreq, plist_dev, bstart_dev, ncu, s);
+  if (prob == PROB_POISSON)
+    return launch_poisson_batch(r, plist_host, bstart_host, nreq, plist_dev, bstart_dev, ncu, s);
+  return -2;
+}
+
 int launch_operator(int prob, int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s) {
   if (prob == PROB_HODGE) return launch_hodge(dim, r, prec, p, nrhs, ncu, s);
   if (prob == PROB_POISSON) return launch_poisson(dim, r, prec, p, nrhs, ncu, s);

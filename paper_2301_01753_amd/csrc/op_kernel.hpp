@@ -314,23 +314,23 @@ __device__ __forceinline__ void vmass2(TC* const in[2], TC* const out[2], const 
   mass<C, T1, ADD, FORM == FORM_KRON>(in[1], out[1], sc[1], w.A, w.B, w.er);
 }
 
-// ---- the kernel ------------------------------------------------------------
+// ---- the kernel body -------------------------------------------------------
+// (bx, by, bz) = (tile, z-chunk, right-hand side) of this workgroup.
 template <class C, int PROB, int FORM, typename TV, typename TC>
-__global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
+__device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int bz, TC* smem) {
   using F = Fields<PROB, C::DIM>;
   using L = Layout<C, F, FORM>;
   constexpr int R = C::R;
   static_assert(FORM != FORM_CURVED || C::DIM == 3, "curved cells are 3-D");
-  __shared__ TC smem[L::total()];
 
   // XCD-aware tile order: consecutive hardware block ids go round-robin over
   // the 8 XCDs; remap so that each XCD receives a contiguous run of tiles.
   const int nt = p.tiles_x * p.tiles_y;
-  int b = blockIdx.x;
+  int b = bx;
   if (nt % 8 == 0) b = (b % 8) * (nt / 8) + b / 8;
   const int tx = b % p.tiles_x, ty = b / p.tiles_x;
   const int X0 = tx * C::BX, Y0 = ty * C::BY;
-  const int rhs = blockIdx.z;
+  const int rhs = bz;
   const TV* __restrict__ xin = reinterpret_cast<const TV*>(p.x) + (long long)rhs * p.ndofs;
   TV* __restrict__ yout = reinterpret_cast<TV*>(p.y) + (long long)rhs * p.ndofs;
   const int gx0 = R * (X0 - 1), gy0 = R * (Y0 - 1);
@@ -351,7 +351,7 @@ __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
 
   int zfirst = 0, zbeg = 0, zend = 1;
   if constexpr (C::DIM == 3) {
-    zfirst = blockIdx.y * p.chunk;
+    zfirst = by * p.chunk;
     zend = min(zfirst + p.chunk, p.nel[2]);
     zbeg = zfirst > 0 ? zfirst - 1 : 0;
   }
@@ -613,6 +613,34 @@ __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
   }
 }
 
+template <class C, int PROB, int FORM, typename TV, typename TC>
+__global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
+  __shared__ TC smem[Layout<C, Fields<PROB, C::DIM>, FORM>::total()];
+  op_body<C, PROB, FORM, TV, TC>(p, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+}
+
+// Ragged batch: one launch over the workgroups of several operators of the
+// same kind and degree (different meshes and vectors).  bstart holds the
+// prefix sums of the per-request workgroup counts (nreq + 1 entries).
+template <class C, int PROB, int FORM, typename TV, typename TC>
+__global__ void __launch_bounds__(kNT) op_kernel_batch(const OpParams* __restrict__ plist,
+                                                       const int* __restrict__ bstart, int nreq) {
+  __shared__ TC smem[Layout<C, Fields<PROB, C::DIM>, FORM>::total()];
+  const int blk = blockIdx.x;
+  int lo = 0, hi = nreq;  // bstart[lo] <= blk < bstart[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (bstart[mid] <= blk) lo = mid;
+    else hi = mid;
+  }
+  const OpParams p = plist[lo];
+  if (p.gate && *p.gate) return;  // that request has converged: leave its vectors alone
+  const int local = blk - bstart[lo];
+  const int nt = p.tiles_x * p.tiles_y;
+  const int bx = local % nt, r2 = local / nt;
+  op_body<C, PROB, FORM, TV, TC>(p, bx, r2 % p.nchunks, r2 / p.nchunks, smem);
+}
+
 // ---- tile-size selection ----------------------------------------------------
 // Largest square tile whose LDS footprint fits `budget` bytes (2..8 per side;
 // up to 16 in 2-D).  Two budgets are compiled: the whole 160 KB of a CU (one
@@ -634,18 +662,15 @@ struct TileSel {
                                                   : 1;
 };
 
-template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, int BUDGET>
-int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
-  constexpr int B = TileSel<DIM, R, PROB, FORM, TC, BUDGET>::B;
-  using C = Cfg<R, B, B, DIM>;
-  static_assert(Layout<C, Fields<PROB, DIM>, FORM>::total() * sizeof(TC) <= 160 * 1024, "LDS");
-  OpParams p = p0;
+// Tiles and z-chunks of one operator for tile size B; returns the number of
+// workgroups (tiles x chunks x nrhs).
+inline int op_tiling(OpParams& p, int B, int dim, int nrhs, int ncu) {
   p.tiles_x = (p.nel[0] + B - 1) / B;
   p.tiles_y = (p.nel[1] + B - 1) / B;
   const int nt = p.tiles_x * p.tiles_y;
   int nchunks = 1;
   p.chunk = 1;
-  if (DIM == 3) {
+  if (dim == 3) {
     // enough workgroups for two per CU, but chunks of at least 4 layers so
     // that the recomputed halo layer costs at most a quarter
     const int target = 2 * ncu;
@@ -656,8 +681,37 @@ int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
     p.chunk = (p.nel[2] + nchunks - 1) / nchunks;
     nchunks = (p.nel[2] + p.chunk - 1) / p.chunk;
   }
-  dim3 grid(nt, nchunks, nrhs);
+  p.nchunks = nchunks;
+  return nt * nchunks * nrhs;
+}
+
+template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, int BUDGET>
+int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
+  constexpr int B = TileSel<DIM, R, PROB, FORM, TC, BUDGET>::B;
+  using C = Cfg<R, B, B, DIM>;
+  static_assert(Layout<C, Fields<PROB, DIM>, FORM>::total() * sizeof(TC) <= 160 * 1024, "LDS");
+  OpParams p = p0;
+  op_tiling(p, B, DIM, nrhs, ncu);
+  dim3 grid(p.tiles_x * p.tiles_y, p.nchunks, nrhs);
   hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC>), grid, dim3(kNT), 0, stream, p);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Batched launch (affine Kronecker form, small tiles, one rhs per request):
+// tile each request, fill the device parameter list and prefix table, launch.
+template <int DIM, int R, int PROB, typename TV, typename TC>
+int launch_op_batch_r(OpParams* plist_host, int* bstart_host, int nreq, OpParams* plist_dev, int* bstart_dev,
+                      int ncu, hipStream_t stream) {
+  constexpr int B = TileSel<DIM, R, PROB, FORM_KRON, TC, 40 * 1024>::B;
+  using C = Cfg<R, B, B, DIM>;
+  bstart_host[0] = 0;
+  for (int i = 0; i < nreq; ++i) bstart_host[i + 1] = bstart_host[i] + op_tiling(plist_host[i], B, DIM, 1, ncu);
+  if (hipMemcpyAsync(plist_dev, plist_host, sizeof(OpParams) * nreq, hipMemcpyHostToDevice, stream) != hipSuccess)
+    return -1;
+  if (hipMemcpyAsync(bstart_dev, bstart_host, sizeof(int) * (nreq + 1), hipMemcpyHostToDevice, stream) != hipSuccess)
+    return -1;
+  hipLaunchKernelGGL((op_kernel_batch<C, PROB, FORM_KRON, TV, TC>), dim3(bstart_host[nreq]), dim3(kNT), 0, stream,
+                     plist_dev, bstart_dev, nreq);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

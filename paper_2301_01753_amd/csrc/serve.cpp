@@ -1,34 +1,548 @@
-// Serving loop entry points (placeholder until the batching engine lands).
+// Serving loop: continuous batching of independent solves on one GPU.
+//
+// A persistent host thread owns the device work.  Each turn it
+//   1. admits queued requests while slots and the memory budget allow
+//      (device buffers are allocated here, never inside a step), builds or
+//      reuses the request's operator and starts its MINRES state;
+//   2. runs ONE MINRES step for every active request: one ragged operator
+//      launch per (problem, degree) group and one launch each of the three
+//      Krylov vector kernels over all active requests;
+//   3. every few steps reads all Krylov states back, retires converged
+//      requests (true FP64 residual, optional copy of the solution) and
+//      frees their memory, so queued requests can enter the mix.
+// Every request keeps its own blocks, partial sums and scalar state, so its
+// iterates are the same whether it runs alone or in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
 #include "gym_internal.hpp"
+#include "kernels.hpp"
+#include "krylov.hpp"
 
 using namespace gym;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+constexpr int kStages = 4;      // ring of per-step parameter uploads
+constexpr int kCheckEvery = 8;  // steps between reads of the Krylov states
+constexpr int kMaxGroups = 8;   // (problem, degree) pairs
+
+struct OpEntry {
+  gym_mesh* mesh = nullptr;
+  gym_op* op = nullptr;
+  int refs = 0;
+  size_t bytes = 0;
+};
+
+struct Pending {
+  uint64_t id;
+  gym_request req;
+  std::vector<double> rhs;
+  Clock::time_point t0;
+  int64_t n;
+  size_t bytes;
+};
+
+struct Slot {
+  uint64_t id;
+  int problem, degree;
+  bool want_x;
+  Clock::time_point t0;
+  OpEntry* op;
+  long long n;
+  int nb;
+  size_t bytes;
+  double *b, *x, *r1, *r2, *y, *v, *w, *w1, *w2, *pa, *pb;
+  void* mem;
+  int sidx;  // state pair index
+  int it;
+  int tighten;          // residual re-checks so far
+  double* R0[3];        // initial (r1, r2, y) buffers
+  double* W0[3];        // initial (w, w1, w2) buffers
+};
+
+struct Done {
+  gym_result res;
+  std::vector<double> x;
+};
+
+int64_t request_ndofs(const gym_request& r) {
+  int64_t nel[3] = {r.nel, r.nel, r.nel};
+  SpaceDesc a, b;
+  if (r.problem == GYM_MIXED_POISSON) {
+    a = make_space_desc(GYM_HDIV, 3, nel, r.degree, GYM_BC_NATURAL);
+    b = make_space_desc(GYM_L2, 3, nel, r.degree, GYM_BC_NATURAL);
+  } else {
+    a = make_space_desc(GYM_H1, 3, nel, r.degree, GYM_BC_ESSENTIAL);
+    b = make_space_desc(GYM_HCURL, 3, nel, r.degree, GYM_BC_ESSENTIAL);
+  }
+  return a.ndofs + b.ndofs;
+}
+
+// slot vectors (9), partial sums, plus the operator's preconditioner
+size_t request_bytes(int64_t n, int ncu) {
+  int nb = vec_grid(n, ncu);
+  return sizeof(double) * (9 * (size_t)n + 2 * (size_t)nb + 4) + sizeof(double) * (size_t)n;
+}
+
+}  // namespace
+
+struct gym_server {
+  gym_ctx* ctx = nullptr;
+  gym_serve_opts opts{};
+  hipStream_t stream = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Pending> queue;
+  std::unordered_map<uint64_t, Done> done;
+  std::unordered_map<uint64_t, int> pending;
+  std::vector<Slot*> active;
+  size_t bytes_used = 0;
+  bool stopping = false;
+  uint64_t next_id = 1;
+  std::map<std::tuple<int, int, int>, OpEntry*> ops;
+  MinresState* d_states = nullptr;
+  MinresState* h_states = nullptr;
+  std::vector<int> free_sidx;
+  OpParams* plist_h[kStages] = {};
+  OpParams* plist_d[kStages] = {};
+  int* bst_h[kStages] = {};
+  int* bst_d[kStages] = {};
+  MinresItem* items_h[kStages] = {};
+  MinresItem* items_d[kStages] = {};
+  int* ibst_h[kStages] = {};
+  int* ibst_d[kStages] = {};
+  hipEvent_t ev[kStages] = {};
+  int stage = 0;
+  int fatal = 0;
+  std::string fatal_msg;
+};
+
+namespace {
+
+int record_fatal(gym_server* s, int code) {
+  s->fatal = code;
+  s->fatal_msg = gym_last_error();
+  return code;
+}
+
+OpEntry* get_op(gym_server* s, int problem, int nel, int degree, int* rc) {
+  auto key = std::make_tuple(problem, nel, degree);
+  auto it = s->ops.find(key);
+  if (it != s->ops.end()) return it->second;
+  OpEntry* e = new OpEntry;
+  int64_t n3[3] = {nel, nel, nel};
+  *rc = gym_mesh_create(s->ctx, 3, n3, nullptr, nullptr, nullptr, &e->mesh);
+  if (*rc) {
+    delete e;
+    return nullptr;
+  }
+  *rc = gym_op_create(s->ctx, problem, e->mesh, degree, &e->op);
+  if (*rc) {
+    gym_mesh_destroy(e->mesh);
+    delete e;
+    return nullptr;
+  }
+  e->bytes = sizeof(double) * (size_t)gym_op_ndofs(e->op);
+  s->ops[key] = e;
+  s->bytes_used += e->bytes;
+  return e;
+}
+
+// free cached operators nobody uses until `need` more bytes fit
+void evict_ops(gym_server* s, size_t need) {
+  for (auto it = s->ops.begin(); it != s->ops.end() && s->bytes_used + need > (size_t)s->opts.mem_budget;) {
+    OpEntry* e = it->second;
+    if (e->refs == 0) {
+      s->bytes_used -= e->bytes;
+      gym_op_destroy(e->op);
+      gym_mesh_destroy(e->mesh);
+      delete e;
+      it = s->ops.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+int admit(gym_server* s, Pending& p) {
+  int rc = 0;
+  OpEntry* e = get_op(s, p.req.problem, p.req.nel, p.req.degree, &rc);
+  if (!e) return rc;
+  Slot* sl = new Slot{};
+  sl->id = p.id;
+  sl->problem = p.req.problem;
+  sl->degree = p.req.degree;
+  sl->want_x = p.req.want_solution != 0;
+  sl->t0 = p.t0;
+  sl->op = e;
+  sl->n = p.n;
+  sl->nb = vec_grid(p.n, s->ctx->ncu);
+  sl->bytes = sizeof(double) * (9 * (size_t)p.n + 2 * (size_t)sl->nb + 4);
+  if (hipMalloc(&sl->mem, sl->bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete sl;
+    return fail(GYM_E_OOM, "serving: device allocation failed at admission");
+  }
+  double* base = (double*)sl->mem;
+  double** vecs[9] = {&sl->b, &sl->x, &sl->r1, &sl->r2, &sl->y, &sl->v, &sl->w, &sl->w1, &sl->w2};
+  for (int k = 0; k < 9; ++k) *vecs[k] = base + (size_t)k * p.n;
+  sl->pa = base + 9 * (size_t)p.n;
+  sl->pb = sl->pa + sl->nb;
+  sl->R0[0] = sl->r1, sl->R0[1] = sl->r2, sl->R0[2] = sl->y;
+  sl->W0[0] = sl->w, sl->W0[1] = sl->w1, sl->W0[2] = sl->w2;
+  sl->tighten = 0;
+  e->refs += 1;
+  s->bytes_used += sl->bytes;
+  sl->sidx = s->free_sidx.back();
+  s->free_sidx.pop_back();
+  sl->it = 0;
+  int64_t nblk[2];
+  gym_op_block_sizes(e->op, nblk);
+  if (!p.rhs.empty()) {
+    GYM_HIP(hipMemcpyAsync(sl->b, p.rhs.data(), sizeof(double) * p.n, hipMemcpyHostToDevice, s->stream));
+    GYM_HIP(hipStreamSynchronize(s->stream));  // the host vector is released below
+  } else {
+    launch_rhs_normal(sl->b, nblk[0], p.n, p.req.seed, sl->nb, s->stream);
+  }
+  MinresVecs<double> V{sl->b, sl->x, sl->r1, sl->r2, sl->y, sl->v, sl->w, sl->w1, sl->w2};
+  minres_launch_init<double>(V, e->op->d_prec, p.n, 1, sl->nb, sl->pa, s->d_states + 2 * sl->sidx, s->opts.rtol,
+                             s->stream);
+  s->active.push_back(sl);
+  return 0;
+}
+
+// One MINRES step of every active request.
+int step(gym_server* s) {
+  const int st = s->stage = (s->stage + 1) % kStages;
+  GYM_HIP(hipEventSynchronize(s->ev[st]));
+  // operator applies, one ragged launch per (problem, degree)
+  std::map<std::pair<int, int>, std::vector<Slot*>> groups;
+  for (Slot* sl : s->active) groups[{sl->problem, sl->degree}].push_back(sl);
+  int off = 0, boff = 0;
+  for (auto& g : groups) {
+    const auto& list = g.second;
+    int prob = 0;
+    for (size_t i = 0; i < list.size(); ++i) {
+      build_op_params(list[i]->op->op, list[i]->v, list[i]->y, s->plist_h[st][off + i], prob);
+      // the done flag of this step's current state gates the apply
+      s->plist_h[st][off + i].gate = &(s->d_states + 2 * list[i]->sidx + (list[i]->it & 1))->done;
+    }
+    int rc = launch_op_batch(prob, 3, g.first.second, s->plist_h[st] + off, s->bst_h[st] + boff, (int)list.size(),
+                             s->plist_d[st] + off, s->bst_d[st] + boff, s->ctx->ncu, s->stream);
+    if (rc) return fail(GYM_E_HIP, "serving: batched operator launch failed");
+    off += (int)list.size();
+    boff += (int)list.size() + 1;
+  }
+  // Krylov vector kernels over all requests
+  const int na = (int)s->active.size();
+  int nblocks = 0;
+  for (int i = 0; i < na; ++i) {
+    Slot* sl = s->active[i];
+    MinresItem& it = s->items_h[st][i];
+    it.n = sl->n;
+    it.nb = sl->nb;
+    it.x = sl->x;
+    it.r1 = sl->r1;
+    it.r2 = sl->r2;
+    it.y = sl->y;
+    it.v = sl->v;
+    it.w = sl->w;
+    it.w1 = sl->w1;
+    it.w2 = sl->w2;
+    it.dinv = sl->op->op->d_prec;
+    it.pa = sl->pa;
+    it.pb = sl->pb;
+    it.cur = s->d_states + 2 * sl->sidx + (sl->it & 1);
+    it.next = s->d_states + 2 * sl->sidx + ((sl->it + 1) & 1);
+    s->ibst_h[st][i] = nblocks;
+    nblocks += sl->nb;
+  }
+  s->ibst_h[st][na] = nblocks;
+  GYM_HIP(hipMemcpyAsync(s->items_d[st], s->items_h[st], sizeof(MinresItem) * na, hipMemcpyHostToDevice, s->stream));
+  GYM_HIP(hipMemcpyAsync(s->ibst_d[st], s->ibst_h[st], sizeof(int) * (na + 1), hipMemcpyHostToDevice, s->stream));
+  launch_batch_step(s->items_d[st], s->ibst_d[st], na, nblocks, s->stream);
+  launch_batch_k5(s->items_d[st], s->ibst_d[st], na, nblocks, s->stream);
+  launch_batch_k7(s->items_d[st], s->ibst_d[st], na, nblocks, s->stream);
+  GYM_HIP(hipEventRecord(s->ev[st], s->stream));
+  GYM_HIP(hipGetLastError());
+  // the same rotation as the single-request driver
+  for (Slot* sl : s->active) {
+    double* r1 = sl->r1;
+    sl->r1 = sl->r2;
+    sl->r2 = sl->y;
+    sl->y = r1;
+    double *w = sl->w, *w1 = sl->w1, *w2 = sl->w2;
+    sl->w = w1;
+    sl->w1 = w2;
+    sl->w2 = w;
+    sl->it += 1;
+  }
+  return 0;
+}
+
+// Buffer roles after k real MINRES iterations (the host kept rotating while
+// the request sat converged on the device, but no kernel touched it).
+void roles_from_itn(Slot* sl, int k) {
+  sl->r1 = sl->R0[k % 3];
+  sl->r2 = sl->R0[(k + 1) % 3];
+  sl->y = sl->R0[(k + 2) % 3];
+  sl->w = sl->W0[k % 3];
+  sl->w1 = sl->W0[(k + 1) % 3];
+  sl->w2 = sl->W0[(k + 2) % 3];
+}
+
+// true relative residual ||b - A x|| / ||b|| in FP64 (y and the partial-sum
+// buffers are scratch between iterations)
+int true_relres(gym_server* s, Slot* sl, double* rel) {
+  if (int rc = launch_op_apply(sl->op->op, GYM_F64, 1, sl->x, sl->y, s->stream)) return rc;
+  double* sums = sl->pb + sl->nb;
+  launch_norm2(sl->y, sl->b, sl->n, 1, sl->nb, 1, sl->pa, sums, s->stream);
+  launch_norm2(sl->b, nullptr, sl->n, 1, sl->nb, 0, sl->pa, sums + 1, s->stream);
+  double h[2];
+  GYM_HIP(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+  GYM_HIP(hipStreamSynchronize(s->stream));
+  double bn = std::sqrt(h[1]);
+  *rel = bn > 0 ? std::sqrt(h[0]) / bn : std::sqrt(h[0]);
+  return 0;
+}
+
+int retire(gym_server* s, Slot* sl, const MinresState& ms, double rel) {
+  Done d;
+  if (sl->want_x) {
+    d.x.resize(sl->n);
+    GYM_HIP(hipMemcpyAsync(d.x.data(), sl->x, sizeof(double) * sl->n, hipMemcpyDeviceToHost, s->stream));
+    GYM_HIP(hipStreamSynchronize(s->stream));
+  }
+  d.res.rel_res = rel;
+  d.res.iters = ms.itn;
+  d.res.ndofs = sl->n;
+  d.res.status = ms.flag < 0 ? GYM_E_BREAKDOWN : (d.res.rel_res <= s->opts.rtol ? GYM_OK : GYM_W_NOT_CONVERGED);
+  d.res.latency_s = std::chrono::duration<double>(Clock::now() - sl->t0).count();
+  (void)hipFree(sl->mem);
+  s->bytes_used -= sl->bytes;
+  sl->op->refs -= 1;
+  s->free_sidx.push_back(sl->sidx);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->pending.erase(sl->id);
+    s->done[sl->id] = std::move(d);
+  }
+  s->cv.notify_all();
+  return 0;
+}
+
+int check_and_retire(gym_server* s) {
+  if (s->active.empty()) return 0;
+  const int maxs = s->opts.max_slots;
+  GYM_HIP(hipMemcpyAsync(s->h_states, s->d_states, sizeof(MinresState) * 2 * maxs, hipMemcpyDeviceToHost, s->stream));
+  GYM_HIP(hipStreamSynchronize(s->stream));
+  std::vector<Slot*> keep;
+  for (Slot* sl : s->active) {
+    MinresState ms = s->h_states[2 * sl->sidx + (sl->it & 1)];
+    if (ms.done || sl->it >= s->opts.maxit) {
+      roles_from_itn(sl, ms.itn);
+      double rel = 0;
+      if (int rc = true_relres(s, sl, &rel)) return rc;
+      if (rel > s->opts.rtol && ms.flag >= 0 && sl->it < s->opts.maxit && sl->tighten < 6) {
+        // the preconditioned estimate was optimistic: tighten and resume
+        sl->tighten += 1;
+        ms.tol *= 0.1;
+        ms.done = 0;
+        ms.flag = 0;
+        MinresState pair[2] = {ms, ms};
+        GYM_HIP(hipMemcpyAsync(s->d_states + 2 * sl->sidx, pair, sizeof(pair), hipMemcpyHostToDevice, s->stream));
+        GYM_HIP(hipStreamSynchronize(s->stream));
+        keep.push_back(sl);
+        continue;
+      }
+      if (int rc = retire(s, sl, ms, rel)) return rc;
+      delete sl;
+    } else {
+      keep.push_back(sl);
+    }
+  }
+  s->active.swap(keep);
+  return 0;
+}
+
+void loop(gym_server* s) {
+  if (hipSetDevice(s->ctx->device) != hipSuccess) {
+    record_fatal(s, GYM_E_HIP);
+    return;
+  }
+  int steps = 0;
+  for (;;) {
+    // admission
+    for (;;) {
+      Pending p;
+      {
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->queue.empty() || (int)s->active.size() >= s->opts.max_slots) break;
+        Pending& f = s->queue.front();
+        size_t need = f.bytes;
+        lk.unlock();
+        if (s->bytes_used + need > (size_t)s->opts.mem_budget) evict_ops(s, need);
+        lk.lock();
+        if (s->bytes_used + need > (size_t)s->opts.mem_budget) break;
+        p = std::move(s->queue.front());
+        s->queue.pop_front();
+      }
+      if (int rc = admit(s, p)) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        Done d;
+        d.res.status = rc;
+        s->pending.erase(p.id);
+        s->done[p.id] = std::move(d);
+        s->cv.notify_all();
+      }
+    }
+    if (s->active.empty()) {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (s->stopping && s->queue.empty()) break;
+      s->cv.wait_for(lk, std::chrono::milliseconds(1));
+      continue;
+    }
+    if (step(s)) {
+      record_fatal(s, GYM_E_HIP);
+      return;
+    }
+    if (++steps % kCheckEvery == 0) {
+      if (check_and_retire(s)) {
+        record_fatal(s, GYM_E_HIP);
+        return;
+      }
+    }
+  }
+}
+
+}  // namespace
 
 extern "C" {
 
 int gym_serve_start(const gym_serve_opts* opts, gym_server** out) {
-  (void)opts;
-  if (out) *out = nullptr;
-  return fail(GYM_E_UNSUPPORTED, "serving loop not built yet");
+  if (!opts || !out) return fail(GYM_E_ARG, "NULL argument");
+  if (opts->max_slots < 1 || opts->max_slots > 4096 || opts->mem_budget <= 0 || opts->maxit < 1 || !(opts->rtol > 0))
+    return fail(GYM_E_ARG, "bad serving options");
+  gym_server* s = new gym_server;
+  s->opts = *opts;
+  if (int rc = gym_create(&s->ctx, opts->device)) {
+    delete s;
+    return rc;
+  }
+  GYM_HIP(hipStreamCreate(&s->stream));
+  const int maxs = opts->max_slots;
+  GYM_HIP(hipMalloc(&s->d_states, sizeof(MinresState) * 2 * maxs));
+  GYM_HIP(hipHostMalloc((void**)&s->h_states, sizeof(MinresState) * 2 * maxs, hipHostMallocDefault));
+  for (int i = maxs - 1; i >= 0; --i) s->free_sidx.push_back(i);
+  for (int k = 0; k < kStages; ++k) {
+    GYM_HIP(hipHostMalloc((void**)&s->plist_h[k], sizeof(OpParams) * maxs, hipHostMallocDefault));
+    GYM_HIP(hipMalloc(&s->plist_d[k], sizeof(OpParams) * maxs));
+    GYM_HIP(hipHostMalloc((void**)&s->bst_h[k], sizeof(int) * (maxs + kMaxGroups + 1), hipHostMallocDefault));
+    GYM_HIP(hipMalloc(&s->bst_d[k], sizeof(int) * (maxs + kMaxGroups + 1)));
+    GYM_HIP(hipHostMalloc((void**)&s->items_h[k], sizeof(MinresItem) * maxs, hipHostMallocDefault));
+    GYM_HIP(hipMalloc(&s->items_d[k], sizeof(MinresItem) * maxs));
+    GYM_HIP(hipHostMalloc((void**)&s->ibst_h[k], sizeof(int) * (maxs + 1), hipHostMallocDefault));
+    GYM_HIP(hipMalloc(&s->ibst_d[k], sizeof(int) * (maxs + 1)));
+    GYM_HIP(hipEventCreate(&s->ev[k]));
+    GYM_HIP(hipEventRecord(s->ev[k], s->stream));
+  }
+  s->th = std::thread(loop, s);
+  *out = s;
+  return GYM_OK;
 }
 
-int gym_serve_submit(gym_server* srv, const gym_request* req, uint64_t* id) {
-  (void)srv;
-  (void)req;
-  (void)id;
-  return fail(GYM_E_UNSUPPORTED, "serving loop not built yet");
+int gym_serve_submit(gym_server* s, const gym_request* req, uint64_t* id) {
+  if (!s || !req || !id) return fail(GYM_E_ARG, "NULL argument");
+  if ((req->problem != GYM_MIXED_POISSON && req->problem != GYM_HODGE1) || req->nel < 1 || req->nel > 1024 ||
+      req->degree < 1 || req->degree > kMaxR)
+    return fail(GYM_E_ARG, "bad request");
+  Pending p;
+  p.req = *req;
+  p.n = request_ndofs(*req);
+  p.bytes = request_bytes(p.n, s->ctx->ncu);
+  if (p.bytes > (size_t)s->opts.mem_budget) return fail(GYM_E_OOM, "request exceeds the server's memory budget");
+  if (req->rhs) p.rhs.assign(req->rhs, req->rhs + p.n);
+  p.req.rhs = nullptr;
+  p.t0 = Clock::now();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return fail(GYM_E_ARG, "server is stopping");
+    p.id = s->next_id++;
+    s->pending[p.id] = 1;
+    *id = p.id;
+    s->queue.push_back(std::move(p));
+  }
+  s->cv.notify_all();
+  return GYM_OK;
 }
 
-int gym_serve_poll(gym_server* srv, uint64_t id, gym_result* res, double* x_host) {
-  (void)srv;
-  (void)id;
-  (void)res;
-  (void)x_host;
-  return fail(GYM_E_UNSUPPORTED, "serving loop not built yet");
+int gym_serve_poll(gym_server* s, uint64_t id, gym_result* res, double* x_host) {
+  if (!s || !res) return fail(GYM_E_ARG, "NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->fatal) return fail(s->fatal, "serving loop stopped: " + s->fatal_msg);
+  auto it = s->done.find(id);
+  if (it == s->done.end()) {
+    if (s->pending.count(id)) {
+      res->status = 2;
+      return 2;
+    }
+    return fail(GYM_E_ARG, "unknown request id");
+  }
+  *res = it->second.res;
+  if (x_host && !it->second.x.empty()) std::copy(it->second.x.begin(), it->second.x.end(), x_host);
+  s->done.erase(it);
+  return 0;
 }
 
-int gym_serve_stop(gym_server* srv) {
-  (void)srv;
-  return fail(GYM_E_UNSUPPORTED, "serving loop not built yet");
+int gym_serve_stop(gym_server* s) {
+  if (!s) return GYM_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stopping = true;
+  }
+  s->cv.notify_all();
+  if (s->th.joinable()) s->th.join();
+  int rc = s->fatal;
+  for (Slot* sl : s->active) {
+    (void)hipFree(sl->mem);
+    delete sl;
+  }
+  for (auto& kv : s->ops) {
+    gym_op_destroy(kv.second->op);
+    gym_mesh_destroy(kv.second->mesh);
+    delete kv.second;
+  }
+  for (int k = 0; k < kStages; ++k) {
+    (void)hipHostFree(s->plist_h[k]);
+    (void)hipFree(s->plist_d[k]);
+    (void)hipHostFree(s->bst_h[k]);
+    (void)hipFree(s->bst_d[k]);
+    (void)hipHostFree(s->items_h[k]);
+    (void)hipFree(s->items_d[k]);
+    (void)hipHostFree(s->ibst_h[k]);
+    (void)hipFree(s->ibst_d[k]);
+    (void)hipEventDestroy(s->ev[k]);
+  }
+  (void)hipFree(s->d_states);
+  (void)hipHostFree(s->h_states);
+  (void)hipStreamDestroy(s->stream);
+  gym_destroy(s->ctx);
+  delete s;
+  return rc ? fail(rc, "serving loop had stopped on an error") : GYM_OK;
 }
 
 }  // extern "C"

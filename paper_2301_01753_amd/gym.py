@@ -58,7 +58,8 @@ class ServeOpts(ctypes.Structure):
 
 class Request(ctypes.Structure):
     _fields_ = [("problem", ctypes.c_int), ("nel", ctypes.c_int), ("degree", ctypes.c_int),
-                ("seed", ctypes.c_uint64), ("rhs", ctypes.POINTER(ctypes.c_double))]
+                ("seed", ctypes.c_uint64), ("rhs", ctypes.POINTER(ctypes.c_double)),
+                ("want_solution", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):

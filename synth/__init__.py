@@ -61,3 +61,30 @@ def modes_3d():
 
 def modes_2d():
     return [(a, b) for b in (1, 2) for a in (1, 2)]
+
+
+def _splitmix64(seed, k):
+    """SplitMix64 word k of stream `seed` (Steele, Lea & Flood 2014), vectorised."""
+    z = (np.uint64(seed) + (k.astype(np.uint64) + np.uint64(1)) * np.uint64(0x9E3779B97F4A7C15))
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+    return z ^ (z >> np.uint64(31))
+
+
+def counter_normal(seed, n, first=0):
+    """N(0, 1) vector of length n, zero below index `first`, from SplitMix64
+    words u = (z >> 11) 2^-53 and Box-Muller: b_i = sqrt(-2 log(1 - u_{2i}))
+    cos(2 pi u_{2i+1}) for i = k - first.  The serving loop draws the same
+    numbers on the GPU from the same published definitions."""
+    out = np.zeros(n)
+    m = n - first
+    if m <= 0:
+        return out
+    i = np.arange(m, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z1 = _splitmix64(seed, 2 * i)
+        z2 = _splitmix64(seed, 2 * i + np.uint64(1))
+    u1 = (z1 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    u2 = (z2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+    out[first:] = np.sqrt(-2.0 * np.log(1.0 - u1)) * np.cos(2.0 * np.pi * u2)
+    return out

@@ -424,3 +424,45 @@ def test_solve_curved_hodge(g, mode):
         assert err < tol, f"rhs {k}: {err} (iters {info.iters}, outer {info.outer_iters})"
     gym.gym_op_destroy(op)
     gym.gym_mesh_destroy(mesh)
+
+
+@pytest.mark.parametrize("curved", [False, True], ids=["affine", "curved"])
+def test_mass_solve_and_exact_feec_operator(g, curved):
+    # K a = M1^{-1} C^T M2 C a, the exact-FEEC curl-of-curl of section 3,
+    # composed from incidence, mass apply and the CG mass solve.
+    import scipy.sparse.linalg as spla
+    gym, ctx = g
+    nel, r = (4, 3, 5), 2
+    verts = synth.perturbed_vertices(nel, 0.15, seed=3) if curved else synth.uniform_vertices(nel)
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts if curved else None)
+    s1 = gym.gym_space_create(ctx, mesh, gym.GYM_HCURL, r, 0)
+    s2 = gym.gym_space_create(ctx, mesh, gym.GYM_HDIV, r, 0)
+    o1, o2 = Space("HCURL", nel, r), Space("HDIV", nel, r)
+    mo = Mesh(verts)
+    M1 = assembly.mass_matrix(o1, mo).tocsc()
+    M2 = assembly.mass_matrix(o2, mo)
+    C = incidence.curl(o1, o2).astype(np.float64)
+    opts = gym.gym_solve_opts_default()
+    opts.rtol = 1e-13
+    b = synth.random_vector(o1.ndofs, seed=2, nrhs=2)
+    x = torch.empty(2 * o1.ndofs, dtype=torch.float64, device=DEV)
+    info = gym.gym_mass_solve(s1, opts, 2, _t(b), x)
+    assert info.status == 0 and info.rel_res < 1e-13
+    for k in range(2):
+        ref = spla.spsolve(M1, b.reshape(2, -1)[k])
+        assert np.linalg.norm(x.cpu().numpy().reshape(2, -1)[k] - ref) / np.linalg.norm(ref) < 1e-11
+    a = _t(synth.random_vector(o1.ndofs, seed=9))
+    ca = torch.empty(o2.ndofs, dtype=torch.float64, device=DEV)
+    mca = torch.empty_like(ca)
+    p2a = torch.empty_like(a)
+    ka = torch.empty_like(a)
+    gym.gym_d_apply(s1, s2, 0, a, ca)
+    gym.gym_mass_apply(s2, gym.GYM_F64, 1, ca, mca)
+    gym.gym_d_apply(s1, s2, 1, mca, p2a)
+    gym.gym_mass_solve(s1, opts, 1, p2a, ka)
+    an = a.cpu().numpy()
+    ref = spla.spsolve(M1, C.T @ (M2 @ (C @ an)))
+    assert np.linalg.norm(ka.cpu().numpy() - ref) / np.linalg.norm(ref) < 1e-10
+    for s in (s1, s2):
+        gym.gym_space_destroy(s)
+    gym.gym_mesh_destroy(mesh)
