@@ -104,6 +104,47 @@ def cpu_baseline(nel, r, rtol):
     }
 
 
+def serving(gym, nreq, seed, max_slots, qps=None, budget=64 << 30):
+    """Run `nreq` mixed-Poisson requests (N ~ U{8..48}, r ~ U{1,2,3}, seeded
+    N(0,1) right-hand sides) through the serving loop.  qps=None submits
+    everything at t = 0; otherwise arrivals are a Poisson process."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    reqs = [(int(rng.integers(8, 49)), int(rng.integers(1, 4)), 1000 + k) for k in range(nreq)]
+    gaps = rng.exponential(1.0 / qps, nreq) if qps else np.zeros(nreq)
+    o = gym.ServeOpts(device=0, mem_budget=budget, max_slots=max_slots, rtol=1e-8, maxit=100000)
+    srv = gym.gym_serve_start(o)
+    t0 = time.perf_counter()
+    due = t0 + np.cumsum(gaps)
+    ids, done = {}, {}
+    k = 0
+    last_log = t0
+    while len(done) < nreq:
+        now = time.perf_counter()
+        while k < nreq and due[k] <= now:
+            nel, r, sd = reqs[k]
+            ids[gym.gym_serve_submit(srv, gym.Request(problem=0, nel=nel, degree=r, seed=sd, rhs=None,
+                                                      want_solution=0))] = k
+            k += 1
+        for rid in [i for i in ids if i not in done]:
+            st, res = gym.gym_serve_poll(srv, rid)
+            if st == 0:
+                done[rid] = res
+        if now - last_log > 10:
+            log(f"  serving: {len(done)}/{nreq} done")
+            last_log = now
+        time.sleep(0.0005)
+    wall = time.perf_counter() - t0
+    gym.gym_serve_stop(srv)
+    lat = np.array([r.latency_s for r in done.values()])
+    dof_it = sum(r.ndofs * r.iters for r in done.values())
+    bad = sum(1 for r in done.values() if r.status != 0)
+    return {"requests": nreq, "max_slots": max_slots, "qps": qps, "solves_per_s": nreq / wall,
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "gdof_s": dof_it / wall / 1e9, "wall_s": wall, "not_converged": bad,
+            "mean_ndofs": float(np.mean([r.ndofs for r in done.values()]))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +155,10 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--profile-apply", type=int, default=0,
+                    help="counter runs: copy calibration + this many applies, no JSON")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests in the serving sample (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -136,6 +181,21 @@ def main():
     b = torch.empty(n, dtype=torch.float64, device=dev)
     gym.gym_rhs_manufactured(op, modes, synth.fourier_coeffs(0, 8, 3), b)
     log(f"workload: {nel} degree {r} Hodge, {n} DoFs")
+
+    if args.profile_apply:
+        # counter runs: a plain copy of known size (calibrates FETCH_SIZE /
+        # WRITE_SIZE per byte), then operator applies on the bench workload
+        src = torch.empty(32 << 20, dtype=torch.float64, device=dev).normal_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        xv = torch.empty(n, dtype=torch.float64, device=dev).normal_()
+        yv = torch.empty_like(xv)
+        for _ in range(args.profile_apply):
+            gym.gym_op_apply(op, gym.GYM_F64, 1, xv, yv)
+        torch.cuda.synchronize()
+        log(f"profile-apply: copy of {src.numel() * 8} bytes x3, {args.profile_apply} applies")
+        return
 
     # FP64 reference (untimed), tight tolerance
     xref = torch.empty_like(b)
@@ -245,6 +305,21 @@ def main():
             "iters_per_solve": it_b / steps_b, "rel_res": worst_b,
             "apply_gdof_s": nb * n / (ms_b / ap_b / 1e3) / 1e9,
             "speedup_vs_fp64": (nb * steps_b / wall_b) / (args.steps / wall),
+        }
+
+    if args.serve_requests > 0:
+        # continuous batching vs one request at a time, same requests, same GPU
+        log("serving (batched) ...")
+        batched = serving(gym, args.serve_requests, 7, max_slots=32)
+        log("serving (one at a time) ...")
+        single = serving(gym, args.serve_requests, 7, max_slots=1)
+        log("serving (Poisson arrivals at half the batched rate) ...")
+        arrivals = serving(gym, args.serve_requests, 7, max_slots=32, qps=0.5 * batched["solves_per_s"])
+        out["serving"] = {
+            "workload": "mixed Poisson, N ~ U{8..48}^3 hex, degree ~ U{1,2,3}, N(0,1) rhs (seeded), "
+                        "rel. residual 1e-8",
+            "batched": batched, "one_at_a_time": single, "poisson_arrivals": arrivals,
+            "speedup_batched_vs_one_at_a_time": batched["solves_per_s"] / single["solves_per_s"],
         }
 
     if not args.no_cpu:
