@@ -221,11 +221,13 @@ int check_mesh_jacobians(const gym_mesh* m) {
   return 0;
 }
 
-void set_form(OpParams& p, const gym_ctx* ctx, const gym_mesh* m) {
+void set_form(OpParams& p, const gym_ctx* ctx, const gym_mesh* m, int r) {
   p.kron = (ctx->mass_form == 0 && !m->curved) ? 1 : 0;
-  // auto: small tiles on affine cells (latency hiding), large ones on curved
-  // cells where the per-Gauss-point work outweighs the LDS latency
-  p.tile_budget = (ctx->tile == 1 || (ctx->tile == 0 && m->curved)) ? 0 : 1;
+  // auto (measured on MI355X): small tiles for affine cells up to degree 2
+  // (more workgroups per CU hide LDS latency); large tiles for degree >= 3
+  // and for curved cells, where small tiles would recompute most of the halo
+  const bool large = ctx->tile == 1 || (ctx->tile == 0 && (m->curved || r >= 3));
+  p.tile_budget = large ? 0 : 1;
   p.curved = m->curved ? 1 : 0;
   p.verts = m->d_vertices;
 }
@@ -242,7 +244,7 @@ void curved_scales(OpParams& p) {
 void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int& prob) {
   const gym_mesh* m = op->mesh;
   p = OpParams{};
-  set_form(p, op->ctx, m);
+  set_form(p, op->ctx, m, op->r);
   p.x = x;
   p.y = y;
   p.ndofs = op->na + op->nb;
@@ -271,6 +273,10 @@ int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y
   OpParams p;
   int prob;
   build_op_params(op, x, y, p, prob);
+  if (prec == GYM_BF16) {
+    p.bf16 = 1;  // FP32 vectors, bf16 contraction operands
+    prec = GYM_F32;
+  }
   int rc = launch_operator(prob, op->mesh->dim, op->r, prec, p, nrhs, op->ctx->ncu, s);
   if (rc == -2) return fail(GYM_E_UNSUPPORTED, "no kernel for this problem/degree/precision");
   if (rc) return fail(GYM_E_HIP, "operator kernel launch failed");
@@ -282,7 +288,7 @@ namespace {
 int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
   const gym_mesh* m = sp->mesh;
   OpParams p{};
-  set_form(p, sp->ctx, m);
+  set_form(p, sp->ctx, m, sp->desc.r);
   p.x = x;
   p.y = y;
   p.ndofs = sp->desc.ndofs;
@@ -295,6 +301,10 @@ int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, vo
   for (int c = 0; c < sp->desc.ncomp; ++c) p.sc[c] = metric_const(sp->desc.kind, c, m);
   if (m->curved) curved_scales(p);
   int prob = PROB_MASS_H1 + sp->desc.kind;
+  if (prec == GYM_BF16) {
+    p.bf16 = 1;
+    prec = GYM_F32;
+  }
   int rc = launch_operator(prob, m->dim, sp->desc.r, prec, p, nrhs, sp->ctx->ncu, s);
   if (rc == -2) return fail(GYM_E_UNSUPPORTED, "no mass kernel for this space/precision");
   if (rc) return fail(GYM_E_HIP, "mass kernel launch failed");
@@ -697,7 +707,7 @@ int gym_d_apply(const gym_space* from, const gym_space* to, int transpose, const
 
 int gym_mass_apply(const gym_space* space, int prec, int nrhs, const void* x, void* y, void* stream) {
   if (!space || !x || !y || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
-  if (prec != GYM_F64 && prec != GYM_F32) return fail(GYM_E_UNSUPPORTED, "precision not available");
+  if (prec != GYM_F64 && prec != GYM_F32 && prec != GYM_BF16) return fail(GYM_E_ARG, "unknown precision");
   return launch_mass_apply(space, prec, nrhs, x, y, (hipStream_t)stream);
 }
 
@@ -766,7 +776,7 @@ int gym_op_destroy(gym_op* op) {
 
 int gym_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, void* stream) {
   if (!op || !x || !y || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
-  if (prec != GYM_F64 && prec != GYM_F32) return fail(GYM_E_UNSUPPORTED, "precision not available");
+  if (prec != GYM_F64 && prec != GYM_F32 && prec != GYM_BF16) return fail(GYM_E_ARG, "unknown precision");
   return launch_op_apply(op, prec, nrhs, x, y, (hipStream_t)stream);
 }
 
@@ -945,9 +955,8 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
     }
     inf.iters = total;
   } else if (opts.mode == GYM_MODE_IR_F32 || opts.mode == GYM_MODE_IR_BF16) {
-    if (opts.mode == GYM_MODE_IR_BF16) return fail(GYM_E_UNSUPPORTED, "BF16 contractions not built yet");
     if (int rc = ensure_work32(op, w)) return rc;
-    const int prec = GYM_F32;
+    const int prec = opts.mode == GYM_MODE_IR_BF16 ? GYM_BF16 : GYM_F32;
     auto apply32 = [&](const float* in, float* out) {
       if (int rc = timer.begin(s)) return rc;
       if (int rc = launch_op_apply(op, prec, nrhs, in, out, s)) return rc;

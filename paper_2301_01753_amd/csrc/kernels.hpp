@@ -33,6 +33,7 @@ struct OpParams {
   int m[3];         // lattice cells per axis (r * nel)
   int tiles_x, tiles_y, chunk, nchunks;
   int kron;         // 1: Kronecker (1-D element matrix) form of the masses
+  int bf16;         // 1: contraction operands rounded to bf16 (FP32 accumulate)
   int curved;       // 1: per-Gauss-point metric from the vertex array
   const double* verts;  // (nel+1)^3 x 3 vertex coordinates (curved only)
   const int* gate;      // batched launches: skip when *gate != 0 (a solve's done flag)

@@ -8,7 +8,7 @@
 
 namespace gym {
 
-void fill_tables(TabSet<double>* hd, TabSet<double>* hl, TabSet<float>* hf) {
+void fill_tables(TabSet<double>* hd, TabSet<double>* hl, TabSet<float>* hf, TabSet<float>* hb) {
   for (int r = 1; r <= 4; ++r) {
     for (int which = 0; which < 2; ++which) {
       int q = r + 1 + which;
@@ -51,6 +51,13 @@ void fill_tables(TabSet<double>* hd, TabSet<double>* hl, TabSet<float>* hf) {
       for (int j = 0; j < 5; ++j) f.mn[i][j] = (float)d.mn[i][j];
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j) f.me[i][j] = (float)d.me[i][j];
+    // bf16-rounded copy (only the Kronecker matrices are read in BF16 mode)
+    TabSet<float>& b = hb[r - 1];
+    b = f;
+    for (int i = 0; i < 5; ++i)
+      for (int j = 0; j < 5; ++j) b.mn[i][j] = round_bf16(f.mn[i][j]);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j) b.me[i][j] = round_bf16(f.me[i][j]);
   }
 }
 

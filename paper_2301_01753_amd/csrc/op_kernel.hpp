@@ -27,7 +27,10 @@
 
 namespace gym {
 
-enum { FORM_GAUSS = 0, FORM_KRON = 1, FORM_CURVED = 2 };
+enum { FORM_GAUSS = 0, FORM_KRON = 1, FORM_CURVED = 2, FORM_KRON_BF16 = 3 };
+// FORM_KRON_BF16: the Kronecker form with every contraction operand rounded
+// to bf16 (FP32 accumulation, FP32 vectors)
+constexpr bool is_kron(int form) { return form == FORM_KRON || form == FORM_KRON_BF16; }
 
 // ---- field lists ---------------------------------------------------------
 // tm: nodal mask of the field's lattice; sp: 0 = first block, 1 = second
@@ -144,8 +147,10 @@ struct Layout {
   }
   static constexpr int nq() { return C::QX * C::QY * C::QZ; }
   static constexpr int A_off() { return car_off(F::NF); }
-  static constexpr int B_off() { return A_off() + (FORM == FORM_KRON ? maxlat() : C::tmpA()); }
-  static constexpr int L_off(int k) { return B_off() + (FORM == FORM_KRON ? maxlat() : C::tmpB()) + k * maxlat(); }
+  static constexpr int B_off() { return A_off() + (is_kron(FORM) ? maxlat() : C::tmpA()); }
+  // Kronecker form: a third lattice temporary (one per vector component)
+  static constexpr int T2_off() { return B_off() + (is_kron(FORM) ? maxlat() : C::tmpB()); }
+  static constexpr int L_off(int k) { return T2_off() + (is_kron(FORM) ? maxlat() : 0) + k * maxlat(); }
   // curved form: three Gauss-point arrays and the layer's vertex block
   static constexpr int Q_off(int k) { return L_off(3) + k * nq(); }
   static constexpr int nvert() { return 2 * (C::EX + 1) * (C::EY + 1) * 3; }
@@ -268,7 +273,7 @@ __device__ __forceinline__ void from_gauss(const TC* Q, TC* out, TC* A, TC* B) {
 // Work buffers of one layer.
 template <typename TC>
 struct Work {
-  TC *A, *B, *L[3], *Q[3], *V;
+  TC *A, *B, *T2, *L[3], *Q[3], *V;
   ElemRange er;
 };
 
@@ -280,8 +285,14 @@ __device__ __forceinline__ void smass(const TC* in, TC* out, TC scale, const Wor
     pointwise_curved<C, KIND>(w.Q[0], w.Q[1], w.Q[2], w.V, scale, w.er);
     __syncthreads();
     from_gauss<C, TM, ADD>(w.Q[0], out, w.A, w.B);
+  } else if constexpr (is_kron(FORM)) {
+    TC* const i3[3] = {const_cast<TC*>(in), nullptr, nullptr};
+    TC* const o3[3] = {out, nullptr, nullptr};
+    TC* const t3[3] = {w.A, w.B, w.T2};
+    const TC s3[3] = {scale, 0, 0};
+    kron_cols<C, 1, TM, TM, TM, ADD, FORM == FORM_KRON_BF16>(i3, o3, s3, t3, w.er);
   } else {
-    mass<C, TM, ADD, FORM == FORM_KRON>(in, out, scale, w.A, w.B, w.er);
+    mass<C, TM, ADD, false>(in, out, scale, w.A, w.B, w.er);
   }
 }
 
@@ -300,18 +311,29 @@ __device__ __forceinline__ void vmass(TC* const in[3], TC* const out[3], const T
     from_gauss<C, T0, ADD>(w.Q[0], out[0], w.A, w.B);
     from_gauss<C, T1, ADD>(w.Q[1], out[1], w.A, w.B);
     from_gauss<C, T2, ADD>(w.Q[2], out[2], w.A, w.B);
+  } else if constexpr (is_kron(FORM)) {
+    TC* const t3[3] = {w.A, w.B, w.T2};
+    kron_cols<C, 3, T0, T1, T2, ADD, FORM == FORM_KRON_BF16>(in, out, sc, t3, w.er);
   } else {
-    mass<C, T0, ADD, FORM == FORM_KRON>(in[0], out[0], sc[0], w.A, w.B, w.er);
-    mass<C, T1, ADD, FORM == FORM_KRON>(in[1], out[1], sc[1], w.A, w.B, w.er);
-    mass<C, T2, ADD, FORM == FORM_KRON>(in[2], out[2], sc[2], w.A, w.B, w.er);
+    mass<C, T0, ADD, false>(in[0], out[0], sc[0], w.A, w.B, w.er);
+    mass<C, T1, ADD, false>(in[1], out[1], sc[1], w.A, w.B, w.er);
+    mass<C, T2, ADD, false>(in[2], out[2], sc[2], w.A, w.B, w.er);
   }
 }
 
 // 2-D vector mass (affine forms only)
 template <class C, int T0, int T1, bool ADD, int FORM, typename TC>
 __device__ __forceinline__ void vmass2(TC* const in[2], TC* const out[2], const TC sc[2], const Work<TC>& w) {
-  mass<C, T0, ADD, FORM == FORM_KRON>(in[0], out[0], sc[0], w.A, w.B, w.er);
-  mass<C, T1, ADD, FORM == FORM_KRON>(in[1], out[1], sc[1], w.A, w.B, w.er);
+  if constexpr (is_kron(FORM)) {
+    TC* const i3[3] = {in[0], in[1], nullptr};
+    TC* const o3[3] = {out[0], out[1], nullptr};
+    TC* const t3[3] = {w.A, w.B, w.T2};
+    const TC s3[3] = {sc[0], sc[1], 0};
+    kron_cols<C, 2, T0, T1, T1, ADD, FORM == FORM_KRON_BF16>(i3, o3, s3, t3, w.er);
+  } else {
+    mass<C, T0, ADD, false>(in[0], out[0], sc[0], w.A, w.B, w.er);
+    mass<C, T1, ADD, false>(in[1], out[1], sc[1], w.A, w.B, w.er);
+  }
 }
 
 // ---- the kernel body -------------------------------------------------------
@@ -338,6 +360,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
   Work<TC> w;
   w.A = smem + L::A_off();
   w.B = smem + L::B_off();
+  w.T2 = smem + L::T2_off();
   for (int k = 0; k < 3; ++k) w.L[k] = smem + L::L_off(k);
   if constexpr (FORM == FORM_CURVED) {
     for (int k = 0; k < 3; ++k) w.Q[k] = smem + L::Q_off(k);
@@ -719,6 +742,7 @@ template <int DIM, int R, int PROB, typename TV, typename TC>
 int launch_op(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
   constexpr int kBig = 160 * 1024, kSmall = 40 * 1024;
   if (p.curved) {
+    if (p.bf16) return -2;  // bf16 contractions exist in the Kronecker form only
     if constexpr (DIM == 3) {
       if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_CURVED, TV, TC, kBig>(p, nrhs, ncu, stream);
       return launch_op_b<DIM, R, PROB, FORM_CURVED, TV, TC, kSmall>(p, nrhs, ncu, stream);
@@ -726,9 +750,16 @@ int launch_op(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
     return -2;
   }
   if (p.kron) {
+    if constexpr (std::is_same<TC, float>::value) {
+      if (p.bf16) {
+        if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_KRON_BF16, TV, TC, kBig>(p, nrhs, ncu, stream);
+        return launch_op_b<DIM, R, PROB, FORM_KRON_BF16, TV, TC, kSmall>(p, nrhs, ncu, stream);
+      }
+    }
     if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_KRON, TV, TC, kBig>(p, nrhs, ncu, stream);
     return launch_op_b<DIM, R, PROB, FORM_KRON, TV, TC, kSmall>(p, nrhs, ncu, stream);
   }
+  if (p.bf16) return -2;  // bf16 contractions exist in the Kronecker form only
   if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_GAUSS, TV, TC, kBig>(p, nrhs, ncu, stream);
   return launch_op_b<DIM, R, PROB, FORM_GAUSS, TV, TC, kSmall>(p, nrhs, ncu, stream);
 }
@@ -748,8 +779,9 @@ int dispatch_r(int r, const OpParams& p, int nrhs, int ncu, hipStream_t s) {
 // definitions below give every unit its own and the upload helper fills it.
 static int upload_tables_unit() {
   TabSet<double> hd[4] = {}, hl[4] = {};
-  TabSet<float> hf[4] = {};
-  fill_tables(hd, hl, hf);
+  TabSet<float> hf[4] = {}, hb[4] = {};
+  fill_tables(hd, hl, hf, hb);
+  GYM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tab_b), hb, sizeof(hb)));
   GYM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tab_d), hd, sizeof(hd)));
   GYM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tabL_d), hl, sizeof(hl)));
   GYM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_tab_f), hf, sizeof(hf)));

@@ -43,10 +43,33 @@ struct TabSet {
 // tables (no relocatable device code); see upload_tables_unit().
 static __constant__ TabSet<double> c_tab_d[4];   // q = r + 1
 static __constant__ TabSet<float> c_tab_f[4];
+static __constant__ TabSet<float> c_tab_b[4];    // FP32 values rounded to bf16
 static __constant__ TabSet<double> c_tabL_d[4];  // q = r + 2 (load vectors)
 
-// Host: fill the table sets for r = 1..4 (op_common.hip).
-void fill_tables(TabSet<double>* hd, TabSet<double>* hl, TabSet<float>* hf);
+// Host: fill the table sets for r = 1..4 (op_common.hip); hb receives the
+// FP32 tables rounded to bf16.
+void fill_tables(TabSet<double>* hd, TabSet<double>* hl, TabSet<float>* hf, TabSet<float>* hb);
+
+// bf16 rounding (round to nearest, ties to even) of an FP32 value, kept in
+// FP32 storage: the BF16 mode rounds every contraction operand this way and
+// accumulates in FP32.
+__host__ __device__ inline float round_bf16(float x) {
+  union {
+    float f;
+    unsigned u;
+  } v;
+  v.f = x;
+  unsigned lsb = (v.u >> 16) & 1u;
+  v.u += 0x7FFFu + lsb;
+  v.u &= 0xFFFF0000u;
+  return v.f;
+}
+
+template <bool BF, typename TC>
+__device__ __forceinline__ TC rd(TC x) {
+  if constexpr (BF) return round_bf16(x);
+  else return x;
+}
 
 template <typename T>
 __device__ __forceinline__ const TabSet<T>& tabs(int r);
@@ -54,6 +77,12 @@ template <>
 __device__ __forceinline__ const TabSet<double>& tabs<double>(int r) { return c_tab_d[r - 1]; }
 template <>
 __device__ __forceinline__ const TabSet<float>& tabs<float>(int r) { return c_tab_f[r - 1]; }
+
+template <bool BF, typename TC>
+__device__ __forceinline__ const TabSet<TC>& ktabs(int r) {
+  if constexpr (BF) return c_tab_b[r - 1];
+  else return tabs<TC>(r);
+}
 
 // Compile-time geometry of one layer of a tile.
 template <int R_, int BX_, int BY_, int DIM_>
@@ -313,6 +342,112 @@ __device__ __forceinline__ void mass_kron(const TC* in, TC* out, TC scale, TC* A
       if constexpr (ADD) out[idx] += scale * v;
       else out[idx] = scale * v;
     }
+  }
+  __syncthreads();
+}
+
+// Column-register form of the Kronecker mass, for up to three components at
+// once (masks T0, T1, T2; NCOMP of them used).  Stage 1: every thread owns
+// lattice columns (x, y) of one component and applies M_x along x for all
+// z values of the column.  Stage 2: the same columns apply M_y along y and,
+// in registers, M_z along the column.  Two barriers per call whatever the
+// number of components.  in[c] == out[c] is allowed.
+template <class C, int TM, bool BF, typename TC>
+__device__ __forceinline__ void kron_x_col(const TC* __restrict__ in, TC* __restrict__ A, int col, const ElemRange& er) {
+  constexpr int NX = C::nx(TM), NY = C::ny(TM), NZ = C::nz(TM);
+  constexpr int R = C::R;
+  constexpr bool N = TM & 1;
+  constexpr int n = N ? R + 1 : R;
+  const TabSet<TC>& T = ktabs<BF, TC>(R);
+  const int j = col % NX, y = col / NX;
+  TC acc[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) acc[k] = 0;
+  auto term = [&](int e, int i) {
+    if (e < er.xlo || e >= er.xhi) return;
+#pragma unroll
+    for (int m = 0; m < n; ++m) {
+      const TC c = kmat<TC, N>(T, i, m);
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) acc[k] += c * rd<BF>(in[(R * e + m) + NX * (y + NY * k)]);
+    }
+  };
+  {
+    int e = j / R, i = j - R * e;
+    if constexpr (N) {
+      if (i == 0 && e > 0) term(e - 1, R);
+      if (e < C::EX) term(e, i);
+    } else {
+      term(e, i);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) A[j + NX * (y + NY * k)] = acc[k];
+}
+
+template <class C, int TM, bool ADD, bool BF, typename TC>
+__device__ __forceinline__ void kron_yz_col(const TC* __restrict__ A, TC* __restrict__ out, TC scale, int col,
+                                            const ElemRange& er) {
+  constexpr int NX = C::nx(TM), NY = C::ny(TM), NZ = C::nz(TM);
+  constexpr int R = C::R;
+  constexpr bool N = TM & 2;
+  constexpr int n = N ? R + 1 : R;
+  const TabSet<TC>& T = ktabs<BF, TC>(R);
+  const int x = col % NX, j = col / NX;
+  TC b[NZ];
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) b[k] = 0;
+  auto term = [&](int e, int i) {
+    if (e < er.ylo || e >= er.yhi) return;
+#pragma unroll
+    for (int m = 0; m < n; ++m) {
+      const TC c = kmat<TC, N>(T, i, m);
+#pragma unroll
+      for (int k = 0; k < NZ; ++k) b[k] += c * rd<BF>(A[x + NX * ((R * e + m) + NY * k)]);
+    }
+  };
+  {
+    int e = j / R, i = j - R * e;
+    if constexpr (N) {
+      if (i == 0 && e > 0) term(e - 1, R);
+      if (e < C::EY) term(e, i);
+    } else {
+      term(e, i);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NZ; ++k) {
+    TC v;
+    if constexpr (C::DIM == 2) {
+      v = b[k];
+    } else {
+      constexpr bool NZB = TM & 4;
+      v = 0;
+#pragma unroll
+      for (int m = 0; m < NZ; ++m) v += kmat<TC, NZB>(T, k, m) * rd<BF>(b[m]);
+    }
+    TC* o = out + x + NX * (j + NY * k);
+    if constexpr (ADD) *o += scale * v;
+    else *o = scale * v;
+  }
+}
+
+template <class C, int NCOMP, int T0, int T1, int T2, bool ADD, bool BF, typename TC>
+__device__ __forceinline__ void kron_cols(TC* const in[3], TC* const out[3], const TC sc[3], TC* const A[3],
+                                          const ElemRange& er) {
+  constexpr int n0 = C::nx(T0) * C::ny(T0);
+  constexpr int n1 = NCOMP > 1 ? C::nx(T1) * C::ny(T1) : 0;
+  constexpr int n2 = NCOMP > 2 ? C::nx(T2) * C::ny(T2) : 0;
+  for (int idx = threadIdx.x; idx < n0 + n1 + n2; idx += kNT) {
+    if (idx < n0) kron_x_col<C, T0, BF>(in[0], A[0], idx, er);
+    else if (NCOMP > 1 && idx < n0 + n1) kron_x_col<C, T1, BF>(in[1], A[1], idx - n0, er);
+    else if (NCOMP > 2) kron_x_col<C, T2, BF>(in[2], A[2], idx - n0 - n1, er);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n0 + n1 + n2; idx += kNT) {
+    if (idx < n0) kron_yz_col<C, T0, ADD, BF>(A[0], out[0], sc[0], idx, er);
+    else if (NCOMP > 1 && idx < n0 + n1) kron_yz_col<C, T1, ADD, BF>(A[1], out[1], sc[1], idx - n0, er);
+    else if (NCOMP > 2) kron_yz_col<C, T2, ADD, BF>(A[2], out[2], sc[2], idx - n0 - n1, er);
   }
   __syncthreads();
 }

@@ -466,3 +466,50 @@ def test_mass_solve_and_exact_feec_operator(g, curved):
     for s in (s1, s2):
         gym.gym_space_destroy(s)
     gym.gym_mesh_destroy(mesh)
+
+
+# ---- BF16 contraction operands (FP32 accumulate), inside FP64 refinement ----------
+@pytest.mark.parametrize("which,nel,r", [("poisson", (4, 5, 3), 4), ("hodge", (5, 4, 4), 2), ("poisson", (9, 7), 2),
+                                         ("hodge", (3, 4, 3), 3)])
+def test_operator_apply_bf16(g, which, nel, r):
+    # every contraction operand is rounded to bf16 (8 significant bits), so
+    # the apply differs from FP64 by a few bf16 ulps of the output scale:
+    # well above FP32 round-off, well below 5e-2
+    gym, ctx = g
+    mesh = _mesh(gym, ctx, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON if which == "poisson" else gym.GYM_HODGE1, mesh, r)
+    P = _oracle_problem(which, nel, r)
+    n = P.A.shape[0]
+    x = synth.random_vector(n, seed=13)
+    y = torch.empty(n, dtype=torch.float32, device=DEV)
+    gym.gym_op_apply(op, gym.GYM_BF16, 1, torch.tensor(x, dtype=torch.float32, device=DEV), y)
+    torch.cuda.synchronize()
+    err = _rel(y.cpu().numpy().astype(np.float64), P.A @ x)
+    assert 1e-5 < err < 5e-2, err
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
+@pytest.mark.parametrize("which,nel,r", [("poisson", (4, 4, 3), 3), ("hodge", (4, 3, 4), 2)])
+def test_solve_mixed_precision_bf16(g, which, nel, r):
+    gym, ctx = g
+    mesh = _mesh(gym, ctx, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON if which == "poisson" else gym.GYM_HODGE1, mesh, r)
+    P = _oracle_problem(which, nel, r)
+    n = P.A.shape[0]
+    b = synth.random_vector(n, seed=17, nrhs=2)
+    x = torch.empty(2 * n, dtype=torch.float64, device=DEV)
+    opts = gym.gym_solve_opts_default()
+    opts.mode = gym.GYM_MODE_IR_BF16
+    opts.rtol = 1e-12
+    opts.inner_rtol = 1e-2
+    opts.max_outer = 60
+    info = gym.gym_solve(op, opts, 2, _t(b), x)
+    assert info.status == 0, (info.rel_res, info.outer_iters)
+    got = x.cpu().numpy().reshape(2, -1)
+    for k in range(2):
+        ref = problems.solve_direct(P.A, b.reshape(2, -1)[k])
+        err = np.linalg.norm(got[k] - ref) / np.linalg.norm(ref)
+        assert err < 1e-8, (k, err, info.outer_iters, info.iters)
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
