@@ -96,7 +96,8 @@ const char* gym_last_error(void);
  *   on affine meshes, Gauss-point form otherwise), 1 = always evaluate at
  *   Gauss points (the paper's mass-matrix definition, quadrature r + 1).
  *   Both forms compute the same operator up to rounding.
- * GYM_OPT_TILE: 0 = automatic, 1 = large tiles (one workgroup per CU),
+ * GYM_OPT_TILE: 0 = automatic (large tiles unless the mesh has fewer of
+ *   them than the device has CUs), 1 = large tiles (one workgroup per CU),
  *   2 = small tiles (several workgroups per CU).
  * Errors: GYM_E_ARG for an unknown option or value. */
 #define GYM_OPT_MASS_FORM 0
@@ -180,7 +181,9 @@ typedef struct gym_solve_opts {
   double inner_rtol;  /* IR: inner relative residual target (e.g. 1e-4)    */
   int max_outer;      /* IR: outer refinement steps                        */
   int check_every;    /* host reads the device residual estimate every k   */
-  int timing;         /* 1: bracket every operator apply with HIP events   */
+  int timing;         /* k > 0: bracket every k-th operator apply with HIP
+                         events (1: every apply; a larger k keeps the
+                         events' own cost out of the solve)                */
 } gym_solve_opts;
 
 typedef struct gym_solve_info {
@@ -189,7 +192,7 @@ typedef struct gym_solve_info {
   int outer_iters;     /* IR outer steps (0 in FP64 mode)                  */
   double rel_res;      /* ||b - A x|| / ||b|| in FP64 at exit, per rhs max */
   double seconds;      /* wall time of the call                            */
-  int applies;         /* operator applies timed (opts.timing = 1)         */
+  int applies;         /* operator applies timed (opts.timing > 0)         */
   double apply_ms;     /* summed HIP-event time of those applies, ms       */
 } gym_solve_info;
 

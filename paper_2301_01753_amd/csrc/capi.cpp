@@ -221,13 +221,11 @@ int check_mesh_jacobians(const gym_mesh* m) {
   return 0;
 }
 
-void set_form(OpParams& p, const gym_ctx* ctx, const gym_mesh* m, int r) {
+void set_form(OpParams& p, const gym_ctx* ctx, const gym_mesh* m) {
   p.kron = (ctx->mass_form == 0 && !m->curved) ? 1 : 0;
-  // auto (measured on MI355X): small tiles for affine cells up to degree 2
-  // (more workgroups per CU hide LDS latency); large tiles for degree >= 3
-  // and for curved cells, where small tiles would recompute most of the halo
-  const bool large = ctx->tile == 1 || (ctx->tile == 0 && (m->curved || r >= 3));
-  p.tile_budget = large ? 0 : 1;
+  // auto: whole-CU tiles (least halo recomputation) unless the mesh is too
+  // small to give every CU one of them; decided at launch
+  p.tile_budget = ctx->tile == 1 ? 0 : ctx->tile == 2 ? 1 : 2;
   p.curved = m->curved ? 1 : 0;
   p.verts = m->d_vertices;
 }
@@ -244,7 +242,7 @@ void curved_scales(OpParams& p) {
 void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int& prob) {
   const gym_mesh* m = op->mesh;
   p = OpParams{};
-  set_form(p, op->ctx, m, op->r);
+  set_form(p, op->ctx, m);
   p.x = x;
   p.y = y;
   p.ndofs = op->na + op->nb;
@@ -269,7 +267,9 @@ void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int&
   if (m->curved) curved_scales(p);
 }
 
-int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
+namespace {
+int op_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s, const MrStep* mr,
+              int* wg_out) {
   OpParams p;
   int prob;
   build_op_params(op, x, y, p, prob);
@@ -277,10 +277,28 @@ int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y
     p.bf16 = 1;  // FP32 vectors, bf16 contraction operands
     prec = GYM_F32;
   }
+  if (mr) {
+    p.fused = 1;
+    p.mr = *mr;
+  }
+  p.wg_out = wg_out;
+  p.dry = wg_out ? 1 : 0;
   int rc = launch_operator(prob, op->mesh->dim, op->r, prec, p, nrhs, op->ctx->ncu, s);
   if (rc == -2) return fail(GYM_E_UNSUPPORTED, "no kernel for this problem/degree/precision");
   if (rc) return fail(GYM_E_HIP, "operator kernel launch failed");
   return 0;
+}
+}  // namespace
+
+int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s,
+                    const MrStep* mr) {
+  return op_launch(op, prec, nrhs, x, y, s, mr, nullptr);
+}
+
+int op_workgroups(const gym_op* op, int prec, int nrhs, int* wg) {
+  *wg = 0;
+  if (int rc = op_launch(op, prec, nrhs, nullptr, nullptr, nullptr, nullptr, wg)) return rc;
+  return *wg > 0 ? 0 : fail(GYM_E_HIP, "operator tiling query failed");
 }
 
 namespace {
@@ -288,7 +306,7 @@ namespace {
 int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
   const gym_mesh* m = sp->mesh;
   OpParams p{};
-  set_form(p, sp->ctx, m, sp->desc.r);
+  set_form(p, sp->ctx, m);
   p.x = x;
   p.y = y;
   p.ndofs = sp->desc.ndofs;
@@ -314,15 +332,18 @@ int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, vo
 // ---- Krylov drivers ---------------------------------------------------------
 template <typename TV>
 struct MinresWork {
-  TV *r1 = nullptr, *r2 = nullptr, *y = nullptr, *v = nullptr, *w = nullptr, *w1 = nullptr, *w2 = nullptr;
-  double *pa = nullptr, *pb = nullptr;
+  TV *r1 = nullptr, *r2 = nullptr, *y = nullptr, *z = nullptr, *zp = nullptr, *w = nullptr, *w1 = nullptr,
+     *w2 = nullptr;
+  // partial sums (fused apply: pa; minres_step2: pb, pc) and alfa per rhs
+  double *pa = nullptr, *pb = nullptr, *pc = nullptr, *alfa = nullptr;
+  int npa_cap = 0;
   MinresState* st = nullptr;
   MinresState* host = nullptr;
 };
 
 template <typename TV>
-int alloc_minres(std::vector<void*>& pool, MinresWork<TV>& w, long long n, int nrhs, int nb) {
-  TV** vecs[7] = {&w.r1, &w.r2, &w.y, &w.v, &w.w, &w.w1, &w.w2};
+int alloc_minres(std::vector<void*>& pool, MinresWork<TV>& w, long long n, int nrhs) {
+  TV** vecs[8] = {&w.r1, &w.r2, &w.y, &w.z, &w.zp, &w.w, &w.w1, &w.w2};
   for (TV** v : vecs) {
     void* p;
     if (int rc = dalloc(&p, sizeof(TV) * n * nrhs)) return rc;
@@ -330,10 +351,6 @@ int alloc_minres(std::vector<void*>& pool, MinresWork<TV>& w, long long n, int n
     *v = (TV*)p;
   }
   void* p;
-  if (int rc = dalloc(&p, sizeof(double) * 2 * nb * nrhs)) return rc;
-  pool.push_back(p);
-  w.pa = (double*)p;
-  w.pb = w.pa + nb * nrhs;
   if (int rc = dalloc(&p, sizeof(MinresState) * 2 * nrhs)) return rc;
   pool.push_back(p);
   w.st = (MinresState*)p;
@@ -341,53 +358,74 @@ int alloc_minres(std::vector<void*>& pool, MinresWork<TV>& w, long long n, int n
   return 0;
 }
 
+// Partial-sum buffers for a fused apply of npa workgroups per rhs (grown
+// when the tiling changes, e.g. after a context option).
+template <typename TV>
+int ensure_partials(std::vector<void*>& pool, MinresWork<TV>& w, int npa, int nb, int nrhs) {
+  if (npa <= w.npa_cap) return 0;
+  void* p;
+  if (int rc = dalloc(&p, sizeof(double) * ((long long)(npa + 2 * nb + 1) * nrhs))) return rc;
+  pool.push_back(p);
+  w.pa = (double*)p;
+  w.pb = w.pa + (long long)npa * nrhs;
+  w.pc = w.pb + (long long)nb * nrhs;
+  w.alfa = w.pc + (long long)nb * nrhs;
+  w.npa_cap = npa;
+  return 0;
+}
+
+// Preconditioned MINRES from x = 0, two launches per step: the operator
+// apply carrying the first half of the step (MrStep) and minres_step2.  The
+// host reads the states every check_every steps; on exit x is complete (a
+// step still pending at the iteration cap is finished by minres_finish).
+// npa = workgroups per rhs of the fused apply.
 template <typename TV, typename Apply>
-int run_minres(Apply&& apply, long long n, int nrhs, int nb, const TV* b, TV* x, const double* dinv, double tol,
-               int maxit, int check_every, MinresWork<TV>& wk, hipStream_t s, int* iters_out, int* flag_out,
-               int resume) {
-  MinresVecs<TV> V{b, x, wk.r1, wk.r2, wk.y, wk.v, wk.w, wk.w1, wk.w2};
-  if (!resume) minres_launch_init<TV>(V, dinv, n, nrhs, nb, wk.pa, wk.st, tol, s);
-  int it = 0;
+int run_minres(Apply&& apply, long long n, int nrhs, int nb, int npa, const TV* b, TV* x, const double* dinv,
+               double tol, int maxit, int check_every, MinresWork<TV>& wk, hipStream_t s, int* iters_out,
+               int* flag_out) {
+  if (npa > wk.npa_cap) return fail(GYM_E_HIP, "MINRES partial-sum buffer too small for this launch");
+  // init: r1 = r2 = b, z = M^-1 b (into wk.z), beta_1 in slot 0
+  MinresVecs<TV> V{b, x, wk.r1, wk.r2, wk.z, wk.y, wk.w, wk.w1, wk.w2};
+  minres_launch_init<TV>(V, dinv, n, nrhs, nb, wk.pb, wk.st, tol, s);
   if (check_every < 1) check_every = 1;
-  bool all_done = false;
+  int it = 0, slot = 0;
+  bool all_done = false, pending = false;
   while (it < maxit && !all_done) {
-    MinresState* cur = wk.st + (it & 1) * nrhs;
-    MinresState* next = wk.st + ((it + 1) & 1) * nrhs;
-    if (int rc = apply(V.v, V.y)) return rc;
-    minres_launch_k3<TV>(V.y, V.r1, V.v, n, nrhs, nb, cur, wk.pa, s);
-    minres_launch_k5<TV>(V.y, V.r2, V.r1, dinv, n, nrhs, nb, cur, wk.pa, wk.pb, s);
-    MinresVecs<TV> U = V;
-    U.y = V.r1;  // z = M^-1 r2 was written over the old r1
-    minres_launch_k7<TV>(U, n, nrhs, nb, cur, next, wk.pa, wk.pb, s);
-    TV* old_r1 = V.r1;
-    V.r1 = V.r2;
-    V.r2 = V.y;
-    V.y = old_r1;
-    TV *ow = V.w, *ow1 = V.w1, *ow2 = V.w2;
-    V.w = ow1;
-    V.w1 = ow2;
-    V.w2 = ow;
+    MinresState* cur = wk.st + slot * nrhs;
+    MinresState* next = wk.st + (slot ^ 1) * nrhs;
+    const MrStep m{cur, next, wk.pb, wk.pc, wk.alfa, wk.pa, nb, pending ? 0 : 1};
+    if (int rc = apply(wk.z, wk.y, m)) return rc;
+    const MrVecs<TV> mv{wk.y, wk.r1, wk.r2, wk.zp, x, wk.w2, wk.w, wk.w1};
+    minres_launch_step2<TV>(mv, dinv, n, nrhs, nb, next, wk.pa, npa, wk.pb, wk.pc, wk.alfa, s);
+    if (pending) {  // the newest w was written over the oldest
+      TV *ow = wk.w, *ow1 = wk.w1, *ow2 = wk.w2;
+      wk.w = ow1;
+      wk.w1 = ow2;
+      wk.w2 = ow;
+    }
+    std::swap(wk.z, wk.zp);  // z_{k+1} becomes the apply input, z_k the previous one
+    TV* old_r1 = wk.r1;
+    wk.r1 = wk.r2;
+    wk.r2 = wk.y;
+    wk.y = old_r1;
+    pending = true;
+    slot ^= 1;
     ++it;
     if (it % check_every == 0 || it == maxit) {
-      GYM_HIP(hipMemcpyAsync(wk.host, next, sizeof(MinresState) * nrhs, hipMemcpyDeviceToHost, s));
+      GYM_HIP(hipMemcpyAsync(wk.host, wk.st + slot * nrhs, sizeof(MinresState) * nrhs, hipMemcpyDeviceToHost, s));
       GYM_HIP(hipStreamSynchronize(s));
       all_done = true;
       for (int r = 0; r < nrhs; ++r) all_done = all_done && wk.host[r].done;
     }
   }
+  if (!all_done && pending) {
+    minres_launch_finish<TV>(x, wk.zp, wk.w2, wk.w, wk.w1, n, nrhs, nb, wk.st + slot * nrhs,
+                             wk.st + (slot ^ 1) * nrhs, wk.pb, wk.alfa, s);
+    slot ^= 1;
+  }
   GYM_HIP(hipGetLastError());
-  // the latest state is in slot (it & 1); keep it in slot 0 for a resume
-  if (it & 1) GYM_HIP(hipMemcpyAsync(wk.st, wk.st + nrhs, sizeof(MinresState) * nrhs, hipMemcpyDeviceToDevice, s));
-  GYM_HIP(hipMemcpyAsync(wk.host, wk.st, sizeof(MinresState) * nrhs, hipMemcpyDeviceToHost, s));
+  GYM_HIP(hipMemcpyAsync(wk.host, wk.st + slot * nrhs, sizeof(MinresState) * nrhs, hipMemcpyDeviceToHost, s));
   GYM_HIP(hipStreamSynchronize(s));
-  // the rotation of work buffers must persist for a resume
-  wk.r1 = V.r1;
-  wk.r2 = V.r2;
-  wk.y = V.y;
-  wk.v = V.v;
-  wk.w = V.w;
-  wk.w1 = V.w1;
-  wk.w2 = V.w2;
   int maxitn = 0, flag = 1;
   for (int r = 0; r < nrhs; ++r) {
     maxitn = std::max(maxitn, wk.host[r].itn);
@@ -418,17 +456,22 @@ int relres_f64(const gym_op* op, int nrhs, const double* b, const double* x, dou
   return 0;
 }
 
-// Brackets operator applies with HIP event pairs (pre-created pool) and sums
-// their elapsed times once the stream has been synchronised.
+// Brackets every `period`-th operator apply with a HIP event pair
+// (pre-created pool) and sums their elapsed times once the stream has been
+// synchronised.  An event pair costs several microseconds of stream time, so
+// sampling keeps the measurement from slowing the solve it measures.
 struct ApplyTimer {
-  bool on = false;
+  int period = 0;  // 0: off
+  long long count = 0;
+  bool open = false;
   std::vector<hipEvent_t> ev;
   size_t used = 0;
   ~ApplyTimer() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
   int begin(hipStream_t s) {
-    if (!on) return 0;
+    open = period > 0 && (count++ % period) == 0;
+    if (!open) return 0;
     if (used + 2 > ev.size()) {
       for (int k = 0; k < 256; ++k) {
         hipEvent_t e;
@@ -440,7 +483,7 @@ struct ApplyTimer {
     return 0;
   }
   int end(hipStream_t s) {
-    if (!on) return 0;
+    if (!open) return 0;
     GYM_HIP(hipEventRecord(ev[used + 1], s));
     used += 2;
     return 0;
@@ -468,7 +511,7 @@ struct OpWork {
   int nrhs = 0, nb = 0;
   MinresWork<double> m64;
   MinresWork<float> m32;
-  double *tmp = nullptr, *part = nullptr, *sums = nullptr, *r64 = nullptr, *scale = nullptr;
+  double *tmp = nullptr, *part = nullptr, *sums = nullptr, *r64 = nullptr, *d64 = nullptr, *scale = nullptr;
   float *r32 = nullptr, *x32 = nullptr;
   std::vector<void*> pool;
 };
@@ -875,12 +918,13 @@ static int ensure_work(gym_op* op, int nrhs, OpWork** out) {
   w->n = n;
   w->nrhs = nrhs;
   w->nb = vec_grid(n, op->ctx->ncu);
-  if (int rc = alloc_minres<double>(w->pool, w->m64, n, nrhs, w->nb)) return rc;
+  if (int rc = alloc_minres<double>(w->pool, w->m64, n, nrhs)) return rc;
   void* p;
-  if (int rc = dalloc(&p, sizeof(double) * n * nrhs * 2)) return rc;
+  if (int rc = dalloc(&p, sizeof(double) * n * nrhs * 3)) return rc;
   w->pool.push_back(p);
   w->tmp = (double*)p;
   w->r64 = w->tmp + n * nrhs;
+  w->d64 = w->r64 + n * nrhs;
   if (int rc = dalloc(&p, sizeof(double) * (w->nb * nrhs + 4 * nrhs))) return rc;
   w->pool.push_back(p);
   w->part = (double*)p;
@@ -892,7 +936,7 @@ static int ensure_work(gym_op* op, int nrhs, OpWork** out) {
 
 static int ensure_work32(gym_op* op, OpWork* w) {
   if (w->r32) return 0;
-  if (int rc = alloc_minres<float>(w->pool, w->m32, w->n, w->nrhs, w->nb)) return rc;
+  if (int rc = alloc_minres<float>(w->pool, w->m32, w->n, w->nrhs)) return rc;
   void* p;
   if (int rc = dalloc(&p, sizeof(float) * w->n * w->nrhs * 2)) return rc;
   w->pool.push_back(p);
@@ -917,25 +961,31 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
   std::vector<double> rel;
   int status = GYM_OK;
   ApplyTimer timer;
-  timer.on = opts.timing != 0;
+  timer.period = opts.timing > 0 ? opts.timing : 0;
   if (opts.mode == GYM_MODE_F64) {
-    auto apply = [&](const double* in, double* out) {
+    auto apply = [&](const double* in, double* out, const MrStep& m) {
       if (int rc = timer.begin(s)) return rc;
-      if (int rc = launch_op_apply(op, GYM_F64, nrhs, in, out, s)) return rc;
+      if (int rc = launch_op_apply(op, GYM_F64, nrhs, in, out, s, &m)) return rc;
       return timer.end(s);
     };
+    int npa = 0;
+    if (int rc = op_workgroups(op, GYM_F64, nrhs, &npa)) return rc;
+    if (int rc = ensure_partials(w->pool, w->m64, npa, w->nb, nrhs)) return rc;
     double tol = opts.rtol;
-    int total = 0, flag = 0, resume = 0;
+    int total = 0, flag = 0;
+    const double* rhs = b;
+    double* sol = x;
     for (int attempt = 0; attempt < 6; ++attempt) {
       int it = 0;
-      if (int rc = run_minres<double>(apply, n, nrhs, w->nb, b, x, op->d_prec, tol, opts.maxit - total,
-                                      opts.check_every, w->m64, s, &it, &flag, resume))
+      if (int rc = run_minres<double>(apply, n, nrhs, w->nb, npa, rhs, sol, op->d_prec, tol, opts.maxit - total,
+                                      opts.check_every, w->m64, s, &it, &flag))
         return rc;
-      total = it;
+      total += it;
       if (flag < 0) {
         status = fail(GYM_E_BREAKDOWN, "MINRES breakdown (NaN or indefinite preconditioner)");
         break;
       }
+      if (sol != x) launch_add(sol, x, n * nrhs, w->nb, s);
       if (int rc = relres_f64(op, nrhs, b, x, w->tmp, w->part, w->sums, w->nb, s, rel)) return rc;
       double worst = *std::max_element(rel.begin(), rel.end());
       if (worst <= opts.rtol) break;
@@ -943,25 +993,28 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
         status = GYM_W_NOT_CONVERGED;
         break;
       }
-      // the preconditioned estimate was optimistic: tighten and continue
-      tol *= 0.1;
-      for (int r = 0; r < nrhs; ++r) {
-        w->m64.host[r].tol = tol;
-        w->m64.host[r].done = 0;
-        w->m64.host[r].flag = 0;
-      }
-      GYM_HIP(hipMemcpyAsync(w->m64.st, w->m64.host, sizeof(MinresState) * nrhs, hipMemcpyHostToDevice, s));
-      resume = 1;
+      // the preconditioned estimate was optimistic: restart on the true
+      // residual, A d = b - A x (zero for right-hand sides already within
+      // rtol), with the tolerance that brings the worst one below rtol
+      launch_sub(b, w->tmp, w->r64, n * nrhs, w->nb, s);
+      for (int r = 0; r < nrhs; ++r)
+        if (rel[r] <= opts.rtol) GYM_HIP(hipMemsetAsync(w->r64 + n * r, 0, sizeof(double) * n, s));
+      tol = std::min(0.5, 0.3 * opts.rtol / worst);
+      rhs = w->r64;
+      sol = w->d64;
     }
     inf.iters = total;
   } else if (opts.mode == GYM_MODE_IR_F32 || opts.mode == GYM_MODE_IR_BF16) {
     if (int rc = ensure_work32(op, w)) return rc;
     const int prec = opts.mode == GYM_MODE_IR_BF16 ? GYM_BF16 : GYM_F32;
-    auto apply32 = [&](const float* in, float* out) {
+    auto apply32 = [&](const float* in, float* out, const MrStep& m) {
       if (int rc = timer.begin(s)) return rc;
-      if (int rc = launch_op_apply(op, prec, nrhs, in, out, s)) return rc;
+      if (int rc = launch_op_apply(op, prec, nrhs, in, out, s, &m)) return rc;
       return timer.end(s);
     };
+    int npa = 0;
+    if (int rc = op_workgroups(op, prec, nrhs, &npa)) return rc;
+    if (int rc = ensure_partials(w->pool, w->m32, npa, w->nb, nrhs)) return rc;
     GYM_HIP(hipMemsetAsync(x, 0, sizeof(double) * n * nrhs, s));
     int total = 0, outer = 0;
     std::vector<double> rn;
@@ -983,8 +1036,8 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
       GYM_HIP(hipMemcpyAsync(w->scale, sc.data(), sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s));
       launch_to_f32_scaled(w->r64, w->r32, n, nrhs, w->nb, w->scale, s);
       int it = 0, flag = 0;
-      if (int rc = run_minres<float>(apply32, n, nrhs, w->nb, w->r32, w->x32, op->d_prec, opts.inner_rtol,
-                                     opts.maxit, opts.check_every, w->m32, s, &it, &flag, 0))
+      if (int rc = run_minres<float>(apply32, n, nrhs, w->nb, npa, w->r32, w->x32, op->d_prec, opts.inner_rtol,
+                                     opts.maxit, opts.check_every, w->m32, s, &it, &flag))
         return rc;
       total += it;
       if (flag < 0) {

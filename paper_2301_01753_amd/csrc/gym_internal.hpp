@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "../../include/gym.h"
+#include "minres_step.hpp"
 
 namespace gym {
 
@@ -61,7 +62,11 @@ namespace gym {
 struct OpParams;
 // Parameters of one block-operator apply (capi.cpp), and the apply itself.
 void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int& prob);
-int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s);
+// y = A x; with `mr` the launch also carries that fused MINRES step.
+int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s,
+                    const MrStep* mr = nullptr);
+// Workgroups per rhs of the operator launch for this precision and nrhs.
+int op_workgroups(const gym_op* op, int prec, int nrhs, int* wg);
 }  // namespace gym
 
 struct gym_ctx {

@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+#include "minres_step.hpp"
+
 namespace gym {
 
 enum {
@@ -37,8 +39,12 @@ struct OpParams {
   int curved;       // 1: per-Gauss-point metric from the vertex array
   const double* verts;  // (nel+1)^3 x 3 vertex coordinates (curved only)
   const int* gate;      // batched launches: skip when *gate != 0 (a solve's done flag)
-  int tile_budget;  // 0: one 160 KB workgroup per CU, 1: 40 KB workgroups
+  int tile_budget;  // 0: one 160 KB workgroup per CU, 1: 40 KB workgroups, 2: automatic
   double sc[8];     // constant pointwise metric factors (affine meshes)
+  int fused;        // 1: the apply carries the MINRES step `mr`
+  MrStep mr;
+  int dry;          // 1: launch nothing, only report the grid in *wg_out
+  int* wg_out;      // host: workgroups per rhs of the launch (may be null)
 };
 
 int upload_tables();

@@ -47,43 +47,6 @@ __device__ __forceinline__ double reduce_partials(const double* part, int np, do
 }
 
 // ---- MINRES ---------------------------------------------------------------
-// Lanczos/Givens scalar recurrence of one MINRES step (Paige & Saunders),
-// given alfa = v.(A v - ...) and b2 = r2 . M^-1 r2; returns the update
-// coefficients and marks convergence (phibar <= tol beta1) or breakdown.
-__device__ __forceinline__ void minres_scalar_update(MinresState& s, double alfa, double b2, double& phi,
-                                                     double& denom, double& oldeps, double& delta, double& vinv) {
-  s.itn += 1;
-  const double oldb = s.beta;
-  const double beta = b2 > 0 ? sqrt(b2) : 0.0;
-  s.tnorm2 += alfa * alfa + oldb * oldb + beta * beta;
-  oldeps = s.epsln;
-  delta = s.cs * s.dbar + s.sn * alfa;
-  const double gbar = s.sn * s.dbar - s.cs * alfa;
-  const double epsln = s.sn * beta;
-  const double dbar = -s.cs * beta;
-  double gamma = sqrt(gbar * gbar + beta * beta);
-  gamma = gamma > 2.2e-308 ? gamma : 2.2e-308;
-  const double cs = gbar / gamma, sn = beta / gamma;
-  phi = cs * s.phibar;
-  const double phibar = sn * s.phibar;
-  denom = 1.0 / gamma;
-  s.oldb = oldb;
-  s.beta = beta;
-  s.epsln = epsln;
-  s.dbar = dbar;
-  s.cs = cs;
-  s.sn = sn;
-  s.phibar = phibar;
-  s.alfa = alfa;
-  if (b2 < 0 || !(b2 == b2) || !(phibar == phibar)) {
-    s.flag = -1;
-    s.done = 1;
-  } else if (phibar <= s.tol * s.beta1 || beta == 0.0) {
-    s.flag = 1;
-    s.done = 1;
-  }
-  vinv = beta > 0 ? 1.0 / beta : 0.0;
-}
 // init: r1 = r2 = b; y = dinv .* b; x = w = w1 = w2 = 0; partial (b . y)
 template <typename TV>
 __global__ void __launch_bounds__(kBT) minres_init_a(MinresVecs<TV> v, const double* __restrict__ dinv,
@@ -140,85 +103,137 @@ __global__ void __launch_bounds__(kBT) minres_init_b(MinresVecs<TV> v, long long
     v.v[off + i] = static_cast<TV>(todbl(v.y[off + i]) * inv);
 }
 
-// after y = A v:  y -= (beta/oldb) r1 ; partial (v . y)
-template <typename TV>
-__global__ void __launch_bounds__(kBT) minres_k3(TV* __restrict__ y, const TV* __restrict__ r1,
-                                                 const TV* __restrict__ vv, long long n,
-                                                 const MinresState* cur, double* part_a) {
-  __shared__ double sh[kBT];
-  const int rhs = blockIdx.y;
-  const MinresState s = cur[rhs];
-  if (s.done) return;
-  const long long off = (long long)rhs * n;
-  const double c = s.oldb > 0 ? s.beta / s.oldb : 0.0;
-  double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
-    double yi = todbl(y[off + i]) - c * todbl(r1[off + i]);
-    TV ys = static_cast<TV>(yi);
-    y[off + i] = ys;
-    acc += todbl(vv[off + i]) * todbl(ys);
+// Second kernel of a fused MINRES step (the first is the operator apply:
+// y = A v_k, partial sums pa of v_k . A v_k, state st with the coefficients
+// of step k-1).  With c1 = beta_k / beta_{k-1}:
+//   alfa = sum(pa) - c1 (z_k . r1) / beta_k
+//   y = A v_k - c1 r1 - (alfa / beta_k) r2 ;  z_{k+1} = dinv .* y
+//   partials of y . z_{k+1} (beta_{k+1}^2) and z_{k+1} . r2 (next z . r1)
+// and, when due, step k-1's w_{k-1} = (v_{k-1} - oldeps w_{k-3} - delta
+// w_{k-2}) * denom with v_{k-1} = zp / beta_{k-1}, x += phi w_{k-1}; zp
+// (z_{k-1}) is read before z_{k+1} is written over it.  Skipped unless st
+// is fresh.
+template <typename TV, bool UPD>
+__device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* __restrict__ dinv, long long n,
+                                            long long off, const MinresState& s, double c1, double c,
+                                            double vpinv, double& ab, double& ac) {
+  // restrict-qualified locals let the compiler issue every load of an
+  // unrolled group before the stores of the previous one
+  TV* __restrict__ y = v.y + off;
+  const TV* __restrict__ r1 = v.r1 + off;
+  const TV* __restrict__ r2 = v.r2 + off;
+  TV* __restrict__ zp = v.zp + off;
+  TV* __restrict__ x = v.x + off;
+  const TV* __restrict__ wa = v.wa + off;
+  const TV* __restrict__ wb = v.wb + off;
+  TV* __restrict__ wo = v.wout + off;
+  constexpr int U = 4;
+  const long long stride = (long long)gridDim.x * kBT;
+  long long i0 = (long long)blockIdx.x * kBT + threadIdx.x;
+  auto one = [&](long long i, double yv, double r1v, double r2v, double dv, double zpv, double wav, double wbv,
+                 double xv) {
+    const TV ys = static_cast<TV>(yv - c1 * r1v - c * r2v);
+    y[i] = ys;
+    const TV zs = static_cast<TV>(dv * todbl(ys));
+    if constexpr (UPD) {
+      const double vp = todbl(static_cast<TV>(zpv * vpinv));
+      const TV ws = static_cast<TV>((vp - s.oldeps * wav - s.delta * wbv) * s.denom);
+      wo[i] = ws;
+      x[i] = static_cast<TV>(xv + s.phi * todbl(ws));
+    }
+    zp[i] = zs;
+    ab += todbl(ys) * todbl(zs);
+    ac += todbl(zs) * r2v;
+  };
+  for (; i0 + (U - 1) * stride < n; i0 += U * stride) {
+    double yv[U], r1v[U], r2v[U], dv[U], zpv[U], wav[U], wbv[U], xv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long long i = i0 + u * stride;
+      yv[u] = todbl(y[i]);
+      r1v[u] = todbl(r1[i]);
+      r2v[u] = todbl(r2[i]);
+      dv[u] = dinv[i];
+      if constexpr (UPD) {
+        zpv[u] = todbl(zp[i]);
+        wav[u] = todbl(wa[i]);
+        wbv[u] = todbl(wb[i]);
+        xv[u] = todbl(x[i]);
+      } else {
+        zpv[u] = wav[u] = wbv[u] = xv[u] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) one(i0 + u * stride, yv[u], r1v[u], r2v[u], dv[u], zpv[u], wav[u], wbv[u], xv[u]);
   }
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part_a[rhs * gridDim.x + blockIdx.x] = t;
+  for (; i0 < n; i0 += stride) {
+    if constexpr (UPD)
+      one(i0, todbl(y[i0]), todbl(r1[i0]), todbl(r2[i0]), dinv[i0], todbl(zp[i0]), todbl(wa[i0]), todbl(wb[i0]),
+          todbl(x[i0]));
+    else
+      one(i0, todbl(y[i0]), todbl(r1[i0]), todbl(r2[i0]), dinv[i0], 0.0, 0.0, 0.0, 0.0);
+  }
 }
 
-// alfa = v . y ; y -= (alfa/beta) r2 ; z = dinv .* y -> zbuf ; partial (y . z)
 template <typename TV>
-__global__ void __launch_bounds__(kBT) minres_k5(TV* __restrict__ y, const TV* __restrict__ r2,
-                                                 TV* __restrict__ zbuf, const double* __restrict__ dinv,
-                                                 long long n, const MinresState* cur,
-                                                 const double* part_a, double* part_b) {
+__global__ void __launch_bounds__(kBT) minres_step2(MrVecs<TV> v, const double* __restrict__ dinv, long long n,
+                                                    const MinresState* st, const double* pa, int npa, double* pb,
+                                                    double* pc, double* alfa_out) {
   __shared__ double sh[kBT];
   const int rhs = blockIdx.y;
-  const MinresState s = cur[rhs];
-  if (s.done) return;
-  const int np = gridDim.x;
-  const double alfa = reduce_partials(part_a + rhs * np, np, sh);
-  const double c = alfa / s.beta;
+  const MinresState s = st[rhs];
+  if (!s.fresh || s.beta == 0.0) return;
+  const double c1 = s.oldb > 0 ? s.beta / s.oldb : 0.0;
+  const double vinv = 1.0 / s.beta;
+  const double alfa = reduce_partials(pa + (long long)rhs * npa, npa, sh) - c1 * s.zr1 * vinv;
+  if (blockIdx.x == 0 && threadIdx.x == 0) alfa_out[rhs] = alfa;
+  const double c = alfa * vinv;
+  const double vpinv = s.oldb > 0 ? 1.0 / s.oldb : 0.0;
   const long long off = (long long)rhs * n;
-  double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
-    double yi = todbl(y[off + i]) - c * todbl(r2[off + i]);
-    TV ys = static_cast<TV>(yi);
-    y[off + i] = ys;
-    double zi = dinv[i] * todbl(ys);
-    TV zs = static_cast<TV>(zi);
-    zbuf[off + i] = zs;
-    acc += todbl(ys) * todbl(zs);
+  double ab = 0.0, ac = 0.0;
+  if (s.upd) step2_sweep<TV, true>(v, dinv, n, off, s, c1, c, vpinv, ab, ac);
+  else step2_sweep<TV, false>(v, dinv, n, off, s, c1, c, vpinv, ab, ac);
+  double tb = block_sum(ab, sh);
+  double tc = block_sum(ac, sh);
+  if (threadIdx.x == 0) {
+    pb[rhs * gridDim.x + blockIdx.x] = tb;
+    pc[rhs * gridDim.x + blockIdx.x] = tc;
   }
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) part_b[rhs * gridDim.x + blockIdx.x] = t;
 }
 
-// Givens update, w/x update and next v:
-//   w_new = (v - oldeps w1 - delta w2) / gamma, x += phi w_new, v = z / beta
-// with (w1, w2) = (old w2, old w); w_new is written over old w1.
+// Completes a pending step without a further apply (iteration cap reached):
+// scalar update, w_k = (v_{k-1} - oldeps w_{k-2} - delta w_{k-1}) / gamma over
+// wout, x += phi w_k.  Converged states are copied forward.
 template <typename TV>
-__global__ void __launch_bounds__(kBT) minres_k7(MinresVecs<TV> v, long long n, const MinresState* cur,
-                                                 MinresState* next, const double* part_a,
-                                                 const double* part_b) {
+__global__ void __launch_bounds__(kBT) minres_finish(TV* __restrict__ x, const TV* __restrict__ zprev,
+                                                     const TV* __restrict__ wa, const TV* __restrict__ wb,
+                                                     TV* __restrict__ wout, long long n, const MinresState* cur,
+                                                     MinresState* next, const double* pb, int npb,
+                                                     const double* alfa) {
   __shared__ double sh[kBT];
   const int rhs = blockIdx.y;
   MinresState s = cur[rhs];
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (s.done) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) next[rhs] = s;
+    if (lead) {
+      s.fresh = 0;
+      next[rhs] = s;
+    }
     return;
   }
-  const int np = gridDim.x;
-  const double alfa = reduce_partials(part_a + rhs * np, np, sh);
-  const double b2 = reduce_partials(part_b + rhs * np, np, sh);
+  const double vinv_prev = s.beta > 0 ? 1.0 / s.beta : 0.0;
   double phi, denom, oldeps, delta, vinv;
-  minres_scalar_update(s, alfa, b2, phi, denom, oldeps, delta, vinv);
-  if (blockIdx.x == 0 && threadIdx.x == 0) next[rhs] = s;
+  const double b2 = reduce_partials(pb + (long long)rhs * npb, npb, sh);
+  minres_scalar_update(s, alfa[rhs], b2, phi, denom, oldeps, delta, vinv);
+  s.fresh = 0;
+  if (lead) next[rhs] = s;
   const long long off = (long long)rhs * n;
   for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
-    double w1 = todbl(v.w2[off + i]);
-    double w2 = todbl(v.w[off + i]);
-    double wn = (todbl(v.v[off + i]) - oldeps * w1 - delta * w2) * denom;
+    double vp = todbl(static_cast<TV>(todbl(zprev[off + i]) * vinv_prev));
+    double wn = (vp - oldeps * todbl(wa[off + i]) - delta * todbl(wb[off + i])) * denom;
     TV ws = static_cast<TV>(wn);
-    v.w1[off + i] = ws;  // old w1 buffer becomes the new w
-    v.x[off + i] = static_cast<TV>(todbl(v.x[off + i]) + phi * todbl(ws));
-    v.v[off + i] = static_cast<TV>(todbl(v.y[off + i]) * vinv);
+    wout[off + i] = ws;
+    x[off + i] = static_cast<TV>(todbl(x[off + i]) + phi * todbl(ws));
   }
 }
 
@@ -360,6 +375,12 @@ __global__ void __launch_bounds__(kBT) sub_kernel(const double* a, const double*
     y[i] = a[i] - b[i];
 }
 
+// x += d (all FP64)
+__global__ void __launch_bounds__(kBT) add_kernel(const double* d, double* x, long long n) {
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
+    x[i] += d[i];
+}
+
 // y32 = scale[rhs] * a64 (rhs-wise scaling)
 __global__ void __launch_bounds__(kBT) to_f32_scaled(const double* a, float* y, long long n, const double* scale) {
   const int rhs = blockIdx.y;
@@ -397,21 +418,17 @@ void minres_launch_init(const MinresVecs<TV>& v, const double* dinv, long long n
 }
 
 template <typename TV>
-void minres_launch_k3(TV* y, const TV* r1, const TV* vv, long long n, int nrhs, int nb, const MinresState* cur,
-                      double* pa, hipStream_t s) {
-  GYM_LAUNCH(minres_k3<TV>, dim3(nb, nrhs), s, y, r1, vv, n, cur, pa);
+void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb,
+                         const MinresState* st, const double* pa, int npa, double* pb, double* pc, double* alfa,
+                         hipStream_t s) {
+  GYM_LAUNCH(minres_step2<TV>, dim3(nb, nrhs), s, v, dinv, n, st, pa, npa, pb, pc, alfa);
 }
 
 template <typename TV>
-void minres_launch_k5(TV* y, const TV* r2, TV* z, const double* dinv, long long n, int nrhs, int nb,
-                      const MinresState* cur, const double* pa, double* pb, hipStream_t s) {
-  GYM_LAUNCH(minres_k5<TV>, dim3(nb, nrhs), s, y, r2, z, dinv, n, cur, pa, pb);
-}
-
-template <typename TV>
-void minres_launch_k7(const MinresVecs<TV>& v, long long n, int nrhs, int nb, const MinresState* cur,
-                      MinresState* next, const double* pa, const double* pb, hipStream_t s) {
-  GYM_LAUNCH(minres_k7<TV>, dim3(nb, nrhs), s, v, n, cur, next, pa, pb);
+void minres_launch_finish(TV* x, const TV* zprev, const TV* wa, const TV* wb, TV* wout, long long n, int nrhs,
+                          int nb, const MinresState* cur, MinresState* next, const double* pb,
+                          const double* alfa, hipStream_t s) {
+  GYM_LAUNCH(minres_finish<TV>, dim3(nb, nrhs), s, x, zprev, wa, wb, wout, n, cur, next, pb, nb, alfa);
 }
 
 template <typename TV>
@@ -439,6 +456,10 @@ void launch_sub(const double* a, const double* b, double* y, long long n, int nb
   GYM_LAUNCH(sub_kernel, dim3(nb), s, a, b, y, n);
 }
 
+void launch_add(const double* d, double* x, long long n, int nb, hipStream_t s) {
+  GYM_LAUNCH(add_kernel, dim3(nb), s, d, x, n);
+}
+
 void launch_to_f32_scaled(const double* a, float* y, long long n, int nrhs, int nb, const double* scale,
                           hipStream_t s) {
   GYM_LAUNCH(to_f32_scaled, dim3(nb, nrhs), s, a, y, n, scale);
@@ -453,18 +474,18 @@ template void minres_launch_init<double>(const MinresVecs<double>&, const double
                                          MinresState*, double, hipStream_t);
 template void minres_launch_init<float>(const MinresVecs<float>&, const double*, long long, int, int, double*,
                                         MinresState*, double, hipStream_t);
-template void minres_launch_k3<double>(double*, const double*, const double*, long long, int, int,
-                                       const MinresState*, double*, hipStream_t);
-template void minres_launch_k3<float>(float*, const float*, const float*, long long, int, int,
-                                      const MinresState*, double*, hipStream_t);
-template void minres_launch_k5<double>(double*, const double*, double*, const double*, long long, int, int,
-                                       const MinresState*, const double*, double*, hipStream_t);
-template void minres_launch_k5<float>(float*, const float*, float*, const double*, long long, int, int,
-                                      const MinresState*, const double*, double*, hipStream_t);
-template void minres_launch_k7<double>(const MinresVecs<double>&, long long, int, int, const MinresState*,
-                                       MinresState*, const double*, const double*, hipStream_t);
-template void minres_launch_k7<float>(const MinresVecs<float>&, long long, int, int, const MinresState*,
-                                      MinresState*, const double*, const double*, hipStream_t);
+template void minres_launch_step2<double>(const MrVecs<double>&, const double*, long long, int, int,
+                                          const MinresState*, const double*, int, double*, double*, double*,
+                                          hipStream_t);
+template void minres_launch_step2<float>(const MrVecs<float>&, const double*, long long, int, int,
+                                         const MinresState*, const double*, int, double*, double*, double*,
+                                         hipStream_t);
+template void minres_launch_finish<double>(double*, const double*, const double*, const double*, double*,
+                                           long long, int, int, const MinresState*, MinresState*,
+                                           const double*, const double*, hipStream_t);
+template void minres_launch_finish<float>(float*, const float*, const float*, const float*, float*, long long,
+                                          int, int, const MinresState*, MinresState*, const double*,
+                                          const double*, hipStream_t);
 template void cg_launch_init<double>(const CgVecs<double>&, const double*, long long, int, int, double*,
                                      CgState*, double, hipStream_t);
 template void cg_launch_iter_tail<double>(const CgVecs<double>&, const double*, long long, int, int,

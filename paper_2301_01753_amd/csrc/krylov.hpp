@@ -2,12 +2,9 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
-namespace gym {
+#include "minres_step.hpp"
 
-struct MinresState {
-  double beta, oldb, dbar, epsln, phibar, cs, sn, tnorm2, beta1, alfa, tol;
-  int itn, done, flag, pad;  // flag: 0 running, 1 converged, -1 breakdown
-};
+namespace gym {
 
 struct CgState {
   double rz, rz0, tol;
@@ -47,15 +44,25 @@ int vec_grid(long long n, int ncu);
 template <typename TV>
 void minres_launch_init(const MinresVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, double* part,
                         MinresState* st0, double tol, hipStream_t s);
+// Vectors of the second kernel of a fused MINRES step (rhs-major).
 template <typename TV>
-void minres_launch_k3(TV* y, const TV* r1, const TV* vv, long long n, int nrhs, int nb, const MinresState* cur,
-                      double* pa, hipStream_t s);
+struct MrVecs {
+  TV *y, *r1, *r2, *zp, *x;
+  const TV *wa, *wb;  // w_{k-3}, w_{k-2}
+  TV* wout;           // receives w_{k-1} (holds w_{k-4})
+};
+
+// Fused MINRES step, second kernel (after the operator apply that carries
+// the first half, see MrStep); npa = workgroups per rhs of that apply.
 template <typename TV>
-void minres_launch_k5(TV* y, const TV* r2, TV* z, const double* dinv, long long n, int nrhs, int nb,
-                      const MinresState* cur, const double* pa, double* pb, hipStream_t s);
+void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb,
+                         const MinresState* st, const double* pa, int npa, double* pb, double* pc, double* alfa,
+                         hipStream_t s);
+// Completes a pending step (iteration cap): state cur -> next, w and x.
 template <typename TV>
-void minres_launch_k7(const MinresVecs<TV>& v, long long n, int nrhs, int nb, const MinresState* cur,
-                      MinresState* next, const double* pa, const double* pb, hipStream_t s);
+void minres_launch_finish(TV* x, const TV* zprev, const TV* wa, const TV* wb, TV* wout, long long n, int nrhs,
+                          int nb, const MinresState* cur, MinresState* next, const double* pb,
+                          const double* alfa, hipStream_t s);
 template <typename TV>
 void cg_launch_init(const CgVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, double* part,
                     CgState* st0, double tol, hipStream_t s);
@@ -66,6 +73,7 @@ void cg_launch_iter_tail(const CgVecs<TV>& v, const double* dinv, long long n, i
 void launch_norm2(const double* a, const double* b, long long n, int nrhs, int nb, int mode, double* part,
                   double* out, hipStream_t s);
 void launch_sub(const double* a, const double* b, double* y, long long n, int nb, hipStream_t s);
+void launch_add(const double* d, double* x, long long n, int nb, hipStream_t s);
 void launch_to_f32_scaled(const double* a, float* y, long long n, int nrhs, int nb, const double* scale,
                           hipStream_t s);
 void launch_axpy_f32(const float* d, double* x, long long n, int nrhs, int nb, const double* scale,

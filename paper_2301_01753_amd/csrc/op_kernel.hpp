@@ -200,7 +200,7 @@ __device__ __forceinline__ void pointwise_curved(TC* Q0, TC* Q1, TC* Q2, const T
                                                  const ElemRange& er) {
   const TabSet<TC>& T = tabs<TC>(C::R);
   constexpr int N = C::QX * C::QY * C::QZ;
-  for (int idx = threadIdx.x; idx < N; idx += kNT) {
+  for (int idx = threadIdx.x; idx < N; idx += C::NT) {
     int qx = idx % C::QX, r = idx / C::QX;
     int qy = r % C::QY, qz = r / C::QY;
     int ex = qx / C::Q, ey = qy / C::Q;
@@ -336,6 +336,67 @@ __device__ __forceinline__ void vmass2(TC* const in[2], TC* const out[2], const 
   }
 }
 
+// ---- fused MINRES step -------------------------------------------------------
+// Sum over the workgroup in a fixed order (every workgroup of a launch, and
+// every launch, adds in the same order: results are reproducible).
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double* sh) {
+  sh[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sh[0];
+  __syncthreads();
+  return r;
+}
+
+struct MrScalars {
+  double vinv;  // 1 / beta_k
+};
+
+// Scalar part of the fused step, redundantly in every workgroup (same
+// inputs, same order: every workgroup agrees); `lead` stores the new state.
+// Returns false when this rhs has already converged (state copied forward).
+template <int NT>
+__device__ __forceinline__ bool mr_prologue(const MrStep& m, int rhs, bool lead, double* sh, MrScalars& ms) {
+  MinresState s = m.cur[rhs];
+  if (s.done) {
+    if (lead && threadIdx.x == 0) {
+      s.fresh = 0;
+      m.next[rhs] = s;
+    }
+    return false;
+  }
+  if (m.first) {
+    s.upd = 0;
+    s.zr1 = 0.0;
+    ms.vinv = s.beta > 0 ? 1.0 / s.beta : 0.0;
+  } else {
+    const double* pb = m.pb + (long long)rhs * m.npb;
+    const double* pc = m.pc + (long long)rhs * m.npb;
+    double vb = 0.0, vc = 0.0;
+    for (int i = threadIdx.x; i < m.npb; i += NT) {
+      vb += pb[i];
+      vc += pc[i];
+    }
+    const double b2 = wg_sum<NT>(vb, sh);
+    s.zr1 = wg_sum<NT>(vc, sh);
+    double phi, denom, oldeps, delta;
+    minres_scalar_update(s, m.alfa[rhs], b2, phi, denom, oldeps, delta, ms.vinv);
+    s.phi = phi;
+    s.denom = denom;
+    s.oldeps = oldeps;
+    s.delta = delta;
+    s.upd = 1;
+  }
+  s.fresh = 1;
+  if (lead && threadIdx.x == 0) m.next[rhs] = s;
+  return true;
+}
+
 // ---- the kernel body -------------------------------------------------------
 // (bx, by, bz) = (tile, z-chunk, right-hand side) of this workgroup.
 template <class C, int PROB, int FORM, typename TV, typename TC>
@@ -353,9 +414,17 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
   const int tx = b % p.tiles_x, ty = b / p.tiles_x;
   const int X0 = tx * C::BX, Y0 = ty * C::BY;
   const int rhs = bz;
-  const TV* __restrict__ xin = reinterpret_cast<const TV*>(p.x) + (long long)rhs * p.ndofs;
-  TV* __restrict__ yout = reinterpret_cast<TV*>(p.y) + (long long)rhs * p.ndofs;
+  const long long voff = (long long)rhs * p.ndofs;
+  const TV* __restrict__ xin = reinterpret_cast<const TV*>(p.x) + voff;
+  TV* __restrict__ yout = reinterpret_cast<TV*>(p.y) + voff;
   const int gx0 = R * (X0 - 1), gy0 = R * (Y0 - 1);
+
+  // ---- fused MINRES step: finish step k-1, take its scalars
+  MrScalars ms{};
+  double mr_acc = 0.0;
+  if (p.fused) {
+    if (!mr_prologue<C::NT>(p.mr, rhs, bx == 0 && by == 0, reinterpret_cast<double*>(smem), ms)) return;
+  }
 
   Work<TC> w;
   w.A = smem + L::A_off();
@@ -383,7 +452,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
     constexpr int f = decltype(fc)::value;
     if constexpr (L::carries(f)) {
       TC* car = smem + L::car_off(f);
-      for (int i = threadIdx.x; i < C::plane(F::tm[f]); i += kNT) car[i] = 0;
+      for (int i = threadIdx.x; i < C::plane(F::tm[f]); i += C::NT) car[i] = 0;
     }
   });
 
@@ -399,13 +468,16 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
       const DevComp& cd = (F::sp[f] == 0 ? p.sa : p.sb).c[F::cp[f]];
       TC* in = smem + L::in_off(f);
       TC* out = smem + L::out_off(f);
-      for (int i = threadIdx.x; i < C::lat(TM); i += kNT) {
+      for (int i = threadIdx.x; i < C::lat(TM); i += C::NT) {
         int lx, ly, lz;
         lpos<C, TM>(i, lx, ly, lz);
         int g0 = gx0 + lx - cd.start[0], g1 = gy0 + ly - cd.start[1], g2 = gz0 + lz - cd.start[2];
         TC v = 0;
-        if (g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2])
-          v = static_cast<TC>(xin[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)]);
+        if (g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2]) {
+          TV xv = xin[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)];
+          if (p.fused) xv = static_cast<TV>(static_cast<double>(xv) * ms.vinv);  // v_k = z_k / beta_k
+          v = static_cast<TC>(xv);
+        }
         in[i] = v;
         out[i] = 0;
       }
@@ -414,7 +486,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
       // vertices of the layer, clamped into the mesh (cells outside it are
       // masked, their clamped geometry only has to stay finite)
       constexpr int NVX = C::EX + 1, NVY = C::EY + 1;
-      for (int i = threadIdx.x; i < 2 * NVX * NVY * 3; i += kNT) {
+      for (int i = threadIdx.x; i < 2 * NVX * NVY * 3; i += C::NT) {
         int a = i % 3, r = i / 3;
         int lx = r % NVX, r2 = r / NVX;
         int ly = r2 % NVY, lz = r2 / NVY;
@@ -436,7 +508,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
       smass<C, 7, GYM_H1, true, FORM>(IN(0), OUT(0), (TC)-p.sc[0], w);
       // G^T (M1 u): v = M1 u on the closure, y_sigma(q) += sum_c v_c(q-e_c) - v_c(q)
       vmass<C, GYM_HCURL, 6, 5, 3, false, FORM>(in_u, Lb, s1, w);
-      for (int i = threadIdx.x; i < C::lat(7); i += kNT) {
+      for (int i = threadIdx.x; i < C::lat(7); i += C::NT) {
         int q[3];
         lpos<C, 7>(i, q[0], q[1], q[2]);
         TC acc = 0;
@@ -458,7 +530,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
         constexpr int c = decltype(cc)::value;
         constexpr int TE = 7 & ~(1 << c);
         const TC* sg = IN(0);
-        for (int i = threadIdx.x; i < C::lat(TE); i += kNT) {
+        for (int i = threadIdx.x; i < C::lat(TE); i += C::NT) {
           int q[3];
           lpos<C, TE>(i, q[0], q[1], q[2]);
           int s[3] = {q[0], q[1], q[2]};
@@ -478,7 +550,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
         constexpr int T1 = 7 & ~(1 << c1), T2 = 7 & ~(1 << c2);
         const TC* a1 = in_u[c1];
         const TC* a2 = in_u[c2];
-        for (int i = threadIdx.x; i < C::lat(TF); i += kNT) {
+        for (int i = threadIdx.x; i < C::lat(TF); i += C::NT) {
           int q[3];
           lpos<C, TF>(i, q[0], q[1], q[2]);
           int t1[3] = {q[0], q[1], q[2]}, t2[3] = {q[0], q[1], q[2]};
@@ -501,7 +573,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
         constexpr int TE = 7 & ~(1 << e);
         constexpr int TF1 = 1 << e1, TF2 = 1 << e2;
         TC* o = out_u[e];
-        for (int i = threadIdx.x; i < C::lat(TE); i += kNT) {
+        for (int i = threadIdx.x; i < C::lat(TE); i += C::NT) {
           int q[3];
           lpos<C, TE>(i, q[0], q[1], q[2]);
           TC acc = 0;
@@ -545,7 +617,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
         constexpr int c = decltype(cc)::value;
         constexpr int TF = F::tm[c];
         TC* o = OUT(c);
-        for (int i = threadIdx.x; i < C::lat(TF); i += kNT) {
+        for (int i = threadIdx.x; i < C::lat(TF); i += C::NT) {
           int q[3];
           lpos<C, TF>(i, q[0], q[1], q[2]);
           TC acc = 0;
@@ -560,7 +632,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
       });
       __syncthreads();
       // -M3 (D s): div(p) = sum_c s_c(p + e_c) - s_c(p)
-      for (int i = threadIdx.x; i < C::lat(0); i += kNT) {
+      for (int i = threadIdx.x; i < C::lat(0); i += C::NT) {
         int q[3];
         lpos<C, 0>(i, q[0], q[1], q[2]);
         TC v = 0;
@@ -602,7 +674,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
           constexpr int PL = C::plane(F::tm[f]);
           TC* out = smem + L::out_off(f);
           TC* car = smem + L::car_off(f);
-          for (int i = threadIdx.x; i < PL; i += kNT) {
+          for (int i = threadIdx.x; i < PL; i += C::NT) {
             out[i] += car[i];
             car[i] = out[i + R * PL];
           }
@@ -618,7 +690,8 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
         constexpr int TM = F::tm[f];
         const DevComp& cd = (F::sp[f] == 0 ? p.sa : p.sb).c[F::cp[f]];
         const TC* out = smem + L::out_off(f);
-        for (int i = threadIdx.x; i < C::lat(TM); i += kNT) {
+        const TC* in = smem + L::in_off(f);
+        for (int i = threadIdx.x; i < C::lat(TM); i += C::NT) {
           int lx, ly, lz;
           lpos<C, TM>(i, lx, ly, lz);
           int G0 = gx0 + lx, G1 = gy0 + ly, G2 = gz0 + lz;
@@ -626,19 +699,28 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
                      (G1 < R * (Y0 + C::BY) || G1 == p.m[1]);
           if constexpr (C::DIM == 3) own = own && (G2 < gz0 + R || G2 == p.m[2]);
           int g0 = G0 - cd.start[0], g1 = G1 - cd.start[1], g2 = G2 - cd.start[2];
-          if (own && g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2])
-            yout[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)] =
-                static_cast<TV>(out[i]);
+          if (own && g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2]) {
+            const long long gi = cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2);
+            const TV ys = static_cast<TV>(out[i]);
+            yout[gi] = ys;
+            if (p.fused) mr_acc += static_cast<double>(in[i]) * static_cast<double>(ys);  // v_k . A v_k
+          }
         }
       });
     }
     __syncthreads();
   }
+  if (p.fused) {
+    const double t = wg_sum<C::NT>(mr_acc, reinterpret_cast<double*>(smem));
+    if (threadIdx.x == 0) p.mr.pa[(long long)rhs * nt * p.nchunks + bx + nt * by] = t;
+  }
 }
 
 template <class C, int PROB, int FORM, typename TV, typename TC>
-__global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
-  __shared__ TC smem[Layout<C, Fields<PROB, C::DIM>, FORM>::total()];
+__global__ void __launch_bounds__(C::NT) op_kernel(const OpParams p) {
+  constexpr int kWords = Layout<C, Fields<PROB, C::DIM>, FORM>::total();
+  static_assert(kWords * sizeof(TC) >= C::NT * sizeof(double), "LDS holds the workgroup sums");
+  __shared__ __align__(16) TC smem[kWords];
   op_body<C, PROB, FORM, TV, TC>(p, blockIdx.x, blockIdx.y, blockIdx.z, smem);
 }
 
@@ -646,9 +728,9 @@ __global__ void __launch_bounds__(kNT) op_kernel(const OpParams p) {
 // same kind and degree (different meshes and vectors).  bstart holds the
 // prefix sums of the per-request workgroup counts (nreq + 1 entries).
 template <class C, int PROB, int FORM, typename TV, typename TC>
-__global__ void __launch_bounds__(kNT) op_kernel_batch(const OpParams* __restrict__ plist,
+__global__ void __launch_bounds__(C::NT) op_kernel_batch(const OpParams* __restrict__ plist,
                                                        const int* __restrict__ bstart, int nreq) {
-  __shared__ TC smem[Layout<C, Fields<PROB, C::DIM>, FORM>::total()];
+  __shared__ __align__(16) TC smem[Layout<C, Fields<PROB, C::DIM>, FORM>::total()];
   const int blk = blockIdx.x;
   int lo = 0, hi = nreq;  // bstart[lo] <= blk < bstart[hi]
   while (hi - lo > 1) {
@@ -708,15 +790,35 @@ inline int op_tiling(OpParams& p, int B, int dim, int nrhs, int ncu) {
   return nt * nchunks * nrhs;
 }
 
+// Threads of a whole-CU workgroup (one per CU: its waves alone must hide the
+// LDS latency).  Measured on MI355X at about 8M unknowns per operator for
+// 512, 768 and 1024 threads: degree 1 has too little work per stage for more
+// than 512; Gauss-point and the FP32/BF16 Kronecker contractions gain up to
+// 1024; the FP64 Kronecker Hodge kernel at degree >= 3 and the curved kernels
+// run out of registers beyond 768.
+template <int DIM, int R, int PROB, int FORM, typename TC>
+constexpr int big_threads() {
+  if (DIM == 2 || PROB >= PROB_MASS_H1) return 512;
+  if (R == 1) return FORM == FORM_CURVED ? 768 : 512;
+  if (FORM == FORM_CURVED) return 768;
+  if (FORM == FORM_GAUSS) return 1024;
+  if (FORM == FORM_KRON && std::is_same<TC, double>::value) return (PROB == PROB_HODGE && R >= 3) ? 768 : 1024;
+  return R == 2 ? 768 : 1024;
+}
+
 template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, int BUDGET>
 int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
   constexpr int B = TileSel<DIM, R, PROB, FORM, TC, BUDGET>::B;
-  using C = Cfg<R, B, B, DIM>;
+  // one workgroup per CU on the whole-CU budget: widen it to keep enough
+  // waves in flight to hide LDS latency
+  using C = Cfg<R, B, B, DIM, (BUDGET > 40 * 1024 ? big_threads<DIM, R, PROB, FORM, TC>() : kNTSmall)>;
   static_assert(Layout<C, Fields<PROB, DIM>, FORM>::total() * sizeof(TC) <= 160 * 1024, "LDS");
   OpParams p = p0;
   op_tiling(p, B, DIM, nrhs, ncu);
+  if (p0.wg_out) *p0.wg_out = p.tiles_x * p.tiles_y * p.nchunks;
+  if (p0.dry) return 0;
   dim3 grid(p.tiles_x * p.tiles_y, p.nchunks, nrhs);
-  hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC>), grid, dim3(kNT), 0, stream, p);
+  hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC>), grid, dim3(C::NT), 0, stream, p);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -733,35 +835,40 @@ int launch_op_batch_r(OpParams* plist_host, int* bstart_host, int nreq, OpParams
     return -1;
   if (hipMemcpyAsync(bstart_dev, bstart_host, sizeof(int) * (nreq + 1), hipMemcpyHostToDevice, stream) != hipSuccess)
     return -1;
-  hipLaunchKernelGGL((op_kernel_batch<C, PROB, FORM_KRON, TV, TC>), dim3(bstart_host[nreq]), dim3(kNT), 0, stream,
+  hipLaunchKernelGGL((op_kernel_batch<C, PROB, FORM_KRON, TV, TC>), dim3(bstart_host[nreq]), dim3(C::NT), 0, stream,
                      plist_dev, bstart_dev, nreq);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Tile budget 0: whole-CU tiles; 1: small tiles; 2: whole-CU tiles when they
+// still give every CU a workgroup, small tiles otherwise (small meshes).
+template <int DIM, int R, int PROB, int FORM, typename TV, typename TC>
+int launch_form(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
+  constexpr int kBig = 160 * 1024, kSmall = 40 * 1024;
+  bool large = p.tile_budget == 0;
+  if (p.tile_budget == 2) {
+    OpParams q = p;
+    large = op_tiling(q, TileSel<DIM, R, PROB, FORM, TC, kBig>::B, DIM, nrhs, ncu) >= ncu;
+  }
+  if (large) return launch_op_b<DIM, R, PROB, FORM, TV, TC, kBig>(p, nrhs, ncu, stream);
+  return launch_op_b<DIM, R, PROB, FORM, TV, TC, kSmall>(p, nrhs, ncu, stream);
+}
+
 template <int DIM, int R, int PROB, typename TV, typename TC>
 int launch_op(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
-  constexpr int kBig = 160 * 1024, kSmall = 40 * 1024;
   if (p.curved) {
     if (p.bf16) return -2;  // bf16 contractions exist in the Kronecker form only
-    if constexpr (DIM == 3) {
-      if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_CURVED, TV, TC, kBig>(p, nrhs, ncu, stream);
-      return launch_op_b<DIM, R, PROB, FORM_CURVED, TV, TC, kSmall>(p, nrhs, ncu, stream);
-    }
+    if constexpr (DIM == 3) return launch_form<DIM, R, PROB, FORM_CURVED, TV, TC>(p, nrhs, ncu, stream);
     return -2;
   }
   if (p.kron) {
     if constexpr (std::is_same<TC, float>::value) {
-      if (p.bf16) {
-        if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_KRON_BF16, TV, TC, kBig>(p, nrhs, ncu, stream);
-        return launch_op_b<DIM, R, PROB, FORM_KRON_BF16, TV, TC, kSmall>(p, nrhs, ncu, stream);
-      }
+      if (p.bf16) return launch_form<DIM, R, PROB, FORM_KRON_BF16, TV, TC>(p, nrhs, ncu, stream);
     }
-    if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_KRON, TV, TC, kBig>(p, nrhs, ncu, stream);
-    return launch_op_b<DIM, R, PROB, FORM_KRON, TV, TC, kSmall>(p, nrhs, ncu, stream);
+    return launch_form<DIM, R, PROB, FORM_KRON, TV, TC>(p, nrhs, ncu, stream);
   }
   if (p.bf16) return -2;  // bf16 contractions exist in the Kronecker form only
-  if (p.tile_budget == 0) return launch_op_b<DIM, R, PROB, FORM_GAUSS, TV, TC, kBig>(p, nrhs, ncu, stream);
-  return launch_op_b<DIM, R, PROB, FORM_GAUSS, TV, TC, kSmall>(p, nrhs, ncu, stream);
+  return launch_form<DIM, R, PROB, FORM_GAUSS, TV, TC>(p, nrhs, ncu, stream);
 }
 
 template <int DIM, int PROB, typename TV, typename TC>

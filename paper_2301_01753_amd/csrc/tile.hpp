@@ -24,7 +24,9 @@
 
 namespace gym {
 
-constexpr int kNT = 256;  // threads per workgroup
+// Threads per workgroup of the small-tile (40 KB) tilings; the whole-CU
+// tilings choose theirs per problem, degree and form (op_kernel.hpp).
+constexpr int kNTSmall = 256;
 
 // 1-D tables for degree r (index r - 1).  Row t = Gauss point.
 template <typename T>
@@ -85,9 +87,9 @@ __device__ __forceinline__ const TabSet<TC>& ktabs(int r) {
 }
 
 // Compile-time geometry of one layer of a tile.
-template <int R_, int BX_, int BY_, int DIM_>
+template <int R_, int BX_, int BY_, int DIM_, int NT_ = kNTSmall>
 struct Cfg {
-  static constexpr int R = R_, Q = R_ + 1, BX = BX_, BY = BY_, DIM = DIM_;
+  static constexpr int R = R_, Q = R_ + 1, BX = BX_, BY = BY_, DIM = DIM_, NT = NT_;
   static constexpr int EX = BX + 1, EY = BY + 1;
   static constexpr int QX = Q * EX, QY = Q * EY, QZ = DIM == 3 ? Q : 1;
   static constexpr int nx(int tm) { return (tm & 1) ? R * EX + 1 : R * EX; }
@@ -126,7 +128,7 @@ __device__ __forceinline__ void fwd_x(const TC* __restrict__ in, TC* __restrict_
   constexpr bool N = TM & 1;
   constexpr int n = N ? C::R + 1 : C::R;
   const TabSet<TC>& T = tabs<TC>(C::R);
-  for (int idx = threadIdx.x; idx < C::QX * NY * NZ; idx += kNT) {
+  for (int idx = threadIdx.x; idx < C::QX * NY * NZ; idx += C::NT) {
     int qx = idx % C::QX, rest = idx / C::QX;
     int e = qx / C::Q, t = qx - e * C::Q;
     const TC* s = in + rest * NX + C::R * e;
@@ -144,7 +146,7 @@ __device__ __forceinline__ void fwd_y(const TC* __restrict__ in, TC* __restrict_
   constexpr bool N = TM & 2;
   constexpr int n = N ? C::R + 1 : C::R;
   const TabSet<TC>& T = tabs<TC>(C::R);
-  for (int idx = threadIdx.x; idx < C::QX * C::QY * NZ; idx += kNT) {
+  for (int idx = threadIdx.x; idx < C::QX * C::QY * NZ; idx += C::NT) {
     int qx = idx % C::QX, r2 = idx / C::QX;
     int qy = r2 % C::QY, k = r2 / C::QY;
     int e = qy / C::Q, t = qy - e * C::Q;
@@ -161,12 +163,12 @@ template <class C, int TM, typename TC>
 __device__ __forceinline__ void fwd_z(const TC* __restrict__ in, TC* __restrict__ out) {
   constexpr int P = C::QX * C::QY;
   if constexpr (C::DIM == 2) {
-    for (int idx = threadIdx.x; idx < P; idx += kNT) out[idx] = in[idx];
+    for (int idx = threadIdx.x; idx < P; idx += C::NT) out[idx] = in[idx];
   } else {
     constexpr bool N = TM & 4;
     constexpr int n = N ? C::R + 1 : C::R;
     const TabSet<TC>& T = tabs<TC>(C::R);
-    for (int idx = threadIdx.x; idx < P * C::Q; idx += kNT) {
+    for (int idx = threadIdx.x; idx < P * C::Q; idx += C::NT) {
       int p = idx % P, t = idx / P;
       TC acc = 0;
 #pragma unroll
@@ -182,12 +184,12 @@ template <class C, int TM, typename TC>
 __device__ __forceinline__ void bwd_z(const TC* __restrict__ in, TC* __restrict__ out) {
   constexpr int P = C::QX * C::QY;
   if constexpr (C::DIM == 2) {
-    for (int idx = threadIdx.x; idx < P; idx += kNT) out[idx] = in[idx];
+    for (int idx = threadIdx.x; idx < P; idx += C::NT) out[idx] = in[idx];
   } else {
     constexpr bool N = TM & 4;
     constexpr int NZ = C::nz(TM);
     const TabSet<TC>& T = tabs<TC>(C::R);
-    for (int idx = threadIdx.x; idx < P * NZ; idx += kNT) {
+    for (int idx = threadIdx.x; idx < P * NZ; idx += C::NT) {
       int p = idx % P, k = idx / P;
       TC acc = 0;
 #pragma unroll
@@ -219,7 +221,7 @@ __device__ __forceinline__ void bwd_y(const TC* __restrict__ in, TC* __restrict_
   constexpr int NY = C::ny(TM), NZ = C::nz(TM);
   constexpr bool N = TM & 2;
   const TabSet<TC>& T = tabs<TC>(C::R);
-  for (int idx = threadIdx.x; idx < C::QX * NY * NZ; idx += kNT) {
+  for (int idx = threadIdx.x; idx < C::QX * NY * NZ; idx += C::NT) {
     int qx = idx % C::QX, r2 = idx / C::QX;
     int j = r2 % NY, k = r2 / NY;
     const TC* base = in + qx + C::QX * C::QY * k;
@@ -239,7 +241,7 @@ __device__ __forceinline__ void bwd_x(const TC* __restrict__ in, TC* __restrict_
   constexpr int NX = C::nx(TM), NY = C::ny(TM), NZ = C::nz(TM);
   constexpr bool N = TM & 1;
   const TabSet<TC>& T = tabs<TC>(C::R);
-  for (int idx = threadIdx.x; idx < NX * NY * NZ; idx += kNT) {
+  for (int idx = threadIdx.x; idx < NX * NY * NZ; idx += C::NT) {
     int j = idx % NX, rest = idx / NX;
     const TC* base = in + C::QX * rest;
     TC v = gather1d<C::R, C::EX, N>(j, [&](int e, int i) {
@@ -294,7 +296,7 @@ __device__ __forceinline__ void mass_kron(const TC* in, TC* out, TC scale, TC* A
   {
     constexpr bool N = TM & 1;
     constexpr int n = N ? R + 1 : R;
-    for (int idx = threadIdx.x; idx < NX * NY * NZ; idx += kNT) {
+    for (int idx = threadIdx.x; idx < NX * NY * NZ; idx += C::NT) {
       int j = idx % NX;
       const TC* s = in + (idx - j);
       A[idx] = gather1d<R, C::EX, N>(j, [&](int e, int i) {
@@ -311,7 +313,7 @@ __device__ __forceinline__ void mass_kron(const TC* in, TC* out, TC scale, TC* A
   {
     constexpr bool N = TM & 2;
     constexpr int n = N ? R + 1 : R;
-    for (int idx = threadIdx.x; idx < NX * NY * NZ; idx += kNT) {
+    for (int idx = threadIdx.x; idx < NX * NY * NZ; idx += C::NT) {
       int x = idx % NX, r2 = idx / NX;
       int j = r2 % NY, k = r2 / NY;
       const TC* s = A + x + NX * NY * k;
@@ -328,7 +330,7 @@ __device__ __forceinline__ void mass_kron(const TC* in, TC* out, TC scale, TC* A
   __syncthreads();
   {
     constexpr int P = NX * NY;
-    for (int idx = threadIdx.x; idx < P * NZ; idx += kNT) {
+    for (int idx = threadIdx.x; idx < P * NZ; idx += C::NT) {
       TC v;
       if constexpr (C::DIM == 2) {
         v = B[idx];
@@ -438,13 +440,13 @@ __device__ __forceinline__ void kron_cols(TC* const in[3], TC* const out[3], con
   constexpr int n0 = C::nx(T0) * C::ny(T0);
   constexpr int n1 = NCOMP > 1 ? C::nx(T1) * C::ny(T1) : 0;
   constexpr int n2 = NCOMP > 2 ? C::nx(T2) * C::ny(T2) : 0;
-  for (int idx = threadIdx.x; idx < n0 + n1 + n2; idx += kNT) {
+  for (int idx = threadIdx.x; idx < n0 + n1 + n2; idx += C::NT) {
     if (idx < n0) kron_x_col<C, T0, BF>(in[0], A[0], idx, er);
     else if (NCOMP > 1 && idx < n0 + n1) kron_x_col<C, T1, BF>(in[1], A[1], idx - n0, er);
     else if (NCOMP > 2) kron_x_col<C, T2, BF>(in[2], A[2], idx - n0 - n1, er);
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < n0 + n1 + n2; idx += kNT) {
+  for (int idx = threadIdx.x; idx < n0 + n1 + n2; idx += C::NT) {
     if (idx < n0) kron_yz_col<C, T0, ADD, BF>(A[0], out[0], sc[0], idx, er);
     else if (NCOMP > 1 && idx < n0 + n1) kron_yz_col<C, T1, ADD, BF>(A[1], out[1], sc[1], idx - n0, er);
     else if (NCOMP > 2) kron_yz_col<C, T2, ADD, BF>(A[2], out[2], sc[2], idx - n0 - n1, er);

@@ -278,6 +278,58 @@ def test_solve_fp64_matches_direct(g, which, nel, r):
     gym.gym_mesh_destroy(mesh)
 
 
+@pytest.mark.parametrize("maxit", [1, 7, 30])
+@pytest.mark.parametrize("which,nel,r", [("hodge", (4, 3, 5), 2), ("poisson", (5, 4, 3), 1)])
+def test_solve_iteration_cap_matches_minres_iterate(g, which, nel, r, maxit):
+    # Stopped by the iteration cap, the solve returns the k-th preconditioned
+    # MINRES iterate (the pending step is completed without another apply):
+    # SciPy's Paige-Saunders MINRES with the same diagonal, k iterations.
+    gym, ctx = g
+    mesh = _mesh(gym, ctx, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON if which == "poisson" else gym.GYM_HODGE1, mesh, r)
+    P = _oracle_problem(which, nel, r)
+    n = P.A.shape[0]
+    b = synth.random_vector(n, seed=21, nrhs=2)
+    x = torch.empty(2 * n, dtype=torch.float64, device=DEV)
+    opts = gym.gym_solve_opts_default()
+    opts.rtol = 1e-14
+    opts.maxit = maxit
+    opts.check_every = 4
+    info = gym.gym_solve(op, opts, 2, _t(b), x)
+    assert info.iters == maxit and info.status == gym.GYM_W_NOT_CONVERGED
+    got = x.cpu().numpy().reshape(2, -1)
+    for k in range(2):
+        ref, _ = problems.solve_minres(P.A, b.reshape(2, -1)[k], P.precond_diag(), rtol=1e-300, maxiter=maxit)
+        err = np.linalg.norm(got[k] - ref) / np.linalg.norm(ref)
+        assert err < 1e-10, f"rhs {k}: {maxit} iterations, rel diff {err}"
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
+def test_solve_converged_rhs_is_left_alone(g):
+    # Three right-hand sides in one launch; the zero one is converged at the
+    # start and must stay exactly zero while the others iterate.
+    gym, ctx = g
+    nel, r = (4, 4, 3), 2
+    mesh = _mesh(gym, ctx, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, r)
+    P = _oracle_problem("hodge", nel, r)
+    n = P.A.shape[0]
+    b = np.concatenate([synth.random_vector(n, seed=5), np.zeros(n), synth.random_vector(n, seed=6)])
+    x = torch.full((3 * n,), 7.0, dtype=torch.float64, device=DEV)
+    opts = gym.gym_solve_opts_default()
+    opts.rtol = 1e-12
+    info = gym.gym_solve(op, opts, 3, _t(b), x)
+    got = x.cpu().numpy().reshape(3, -1)
+    assert info.status == 0
+    assert np.all(got[1] == 0.0)
+    for k in (0, 2):
+        ref = problems.solve_direct(P.A, b.reshape(3, -1)[k])
+        assert np.linalg.norm(got[k] - ref) / np.linalg.norm(ref) < 1e-9
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
 @pytest.mark.parametrize("which,nel,r", [("poisson", (5, 6, 4), 2), ("hodge", (4, 5, 4), 2)])
 def test_solve_mixed_precision_refinement(g, which, nel, r):
     gym, ctx = g
