@@ -1,0 +1,131 @@
+"""GPU parity at the full workload sizes, on sampled outputs.
+
+The oracle cannot assemble the full systems (1 M to 95 M unknowns), but one
+row of either block operator only couples unknowns of the elements that
+contain its own unknown (every product in it - M G, G^T M G, C^T M C, M D -
+stays inside one element).  So the oracle is assembled on a 5 x 5 x 5 element
+patch of the same mesh (same vertices, perturbed ones included) and the rows
+of the unknowns on the closure of the patch's middle element are exact rows
+of the global operator: the elements they touch lie inside the patch, away
+from its boundary, where the patch problem drops its own boundary unknowns.
+Patches at the low and high corners put the domain boundary (and its
+essential conditions, for the Hodge problem) into the sample.
+
+The operator is applied by the GPU in the launch configuration the benchmark
+times (automatic tiles, 1 or 8 right-hand sides) to a seeded N(0, 1) vector;
+only the patch's entries of x and the sampled entries of y cross to the host.
+Tolerances as in test_gpu_parity: FP64 1e-13, FP32 2e-5 of the sampled max
+norm; BF16 contractions sit between 1e-5 and 5e-2.
+"""
+import numpy as np
+import pytest
+
+import synth
+from patch_rows import global_spaces, origins, patch_rows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def g():
+    from paper_2301_01753_amd import gym
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = gym.gym_create(0)
+    yield gym, ctx
+    gym.gym_destroy(ctx)
+
+
+def _check(gym, ctx, which, nel, r, verts, nrhs, prec, tol, seed):
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=None if verts is None else verts)
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1 if which == "hodge" else gym.GYM_MIXED_POISSON, mesh, r)
+    n = gym.gym_op_ndofs(op)
+    gspaces = global_spaces(which, nel, r)
+    assert n == gspaces[0].ndofs + gspaces[1].ndofs
+    dt = torch.float64 if prec == gym.GYM_F64 else torch.float32
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(seed)
+    x = torch.randn(nrhs * n, dtype=dt, device=DEV, generator=gen)
+    y = torch.empty_like(x)
+    gym.gym_op_apply(op, prec, nrhs, x, y)
+    torch.cuda.synchronize()
+    vg = synth.uniform_vertices(nel) if verts is None else verts
+    rng = np.random.default_rng(seed)
+    worst = 0.0
+    for origin, mid in origins(nel, rng):
+        A, gmap, rows = patch_rows(which, vg, nel, r, origin, mid)
+        for k in sorted({0, nrhs - 1}):
+            idx = torch.as_tensor(gmap + k * n, device=DEV)
+            xp = x.index_select(0, idx).double().cpu().numpy()
+            yp = y.index_select(0, idx[torch.as_tensor(rows, device=DEV)]).double().cpu().numpy()
+            ref = (A @ xp)[rows]
+            err = np.abs(yp - ref).max() / np.abs(ref).max()
+            worst = max(worst, err)
+            print(f"{which} nel={nel} r={r} rhs {k} patch {origin}: {len(rows)} rows, rel err {err:.2e}",
+                  flush=True)
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+    if isinstance(tol, tuple):
+        assert tol[0] < worst < tol[1], worst
+    else:
+        assert worst < tol, worst
+
+
+def test_hodge_r2_32cube_fp64(g):
+    # the benchmark workload: 32^3 hexahedra, degree 2 Hodge Laplacian, FP64
+    gym, ctx = g
+    _check(gym, ctx, "hodge", (32, 32, 32), 2, None, 1, gym.GYM_F64, 1e-13, seed=1)
+
+
+def test_hodge_r2_32cube_fp64_8rhs(g):
+    gym, ctx = g
+    _check(gym, ctx, "hodge", (32, 32, 32), 2, None, 8, gym.GYM_F64, 1e-13, seed=2)
+
+
+@pytest.mark.parametrize("prec,tol", [("F64", 1e-13), ("F32", 2e-5), ("BF16", (1e-5, 5e-2))])
+def test_poisson_r4_64cube(g, prec, tol):
+    # 64^3 hexahedra, degree 4 mixed Poisson (67.3 M unknowns), every contraction precision
+    gym, ctx = g
+    p = {"F64": gym.GYM_F64, "F32": gym.GYM_F32, "BF16": gym.GYM_BF16}[prec]
+    _check(gym, ctx, "poisson", (64, 64, 64), 4, None, 1, p, tol, seed=3)
+
+
+def test_hodge_r3_96cube_perturbed_8rhs(g):
+    # 96^3 hexahedra with vertices perturbed by up to 15% of h, degree 3 Hodge, 8 rhs
+    gym, ctx = g
+    verts = synth.perturbed_vertices((96, 96, 96), 0.15, seed=0)
+    _check(gym, ctx, "hodge", (96, 96, 96), 3, verts, 8, gym.GYM_F64, 1e-13, seed=4)
+
+
+def test_hodge_r3_96cube_perturbed_fp32(g):
+    gym, ctx = g
+    verts = synth.perturbed_vertices((96, 96, 96), 0.15, seed=0)
+    _check(gym, ctx, "hodge", (96, 96, 96), 3, verts, 1, gym.GYM_F32, 2e-5, seed=5)
+
+
+def test_incidence_complex_at_full_size(g):
+    # C G = 0 exactly on the 32^3, degree 2 lattice (a property at any size);
+    # integer-valued input keeps every +-1 sum exact in FP64
+    gym, ctx = g
+    nel, r = (32, 32, 32), 2
+    mesh = gym.gym_mesh_create(ctx, 3, nel)
+    s0 = gym.gym_space_create(ctx, mesh, 0, r, 0)
+    s1 = gym.gym_space_create(ctx, mesh, 1, r, 0)
+    s2 = gym.gym_space_create(ctx, mesh, 2, r, 0)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(9)
+    u = torch.randint(-1000, 1001, (gym.gym_space_ndofs(s0),), device=DEV, generator=gen).double()
+    gu = torch.empty(gym.gym_space_ndofs(s1), dtype=torch.float64, device=DEV)
+    cgu = torch.empty(gym.gym_space_ndofs(s2), dtype=torch.float64, device=DEV)
+    gym.gym_d_apply(s0, s1, 0, u, gu)
+    gym.gym_d_apply(s1, s2, 0, gu, cgu)
+    torch.cuda.synchronize()
+    assert float(gu.abs().max()) > 0
+    assert float(cgu.abs().max()) == 0.0
+    for s in (s0, s1, s2):
+        gym.gym_space_destroy(s)
+    gym.gym_mesh_destroy(mesh)

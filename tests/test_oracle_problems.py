@@ -149,3 +149,23 @@ def test_mass_cg_solves():
     x, info = problems.mass_cg(M, b)
     assert info == 0
     assert np.linalg.norm(M @ x - b) < 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("which,nel,r,perturb", [("hodge", (6, 7, 5), 2, 0.0), ("hodge", (5, 6, 6), 1, 0.15),
+                                                 ("poisson", (6, 5, 7), 2, 0.15), ("poisson", (5, 5, 6), 3, 0.0)])
+def test_patch_rows_equal_global_rows(which, nel, r, perturb):
+    # The full-size GPU tests sample rows of the global operator from an
+    # oracle patch; on meshes small enough to assemble whole, those rows must
+    # equal the global ones exactly (up to summation order), at the domain's
+    # corners (boundary conditions) and inside.
+    from patch_rows import origins, patch_rows
+    verts = synth.perturbed_vertices(nel, perturb, seed=8) if perturb else synth.uniform_vertices(nel)
+    P = problems.Hodge1(Mesh(verts), r) if which == "hodge" else problems.MixedPoisson(Mesh(verts), r)
+    A = P.A.tocsr()
+    x = synth.random_vector(A.shape[0], seed=13)
+    y = A @ x
+    for origin, mid in origins(nel, np.random.default_rng(3)):
+        Ap, gmap, rows = patch_rows(which, verts, nel, r, origin, mid)
+        yp = (Ap @ x[gmap])[rows]
+        assert len(rows) > 0
+        assert np.abs(yp - y[gmap[rows]]).max() <= 1e-13 * np.abs(y).max()
