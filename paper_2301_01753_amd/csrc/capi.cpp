@@ -334,8 +334,9 @@ template <typename TV>
 struct MinresWork {
   TV *r1 = nullptr, *r2 = nullptr, *y = nullptr, *z = nullptr, *zp = nullptr, *w = nullptr, *w1 = nullptr,
      *w2 = nullptr;
-  // partial sums (fused apply: pa; minres_step2: pb, pc) and alfa per rhs
-  double *pa = nullptr, *pb = nullptr, *pc = nullptr, *alfa = nullptr;
+  // partial sums (fused apply: pa; minres_step2: two alternating sets of
+  // pb, pc and alfa per rhs)
+  double *pa = nullptr, *pb[2] = {}, *pc[2] = {}, *alfa[2] = {};
   int npa_cap = 0;
   MinresState* st = nullptr;
   MinresState* host = nullptr;
@@ -364,12 +365,16 @@ template <typename TV>
 int ensure_partials(std::vector<void*>& pool, MinresWork<TV>& w, int npa, int nb, int nrhs) {
   if (npa <= w.npa_cap) return 0;
   void* p;
-  if (int rc = dalloc(&p, sizeof(double) * ((long long)(npa + 2 * nb + 1) * nrhs))) return rc;
+  if (int rc = dalloc(&p, sizeof(double) * ((long long)(npa + 4 * nb + 2) * nrhs))) return rc;
   pool.push_back(p);
   w.pa = (double*)p;
-  w.pb = w.pa + (long long)npa * nrhs;
-  w.pc = w.pb + (long long)nb * nrhs;
-  w.alfa = w.pc + (long long)nb * nrhs;
+  double* q = w.pa + (long long)npa * nrhs;
+  for (int k = 0; k < 2; ++k) {
+    w.pb[k] = q;
+    w.pc[k] = q + (long long)nb * nrhs;
+    w.alfa[k] = q + 2LL * nb * nrhs;
+    q += (2LL * nb + 1) * nrhs;
+  }
   w.npa_cap = npa;
   return 0;
 }
@@ -386,17 +391,21 @@ int run_minres(Apply&& apply, long long n, int nrhs, int nb, int npa, const TV* 
   if (npa > wk.npa_cap) return fail(GYM_E_HIP, "MINRES partial-sum buffer too small for this launch");
   // init: r1 = r2 = b, z = M^-1 b (into wk.z), beta_1 in slot 0
   MinresVecs<TV> V{b, x, wk.r1, wk.r2, wk.z, wk.y, wk.w, wk.w1, wk.w2};
-  minres_launch_init<TV>(V, dinv, n, nrhs, nb, wk.pb, wk.st, tol, s);
+  minres_launch_init<TV>(V, dinv, n, nrhs, nb, wk.pb[0], wk.st, tol, s);
+  int par = 0;  // set of step2 partials written last
   if (check_every < 1) check_every = 1;
   int it = 0, slot = 0;
   bool all_done = false, pending = false;
   while (it < maxit && !all_done) {
     MinresState* cur = wk.st + slot * nrhs;
     MinresState* next = wk.st + (slot ^ 1) * nrhs;
-    const MrStep m{cur, next, wk.pb, wk.pc, wk.alfa, wk.pa, nb, pending ? 0 : 1};
+    const MrStep m{cur, wk.pa};
     if (int rc = apply(wk.z, wk.y, m)) return rc;
     const MrVecs<TV> mv{wk.y, wk.r1, wk.r2, wk.zp, x, wk.w2, wk.w, wk.w1};
-    minres_launch_step2<TV>(mv, dinv, n, nrhs, nb, next, wk.pa, npa, wk.pb, wk.pc, wk.alfa, s);
+    const Step2Io io{cur, next, pending ? 0 : 1, npa, nb, wk.pa, wk.pb[par], wk.pc[par], wk.alfa[par],
+                     wk.pb[par ^ 1], wk.pc[par ^ 1], wk.alfa[par ^ 1]};
+    minres_launch_step2<TV>(mv, dinv, n, nrhs, nb, io, s);
+    par ^= 1;
     if (pending) {  // the newest w was written over the oldest
       TV *ow = wk.w, *ow1 = wk.w1, *ow2 = wk.w2;
       wk.w = ow1;
@@ -420,7 +429,7 @@ int run_minres(Apply&& apply, long long n, int nrhs, int nb, int npa, const TV* 
   }
   if (!all_done && pending) {
     minres_launch_finish<TV>(x, wk.zp, wk.w2, wk.w, wk.w1, n, nrhs, nb, wk.st + slot * nrhs,
-                             wk.st + (slot ^ 1) * nrhs, wk.pb, wk.alfa, s);
+                             wk.st + (slot ^ 1) * nrhs, wk.pb[par], wk.alfa[par], s);
     slot ^= 1;
   }
   GYM_HIP(hipGetLastError());

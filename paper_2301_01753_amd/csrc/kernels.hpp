@@ -53,6 +53,9 @@ int launch_operator(int prob, int dim, int r, int prec, const OpParams& p, int n
 // per-unit entry points (op_hodge.hip, op_poisson.hip, op_mass.hip)
 int launch_hodge(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
 int launch_poisson(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
+// the same with the fused MINRES step (p.fused, p.mr; op_hodge_mr.hip, op_poisson_mr.hip)
+int launch_hodge_mr(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
+int launch_poisson_mr(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
 int launch_mass(int prob, int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
 // ragged batch of affine operators of one problem and degree (FP64)
 int launch_op_batch(int prob, int dim, int r, OpParams* plist_host, int* bstart_host, int nreq,
@@ -62,6 +65,8 @@ int launch_poisson_batch(int r, OpParams* ph, int* bh, int n, OpParams* pd, int*
 int upload_tables_hodge();
 int upload_tables_poisson();
 int upload_tables_mass();
+int upload_tables_hodge_mr();
+int upload_tables_poisson_mr();
 
 // incidence: y = d x or d^T x, bit-reproducible ascending-index sums
 struct IncParams {

@@ -25,18 +25,11 @@ constexpr int kBT = 256;
 template <typename T>
 __device__ __forceinline__ double todbl(T v) { return static_cast<double>(v); }
 
-// Block tree reduction of `v` (fixed order); returns the sum in thread 0.
+// Block sum of `v` (fixed order, see wg_sums); returned in every thread.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-#pragma unroll
-  for (int s = kBT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = sh[0];
-  __syncthreads();
-  return r;
+  double a[1] = {v};
+  wg_sums<kBT, 1>(a, sh);
+  return a[0];
 }
 
 // Sum of `np` partials, same order in every block.
@@ -103,20 +96,26 @@ __global__ void __launch_bounds__(kBT) minres_init_b(MinresVecs<TV> v, long long
     v.v[off + i] = static_cast<TV>(todbl(v.y[off + i]) * inv);
 }
 
-// Second kernel of a fused MINRES step (the first is the operator apply:
-// y = A v_k, partial sums pa of v_k . A v_k, state st with the coefficients
-// of step k-1).  With c1 = beta_k / beta_{k-1}:
-//   alfa = sum(pa) - c1 (z_k . r1) / beta_k
-//   y = A v_k - c1 r1 - (alfa / beta_k) r2 ;  z_{k+1} = dinv .* y
-//   partials of y . z_{k+1} (beta_{k+1}^2) and z_{k+1} . r2 (next z . r1)
-// and, when due, step k-1's w_{k-1} = (v_{k-1} - oldeps w_{k-3} - delta
-// w_{k-2}) * denom with v_{k-1} = zp / beta_{k-1}, x += phi w_{k-1}; zp
-// (z_{k-1}) is read before z_{k+1} is written over it.  Skipped unless st
-// is fresh.
+// Second kernel of a fused MINRES step.  The operator kernel left
+// y = A z_k and per-workgroup partial sums pa of z_k . A z_k.  Every block:
+//   1. closes step k-1 (unless `first`): scalar update of state cur with
+//      alfa_{k-1} and the sums of the previous pass's partials (beta_k^2 from
+//      pb_prev, z_k . r1_k from pc_prev); block 0 stores the state in next;
+//   2. alfa_k = (z.Az) / beta_k^2 - (beta_k / beta_{k-1}) (z_k . r1_k) / beta_k;
+//   3. one pass over the vectors: y = (A z_k) / beta_k - (beta_k / beta_{k-1}) r1
+//      - (alfa_k / beta_k) r2, z_{k+1} = dinv .* y written over zp, step k-1's
+//      w_{k-1} = (v_{k-1} - oldeps w_{k-3} - delta w_{k-2}) / gamma with
+//      v_{k-1} = zp / beta_{k-1} (zp is read before it is overwritten),
+//      x += phi w_{k-1}; partial sums of y . z_{k+1} and z_{k+1} . r2 into
+//      pb, pc.
+// A converged state is copied forward and nothing else is done.
+struct Step2Coef {
+  double ys, c1, c, vpinv, phi, denom, oldeps, delta;
+};
+
 template <typename TV, bool UPD>
 __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* __restrict__ dinv, long long n,
-                                            long long off, const MinresState& s, double c1, double c,
-                                            double vpinv, double& ab, double& ac) {
+                                            long long off, const Step2Coef& k, double& ab, double& ac) {
   // restrict-qualified locals let the compiler issue every load of an
   // unrolled group before the stores of the previous one
   TV* __restrict__ y = v.y + off;
@@ -132,14 +131,14 @@ __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* _
   long long i0 = (long long)blockIdx.x * kBT + threadIdx.x;
   auto one = [&](long long i, double yv, double r1v, double r2v, double dv, double zpv, double wav, double wbv,
                  double xv) {
-    const TV ys = static_cast<TV>(yv - c1 * r1v - c * r2v);
+    const TV ys = static_cast<TV>(k.ys * yv - k.c1 * r1v - k.c * r2v);
     y[i] = ys;
     const TV zs = static_cast<TV>(dv * todbl(ys));
     if constexpr (UPD) {
-      const double vp = todbl(static_cast<TV>(zpv * vpinv));
-      const TV ws = static_cast<TV>((vp - s.oldeps * wav - s.delta * wbv) * s.denom);
+      const double vp = todbl(static_cast<TV>(zpv * k.vpinv));
+      const TV ws = static_cast<TV>((vp - k.oldeps * wav - k.delta * wbv) * k.denom);
       wo[i] = ws;
-      x[i] = static_cast<TV>(xv + s.phi * todbl(ws));
+      x[i] = static_cast<TV>(xv + k.phi * todbl(ws));
     }
     zp[i] = zs;
     ab += todbl(ys) * todbl(zs);
@@ -177,27 +176,53 @@ __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* _
 
 template <typename TV>
 __global__ void __launch_bounds__(kBT) minres_step2(MrVecs<TV> v, const double* __restrict__ dinv, long long n,
-                                                    const MinresState* st, const double* pa, int npa, double* pb,
-                                                    double* pc, double* alfa_out) {
-  __shared__ double sh[kBT];
+                                                    Step2Io io) {
+  __shared__ double sh[3 * kBT];
   const int rhs = blockIdx.y;
-  const MinresState s = st[rhs];
-  if (!s.fresh || s.beta == 0.0) return;
-  const double c1 = s.oldb > 0 ? s.beta / s.oldb : 0.0;
-  const double vinv = 1.0 / s.beta;
-  const double alfa = reduce_partials(pa + (long long)rhs * npa, npa, sh) - c1 * s.zr1 * vinv;
-  if (blockIdx.x == 0 && threadIdx.x == 0) alfa_out[rhs] = alfa;
-  const double c = alfa * vinv;
-  const double vpinv = s.oldb > 0 ? 1.0 / s.oldb : 0.0;
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  MinresState s = io.cur[rhs];
+  if (s.done) {
+    if (lead) io.next[rhs] = s;
+    return;
+  }
+  Step2Coef k{};
+  double zr1 = 0.0;
+  k.vpinv = s.beta > 0 ? 1.0 / s.beta : 0.0;  // 1 / beta_{k-1}
+  // the three sums in one block reduction: beta_k^2, z_k . r1_k, z_k . A z_k
+  double t3[3] = {0.0, 0.0, 0.0};
+  if (!io.first) {
+    const double* pb = io.pb_prev + (long long)rhs * io.npb;
+    const double* pc = io.pc_prev + (long long)rhs * io.npb;
+    for (int i = threadIdx.x; i < io.npb; i += kBT) {
+      t3[0] += pb[i];
+      t3[1] += pc[i];
+    }
+  }
+  const double* pa = io.pa + (long long)rhs * io.npa;
+  for (int i = threadIdx.x; i < io.npa; i += kBT) t3[2] += pa[i];
+  wg_sums<kBT, 3>(t3, sh);
+  if (!io.first) {
+    zr1 = t3[1];
+    double vinv;
+    minres_scalar_update(s, io.alfa_prev[rhs], t3[0], k.phi, k.denom, k.oldeps, k.delta, vinv);
+  }
+  if (lead) io.next[rhs] = s;
+  const double vinv = s.beta > 0 ? 1.0 / s.beta : 0.0;  // 1 / beta_k
+  k.c1 = s.oldb > 0 ? s.beta / s.oldb : 0.0;
+  const double zaz = t3[2];
+  const double alfa = vinv * vinv * zaz - k.c1 * zr1 * vinv;
+  if (lead) io.alfa[rhs] = alfa;
+  k.ys = vinv;
+  k.c = alfa * vinv;
   const long long off = (long long)rhs * n;
   double ab = 0.0, ac = 0.0;
-  if (s.upd) step2_sweep<TV, true>(v, dinv, n, off, s, c1, c, vpinv, ab, ac);
-  else step2_sweep<TV, false>(v, dinv, n, off, s, c1, c, vpinv, ab, ac);
-  double tb = block_sum(ab, sh);
-  double tc = block_sum(ac, sh);
+  if (io.first) step2_sweep<TV, false>(v, dinv, n, off, k, ab, ac);
+  else step2_sweep<TV, true>(v, dinv, n, off, k, ab, ac);
+  double t2[2] = {ab, ac};
+  wg_sums<kBT, 2>(t2, sh);
   if (threadIdx.x == 0) {
-    pb[rhs * gridDim.x + blockIdx.x] = tb;
-    pc[rhs * gridDim.x + blockIdx.x] = tc;
+    io.pb[rhs * gridDim.x + blockIdx.x] = t2[0];
+    io.pc[rhs * gridDim.x + blockIdx.x] = t2[1];
   }
 }
 
@@ -215,17 +240,13 @@ __global__ void __launch_bounds__(kBT) minres_finish(TV* __restrict__ x, const T
   MinresState s = cur[rhs];
   const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
   if (s.done) {
-    if (lead) {
-      s.fresh = 0;
-      next[rhs] = s;
-    }
+    if (lead) next[rhs] = s;
     return;
   }
   const double vinv_prev = s.beta > 0 ? 1.0 / s.beta : 0.0;
   double phi, denom, oldeps, delta, vinv;
   const double b2 = reduce_partials(pb + (long long)rhs * npb, npb, sh);
   minres_scalar_update(s, alfa[rhs], b2, phi, denom, oldeps, delta, vinv);
-  s.fresh = 0;
   if (lead) next[rhs] = s;
   const long long off = (long long)rhs * n;
   for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
@@ -418,10 +439,9 @@ void minres_launch_init(const MinresVecs<TV>& v, const double* dinv, long long n
 }
 
 template <typename TV>
-void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb,
-                         const MinresState* st, const double* pa, int npa, double* pb, double* pc, double* alfa,
+void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, const Step2Io& io,
                          hipStream_t s) {
-  GYM_LAUNCH(minres_step2<TV>, dim3(nb, nrhs), s, v, dinv, n, st, pa, npa, pb, pc, alfa);
+  GYM_LAUNCH(minres_step2<TV>, dim3(nb, nrhs), s, v, dinv, n, io);
 }
 
 template <typename TV>
@@ -474,11 +494,9 @@ template void minres_launch_init<double>(const MinresVecs<double>&, const double
                                          MinresState*, double, hipStream_t);
 template void minres_launch_init<float>(const MinresVecs<float>&, const double*, long long, int, int, double*,
                                         MinresState*, double, hipStream_t);
-template void minres_launch_step2<double>(const MrVecs<double>&, const double*, long long, int, int,
-                                          const MinresState*, const double*, int, double*, double*, double*,
+template void minres_launch_step2<double>(const MrVecs<double>&, const double*, long long, int, int, const Step2Io&,
                                           hipStream_t);
-template void minres_launch_step2<float>(const MrVecs<float>&, const double*, long long, int, int,
-                                         const MinresState*, const double*, int, double*, double*, double*,
+template void minres_launch_step2<float>(const MrVecs<float>&, const double*, long long, int, int, const Step2Io&,
                                          hipStream_t);
 template void minres_launch_finish<double>(double*, const double*, const double*, const double*, double*,
                                            long long, int, int, const MinresState*, MinresState*,

@@ -52,11 +52,24 @@ struct MrVecs {
   TV* wout;           // receives w_{k-1} (holds w_{k-4})
 };
 
-// Fused MINRES step, second kernel (after the operator apply that carries
-// the first half, see MrStep); npa = workgroups per rhs of that apply.
+// Scalars and partial sums of the second kernel of a fused MINRES step
+// (see minres_step2): the previous pass's partials are read while the new
+// ones are written, so the host alternates two sets.
+struct Step2Io {
+  const MinresState* cur;  // latest state
+  MinresState* next;       // receives the state after closing step k-1
+  int first;               // 1: no step to close (fresh start)
+  int npa, npb;            // partials per rhs: operator workgroups, step2 blocks
+  const double* pa;        // z_k . A z_k partials (operator kernel)
+  const double* pb_prev;   // beta_k^2 partials (previous pass)
+  const double* pc_prev;   // z_k . r1_k partials (previous pass)
+  const double* alfa_prev; // alfa_{k-1} per rhs
+  double *pb, *pc;         // out: this pass's partials
+  double* alfa;            // out: alfa_k per rhs
+};
+
 template <typename TV>
-void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb,
-                         const MinresState* st, const double* pa, int npa, double* pb, double* pc, double* alfa,
+void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, const Step2Io& io,
                          hipStream_t s);
 // Completes a pending step (iteration cap): state cur -> next, w and x.
 template <typename TV>

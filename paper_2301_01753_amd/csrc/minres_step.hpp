@@ -8,14 +8,40 @@ namespace gym {
 
 struct MinresState {
   double beta, oldb, dbar, epsln, phibar, cs, sn, tnorm2, beta1, alfa, tol;
-  // fused driver: coefficients of the w / x update of the step just closed
-  // by the scalar update, and z_k . r1_k for the next alfa
-  double phi, denom, oldeps, delta, zr1;
   int itn, done, flag;  // flag: 0 running, 1 converged, -1 breakdown
-  int fresh;            // fused driver: 1 when the operator kernel produced this state
-  int upd;              // fused driver: the w / x update of that step is due
   int pad;
 };
+
+// Sums over a workgroup of NT threads of N values per thread, returned in
+// every thread: a tree in LDS over all N values at once (one barrier per
+// level).  When NT is not a power of two the threads above the largest power
+// of two P are first folded onto the first NT - P.  The order is fixed, so
+// results are reproducible.  sh holds N * NT doubles.
+template <int NT, int N>
+__device__ __forceinline__ void wg_sums(double (&v)[N], double* sh) {
+  constexpr int P = NT >= 1024 ? 1024 : NT >= 512 ? 512 : NT >= 256 ? 256 : NT >= 128 ? 128 : 64;
+  static_assert(NT <= 2 * P && NT >= 64, "workgroup size");
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < N; ++k) sh[k * NT + t] = v[k];
+  __syncthreads();
+  if constexpr (NT > P) {
+    if (t < NT - P)
+#pragma unroll
+      for (int k = 0; k < N; ++k) sh[k * NT + t] += sh[k * NT + t + P];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int s = P / 2; s > 0; s >>= 1) {
+    if (t < s)
+#pragma unroll
+      for (int k = 0; k < N; ++k) sh[k * NT + t] += sh[k * NT + t + s];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = sh[k * NT];
+  __syncthreads();
+}
 
 // Lanczos/Givens scalar recurrence of one MINRES step (Paige & Saunders),
 // given alfa = v.(A v - ...) and b2 = r2 . M^-1 r2; returns the update
@@ -55,25 +81,15 @@ __device__ __forceinline__ void minres_scalar_update(MinresState& s, double alfa
   vinv = beta > 0 ? 1.0 / beta : 0.0;
 }
 
-// First half of a fused MINRES step, carried by an operator apply of
-// v_k = z_k / beta_k (z_k is the apply input; y receives A v_k unchanged).
-// Unless `first`, every workgroup first closes step k-1: it sums the
-// partials pb (beta_k^2) and pc (z_k . r1_k) left by minres_step2 and runs
-// the scalar update from alfa_{k-1}; one workgroup stores the new state with
-// the w / x coefficients.  The epilogue adds v_k . (A v_k) over the owned
-// positions into one partial sum per workgroup (pa); minres_step2 completes
-// alfa_k = v_k . (A v_k) - (beta_k / beta_{k-1}) v_k . r1_k.  (Each consumer
-// re-adds the partials in the same order: a last-workgroup reduction would
-// need a device-scope fence per workgroup, which writes back the L2.)
+// First half of a fused MINRES step, carried by an operator apply of z_k
+// (z_k = M^-1 r2_k, so v_k = z_k / beta_k): y receives A z_k, and the epilogue
+// adds z_k . (A z_k) over the owned positions into one partial sum per
+// workgroup (pa).  The apply needs no scalar of the recurrence (A is linear):
+// minres_step2 closes step k-1, then scales by 1 / beta_k.  Workgroups of a
+// right-hand side whose state is already converged do nothing.
 struct MrStep {
-  const MinresState* cur;  // state before the update of step k-1
-  MinresState* next;       // state after it
-  const double* pb;        // npb partial sums per rhs of beta_k^2
-  const double* pc;        // npb partial sums per rhs of z_k . r1_k
-  const double* alfa;      // alfa_{k-1} per rhs
-  double* pa;              // out: one partial sum of v_k . A v_k per workgroup
-  int npb;
-  int first;  // 1: no step is pending (fresh start)
+  const MinresState* cur;  // latest state (written by the previous minres_step2)
+  double* pa;              // out: one partial sum of z_k . A z_k per workgroup
 };
 
 }  // namespace gym

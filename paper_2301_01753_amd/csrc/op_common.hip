@@ -65,6 +65,8 @@ void fill_tables(TabSet<double>* hd, TabSet<double>* hl, TabSet<float>* hf, TabS
 int upload_tables() {
   if (int rc = upload_tables_hodge()) return rc;
   if (int rc = upload_tables_poisson()) return rc;
+  if (int rc = upload_tables_hodge_mr()) return rc;
+  if (int rc = upload_tables_poisson_mr()) return rc;
   return upload_tables_mass();
 }
 
@@ -78,6 +80,11 @@ int launch_op_batch(int prob, int dim, int r, OpParams* plist_host, int* bstart_
 }
 
 int launch_operator(int prob, int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s) {
+  if (p.fused) {
+    if (prob == PROB_HODGE) return launch_hodge_mr(dim, r, prec, p, nrhs, ncu, s);
+    if (prob == PROB_POISSON) return launch_poisson_mr(dim, r, prec, p, nrhs, ncu, s);
+    return -2;
+  }
   if (prob == PROB_HODGE) return launch_hodge(dim, r, prec, p, nrhs, ncu, s);
   if (prob == PROB_POISSON) return launch_poisson(dim, r, prec, p, nrhs, ncu, s);
   return launch_mass(prob, dim, r, prec, p, nrhs, ncu, s);

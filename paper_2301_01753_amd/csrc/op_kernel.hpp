@@ -337,69 +337,17 @@ __device__ __forceinline__ void vmass2(TC* const in[2], TC* const out[2], const 
 }
 
 // ---- fused MINRES step -------------------------------------------------------
-// Sum over the workgroup in a fixed order (every workgroup of a launch, and
-// every launch, adds in the same order: results are reproducible).
+// Sum over the workgroup in a fixed order (see wg_sums).
 template <int NT>
 __device__ __forceinline__ double wg_sum(double v, double* sh) {
-  sh[threadIdx.x] = v;
-  __syncthreads();
-#pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = sh[0];
-  __syncthreads();
-  return r;
-}
-
-struct MrScalars {
-  double vinv;  // 1 / beta_k
-};
-
-// Scalar part of the fused step, redundantly in every workgroup (same
-// inputs, same order: every workgroup agrees); `lead` stores the new state.
-// Returns false when this rhs has already converged (state copied forward).
-template <int NT>
-__device__ __forceinline__ bool mr_prologue(const MrStep& m, int rhs, bool lead, double* sh, MrScalars& ms) {
-  MinresState s = m.cur[rhs];
-  if (s.done) {
-    if (lead && threadIdx.x == 0) {
-      s.fresh = 0;
-      m.next[rhs] = s;
-    }
-    return false;
-  }
-  if (m.first) {
-    s.upd = 0;
-    s.zr1 = 0.0;
-    ms.vinv = s.beta > 0 ? 1.0 / s.beta : 0.0;
-  } else {
-    const double* pb = m.pb + (long long)rhs * m.npb;
-    const double* pc = m.pc + (long long)rhs * m.npb;
-    double vb = 0.0, vc = 0.0;
-    for (int i = threadIdx.x; i < m.npb; i += NT) {
-      vb += pb[i];
-      vc += pc[i];
-    }
-    const double b2 = wg_sum<NT>(vb, sh);
-    s.zr1 = wg_sum<NT>(vc, sh);
-    double phi, denom, oldeps, delta;
-    minres_scalar_update(s, m.alfa[rhs], b2, phi, denom, oldeps, delta, ms.vinv);
-    s.phi = phi;
-    s.denom = denom;
-    s.oldeps = oldeps;
-    s.delta = delta;
-    s.upd = 1;
-  }
-  s.fresh = 1;
-  if (lead && threadIdx.x == 0) m.next[rhs] = s;
-  return true;
+  double a[1] = {v};
+  wg_sums<NT, 1>(a, sh);
+  return a[0];
 }
 
 // ---- the kernel body -------------------------------------------------------
 // (bx, by, bz) = (tile, z-chunk, right-hand side) of this workgroup.
-template <class C, int PROB, int FORM, typename TV, typename TC>
+template <class C, int PROB, int FORM, typename TV, typename TC, bool MR>
 __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int bz, TC* smem) {
   using F = Fields<PROB, C::DIM>;
   using L = Layout<C, F, FORM>;
@@ -419,11 +367,10 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
   TV* __restrict__ yout = reinterpret_cast<TV*>(p.y) + voff;
   const int gx0 = R * (X0 - 1), gy0 = R * (Y0 - 1);
 
-  // ---- fused MINRES step: finish step k-1, take its scalars
-  MrScalars ms{};
+  // ---- fused MINRES step: nothing to do once this rhs has converged
   double mr_acc = 0.0;
-  if (p.fused) {
-    if (!mr_prologue<C::NT>(p.mr, rhs, bx == 0 && by == 0, reinterpret_cast<double*>(smem), ms)) return;
+  if constexpr (MR) {
+    if (p.mr.cur[rhs].done) return;
   }
 
   Work<TC> w;
@@ -456,6 +403,16 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
     }
   });
 
+  // Layout descriptors of the fields, staged in LDS: read from there in the
+  // load and write stages, they stay live only within those stages instead
+  // of occupying scalar registers across the layer loop (where they spilled).
+  __shared__ DevComp sh_comp[F::NF];
+  static_for<0, F::NF>([&](auto fc) {
+    constexpr int f = decltype(fc)::value;
+    if (threadIdx.x == f) sh_comp[f] = (F::sp[f] == 0 ? p.sa : p.sb).c[F::cp[f]];
+  });
+  __syncthreads();
+
   auto IN = [&](int f) { return smem + L::in_off(f); };
   auto OUT = [&](int f) { return smem + L::out_off(f); };
 
@@ -465,7 +422,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
     static_for<0, F::NF>([&](auto fc) {
       constexpr int f = decltype(fc)::value;
       constexpr int TM = F::tm[f];
-      const DevComp& cd = (F::sp[f] == 0 ? p.sa : p.sb).c[F::cp[f]];
+      const DevComp& cd = sh_comp[f];
       TC* in = smem + L::in_off(f);
       TC* out = smem + L::out_off(f);
       for (int i = threadIdx.x; i < C::lat(TM); i += C::NT) {
@@ -474,9 +431,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
         int g0 = gx0 + lx - cd.start[0], g1 = gy0 + ly - cd.start[1], g2 = gz0 + lz - cd.start[2];
         TC v = 0;
         if (g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2]) {
-          TV xv = xin[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)];
-          if (p.fused) xv = static_cast<TV>(static_cast<double>(xv) * ms.vinv);  // v_k = z_k / beta_k
-          v = static_cast<TC>(xv);
+          v = static_cast<TC>(xin[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)]);
         }
         in[i] = v;
         out[i] = 0;
@@ -688,7 +643,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
       static_for<0, F::NF>([&](auto fc) {
         constexpr int f = decltype(fc)::value;
         constexpr int TM = F::tm[f];
-        const DevComp& cd = (F::sp[f] == 0 ? p.sa : p.sb).c[F::cp[f]];
+        const DevComp& cd = sh_comp[f];
         const TC* out = smem + L::out_off(f);
         const TC* in = smem + L::in_off(f);
         for (int i = threadIdx.x; i < C::lat(TM); i += C::NT) {
@@ -703,25 +658,25 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
             const long long gi = cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2);
             const TV ys = static_cast<TV>(out[i]);
             yout[gi] = ys;
-            if (p.fused) mr_acc += static_cast<double>(in[i]) * static_cast<double>(ys);  // v_k . A v_k
+            if constexpr (MR) mr_acc += static_cast<double>(in[i]) * static_cast<double>(ys);  // z_k . A z_k
           }
         }
       });
     }
     __syncthreads();
   }
-  if (p.fused) {
+  if constexpr (MR) {
     const double t = wg_sum<C::NT>(mr_acc, reinterpret_cast<double*>(smem));
     if (threadIdx.x == 0) p.mr.pa[(long long)rhs * nt * p.nchunks + bx + nt * by] = t;
   }
 }
 
-template <class C, int PROB, int FORM, typename TV, typename TC>
+template <class C, int PROB, int FORM, typename TV, typename TC, bool MR>
 __global__ void __launch_bounds__(C::NT) op_kernel(const OpParams p) {
   constexpr int kWords = Layout<C, Fields<PROB, C::DIM>, FORM>::total();
   static_assert(kWords * sizeof(TC) >= C::NT * sizeof(double), "LDS holds the workgroup sums");
   __shared__ __align__(16) TC smem[kWords];
-  op_body<C, PROB, FORM, TV, TC>(p, blockIdx.x, blockIdx.y, blockIdx.z, smem);
+  op_body<C, PROB, FORM, TV, TC, MR>(p, blockIdx.x, blockIdx.y, blockIdx.z, smem);
 }
 
 // Ragged batch: one launch over the workgroups of several operators of the
@@ -743,7 +698,7 @@ __global__ void __launch_bounds__(C::NT) op_kernel_batch(const OpParams* __restr
   const int local = blk - bstart[lo];
   const int nt = p.tiles_x * p.tiles_y;
   const int bx = local % nt, r2 = local / nt;
-  op_body<C, PROB, FORM, TV, TC>(p, bx, r2 % p.nchunks, r2 / p.nchunks, smem);
+  op_body<C, PROB, FORM, TV, TC, false>(p, bx, r2 % p.nchunks, r2 / p.nchunks, smem);
 }
 
 // ---- tile-size selection ----------------------------------------------------
@@ -806,7 +761,7 @@ constexpr int big_threads() {
   return R == 2 ? 768 : 1024;
 }
 
-template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, int BUDGET>
+template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, int BUDGET, bool MR>
 int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
   constexpr int B = TileSel<DIM, R, PROB, FORM, TC, BUDGET>::B;
   // one workgroup per CU on the whole-CU budget: widen it to keep enough
@@ -818,7 +773,7 @@ int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
   if (p0.wg_out) *p0.wg_out = p.tiles_x * p.tiles_y * p.nchunks;
   if (p0.dry) return 0;
   dim3 grid(p.tiles_x * p.tiles_y, p.nchunks, nrhs);
-  hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC>), grid, dim3(C::NT), 0, stream, p);
+  hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC, MR>), grid, dim3(C::NT), 0, stream, p);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -842,7 +797,7 @@ int launch_op_batch_r(OpParams* plist_host, int* bstart_host, int nreq, OpParams
 
 // Tile budget 0: whole-CU tiles; 1: small tiles; 2: whole-CU tiles when they
 // still give every CU a workgroup, small tiles otherwise (small meshes).
-template <int DIM, int R, int PROB, int FORM, typename TV, typename TC>
+template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, bool MR>
 int launch_form(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
   constexpr int kBig = 160 * 1024, kSmall = 40 * 1024;
   bool large = p.tile_budget == 0;
@@ -850,34 +805,34 @@ int launch_form(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
     OpParams q = p;
     large = op_tiling(q, TileSel<DIM, R, PROB, FORM, TC, kBig>::B, DIM, nrhs, ncu) >= ncu;
   }
-  if (large) return launch_op_b<DIM, R, PROB, FORM, TV, TC, kBig>(p, nrhs, ncu, stream);
-  return launch_op_b<DIM, R, PROB, FORM, TV, TC, kSmall>(p, nrhs, ncu, stream);
+  if (large) return launch_op_b<DIM, R, PROB, FORM, TV, TC, kBig, MR>(p, nrhs, ncu, stream);
+  return launch_op_b<DIM, R, PROB, FORM, TV, TC, kSmall, MR>(p, nrhs, ncu, stream);
 }
 
-template <int DIM, int R, int PROB, typename TV, typename TC>
+template <int DIM, int R, int PROB, typename TV, typename TC, bool MR>
 int launch_op(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
   if (p.curved) {
     if (p.bf16) return -2;  // bf16 contractions exist in the Kronecker form only
-    if constexpr (DIM == 3) return launch_form<DIM, R, PROB, FORM_CURVED, TV, TC>(p, nrhs, ncu, stream);
+    if constexpr (DIM == 3) return launch_form<DIM, R, PROB, FORM_CURVED, TV, TC, MR>(p, nrhs, ncu, stream);
     return -2;
   }
   if (p.kron) {
     if constexpr (std::is_same<TC, float>::value) {
-      if (p.bf16) return launch_form<DIM, R, PROB, FORM_KRON_BF16, TV, TC>(p, nrhs, ncu, stream);
+      if (p.bf16) return launch_form<DIM, R, PROB, FORM_KRON_BF16, TV, TC, MR>(p, nrhs, ncu, stream);
     }
-    return launch_form<DIM, R, PROB, FORM_KRON, TV, TC>(p, nrhs, ncu, stream);
+    return launch_form<DIM, R, PROB, FORM_KRON, TV, TC, MR>(p, nrhs, ncu, stream);
   }
   if (p.bf16) return -2;  // bf16 contractions exist in the Kronecker form only
-  return launch_form<DIM, R, PROB, FORM_GAUSS, TV, TC>(p, nrhs, ncu, stream);
+  return launch_form<DIM, R, PROB, FORM_GAUSS, TV, TC, MR>(p, nrhs, ncu, stream);
 }
 
-template <int DIM, int PROB, typename TV, typename TC>
+template <int DIM, int PROB, typename TV, typename TC, bool MR = false>
 int dispatch_r(int r, const OpParams& p, int nrhs, int ncu, hipStream_t s) {
   switch (r) {
-    case 1: return launch_op<DIM, 1, PROB, TV, TC>(p, nrhs, ncu, s);
-    case 2: return launch_op<DIM, 2, PROB, TV, TC>(p, nrhs, ncu, s);
-    case 3: return launch_op<DIM, 3, PROB, TV, TC>(p, nrhs, ncu, s);
-    case 4: return launch_op<DIM, 4, PROB, TV, TC>(p, nrhs, ncu, s);
+    case 1: return launch_op<DIM, 1, PROB, TV, TC, MR>(p, nrhs, ncu, s);
+    case 2: return launch_op<DIM, 2, PROB, TV, TC, MR>(p, nrhs, ncu, s);
+    case 3: return launch_op<DIM, 3, PROB, TV, TC, MR>(p, nrhs, ncu, s);
+    case 4: return launch_op<DIM, 4, PROB, TV, TC, MR>(p, nrhs, ncu, s);
   }
   return -2;
 }

@@ -478,6 +478,47 @@ def test_solve_curved_hodge(g, mode):
     gym.gym_mesh_destroy(mesh)
 
 
+# Whole-CU tiles run 512, 768 or 1024 threads per workgroup depending on the
+# problem, degree and form; the fused MINRES step sums partials over the
+# workgroup, so every width is exercised in a solve (automatic tiling would
+# pick small tiles on these meshes).
+WIDE_CASES = [("poisson", (5, 4, 6), 1, 0.0, "f64"),    # 512 threads
+              ("hodge", (4, 5, 3), 2, 0.0, "f64"),      # Kronecker, 1024
+              ("hodge", (3, 4, 3), 3, 0.0, "f64"),      # Kronecker Hodge r = 3, 768
+              ("hodge", (4, 3, 4), 2, 0.15, "f64"),     # curved, 768
+              ("hodge", (4, 5, 3), 2, 0.0, "ir_f32")]   # FP32 Kronecker r = 2, 768
+
+
+@pytest.mark.parametrize("which,nel,r,perturb,mode", WIDE_CASES)
+def test_solve_whole_cu_tiles(g, which, nel, r, perturb, mode):
+    gym, ctx = g
+    verts = synth.perturbed_vertices(nel, perturb, seed=2) if perturb else None
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON if which == "poisson" else gym.GYM_HODGE1, mesh, r)
+    vo = verts if perturb else synth.uniform_vertices(nel)
+    P = problems.Hodge1(Mesh(vo), r) if which == "hodge" else problems.MixedPoisson(Mesh(vo), r)
+    n = P.A.shape[0]
+    b = synth.random_vector(n, seed=41, nrhs=2)
+    x = torch.empty(2 * n, dtype=torch.float64, device=DEV)
+    opts = gym.gym_solve_opts_default()
+    opts.rtol = 1e-13 if mode == "f64" else 1e-12
+    if mode == "ir_f32":
+        opts.mode = gym.GYM_MODE_IR_F32
+    gym.gym_ctx_set(ctx, gym.GYM_OPT_TILE, 1)
+    try:
+        info = gym.gym_solve(op, opts, 2, _t(b), x)
+    finally:
+        gym.gym_ctx_set(ctx, gym.GYM_OPT_TILE, 0)
+    got = x.cpu().numpy().reshape(2, -1)
+    tol = 1e-10 if mode == "f64" else 1e-8
+    for k in range(2):
+        ref = problems.solve_direct(P.A, b.reshape(2, -1)[k])
+        err = np.linalg.norm(got[k] - ref) / np.linalg.norm(ref)
+        assert err < tol, f"rhs {k}: {err} (iters {info.iters})"
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
 @pytest.mark.parametrize("curved", [False, True], ids=["affine", "curved"])
 def test_mass_solve_and_exact_feec_operator(g, curved):
     # K a = M1^{-1} C^T M2 C a, the exact-FEEC curl-of-curl of section 3,
