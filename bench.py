@@ -145,6 +145,69 @@ def serving(gym, nreq, seed, max_slots, qps=None, budget=64 << 30):
             "mean_ndofs": float(np.mean([r.ndofs for r in done.values()]))}
 
 
+def workload_rates(gym, ctx, which, N, r, perturb, nrhs, steps, seed):
+    """Apply rates per contraction precision (with the error against the FP64
+    apply on the same vector), and MINRES step throughput over a fixed number
+    of steps: FP64, and FP32 / BF16 inner steps of the refinement."""
+    import torch
+    import synth
+    verts = synth.perturbed_vertices((N, N, N), perturb, seed=0) if perturb else None
+    mesh = gym.gym_mesh_create(ctx, 3, (N, N, N), vertices=verts)
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1 if which == "hodge" else gym.GYM_MIXED_POISSON, mesh, r)
+    n = gym.gym_op_ndofs(op)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(seed)
+    x = torch.randn(nrhs * n, dtype=torch.float64, device="cuda:0", generator=gen)
+    y64 = torch.empty_like(x)
+    res = {"ndofs": n, "nrhs": nrhs, "apply": {}, "minres_steps": {}}
+    precs = [("f64", gym.GYM_F64), ("f32", gym.GYM_F32)] + ([] if perturb else [("bf16", gym.GYM_BF16)])
+    for name, prec in precs:
+        xi = x if prec == gym.GYM_F64 else x.float()
+        yi = y64 if prec == gym.GYM_F64 else torch.empty_like(xi)
+        gym.gym_op_apply(op, prec, nrhs, xi, yi)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            gym.gym_op_apply(op, prec, nrhs, xi, yi)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) / reps * 1e3
+        entry = {"us_per_apply": us, "gdof_s": nrhs * n / us / 1e3}
+        if prec != gym.GYM_F64:
+            entry["rel_err_vs_f64_apply"] = float(torch.linalg.norm(yi.double() - y64) / torch.linalg.norm(y64))
+        res["apply"][name] = entry
+        del yi
+    b = torch.randn(nrhs * n, dtype=torch.float64, device="cuda:0", generator=gen)
+    xs = torch.empty_like(b)
+    modes = [("f64", gym.GYM_MODE_F64), ("ir_f32", gym.GYM_MODE_IR_F32)] + \
+        ([] if perturb else [("ir_bf16", gym.GYM_MODE_IR_BF16)])
+    for name, mode in modes:
+        o = gym.gym_solve_opts_default()
+        o.mode = mode
+        o.maxit = steps
+        o.max_outer = 1
+        o.inner_rtol = 1e-30
+        o.check_every = steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        inf = gym.gym_solve(op, o, nrhs, b, xs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res["minres_steps"][name] = {"steps": inf.iters, "wall_s": wall,
+                                     "gdof_s": nrhs * n * inf.iters / wall / 1e9, "rel_res": inf.rel_res}
+    res["minres_steps"]["note"] = ("fixed step count from x = 0 (one solve call, including its setup and the "
+                                   "final FP64 residual); a full solve to 1e-8 with the block-Jacobi "
+                                   "preconditioner takes thousands of steps at this size")
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+    del x, y64, b, xs
+    torch.cuda.empty_cache()
+    return res
+
+
 # Sources of the operator kernel: the HBM traffic recorded under profiles/
 # (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) is reported only while these are
 # unchanged since the counters were taken.
@@ -191,6 +254,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-modes", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 64^3 degree-4 Poisson and perturbed 96^3 degree-3 Hodge rates")
     ap.add_argument("--profile-apply", type=int, default=0,
                     help="counter runs: copy calibration + this many MINRES steps, no JSON")
     ap.add_argument("--serve-requests", type=int, default=24,
@@ -359,6 +424,15 @@ def main():
             "batched": batched, "one_at_a_time": single, "poisson_arrivals": arrivals,
             "speedup_batched_vs_one_at_a_time": batched["solves_per_s"] / single["solves_per_s"],
         }
+
+    if not args.no_extras:
+        # the other two workloads: mixed precision at 64^3 degree 4 (Poisson) and
+        # perturbed 96^3 degree 3 (Hodge, 8 rhs)
+        log("extras: 64^3 degree-4 Poisson ...")
+        ext = {"poisson_r4_64cube": workload_rates(gym, ctx, "poisson", 64, 4, 0.0, 1, 200, 11)}
+        log("extras: perturbed 96^3 degree-3 Hodge, 8 rhs ...")
+        ext["hodge_r3_96cube_perturbed_8rhs"] = workload_rates(gym, ctx, "hodge", 96, 3, 0.15, 8, 30, 12)
+        out["extras"] = ext
 
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
