@@ -57,11 +57,14 @@ int launch_poisson(int dim, int r, int prec, const OpParams& p, int nrhs, int nc
 int launch_hodge_mr(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
 int launch_poisson_mr(int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
 int launch_mass(int prob, int dim, int r, int prec, const OpParams& p, int nrhs, int ncu, hipStream_t s);
-// ragged batch of affine operators of one problem and degree (FP64)
+// ragged batch of affine operators of one problem and degree (FP64); with
+// plist_host[0].fused every item carries its fused MINRES step (p.mr)
 int launch_op_batch(int prob, int dim, int r, OpParams* plist_host, int* bstart_host, int nreq,
                     OpParams* plist_dev, int* bstart_dev, int ncu, hipStream_t s);
 int launch_hodge_batch(int r, OpParams* ph, int* bh, int n, OpParams* pd, int* bd, int ncu, hipStream_t s);
 int launch_poisson_batch(int r, OpParams* ph, int* bh, int n, OpParams* pd, int* bd, int ncu, hipStream_t s);
+int launch_hodge_batch_mr(int r, OpParams* ph, int* bh, int n, OpParams* pd, int* bd, int ncu, hipStream_t s);
+int launch_poisson_batch_mr(int r, OpParams* ph, int* bh, int n, OpParams* pd, int* bd, int ncu, hipStream_t s);
 int upload_tables_hodge();
 int upload_tables_poisson();
 int upload_tables_mass();

@@ -115,7 +115,8 @@ struct Step2Coef {
 
 template <typename TV, bool UPD>
 __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* __restrict__ dinv, long long n,
-                                            long long off, const Step2Coef& k, double& ab, double& ac) {
+                                            long long off, const Step2Coef& k, int blk, int nblk, double& ab,
+                                            double& ac) {
   // restrict-qualified locals let the compiler issue every load of an
   // unrolled group before the stores of the previous one
   TV* __restrict__ y = v.y + off;
@@ -127,8 +128,8 @@ __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* _
   const TV* __restrict__ wb = v.wb + off;
   TV* __restrict__ wo = v.wout + off;
   constexpr int U = 4;
-  const long long stride = (long long)gridDim.x * kBT;
-  long long i0 = (long long)blockIdx.x * kBT + threadIdx.x;
+  const long long stride = (long long)nblk * kBT;
+  long long i0 = (long long)blk * kBT + threadIdx.x;
   auto one = [&](long long i, double yv, double r1v, double r2v, double dv, double zpv, double wav, double wbv,
                  double xv) {
     const TV ys = static_cast<TV>(k.ys * yv - k.c1 * r1v - k.c * r2v);
@@ -174,12 +175,11 @@ __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* _
   }
 }
 
+// blk / nblk: this block and the blocks of this right-hand side.
 template <typename TV>
-__global__ void __launch_bounds__(kBT) minres_step2(MrVecs<TV> v, const double* __restrict__ dinv, long long n,
-                                                    Step2Io io) {
-  __shared__ double sh[3 * kBT];
-  const int rhs = blockIdx.y;
-  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+__device__ __forceinline__ void step2_body(const MrVecs<TV>& v, const double* __restrict__ dinv, long long n,
+                                           const Step2Io& io, int rhs, int blk, int nblk, double* sh) {
+  const bool lead = blk == 0 && threadIdx.x == 0;
   MinresState s = io.cur[rhs];
   if (s.done) {
     if (lead) io.next[rhs] = s;
@@ -216,14 +216,21 @@ __global__ void __launch_bounds__(kBT) minres_step2(MrVecs<TV> v, const double* 
   k.c = alfa * vinv;
   const long long off = (long long)rhs * n;
   double ab = 0.0, ac = 0.0;
-  if (io.first) step2_sweep<TV, false>(v, dinv, n, off, k, ab, ac);
-  else step2_sweep<TV, true>(v, dinv, n, off, k, ab, ac);
+  if (io.first) step2_sweep<TV, false>(v, dinv, n, off, k, blk, nblk, ab, ac);
+  else step2_sweep<TV, true>(v, dinv, n, off, k, blk, nblk, ab, ac);
   double t2[2] = {ab, ac};
   wg_sums<kBT, 2>(t2, sh);
   if (threadIdx.x == 0) {
-    io.pb[rhs * gridDim.x + blockIdx.x] = t2[0];
-    io.pc[rhs * gridDim.x + blockIdx.x] = t2[1];
+    io.pb[(long long)rhs * nblk + blk] = t2[0];
+    io.pc[(long long)rhs * nblk + blk] = t2[1];
   }
+}
+
+template <typename TV>
+__global__ void __launch_bounds__(kBT) minres_step2(MrVecs<TV> v, const double* __restrict__ dinv, long long n,
+                                                    Step2Io io) {
+  __shared__ double sh[3 * kBT];
+  step2_body<TV>(v, dinv, n, io, blockIdx.y, blockIdx.x, gridDim.x, sh);
 }
 
 // Completes a pending step without a further apply (iteration cap reached):
@@ -527,66 +534,13 @@ __device__ __forceinline__ int find_item(const int* bstart, int nitem, int blk) 
   return lo;
 }
 
-__global__ void __launch_bounds__(kBT) batch_k3(const MinresItem* items, const int* bstart, int nitem) {
-  __shared__ double sh[kBT];
+// Second kernel of a fused MINRES step for every request of a ragged batch
+// (each item: one request, one rhs, its own blocks and partial sums).
+__global__ void __launch_bounds__(kBT) batch_step2(const MrItem* items, const int* bstart, int nitem) {
+  __shared__ double sh[3 * kBT];
   const int i = find_item(bstart, nitem, blockIdx.x);
-  const MinresItem it = items[i];
-  const int blk = blockIdx.x - bstart[i];
-  const MinresState s = *it.cur;
-  if (s.done) return;
-  const double c = s.oldb > 0 ? s.beta / s.oldb : 0.0;
-  double acc = 0.0;
-  for (long long k = (long long)blk * kBT + threadIdx.x; k < it.n; k += (long long)it.nb * kBT) {
-    double yi = it.y[k] - c * it.r1[k];
-    it.y[k] = yi;
-    acc += it.v[k] * yi;
-  }
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) it.pa[blk] = t;
-}
-
-__global__ void __launch_bounds__(kBT) batch_k5(const MinresItem* items, const int* bstart, int nitem) {
-  __shared__ double sh[kBT];
-  const int i = find_item(bstart, nitem, blockIdx.x);
-  const MinresItem it = items[i];
-  const int blk = blockIdx.x - bstart[i];
-  const MinresState s = *it.cur;
-  if (s.done) return;
-  const double alfa = reduce_partials(it.pa, it.nb, sh);
-  const double c = alfa / s.beta;
-  double acc = 0.0;
-  for (long long k = (long long)blk * kBT + threadIdx.x; k < it.n; k += (long long)it.nb * kBT) {
-    double yi = it.y[k] - c * it.r2[k];
-    it.y[k] = yi;
-    double zi = it.dinv[k] * yi;
-    it.r1[k] = zi;  // z over the old r1
-    acc += yi * zi;
-  }
-  double t = block_sum(acc, sh);
-  if (threadIdx.x == 0) it.pb[blk] = t;
-}
-
-__global__ void __launch_bounds__(kBT) batch_k7(const MinresItem* items, const int* bstart, int nitem) {
-  __shared__ double sh[kBT];
-  const int i = find_item(bstart, nitem, blockIdx.x);
-  const MinresItem it = items[i];
-  const int blk = blockIdx.x - bstart[i];
-  MinresState s = *it.cur;
-  if (s.done) {
-    if (blk == 0 && threadIdx.x == 0) *it.next = s;
-    return;
-  }
-  const double alfa = reduce_partials(it.pa, it.nb, sh);
-  const double b2 = reduce_partials(it.pb, it.nb, sh);
-  double phi, denom, oldeps, delta, vinv;
-  minres_scalar_update(s, alfa, b2, phi, denom, oldeps, delta, vinv);
-  if (blk == 0 && threadIdx.x == 0) *it.next = s;
-  for (long long k = (long long)blk * kBT + threadIdx.x; k < it.n; k += (long long)it.nb * kBT) {
-    double wn = (it.v[k] - oldeps * it.w2[k] - delta * it.w[k]) * denom;
-    it.w1[k] = wn;
-    it.x[k] += phi * wn;
-    it.v[k] = it.r1[k] * vinv;  // next v from z (in the old r1 buffer)
-  }
+  const MrItem it = items[i];
+  step2_body<double>(it.v, it.dinv, it.n, it.io, 0, blockIdx.x - bstart[i], it.nb, sh);
 }
 
 // N(0,1) right-hand side from a counter-based generator: SplitMix64
@@ -614,14 +568,8 @@ __global__ void __launch_bounds__(kBT) rhs_normal(double* b, long long first, lo
   }
 }
 
-void launch_batch_step(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(batch_k3, dim3(nblocks), dim3(kBT), 0, s, items_dev, bstart_dev, nitem);
-}
-void launch_batch_k5(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(batch_k5, dim3(nblocks), dim3(kBT), 0, s, items_dev, bstart_dev, nitem);
-}
-void launch_batch_k7(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(batch_k7, dim3(nblocks), dim3(kBT), 0, s, items_dev, bstart_dev, nitem);
+void launch_batch_step2(const MrItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(batch_step2, dim3(nblocks), dim3(kBT), 0, s, items_dev, bstart_dev, nitem);
 }
 void launch_rhs_normal(double* b, long long first, long long n, unsigned long long seed, int nb, hipStream_t s) {
   hipLaunchKernelGGL(rhs_normal, dim3(nb), dim3(kBT), 0, s, b, first, n, seed);

@@ -23,20 +23,6 @@ struct CgVecs {
   TV *x, *r, *p, *q;  // q holds A p, then z = M^-1 r
 };
 
-// One request of a ragged MINRES batch (FP64); pointers follow the same
-// rotation as the single-request driver.
-struct MinresItem {
-  long long n;
-  int nb, pad;
-  double *x, *r1, *r2, *y, *v, *w, *w1, *w2;
-  const double* dinv;
-  double *pa, *pb;
-  MinresState *cur, *next;
-};
-
-void launch_batch_step(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s);
-void launch_batch_k5(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s);
-void launch_batch_k7(const MinresItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s);
 void launch_rhs_normal(double* b, long long first, long long n, unsigned long long seed, int nb, hipStream_t s);
 
 int vec_grid(long long n, int ncu);
@@ -71,6 +57,17 @@ struct Step2Io {
 template <typename TV>
 void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, const Step2Io& io,
                          hipStream_t s);
+
+// One request of a ragged batch of fused MINRES steps (FP64, one rhs).
+struct MrItem {
+  long long n;
+  int nb, pad;  // nb: blocks of this request in the batch
+  MrVecs<double> v;
+  const double* dinv;
+  Step2Io io;
+};
+// minres_step2 for every item; bstart = prefix sums of the items' nb.
+void launch_batch_step2(const MrItem* items_dev, const int* bstart_dev, int nitem, int nblocks, hipStream_t s);
 // Completes a pending step (iteration cap): state cur -> next, w and x.
 template <typename TV>
 void minres_launch_finish(TV* x, const TV* zprev, const TV* wa, const TV* wb, TV* wout, long long n, int nrhs,

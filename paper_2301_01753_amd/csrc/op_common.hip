@@ -73,6 +73,13 @@ int upload_tables() {
 int launch_op_batch(int prob, int dim, int r, OpParams* plist_host, int* bstart_host, int nreq, OpParams* plist_dev,
                     int* bstart_dev, int ncu, hipStream_t s) {
   if (dim != 3) return -2;
+  if (nreq > 0 && plist_host[0].fused) {
+    if (prob == PROB_HODGE)
+      return launch_hodge_batch_mr(r, plist_host, bstart_host, nreq, plist_dev, bstart_dev, ncu, s);
+    if (prob == PROB_POISSON)
+      return launch_poisson_batch_mr(r, plist_host, bstart_host, nreq, plist_dev, bstart_dev, ncu, s);
+    return -2;
+  }
   if (prob == PROB_HODGE) return launch_hodge_batch(r, plist_host, bstart_host, nreq, plist_dev, bstart_dev, ncu, s);
   if (prob == PROB_POISSON)
     return launch_poisson_batch(r, plist_host, bstart_host, nreq, plist_dev, bstart_dev, ncu, s);

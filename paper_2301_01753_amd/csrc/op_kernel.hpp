@@ -682,7 +682,7 @@ __global__ void __launch_bounds__(C::NT) op_kernel(const OpParams p) {
 // Ragged batch: one launch over the workgroups of several operators of the
 // same kind and degree (different meshes and vectors).  bstart holds the
 // prefix sums of the per-request workgroup counts (nreq + 1 entries).
-template <class C, int PROB, int FORM, typename TV, typename TC>
+template <class C, int PROB, int FORM, typename TV, typename TC, bool MR>
 __global__ void __launch_bounds__(C::NT) op_kernel_batch(const OpParams* __restrict__ plist,
                                                        const int* __restrict__ bstart, int nreq) {
   __shared__ __align__(16) TC smem[Layout<C, Fields<PROB, C::DIM>, FORM>::total()];
@@ -694,11 +694,13 @@ __global__ void __launch_bounds__(C::NT) op_kernel_batch(const OpParams* __restr
     else hi = mid;
   }
   const OpParams p = plist[lo];
-  if (p.gate && *p.gate) return;  // that request has converged: leave its vectors alone
+  if constexpr (!MR) {
+    if (p.gate && *p.gate) return;  // that request has converged: leave its vectors alone
+  }
   const int local = blk - bstart[lo];
   const int nt = p.tiles_x * p.tiles_y;
   const int bx = local % nt, r2 = local / nt;
-  op_body<C, PROB, FORM, TV, TC, false>(p, bx, r2 % p.nchunks, r2 / p.nchunks, smem);
+  op_body<C, PROB, FORM, TV, TC, MR>(p, bx, r2 % p.nchunks, r2 / p.nchunks, smem);
 }
 
 // ---- tile-size selection ----------------------------------------------------
@@ -779,7 +781,7 @@ int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
 
 // Batched launch (affine Kronecker form, small tiles, one rhs per request):
 // tile each request, fill the device parameter list and prefix table, launch.
-template <int DIM, int R, int PROB, typename TV, typename TC>
+template <int DIM, int R, int PROB, typename TV, typename TC, bool MR = false>
 int launch_op_batch_r(OpParams* plist_host, int* bstart_host, int nreq, OpParams* plist_dev, int* bstart_dev,
                       int ncu, hipStream_t stream) {
   constexpr int B = TileSel<DIM, R, PROB, FORM_KRON, TC, 40 * 1024>::B;
@@ -790,7 +792,7 @@ int launch_op_batch_r(OpParams* plist_host, int* bstart_host, int nreq, OpParams
     return -1;
   if (hipMemcpyAsync(bstart_dev, bstart_host, sizeof(int) * (nreq + 1), hipMemcpyHostToDevice, stream) != hipSuccess)
     return -1;
-  hipLaunchKernelGGL((op_kernel_batch<C, PROB, FORM_KRON, TV, TC>), dim3(bstart_host[nreq]), dim3(C::NT), 0, stream,
+  hipLaunchKernelGGL((op_kernel_batch<C, PROB, FORM_KRON, TV, TC, MR>), dim3(bstart_host[nreq]), dim3(C::NT), 0, stream,
                      plist_dev, bstart_dev, nreq);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

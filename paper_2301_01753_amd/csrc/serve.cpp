@@ -5,8 +5,9 @@
 //      (device buffers are allocated here, never inside a step), builds or
 //      reuses the request's operator and starts its MINRES state;
 //   2. runs ONE MINRES step for every active request: one ragged operator
-//      launch per (problem, degree) group and one launch each of the three
-//      Krylov vector kernels over all active requests;
+//      launch per (problem, degree) group carrying the first half of the
+//      fused step, then one ragged launch of the second half over all active
+//      requests;
 //   3. every few steps reads all Krylov states back, retires converged
 //      requests (true FP64 residual, optional copy of the solution) and
 //      frees their memory, so queued requests can enter the mix.
@@ -62,15 +63,22 @@ struct Slot {
   Clock::time_point t0;
   OpEntry* op;
   long long n;
-  int nb;
+  int nb;   // blocks of the vector kernel
+  int npa;  // operator workgroups of the last step
   size_t bytes;
-  double *b, *x, *r1, *r2, *y, *v, *w, *w1, *w2, *pa, *pb;
+  double *b, *x;
+  double *r1, *r2, *y, *z, *zp, *w, *w1, *w2;  // current roles
+  double *pa, *pb[2], *pc[2], *alfa[2];         // step partials (two alternating sets)
+  double *scratch, *sums;                       // residual norms
+  int par;       // partial set written last
+  bool pending;  // a MINRES step awaits closing
   void* mem;
   int sidx;  // state pair index
-  int it;
-  int tighten;          // residual re-checks so far
-  double* R0[3];        // initial (r1, r2, y) buffers
-  double* W0[3];        // initial (w, w1, w2) buffers
+  int it;    // steps launched
+  int tighten;    // residual re-checks so far
+  double* R0[3];  // initial (r1, r2, y) buffers
+  double* Z0[2];  // initial (z, zp)
+  double* W0[3];  // initial (w, w1, w2) buffers
 };
 
 struct Done {
@@ -91,10 +99,16 @@ int64_t request_ndofs(const gym_request& r) {
   return a.ndofs + b.ndofs;
 }
 
-// slot vectors (9), partial sums, plus the operator's preconditioner
-size_t request_bytes(int64_t n, int ncu) {
-  int nb = vec_grid(n, ncu);
-  return sizeof(double) * (9 * (size_t)n + 2 * (size_t)nb + 4) + sizeof(double) * (size_t)n;
+// Device doubles of a slot: 10 vectors, the operator's partial sums (at
+// most one workgroup per element), two sets of step partials, the residual
+// scratch.
+size_t slot_doubles(int64_t n, int nel, int nb) {
+  return 10 * (size_t)n + (size_t)nel * nel * nel + 4 * (size_t)nb + 2 + (size_t)nb + 2;
+}
+
+// slot buffers plus the operator's preconditioner
+size_t request_bytes(int64_t n, int nel, int ncu) {
+  return sizeof(double) * (slot_doubles(n, nel, vec_grid(n, ncu)) + (size_t)n);
 }
 
 }  // namespace
@@ -121,8 +135,8 @@ struct gym_server {
   OpParams* plist_d[kStages] = {};
   int* bst_h[kStages] = {};
   int* bst_d[kStages] = {};
-  MinresItem* items_h[kStages] = {};
-  MinresItem* items_d[kStages] = {};
+  MrItem* items_h[kStages] = {};
+  MrItem* items_d[kStages] = {};
   int* ibst_h[kStages] = {};
   int* ibst_d[kStages] = {};
   hipEvent_t ev[kStages] = {};
@@ -191,20 +205,33 @@ int admit(gym_server* s, Pending& p) {
   sl->op = e;
   sl->n = p.n;
   sl->nb = vec_grid(p.n, s->ctx->ncu);
-  sl->bytes = sizeof(double) * (9 * (size_t)p.n + 2 * (size_t)sl->nb + 4);
+  sl->bytes = sizeof(double) * slot_doubles(p.n, p.req.nel, sl->nb);
   if (hipMalloc(&sl->mem, sl->bytes) != hipSuccess) {
     (void)hipGetLastError();
     delete sl;
     return fail(GYM_E_OOM, "serving: device allocation failed at admission");
   }
   double* base = (double*)sl->mem;
-  double** vecs[9] = {&sl->b, &sl->x, &sl->r1, &sl->r2, &sl->y, &sl->v, &sl->w, &sl->w1, &sl->w2};
-  for (int k = 0; k < 9; ++k) *vecs[k] = base + (size_t)k * p.n;
-  sl->pa = base + 9 * (size_t)p.n;
-  sl->pb = sl->pa + sl->nb;
+  double** vecs[10] = {&sl->b, &sl->x, &sl->r1, &sl->r2, &sl->y, &sl->z, &sl->zp, &sl->w, &sl->w1, &sl->w2};
+  for (int k = 0; k < 10; ++k) *vecs[k] = base + (size_t)k * p.n;
+  double* q = base + 10 * (size_t)p.n;
+  sl->pa = q;
+  q += (size_t)p.req.nel * p.req.nel * p.req.nel;
+  for (int k = 0; k < 2; ++k) {
+    sl->pb[k] = q;
+    sl->pc[k] = q + sl->nb;
+    sl->alfa[k] = q + 2 * sl->nb;
+    q += 2 * sl->nb + 1;
+  }
+  sl->scratch = q;
+  sl->sums = q + sl->nb;
   sl->R0[0] = sl->r1, sl->R0[1] = sl->r2, sl->R0[2] = sl->y;
+  sl->Z0[0] = sl->z, sl->Z0[1] = sl->zp;
   sl->W0[0] = sl->w, sl->W0[1] = sl->w1, sl->W0[2] = sl->w2;
   sl->tighten = 0;
+  sl->par = 0;
+  sl->pending = false;
+  sl->npa = 0;
   e->refs += 1;
   s->bytes_used += sl->bytes;
   sl->sidx = s->free_sidx.back();
@@ -218,18 +245,19 @@ int admit(gym_server* s, Pending& p) {
   } else {
     launch_rhs_normal(sl->b, nblk[0], p.n, p.req.seed, sl->nb, s->stream);
   }
-  MinresVecs<double> V{sl->b, sl->x, sl->r1, sl->r2, sl->y, sl->v, sl->w, sl->w1, sl->w2};
-  minres_launch_init<double>(V, e->op->d_prec, p.n, 1, sl->nb, sl->pa, s->d_states + 2 * sl->sidx, s->opts.rtol,
-                             s->stream);
+  // init: r1 = r2 = b, z = M^-1 b, beta_1 (y receives v_1, unused)
+  MinresVecs<double> V{sl->b, sl->x, sl->r1, sl->r2, sl->z, sl->y, sl->w, sl->w1, sl->w2};
+  minres_launch_init<double>(V, e->op->d_prec, p.n, 1, sl->nb, sl->scratch, s->d_states + 2 * sl->sidx,
+                             s->opts.rtol, s->stream);
   s->active.push_back(sl);
   return 0;
 }
 
-// One MINRES step of every active request.
+// One fused MINRES step of every active request.
 int step(gym_server* s) {
   const int st = s->stage = (s->stage + 1) % kStages;
   GYM_HIP(hipEventSynchronize(s->ev[st]));
-  // operator applies, one ragged launch per (problem, degree)
+  // first half: operator applies with the fused epilogue, one ragged launch per (problem, degree)
   std::map<std::pair<int, int>, std::vector<Slot*>> groups;
   for (Slot* sl : s->active) groups[{sl->problem, sl->degree}].push_back(sl);
   int off = 0, boff = 0;
@@ -237,83 +265,88 @@ int step(gym_server* s) {
     const auto& list = g.second;
     int prob = 0;
     for (size_t i = 0; i < list.size(); ++i) {
-      build_op_params(list[i]->op->op, list[i]->v, list[i]->y, s->plist_h[st][off + i], prob);
-      // the done flag of this step's current state gates the apply
-      s->plist_h[st][off + i].gate = &(s->d_states + 2 * list[i]->sidx + (list[i]->it & 1))->done;
+      Slot* sl = list[i];
+      OpParams& p = s->plist_h[st][off + i];
+      build_op_params(sl->op->op, sl->z, sl->y, p, prob);
+      p.fused = 1;
+      p.mr = MrStep{s->d_states + 2 * sl->sidx + (sl->it & 1), sl->pa};
     }
     int rc = launch_op_batch(prob, 3, g.first.second, s->plist_h[st] + off, s->bst_h[st] + boff, (int)list.size(),
                              s->plist_d[st] + off, s->bst_d[st] + boff, s->ctx->ncu, s->stream);
     if (rc) return fail(GYM_E_HIP, "serving: batched operator launch failed");
+    for (size_t i = 0; i < list.size(); ++i) list[i]->npa = s->bst_h[st][boff + i + 1] - s->bst_h[st][boff + i];
     off += (int)list.size();
     boff += (int)list.size() + 1;
   }
-  // Krylov vector kernels over all requests
+  // second half over all requests
   const int na = (int)s->active.size();
   int nblocks = 0;
   for (int i = 0; i < na; ++i) {
     Slot* sl = s->active[i];
-    MinresItem& it = s->items_h[st][i];
+    MrItem& it = s->items_h[st][i];
     it.n = sl->n;
     it.nb = sl->nb;
-    it.x = sl->x;
-    it.r1 = sl->r1;
-    it.r2 = sl->r2;
-    it.y = sl->y;
-    it.v = sl->v;
-    it.w = sl->w;
-    it.w1 = sl->w1;
-    it.w2 = sl->w2;
+    it.pad = 0;
+    it.v = MrVecs<double>{sl->y, sl->r1, sl->r2, sl->zp, sl->x, sl->w2, sl->w, sl->w1};
     it.dinv = sl->op->op->d_prec;
-    it.pa = sl->pa;
-    it.pb = sl->pb;
-    it.cur = s->d_states + 2 * sl->sidx + (sl->it & 1);
-    it.next = s->d_states + 2 * sl->sidx + ((sl->it + 1) & 1);
+    MinresState* cur = s->d_states + 2 * sl->sidx + (sl->it & 1);
+    MinresState* next = s->d_states + 2 * sl->sidx + ((sl->it + 1) & 1);
+    const int pr = sl->par;
+    it.io = Step2Io{cur, next, sl->pending ? 0 : 1, sl->npa, sl->nb, sl->pa, sl->pb[pr], sl->pc[pr],
+                    sl->alfa[pr], sl->pb[pr ^ 1], sl->pc[pr ^ 1], sl->alfa[pr ^ 1]};
     s->ibst_h[st][i] = nblocks;
     nblocks += sl->nb;
   }
   s->ibst_h[st][na] = nblocks;
-  GYM_HIP(hipMemcpyAsync(s->items_d[st], s->items_h[st], sizeof(MinresItem) * na, hipMemcpyHostToDevice, s->stream));
+  GYM_HIP(hipMemcpyAsync(s->items_d[st], s->items_h[st], sizeof(MrItem) * na, hipMemcpyHostToDevice, s->stream));
   GYM_HIP(hipMemcpyAsync(s->ibst_d[st], s->ibst_h[st], sizeof(int) * (na + 1), hipMemcpyHostToDevice, s->stream));
-  launch_batch_step(s->items_d[st], s->ibst_d[st], na, nblocks, s->stream);
-  launch_batch_k5(s->items_d[st], s->ibst_d[st], na, nblocks, s->stream);
-  launch_batch_k7(s->items_d[st], s->ibst_d[st], na, nblocks, s->stream);
+  launch_batch_step2(s->items_d[st], s->ibst_d[st], na, nblocks, s->stream);
   GYM_HIP(hipEventRecord(s->ev[st], s->stream));
   GYM_HIP(hipGetLastError());
   // the same rotation as the single-request driver
   for (Slot* sl : s->active) {
+    if (sl->pending) {
+      double *w = sl->w, *w1 = sl->w1, *w2 = sl->w2;
+      sl->w = w1;
+      sl->w1 = w2;
+      sl->w2 = w;
+    }
+    std::swap(sl->z, sl->zp);
     double* r1 = sl->r1;
     sl->r1 = sl->r2;
     sl->r2 = sl->y;
     sl->y = r1;
-    double *w = sl->w, *w1 = sl->w1, *w2 = sl->w2;
-    sl->w = w1;
-    sl->w1 = w2;
-    sl->w2 = w;
+    sl->pending = true;
+    sl->par ^= 1;
     sl->it += 1;
   }
   return 0;
 }
 
-// Buffer roles after k real MINRES iterations (the host kept rotating while
+// Buffer roles after k working MINRES steps (the host kept rotating while
 // the request sat converged on the device, but no kernel touched it).
-void roles_from_itn(Slot* sl, int k) {
+void roles_from_steps(Slot* sl, int k) {
   sl->r1 = sl->R0[k % 3];
   sl->r2 = sl->R0[(k + 1) % 3];
   sl->y = sl->R0[(k + 2) % 3];
-  sl->w = sl->W0[k % 3];
-  sl->w1 = sl->W0[(k + 1) % 3];
-  sl->w2 = sl->W0[(k + 2) % 3];
+  sl->z = sl->Z0[k & 1];
+  sl->zp = sl->Z0[(k + 1) & 1];
+  const int kw = k > 0 ? k - 1 : 0;  // the first step does not rotate the w buffers
+  sl->w = sl->W0[kw % 3];
+  sl->w1 = sl->W0[(kw + 1) % 3];
+  sl->w2 = sl->W0[(kw + 2) % 3];
+  sl->par = k & 1;
+  sl->pending = k > 0;
 }
 
-// true relative residual ||b - A x|| / ||b|| in FP64 (y and the partial-sum
-// buffers are scratch between iterations)
+// true relative residual ||b - A x|| / ||b|| in FP64 (y is scratch between
+// steps)
 int true_relres(gym_server* s, Slot* sl, double* rel) {
   if (int rc = launch_op_apply(sl->op->op, GYM_F64, 1, sl->x, sl->y, s->stream)) return rc;
-  double* sums = sl->pb + sl->nb;
-  launch_norm2(sl->y, sl->b, sl->n, 1, sl->nb, 1, sl->pa, sums, s->stream);
-  launch_norm2(sl->b, nullptr, sl->n, 1, sl->nb, 0, sl->pa, sums + 1, s->stream);
+  launch_norm2(sl->y, sl->b, sl->n, 1, sl->nb, 1, sl->scratch, sl->sums, s->stream);
+  launch_norm2(sl->b, nullptr, sl->n, 1, sl->nb, 0, sl->scratch, sl->sums + 1, s->stream);
   double h[2];
-  GYM_HIP(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+  GYM_HIP(hipMemcpyAsync(h, sl->sums, sizeof(h), hipMemcpyDeviceToHost, s->stream));
   GYM_HIP(hipStreamSynchronize(s->stream));
   double bn = std::sqrt(h[1]);
   *rel = bn > 0 ? std::sqrt(h[0]) / bn : std::sqrt(h[0]);
@@ -354,11 +387,23 @@ int check_and_retire(gym_server* s) {
   for (Slot* sl : s->active) {
     MinresState ms = s->h_states[2 * sl->sidx + (sl->it & 1)];
     if (ms.done || sl->it >= s->opts.maxit) {
-      roles_from_itn(sl, ms.itn);
+      if (ms.done) {
+        // converged when step itn was closed, in working step itn + 1
+        roles_from_steps(sl, ms.itn + 1);
+      } else if (sl->pending) {
+        // iteration cap: complete the pending step so that x is its iterate
+        MinresState* cur = s->d_states + 2 * sl->sidx + (sl->it & 1);
+        MinresState* next = s->d_states + 2 * sl->sidx + ((sl->it + 1) & 1);
+        minres_launch_finish<double>(sl->x, sl->zp, sl->w2, sl->w, sl->w1, sl->n, 1, sl->nb, cur, next,
+                                     sl->pb[sl->par], sl->alfa[sl->par], s->stream);
+        GYM_HIP(hipMemcpyAsync(&ms, next, sizeof(MinresState), hipMemcpyDeviceToHost, s->stream));
+        GYM_HIP(hipStreamSynchronize(s->stream));
+      }
       double rel = 0;
       if (int rc = true_relres(s, sl, &rel)) return rc;
-      if (rel > s->opts.rtol && ms.flag >= 0 && sl->it < s->opts.maxit && sl->tighten < 6) {
+      if (ms.done && rel > s->opts.rtol && ms.flag >= 0 && sl->it < s->opts.maxit && sl->tighten < 6) {
         // the preconditioned estimate was optimistic: tighten and resume
+        // the same recurrence (the pending step is closed next)
         sl->tighten += 1;
         ms.tol *= 0.1;
         ms.done = 0;
@@ -453,8 +498,8 @@ int gym_serve_start(const gym_serve_opts* opts, gym_server** out) {
     GYM_HIP(hipMalloc(&s->plist_d[k], sizeof(OpParams) * maxs));
     GYM_HIP(hipHostMalloc((void**)&s->bst_h[k], sizeof(int) * (maxs + kMaxGroups + 1), hipHostMallocDefault));
     GYM_HIP(hipMalloc(&s->bst_d[k], sizeof(int) * (maxs + kMaxGroups + 1)));
-    GYM_HIP(hipHostMalloc((void**)&s->items_h[k], sizeof(MinresItem) * maxs, hipHostMallocDefault));
-    GYM_HIP(hipMalloc(&s->items_d[k], sizeof(MinresItem) * maxs));
+    GYM_HIP(hipHostMalloc((void**)&s->items_h[k], sizeof(MrItem) * maxs, hipHostMallocDefault));
+    GYM_HIP(hipMalloc(&s->items_d[k], sizeof(MrItem) * maxs));
     GYM_HIP(hipHostMalloc((void**)&s->ibst_h[k], sizeof(int) * (maxs + 1), hipHostMallocDefault));
     GYM_HIP(hipMalloc(&s->ibst_d[k], sizeof(int) * (maxs + 1)));
     GYM_HIP(hipEventCreate(&s->ev[k]));
@@ -473,7 +518,7 @@ int gym_serve_submit(gym_server* s, const gym_request* req, uint64_t* id) {
   Pending p;
   p.req = *req;
   p.n = request_ndofs(*req);
-  p.bytes = request_bytes(p.n, s->ctx->ncu);
+  p.bytes = request_bytes(p.n, req->nel, s->ctx->ncu);
   if (p.bytes > (size_t)s->opts.mem_budget) return fail(GYM_E_OOM, "request exceeds the server's memory budget");
   if (req->rhs) p.rhs.assign(req->rhs, req->rhs + p.n);
   p.req.rhs = nullptr;
