@@ -79,6 +79,7 @@ typedef struct gym_mesh gym_mesh;
 typedef struct gym_space gym_space;
 typedef struct gym_op gym_op;
 typedef struct gym_server gym_server;
+typedef struct gym_maxwell gym_maxwell;
 
 /* ---- context --------------------------------------------------------- */
 /* Bind to HIP device `device`, upload the 1-D basis/quadrature tables.
@@ -213,6 +214,48 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts, int nrhs,
 int gym_mass_solve(const gym_space* space, const gym_solve_opts* opts,
                    int nrhs, const double* b, double* x, gym_solve_info* info,
                    void* stream);
+
+/* ---- time stepping: generalized Yee methods (paper section 3) --------- */
+/* The Maxwell system in the canonical pair (a, e), both in Lambda^1 with a
+ * perfect-conductor boundary (tangential components zero: H0(curl)), units
+ * eps0 = 1, mu0 = 1 / c^2.  Hamiltonian H = 1/2 e^T Q1 e + 1/2 a^T P2 a with
+ * P2 = c^2 C^T M2~ C (eq. discTildeHamilSystem); shear maps
+ * a <- a - tau Q1 e and e <- e + tau P2 a (eq. shearMaps) composed by Strang
+ * splitting, half step in a, full step in e, half step in a (eq.
+ * strangSplit).  Stable iff tau <= 2 / omega_max, omega_max^2 the largest
+ * eigenvalue of Q1 P2 (Proposition Stability). */
+#define GYM_Q1_EXACT  0  /* Q1 = M1^-1, applied by a CG mass solve           */
+#define GYM_Q1_LUMPED 1  /* inverse row sums of M1 (section 4.3; affine only) */
+#define GYM_M2_EXACT  0  /* M2~ = M2                                         */
+#define GYM_M2_LUMPED 1  /* row sums of M2 (affine only)                     */
+/* Lumped row sums are those of the mass matrix without boundary conditions,
+ * at the kept unknowns; with Whitney forms (degree 1) on a box, lumped Q1 and
+ * M2~ give Yee's leapfrog (section 4). */
+typedef struct gym_maxwell_opts {
+  int q1;           /* GYM_Q1_*                                            */
+  int m2;           /* GYM_M2_*                                            */
+  double c;         /* wave speed (> 0)                                    */
+  double cg_rtol;   /* exact Q1: relative residual of each M1 solve        */
+  int cg_maxit;     /* exact Q1: CG iteration cap per solve                */
+} gym_maxwell_opts;
+/* Defaults: exact Q1 and M2~, c = 1, cg_rtol 1e-14, cg_maxit 1000. */
+void gym_maxwell_opts_default(gym_maxwell_opts* opts);
+/* Errors: GYM_E_ARG (not 3-D, degree outside 1..4, bad option),
+ * GYM_E_UNSUPPORTED (lumped masses on a curved mesh), GYM_E_OOM. */
+int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree,
+                       const gym_maxwell_opts* opts, gym_maxwell** out);
+/* Unknowns of a and of e (each). */
+int64_t gym_maxwell_ndofs(const gym_maxwell* mx);
+/* nsteps Strang steps of length tau on device vectors a and e (ndofs
+ * doubles each, updated in place).  Consecutive half steps in a are merged,
+ * so a step costs one Q1 and one P2 application.  Synchronises the stream
+ * when Q1 is exact (the CG solves read their convergence state).
+ * Errors: GYM_E_ARG (tau <= 0, nsteps < 0), GYM_W_NOT_CONVERGED if an M1
+ * solve missed cg_rtol (the step is still taken). */
+int gym_maxwell_step(gym_maxwell* mx, double tau, int nsteps, double* a, double* e, void* stream);
+/* *H = 1/2 e^T Q1 e + 1/2 a^T P2 a (host value; synchronises the stream). */
+int gym_maxwell_energy(gym_maxwell* mx, const double* a, const double* e, double* H, void* stream);
+int gym_maxwell_destroy(gym_maxwell* mx);
 
 /* ---- serving: continuous batching of independent solves --------------- */
 typedef struct gym_serve_opts {

@@ -102,6 +102,27 @@ Diag1D diag1d(int r, int64_t nel) {
   return d;
 }
 
+// Row sums of the global 1-D reference mass matrices along one axis, without
+// boundary conditions: nodal (r nel + 1 entries), edge (r nel).
+void rowsum1d(int r, int64_t nel, std::vector<double>& rn, std::vector<double>& re) {
+  Tables1D t = make_tables(r, r + 1);
+  const int q = r + 1;
+  std::vector<double> sn(r + 1, 0.0), se(r, 0.0);
+  for (int i = 0; i <= r; ++i)
+    for (int j = 0; j <= r; ++j)
+      for (int k = 0; k < q; ++k) sn[i] += t.gw[k] * t.phi[k * (r + 1) + i] * t.phi[k * (r + 1) + j];
+  for (int i = 0; i < r; ++i)
+    for (int j = 0; j < r; ++j)
+      for (int k = 0; k < q; ++k) se[i] += t.gw[k] * t.edge[k * r + i] * t.edge[k * r + j];
+  const int64_t m = r * nel;
+  rn.assign(m + 1, 0.0);
+  re.assign(m, 0.0);
+  for (int64_t e = 0; e < nel; ++e) {
+    for (int i = 0; i <= r; ++i) rn[r * e + i] += sn[i];
+    for (int j = 0; j < r; ++j) re[r * e + j] = se[j];
+  }
+}
+
 // Preconditioner diagonal on affine meshes (see gym_op_precond_diag).
 std::vector<double> precond_diag_host(const gym_op* op) {
   const gym_mesh* m = op->mesh;
@@ -553,6 +574,31 @@ std::vector<double> mass_diag_host(const gym_space* sp) {
           int64_t p[3] = {cd.start[0] + i, cd.start[1] + j, cd.start[2] + k};
           double v = sc;
           for (int a = 0; a < m->dim; ++a) v *= (cd.nodal_mask >> a & 1) ? D[a].dn[p[a]] : D[a].de[p[a]];
+          out[idx++] = v;
+        }
+  }
+  return out;
+}
+
+// Lumped mass of an affine space: the row sums of its mass matrix without
+// boundary conditions, at the kept unknowns (Kronecker product of 1-D row
+// sums times the constant metric of the component).
+std::vector<double> lumped_diag_host(const gym_space* sp) {
+  const gym_mesh* m = sp->mesh;
+  const SpaceDesc& s = sp->desc;
+  std::vector<double> rn[3], re[3];
+  for (int a = 0; a < 3; ++a) rowsum1d(s.r, a < m->dim ? m->nel[a] : 1, rn[a], re[a]);
+  std::vector<double> out(s.ndofs);
+  for (int c = 0; c < s.ncomp; ++c) {
+    const CompDesc& cd = s.comp[c];
+    const double sc = metric_const(s.kind, c, m);
+    int64_t idx = cd.offset;
+    for (int64_t k = 0; k < cd.count[2]; ++k)
+      for (int64_t j = 0; j < cd.count[1]; ++j)
+        for (int64_t i = 0; i < cd.count[0]; ++i) {
+          int64_t p[3] = {cd.start[0] + i, cd.start[1] + j, cd.start[2] + k};
+          double v = sc;
+          for (int a = 0; a < m->dim; ++a) v *= (cd.nodal_mask >> a & 1) ? rn[a][p[a]] : re[a][p[a]];
           out[idx++] = v;
         }
   }

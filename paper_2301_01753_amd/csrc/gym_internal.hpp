@@ -62,6 +62,9 @@ namespace gym {
 struct OpParams;
 // Parameters of one block-operator apply (capi.cpp), and the apply itself.
 void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int& prob);
+// Row sums of the mass matrix of an affine space without boundary
+// conditions, at its kept unknowns (canonical order).
+std::vector<double> lumped_diag_host(const gym_space* sp);
 // y = A x; with `mr` the launch also carries that fused MINRES step.
 int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s,
                     const MrStep* mr = nullptr);

@@ -383,8 +383,12 @@ __global__ void __launch_bounds__(kBT) norm2_partial(const TA* __restrict__ a, c
   const long long off = (long long)rhs * n;
   double acc = 0.0;
   for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
-    double d = todbl(a[off + i]) - (mode ? b[off + i] : 0.0);
-    acc += d * d;
+    if (mode == 2) {
+      acc += todbl(a[off + i]) * b[off + i];
+    } else {
+      double d = todbl(a[off + i]) - (mode ? b[off + i] : 0.0);
+      acc += d * d;
+    }
   }
   double t = block_sum(acc, sh);
   if (threadIdx.x == 0) part[rhs * gridDim.x + blockIdx.x] = t;
@@ -401,6 +405,16 @@ __global__ void __launch_bounds__(kBT) finish_sums(const double* part, int np, d
 __global__ void __launch_bounds__(kBT) sub_kernel(const double* a, const double* b, double* y, long long n) {
   for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
     y[i] = a[i] - b[i];
+}
+
+// y = beta y + alpha (d .* x), d = NULL meaning ones (all FP64; beta = 0
+// overwrites y)
+__global__ void __launch_bounds__(kBT) axpy_diag_kernel(double* y, double beta, double alpha, const double* d,
+                                                        const double* x, long long n) {
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    const double v = alpha * (d ? d[i] * x[i] : x[i]);
+    y[i] = beta == 0.0 ? v : beta * y[i] + v;
+  }
 }
 
 // x += d (all FP64)
@@ -481,6 +495,11 @@ void launch_norm2(const double* a, const double* b, long long n, int nrhs, int n
 
 void launch_sub(const double* a, const double* b, double* y, long long n, int nb, hipStream_t s) {
   GYM_LAUNCH(sub_kernel, dim3(nb), s, a, b, y, n);
+}
+
+void launch_axpy_diag(double* y, double beta, double alpha, const double* d, const double* x, long long n, int nb,
+                      hipStream_t s) {
+  GYM_LAUNCH(axpy_diag_kernel, dim3(nb), s, y, beta, alpha, d, x, n);
 }
 
 void launch_add(const double* d, double* x, long long n, int nb, hipStream_t s) {

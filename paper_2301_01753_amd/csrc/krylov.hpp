@@ -80,10 +80,14 @@ template <typename TV>
 void cg_launch_iter_tail(const CgVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb,
                          const CgState* cur, CgState* next, double* pa, double* pb, hipStream_t s);
 
+// per rhs: mode 0 |a|^2, mode 1 |a - b|^2, mode 2 a . b (deterministic two-stage sums)
 void launch_norm2(const double* a, const double* b, long long n, int nrhs, int nb, int mode, double* part,
                   double* out, hipStream_t s);
 void launch_sub(const double* a, const double* b, double* y, long long n, int nb, hipStream_t s);
 void launch_add(const double* d, double* x, long long n, int nb, hipStream_t s);
+// y = beta y + alpha (d .* x); d = NULL: ones
+void launch_axpy_diag(double* y, double beta, double alpha, const double* d, const double* x, long long n, int nb,
+                      hipStream_t s);
 void launch_to_f32_scaled(const double* a, float* y, long long n, int nrhs, int nb, const double* scale,
                           hipStream_t s);
 void launch_axpy_f32(const float* d, double* x, long long n, int nrhs, int nb, const double* scale,

@@ -29,6 +29,8 @@ GYM_F64, GYM_F32, GYM_BF16 = 0, 1, 2
 GYM_MIXED_POISSON, GYM_HODGE1 = 0, 1
 GYM_MINRES, GYM_CG = 0, 1
 GYM_MODE_F64, GYM_MODE_IR_F32, GYM_MODE_IR_BF16 = 0, 1, 2
+GYM_Q1_EXACT, GYM_Q1_LUMPED = 0, 1
+GYM_M2_EXACT, GYM_M2_LUMPED = 0, 1
 
 KIND = {"H1": GYM_H1, "HCURL": GYM_HCURL, "HDIV": GYM_HDIV, "L2": GYM_L2}
 
@@ -67,6 +69,11 @@ class Result(ctypes.Structure):
                 ("latency_s", ctypes.c_double), ("ndofs", ctypes.c_int64)]
 
 
+class MaxwellOpts(ctypes.Structure):
+    _fields_ = [("q1", ctypes.c_int), ("m2", ctypes.c_int), ("c", ctypes.c_double), ("cg_rtol", ctypes.c_double),
+                ("cg_maxit", ctypes.c_int)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _I64 = ctypes.c_int64
@@ -97,6 +104,12 @@ SIGNATURES = {
     "gym_serve_submit": (_I, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
     "gym_serve_poll": (_I, [_P, ctypes.c_uint64, ctypes.POINTER(Result), _P]),
     "gym_serve_stop": (_I, [_P]),
+    "gym_maxwell_opts_default": (None, [ctypes.POINTER(MaxwellOpts)]),
+    "gym_maxwell_create": (_I, [_P, _P, _I, ctypes.POINTER(MaxwellOpts), ctypes.POINTER(_P)]),
+    "gym_maxwell_ndofs": (_I64, [_P]),
+    "gym_maxwell_step": (_I, [_P, ctypes.c_double, _I, _P, _P, _P]),
+    "gym_maxwell_energy": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
+    "gym_maxwell_destroy": (_I, [_P]),
 }
 
 _lib = None
@@ -260,6 +273,40 @@ def gym_mass_solve(space, opts, nrhs, b, x, stream=None):
                               _stream(stream))
     _check(st, ok=(GYM_OK, GYM_W_NOT_CONVERGED))
     return info
+
+
+def gym_maxwell_opts_default():
+    o = MaxwellOpts()
+    lib().gym_maxwell_opts_default(ctypes.byref(o))
+    return o
+
+
+def gym_maxwell_create(ctx, mesh, degree, opts=None):
+    h = _P()
+    _check(lib().gym_maxwell_create(ctx, mesh, degree, ctypes.byref(opts) if opts is not None else None,
+                                    ctypes.byref(h)))
+    return h
+
+
+def gym_maxwell_ndofs(mx):
+    return int(lib().gym_maxwell_ndofs(mx))
+
+
+def gym_maxwell_step(mx, tau, nsteps, a, e, stream=None):
+    st = lib().gym_maxwell_step(mx, float(tau), int(nsteps), _ptr(a), _ptr(e), _stream(stream))
+    _check(st, ok=(GYM_OK, GYM_W_NOT_CONVERGED))
+    return st
+
+
+def gym_maxwell_energy(mx, a, e, stream=None):
+    h = ctypes.c_double()
+    st = lib().gym_maxwell_energy(mx, _ptr(a), _ptr(e), ctypes.byref(h), _stream(stream))
+    _check(st, ok=(GYM_OK, GYM_W_NOT_CONVERGED))
+    return h.value
+
+
+def gym_maxwell_destroy(mx):
+    _check(lib().gym_maxwell_destroy(mx))
 
 
 def gym_serve_start(opts):

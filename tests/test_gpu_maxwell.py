@@ -1,0 +1,149 @@
+"""GPU parity of the generalized Yee time stepping (gym_maxwell_*) with the oracle.
+
+The GPU merges the two half steps in a between consecutive Strang steps;
+the oracle applies every half step literally.  Lumped masses: the two differ
+by rounding only (1e-13 of the state's scale).  Exact Q1: every M1 solve is a
+CG solve to 1e-14, so the trajectories agree to 1e-10 after a few steps.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import maxwell
+from oracle.lattice import Mesh
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def g():
+    from paper_2301_01753_amd import gym
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = gym.gym_create(0)
+    yield gym, ctx
+    gym.gym_destroy(ctx)
+
+
+def _t(a):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV)
+
+
+def _setup(gym, ctx, nel, r, q1, m2, c=1.0, hi=(1.0, 1.0, 1.0), perturb=0.0):
+    verts = synth.perturbed_vertices(nel, perturb, seed=5, hi=hi) if perturb else synth.uniform_vertices(nel, hi=hi)
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts if perturb else None, hi=hi)
+    o = gym.gym_maxwell_opts_default()
+    o.q1 = gym.GYM_Q1_EXACT if q1 == "exact" else gym.GYM_Q1_LUMPED
+    o.m2 = gym.GYM_M2_EXACT if m2 == "exact" else gym.GYM_M2_LUMPED
+    o.c = c
+    mx = gym.gym_maxwell_create(ctx, mesh, r, o)
+    G = maxwell.Gym(Mesh(verts), r, q1=q1, m2=m2, c=c)
+    assert gym.gym_maxwell_ndofs(mx) == G.n
+    return mesh, mx, G
+
+
+def _close(gym, mesh, mx):
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+
+
+CASES = [((4, 3, 5), 1, "lumped", "lumped", 1.3, (1.0, 0.9, 1.3), 0.0, 1e-13),
+         ((3, 3, 2), 2, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.0, 1e-10),
+         ((3, 2, 3), 2, "lumped", "exact", 0.7, (1.0, 1.2, 1.0), 0.0, 1e-13),
+         ((2, 3, 2), 3, "exact", "lumped", 1.0, (1.0, 1.0, 1.0), 0.0, 1e-10),
+         ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15, 1e-10)]
+
+
+@pytest.mark.parametrize("nel,r,q1,m2,c,hi,perturb,tol", CASES)
+def test_steps_match_oracle(g, nel, r, q1, m2, c, hi, perturb, tol):
+    gym, ctx = g
+    mesh, mx, G = _setup(gym, ctx, nel, r, q1, m2, c, hi, perturb)
+    a0 = synth.random_vector(G.n, seed=7)
+    e0 = synth.random_vector(G.n, seed=8)
+    tau = 0.5 * G.tau_cfl()
+    a, e = _t(a0), _t(e0)
+    gym.gym_maxwell_step(mx, tau, 7, a, e)
+    ar, er = G.strang(a0, e0, tau, 7)
+    for got, ref in ((a, ar), (e, er)):
+        err = np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err < tol, err
+    H = gym.gym_maxwell_energy(mx, a, e)
+    Hr = G.energy(ar, er)
+    assert abs(H - Hr) < max(tol, 1e-12) * abs(Hr)
+    _close(gym, mesh, mx)
+
+
+def test_yee_leapfrog_on_gpu(g):
+    # Whitney forms, lumped masses: the GPU steps are Yee's finite differences.
+    import test_oracle_maxwell as tom
+    gym, ctx = g
+    mesh, mx, G = _setup(gym, ctx, (5, 4, 6), 1, "lumped", "lumped", 1.0, (1.0, 0.8, 1.2))
+    a0 = synth.random_vector(G.n, seed=9)
+    e0 = synth.random_vector(G.n, seed=10)
+    tau = 0.6 * G.tau_cfl()
+    a, e = _t(a0), _t(e0)
+    gym.gym_maxwell_step(mx, tau, 10, a, e)
+    E0, B0, h = tom._yee_arrays(G, e0, G.C @ a0)
+    E1, B1 = maxwell.yee_fdtd(G.mesh.nel, h, G.c, tau, E0, B0, 10)
+    Eg, Bg, _ = tom._yee_arrays(G, e.cpu().numpy(), G.C @ a.cpu().numpy())
+    for x, y in zip(list(E1) + list(B1), list(Eg) + list(Bg)):
+        assert np.abs(x - y).max() <= 1e-13 * np.abs(x).max()
+    _close(gym, mesh, mx)
+
+
+@pytest.mark.parametrize("q1", ["lumped", "exact"])
+def test_cfl_on_gpu(g, q1):
+    # Proposition Stability: bounded at 0.9 tau_CFL, exponential growth at 1.1.
+    gym, ctx = g
+    mesh, mx, G = _setup(gym, ctx, (3, 3, 3), 1, q1, "exact")
+    tcfl = G.tau_cfl()
+    a0 = synth.random_vector(G.n, seed=11)
+    e0 = synth.random_vector(G.n, seed=12)
+    a, e = _t(a0), _t(e0)
+    H0 = gym.gym_maxwell_energy(mx, a, e)
+    gym.gym_maxwell_step(mx, 0.9 * tcfl, 300, a, e)
+    assert abs(gym.gym_maxwell_energy(mx, a, e) / H0 - 1) < 0.5
+    a, e = _t(a0), _t(e0)
+    gym.gym_maxwell_step(mx, 1.1 * tcfl, 60, a, e)
+    assert gym.gym_maxwell_energy(mx, a, e) / H0 > 1e3
+    _close(gym, mesh, mx)
+
+
+def test_eigenmode_phase_on_gpu(g):
+    # (a, e) = (0, M1 v) for a mode v of M1^-1 P2: <e(n), e(0)> = |e(0)|^2 cos(n theta),
+    # cos(theta) = 1 - tau^2 omega^2 / 2 (the Strang eigenvalue pair).
+    gym, ctx = g
+    mesh, mx, G = _setup(gym, ctx, (3, 2, 3), 2, "exact", "exact")
+    w2, v = G.eigenmode(0)
+    tau = 0.3 * G.tau_cfl()
+    theta = 2 * np.arcsin(tau * np.sqrt(w2) / 2)
+    e0 = G.M1 @ v
+    a, e = _t(np.zeros(G.n)), _t(e0)
+    e0t = _t(e0)
+    for n in range(1, 41):
+        gym.gym_maxwell_step(mx, tau, 1, a, e)
+        proj = float(torch.dot(e, e0t)) / float(e0 @ e0)
+        assert abs(proj - np.cos(n * theta)) < 1e-9, (n, proj, np.cos(n * theta))
+    _close(gym, mesh, mx)
+
+
+def test_errors(g):
+    gym, ctx = g
+    verts = synth.perturbed_vertices((2, 2, 2), 0.1, seed=1)
+    mesh = gym.gym_mesh_create(ctx, 3, (2, 2, 2), vertices=verts)
+    o = gym.gym_maxwell_opts_default()
+    o.q1 = gym.GYM_Q1_LUMPED
+    with pytest.raises(gym.GymError):
+        gym.gym_maxwell_create(ctx, mesh, 1, o)
+    o = gym.gym_maxwell_opts_default()
+    with pytest.raises(gym.GymError):
+        gym.gym_maxwell_create(ctx, mesh, 5, o)
+    mx = gym.gym_maxwell_create(ctx, mesh, 1, o)
+    n = gym.gym_maxwell_ndofs(mx)
+    a = torch.zeros(n, dtype=torch.float64, device=DEV)
+    with pytest.raises(gym.GymError):
+        gym.gym_maxwell_step(mx, -1.0, 1, a, a.clone())
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
