@@ -217,6 +217,35 @@ def workload_rates(gym, ctx, which, N, r, perturb, nrhs, steps, seed):
     return res
 
 
+def maxwell_rates(gym, ctx, N, r, q1, steps):
+    """Strang steps per second of the generalized Yee time stepping on an
+    N^3 unit box (perfect conductor), lumped or exact Q1, exact M2~ unless
+    Q1 is lumped (then both lumped: Yee's method for r = 1)."""
+    import torch
+    mesh = gym.gym_mesh_create(ctx, 3, (N, N, N))
+    o = gym.gym_maxwell_opts_default()
+    lumped = q1 == "lumped"
+    o.q1 = gym.GYM_Q1_LUMPED if lumped else gym.GYM_Q1_EXACT
+    o.m2 = gym.GYM_M2_LUMPED if lumped else gym.GYM_M2_EXACT
+    mx = gym.gym_maxwell_create(ctx, mesh, r, o)
+    n = gym.gym_maxwell_ndofs(mx)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(21)
+    a = torch.randn(n, dtype=torch.float64, device="cuda:0", generator=gen)
+    e = torch.randn(n, dtype=torch.float64, device="cuda:0", generator=gen)
+    # a step well inside the stability bound (2 / omega_max <= h / (c sqrt(3)) for Whitney; r^2 finer)
+    tau = 0.25 / (N * r * r)
+    gym.gym_maxwell_step(mx, tau, 2, a, e)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gym.gym_maxwell_step(mx, tau, steps, a, e)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+    return {"ndofs": n, "steps": steps, "steps_per_s": steps / wall, "gdof_steps_s": n * steps / wall / 1e9}
+
+
 # Sources of the operator kernel: the HBM traffic recorded under profiles/
 # (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) is reported only while these are
 # unchanged since the counters were taken.
@@ -447,6 +476,12 @@ def main():
         ext = {"poisson_r4_64cube": workload_rates(gym, ctx, "poisson", 64, 4, 0.0, 1, 200, 11)}
         log("extras: perturbed 96^3 degree-3 Hodge, 8 rhs ...")
         ext["hodge_r3_96cube_perturbed_8rhs"] = workload_rates(gym, ctx, "hodge", 96, 3, 0.15, 8, 30, 12)
+        log("extras: generalized Yee time stepping ...")
+        ext["gym_time_stepping"] = {
+            "yee_r1_128cube_lumped": maxwell_rates(gym, ctx, 128, 1, "lumped", 200),
+            "r2_32cube_lumped": maxwell_rates(gym, ctx, 32, 2, "lumped", 200),
+            "r2_32cube_exact_q1_cg": maxwell_rates(gym, ctx, 32, 2, "exact", 20),
+        }
         out["extras"] = ext
 
     if not args.no_cpu:
