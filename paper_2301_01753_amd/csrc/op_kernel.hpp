@@ -345,6 +345,17 @@ __device__ __forceinline__ double wg_sum(double v, double* sh) {
   return a[0];
 }
 
+// Most lattice values of one field a thread loads per layer.
+template <class C, class F>
+constexpr int max_per_thread() {
+  int m = 1;
+  for (int f = 0; f < F::NF; ++f) {
+    const int k = (C::lat(F::tm[f]) + C::NT - 1) / C::NT;
+    m = k > m ? k : m;
+  }
+  return m;
+}
+
 // ---- the kernel body -------------------------------------------------------
 // (bx, by, bz) = (tile, z-chunk, right-hand side) of this workgroup.
 template <class C, int PROB, int FORM, typename TV, typename TC, bool MR>
@@ -416,25 +427,68 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
   auto IN = [&](int f) { return smem + L::in_off(f); };
   auto OUT = [&](int f) { return smem + L::out_off(f); };
 
-  for (int ez = zbeg; ez < zend; ++ez) {
+  // Inputs of a layer are loaded into registers one layer ahead (a thread
+  // holds at most KMAX values per field), so the global loads of layer ez + 1
+  // are in flight while layer ez is computed.  Only for workgroups of up to
+  // 512 threads: wider ones are already at their register limit, and the
+  // extra registers spill to scratch (measured slower).
+  constexpr bool PREFETCH = C::NT <= 512;
+  constexpr int KMAX = PREFETCH ? max_per_thread<C, F>() : 1;
+  TC pre[F::NF][KMAX];
+  auto prefetch = [&](int ez) {
     const int gz0 = C::DIM == 3 ? R * ez : 0;
-    // ---- load inputs, zero outputs (and the cell vertices when curved)
     static_for<0, F::NF>([&](auto fc) {
       constexpr int f = decltype(fc)::value;
       constexpr int TM = F::tm[f];
+      constexpr int K = (C::lat(TM) + C::NT - 1) / C::NT;
       const DevComp& cd = sh_comp[f];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int i = threadIdx.x + k * C::NT;
+        TC v = 0;
+        if (i < C::lat(TM)) {
+          int lx, ly, lz;
+          lpos<C, TM>(i, lx, ly, lz);
+          int g0 = gx0 + lx - cd.start[0], g1 = gy0 + ly - cd.start[1], g2 = gz0 + lz - cd.start[2];
+          if (g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2])
+            v = static_cast<TC>(xin[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)]);
+        }
+        pre[f][k] = v;
+      }
+    });
+  };
+  if constexpr (PREFETCH) prefetch(zbeg);
+
+  for (int ez = zbeg; ez < zend; ++ez) {
+    const int gz0 = C::DIM == 3 ? R * ez : 0;
+    // ---- stage the inputs, zero outputs (and the cell vertices when curved)
+    static_for<0, F::NF>([&](auto fc) {
+      constexpr int f = decltype(fc)::value;
+      constexpr int TM = F::tm[f];
       TC* in = smem + L::in_off(f);
       TC* out = smem + L::out_off(f);
-      for (int i = threadIdx.x; i < C::lat(TM); i += C::NT) {
-        int lx, ly, lz;
-        lpos<C, TM>(i, lx, ly, lz);
-        int g0 = gx0 + lx - cd.start[0], g1 = gy0 + ly - cd.start[1], g2 = gz0 + lz - cd.start[2];
-        TC v = 0;
-        if (g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2]) {
-          v = static_cast<TC>(xin[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)]);
+      if constexpr (PREFETCH) {
+        constexpr int K = (C::lat(TM) + C::NT - 1) / C::NT;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const int i = threadIdx.x + k * C::NT;
+          if (i < C::lat(TM)) {
+            in[i] = pre[f][k];
+            out[i] = 0;
+          }
         }
-        in[i] = v;
-        out[i] = 0;
+      } else {
+        const DevComp& cd = sh_comp[f];
+        for (int i = threadIdx.x; i < C::lat(TM); i += C::NT) {
+          int lx, ly, lz;
+          lpos<C, TM>(i, lx, ly, lz);
+          int g0 = gx0 + lx - cd.start[0], g1 = gy0 + ly - cd.start[1], g2 = gz0 + lz - cd.start[2];
+          TC v = 0;
+          if (g0 >= 0 && g0 < cd.count[0] && g1 >= 0 && g1 < cd.count[1] && g2 >= 0 && g2 < cd.count[2])
+            v = static_cast<TC>(xin[cd.offset + g0 + (long long)cd.count[0] * (g1 + (long long)cd.count[1] * g2)]);
+          in[i] = v;
+          out[i] = 0;
+        }
       }
     });
     if constexpr (FORM == FORM_CURVED) {
@@ -452,6 +506,9 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
       }
     }
     __syncthreads();
+    if constexpr (PREFETCH) {
+      if (ez + 1 < zend) prefetch(ez + 1);
+    }
 
     if constexpr (PROB == PROB_HODGE) {
       TC* in_u[3] = {IN(1), IN(2), IN(3)};
