@@ -243,7 +243,13 @@ def maxwell_rates(gym, ctx, N, r, q1, steps):
     wall = time.perf_counter() - t0
     gym.gym_maxwell_destroy(mx)
     gym.gym_mesh_destroy(mesh)
-    return {"ndofs": n, "steps": steps, "steps_per_s": steps / wall, "gdof_steps_s": n * steps / wall / 1e9}
+    out = {"ndofs": n, "steps": steps, "steps_per_s": steps / wall, "gdof_steps_s": n * steps / wall / 1e9}
+    if lumped:
+        # one stencil kernel per step reads a and e and writes both: 32 B per unknown
+        out["kernel"] = "yee_kernel (fused lumped Strang step)"
+        out["algorithmic_gb_s"] = 32.0 * n * steps / wall / 1e9
+        out["hbm_frac"] = out["algorithmic_gb_s"] / PEAK_HBM_GBS
+    return out
 
 
 # Sources of the operator kernel: the HBM traffic recorded under profiles/
@@ -296,6 +302,8 @@ def main():
                     help="skip the 64^3 degree-4 Poisson and perturbed 96^3 degree-3 Hodge rates")
     ap.add_argument("--profile-apply", type=int, default=0,
                     help="counter runs: copy calibration + this many MINRES steps, no JSON")
+    ap.add_argument("--profile-maxwell", action="store_true",
+                    help="profiling runs: only the lumped time-stepping rates (Yee 128^3, degree 2 on 32^3), no JSON")
     ap.add_argument("--serve-requests", type=int, default=24,
                     help="requests in the serving sample (0 skips it)")
     args = ap.parse_args()
@@ -313,6 +321,11 @@ def main():
     dev = torch.device("cuda:0")
     nel, r = (args.nel,) * 3, args.degree
     ctx = gym.gym_create(0)
+    if args.profile_maxwell:
+        for N, deg in ((128, 1), (32, 2)):
+            log(f"lumped time stepping {N}^3 degree {deg}: {maxwell_rates(gym, ctx, N, deg, 'lumped', 2000)}")
+        gym.gym_destroy(ctx)
+        return
     mesh = gym.gym_mesh_create(ctx, 3, nel)
     op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, r)
     n = gym.gym_op_ndofs(op)
@@ -478,8 +491,8 @@ def main():
         ext["hodge_r3_96cube_perturbed_8rhs"] = workload_rates(gym, ctx, "hodge", 96, 3, 0.15, 8, 30, 12)
         log("extras: generalized Yee time stepping ...")
         ext["gym_time_stepping"] = {
-            "yee_r1_128cube_lumped": maxwell_rates(gym, ctx, 128, 1, "lumped", 200),
-            "r2_32cube_lumped": maxwell_rates(gym, ctx, 32, 2, "lumped", 200),
+            "yee_r1_128cube_lumped": maxwell_rates(gym, ctx, 128, 1, "lumped", 2000),
+            "r2_32cube_lumped": maxwell_rates(gym, ctx, 32, 2, "lumped", 2000),
             "r2_32cube_exact_q1_cg": maxwell_rates(gym, ctx, 32, 2, "exact", 20),
         }
         out["extras"] = ext

@@ -583,22 +583,28 @@ std::vector<double> mass_diag_host(const gym_space* sp) {
 // Lumped mass of an affine space: the row sums of its mass matrix without
 // boundary conditions, at the kept unknowns (Kronecker product of 1-D row
 // sums times the constant metric of the component).
+LumpedTables lumped_tables_host(const gym_space* sp) {
+  const gym_mesh* m = sp->mesh;
+  LumpedTables t;
+  for (int a = 0; a < 3; ++a) rowsum1d(sp->desc.r, a < m->dim ? m->nel[a] : 1, t.rn[a], t.re[a]);
+  for (int c = 0; c < 3; ++c) t.sc[c] = c < sp->desc.ncomp ? metric_const(sp->desc.kind, c, m) : 0.0;
+  return t;
+}
+
 std::vector<double> lumped_diag_host(const gym_space* sp) {
   const gym_mesh* m = sp->mesh;
   const SpaceDesc& s = sp->desc;
-  std::vector<double> rn[3], re[3];
-  for (int a = 0; a < 3; ++a) rowsum1d(s.r, a < m->dim ? m->nel[a] : 1, rn[a], re[a]);
+  const LumpedTables t = lumped_tables_host(sp);
   std::vector<double> out(s.ndofs);
   for (int c = 0; c < s.ncomp; ++c) {
     const CompDesc& cd = s.comp[c];
-    const double sc = metric_const(s.kind, c, m);
     int64_t idx = cd.offset;
     for (int64_t k = 0; k < cd.count[2]; ++k)
       for (int64_t j = 0; j < cd.count[1]; ++j)
         for (int64_t i = 0; i < cd.count[0]; ++i) {
           int64_t p[3] = {cd.start[0] + i, cd.start[1] + j, cd.start[2] + k};
-          double v = sc;
-          for (int a = 0; a < m->dim; ++a) v *= (cd.nodal_mask >> a & 1) ? rn[a][p[a]] : re[a][p[a]];
+          double v = t.sc[c];
+          for (int a = 0; a < m->dim; ++a) v *= (cd.nodal_mask >> a & 1) ? t.rn[a][p[a]] : t.re[a][p[a]];
           out[idx++] = v;
         }
   }

@@ -65,6 +65,14 @@ void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int&
 // Row sums of the mass matrix of an affine space without boundary
 // conditions, at its kept unknowns (canonical order).
 std::vector<double> lumped_diag_host(const gym_space* sp);
+// The same row sums in factored form: at lattice position p, component c has
+// sc[c] prod_a w_a(p_a), w_a = rn[a] (nodal along axis a, r N_a + 1 values)
+// or re[a] (edge, r N_a values); the product is taken in axis order.
+struct LumpedTables {
+  std::vector<double> rn[3], re[3];
+  double sc[3];
+};
+LumpedTables lumped_tables_host(const gym_space* sp);
 // y = A x; with `mr` the launch also carries that fused MINRES step.
 int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s,
                     const MrStep* mr = nullptr);

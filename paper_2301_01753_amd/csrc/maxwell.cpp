@@ -9,7 +9,9 @@
 //   a-update halved,
 // one Q1 and one P2 application per step.  P2 a = c^2 C^T M2~ C a runs as
 // incidence, mass apply (or lumped scaling), transposed incidence; Q1 e as a
-// CG mass solve (exact) or a diagonal scaling (lumped).
+// CG mass solve (exact) or a diagonal scaling (lumped).  With both masses
+// lumped the whole step is one stencil kernel (yee.hip), a ping-ponging
+// between the caller's vector and a work vector.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -17,6 +19,7 @@
 
 #include "gym_internal.hpp"
 #include "krylov.hpp"
+#include "yee.hpp"
 
 using namespace gym;
 
@@ -33,6 +36,8 @@ struct gym_maxwell {
   double *q = nullptr, *t = nullptr;      // n1: Q1 e, C^T M2~ C a
   double *b = nullptr, *mb = nullptr;     // n2: C a, M2~ C a
   double *part = nullptr, *sums = nullptr;
+  bool fused = false;  // both masses lumped: one stencil kernel per step
+  YeeParams yp{};      // its fixed parameters (1-D row sums in w)
 };
 
 namespace {
@@ -107,7 +112,20 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
   mx->n2 = gym_space_ndofs(mx->s2);
   mx->nb1 = vec_grid(mx->n1, ctx->ncu);
   mx->nb2 = vec_grid(mx->n2, ctx->ncu);
-  const size_t total = 3 * (size_t)mx->n1 + 3 * (size_t)mx->n2 + (size_t)mx->nb1 + 4;
+  const bool lumped = o.q1 == GYM_Q1_LUMPED && o.m2 == GYM_M2_LUMPED;
+  LumpedTables tab1, tab2;
+  long long npos = 1, nw = 0;
+  if (lumped) {
+    tab1 = lumped_tables_host(mx->s1);
+    tab2 = lumped_tables_host(mx->s2);
+    for (int a = 0; a < 3; ++a) {
+      npos *= (long long)tab1.rn[a].size();
+      nw += (long long)(tab1.rn[a].size() + tab1.re[a].size());
+    }
+  }
+  // one thread per lattice position, indexed in 32 bits
+  mx->fused = lumped && npos < (1LL << 31) - 256;
+  const size_t total = 3 * (size_t)mx->n1 + 3 * (size_t)mx->n2 + (size_t)mx->nb1 + 4 + (mx->fused ? nw : 0);
   if (hipMalloc(&mx->mem, sizeof(double) * total) != hipSuccess) {
     (void)hipGetLastError();
     gym_maxwell_destroy(mx);
@@ -121,7 +139,34 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
   mx->b = p, p += mx->n2;
   mx->mb = p, p += mx->n2;
   mx->part = p, p += mx->nb1;
-  mx->sums = p;
+  mx->sums = p, p += 4;
+  if (mx->fused) {
+    YeeParams& y = mx->yp;
+    std::vector<double> w;
+    for (int a = 0; a < 3; ++a) {
+      y.wn[a] = (int)w.size();
+      w.insert(w.end(), tab1.rn[a].begin(), tab1.rn[a].end());
+      y.we[a] = (int)w.size();
+      w.insert(w.end(), tab1.re[a].begin(), tab1.re[a].end());
+      y.len[a] = (int)tab1.rn[a].size();
+      y.q1s[a] = tab1.sc[a];
+      y.m2s[a] = tab2.sc[a];
+    }
+    y.w = p;
+    y.npos = (unsigned)npos;
+    const SpaceDesc& d = mx->s1->desc;
+    for (int c = 0; c < 3; ++c) {
+      y.s1.c[c].offset = d.comp[c].offset;
+      for (int a = 0; a < 3; ++a) {
+        y.s1.c[c].start[a] = (int)d.comp[c].start[a];
+        y.s1.c[c].count[a] = (int)d.comp[c].count[a];
+      }
+    }
+    if (hipMemcpy(p, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      gym_maxwell_destroy(mx);
+      return fail(GYM_E_HIP, "time stepping: upload failed");
+    }
+  }
   if (o.q1 == GYM_Q1_LUMPED) {
     std::vector<double> d = lumped_diag_host(mx->s1);
     for (double& v : d) v = 1.0 / v;
@@ -148,6 +193,26 @@ int gym_maxwell_step(gym_maxwell* mx, double tau, int nsteps, double* a, double*
   if (nsteps == 0) return GYM_OK;
   hipStream_t s = (hipStream_t)stream;
   const double c2 = mx->o.c * mx->o.c;
+  if (mx->fused) {
+    // a lives in buf[(nsteps - k) & 1] after k steps, so in the caller's
+    // vector at the end
+    double* buf[2] = {a, mx->t};
+    YeeParams p = mx->yp;
+    p.e = e;
+    p.te = tau * c2;
+    p.a_in = a;
+    p.a_out = buf[nsteps & 1];
+    p.ha = 0.5 * tau;
+    if (launch_yee(p, true, s)) return fail(GYM_E_HIP, "time stepping: kernel launch failed");
+    for (int k = 0; k < nsteps; ++k) {
+      p.a_in = buf[(nsteps - k) & 1];
+      p.a_out = buf[(nsteps - k - 1) & 1];
+      p.ha = (k == nsteps - 1) ? 0.5 * tau : tau;
+      if (launch_yee(p, false, s)) return fail(GYM_E_HIP, "time stepping: kernel launch failed");
+    }
+    GYM_HIP(hipGetLastError());
+    return GYM_OK;
+  }
   int warn = 0;
   if (int rc = apply_q1(mx, e, mx->q, s, &warn)) return rc;
   launch_axpy_diag(a, 1.0, -0.5 * tau, nullptr, mx->q, mx->n1, mx->nb1, s);

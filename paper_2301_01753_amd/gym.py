@@ -121,6 +121,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2301_01753_amd.build")
+        # torch ships its own HIP runtime under the same soname as the one
+        # libgym links.  Loaded first, torch's copy serves both; loaded after
+        # libgym it would start a second runtime that finds no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)

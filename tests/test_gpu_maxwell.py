@@ -1,7 +1,9 @@
 """GPU parity of the generalized Yee time stepping (gym_maxwell_*) with the oracle.
 
 The GPU merges the two half steps in a between consecutive Strang steps;
-the oracle applies every half step literally.  Lumped masses: the two differ
+the oracle applies every half step literally.  With both masses lumped a
+whole step is one stencil kernel; those cases run every degree, odd and
+even step counts, and the full 128^3 Yee lattice.  Lumped masses: the two differ
 by rounding only (1e-13 of the state's scale).  Exact Q1: every M1 solve is a
 CG solve to 1e-14, so the trajectories agree to 1e-10 after a few steps.
 """
@@ -88,6 +90,62 @@ def test_yee_leapfrog_on_gpu(g):
     E0, B0, h = tom._yee_arrays(G, e0, G.C @ a0)
     E1, B1 = maxwell.yee_fdtd(G.mesh.nel, h, G.c, tau, E0, B0, 10)
     Eg, Bg, _ = tom._yee_arrays(G, e.cpu().numpy(), G.C @ a.cpu().numpy())
+    for x, y in zip(list(E1) + list(B1), list(Eg) + list(Bg)):
+        assert np.abs(x - y).max() <= 1e-13 * np.abs(x).max()
+    _close(gym, mesh, mx)
+
+
+LUMPED = [((3, 2, 3), 2, 0.9, (1.0, 1.1, 1.0)), ((2, 3, 2), 3, 1.0, (1.0, 1.0, 1.0)),
+          ((2, 2, 3), 4, 1.2, (0.8, 1.0, 1.0)), ((5, 3, 4), 1, 1.0, (1.0, 1.0, 1.0))]
+
+
+@pytest.mark.parametrize("nel,r,c,hi", LUMPED)
+@pytest.mark.parametrize("nsteps", [0, 1, 2, 5])
+def test_lumped_steps_every_degree(g, nel, r, c, hi, nsteps):
+    # Both masses lumped: one stencil kernel per step on the degree-r lattice;
+    # odd and even step counts end the ping-pong of a in different buffers.
+    gym, ctx = g
+    mesh, mx, G = _setup(gym, ctx, nel, r, "lumped", "lumped", c, hi)
+    a0 = synth.random_vector(G.n, seed=13 + nsteps)
+    e0 = synth.random_vector(G.n, seed=14 + nsteps)
+    tau = 0.7 * G.tau_cfl()
+    a, e = _t(a0), _t(e0)
+    gym.gym_maxwell_step(mx, tau, nsteps, a, e)
+    ar, er = G.strang(a0, e0, tau, nsteps)
+    for got, ref in ((a, ar), (e, er)):
+        err = np.abs(got.cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err < 1e-13, err
+    _close(gym, mesh, mx)
+
+
+def test_yee_128cube_full_size(g):
+    # Yee's method at its benchmark size, 128^3 cells (6.2 M unknowns): the
+    # GPU against Yee's finite differences on the whole lattice (the finite
+    # differences are pinned to the oracle's lumped Whitney steps at small
+    # sizes by the oracle tests).
+    import types
+    import test_oracle_maxwell as tom
+    from oracle import incidence
+    from oracle.lattice import Mesh, Space
+    gym, ctx = g
+    N, c, nsteps = 128, 1.0, 6
+    print(f"yee {N}^3: {nsteps} steps", flush=True)
+    mesh = gym.gym_mesh_create(ctx, 3, (N, N, N))
+    o = gym.gym_maxwell_opts_default()
+    o.q1, o.m2, o.c = gym.GYM_Q1_LUMPED, gym.GYM_M2_LUMPED, c
+    mx = gym.gym_maxwell_create(ctx, mesh, 1, o)
+    G = types.SimpleNamespace(mesh=Mesh(synth.uniform_vertices((N, N, N))),
+                              s1=Space("HCURL", (N, N, N), 1, "essential"), s2=Space("HDIV", (N, N, N), 1, "natural"))
+    assert gym.gym_maxwell_ndofs(mx) == G.s1.ndofs
+    C = incidence.curl(G.s1, G.s2).astype(np.float64).tocsr()
+    a0 = synth.random_vector(G.s1.ndofs, seed=15)
+    e0 = synth.random_vector(G.s1.ndofs, seed=16)
+    tau = 0.5 / (N * c * np.sqrt(3.0))
+    a, e = _t(a0), _t(e0)
+    gym.gym_maxwell_step(mx, tau, nsteps, a, e)
+    E0, B0, h = tom._yee_arrays(G, e0, C @ a0)
+    E1, B1 = maxwell.yee_fdtd((N, N, N), h, c, tau, E0, B0, nsteps)
+    Eg, Bg, _ = tom._yee_arrays(G, e.cpu().numpy(), C @ a.cpu().numpy())
     for x, y in zip(list(E1) + list(B1), list(Eg) + list(Bg)):
         assert np.abs(x - y).max() <= 1e-13 * np.abs(x).max()
     _close(gym, mesh, mx)
