@@ -782,23 +782,50 @@ struct TileSel {
 };
 
 // Tiles and z-chunks of one operator for tile size B; returns the number of
-// workgroups (tiles x chunks x nrhs).
-inline int op_tiling(OpParams& p, int B, int dim, int nrhs, int ncu) {
+// workgroups (tiles x chunks x nrhs).  A chunk of c element layers costs its
+// workgroup c + 1 layers (the halo layer below it is recomputed), except the
+// bottom chunk.  Modes:
+//   kTileWhole  whole-CU tiles, `occ` workgroups per CU (one in FP64, two
+//               for some FP32 kernels): the launch runs in
+//               ceil(workgroups / (occ ncu)) rounds of one chunk each, so the
+//               chunk minimises rounds x (c + 1), a cost that tracks the
+//               measured kernel times on MI355X.
+//   kTileSmall  40 KB tiles, several workgroups per CU: about four
+//               workgroups per CU, chunks of at least two layers.
+//   kTileBatch  the ragged serving batch, where many requests fill the GPU
+//               together: about two workgroups per CU and request, chunks of
+//               at least four layers.
+enum { kTileWhole = 0, kTileSmall = 1, kTileBatch = 2 };
+inline int op_tiling(OpParams& p, int B, int dim, int nrhs, int ncu, int mode, int occ = 1) {
   p.tiles_x = (p.nel[0] + B - 1) / B;
   p.tiles_y = (p.nel[1] + B - 1) / B;
   const int nt = p.tiles_x * p.tiles_y;
   int nchunks = 1;
   p.chunk = 1;
   if (dim == 3) {
-    // enough workgroups for two per CU, but chunks of at least 4 layers so
-    // that the recomputed halo layer costs at most a quarter
-    const int target = 2 * ncu;
-    nchunks = (target + nt * nrhs - 1) / (nt * nrhs);
-    int maxch = p.nel[2] / 4;
-    if (nchunks > maxch) nchunks = maxch;
-    if (nchunks < 1) nchunks = 1;
-    p.chunk = (p.nel[2] + nchunks - 1) / nchunks;
-    nchunks = (p.nel[2] + p.chunk - 1) / p.chunk;
+    const int nz = p.nel[2];
+    if (mode == kTileWhole) {
+      long long best = -1;
+      for (int c = 1; c <= nz; ++c) {
+        const int nch = (nz + c - 1) / c;
+        if ((nz + nch - 1) / nch != c) continue;  // the same split as a smaller c
+        const long long slots = (long long)occ * ncu;
+        const long long rounds = ((long long)nt * nrhs * nch + slots - 1) / slots;
+        const long long cost = rounds * (c + (nch > 1 ? 1 : 0));
+        if (best < 0 || cost < best) {
+          best = cost;
+          p.chunk = c;
+        }
+      }
+    } else {
+      const int target = (mode == kTileSmall ? 4 : 2) * ncu;
+      nchunks = (target + nt * nrhs - 1) / (nt * nrhs);
+      int maxch = nz / (mode == kTileSmall ? 2 : 4);
+      if (nchunks > maxch) nchunks = maxch;
+      if (nchunks < 1) nchunks = 1;
+      p.chunk = (nz + nchunks - 1) / nchunks;
+    }
+    nchunks = (nz + p.chunk - 1) / p.chunk;
   }
   p.nchunks = nchunks;
   return nt * nchunks * nrhs;
@@ -820,15 +847,39 @@ constexpr int big_threads() {
   return R == 2 ? 768 : 1024;
 }
 
-template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, int BUDGET, bool MR>
-int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
-  constexpr int B = TileSel<DIM, R, PROB, FORM, TC, BUDGET>::B;
+template <int DIM, int R, int PROB, int FORM, typename TC, int BUDGET>
+struct OpCfg {
+  static constexpr int B = TileSel<DIM, R, PROB, FORM, TC, BUDGET>::B;
   // one workgroup per CU on the whole-CU budget: widen it to keep enough
   // waves in flight to hide LDS latency
   using C = Cfg<R, B, B, DIM, (BUDGET > 40 * 1024 ? big_threads<DIM, R, PROB, FORM, TC>() : kNTSmall)>;
+};
+
+// Workgroups of one operator kernel that fit on a CU at once (LDS, waves and
+// registers), asked of the runtime once per kernel.
+template <class C, int PROB, int FORM, typename TV, typename TC, bool MR>
+int op_occupancy() {
+  static const int occ = [] {
+    int k = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, reinterpret_cast<const void*>(&op_kernel<C, PROB, FORM, TV, TC, MR>),
+                                                     C::NT, 0) != hipSuccess) {
+      (void)hipGetLastError();
+      k = 1;
+    }
+    return k < 1 ? 1 : k;
+  }();
+  return occ;
+}
+
+template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, int BUDGET, bool MR>
+int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
+  using OC = OpCfg<DIM, R, PROB, FORM, TC, BUDGET>;
+  constexpr int B = OC::B;
+  using C = typename OC::C;
   static_assert(Layout<C, Fields<PROB, DIM>, FORM>::total() * sizeof(TC) <= 160 * 1024, "LDS");
   OpParams p = p0;
-  op_tiling(p, B, DIM, nrhs, ncu);
+  if constexpr (BUDGET > 40 * 1024) op_tiling(p, B, DIM, nrhs, ncu, kTileWhole, op_occupancy<C, PROB, FORM, TV, TC, MR>());
+  else op_tiling(p, B, DIM, nrhs, ncu, kTileSmall);
   if (p0.wg_out) *p0.wg_out = p.tiles_x * p.tiles_y * p.nchunks;
   if (p0.dry) return 0;
   dim3 grid(p.tiles_x * p.tiles_y, p.nchunks, nrhs);
@@ -844,7 +895,7 @@ int launch_op_batch_r(OpParams* plist_host, int* bstart_host, int nreq, OpParams
   constexpr int B = TileSel<DIM, R, PROB, FORM_KRON, TC, 40 * 1024>::B;
   using C = Cfg<R, B, B, DIM>;
   bstart_host[0] = 0;
-  for (int i = 0; i < nreq; ++i) bstart_host[i + 1] = bstart_host[i] + op_tiling(plist_host[i], B, DIM, 1, ncu);
+  for (int i = 0; i < nreq; ++i) bstart_host[i + 1] = bstart_host[i] + op_tiling(plist_host[i], B, DIM, 1, ncu, kTileBatch);
   if (hipMemcpyAsync(plist_dev, plist_host, sizeof(OpParams) * nreq, hipMemcpyHostToDevice, stream) != hipSuccess)
     return -1;
   if (hipMemcpyAsync(bstart_dev, bstart_host, sizeof(int) * (nreq + 1), hipMemcpyHostToDevice, stream) != hipSuccess)
@@ -854,15 +905,18 @@ int launch_op_batch_r(OpParams* plist_host, int* bstart_host, int nreq, OpParams
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Tile budget 0: whole-CU tiles; 1: small tiles; 2: whole-CU tiles when they
-// still give every CU a workgroup, small tiles otherwise (small meshes).
+// Tile budget 0: whole-CU tiles; 1: small tiles; 2: whole-CU tiles when their
+// best chunking fills at least half of the slots they have on the GPU, small
+// tiles otherwise (small meshes).
 template <int DIM, int R, int PROB, int FORM, typename TV, typename TC, bool MR>
 int launch_form(const OpParams& p, int nrhs, int ncu, hipStream_t stream) {
   constexpr int kBig = 160 * 1024, kSmall = 40 * 1024;
   bool large = p.tile_budget == 0;
   if (p.tile_budget == 2) {
+    using OC = OpCfg<DIM, R, PROB, FORM, TC, kBig>;
+    const int occ = op_occupancy<typename OC::C, PROB, FORM, TV, TC, MR>();
     OpParams q = p;
-    large = op_tiling(q, TileSel<DIM, R, PROB, FORM, TC, kBig>::B, DIM, nrhs, ncu) >= ncu;
+    large = 2 * op_tiling(q, OC::B, DIM, nrhs, ncu, kTileWhole, occ) >= occ * ncu;
   }
   if (large) return launch_op_b<DIM, R, PROB, FORM, TV, TC, kBig, MR>(p, nrhs, ncu, stream);
   return launch_op_b<DIM, R, PROB, FORM, TV, TC, kSmall, MR>(p, nrhs, ncu, stream);
