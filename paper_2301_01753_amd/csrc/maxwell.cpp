@@ -203,12 +203,12 @@ int gym_maxwell_step(gym_maxwell* mx, double tau, int nsteps, double* a, double*
     p.a_in = a;
     p.a_out = buf[nsteps & 1];
     p.ha = 0.5 * tau;
-    if (launch_yee(p, true, s)) return fail(GYM_E_HIP, "time stepping: kernel launch failed");
+    if (launch_yee(p, true, mx->ctx->ncu, s)) return fail(GYM_E_HIP, "time stepping: kernel launch failed");
     for (int k = 0; k < nsteps; ++k) {
       p.a_in = buf[(nsteps - k) & 1];
       p.a_out = buf[(nsteps - k - 1) & 1];
       p.ha = (k == nsteps - 1) ? 0.5 * tau : tau;
-      if (launch_yee(p, false, s)) return fail(GYM_E_HIP, "time stepping: kernel launch failed");
+      if (launch_yee(p, false, mx->ctx->ncu, s)) return fail(GYM_E_HIP, "time stepping: kernel launch failed");
     }
     GYM_HIP(hipGetLastError());
     return GYM_OK;

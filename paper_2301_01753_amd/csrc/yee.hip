@@ -3,18 +3,20 @@
 // On the refined lattice of a degree-r space (r N_d cells per axis, integral
 // unknowns) the incidence C is the lattice curl, and the lumped M1 and M2~
 // are diagonal.  So the P2 shear e += tau c^2 C^T M2~ C a and the Q1 shear
-// a -= h Q1 e of one Strang step form a single stencil.  One thread per
-// lattice position p holds the (up to three) Lambda^1 unknowns at p.  It forms
-// the nine face circulations b = C a that they bound, weights each by its
-// lumped face mass, applies C^T, and updates e and then a at p.  Neighbours
-// read a, so a goes from one buffer into another.  The lumped diagonals are
-// recomputed from their 1-D row-sum factors, so a step moves a and e in and
-// out once: 32 bytes per unknown.
+// a -= h Q1 e of one Strang step form a single stencil: at each lattice
+// position the (up to three) Lambda^1 unknowns bound nine faces; their
+// circulations b = C a, weighted by the lumped face masses, give C^T M2~ C a
+// at the position, and e and then a are updated there.  Neighbours read a, so
+// a goes from one buffer into another.  The lumped diagonals are recomputed
+// from their 1-D row-sum factors, so a step moves a and e in and out once:
+// 32 bytes per unknown.
 //
 // Blocks are renumbered so that the blocks one XCD runs (hardware dispatch
 // hands block b to XCD b mod 8) cover one contiguous range of z-planes: the
 // neighbour planes a block reads are then mostly in that XCD's own L2.
 #include "yee.hpp"
+
+#include <type_traits>
 
 namespace gym {
 namespace {
@@ -27,6 +29,13 @@ __device__ __forceinline__ bool kept(const DevComp& c, int x, int y, int z) {
 __device__ __forceinline__ long long at(const DevComp& c, int x, int y, int z) {
   return c.offset + (x - c.start[0]) +
          (long long)c.count[0] * ((y - c.start[1]) + (long long)c.count[1] * (z - c.start[2]));
+}
+
+template <class Fn>
+__device__ __forceinline__ void static_for_comp(Fn&& fn) {
+  fn(std::integral_constant<int, 0>{});
+  fn(std::integral_constant<int, 1>{});
+  fn(std::integral_constant<int, 2>{});
 }
 
 // a_c at lattice position (x, y, z); zero at the unknowns the conductor removes
@@ -48,71 +57,144 @@ __device__ __forceinline__ double lumped(const YeeParams& p, double sc, int x, i
   return v;
 }
 
-// (M2~ C a) on the face of component C at (x, y, z):
-// b_C = (a_C2(q + e_C1) - a_C2(q)) - (a_C1(q + e_C2) - a_C1(q)), C1 = C + 1, C2 = C + 2 (mod 3).
-template <int C>
-__device__ __forceinline__ double face(const YeeParams& p, int x, int y, int z) {
-  constexpr int C1 = (C + 1) % 3, C2 = (C + 2) % 3;
-  const double b = (lda<C2>(p, x + (C1 == 0), y + (C1 == 1), z + (C1 == 2)) - lda<C2>(p, x, y, z)) -
-                   (lda<C1>(p, x + (C2 == 0), y + (C2 == 1), z + (C2 == 2)) - lda<C1>(p, x, y, z));
-  return lumped<1 << C>(p, p.m2s[C], x, y, z) * b;
-}
-
-template <int C, bool HALF>
-__device__ __forceinline__ void update(const YeeParams& p, int x, int y, int z, double t) {
-  const long long i = at(p.s1.c[C], x, y, z);
-  double ev = p.e[i];
-  if constexpr (!HALF) {
-    ev = fma(p.te, t, ev);
-    p.e[i] = ev;
-  }
-  const double q = ev * (1.0 / lumped<7 & ~(1 << C)>(p, p.q1s[C], x, y, z));
-  p.a_out[i] = fma(-p.ha, q, p.a_in[i]);
-}
-
-template <bool HALF>
-__global__ void __launch_bounds__(256) yee_kernel(const YeeParams p) {
-  const unsigned nb = gridDim.x, b = blockIdx.x, xcd = b & 7u;
-  const unsigned per = nb >> 3, rem = nb & 7u;
-  const unsigned blk = xcd * per + min(xcd, rem) + (b >> 3);
-  const unsigned t = blk * 256u + threadIdx.x;
+// The first half step in a, a <- a - ha Q1 e: pointwise, one thread per lattice position.
+__global__ void __launch_bounds__(256) yee_half_kernel(const YeeParams p) {
+  const unsigned t = blockIdx.x * 256u + threadIdx.x;
   if (t >= p.npos) return;
   const unsigned row = t / (unsigned)p.len[0];
   const int x = (int)(t - row * (unsigned)p.len[0]);
   const int z = (int)(row / (unsigned)p.len[1]);
   const int y = (int)(row - (unsigned)z * (unsigned)p.len[1]);
-  const bool k0 = kept(p.s1.c[0], x, y, z), k1 = kept(p.s1.c[1], x, y, z), k2 = kept(p.s1.c[2], x, y, z);
-  if (!(k0 || k1 || k2)) return;
-  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-  if constexpr (!HALF) {
-    // C^T h at p (h = M2~ C a): each Lambda^1 unknown bounds four faces.  A
-    // face is formed only when an unknown kept at p needs it; those faces all
-    // exist in Lambda^2.
-    const double hx = (k1 || k2) ? face<0>(p, x, y, z) : 0.0;
-    const double hx_z = k1 ? face<0>(p, x, y, z - 1) : 0.0;
-    const double hx_y = k2 ? face<0>(p, x, y - 1, z) : 0.0;
-    const double hy = (k0 || k2) ? face<1>(p, x, y, z) : 0.0;
-    const double hy_z = k0 ? face<1>(p, x, y, z - 1) : 0.0;
-    const double hy_x = k2 ? face<1>(p, x - 1, y, z) : 0.0;
-    const double hz = (k0 || k1) ? face<2>(p, x, y, z) : 0.0;
-    const double hz_y = k0 ? face<2>(p, x, y - 1, z) : 0.0;
-    const double hz_x = k1 ? face<2>(p, x - 1, y, z) : 0.0;
-    t0 = (hz - hz_y) - (hy - hy_z);
-    t1 = (hx - hx_z) - (hz - hz_x);
-    t2 = (hy - hy_x) - (hx - hx_y);
+  static_for_comp([&](auto cc) {
+    constexpr int C = decltype(cc)::value;
+    const DevComp& d = p.s1.c[C];
+    if (!kept(d, x, y, z)) return;
+    const long long i = at(d, x, y, z);
+    const double q = p.e[i] * (1.0 / lumped<7 & ~(1 << C)>(p, p.q1s[C], x, y, z));
+    p.a_out[i] = fma(-p.ha, q, p.a_in[i]);
+  });
+}
+
+// 1-D lumped factor along axis D at lattice index i, nodal (i in [0, M_D]) or
+// edge (i in [0, M_D)); zero where no such position exists.
+template <int D, bool NODAL>
+__device__ __forceinline__ double wfac(const YeeParams& p, int i) {
+  const int m = p.len[D] - 1;
+  if constexpr (NODAL) return (i >= 0 && i <= m) ? p.w[p.wn[D] + i] : 0.0;
+  else return (i >= 0 && i < m) ? p.w[p.we[D] + i] : 0.0;
+}
+
+// A full Strang step, one thread per lattice column (x, y) and chunk of
+// z-planes.  Going up the column, the thread carries a_x and a_y of its own
+// column and of the columns at x - 1 and y - 1 from plane z + 1 to plane z,
+// and the circulations of its x- and y-faces from plane z to the plane above,
+// where they are the faces below.  Per plane it loads 15 values of a (its own
+// a_z, and a of the neighbouring columns the nine faces reach), forms seven
+// faces, applies C^T to the four faces around each of its unknowns, and
+// updates e and a.  The x-y factors of the lumped masses are fixed along a
+// column.  Neighbouring threads are neighbouring x, so every load and store
+// of a wave is one contiguous row segment.
+__global__ void __launch_bounds__(256) yee_column_kernel(const YeeParams p, int zc, unsigned ncol, unsigned nthr) {
+  const unsigned nb = gridDim.x, b = blockIdx.x, xcd = b & 7u;
+  const unsigned per = nb >> 3, rem = nb & 7u;
+  const unsigned blk = xcd * per + min(xcd, rem) + (b >> 3);
+  const unsigned t = blk * 256u + threadIdx.x;
+  if (t >= nthr) return;
+  const unsigned zch = t / ncol;
+  const unsigned col = t - zch * ncol;
+  const int x = (int)(col % (unsigned)p.len[0]);
+  const int y = (int)(col / (unsigned)p.len[0]);
+  const int z0 = (int)zch * zc;
+  const int z1 = min(z0 + zc, p.len[2]);
+  const DevComp& d0 = p.s1.c[0];
+  const DevComp& d1 = p.s1.c[1];
+  const DevComp& d2 = p.s1.c[2];
+  auto okxy = [&](const DevComp& d, int dx, int dy) {
+    return (unsigned)(x + dx - d.start[0]) < (unsigned)d.count[0] &&
+           (unsigned)(y + dy - d.start[1]) < (unsigned)d.count[1];
+  };
+  auto idx = [&](const DevComp& d, int dx, int dy, int z) {
+    return d.offset + (x + dx - d.start[0]) +
+           (long long)d.count[0] * ((y + dy - d.start[1]) + (long long)d.count[1] * (z - d.start[2]));
+  };
+  // a of component d in column (x + dx, y + dy) at plane z; zero at removed unknowns
+  auto A = [&](const DevComp& d, int dx, int dy, int z) {
+    return (okxy(d, dx, dy) && (unsigned)(z - d.start[2]) < (unsigned)d.count[2]) ? p.a_in[idx(d, dx, dy, z)] : 0.0;
+  };
+  // x-y factors of the face masses (component: nodal along itself, edge along the others)
+  const double rnx = wfac<0, true>(p, x), rex = wfac<0, false>(p, x), rexm = wfac<0, false>(p, x - 1);
+  const double rny = wfac<1, true>(p, y), rey = wfac<1, false>(p, y), reym = wfac<1, false>(p, y - 1);
+  const double whx = p.m2s[0] * rnx * rey, whx_y = p.m2s[0] * rnx * reym;
+  const double why = p.m2s[1] * rex * rny, why_x = p.m2s[1] * rexm * rny;
+  const double whz = p.m2s[2] * rex * rey, whz_y = p.m2s[2] * rex * reym, whz_x = p.m2s[2] * rexm * rey;
+  // x-y factors of the edge masses (component: edge along itself, nodal along the others)
+  const double wq0 = p.q1s[0] * rex * rny, wq1 = p.q1s[1] * rnx * rey, wq2 = p.q1s[2] * rnx * rny;
+  const bool own0 = okxy(d0, 0, 0), own1 = okxy(d1, 0, 0), own2 = okxy(d2, 0, 0);
+
+  double ax = A(d0, 0, 0, z0), ay = A(d1, 0, 0, z0);  // a_x, a_y of this column at plane z
+  double axm = A(d0, -1, 0, z0), aym = A(d1, 0, -1, z0);  // a_x at x - 1, a_y at y - 1
+  double hxb = 0.0, hyb = 0.0;  // x- and y-faces of this column below plane z
+  if (z0 > 0) {
+    const int zb = z0 - 1;
+    const double reb = wfac<2, false>(p, zb), azb = A(d2, 0, 0, zb);
+    hxb = whx * reb * ((A(d2, 0, 1, zb) - azb) - (ay - A(d1, 0, 0, zb)));
+    hyb = why * reb * ((ax - A(d0, 0, 0, zb)) - (A(d2, 1, 0, zb) - azb));
   }
-  if (k0) update<0, HALF>(p, x, y, z, t0);
-  if (k1) update<1, HALF>(p, x, y, z, t1);
-  if (k2) update<2, HALF>(p, x, y, z, t2);
+  for (int z = z0; z < z1; ++z) {
+    const double rez = wfac<2, false>(p, z), rnz = wfac<2, true>(p, z);
+    const double az = A(d2, 0, 0, z);
+    const double axu = A(d0, 0, 0, z + 1), ayu = A(d1, 0, 0, z + 1);
+    const double axmu = A(d0, -1, 0, z + 1), aymu = A(d1, 0, -1, z + 1);
+    const double az_xm = A(d2, -1, 0, z), ay_xm = A(d1, -1, 0, z);
+    const double az_ym = A(d2, 0, -1, z), ax_ym = A(d0, 0, -1, z);
+    const double az_xp = A(d2, 1, 0, z), ay_xp = A(d1, 1, 0, z);
+    const double az_yp = A(d2, 0, 1, z), ax_yp = A(d0, 0, 1, z);
+    const double ay_xp_ym = A(d1, 1, -1, z), ax_xm_yp = A(d0, -1, 1, z);
+    // faces at (x, y, z) and at the neighbours the unknowns of (x, y, z) bound
+    const double hx = whx * rez * ((az_yp - az) - (ayu - ay));
+    const double hy = why * rez * ((axu - ax) - (az_xp - az));
+    const double hz = whz * rnz * ((ay_xp - ay) - (ax_yp - ax));
+    const double hx_y = whx_y * rez * ((az - az_ym) - (aymu - aym));
+    const double hy_x = why_x * rez * ((axmu - axm) - (az - az_xm));
+    const double hz_y = whz_y * rnz * ((ay_xp_ym - aym) - (ax - ax_ym));
+    const double hz_x = whz_x * rnz * ((ay - ay_xm) - (ax_xm_yp - axm));
+    const double tv[3] = {(hz - hz_y) - (hy - hyb), (hx - hxb) - (hz - hz_x), (hy - hy_x) - (hx - hx_y)};
+    const double av[3] = {ax, ay, az};
+    const double wq[3] = {wq0 * rnz, wq1 * rnz, wq2 * rez};
+    const bool own[3] = {own0, own1, own2};
+    static_for_comp([&](auto cc) {
+      constexpr int C = decltype(cc)::value;
+      const DevComp& d = p.s1.c[C];
+      if (!own[C] || (unsigned)(z - d.start[2]) >= (unsigned)d.count[2]) return;
+      const long long i = idx(d, 0, 0, z);
+      const double ev = fma(p.te, tv[C], p.e[i]);
+      p.e[i] = ev;
+      p.a_out[i] = fma(-p.ha, ev * (1.0 / wq[C]), av[C]);
+    });
+    hxb = hx;
+    hyb = hy;
+    ax = axu;
+    ay = ayu;
+    axm = axmu;
+    aym = aymu;
+  }
 }
 
 }  // namespace
 
-int launch_yee(const YeeParams& p, bool half, hipStream_t s) {
+int launch_yee(const YeeParams& p, bool half, int ncu, hipStream_t s) {
   if (p.npos == 0) return 0;
-  const unsigned blocks = (p.npos + 255u) / 256u;
-  if (half) hipLaunchKernelGGL(yee_kernel<true>, dim3(blocks), dim3(256), 0, s, p);
-  else hipLaunchKernelGGL(yee_kernel<false>, dim3(blocks), dim3(256), 0, s, p);
+  if (half) {
+    hipLaunchKernelGGL(yee_half_kernel, dim3((p.npos + 255u) / 256u), dim3(256), 0, s, p);
+  } else {
+    // z-chunks short enough for about four blocks per CU, 2..32 planes long
+    const unsigned ncol = (unsigned)p.len[0] * (unsigned)p.len[1];
+    long long zc = (long long)p.npos / (4LL * ncu * 256);
+    zc = zc < 2 ? 2 : (zc > 32 ? 32 : zc);
+    const unsigned nzc = (unsigned)((p.len[2] + zc - 1) / zc);
+    const unsigned nthr = ncol * nzc;
+    hipLaunchKernelGGL(yee_column_kernel, dim3((nthr + 255u) / 256u), dim3(256), 0, s, p, (int)zc, ncol, nthr);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -25,7 +25,8 @@ struct YeeParams {
 };
 
 // half: only a_out = a_in - ha Q1 e (the first half step in a); else a full
-// step e += te C^T M2~ C a_in, a_out = a_in - ha Q1 e.
-int launch_yee(const YeeParams& p, bool half, hipStream_t s);
+// step e += te C^T M2~ C a_in, a_out = a_in - ha Q1 e.  ncu: compute units
+// (sizes the z-chunks of the full step).
+int launch_yee(const YeeParams& p, bool half, int ncu, hipStream_t s);
 
 }  // namespace gym
