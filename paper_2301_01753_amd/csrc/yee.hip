@@ -113,14 +113,21 @@ __global__ void __launch_bounds__(256) yee_column_kernel(const YeeParams p, int 
     return (unsigned)(x + dx - d.start[0]) < (unsigned)d.count[0] &&
            (unsigned)(y + dy - d.start[1]) < (unsigned)d.count[1];
   };
+  // index within the component block (a component has fewer than 2^31
+  // unknowns: the host launches this kernel only then)
   auto idx = [&](const DevComp& d, int dx, int dy, int z) {
-    return d.offset + (x + dx - d.start[0]) +
-           (long long)d.count[0] * ((y + dy - d.start[1]) + (long long)d.count[1] * (z - d.start[2]));
+    return (x + dx - d.start[0]) + d.count[0] * ((y + dy - d.start[1]) + d.count[1] * (z - d.start[2]));
   };
-  // a of component d in column (x + dx, y + dy) at plane z; zero at removed unknowns
-  auto A = [&](const DevComp& d, int dx, int dy, int z) {
-    return (okxy(d, dx, dy) && (unsigned)(z - d.start[2]) < (unsigned)d.count[2]) ? p.a_in[idx(d, dx, dy, z)] : 0.0;
+  const double* __restrict__ ain[3] = {p.a_in + d0.offset, p.a_in + d1.offset, p.a_in + d2.offset};
+  // a of component C in column (x + dx, y + dy) at plane z; zero at removed unknowns
+  auto A = [&](auto cc, int dx, int dy, int z) {
+    constexpr int C = decltype(cc)::value;
+    const DevComp& d = p.s1.c[C];
+    return (okxy(d, dx, dy) && (unsigned)(z - d.start[2]) < (unsigned)d.count[2]) ? ain[C][idx(d, dx, dy, z)] : 0.0;
   };
+  constexpr std::integral_constant<int, 0> X{};
+  constexpr std::integral_constant<int, 1> Y{};
+  constexpr std::integral_constant<int, 2> Z{};
   // x-y factors of the face masses (component: nodal along itself, edge along the others)
   const double rnx = wfac<0, true>(p, x), rex = wfac<0, false>(p, x), rexm = wfac<0, false>(p, x - 1);
   const double rny = wfac<1, true>(p, y), rey = wfac<1, false>(p, y), reym = wfac<1, false>(p, y - 1);
@@ -131,25 +138,25 @@ __global__ void __launch_bounds__(256) yee_column_kernel(const YeeParams p, int 
   const double wq0 = p.q1s[0] * rex * rny, wq1 = p.q1s[1] * rnx * rey, wq2 = p.q1s[2] * rnx * rny;
   const bool own0 = okxy(d0, 0, 0), own1 = okxy(d1, 0, 0), own2 = okxy(d2, 0, 0);
 
-  double ax = A(d0, 0, 0, z0), ay = A(d1, 0, 0, z0);  // a_x, a_y of this column at plane z
-  double axm = A(d0, -1, 0, z0), aym = A(d1, 0, -1, z0);  // a_x at x - 1, a_y at y - 1
+  double ax = A(X, 0, 0, z0), ay = A(Y, 0, 0, z0);  // a_x, a_y of this column at plane z
+  double axm = A(X, -1, 0, z0), aym = A(Y, 0, -1, z0);  // a_x at x - 1, a_y at y - 1
   double hxb = 0.0, hyb = 0.0;  // x- and y-faces of this column below plane z
   if (z0 > 0) {
     const int zb = z0 - 1;
-    const double reb = wfac<2, false>(p, zb), azb = A(d2, 0, 0, zb);
-    hxb = whx * reb * ((A(d2, 0, 1, zb) - azb) - (ay - A(d1, 0, 0, zb)));
-    hyb = why * reb * ((ax - A(d0, 0, 0, zb)) - (A(d2, 1, 0, zb) - azb));
+    const double reb = wfac<2, false>(p, zb), azb = A(Z, 0, 0, zb);
+    hxb = whx * reb * ((A(Z, 0, 1, zb) - azb) - (ay - A(Y, 0, 0, zb)));
+    hyb = why * reb * ((ax - A(X, 0, 0, zb)) - (A(Z, 1, 0, zb) - azb));
   }
   for (int z = z0; z < z1; ++z) {
     const double rez = wfac<2, false>(p, z), rnz = wfac<2, true>(p, z);
-    const double az = A(d2, 0, 0, z);
-    const double axu = A(d0, 0, 0, z + 1), ayu = A(d1, 0, 0, z + 1);
-    const double axmu = A(d0, -1, 0, z + 1), aymu = A(d1, 0, -1, z + 1);
-    const double az_xm = A(d2, -1, 0, z), ay_xm = A(d1, -1, 0, z);
-    const double az_ym = A(d2, 0, -1, z), ax_ym = A(d0, 0, -1, z);
-    const double az_xp = A(d2, 1, 0, z), ay_xp = A(d1, 1, 0, z);
-    const double az_yp = A(d2, 0, 1, z), ax_yp = A(d0, 0, 1, z);
-    const double ay_xp_ym = A(d1, 1, -1, z), ax_xm_yp = A(d0, -1, 1, z);
+    const double az = A(Z, 0, 0, z);
+    const double axu = A(X, 0, 0, z + 1), ayu = A(Y, 0, 0, z + 1);
+    const double axmu = A(X, -1, 0, z + 1), aymu = A(Y, 0, -1, z + 1);
+    const double az_xm = A(Z, -1, 0, z), ay_xm = A(Y, -1, 0, z);
+    const double az_ym = A(Z, 0, -1, z), ax_ym = A(X, 0, -1, z);
+    const double az_xp = A(Z, 1, 0, z), ay_xp = A(Y, 1, 0, z);
+    const double az_yp = A(Z, 0, 1, z), ax_yp = A(X, 0, 1, z);
+    const double ay_xp_ym = A(Y, 1, -1, z), ax_xm_yp = A(X, -1, 1, z);
     // faces at (x, y, z) and at the neighbours the unknowns of (x, y, z) bound
     const double hx = whx * rez * ((az_yp - az) - (ayu - ay));
     const double hy = why * rez * ((axu - ax) - (az_xp - az));
@@ -166,7 +173,7 @@ __global__ void __launch_bounds__(256) yee_column_kernel(const YeeParams p, int 
       constexpr int C = decltype(cc)::value;
       const DevComp& d = p.s1.c[C];
       if (!own[C] || (unsigned)(z - d.start[2]) >= (unsigned)d.count[2]) return;
-      const long long i = idx(d, 0, 0, z);
+      const long long i = d.offset + idx(d, 0, 0, z);
       const double ev = fma(p.te, tv[C], p.e[i]);
       p.e[i] = ev;
       p.a_out[i] = fma(-p.ha, ev * (1.0 / wq[C]), av[C]);
@@ -187,10 +194,11 @@ int launch_yee(const YeeParams& p, bool half, int ncu, hipStream_t s) {
   if (half) {
     hipLaunchKernelGGL(yee_half_kernel, dim3((p.npos + 255u) / 256u), dim3(256), 0, s, p);
   } else {
-    // z-chunks short enough for about four blocks per CU, 2..32 planes long
+    // z-chunks short enough for about eight blocks per CU, 2..8 planes long
+    // (measured best on MI355X: 2 planes at 65^3 positions, 4 at 129^3, 8 at 257^3)
     const unsigned ncol = (unsigned)p.len[0] * (unsigned)p.len[1];
-    long long zc = (long long)p.npos / (4LL * ncu * 256);
-    zc = zc < 2 ? 2 : (zc > 32 ? 32 : zc);
+    long long zc = (long long)p.npos / (8LL * ncu * 256);
+    zc = zc < 2 ? 2 : (zc > 8 ? 8 : zc);
     const unsigned nzc = (unsigned)((p.len[2] + zc - 1) / zc);
     const unsigned nthr = ncol * nzc;
     hipLaunchKernelGGL(yee_column_kernel, dim3((nthr + 255u) / 256u), dim3(256), 0, s, p, (int)zc, ncol, nthr);
