@@ -257,6 +257,44 @@ int gym_maxwell_step(gym_maxwell* mx, double tau, int nsteps, double* a, double*
 int gym_maxwell_energy(gym_maxwell* mx, const double* a, const double* e, double* H, void* stream);
 int gym_maxwell_destroy(gym_maxwell* mx);
 
+/* ---- eigenmodes of the time-stepping operator (paper section 3) -------
+ * The lowest non-kernel eigenpairs of K~ = Q1 P2, i.e. of the generalized
+ * problem P2 v = omega^2 Q1^-1 v with Q1^-1 = M1 (exact) or the row sums of
+ * M1 (lumped) and P2 = c^2 C^T M2~ C.  The eigenvalues set the stability
+ * bound tau <= 2 / omega_max (Proposition Stability) and the numerical
+ * dispersion of the scheme (section 5).  P2 vanishes on gradients G Lambda^0;
+ * the solver works on P2 + c^2 s Q1^-1 G M0^-1 G^T Q1^-1 instead, which lifts
+ * the gradients to c^2 s times the eigenvalues of the Lambda^0 Laplacian and
+ * leaves every other eigenpair unchanged, s = grad_shift.  Method: LOBPCG
+ * (Knyazev 2001) with block size `block`, preconditioned by the inverse row
+ * sums of M1, from a seeded N(0,1) block. */
+typedef struct gym_eig_opts {
+  int nev;            /* eigenpairs wanted (1 <= nev <= block)                 */
+  int block;          /* LOBPCG block size, <= 8; 0: min(nev + 2, 8)           */
+  double tol;         /* stop when every wanted pair has
+                         ||P2 v - omega^2 B v|| <= tol omega^2 ||B v||         */
+  int maxit;          /* iteration cap                                        */
+  double grad_shift;  /* s > 0; must lift the gradients above the wanted pairs */
+  uint64_t seed;      /* initial block                                        */
+} gym_eig_opts;
+typedef struct gym_eig_info {
+  int iters;          /* LOBPCG iterations                                    */
+  int converged;      /* leading pairs that met tol                           */
+  double max_resid;   /* largest relative residual over the wanted pairs      */
+  int gradient_modes; /* wanted pairs found to be gradients (G^T B v != 0)    */
+} gym_eig_info;
+/* Defaults: nev 4, block 0, tol 1e-8, maxit 3000, grad_shift 4, seed 1. */
+void gym_eig_opts_default(gym_eig_opts* opts);
+/* omega2: host array of nev values (ascending).  vecs: NULL or a device array
+ * of nev x ndofs doubles receiving the Q1^-1-orthonormal eigenvectors, one
+ * after another.  Allocates its work space (device, about 16 block vectors)
+ * per call and synchronises the stream.  Returns GYM_W_NOT_CONVERGED if the
+ * cap came first, or if a wanted pair is a gradient (grad_shift too small,
+ * info->gradient_modes > 0); GYM_E_ARG for bad options; GYM_E_BREAKDOWN if
+ * the search space lost rank; GYM_E_OOM. */
+int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, double* vecs,
+                     gym_eig_info* info, void* stream);
+
 /* ---- serving: continuous batching of independent solves --------------- */
 typedef struct gym_serve_opts {
   int device;            /* HIP device                                       */

@@ -38,8 +38,9 @@ Pins (tests/test_oracle_maxwell.py): equivalence with the hand-written Yee
 finite differences; the one-step Jacobian against the paper's printed block
 form; its spectrum on / off the unit circle at 0.9 / 1.1 tau_CFL and the
 closed form of its eigenvalues; the lumped curl-of-curl spectrum against the
-finite-difference symbol; bounded energy; the phase rate of a propagated
-eigenmode against 2 arcsin(tau omega / 2) / tau.
+finite-difference symbol, and the exact (Whitney) one against the tensor
+product of 1-D generalized eigenvalues; bounded energy; the phase rate of a
+propagated eigenmode against 2 arcsin(tau omega / 2) / tau.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -129,6 +130,12 @@ class Gym:
 
     def tau_cfl(self):
         return 2.0 / np.sqrt(self.omega2()[-1])
+
+    def lowest_modes(self, k):
+        """The k smallest eigenvalues omega^2 of K~ = Q1 P2 outside its kernel
+        (the gradients), ascending (dense generalized eigenproblem)."""
+        w = self.omega2()
+        return np.sort(w[w > 1e-9 * w[-1]])[:k]
 
     def eigenmode(self, k):
         """k-th smallest non-kernel mode (omega^2, v) of the exact operator

@@ -1,0 +1,42 @@
+// Block kernels and the LOBPCG driver of the generalized eigen-solver
+// (paper section 3: the spectrum of K~ = Q1 P2 sets the CFL bound; the
+// lowest modes of the exact operator are the paper's dispersion tests).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <functional>
+
+namespace gym {
+
+// Blocks of column vectors: column j of an n x m block U is U + j n.
+// G (p x q, row-major, host) = U^T V, summed in a fixed order (per-block
+// partials, then one pass over the partials).  p, q <= kEigMaxCols.
+constexpr int kEigMaxCols = 24;
+int eig_gram(const double* U, int p, const double* V, int q, long long n, double* G_host, double* work, int nb,
+             hipStream_t s);
+// Y (n x q) = U (n x m) C (m x q); C row-major on the device, m, q <= kEigMaxCols.
+void eig_combine(const double* U, int m, const double* C_dev, int q, long long n, double* Y, int nb, hipStream_t s);
+// Column j of X (n x k) scaled by f[j] (device array).
+void eig_scale(double* X, const double* f_dev, int k, long long n, int nb, hipStream_t s);
+// Partial-sum slots eig_gram needs in `work`.
+long long eig_gram_work(int nb);
+
+// Generalized symmetric-definite eigenproblem A x = lambda B x, lowest k
+// eigenpairs, by LOBPCG (Knyazev 2001) with Rayleigh-Ritz on [X, W, P].  The
+// operators act on blocks of columns (device pointers, ncol columns of
+// length n); T is the preconditioner applied to the residuals (may be empty).
+struct EigOperators {
+  std::function<int(const double* x, double* y, int ncol)> A, B, T;
+};
+struct EigResult {
+  int iters = 0;
+  int converged = 0;       // leading eigenpairs with relative residual <= tol
+  double max_resid = 0.0;  // over the first nev pairs
+};
+// X: n x k device block, the initial guess on entry, the eigenvectors on exit
+// (B-orthonormal).  lam: k host values, ascending.  Returns 0, a negative
+// status on error, or 1 when the iteration cap was reached first.
+int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int maxit, double* X, double* lam,
+           EigResult* res, int ncu, hipStream_t s);
+
+}  // namespace gym

@@ -14,10 +14,12 @@
 // between the caller's vector and a work vector.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
 #include "gym_internal.hpp"
+#include "eig.hpp"
 #include "krylov.hpp"
 #include "yee.hpp"
 
@@ -240,6 +242,147 @@ int gym_maxwell_energy(gym_maxwell* mx, const double* a, const double* e, double
   GYM_HIP(hipStreamSynchronize(s));
   *H = 0.5 * h[0] + 0.5 * mx->o.c * mx->o.c * h[1];
   return warn ? GYM_W_NOT_CONVERGED : GYM_OK;
+}
+
+void gym_eig_opts_default(gym_eig_opts* o) {
+  o->nev = 4;
+  o->block = 0;
+  o->tol = 1e-8;
+  o->maxit = 3000;
+  o->grad_shift = 4.0;
+  o->seed = 1;
+}
+
+int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, double* vecs, gym_eig_info* info,
+                     void* stream) {
+  if (!mx || !omega2) return fail(GYM_E_ARG, "NULL argument");
+  gym_eig_opts o;
+  if (opts) o = *opts;
+  else gym_eig_opts_default(&o);
+  const int k = o.block > 0 ? o.block : std::min(o.nev + 2, kEigMaxCols / 3);
+  if (o.nev < 1 || k < o.nev || 3 * k > kEigMaxCols || !(o.tol > 0) || o.maxit < 1 || !(o.grad_shift > 0))
+    return fail(GYM_E_ARG, "bad eigen-solver options (1 <= nev <= block <= 8)");
+  hipStream_t s = (hipStream_t)stream;
+  const long long n1 = mx->n1;
+  if (n1 < 3LL * k) return fail(GYM_E_ARG, "eigen-solver: fewer unknowns than the search space needs");
+  const double c2 = mx->o.c * mx->o.c;
+  const bool lumped = mx->o.q1 == GYM_Q1_LUMPED;
+  gym_space* s0 = nullptr;  // Lambda^0 with the conductor's boundary values removed
+  if (int rc = gym_space_create(mx->ctx, mx->mesh, GYM_H1, mx->s1->desc.r, GYM_BC_ESSENTIAL, &s0)) return rc;
+  const long long n0 = gym_space_ndofs(s0);
+  const int nb1 = mx->nb1;
+  std::vector<void*> pool;
+  auto alloc = [&](long long cnt) -> double* {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(double) * cnt) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    pool.push_back(p);
+    return (double*)p;
+  };
+  auto cleanup = [&] {
+    for (void* p : pool) (void)hipFree(p);
+    gym_space_destroy(s0);
+  };
+  double* X = alloc(n1 * k);
+  double* bx = alloc(n1 * k);
+  double* gp = alloc(n1 * k);
+  double* bgp = alloc(n1 * k);
+  double* g0 = alloc(std::max(1LL, n0) * k);
+  double* phi = alloc(std::max(1LL, n0) * k);
+  double* dB = alloc(n1);    // lumped: the row sums of M1 (B itself)
+  double* dT = alloc(n1);    // their inverses (the preconditioner)
+  double* gw = alloc(eig_gram_work(nb1));
+  if (!X || !bx || !gp || !bgp || !g0 || !phi || !dB || !dT || !gw) {
+    cleanup();
+    return fail(GYM_E_OOM, "eigen-solver: device allocation failed");
+  }
+  {
+    std::vector<double> d = lumped_diag_host(mx->s1), di(d.size());
+    for (size_t i = 0; i < d.size(); ++i) di[i] = 1.0 / d[i];
+    if (hipMemcpy(dB, d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dT, di.data(), sizeof(double) * di.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      cleanup();
+      return fail(GYM_E_HIP, "eigen-solver: upload failed");
+    }
+  }
+  auto colp = [](double* b, long long n, int j) { return b + (long long)j * n; };
+  int warn = 0;
+  EigOperators ops;
+  // B = Q1^-1: M1, or its row sums when lumped
+  ops.B = [&](const double* x, double* y, int ncol) -> int {
+    if (!lumped) return gym_mass_apply(mx->s1, GYM_F64, ncol, x, y, s);
+    for (int j = 0; j < ncol; ++j)
+      launch_axpy_diag(colp(y, n1, j), 0.0, 1.0, dB, colp(const_cast<double*>(x), n1, j), n1, nb1, s);
+    return 0;
+  };
+  // T: inverse row sums of M1
+  ops.T = [&](const double* x, double* y, int ncol) -> int {
+    for (int j = 0; j < ncol; ++j)
+      launch_axpy_diag(colp(y, n1, j), 0.0, 1.0, dT, colp(const_cast<double*>(x), n1, j), n1, nb1, s);
+    return 0;
+  };
+  // A = c^2 (C^T M2~ C + s B G M0^-1 G^T B): P2 plus a multiple of the
+  // gradient-space operator, which lifts the gradients (the kernel of P2)
+  // above the wanted modes and leaves every other eigenpair of (P2, B) alone
+  ops.A = [&](const double* x, double* y, int ncol) -> int {
+    for (int j = 0; j < ncol; ++j) {
+      if (int rc = apply_p2(mx, colp(const_cast<double*>(x), n1, j), s)) return rc;
+      if (hipMemcpyAsync(colp(y, n1, j), mx->t, sizeof(double) * n1, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return hip_fail(hipGetLastError(), "eigen-solver copy");
+    }
+    if (int rc = ops.B(x, bx, ncol)) return rc;
+    for (int j = 0; j < ncol; ++j)
+      if (int rc = gym_d_apply(s0, mx->s1, 1, colp(bx, n1, j), colp(g0, n0, j), s)) return rc;
+    gym_solve_opts so;
+    gym_solve_opts_default(&so);
+    so.method = GYM_CG;
+    so.rtol = 1e-13;
+    so.maxit = 5000;
+    gym_solve_info si{};
+    int rc = gym_mass_solve(s0, &so, ncol, g0, phi, &si, s);
+    if (rc == GYM_W_NOT_CONVERGED) warn = 1;
+    else if (rc) return rc;
+    for (int j = 0; j < ncol; ++j)
+      if (int rc2 = gym_d_apply(s0, mx->s1, 0, colp(phi, n0, j), colp(gp, n1, j), s)) return rc2;
+    if (int rc2 = ops.B(gp, bgp, ncol)) return rc2;
+    for (int j = 0; j < ncol; ++j)
+      launch_axpy_diag(colp(y, n1, j), c2, c2 * o.grad_shift, nullptr, colp(bgp, n1, j), n1, nb1, s);
+    return 0;
+  };
+  launch_rhs_normal(X, 0, n1 * k, o.seed, vec_grid(n1 * k, mx->ctx->ncu), s);
+  std::vector<double> lam(k);
+  EigResult er;
+  int rc = lobpcg(ops, n1, k, o.nev, o.tol, o.maxit, X, lam.data(), &er, mx->ctx->ncu, s);
+  int ngrad = 0;
+  if (rc >= 0) {
+    // a wanted pair with G^T B x != 0 is a gradient the shift did not lift far enough
+    if (int r2 = ops.B(X, bx, k)) rc = r2;
+    for (int j = 0; j < k && rc >= 0; ++j)
+      if (int r2 = gym_d_apply(s0, mx->s1, 1, colp(bx, n1, j), colp(g0, n0, j), s)) rc = r2;
+    std::vector<double> gg((size_t)k * k), bb((size_t)k * k);
+    if (rc >= 0 && (eig_gram(g0, k, g0, k, n0, gg.data(), gw, nb1, s) || eig_gram(bx, k, bx, k, n1, bb.data(), gw, nb1, s)))
+      rc = hip_fail(hipGetLastError(), "eigen-solver check");
+    for (int j = 0; j < o.nev && rc >= 0; ++j)
+      if (std::sqrt(gg[(size_t)j * k + j]) > 1e-4 * std::sqrt(bb[(size_t)j * k + j])) ++ngrad;
+  }
+  if (rc >= 0) {
+    for (int j = 0; j < o.nev; ++j) omega2[j] = lam[j];
+    if (vecs && hipMemcpyAsync(vecs, X, sizeof(double) * n1 * o.nev, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      rc = hip_fail(hipGetLastError(), "eigen-solver copy");
+    if (hipStreamSynchronize(s) != hipSuccess) rc = hip_fail(hipGetLastError(), "eigen-solver sync");
+  }
+  if (info) {
+    info->iters = er.iters;
+    info->converged = er.converged;
+    info->max_resid = er.max_resid;
+    info->gradient_modes = ngrad;
+  }
+  cleanup();
+  if (rc < 0) return rc;
+  if (ngrad) return fail(GYM_W_NOT_CONVERGED, "eigen-solver: a wanted pair is a gradient; raise grad_shift");
+  return (rc == 1 || warn) ? GYM_W_NOT_CONVERGED : GYM_OK;
 }
 
 int gym_maxwell_destroy(gym_maxwell* mx) {

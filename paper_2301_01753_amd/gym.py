@@ -74,6 +74,16 @@ class MaxwellOpts(ctypes.Structure):
                 ("cg_maxit", ctypes.c_int)]
 
 
+class EigOpts(ctypes.Structure):
+    _fields_ = [("nev", ctypes.c_int), ("block", ctypes.c_int), ("tol", ctypes.c_double), ("maxit", ctypes.c_int),
+                ("grad_shift", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+class EigInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("max_resid", ctypes.c_double),
+                ("gradient_modes", ctypes.c_int)]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _I64 = ctypes.c_int64
@@ -110,6 +120,9 @@ SIGNATURES = {
     "gym_maxwell_step": (_I, [_P, ctypes.c_double, _I, _P, _P, _P]),
     "gym_maxwell_energy": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "gym_maxwell_destroy": (_I, [_P]),
+    "gym_eig_opts_default": (None, [ctypes.POINTER(EigOpts)]),
+    "gym_maxwell_eigs": (_I, [_P, ctypes.POINTER(EigOpts), ctypes.POINTER(ctypes.c_double), _P,
+                             ctypes.POINTER(EigInfo), _P]),
 }
 
 _lib = None
@@ -314,6 +327,24 @@ def gym_maxwell_energy(mx, a, e, stream=None):
 
 def gym_maxwell_destroy(mx):
     _check(lib().gym_maxwell_destroy(mx))
+
+
+def gym_eig_opts_default():
+    o = EigOpts()
+    lib().gym_eig_opts_default(ctypes.byref(o))
+    return o
+
+
+def gym_maxwell_eigs(mx, opts=None, vecs=None, stream=None):
+    """Lowest non-kernel omega^2 of Q1 P2: returns (omega2 numpy array, EigInfo,
+    status); `vecs`, if given, is a device tensor of nev x ndofs doubles."""
+    o = opts if opts is not None else gym_eig_opts_default()
+    w = np.zeros(o.nev, dtype=np.float64)
+    info = EigInfo()
+    st = lib().gym_maxwell_eigs(mx, ctypes.byref(o), w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                _ptr(vecs) if vecs is not None else None, ctypes.byref(info), _stream(stream))
+    _check(st, ok=(GYM_OK, GYM_W_NOT_CONVERGED))
+    return w, info, st
 
 
 def gym_serve_start(opts):

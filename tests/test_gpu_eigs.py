@@ -1,0 +1,119 @@
+"""GPU eigenmodes of the time-stepping operator (gym_maxwell_eigs) against the oracle.
+
+The lowest non-kernel omega^2 of K~ = Q1 P2 come from the oracle's dense
+generalized eigenproblem on small meshes (exact and lumped Q1, degrees 1-3, a
+perturbed mesh), and from the closed-form Whitney spectrum (pinned to the
+oracle in test_oracle_maxwell) on a 24^3 box.  Eigenvectors are checked by
+properties that hold for any basis of a degenerate eigenspace: the residual
+with the oracle's sparse P2 and Q1^-1, Q1^-1-orthonormality, and G^T Q1^-1 v = 0
+(no gradient content).  Eigenvalue tolerance 1e-9 relative: LOBPCG stops at
+relative residual 1e-10 here, and the eigenvalue error is of its square.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import synth
+from oracle import incidence, maxwell
+from oracle.lattice import Mesh, Space
+from test_oracle_maxwell import whitney_spectrum
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def g():
+    from paper_2301_01753_amd import gym
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = gym.gym_create(0)
+    yield gym, ctx
+    gym.gym_destroy(ctx)
+
+
+def _maxwell(gym, ctx, nel, r, q1, m2, c, hi, perturb):
+    verts = synth.perturbed_vertices(nel, perturb, seed=3, hi=hi) if perturb else synth.uniform_vertices(nel, hi=hi)
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts if perturb else None, hi=hi)
+    o = gym.gym_maxwell_opts_default()
+    o.q1 = gym.GYM_Q1_EXACT if q1 == "exact" else gym.GYM_Q1_LUMPED
+    o.m2 = gym.GYM_M2_EXACT if m2 == "exact" else gym.GYM_M2_LUMPED
+    o.c = c
+    return mesh, gym.gym_maxwell_create(ctx, mesh, r, o), verts
+
+
+CASES = [((3, 4, 3), 1, "exact", "exact", 1.0, (1.0, 1.2, 0.9), 0.0, 4),
+         ((3, 3, 2), 2, "exact", "exact", 1.3, (1.0, 1.0, 1.0), 0.0, 4),
+         ((4, 3, 3), 1, "lumped", "lumped", 1.0, (1.0, 1.0, 1.0), 0.0, 4),
+         ((2, 3, 2), 3, "lumped", "exact", 0.8, (1.0, 1.0, 1.0), 0.0, 3),
+         ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15, 3)]
+
+
+@pytest.mark.parametrize("nel,r,q1,m2,c,hi,perturb,nev", CASES)
+def test_lowest_modes_match_oracle(g, nel, r, q1, m2, c, hi, perturb, nev):
+    gym, ctx = g
+    mesh, mx, verts = _maxwell(gym, ctx, nel, r, q1, m2, c, hi, perturb)
+    n = gym.gym_maxwell_ndofs(mx)
+    o = gym.gym_eig_opts_default()
+    o.nev, o.tol = nev, 1e-10
+    vecs = torch.empty(nev * n, dtype=torch.float64, device=DEV)
+    w, info, st = gym.gym_maxwell_eigs(mx, o, vecs)
+    print(f"nel={nel} r={r} {q1}/{m2}: {info.iters} iterations, resid {info.max_resid:.1e}", flush=True)
+    assert st == gym.GYM_OK and info.converged == nev and info.gradient_modes == 0
+    G = maxwell.Gym(Mesh(verts), r, q1=q1, m2=m2, c=c)
+    ref = G.lowest_modes(nev)
+    assert np.allclose(w, ref, rtol=1e-9, atol=0), (w, ref)
+    V = vecs.cpu().numpy().reshape(nev, n).T
+    B = G.M1 if q1 == "exact" else sp.diags(G.rs1)
+    BV = B @ V
+    res = G.P2 @ V - BV * w[None, :]
+    assert np.abs(res).max(axis=0).max() <= 1e-7 * (np.abs(BV).max(axis=0) * w).max()
+    assert np.allclose(V.T @ BV, np.eye(nev), atol=1e-8)
+    s0 = Space("H1", nel, r, "essential")
+    Gr = incidence.gradient(s0, G.s1).astype(np.float64)
+    assert np.abs(Gr.T @ BV).max() <= 1e-7 * np.abs(BV).max()
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+
+
+def test_whitney_24cube_closed_form(g):
+    # 24^3 Whitney box (38,088 unknowns), exact masses: the six lowest modes
+    # (a triple at 2 pi^2 (6/h^2 form) and the pair above it) against the closed form
+    gym, ctx = g
+    nel, hi, c = (24, 24, 24), (1.0, 1.0, 1.0), 1.0
+    mesh, mx, _ = _maxwell(gym, ctx, nel, 1, "exact", "exact", c, hi, 0.0)
+    o = gym.gym_eig_opts_default()
+    o.nev, o.block, o.tol = 5, 7, 1e-10
+    w, info, st = gym.gym_maxwell_eigs(mx, o)
+    print(f"24^3: {info.iters} iterations, resid {info.max_resid:.1e}, omega2 {w}", flush=True)
+    assert st == gym.GYM_OK and info.gradient_modes == 0
+    ref = whitney_spectrum(nel, hi, c)[:5]
+    assert np.allclose(w, ref, rtol=1e-9, atol=0), (w, ref)
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+
+
+def test_small_grad_shift_is_reported(g):
+    # With the gradients lifted by too little, the lowest pairs are gradients:
+    # the solver says so instead of returning them as modes.
+    gym, ctx = g
+    mesh, mx, _ = _maxwell(gym, ctx, (3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.0)
+    o = gym.gym_eig_opts_default()
+    o.nev, o.grad_shift = 2, 1e-3
+    w, info, st = gym.gym_maxwell_eigs(mx, o)
+    assert st == gym.GYM_W_NOT_CONVERGED and info.gradient_modes > 0
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+
+
+def test_eig_errors(g):
+    gym, ctx = g
+    mesh, mx, _ = _maxwell(gym, ctx, (2, 2, 2), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.0)
+    for nev, block in ((0, 0), (5, 4), (4, 9)):
+        o = gym.gym_eig_opts_default()
+        o.nev, o.block = nev, block
+        with pytest.raises(gym.GymError):
+            gym.gym_maxwell_eigs(mx, o)
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)

@@ -125,6 +125,39 @@ def test_lumped_spectrum_is_the_yee_dispersion_symbol():
     assert np.allclose(nonzero, pred, rtol=1e-12)
 
 
+def whitney_spectrum(nel, hi, c):
+    """Non-kernel omega^2 of M1^-1 P2 for Whitney forms with exact masses on
+    a uniform perfect-conductor box: on a tensor lattice the curl-of-curl
+    separates into 1-D problems, and the 1-D nodal stiffness (1/h)[2, -1]
+    against the 1-D mass (h/6)[4, 1] has the eigenvalues
+    (6/h^2)(1 - cos t)/(2 + cos t), t = pi n / N.  Multiplicity: two
+    polarisations when n_x, n_y, n_z > 0, one when exactly one is zero."""
+    h = [hi[a] / nel[a] for a in range(3)]
+    lam = [[(6 / h[a] ** 2) * (1 - np.cos(np.pi * n / nel[a])) / (2 + np.cos(np.pi * n / nel[a]))
+            for n in range(nel[a])] for a in range(3)]
+    out = []
+    for nx in range(nel[0]):
+        for ny in range(nel[1]):
+            for nz in range(nel[2]):
+                pos = (nx > 0) + (ny > 0) + (nz > 0)
+                mult = 2 if pos == 3 else (1 if pos == 2 else 0)
+                out += [c * c * (lam[0][nx] + lam[1][ny] + lam[2][nz])] * mult
+    return np.sort(out)
+
+
+@pytest.mark.parametrize("nel,hi", [((3, 4, 2), (1.2, 1.0, 0.7)), ((3, 3, 3), (1.0, 1.0, 1.0))])
+def test_exact_whitney_spectrum_closed_form(nel, hi):
+    # The exact-FEEC operator K = M1^-1 P2 (section 3) on a box: every
+    # non-kernel eigenvalue of the dense generalized problem against the
+    # closed form, with multiplicities.
+    c = 0.8
+    G = maxwell.Gym(_mesh(nel, hi), 1, q1="exact", m2="exact", c=c)
+    pred = whitney_spectrum(nel, hi, c)
+    got = G.lowest_modes(10 ** 6)
+    assert len(got) == len(pred)
+    assert np.allclose(got, pred, rtol=1e-12)
+
+
 def test_energy_is_bounded():
     # Symplectic Strang splitting: the modified energy oscillates without drift.
     G = maxwell.Gym(_mesh((3, 3, 3), (1.0, 1.0, 1.0)), 2, q1="exact", m2="exact")
