@@ -252,6 +252,33 @@ def maxwell_rates(gym, ctx, N, r, q1, steps):
     return out
 
 
+def eig_rates(gym, ctx, N, r, nev, block):
+    """Lowest non-kernel eigenpairs of the exact (Q1 = M1^-1) time-stepping
+    operator on an N^3 unit box: wall time, LOBPCG iterations, and the
+    relative deviation from the closed-form Whitney spectrum (r = 1)."""
+    import numpy as np
+    import torch
+    mesh = gym.gym_mesh_create(ctx, 3, (N, N, N))
+    mx = gym.gym_maxwell_create(ctx, mesh, r, gym.gym_maxwell_opts_default())
+    o = gym.gym_eig_opts_default()
+    o.nev, o.block, o.tol = nev, block, 1e-10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, info, st = gym.gym_maxwell_eigs(mx, o)
+    wall = time.perf_counter() - t0
+    out = {"ndofs": gym.gym_maxwell_ndofs(mx), "nev": nev, "block": block, "seconds": wall, "iters": info.iters,
+           "max_resid": info.max_resid, "status": st, "omega2": [float(v) for v in w]}
+    if r == 1:
+        h = 1.0 / N
+        lam = [(6 / h ** 2) * (1 - np.cos(np.pi * n / N)) / (2 + np.cos(np.pi * n / N)) for n in range(N)]
+        ref = sorted(lam[a] + lam[b] + lam[c] for a in range(N) for b in range(N) for c in range(N)
+                     if (a > 0) + (b > 0) + (c > 0) >= 2 for _ in range(2 if min(a, b, c) > 0 else 1))[:nev]
+        out["max_rel_dev_closed_form"] = float(max(abs(x - y) / y for x, y in zip(w, ref)))
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+    return out
+
+
 # Sources of the operator kernel: the HBM traffic recorded under profiles/
 # (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) is reported only while these are
 # unchanged since the counters were taken.
@@ -494,6 +521,11 @@ def main():
             "yee_r1_128cube_lumped": maxwell_rates(gym, ctx, 128, 1, "lumped", 2000),
             "r2_32cube_lumped": maxwell_rates(gym, ctx, 32, 2, "lumped", 2000),
             "r2_32cube_exact_q1_cg": maxwell_rates(gym, ctx, 32, 2, "exact", 20),
+        }
+        log("eigenmodes ...")
+        ext["gym_eigenmodes"] = {
+            "whitney_24cube_lowest5": eig_rates(gym, ctx, 24, 1, 5, 7),
+            "whitney_32cube_lowest5": eig_rates(gym, ctx, 32, 1, 5, 7),
         }
         out["extras"] = ext
 
