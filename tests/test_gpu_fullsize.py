@@ -15,7 +15,9 @@ The operator is applied by the GPU in the launch configuration the benchmark
 times (automatic tiles, 1 or 8 right-hand sides) to a seeded N(0, 1) vector;
 only the patch's entries of x and the sampled entries of y cross to the host.
 Tolerances as in test_gpu_parity: FP64 1e-13, FP32 2e-5 of the sampled max
-norm; BF16 contractions sit between 1e-5 and 5e-2.
+norm; BF16 contractions sit between 1e-5 and 5e-2.  The benchmark's solve is
+checked the same way: its solution satisfies the sampled rows of A x = b to
+within the global residual.
 """
 import numpy as np
 import pytest
@@ -128,4 +130,41 @@ def test_incidence_complex_at_full_size(g):
     assert float(cgu.abs().max()) == 0.0
     for s in (s0, s1, s2):
         gym.gym_space_destroy(s)
+    gym.gym_mesh_destroy(mesh)
+
+
+def test_hodge_r2_32cube_solve_rows(g):
+    # The benchmark's solve end to end: the fused two-launch MINRES path in the
+    # benchmark's launch configuration, the manufactured right-hand side of
+    # the benchmark, to relative residual 1e-10.  On sampled oracle rows,
+    # |b_i - (A x)_i| is bounded by the global residual, ||b - A x||_2 <=
+    # rel_res ||b||_2, plus the rounding of the row sum itself.
+    gym, ctx = g
+    nel, r = (32, 32, 32), 2
+    mesh = gym.gym_mesh_create(ctx, 3, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, r)
+    n = gym.gym_op_ndofs(op)
+    b = torch.empty(n, dtype=torch.float64, device=DEV)
+    gym.gym_rhs_manufactured(op, synth.modes_3d(), synth.fourier_coeffs(0, 8, 3), b)
+    x = torch.empty_like(b)
+    o = gym.gym_solve_opts_default()
+    o.rtol = 1e-10
+    info = gym.gym_solve(op, o, 1, b, x)
+    torch.cuda.synchronize()
+    print(f"32^3 r=2 Hodge solve: {info.iters} iterations, rel_res {info.rel_res:.2e}", flush=True)
+    assert info.status == gym.GYM_OK and info.rel_res <= 1e-10
+    bound = 1.01 * info.rel_res * float(torch.linalg.vector_norm(b))
+    vg = synth.uniform_vertices(nel)
+    rng = np.random.default_rng(6)
+    for origin, mid in origins(nel, rng):
+        A, gmap, rows = patch_rows("hodge", vg, nel, r, origin, mid)
+        idx = torch.as_tensor(gmap, device=DEV)
+        xp = x.index_select(0, idx).cpu().numpy()
+        bp = b.index_select(0, idx).cpu().numpy()[rows]
+        ax = (A @ xp)[rows]
+        scale = (abs(A) @ np.abs(xp))[rows]
+        err = np.abs(bp - ax)
+        print(f"patch {origin}: {len(rows)} rows, max |b - A x| {err.max():.2e} (bound {bound:.2e})", flush=True)
+        assert (err <= bound + 1e-12 * scale).all()
+    gym.gym_op_destroy(op)
     gym.gym_mesh_destroy(mesh)
