@@ -279,6 +279,31 @@ def eig_rates(gym, ctx, N, r, nev, block):
     return out
 
 
+def cfl_rate(gym, ctx, N):
+    """omega_max of Yee's method (Whitney forms, lumped masses) on an N^3 unit
+    box by the largest-pair solver, tau_CFL = 2 / omega_max, and the relative
+    deviation from the closed form (the Yee symbol at n = N - 1 on every axis)."""
+    import numpy as np
+    import torch
+    mesh = gym.gym_mesh_create(ctx, 3, (N, N, N))
+    o = gym.gym_maxwell_opts_default()
+    o.q1, o.m2 = gym.GYM_Q1_LUMPED, gym.GYM_M2_LUMPED
+    mx = gym.gym_maxwell_create(ctx, mesh, 1, o)
+    e = gym.gym_eig_opts_default()
+    e.nev, e.largest, e.block, e.tol = 2, 1, 4, 1e-10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w, info, st = gym.gym_maxwell_eigs(mx, e)
+    wall = time.perf_counter() - t0
+    ref = 3 * (2 * N) ** 2 * np.sin(np.pi * (N - 1) / (2 * N)) ** 2
+    out = {"ndofs": gym.gym_maxwell_ndofs(mx), "seconds": wall, "iters": info.iters, "status": st,
+           "omega_max2": float(w[0]), "tau_cfl": float(2 / np.sqrt(w[0])),
+           "rel_dev_closed_form": float(abs(w[0] - ref) / ref)}
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+    return out
+
+
 # Sources of the operator kernel: the HBM traffic recorded under profiles/
 # (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) is reported only while these are
 # unchanged since the counters were taken.
@@ -526,6 +551,7 @@ def main():
         ext["gym_eigenmodes"] = {
             "whitney_24cube_lowest5": eig_rates(gym, ctx, 24, 1, 5, 7),
             "whitney_32cube_lowest5": eig_rates(gym, ctx, 32, 1, 5, 7),
+            "yee_128cube_omega_max": cfl_rate(gym, ctx, 128),
         }
         out["extras"] = ext
 

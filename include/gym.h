@@ -270,6 +270,8 @@ int gym_maxwell_destroy(gym_maxwell* mx);
  * sums of M1, from a seeded N(0,1) block. */
 typedef struct gym_eig_opts {
   int nev;            /* eigenpairs wanted (1 <= nev <= block)                 */
+  int largest;        /* 0: the lowest non-kernel pairs; 1: the largest ones
+                         (omega_max: the step is stable iff tau <= 2/omega_max) */
   int block;          /* LOBPCG block size, <= 8; 0: min(nev + 2, 8)           */
   double tol;         /* stop when every wanted pair has
                          ||P2 v - omega^2 B v|| <= tol omega^2 ||B v||         */
@@ -283,9 +285,11 @@ typedef struct gym_eig_info {
   double max_resid;   /* largest relative residual over the wanted pairs      */
   int gradient_modes; /* wanted pairs found to be gradients (G^T B v != 0)    */
 } gym_eig_info;
-/* Defaults: nev 4, block 0, tol 1e-8, maxit 3000, grad_shift 4, seed 1. */
+/* Defaults: nev 4, largest 0, block 0, tol 1e-8, maxit 3000, grad_shift 4, seed 1. */
 void gym_eig_opts_default(gym_eig_opts* opts);
-/* omega2: host array of nev values (ascending).  vecs: NULL or a device array
+/* omega2: host array of nev values (ascending; descending when largest:
+ * then the solver runs on -P2, without the gradient shift, which the
+ * largest pairs never meet).  vecs: NULL or a device array
  * of nev x ndofs doubles receiving the Q1^-1-orthonormal eigenvectors, one
  * after another.  Allocates its work space (device, about 16 block vectors)
  * per call and synchronises the stream.  Returns GYM_W_NOT_CONVERGED if the

@@ -246,6 +246,7 @@ int gym_maxwell_energy(gym_maxwell* mx, const double* a, const double* e, double
 
 void gym_eig_opts_default(gym_eig_opts* o) {
   o->nev = 4;
+  o->largest = 0;
   o->block = 0;
   o->tol = 1e-8;
   o->maxit = 3000;
@@ -260,7 +261,8 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   if (opts) o = *opts;
   else gym_eig_opts_default(&o);
   const int k = o.block > 0 ? o.block : std::min(o.nev + 2, kEigMaxCols / 3);
-  if (o.nev < 1 || k < o.nev || 3 * k > kEigMaxCols || !(o.tol > 0) || o.maxit < 1 || !(o.grad_shift > 0))
+  if (o.nev < 1 || k < o.nev || 3 * k > kEigMaxCols || !(o.tol > 0) || o.maxit < 1 || !(o.grad_shift > 0) ||
+      (o.largest != 0 && o.largest != 1))
     return fail(GYM_E_ARG, "bad eigen-solver options (1 <= nev <= block <= 8)");
   hipStream_t s = (hipStream_t)stream;
   const long long n1 = mx->n1;
@@ -327,6 +329,13 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   // gradient-space operator, which lifts the gradients (the kernel of P2)
   // above the wanted modes and leaves every other eigenpair of (P2, B) alone
   ops.A = [&](const double* x, double* y, int ncol) -> int {
+    if (o.largest) {  // -P2: its lowest pairs are the largest of P2
+      for (int j = 0; j < ncol; ++j) {
+        if (int rc = apply_p2(mx, colp(const_cast<double*>(x), n1, j), s)) return rc;
+        launch_axpy_diag(colp(y, n1, j), 0.0, -c2, nullptr, mx->t, n1, nb1, s);
+      }
+      return 0;
+    }
     for (int j = 0; j < ncol; ++j) {
       if (int rc = apply_p2(mx, colp(const_cast<double*>(x), n1, j), s)) return rc;
       if (hipMemcpyAsync(colp(y, n1, j), mx->t, sizeof(double) * n1, hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -356,7 +365,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   EigResult er;
   int rc = lobpcg(ops, n1, k, o.nev, o.tol, o.maxit, X, lam.data(), &er, mx->ctx->ncu, s);
   int ngrad = 0;
-  if (rc >= 0) {
+  if (rc >= 0 && !o.largest) {
     // a wanted pair with G^T B x != 0 is a gradient the shift did not lift far enough
     if (int r2 = ops.B(X, bx, k)) rc = r2;
     for (int j = 0; j < k && rc >= 0; ++j)
@@ -368,7 +377,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
       if (std::sqrt(gg[(size_t)j * k + j]) > 1e-4 * std::sqrt(bb[(size_t)j * k + j])) ++ngrad;
   }
   if (rc >= 0) {
-    for (int j = 0; j < o.nev; ++j) omega2[j] = lam[j];
+    for (int j = 0; j < o.nev; ++j) omega2[j] = o.largest ? -lam[j] : lam[j];
     if (vecs && hipMemcpyAsync(vecs, X, sizeof(double) * n1 * o.nev, hipMemcpyDeviceToDevice, s) != hipSuccess)
       rc = hip_fail(hipGetLastError(), "eigen-solver copy");
     if (hipStreamSynchronize(s) != hipSuccess) rc = hip_fail(hipGetLastError(), "eigen-solver sync");

@@ -75,8 +75,8 @@ class MaxwellOpts(ctypes.Structure):
 
 
 class EigOpts(ctypes.Structure):
-    _fields_ = [("nev", ctypes.c_int), ("block", ctypes.c_int), ("tol", ctypes.c_double), ("maxit", ctypes.c_int),
-                ("grad_shift", ctypes.c_double), ("seed", ctypes.c_uint64)]
+    _fields_ = [("nev", ctypes.c_int), ("largest", ctypes.c_int), ("block", ctypes.c_int), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("grad_shift", ctypes.c_double), ("seed", ctypes.c_uint64)]
 
 
 class EigInfo(ctypes.Structure):
@@ -336,8 +336,9 @@ def gym_eig_opts_default():
 
 
 def gym_maxwell_eigs(mx, opts=None, vecs=None, stream=None):
-    """Lowest non-kernel omega^2 of Q1 P2: returns (omega2 numpy array, EigInfo,
-    status); `vecs`, if given, is a device tensor of nev x ndofs doubles."""
+    """Lowest non-kernel (or, with opts.largest, the largest) omega^2 of Q1 P2:
+    returns (omega2 numpy array, EigInfo, status); `vecs`, if given, is a device
+    tensor of nev x ndofs doubles."""
     o = opts if opts is not None else gym_eig_opts_default()
     w = np.zeros(o.nev, dtype=np.float64)
     info = EigInfo()

@@ -1,6 +1,7 @@
 """GPU eigenmodes of the time-stepping operator (gym_maxwell_eigs) against the oracle.
 
-The lowest non-kernel omega^2 of K~ = Q1 P2 come from the oracle's dense
+The lowest non-kernel omega^2 of K~ = Q1 P2, and the largest ones with
+tau_CFL = 2 / omega_max, come from the oracle's dense
 generalized eigenproblem on small meshes (exact and lumped Q1, degrees 1-3, a
 perturbed mesh), and from the closed-form Whitney spectrum (pinned to the
 oracle in test_oracle_maxwell) on a 24^3 box.  Eigenvectors are checked by
@@ -94,6 +95,48 @@ def test_whitney_24cube_closed_form(g):
     gym.gym_mesh_destroy(mesh)
 
 
+LARGEST = [((3, 4, 3), 1, "exact", "exact", 1.0, (1.0, 1.2, 0.9), 0.0),
+           ((3, 3, 2), 2, "lumped", "lumped", 1.3, (1.0, 1.0, 1.0), 0.0),
+           ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15)]
+
+
+@pytest.mark.parametrize("nel,r,q1,m2,c,hi,perturb", LARGEST)
+def test_largest_modes_and_cfl(g, nel, r, q1, m2, c, hi, perturb):
+    # omega_max and tau_CFL = 2 / omega_max (Proposition Stability) against the
+    # oracle's dense spectrum
+    gym, ctx = g
+    mesh, mx, verts = _maxwell(gym, ctx, nel, r, q1, m2, c, hi, perturb)
+    o = gym.gym_eig_opts_default()
+    o.nev, o.largest, o.tol = 2, 1, 1e-10
+    w, info, st = gym.gym_maxwell_eigs(mx, o)
+    print(f"largest nel={nel} r={r} {q1}/{m2}: {info.iters} iterations", flush=True)
+    assert st == gym.GYM_OK and info.converged == 2
+    G = maxwell.Gym(Mesh(verts), r, q1=q1, m2=m2, c=c)
+    ref = np.sort(G.omega2())[::-1][:2]
+    assert np.allclose(w, ref, rtol=1e-9, atol=0), (w, ref)
+    assert abs(2 / np.sqrt(w[0]) - G.tau_cfl()) <= 1e-9 * G.tau_cfl()
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+
+
+def test_yee_32cube_omega_max_closed_form(g):
+    # Yee's method (Whitney forms, lumped masses) on a 32^3 box: the largest
+    # omega^2 is the Yee symbol at n_a = N_a - 1 on every axis, c^2 sum_a
+    # (2/h_a)^2 sin^2(pi (N_a - 1) / (2 N_a)), with two polarisations.
+    gym, ctx = g
+    nel, hi, c = (32, 32, 32), (1.0, 1.0, 1.0), 1.0
+    mesh, mx, _ = _maxwell(gym, ctx, nel, 1, "lumped", "lumped", c, hi, 0.0)
+    o = gym.gym_eig_opts_default()
+    o.nev, o.largest, o.block, o.tol = 2, 1, 4, 1e-10
+    w, info, st = gym.gym_maxwell_eigs(mx, o)
+    print(f"yee 32^3 omega_max^2 {w}, {info.iters} iterations", flush=True)
+    assert st == gym.GYM_OK
+    ref = c * c * sum((2 / (hi[a] / nel[a])) ** 2 * np.sin(np.pi * (nel[a] - 1) / (2 * nel[a])) ** 2 for a in range(3))
+    assert np.allclose(w, [ref, ref], rtol=1e-9, atol=0), (w, ref)
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+
+
 def test_small_grad_shift_is_reported(g):
     # With the gradients lifted by too little, the lowest pairs are gradients:
     # the solver says so instead of returning them as modes.
@@ -110,9 +153,9 @@ def test_small_grad_shift_is_reported(g):
 def test_eig_errors(g):
     gym, ctx = g
     mesh, mx, _ = _maxwell(gym, ctx, (2, 2, 2), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.0)
-    for nev, block in ((0, 0), (5, 4), (4, 9)):
+    for nev, block, largest in ((0, 0, 0), (5, 4, 0), (4, 9, 0), (2, 0, 2)):
         o = gym.gym_eig_opts_default()
-        o.nev, o.block = nev, block
+        o.nev, o.block, o.largest = nev, block, largest
         with pytest.raises(gym.GymError):
             gym.gym_maxwell_eigs(mx, o)
     gym.gym_maxwell_destroy(mx)
