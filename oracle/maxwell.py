@@ -18,8 +18,11 @@ composed here by Strang splitting Phi_tau = Phi^e_{tau/2} o Phi^a_tau o
 Phi^e_{tau/2} (eq. strangSplit), applied literally, one step after another.
 
 Choices of Q1 and M~2 (section 3 "Stability"; section 4.3 for the lumped
-ones): 'exact' (Q1 = M1^-1 applied by a sparse LU solve; M~2 = M2) or
-'lumped' (the inverse row sums of M1; the row sums of M2).  Row sums are
+ones; section 5 for the sparse approximate inverses): 'exact' (Q1 = M1^-1
+applied by a sparse LU solve; M~2 = M2), 'lumped' (the inverse row sums of
+M1; the row sums of M2), and for Q1 only 'spai_diag' / 'spai' (the
+symmetrised SPAI of M1 with the diagonal pattern S(1) or the pattern S(M1),
+oracle/spai.py).  Row sums are
 taken over the mass matrix of the space without boundary conditions and then
 restricted to the kept unknowns: section 4.3 lumps rows that sum to the cell
 volume, which the rows next to a perfect conductor only do before the
@@ -47,7 +50,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import assembly, incidence
+from . import assembly, incidence, spai
 from .lattice import Space
 
 
@@ -67,8 +70,8 @@ class Gym:
     """Generalized Yee method on a structured hexahedral mesh."""
 
     def __init__(self, mesh, r, q1="exact", m2="exact", c=1.0):
-        if q1 not in ("exact", "lumped") or m2 not in ("exact", "lumped"):
-            raise ValueError("q1 / m2: 'exact' or 'lumped'")
+        if q1 not in ("exact", "lumped", "spai_diag", "spai") or m2 not in ("exact", "lumped"):
+            raise ValueError("q1: 'exact', 'lumped', 'spai_diag' or 'spai'; m2: 'exact' or 'lumped'")
         self.mesh, self.r, self.c = mesh, r, float(c)
         self.q1_kind, self.m2_kind = q1, m2
         self.s1 = Space("HCURL", mesh.nel, r, "essential")
@@ -81,12 +84,17 @@ class Gym:
         M2t = self.M2 if m2 == "exact" else sp.diags(self.rs2)
         self.P2 = (self.c ** 2 * (self.C.T @ M2t @ self.C)).tocsr()
         self._lu = spla.splu(self.M1) if q1 == "exact" else None
+        self.Q1 = None
+        if q1.startswith("spai"):
+            self.Q1 = spai.spai(self.M1, "diag" if q1 == "spai_diag" else "m")
         self.n = self.s1.ndofs
 
     def q1(self, e):
-        """Q1 e: M1^-1 e (exact) or e / rowsum(M1) (lumped)."""
+        """Q1 e: M1^-1 e (exact), e / rowsum(M1) (lumped) or the SPAI times e."""
         if self._lu is not None:
             return self._lu.solve(e)
+        if self.Q1 is not None:
+            return self.Q1 @ e
         return e / self.rs1
 
     def p2(self, a):
@@ -108,6 +116,8 @@ class Gym:
     def q1_dense(self):
         if self._lu is not None:
             return np.linalg.inv(self.M1.toarray())
+        if self.Q1 is not None:
+            return self.Q1.toarray()
         return np.diag(1.0 / self.rs1)
 
     def jacobian(self, tau):
@@ -125,6 +135,13 @@ class Gym:
         """Eigenvalues omega^2 of K~ = Q1 P2 (ascending): P2 v = omega^2 Q1^-1 v."""
         if self._lu is not None:
             return sla.eigh(self.P2.toarray(), self.M1.toarray(), eigvals_only=True)
+        if self.Q1 is not None:
+            # Q1 P2 is similar to Q1^1/2 P2 Q1^1/2 when Q1 is positive definite
+            wq, V = np.linalg.eigh(self.Q1.toarray())
+            if wq.min() <= 0:
+                raise ValueError("the SPAI is not positive definite")
+            Qh = (V * np.sqrt(wq)) @ V.T
+            return np.linalg.eigvalsh(Qh @ self.P2.toarray() @ Qh)
         d = 1.0 / np.sqrt(self.rs1)
         return np.linalg.eigvalsh(d[:, None] * self.P2.toarray() * d[None, :])
 
