@@ -226,6 +226,11 @@ int gym_mass_solve(const gym_space* space, const gym_solve_opts* opts,
  * eigenvalue of Q1 P2 (Proposition Stability). */
 #define GYM_Q1_EXACT  0  /* Q1 = M1^-1, applied by a CG mass solve           */
 #define GYM_Q1_LUMPED 1  /* inverse row sums of M1 (section 4.3; affine only) */
+#define GYM_Q1_SPAI_DIAG 2 /* symmetrised SPAI of M1, diagonal pattern S(1)
+                              (section 5; affine only)                       */
+#define GYM_Q1_SPAI   3  /* symmetrised SPAI of M1, pattern S(M1): columns
+                            q_l = argmin ||M1[:, I_l] q - e_l||_2, then
+                            (Q + Q^T)/2 (section 5; affine only)            */
 #define GYM_M2_EXACT  0  /* M2~ = M2                                         */
 #define GYM_M2_LUMPED 1  /* row sums of M2 (affine only)                     */
 /* Lumped row sums are those of the mass matrix without boundary conditions,
@@ -241,7 +246,7 @@ typedef struct gym_maxwell_opts {
 /* Defaults: exact Q1 and M2~, c = 1, cg_rtol 1e-14, cg_maxit 1000. */
 void gym_maxwell_opts_default(gym_maxwell_opts* opts);
 /* Errors: GYM_E_ARG (not 3-D, degree outside 1..4, bad option),
- * GYM_E_UNSUPPORTED (lumped masses on a curved mesh), GYM_E_OOM. */
+ * GYM_E_UNSUPPORTED (lumped masses or a SPAI on a curved mesh), GYM_E_OOM. */
 int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree,
                        const gym_maxwell_opts* opts, gym_maxwell** out);
 /* Unknowns of a and of e (each). */
@@ -295,7 +300,8 @@ void gym_eig_opts_default(gym_eig_opts* opts);
  * per call and synchronises the stream.  Returns GYM_W_NOT_CONVERGED if the
  * cap came first, or if a wanted pair is a gradient (grad_shift too small,
  * info->gradient_modes > 0); GYM_E_ARG for bad options; GYM_E_BREAKDOWN if
- * the search space lost rank; GYM_E_OOM. */
+ * the search space lost rank; GYM_E_UNSUPPORTED for a SPAI Q1 (its inverse,
+ * the B of the generalized problem, is not available); GYM_E_OOM. */
 int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, double* vecs,
                      gym_eig_info* info, void* stream);
 

@@ -21,6 +21,7 @@
 #include "gym_internal.hpp"
 #include "eig.hpp"
 #include "krylov.hpp"
+#include "spai.hpp"
 #include "yee.hpp"
 
 using namespace gym;
@@ -38,6 +39,8 @@ struct gym_maxwell {
   double *q = nullptr, *t = nullptr;      // n1: Q1 e, C^T M2~ C a
   double *b = nullptr, *mb = nullptr;     // n2: C a, M2~ C a
   double *part = nullptr, *sums = nullptr;
+  SpaiParams spai{};   // SPAI Q1: its 1-D factors
+  double* spai_mem = nullptr;
   bool fused = false;  // both masses lumped: one stencil kernel per step
   YeeParams yp{};      // its fixed parameters (1-D row sums in w)
 };
@@ -46,6 +49,10 @@ namespace {
 
 // q = Q1 e
 int apply_q1(gym_maxwell* mx, const double* e, double* q, hipStream_t s, int* warn) {
+  if (mx->o.q1 == GYM_Q1_SPAI_DIAG || mx->o.q1 == GYM_Q1_SPAI) {
+    launch_spai_apply(mx->spai, e, q, mx->nb1, s);
+    return 0;
+  }
   if (mx->o.q1 == GYM_Q1_LUMPED) {
     launch_axpy_diag(q, 0.0, 1.0, mx->q1d, e, mx->n1, mx->nb1, s);
     return 0;
@@ -95,11 +102,12 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
   else gym_maxwell_opts_default(&o);
   if (mesh->dim != 3) return fail(GYM_E_ARG, "time stepping is 3-D");
   if (degree < 1 || degree > 4) return fail(GYM_E_ARG, "degree must be 1..4");
-  if ((o.q1 != GYM_Q1_EXACT && o.q1 != GYM_Q1_LUMPED) || (o.m2 != GYM_M2_EXACT && o.m2 != GYM_M2_LUMPED) ||
+  if ((o.q1 != GYM_Q1_EXACT && o.q1 != GYM_Q1_LUMPED && o.q1 != GYM_Q1_SPAI_DIAG && o.q1 != GYM_Q1_SPAI) ||
+      (o.m2 != GYM_M2_EXACT && o.m2 != GYM_M2_LUMPED) ||
       !(o.c > 0) || !(o.cg_rtol > 0) || o.cg_maxit < 1)
     return fail(GYM_E_ARG, "bad time-stepping options");
-  if (mesh->curved && (o.q1 == GYM_Q1_LUMPED || o.m2 == GYM_M2_LUMPED))
-    return fail(GYM_E_UNSUPPORTED, "lumped masses need an affine mesh");
+  if (mesh->curved && (o.q1 != GYM_Q1_EXACT || o.m2 == GYM_M2_LUMPED))
+    return fail(GYM_E_UNSUPPORTED, "lumped masses and the SPAI need an affine mesh");
   gym_maxwell* mx = new gym_maxwell;
   mx->ctx = ctx;
   mx->mesh = mesh;
@@ -175,6 +183,12 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
     if (hipMemcpy(mx->q1d, d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice) != hipSuccess) {
       gym_maxwell_destroy(mx);
       return fail(GYM_E_HIP, "time stepping: upload failed");
+    }
+  }
+  if (o.q1 == GYM_Q1_SPAI_DIAG || o.q1 == GYM_Q1_SPAI) {
+    if (int rc2 = build_spai_q1(mx->s1, o.q1 == GYM_Q1_SPAI ? 1 : 0, &mx->spai, &mx->spai_mem)) {
+      gym_maxwell_destroy(mx);
+      return rc2;
     }
   }
   if (o.m2 == GYM_M2_LUMPED) {
@@ -264,6 +278,8 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   if (o.nev < 1 || k < o.nev || 3 * k > kEigMaxCols || !(o.tol > 0) || o.maxit < 1 || !(o.grad_shift > 0) ||
       (o.largest != 0 && o.largest != 1))
     return fail(GYM_E_ARG, "bad eigen-solver options (1 <= nev <= block <= 8)");
+  if (mx->o.q1 == GYM_Q1_SPAI_DIAG || mx->o.q1 == GYM_Q1_SPAI)
+    return fail(GYM_E_UNSUPPORTED, "eigen-solver: needs Q1^-1, which the SPAI does not provide");
   hipStream_t s = (hipStream_t)stream;
   const long long n1 = mx->n1;
   if (n1 < 3LL * k) return fail(GYM_E_ARG, "eigen-solver: fewer unknowns than the search space needs");
@@ -397,6 +413,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
 int gym_maxwell_destroy(gym_maxwell* mx) {
   if (!mx) return GYM_OK;
   if (mx->mem) (void)hipFree(mx->mem);
+  if (mx->spai_mem) (void)hipFree(mx->spai_mem);
   if (mx->s1) gym_space_destroy(mx->s1);
   if (mx->s2) gym_space_destroy(mx->s2);
   delete mx;

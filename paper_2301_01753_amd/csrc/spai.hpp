@@ -1,0 +1,43 @@
+// Sparse approximate inverse Q1 of the Lambda^1 mass matrix on affine,
+// axis-aligned meshes (paper section 5), as used by the time stepping.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+struct gym_space;
+
+namespace gym {
+
+// One component block of Q1 (a component of Lambda^1 couples to no other on
+// axis-aligned cells):
+//   y = scale (Q_x (x) Q_y (x) Q_z + Q_x^T (x) Q_y^T (x) Q_z^T) x,
+// the symmetrised Kronecker product of 1-D banded factors.  band[t][a]:
+// count[a] rows of 2w + 1 entries, row i holding (Q_a)_{i, i+k} (t = 0) or
+// (Q_a^T)_{i, i+k} (t = 1) at k + w, k = -w..w, zero outside the matrix.
+struct SpaiComp {
+  long long offset;  // first unknown of the block
+  int count[3];      // kept lattice positions per axis
+  int w;             // half bandwidth of the 1-D factors
+  double scale;
+  const double* band[2][3];
+};
+struct SpaiParams {
+  SpaiComp c[3];
+  long long n;  // unknowns of Lambda^1
+};
+
+// Builds Q1 = (Q + Q^T) / 2, Q the column-wise least-squares SPAI of M1 with
+// the diagonal pattern (pattern 0) or the pattern of M1 (pattern 1).  On an
+// axis-aligned box M1's block of component c is s_c M_x (x) M_y (x) M_z
+// (1-D assembled masses, edge along c and nodal along the other axes,
+// restricted to the kept positions), both patterns are Kronecker products
+// of 1-D patterns, and each column's normal equations are the Kronecker
+// product of 1-D normal equations: so Q's block is (1/s_c) Q_x (x) Q_y (x) Q_z
+// with Q_a the 1-D SPAI of M_a.  The bands go to one device allocation,
+// returned in *mem (the caller frees it).
+int build_spai_q1(const gym_space* s1, int pattern, SpaiParams* out, double** mem);
+// y = Q1 x
+void launch_spai_apply(const SpaiParams& p, const double* x, double* y, int nb, hipStream_t s);
+
+}  // namespace gym

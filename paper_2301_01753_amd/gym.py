@@ -29,7 +29,7 @@ GYM_F64, GYM_F32, GYM_BF16 = 0, 1, 2
 GYM_MIXED_POISSON, GYM_HODGE1 = 0, 1
 GYM_MINRES, GYM_CG = 0, 1
 GYM_MODE_F64, GYM_MODE_IR_F32, GYM_MODE_IR_BF16 = 0, 1, 2
-GYM_Q1_EXACT, GYM_Q1_LUMPED = 0, 1
+GYM_Q1_EXACT, GYM_Q1_LUMPED, GYM_Q1_SPAI_DIAG, GYM_Q1_SPAI = 0, 1, 2, 3
 GYM_M2_EXACT, GYM_M2_LUMPED = 0, 1
 
 KIND = {"H1": GYM_H1, "HCURL": GYM_HCURL, "HDIV": GYM_HDIV, "L2": GYM_L2}

@@ -160,3 +160,13 @@ def test_eig_errors(g):
             gym.gym_maxwell_eigs(mx, o)
     gym.gym_maxwell_destroy(mx)
     gym.gym_mesh_destroy(mesh)
+    # a SPAI Q1 has no inverse to serve as B
+    mesh, mx, _ = _maxwell(gym, ctx, (3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.0)
+    gym.gym_maxwell_destroy(mx)
+    o = gym.gym_maxwell_opts_default()
+    o.q1 = gym.GYM_Q1_SPAI
+    mx = gym.gym_maxwell_create(ctx, mesh, 1, o)
+    with pytest.raises(gym.GymError):
+        gym.gym_maxwell_eigs(mx, gym.gym_eig_opts_default())
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)

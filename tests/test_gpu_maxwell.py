@@ -37,7 +37,8 @@ def _setup(gym, ctx, nel, r, q1, m2, c=1.0, hi=(1.0, 1.0, 1.0), perturb=0.0):
     verts = synth.perturbed_vertices(nel, perturb, seed=5, hi=hi) if perturb else synth.uniform_vertices(nel, hi=hi)
     mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts if perturb else None, hi=hi)
     o = gym.gym_maxwell_opts_default()
-    o.q1 = gym.GYM_Q1_EXACT if q1 == "exact" else gym.GYM_Q1_LUMPED
+    o.q1 = {"exact": gym.GYM_Q1_EXACT, "lumped": gym.GYM_Q1_LUMPED, "spai_diag": gym.GYM_Q1_SPAI_DIAG,
+            "spai": gym.GYM_Q1_SPAI}[q1]
     o.m2 = gym.GYM_M2_EXACT if m2 == "exact" else gym.GYM_M2_LUMPED
     o.c = c
     mx = gym.gym_maxwell_create(ctx, mesh, r, o)
@@ -55,7 +56,13 @@ CASES = [((4, 3, 5), 1, "lumped", "lumped", 1.3, (1.0, 0.9, 1.3), 0.0, 1e-13),
          ((3, 3, 2), 2, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.0, 1e-10),
          ((3, 2, 3), 2, "lumped", "exact", 0.7, (1.0, 1.2, 1.0), 0.0, 1e-13),
          ((2, 3, 2), 3, "exact", "lumped", 1.0, (1.0, 1.0, 1.0), 0.0, 1e-10),
-         ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15, 1e-10)]
+         ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15, 1e-10),
+         # sparse approximate inverses of M1 (section 5): Kronecker-factored on the GPU,
+         # column-wise least squares on the assembled M1 in the oracle
+         ((3, 2, 3), 1, "spai", "exact", 1.0, (1.0, 1.1, 1.0), 0.0, 1e-12),
+         ((2, 3, 2), 2, "spai_diag", "lumped", 0.9, (1.0, 1.0, 1.2), 0.0, 1e-12),
+         ((2, 2, 3), 2, "spai", "lumped", 1.0, (1.0, 1.0, 1.0), 0.0, 1e-12),
+         ((2, 2, 2), 3, "spai", "exact", 1.0, (0.8, 1.0, 1.0), 0.0, 1e-12)]
 
 
 @pytest.mark.parametrize("nel,r,q1,m2,c,hi,perturb,tol", CASES)
@@ -198,6 +205,10 @@ def test_errors(g):
     o = gym.gym_maxwell_opts_default()
     with pytest.raises(gym.GymError):
         gym.gym_maxwell_create(ctx, mesh, 5, o)
+    o.q1 = gym.GYM_Q1_SPAI
+    with pytest.raises(gym.GymError):  # the SPAI needs an affine mesh
+        gym.gym_maxwell_create(ctx, mesh, 1, o)
+    o = gym.gym_maxwell_opts_default()
     mx = gym.gym_maxwell_create(ctx, mesh, 1, o)
     n = gym.gym_maxwell_ndofs(mx)
     a = torch.zeros(n, dtype=torch.float64, device=DEV)
