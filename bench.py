@@ -219,13 +219,14 @@ def workload_rates(gym, ctx, which, N, r, perturb, nrhs, steps, seed):
 
 def maxwell_rates(gym, ctx, N, r, q1, steps):
     """Strang steps per second of the generalized Yee time stepping on an
-    N^3 unit box (perfect conductor), lumped or exact Q1, exact M2~ unless
-    Q1 is lumped (then both lumped: Yee's method for r = 1)."""
+    N^3 unit box (perfect conductor), lumped, exact or SPAI (pattern S(M1))
+    Q1, exact M2~ unless Q1 is lumped (then both lumped: Yee's method for
+    r = 1)."""
     import torch
     mesh = gym.gym_mesh_create(ctx, 3, (N, N, N))
     o = gym.gym_maxwell_opts_default()
     lumped = q1 == "lumped"
-    o.q1 = gym.GYM_Q1_LUMPED if lumped else gym.GYM_Q1_EXACT
+    o.q1 = {"lumped": gym.GYM_Q1_LUMPED, "exact": gym.GYM_Q1_EXACT, "spai": gym.GYM_Q1_SPAI}[q1]
     o.m2 = gym.GYM_M2_LUMPED if lumped else gym.GYM_M2_EXACT
     mx = gym.gym_maxwell_create(ctx, mesh, r, o)
     n = gym.gym_maxwell_ndofs(mx)
@@ -546,6 +547,8 @@ def main():
             "yee_r1_128cube_lumped": maxwell_rates(gym, ctx, 128, 1, "lumped", 2000),
             "r2_32cube_lumped": maxwell_rates(gym, ctx, 32, 2, "lumped", 2000),
             "r2_32cube_exact_q1_cg": maxwell_rates(gym, ctx, 32, 2, "exact", 20),
+            "r1_128cube_spai_q1": maxwell_rates(gym, ctx, 128, 1, "spai", 200),
+            "r2_32cube_spai_q1": maxwell_rates(gym, ctx, 32, 2, "spai", 500),
         }
         log("eigenmodes ...")
         ext["gym_eigenmodes"] = {
