@@ -300,8 +300,8 @@ void gym_eig_opts_default(gym_eig_opts* opts);
  * per call and synchronises the stream.  Returns GYM_W_NOT_CONVERGED if the
  * cap came first, or if a wanted pair is a gradient (grad_shift too small,
  * info->gradient_modes > 0); GYM_E_ARG for bad options; GYM_E_BREAKDOWN if
- * the search space lost rank; GYM_E_UNSUPPORTED for a SPAI Q1 (its inverse,
- * the B of the generalized problem, is not available); GYM_E_OOM. */
+ * the search space lost rank (or a SPAI Q1 is not positive definite);
+ * GYM_E_OOM.  A SPAI Q1 enters as B = Q1^-1 through CG solves with Q1. */
 int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, double* vecs,
                      gym_eig_info* info, void* stream);
 

@@ -278,13 +278,12 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   if (o.nev < 1 || k < o.nev || 3 * k > kEigMaxCols || !(o.tol > 0) || o.maxit < 1 || !(o.grad_shift > 0) ||
       (o.largest != 0 && o.largest != 1))
     return fail(GYM_E_ARG, "bad eigen-solver options (1 <= nev <= block <= 8)");
-  if (mx->o.q1 == GYM_Q1_SPAI_DIAG || mx->o.q1 == GYM_Q1_SPAI)
-    return fail(GYM_E_UNSUPPORTED, "eigen-solver: needs Q1^-1, which the SPAI does not provide");
   hipStream_t s = (hipStream_t)stream;
   const long long n1 = mx->n1;
   if (n1 < 3LL * k) return fail(GYM_E_ARG, "eigen-solver: fewer unknowns than the search space needs");
   const double c2 = mx->o.c * mx->o.c;
   const bool lumped = mx->o.q1 == GYM_Q1_LUMPED;
+  const bool spai_q1 = mx->o.q1 == GYM_Q1_SPAI_DIAG || mx->o.q1 == GYM_Q1_SPAI;
   gym_space* s0 = nullptr;  // Lambda^0 with the conductor's boundary values removed
   if (int rc = gym_space_create(mx->ctx, mx->mesh, GYM_H1, mx->s1->desc.r, GYM_BC_ESSENTIAL, &s0)) return rc;
   const long long n0 = gym_space_ndofs(s0);
@@ -312,7 +311,8 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   double* dB = alloc(n1);    // lumped: the row sums of M1 (B itself)
   double* dT = alloc(n1);    // their inverses (the preconditioner)
   double* gw = alloc(eig_gram_work(nb1));
-  if (!X || !bx || !gp || !bgp || !g0 || !phi || !dB || !dT || !gw) {
+  double* cgw = spai_q1 ? alloc(3 * n1 * k) : nullptr;  // CG work of B = Q1^-1
+  if (!X || !bx || !gp || !bgp || !g0 || !phi || !dB || !dT || !gw || (spai_q1 && !cgw)) {
     cleanup();
     return fail(GYM_E_OOM, "eigen-solver: device allocation failed");
   }
@@ -328,15 +328,64 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   auto colp = [](double* b, long long n, int j) { return b + (long long)j * n; };
   int warn = 0;
   EigOperators ops;
-  // B = Q1^-1: M1, or its row sums when lumped
+  // B = Q1^-1 for a SPAI Q1: CG on Q1 (symmetric positive definite, close to
+  // M1^-1, so well conditioned), every column to relative residual 1e-13
+  auto spai_inverse = [&](const double* x, double* y, int ncol) -> int {
+    double* r = cgw;
+    double* p = cgw + n1 * ncol;
+    double* q = cgw + 2 * n1 * ncol;
+    const long long nc = n1 * ncol;
+    if (hipMemcpyAsync(r, x, sizeof(double) * nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(p, x, sizeof(double) * nc, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemsetAsync(y, 0, sizeof(double) * nc, s) != hipSuccess)
+      return hip_fail(hipGetLastError(), "SPAI inverse");
+    std::vector<double> G((size_t)ncol * ncol), rr(ncol), rr0(ncol);
+    if (eig_gram(r, ncol, r, ncol, n1, G.data(), gw, nb1, s)) return hip_fail(hipGetLastError(), "SPAI inverse");
+    for (int j = 0; j < ncol; ++j) rr[j] = rr0[j] = G[(size_t)j * ncol + j];
+    for (int it = 0; it < 2000; ++it) {
+      bool done = true;
+      for (int j = 0; j < ncol; ++j)
+        if (rr[j] > 1e-26 * rr0[j]) done = false;
+      if (done) return 0;
+      for (int j = 0; j < ncol; ++j) launch_spai_apply(mx->spai, colp(p, n1, j), colp(q, n1, j), nb1, s);
+      if (eig_gram(p, ncol, q, ncol, n1, G.data(), gw, nb1, s)) return hip_fail(hipGetLastError(), "SPAI inverse");
+      for (int j = 0; j < ncol; ++j) {
+        const double pq = G[(size_t)j * ncol + j];
+        if (!(pq > 0)) {
+          if (rr[j] == 0.0) continue;
+          return fail(GYM_E_BREAKDOWN, "eigen-solver: the SPAI Q1 is not positive definite");
+        }
+        const double al = rr[j] / pq;
+        launch_axpy_diag(colp(y, n1, j), 1.0, al, nullptr, colp(p, n1, j), n1, nb1, s);
+        launch_axpy_diag(colp(r, n1, j), 1.0, -al, nullptr, colp(q, n1, j), n1, nb1, s);
+      }
+      if (eig_gram(r, ncol, r, ncol, n1, G.data(), gw, nb1, s)) return hip_fail(hipGetLastError(), "SPAI inverse");
+      for (int j = 0; j < ncol; ++j) {
+        const double rn = G[(size_t)j * ncol + j];
+        const double be = rr[j] > 0 ? rn / rr[j] : 0.0;
+        rr[j] = rn;
+        launch_axpy_diag(colp(p, n1, j), be, 1.0, nullptr, colp(r, n1, j), n1, nb1, s);
+      }
+    }
+    warn = 1;
+    return 0;
+  };
+  // B = Q1^-1: M1, its row sums when lumped, or the inverse of a SPAI
   ops.B = [&](const double* x, double* y, int ncol) -> int {
+    if (spai_q1) return spai_inverse(x, y, ncol);
     if (!lumped) return gym_mass_apply(mx->s1, GYM_F64, ncol, x, y, s);
     for (int j = 0; j < ncol; ++j)
       launch_axpy_diag(colp(y, n1, j), 0.0, 1.0, dB, colp(const_cast<double*>(x), n1, j), n1, nb1, s);
     return 0;
   };
-  // T: inverse row sums of M1
+  // T: Q1 itself for a SPAI (it approximates B^-1 = Q1 exactly); otherwise
+  // the inverse row sums of M1
   ops.T = [&](const double* x, double* y, int ncol) -> int {
+    if (spai_q1) {
+      for (int j = 0; j < ncol; ++j)
+        launch_spai_apply(mx->spai, colp(const_cast<double*>(x), n1, j), colp(y, n1, j), nb1, s);
+      return 0;
+    }
     for (int j = 0; j < ncol; ++j)
       launch_axpy_diag(colp(y, n1, j), 0.0, 1.0, dT, colp(const_cast<double*>(x), n1, j), n1, nb1, s);
     return 0;
