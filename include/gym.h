@@ -228,6 +228,7 @@ int gym_mass_solve(const gym_space* space, const gym_solve_opts* opts,
 #define GYM_Q1_LUMPED 1  /* inverse row sums of M1 (section 4.3; affine only) */
 #define GYM_Q1_SPAI_DIAG 2 /* symmetrised SPAI of M1, diagonal pattern S(1)
                               (section 5; affine only)                       */
+#define GYM_Q1_SPAI_OP 4 /* SPAI-OP (set by gym_maxwell_spai_op only)        */
 #define GYM_Q1_SPAI   3  /* symmetrised SPAI of M1, pattern S(M1): columns
                             q_l = argmin ||M1[:, I_l] q - e_l||_2, then
                             (Q + Q^T)/2 (section 5; affine only)            */
@@ -249,6 +250,19 @@ void gym_maxwell_opts_default(gym_maxwell_opts* opts);
  * GYM_E_UNSUPPORTED (lumped masses or a SPAI on a curved mesh), GYM_E_OOM. */
 int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree,
                        const gym_maxwell_opts* opts, gym_maxwell** out);
+/* SPAI-OP (section 5, eqs. SPAIOPobjective to diagonalPreconditioner): the
+ * symmetric Q1 on the pattern of M1 minimising ||M1 Q1 - 1||_F^2 +
+ * lambda sum_k ||(M1 Q1 - 1) P2 v_k||^2, from the generalized Sylvester
+ * equations (U Q1 T + T Q1 U)_ij = (M1 T + T M1)_ij on the pattern, U = M1^2,
+ * T = 1 + lambda W W^T, W = P2 V, solved matrix-free by Jacobi-preconditioned
+ * CG from the symmetrised column-wise SPAI (Tikhonov shift 1e-12 max diag U).
+ * probes: device array of nprobe x ndofs doubles, the modes v_k (nprobe may be
+ * 0: the optimal symmetric SPAI).  On success the object's Q1 becomes this
+ * SPAI-OP (GYM_Q1_SPAI_OP) for the time stepping, the energy and the
+ * eigen-solver.  Affine meshes only.  Returns GYM_W_NOT_CONVERGED (Q1 is
+ * still replaced) if maxit came before rtol; *iters and *rel_res may be NULL. */
+int gym_maxwell_spai_op(gym_maxwell* mx, int nprobe, const double* probes, double lambda, double rtol,
+                        int maxit, int* iters, double* rel_res, void* stream);
 /* Unknowns of a and of e (each). */
 int64_t gym_maxwell_ndofs(const gym_maxwell* mx);
 /* nsteps Strang steps of length tau on device vectors a and e (ndofs

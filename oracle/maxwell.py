@@ -22,7 +22,7 @@ ones; section 5 for the sparse approximate inverses): 'exact' (Q1 = M1^-1
 applied by a sparse LU solve; M~2 = M2), 'lumped' (the inverse row sums of
 M1; the row sums of M2), and for Q1 only 'spai_diag' / 'spai' (the
 symmetrised SPAI of M1 with the diagonal pattern S(1) or the pattern S(M1),
-oracle/spai.py).  Row sums are
+oracle/spai.py) or an explicit symmetric matrix (SPAI-OP, oracle/spai_op.py).  Row sums are
 taken over the mass matrix of the space without boundary conditions and then
 restricted to the kept unknowns: section 4.3 lumps rows that sum to the cell
 volume, which the rows next to a perfect conductor only do before the
@@ -70,10 +70,11 @@ class Gym:
     """Generalized Yee method on a structured hexahedral mesh."""
 
     def __init__(self, mesh, r, q1="exact", m2="exact", c=1.0):
-        if q1 not in ("exact", "lumped", "spai_diag", "spai") or m2 not in ("exact", "lumped"):
-            raise ValueError("q1: 'exact', 'lumped', 'spai_diag' or 'spai'; m2: 'exact' or 'lumped'")
+        given = sp.issparse(q1) or isinstance(q1, np.ndarray)
+        if (not given and q1 not in ("exact", "lumped", "spai_diag", "spai")) or m2 not in ("exact", "lumped"):
+            raise ValueError("q1: 'exact', 'lumped', 'spai_diag', 'spai' or a matrix; m2: 'exact' or 'lumped'")
         self.mesh, self.r, self.c = mesh, r, float(c)
-        self.q1_kind, self.m2_kind = q1, m2
+        self.q1_kind, self.m2_kind = ("given" if given else q1), m2
         self.s1 = Space("HCURL", mesh.nel, r, "essential")
         self.s2 = Space("HDIV", mesh.nel, r, "natural")
         self.M1 = assembly.mass_matrix(self.s1, mesh).tocsc()
@@ -83,9 +84,11 @@ class Gym:
         self.rs2 = _kept_row_sums(self.s2, mesh)
         M2t = self.M2 if m2 == "exact" else sp.diags(self.rs2)
         self.P2 = (self.c ** 2 * (self.C.T @ M2t @ self.C)).tocsr()
-        self._lu = spla.splu(self.M1) if q1 == "exact" else None
+        self._lu = spla.splu(self.M1) if self.q1_kind == "exact" else None
         self.Q1 = None
-        if q1.startswith("spai"):
+        if given:  # an explicit symmetric Q1 (e.g. SPAI-OP, oracle/spai_op.py)
+            self.Q1 = sp.csr_matrix(q1)
+        elif q1.startswith("spai"):
             self.Q1 = spai.spai(self.M1, "diag" if q1 == "spai_diag" else "m")
         self.n = self.s1.ndofs
 

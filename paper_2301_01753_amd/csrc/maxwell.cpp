@@ -22,6 +22,7 @@
 #include "eig.hpp"
 #include "krylov.hpp"
 #include "spai.hpp"
+#include "spai_op.hpp"
 #include "yee.hpp"
 
 using namespace gym;
@@ -41,6 +42,7 @@ struct gym_maxwell {
   double *part = nullptr, *sums = nullptr;
   SpaiParams spai{};   // SPAI Q1: its 1-D factors
   double* spai_mem = nullptr;
+  SpaiOpQ1 spai_op;    // SPAI-OP Q1 (set by gym_maxwell_spai_op)
   bool fused = false;  // both masses lumped: one stencil kernel per step
   YeeParams yp{};      // its fixed parameters (1-D row sums in w)
 };
@@ -48,9 +50,19 @@ struct gym_maxwell {
 namespace {
 
 // q = Q1 e
+bool sparse_q1(const gym_maxwell* mx) {
+  return mx->o.q1 == GYM_Q1_SPAI_DIAG || mx->o.q1 == GYM_Q1_SPAI || mx->o.q1 == GYM_Q1_SPAI_OP;
+}
+
+// q = Q1 e for the sparse approximate inverses
+void apply_sparse_q1(gym_maxwell* mx, const double* e, double* q, hipStream_t s) {
+  if (mx->o.q1 == GYM_Q1_SPAI_OP) launch_spai_op_apply(mx->spai_op, e, q, mx->ctx->ncu, s);
+  else launch_spai_apply(mx->spai, e, q, mx->nb1, s);
+}
+
 int apply_q1(gym_maxwell* mx, const double* e, double* q, hipStream_t s, int* warn) {
-  if (mx->o.q1 == GYM_Q1_SPAI_DIAG || mx->o.q1 == GYM_Q1_SPAI) {
-    launch_spai_apply(mx->spai, e, q, mx->nb1, s);
+  if (sparse_q1(mx)) {
+    apply_sparse_q1(mx, e, q, s);
     return 0;
   }
   if (mx->o.q1 == GYM_Q1_LUMPED) {
@@ -283,7 +295,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   if (n1 < 3LL * k) return fail(GYM_E_ARG, "eigen-solver: fewer unknowns than the search space needs");
   const double c2 = mx->o.c * mx->o.c;
   const bool lumped = mx->o.q1 == GYM_Q1_LUMPED;
-  const bool spai_q1 = mx->o.q1 == GYM_Q1_SPAI_DIAG || mx->o.q1 == GYM_Q1_SPAI;
+  const bool spai_q1 = sparse_q1(mx);
   gym_space* s0 = nullptr;  // Lambda^0 with the conductor's boundary values removed
   if (int rc = gym_space_create(mx->ctx, mx->mesh, GYM_H1, mx->s1->desc.r, GYM_BC_ESSENTIAL, &s0)) return rc;
   const long long n0 = gym_space_ndofs(s0);
@@ -347,7 +359,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
       for (int j = 0; j < ncol; ++j)
         if (rr[j] > 1e-26 * rr0[j]) done = false;
       if (done) return 0;
-      for (int j = 0; j < ncol; ++j) launch_spai_apply(mx->spai, colp(p, n1, j), colp(q, n1, j), nb1, s);
+      for (int j = 0; j < ncol; ++j) apply_sparse_q1(mx, colp(p, n1, j), colp(q, n1, j), s);
       if (eig_gram(p, ncol, q, ncol, n1, G.data(), gw, nb1, s)) return hip_fail(hipGetLastError(), "SPAI inverse");
       for (int j = 0; j < ncol; ++j) {
         const double pq = G[(size_t)j * ncol + j];
@@ -382,8 +394,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   // the inverse row sums of M1
   ops.T = [&](const double* x, double* y, int ncol) -> int {
     if (spai_q1) {
-      for (int j = 0; j < ncol; ++j)
-        launch_spai_apply(mx->spai, colp(const_cast<double*>(x), n1, j), colp(y, n1, j), nb1, s);
+      for (int j = 0; j < ncol; ++j) apply_sparse_q1(mx, colp(const_cast<double*>(x), n1, j), colp(y, n1, j), s);
       return 0;
     }
     for (int j = 0; j < ncol; ++j)
@@ -459,10 +470,54 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   return (rc == 1 || warn) ? GYM_W_NOT_CONVERGED : GYM_OK;
 }
 
+int gym_maxwell_spai_op(gym_maxwell* mx, int nprobe, const double* probes, double lambda, double rtol, int maxit,
+                        int* iters, double* rel_res, void* stream) {
+  if (!mx || nprobe < 0 || (nprobe > 0 && !probes) || !(lambda >= 0) || !(rtol > 0) || maxit < 1)
+    return fail(GYM_E_ARG, "bad SPAI-OP arguments");
+  if (mx->mesh->curved) return fail(GYM_E_UNSUPPORTED, "SPAI-OP needs an affine mesh");
+  hipStream_t s = (hipStream_t)stream;
+  const long long n1 = mx->n1;
+  const double c2 = mx->o.c * mx->o.c;
+  double* W = nullptr;
+  if (hipMalloc(&W, sizeof(double) * 2 * std::max(1, nprobe) * n1) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(GYM_E_OOM, "SPAI-OP: device allocation failed");
+  }
+  double* MW = W + (long long)std::max(1, nprobe) * n1;
+  // the probing vectors P2 v_k and M1 P2 v_k
+  for (int k = 0; k < nprobe; ++k) {
+    if (int rc = apply_p2(mx, probes + (long long)k * n1, s)) {
+      (void)hipFree(W);
+      return rc;
+    }
+    launch_axpy_diag(W + (long long)k * n1, 0.0, c2, nullptr, mx->t, n1, mx->nb1, s);
+  }
+  if (nprobe > 0) {
+    if (int rc = gym_mass_apply(mx->s1, GYM_F64, nprobe, W, MW, s)) {
+      (void)hipFree(W);
+      return rc;
+    }
+  }
+  SpaiOpQ1 Q;
+  int it = 0;
+  double rel = 0.0;
+  int rc = spai_op_build(mx->s1, W, MW, nprobe, lambda, rtol, maxit, mx->ctx->ncu, s, &Q, &it, &rel);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(W);
+  if (iters) *iters = it;
+  if (rel_res) *rel_res = rel;
+  if (rc < 0) return rc;
+  spai_op_free(&mx->spai_op);
+  mx->spai_op = Q;
+  mx->o.q1 = GYM_Q1_SPAI_OP;
+  return rc;
+}
+
 int gym_maxwell_destroy(gym_maxwell* mx) {
   if (!mx) return GYM_OK;
   if (mx->mem) (void)hipFree(mx->mem);
   if (mx->spai_mem) (void)hipFree(mx->spai_mem);
+  spai_op_free(&mx->spai_op);
   if (mx->s1) gym_space_destroy(mx->s1);
   if (mx->s2) gym_space_destroy(mx->s2);
   delete mx;

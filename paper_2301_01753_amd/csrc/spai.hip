@@ -8,7 +8,6 @@
 #include "krylov.hpp"
 
 namespace gym {
-namespace {
 
 // Assembled 1-D mass of nel elements of degree r (reference element: the
 // spacing sits in the metric constant), nodal (r nel + 1) or edge (r nel),
@@ -36,6 +35,8 @@ std::vector<double> mass1d_band(int r, int nel, bool nodal, int start, int count
       }
   return band;
 }
+
+namespace {
 
 // 1-D SPAI of the banded symmetric A (count x count, half width r): column l
 // minimises || A[:, I_l] q - e_l ||_2 over its pattern I_l ({l}, or the

@@ -40,4 +40,9 @@ int build_spai_q1(const gym_space* s1, int pattern, SpaiParams* out, double** me
 // y = Q1 x
 void launch_spai_apply(const SpaiParams& p, const double* x, double* y, int nb, hipStream_t s);
 
+// Assembled 1-D mass of nel elements of degree r on the reference element,
+// nodal (r nel + 1 positions) or edge (r nel), restricted to [start, start +
+// count): row-major band of half width r, A[i][k + r] = A_{i, i+k}.
+std::vector<double> mass1d_band(int r, int nel, bool nodal, int start, int count);
+
 }  // namespace gym

@@ -1,0 +1,452 @@
+// SPAI-OP, the operator-probed sparse approximate inverse of M1 (paper
+// section 5, eqs. SPAIOPobjective to diagonalPreconditioner), on axis-aligned
+// meshes.
+//
+// Q1 lives on S = S(M1): in a component block, row i couples to the j with
+// M1_ij != 0, a box of (2r + 1)^3 offsets of which the 1-D masses mark the
+// live ones.  The unknowns q are stored row by row, one slot per box offset
+// (dead slots stay zero).  The symmetric Q1 that minimises
+// ||M1 Q1 - 1||_F^2 + lambda sum_k ||(M1 Q1 - 1) W_k||^2, W = P2 V, solves
+// (U Q1 T + T Q1 U)_ij = R_ij on S with U = M1^2, T = 1 + lambda W W^T and
+// R = M1 T + T M1.  The operator is applied matrix-free:
+//   (U Q)_ij = sum_m U_im Q_mj over the m with Q_mj in the box of row m,
+//   (Q U)_ij = sum_m Q_im U_mj over the box of row i,
+// U_im a product of 1-D entries of M_a^2 (Kronecker structure of M1 per
+// component), and the rank-n_probe parts through X = U Q W and
+// Y = U Q^T W.  Jacobi-preconditioned CG solves it, started from the
+// symmetrised column-wise SPAI; one thread per (row, slot) in the operator,
+// one per row in the stencil applies.
+#include "spai_op.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "eig.hpp"
+#include "gym_internal.hpp"
+#include "krylov.hpp"
+#include "spai.hpp"
+
+namespace gym {
+namespace {
+
+struct OpComp {
+  long long off;         // first row of the block
+  int n[3];              // kept positions per axis
+  double sc;             // M1 block = sc (x)_a M_a
+  const double* M[3];    // n[a] x (2r + 1): M_a band
+  const double* M2[3];   // n[a] x (4r + 1): (M_a^2) band
+};
+
+struct SylvParams {
+  OpComp c[3];
+  long long n1;
+  int r;
+  int np;            // probes
+  const double* W;   // np x n1: P2 v_k
+  const double* X;   // np x n1: U Q W  (for the current direction)
+  const double* Y;   // np x n1: U Q^T W
+  const double* MW;  // np x n1: M1 W
+  double lam, eps;
+};
+
+__device__ __forceinline__ int comp_of(const SylvParams& p, long long g) {
+  return (g >= p.c[1].off) + (g >= p.c[2].off);
+}
+
+__device__ __forceinline__ void decode(const OpComp& d, long long g, int& x, int& y, int& z) {
+  const long long loc = g - d.off;
+  x = (int)(loc % d.n[0]);
+  const long long rest = loc / d.n[0];
+  y = (int)(rest % d.n[1]);
+  z = (int)(rest / d.n[1]);
+}
+
+__device__ __forceinline__ long long at(const OpComp& d, int x, int y, int z) {
+  return d.off + x + (long long)d.n[0] * (y + (long long)d.n[1] * z);
+}
+
+__device__ __forceinline__ bool inside(const OpComp& d, int x, int y, int z) {
+  return (unsigned)x < (unsigned)d.n[0] && (unsigned)y < (unsigned)d.n[1] && (unsigned)z < (unsigned)d.n[2];
+}
+
+// M1_ij / sc for j = i + (dx, dy, dz) (zero off the pattern)
+__device__ __forceinline__ double m1_rel(const OpComp& d, int r, int x, int y, int z, int dx, int dy, int dz) {
+  const int L = 2 * r + 1;
+  return d.M[0][(long long)x * L + dx + r] * d.M[1][(long long)y * L + dy + r] * d.M[2][(long long)z * L + dz + r];
+}
+
+// U_ij / sc^2 for j = i + (dx, dy, dz), |d_a| <= 2r
+__device__ __forceinline__ double u_rel(const OpComp& d, int r, int x, int y, int z, int dx, int dy, int dz) {
+  const int L2 = 4 * r + 1;
+  return d.M2[0][(long long)x * L2 + dx + 2 * r] * d.M2[1][(long long)y * L2 + dy + 2 * r] *
+         d.M2[2][(long long)z * L2 + dz + 2 * r];
+}
+
+__device__ __forceinline__ int slot(int r, int dx, int dy, int dz) {
+  const int L = 2 * r + 1;
+  return ((dz + r) * L + (dy + r)) * L + (dx + r);
+}
+
+// out = A q on S (+ eps q); one thread per (row, slot)
+__global__ void __launch_bounds__(256) sylv_apply(const SylvParams p, const double* __restrict__ q,
+                                                  double* __restrict__ out) {
+  const int r = p.r, L = 2 * r + 1, L3 = L * L * L;
+  const long long total = p.n1 * L3;
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+    const long long i = t / L3;
+    const int s = (int)(t - i * L3);
+    const int dx = s % L - r, dy = (s / L) % L - r, dz = s / (L * L) - r;
+    const OpComp& d = p.c[comp_of(p, i)];
+    int x, y, z;
+    decode(d, i, x, y, z);
+    if (m1_rel(d, r, x, y, z, dx, dy, dz) == 0.0) {
+      out[t] = 0.0;
+      continue;
+    }
+    const int jx = x + dx, jy = y + dy, jz = z + dz;
+    double uq = 0.0, qu = 0.0;
+    for (int ez = -r; ez <= r; ++ez)
+      for (int ey = -r; ey <= r; ++ey)
+        for (int ex = -r; ex <= r; ++ex) {
+          // (U Q)_ij: m = j - e, Q_mj in slot e of row m
+          const int mx = jx - ex, my = jy - ey, mz = jz - ez;
+          if (inside(d, mx, my, mz)) {
+            const double u = u_rel(d, r, x, y, z, mx - x, my - y, mz - z);
+            if (u != 0.0) uq += u * q[at(d, mx, my, mz) * L3 + slot(r, ex, ey, ez)];
+          }
+          // (Q U)_ij: m = i + e, Q_im in slot e of row i
+          const int nx = x + ex, ny = y + ey, nz = z + ez;
+          if (inside(d, nx, ny, nz)) {
+            const double qv = q[i * L3 + slot(r, ex, ey, ez)];
+            if (qv != 0.0) qu += qv * u_rel(d, r, nx, ny, nz, jx - nx, jy - ny, jz - nz);
+          }
+        }
+    double acc = d.sc * d.sc * (uq + qu);
+    const long long j = at(d, jx, jy, jz);
+    for (int k = 0; k < p.np; ++k) {
+      const long long o = (long long)k * p.n1;
+      acc += p.lam * (p.X[o + i] * p.W[o + j] + p.W[o + i] * p.Y[o + j]);
+    }
+    out[t] = acc + p.eps * q[t];
+  }
+}
+
+// right-hand side R = M1 T + T M1 on S, and the Jacobi preconditioner
+// (its inverse; 1 on dead slots, whose right-hand side is zero)
+__global__ void __launch_bounds__(256) sylv_setup(const SylvParams p, double* __restrict__ rhs,
+                                                  double* __restrict__ pinv) {
+  const int r = p.r, L = 2 * r + 1, L3 = L * L * L;
+  const long long total = p.n1 * L3;
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+    const long long i = t / L3;
+    const int s = (int)(t - i * L3);
+    const int dx = s % L - r, dy = (s / L) % L - r, dz = s / (L * L) - r;
+    const OpComp& d = p.c[comp_of(p, i)];
+    int x, y, z;
+    decode(d, i, x, y, z);
+    const double m = m1_rel(d, r, x, y, z, dx, dy, dz);
+    if (m == 0.0) {
+      rhs[t] = 0.0;
+      pinv[t] = 1.0;
+      continue;
+    }
+    const long long j = at(d, x + dx, y + dy, z + dz);
+    double rv = 2.0 * d.sc * m, ti = 1.0, tj = 1.0;
+    for (int k = 0; k < p.np; ++k) {
+      const long long o = (long long)k * p.n1;
+      rv += p.lam * (p.MW[o + i] * p.W[o + j] + p.W[o + i] * p.MW[o + j]);
+      ti += p.lam * p.W[o + i] * p.W[o + i];
+      tj += p.lam * p.W[o + j] * p.W[o + j];
+    }
+    rhs[t] = rv;
+    const double uii = d.sc * d.sc * u_rel(d, r, x, y, z, 0, 0, 0);
+    int jx, jy, jz;
+    decode(d, j, jx, jy, jz);
+    const double ujj = d.sc * d.sc * u_rel(d, r, jx, jy, jz, 0, 0, 0);
+    pinv[t] = 1.0 / (uii * tj + ti * ujj + p.eps);
+  }
+}
+
+// y = Q x (transpose = 0) or Q^T x (transpose = 1), Q from the slots q
+__global__ void __launch_bounds__(256) box_apply(const SylvParams p, const double* __restrict__ q,
+                                                 const double* __restrict__ xv, double* __restrict__ yv,
+                                                 int transpose) {
+  const int r = p.r, L = 2 * r + 1, L3 = L * L * L;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < p.n1; i += (long long)gridDim.x * 256) {
+    const OpComp& d = p.c[comp_of(p, i)];
+    int x, y, z;
+    decode(d, i, x, y, z);
+    double acc = 0.0;
+    for (int ez = -r; ez <= r; ++ez)
+      for (int ey = -r; ey <= r; ++ey)
+        for (int ex = -r; ex <= r; ++ex) {
+          const int nx = x + ex, ny = y + ey, nz = z + ez;
+          if (!inside(d, nx, ny, nz)) continue;
+          const long long m = at(d, nx, ny, nz);
+          const double c = transpose ? q[m * L3 + slot(r, -ex, -ey, -ez)] : q[i * L3 + slot(r, ex, ey, ez)];
+          acc += c * xv[m];
+        }
+    yv[i] = acc;
+  }
+}
+
+// y = U x = M1^2 x
+__global__ void __launch_bounds__(256) u_apply(const SylvParams p, const double* __restrict__ xv,
+                                               double* __restrict__ yv) {
+  const int r = p.r;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < p.n1; i += (long long)gridDim.x * 256) {
+    const OpComp& d = p.c[comp_of(p, i)];
+    int x, y, z;
+    decode(d, i, x, y, z);
+    double acc = 0.0;
+    for (int ez = -2 * r; ez <= 2 * r; ++ez)
+      for (int ey = -2 * r; ey <= 2 * r; ++ey)
+        for (int ex = -2 * r; ex <= 2 * r; ++ex) {
+          const int nx = x + ex, ny = y + ey, nz = z + ez;
+          if (!inside(d, nx, ny, nz)) continue;
+          const double u = u_rel(d, r, x, y, z, ex, ey, ez);
+          if (u != 0.0) acc += u * xv[at(d, nx, ny, nz)];
+        }
+    yv[i] = d.sc * d.sc * acc;
+  }
+}
+
+// the symmetrised column-wise SPAI written into the slots (the warm start)
+__global__ void __launch_bounds__(256) spai_to_slots(const SylvParams p, const SpaiParams sp, double* __restrict__ q) {
+  const int r = p.r, L = 2 * r + 1, L3 = L * L * L;
+  const long long total = p.n1 * L3;
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+    const long long i = t / L3;
+    const int s = (int)(t - i * L3);
+    const int dx = s % L - r, dy = (s / L) % L - r, dz = s / (L * L) - r;
+    const int c = comp_of(p, i);
+    const OpComp& d = p.c[c];
+    int x, y, z;
+    decode(d, i, x, y, z);
+    const SpaiComp& a = sp.c[c];
+    double v = 0.0;
+    if (inside(d, x + dx, y + dy, z + dz) && m1_rel(d, r, x, y, z, dx, dy, dz) != 0.0) {
+      v = a.band[0][0][(long long)x * L + dx + r] * a.band[0][1][(long long)y * L + dy + r] *
+              a.band[0][2][(long long)z * L + dz + r] +
+          a.band[1][0][(long long)x * L + dx + r] * a.band[1][1][(long long)y * L + dy + r] *
+              a.band[1][2][(long long)z * L + dz + r];
+      v *= a.scale;
+    }
+    q[t] = v;
+  }
+}
+
+}  // namespace
+
+int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, int np, double lam, double rtol,
+                  int maxit, int ncu, hipStream_t s, SpaiOpQ1* out, int* iters, double* rel_res) {
+  const SpaceDesc& sd = s1->desc;
+  const gym_mesh* m = s1->mesh;
+  if (sd.ncomp != 3 || m->dim != 3) return fail(GYM_E_ARG, "SPAI-OP: 3-D Lambda^1 only");
+  const int r = sd.r, L = 2 * r + 1, L2 = 4 * r + 1, L3 = L * L * L;
+  const long long n1 = sd.ndofs, nq = n1 * L3;
+  const LumpedTables lt = lumped_tables_host(s1);
+  // 1-D bands of M_a and M_a^2 per component and axis
+  std::vector<double> host;
+  size_t offM[3][3], offM2[3][3];
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 3; ++a) {
+      const CompDesc& cd = sd.comp[c];
+      const int cnt = (int)cd.count[a];
+      const std::vector<double> A = mass1d_band(r, (int)m->nel[a], (cd.nodal_mask >> a) & 1, (int)cd.start[a], cnt);
+      std::vector<double> A2((size_t)cnt * L2, 0.0);
+      for (int i = 0; i < cnt; ++i)
+        for (int k = -r; k <= r; ++k) {
+          const int mm = i + k;
+          if (mm < 0 || mm >= cnt) continue;
+          for (int k2 = -r; k2 <= r; ++k2) {
+            const int j = mm + k2;
+            if (j < 0 || j >= cnt) continue;
+            A2[(size_t)i * L2 + (j - i + 2 * r)] += A[(size_t)i * L + k + r] * A[(size_t)mm * L + k2 + r];
+          }
+        }
+      offM[c][a] = host.size();
+      host.insert(host.end(), A.begin(), A.end());
+      offM2[c][a] = host.size();
+      host.insert(host.end(), A2.begin(), A2.end());
+    }
+  std::vector<void*> pool;
+  auto alloc = [&](long long cnt) -> double* {
+    void* p = nullptr;
+    if (hipMalloc(&p, sizeof(double) * cnt) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    pool.push_back(p);
+    return (double*)p;
+  };
+  auto release = [&](bool keep_first) {
+    for (size_t i = keep_first ? 2 : 0; i < pool.size(); ++i) (void)hipFree(pool[i]);
+  };
+  // the first two allocations (tables, the solution q) outlive the call
+  double* tab = alloc((long long)host.size());
+  double* q = alloc(nq);
+  double* rv = alloc(nq);
+  double* pv = alloc(nq);
+  double* ap = alloc(nq);
+  double* pinv = alloc(nq);
+  double* X = alloc(std::max(1, np) * n1);
+  double* Y = alloc(std::max(1, np) * n1);
+  double* tmp = alloc(n1);
+  const int nb = vec_grid(nq, ncu);
+  double* gw = alloc(eig_gram_work(nb));
+  if (!tab || !q || !rv || !pv || !ap || !pinv || !X || !Y || !tmp || !gw) {
+    release(false);
+    return fail(GYM_E_OOM, "SPAI-OP: device allocation failed");
+  }
+  if (hipMemcpy(tab, host.data(), sizeof(double) * host.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    release(false);
+    return fail(GYM_E_HIP, "SPAI-OP: upload failed");
+  }
+  SylvParams P{};
+  double dmax = 0.0;  // largest diagonal of U, for the Tikhonov shift
+  for (int c = 0; c < 3; ++c) {
+    OpComp& d = P.c[c];
+    d.off = sd.comp[c].offset;
+    for (int a = 0; a < 3; ++a) {
+      d.n[a] = (int)sd.comp[c].count[a];
+      d.M[a] = tab + offM[c][a];
+      d.M2[a] = tab + offM2[c][a];
+    }
+    d.sc = lt.sc[c];
+    double u = d.sc * d.sc;
+    for (int a = 0; a < 3; ++a) {
+      double mx = 0.0;
+      for (int i = 0; i < d.n[a]; ++i) mx = std::max(mx, host[offM2[c][a] + (size_t)i * L2 + 2 * r]);
+      u *= mx;
+    }
+    dmax = std::max(dmax, u);
+  }
+  P.n1 = n1;
+  P.r = r;
+  P.np = np;
+  P.W = Wdev;
+  P.MW = MWdev;
+  P.X = X;
+  P.Y = Y;
+  P.lam = lam;
+  P.eps = 1e-12 * dmax;
+  const int nbr = vec_grid(n1, ncu);
+  // A v for a slot vector v: X = U V W, Y = U V^T W, then the Sylvester operator
+  auto apply = [&](const double* v, double* out) {
+    for (int k = 0; k < np; ++k) {
+      hipLaunchKernelGGL(box_apply, dim3(nbr), dim3(256), 0, s, P, v, Wdev + (long long)k * n1, tmp, 0);
+      hipLaunchKernelGGL(u_apply, dim3(nbr), dim3(256), 0, s, P, tmp, X + (long long)k * n1);
+      hipLaunchKernelGGL(box_apply, dim3(nbr), dim3(256), 0, s, P, v, Wdev + (long long)k * n1, tmp, 1);
+      hipLaunchKernelGGL(u_apply, dim3(nbr), dim3(256), 0, s, P, tmp, Y + (long long)k * n1);
+    }
+    hipLaunchKernelGGL(sylv_apply, dim3(nb), dim3(256), 0, s, P, v, out);
+  };
+  auto dot = [&](const double* a, const double* b, double* res) {
+    return eig_gram(a, 1, b, 1, nq, res, gw, nb, s);
+  };
+  // rhs into pv for now (pv is free until the first direction)
+  hipLaunchKernelGGL(sylv_setup, dim3(nb), dim3(256), 0, s, P, pv, pinv);
+  SpaiParams spp{};
+  double* spmem = nullptr;
+  if (int rc = build_spai_q1(s1, 1, &spp, &spmem)) {
+    release(false);
+    return rc;
+  }
+  hipLaunchKernelGGL(spai_to_slots, dim3(nb), dim3(256), 0, s, P, spp, q);
+  // r = b - A q
+  apply(q, ap);
+  launch_axpy_diag(rv, 0.0, 1.0, nullptr, pv, nq, nb, s);
+  launch_axpy_diag(rv, 1.0, -1.0, nullptr, ap, nq, nb, s);
+  double bn2 = 0.0, rr = 0.0, rz = 0.0;
+  int status = 0, it = 0;
+  if (dot(pv, pv, &bn2) || dot(rv, rv, &rr)) status = -1;
+  // p = z = Pinv r
+  launch_axpy_diag(pv, 0.0, 1.0, pinv, rv, nq, nb, s);
+  if (!status && dot(rv, pv, &rz)) status = -1;
+  const double bn = std::sqrt(bn2);
+  double rel = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+  while (!status && rel > rtol && it < maxit) {
+    apply(pv, ap);
+    double pap = 0.0;
+    if (dot(pv, ap, &pap)) {
+      status = -1;
+      break;
+    }
+    if (!(pap > 0)) {
+      status = fail(GYM_E_BREAKDOWN, "SPAI-OP: the Sylvester operator is not positive definite");
+      break;
+    }
+    const double al = rz / pap;
+    launch_axpy_diag(q, 1.0, al, nullptr, pv, nq, nb, s);
+    launch_axpy_diag(rv, 1.0, -al, nullptr, ap, nq, nb, s);
+    ++it;
+    if (dot(rv, rv, &rr)) {
+      status = -1;
+      break;
+    }
+    rel = std::sqrt(rr) / bn;
+    // z = Pinv r into ap (free now), rz_new = r . z, p = z + beta p
+    launch_axpy_diag(ap, 0.0, 1.0, pinv, rv, nq, nb, s);
+    double rzn = 0.0;
+    if (dot(rv, ap, &rzn)) {
+      status = -1;
+      break;
+    }
+    launch_axpy_diag(pv, rzn / rz, 1.0, nullptr, ap, nq, nb, s);
+    rz = rzn;
+  }
+  (void)hipFree(spmem);
+  if (status == -1) status = hip_fail(hipGetLastError(), "SPAI-OP");
+  if (status) {
+    release(false);
+    return status;
+  }
+  if (hipStreamSynchronize(s) != hipSuccess) {
+    release(false);
+    return hip_fail(hipGetLastError(), "SPAI-OP");
+  }
+  release(true);
+  out->params_tab = tab;
+  out->q = q;
+  out->r = r;
+  out->n1 = n1;
+  for (int c = 0; c < 3; ++c) {
+    out->off[c] = P.c[c].off;
+    for (int a = 0; a < 3; ++a) {
+      out->n[c][a] = P.c[c].n[a];
+      out->M[c][a] = P.c[c].M[a];
+      out->M2[c][a] = P.c[c].M2[a];
+    }
+    out->sc[c] = P.c[c].sc;
+  }
+  *iters = it;
+  *rel_res = rel;
+  return rel <= rtol ? 0 : GYM_W_NOT_CONVERGED;
+}
+
+void launch_spai_op_apply(const SpaiOpQ1& Q, const double* x, double* y, int ncu, hipStream_t s) {
+  SylvParams P{};
+  for (int c = 0; c < 3; ++c) {
+    P.c[c].off = Q.off[c];
+    for (int a = 0; a < 3; ++a) {
+      P.c[c].n[a] = Q.n[c][a];
+      P.c[c].M[a] = Q.M[c][a];
+      P.c[c].M2[a] = Q.M2[c][a];
+    }
+    P.c[c].sc = Q.sc[c];
+  }
+  P.n1 = Q.n1;
+  P.r = Q.r;
+  hipLaunchKernelGGL(box_apply, dim3(vec_grid(Q.n1, ncu)), dim3(256), 0, s, P, Q.q, x, y, 0);
+}
+
+void spai_op_free(SpaiOpQ1* Q) {
+  if (Q->q) (void)hipFree(Q->q);
+  if (Q->params_tab) (void)hipFree(Q->params_tab);
+  Q->q = nullptr;
+  Q->params_tab = nullptr;
+}
+
+}  // namespace gym

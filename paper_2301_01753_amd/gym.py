@@ -29,7 +29,7 @@ GYM_F64, GYM_F32, GYM_BF16 = 0, 1, 2
 GYM_MIXED_POISSON, GYM_HODGE1 = 0, 1
 GYM_MINRES, GYM_CG = 0, 1
 GYM_MODE_F64, GYM_MODE_IR_F32, GYM_MODE_IR_BF16 = 0, 1, 2
-GYM_Q1_EXACT, GYM_Q1_LUMPED, GYM_Q1_SPAI_DIAG, GYM_Q1_SPAI = 0, 1, 2, 3
+GYM_Q1_EXACT, GYM_Q1_LUMPED, GYM_Q1_SPAI_DIAG, GYM_Q1_SPAI, GYM_Q1_SPAI_OP = 0, 1, 2, 3, 4
 GYM_M2_EXACT, GYM_M2_LUMPED = 0, 1
 
 KIND = {"H1": GYM_H1, "HCURL": GYM_HCURL, "HDIV": GYM_HDIV, "L2": GYM_L2}
@@ -120,6 +120,8 @@ SIGNATURES = {
     "gym_maxwell_step": (_I, [_P, ctypes.c_double, _I, _P, _P, _P]),
     "gym_maxwell_energy": (_I, [_P, _P, _P, ctypes.POINTER(ctypes.c_double), _P]),
     "gym_maxwell_destroy": (_I, [_P]),
+    "gym_maxwell_spai_op": (_I, [_P, _I, _P, ctypes.c_double, ctypes.c_double, _I, ctypes.POINTER(_I),
+                                ctypes.POINTER(ctypes.c_double), _P]),
     "gym_eig_opts_default": (None, [ctypes.POINTER(EigOpts)]),
     "gym_maxwell_eigs": (_I, [_P, ctypes.POINTER(EigOpts), ctypes.POINTER(ctypes.c_double), _P,
                              ctypes.POINTER(EigInfo), _P]),
@@ -327,6 +329,19 @@ def gym_maxwell_energy(mx, a, e, stream=None):
 
 def gym_maxwell_destroy(mx):
     _check(lib().gym_maxwell_destroy(mx))
+
+
+def gym_maxwell_spai_op(mx, probes, lam, rtol=1e-12, maxit=5000, stream=None):
+    """Replace Q1 by SPAI-OP with the modes `probes` (device tensor of
+    nprobe x ndofs doubles, or None); returns (iterations, rel_res, status)."""
+    n = gym_maxwell_ndofs(mx)
+    npb = 0 if probes is None else probes.numel() // n
+    it = ctypes.c_int()
+    rel = ctypes.c_double()
+    st = lib().gym_maxwell_spai_op(mx, npb, _ptr(probes), float(lam), float(rtol), int(maxit), ctypes.byref(it),
+                                   ctypes.byref(rel), _stream(stream))
+    _check(st, ok=(GYM_OK, GYM_W_NOT_CONVERGED))
+    return it.value, rel.value, st
 
 
 def gym_eig_opts_default():
