@@ -11,7 +11,7 @@ M[:, I_l] is nonzero.  The result is then made symmetric, Q <- (Q + Q^T) / 2,
 as section 5 does, so that it can serve as the Q1 of a symplectic scheme.
 
 Patterns: 'diag' is S(1), one entry per column; 'm' is S(M), the sparsity of
-M itself.
+M itself (its structural nonzeros: see :func:`structural`).
 
 Pins (tests/test_oracle_spai.py): on the paper's 20 x 20 periodic Whitney mesh
 the lowest non-kernel frequency of Q P2 against the printed 1.1499 (S(1)) and
@@ -22,12 +22,23 @@ import numpy as np
 import scipy.sparse as sp
 
 
+def structural(M, rel=1e-14):
+    """M without the entries below rel times its largest: quadrature in
+    floating point leaves roundoff (1e-17 and less) where the exact mass matrix
+    has zeros, e.g. between the components of a 1-form on box cells; the
+    pattern S(M) is that of the exact matrix."""
+    M = sp.csr_matrix(M, copy=True)
+    M.data[np.abs(M.data) <= rel * np.abs(M.data).max()] = 0.0
+    M.eliminate_zeros()
+    return M
+
+
 def spai(M, pattern="m"):
     """Symmetrised column-wise SPAI of the sparse matrix M with pattern
     'diag' (S(1)) or 'm' (S(M))."""
     if pattern not in ("diag", "m"):
         raise ValueError("pattern: 'diag' or 'm'")
-    M = sp.csc_matrix(M)
+    M = sp.csc_matrix(structural(M))
     M.sort_indices()
     n = M.shape[0]
     rows, cols, vals = [], [], []
@@ -48,7 +59,7 @@ def spai(M, pattern="m"):
 def spai_unsymmetrised(M, pattern="m"):
     """The column-wise least-squares solution before symmetrisation (for the
     optimality pins)."""
-    M = sp.csc_matrix(M)
+    M = sp.csc_matrix(structural(M))
     M.sort_indices()
     n = M.shape[0]
     rows, cols, vals = [], [], []

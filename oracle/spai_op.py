@@ -30,12 +30,14 @@ fit stays within 8% of SPAI's (all three printed).
 import numpy as np
 import scipy.sparse as sp
 
+from .spai import structural
+
 
 class SpaiOp:
     """The Sylvester system of SPAI-OP for M1 on the pattern S(M1)."""
 
     def __init__(self, M1, W=None, lam=0.0, eps=None):
-        self.M = sp.csr_matrix(M1)
+        self.M = structural(M1)  # the exact zeros of M1 are not in S
         self.n = self.M.shape[0]
         self.U = (self.M @ self.M).tocsr()
         pat = sp.coo_matrix(self.M)

@@ -3,16 +3,19 @@
 The GPU solves the Sylvester system of section 5 matrix-free on the box
 slots of each row; the oracle assembles Q1 as a sparse matrix and runs the
 same Jacobi PCG.  Both solve to relative residual 1e-13, so the two Q1 agree
-to about that; they are compared through 7 Strang steps (the time stepping
-then applies the GPU's Q1 through its box stencil), to 1e-9.  Cases: lambda = 0
-(the optimal symmetric SPAI) and lambda > 0 with two seeded probe vectors, at
-degrees 1 and 2.  Then the paper's point in 3-D: probing the lowest exact mode
+to about that times the system's condition number; they are compared through
+7 Strang steps (the time stepping then applies the GPU's Q1 through its box
+stencil), to 1e-9.  Cases: lambda = 0 (the optimal symmetric SPAI) and lambda
+> 0 with two seeded probe vectors, at degrees 1 and 2.  Each probe v is scaled
+to || P2 v || = 1, as an eigenmode probe is; then the Jacobi-preconditioned
+system's condition number stays near 1e3 at these lambdas (two oracle solves
+from different starts agree to 2e-12), so 1e-9 measures the arithmetic, not
+the conditioning.  Then the paper's point in 3-D: probing the lowest exact mode
 with lambda = 5e5 makes the scheme's frequency of that mode exact to 1e-4,
 where the plain SPAI is off by more than 0.1%.
 """
 import numpy as np
 import pytest
-import scipy.sparse as sp
 
 import synth
 from oracle import maxwell, spai_op
@@ -48,7 +51,7 @@ def _create(gym, ctx, nel, r, m2, c, hi):
 CASES = [((4, 3, 4), 1, "exact", 1.0, (1.0, 1.2, 0.9), 0.0, 0),
          ((4, 3, 4), 1, "exact", 0.9, (1.0, 1.2, 0.9), 1e3, 2),
          ((3, 3, 2), 2, "lumped", 1.0, (1.0, 1.0, 1.0), 0.0, 0),
-         ((3, 3, 2), 2, "exact", 1.0, (1.0, 1.0, 1.0), 50.0, 2)]
+         ((3, 3, 2), 2, "exact", 1.0, (1.0, 1.0, 1.0), 100.0, 2)]
 
 
 @pytest.mark.parametrize("nel,r,m2,c,hi,lam,nprobe", CASES)
@@ -56,13 +59,16 @@ def test_spai_op_steps_match_oracle(g, nel, r, m2, c, hi, lam, nprobe):
     gym, ctx = g
     mesh, mx = _create(gym, ctx, nel, r, m2, c, hi)
     n = gym.gym_maxwell_ndofs(mx)
-    V = synth.random_vector(nprobe * n, seed=31).reshape(nprobe, n) if nprobe else None
+    verts = synth.uniform_vertices(nel, hi=hi)
+    G0 = maxwell.Gym(Mesh(verts), r, q1="exact", m2=m2, c=c)
+    V = W = None
+    if nprobe:
+        V = synth.random_vector(nprobe * n, seed=31).reshape(nprobe, n)
+        V /= np.linalg.norm(G0.P2 @ V.T, axis=0)[:, None]
+        W = G0.P2 @ V.T
     it, rel, st = gym.gym_maxwell_spai_op(mx, _t(V.ravel()) if nprobe else None, lam, rtol=1e-13)
     print(f"nel={nel} r={r} lambda={lam}: {it} PCG iterations, rel {rel:.1e}", flush=True)
     assert st == gym.GYM_OK
-    verts = synth.uniform_vertices(nel, hi=hi)
-    G0 = maxwell.Gym(Mesh(verts), r, q1="exact", m2=m2, c=c)
-    W = (G0.P2 @ V.T) if nprobe else None
     Q, oit, orel = spai_op.SpaiOp(G0.M1, W=W, lam=lam).solve(rtol=1e-13)
     G = maxwell.Gym(Mesh(verts), r, q1=Q, m2=m2, c=c)
     a0 = synth.random_vector(n, seed=32)

@@ -51,7 +51,7 @@ def test_spai_diag_closed_form():
 def test_spai_columns_are_least_squares_optimal():
     # S(M): M[:, I]^T (M[:, I] q_l - e_l) = 0 on each column's pattern I
     mesh = Mesh(synth.perturbed_vertices((2, 3, 2), 0.1, seed=4))
-    M = assembly.mass_matrix(Space("HCURL", (2, 3, 2), 1, "essential"), mesh).tocsc()
+    M = spai.structural(assembly.mass_matrix(Space("HCURL", (2, 3, 2), 1, "essential"), mesh)).tocsc()
     Q = spai.spai_unsymmetrised(M, "m").tocsc()
     Md = M.toarray()
     for l in range(M.shape[0]):
