@@ -280,6 +280,42 @@ def eig_rates(gym, ctx, N, r, nev, block):
     return out
 
 
+def spai_op_rates(gym, ctx, nel, hi, r, lam, steps):
+    """SPAI-OP on an nel box with extents hi (perfect conductor, exact M2~):
+    the lowest exact mode v (LOBPCG, not timed) is the probe P2 v; times the
+    matrix-free Sylvester PCG that builds Q1 and the Strang steps with that
+    Q1.  (The probed frequency itself is checked by the GPU tests: an
+    eigen-solve on a SPAI Q1 takes B = Q1^-1 by an inner CG and is slow.)"""
+    import torch
+    mesh = gym.gym_mesh_create(ctx, 3, nel, hi=hi)
+    mx = gym.gym_maxwell_create(ctx, mesh, r, gym.gym_maxwell_opts_default())
+    n = gym.gym_maxwell_ndofs(mx)
+    e = gym.gym_eig_opts_default()
+    e.nev, e.tol = 1, 1e-10
+    v = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    gym.gym_maxwell_eigs(mx, e, v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, rel, st = gym.gym_maxwell_spai_op(mx, v, lam, rtol=1e-10, maxit=20000)
+    torch.cuda.synchronize()
+    build = time.perf_counter() - t0
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(22)
+    a = torch.randn(n, dtype=torch.float64, device="cuda:0", generator=gen)
+    f = torch.randn(n, dtype=torch.float64, device="cuda:0", generator=gen)
+    tau = 0.25 / (max(nel) * r * r)
+    gym.gym_maxwell_step(mx, tau, 2, a, f)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gym.gym_maxwell_step(mx, tau, steps, a, f)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gym.gym_maxwell_destroy(mx)
+    gym.gym_mesh_destroy(mesh)
+    return {"ndofs": n, "lambda": lam, "probes": 1, "pcg_iters": it, "pcg_rel_res": rel, "status": st,
+            "build_seconds": build, "pcg_iters_per_s": it / build, "steps": steps, "steps_per_s": steps / wall}
+
+
 def cfl_rate(gym, ctx, N):
     """omega_max of Yee's method (Whitney forms, lumped masses) on an N^3 unit
     box by the largest-pair solver, tau_CFL = 2 / omega_max, and the relative
@@ -550,6 +586,8 @@ def main():
             "r1_128cube_spai_q1": maxwell_rates(gym, ctx, 128, 1, "spai", 200),
             "r2_32cube_spai_q1": maxwell_rates(gym, ctx, 32, 2, "spai", 500),
         }
+        log("SPAI-OP ...")
+        ext["gym_spai_op"] = {"r1_24x20x16_box": spai_op_rates(gym, ctx, (24, 20, 16), (1.0, 1.3, 0.8), 1, 5e5, 500)}
         log("eigenmodes ...")
         ext["gym_eigenmodes"] = {
             "whitney_24cube_lowest5": eig_rates(gym, ctx, 24, 1, 5, 7),

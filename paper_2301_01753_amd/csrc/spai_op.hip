@@ -287,7 +287,7 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
   // the first two allocations (tables, the solution q) outlive the call
   double* tab = alloc((long long)host.size());
   double* q = alloc(nq);
-  double* rv = alloc(nq);
+  double* rv = alloc(2 * nq);  // r, then z = Pinv r: one Gram call gives r . r and r . z
   double* pv = alloc(nq);
   double* ap = alloc(nq);
   double* pinv = alloc(nq);
@@ -359,14 +359,17 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
   apply(q, ap);
   launch_axpy_diag(rv, 0.0, 1.0, nullptr, pv, nq, nb, s);
   launch_axpy_diag(rv, 1.0, -1.0, nullptr, ap, nq, nb, s);
-  double bn2 = 0.0, rr = 0.0, rz = 0.0;
+  double* zv = rv + nq;
+  double bn2 = 0.0, rrz[2] = {0.0, 0.0};
   int status = 0, it = 0;
-  if (dot(pv, pv, &bn2) || dot(rv, rv, &rr)) status = -1;
-  // p = z = Pinv r
-  launch_axpy_diag(pv, 0.0, 1.0, pinv, rv, nq, nb, s);
-  if (!status && dot(rv, pv, &rz)) status = -1;
+  if (dot(pv, pv, &bn2)) status = -1;
+  // z = Pinv r, p = z
+  launch_axpy_diag(zv, 0.0, 1.0, pinv, rv, nq, nb, s);
+  launch_axpy_diag(pv, 0.0, 1.0, nullptr, zv, nq, nb, s);
+  if (!status && eig_gram(rv, 1, rv, 2, nq, rrz, gw, nb, s)) status = -1;
+  double rz = rrz[1];
   const double bn = std::sqrt(bn2);
-  double rel = bn > 0 ? std::sqrt(rr) / bn : 0.0;
+  double rel = bn > 0 ? std::sqrt(rrz[0]) / bn : 0.0;
   while (!status && rel > rtol && it < maxit) {
     apply(pv, ap);
     double pap = 0.0;
@@ -382,19 +385,15 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
     launch_axpy_diag(q, 1.0, al, nullptr, pv, nq, nb, s);
     launch_axpy_diag(rv, 1.0, -al, nullptr, ap, nq, nb, s);
     ++it;
-    if (dot(rv, rv, &rr)) {
+    // z = Pinv r; r . r and r . z in one reduction; p = z + beta p
+    launch_axpy_diag(zv, 0.0, 1.0, pinv, rv, nq, nb, s);
+    if (eig_gram(rv, 1, rv, 2, nq, rrz, gw, nb, s)) {
       status = -1;
       break;
     }
-    rel = std::sqrt(rr) / bn;
-    // z = Pinv r into ap (free now), rz_new = r . z, p = z + beta p
-    launch_axpy_diag(ap, 0.0, 1.0, pinv, rv, nq, nb, s);
-    double rzn = 0.0;
-    if (dot(rv, ap, &rzn)) {
-      status = -1;
-      break;
-    }
-    launch_axpy_diag(pv, rzn / rz, 1.0, nullptr, ap, nq, nb, s);
+    rel = std::sqrt(rrz[0]) / bn;
+    const double rzn = rrz[1];
+    launch_axpy_diag(pv, rzn / rz, 1.0, nullptr, zv, nq, nb, s);
     rz = rzn;
   }
   (void)hipFree(spmem);
