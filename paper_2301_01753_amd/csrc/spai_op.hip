@@ -14,8 +14,9 @@
 // U_im a product of 1-D entries of M_a^2 (Kronecker structure of M1 per
 // component), and the rank-n_probe parts through X = U Q W and
 // Y = U Q^T W.  Jacobi-preconditioned CG solves it, started from the
-// symmetrised column-wise SPAI; one thread per (row, slot) in the operator,
-// one per row in the stencil applies.
+// symmetrised column-wise SPAI; the operator is two box contractions with
+// U's 1-D factors (rows for Q U, columns for U Q), one thread per row in the
+// stencil applies.
 #include "spai_op.hpp"
 
 #include <algorithm>
@@ -88,47 +89,124 @@ __device__ __forceinline__ int slot(int r, int dx, int dy, int dz) {
   return ((dz + r) * L + (dy + r)) * L + (dx + r);
 }
 
-// out = A q on S (+ eps q); one thread per (row, slot)
-__global__ void __launch_bounds__(256) sylv_apply(const SylvParams p, const double* __restrict__ q,
-                                                  double* __restrict__ out) {
-  const int r = p.r, L = 2 * r + 1, L3 = L * L * L;
-  const long long total = p.n1 * L3;
-  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
-    const long long i = t / L3;
-    const int s = (int)(t - i * L3);
-    const int dx = s % L - r, dy = (s / L) % L - r, dz = s / (L * L) - r;
-    const OpComp& d = p.c[comp_of(p, i)];
-    int x, y, z;
-    decode(d, i, x, y, z);
-    if (m1_rel(d, r, x, y, z, dx, dy, dz) == 0.0) {
-      out[t] = 0.0;
-      continue;
+// One half of A q per launch: a (2r + 1)^3-box to box contraction with the
+// Kronecker factors of U, applied one axis at a time (3 (2r + 1)^4 terms per
+// box instead of (2r + 1)^6).  A workgroup stages `per` boxes in LDS.
+//  ROWS (Q U): for row i, (Q U)_{i, i+e'} = sum_e Q_{i, i+e} U_{i+e, i+e'};
+//    writes every slot of the row: sc^2 (Q U) + the probe terms + eps q on
+//    live slots, zero on dead ones.
+//  columns (U Q): for column j, (U Q)_{j-e', j} = sum_e U_{j-e', j-e} Q_{j-e, j},
+//    the box of column j gathered from the rows j - e; adds sc^2 (U Q) into
+//    the live slot e' of row j - e'.
+// Each (i, j) has one owner in either pass, so the ROWS launch followed by
+// the columns launch on one stream needs no atomics.
+template <int R, bool ROWS>
+__global__ void __launch_bounds__(256) sylv_box(const SylvParams p, const double* __restrict__ q,
+                                                double* __restrict__ out, int per) {
+  constexpr int L = 2 * R + 1, L2 = 4 * R + 1, L3 = L * L * L;
+  constexpr int sg = ROWS ? 1 : -1;
+  extern __shared__ double sb[];
+  __shared__ int pos[256][4];  // lattice position and component of each box centre
+  double* g = sb;
+  double* h = sb + per * L3;
+  for (long long c0 = (long long)blockIdx.x * per; c0 < p.n1; c0 += (long long)gridDim.x * per) {
+    const int cnt = (int)(p.n1 - c0 < per ? p.n1 - c0 : per);
+    if (threadIdx.x < cnt) {
+      const long long c = c0 + threadIdx.x;
+      const int cc = comp_of(p, c);
+      decode(p.c[cc], c, pos[threadIdx.x][0], pos[threadIdx.x][1], pos[threadIdx.x][2]);
+      pos[threadIdx.x][3] = cc;
     }
-    const int jx = x + dx, jy = y + dy, jz = z + dz;
-    double uq = 0.0, qu = 0.0;
-    for (int ez = -r; ez <= r; ++ez)
-      for (int ey = -r; ey <= r; ++ey)
-        for (int ex = -r; ex <= r; ++ex) {
-          // (U Q)_ij: m = j - e, Q_mj in slot e of row m
-          const int mx = jx - ex, my = jy - ey, mz = jz - ez;
-          if (inside(d, mx, my, mz)) {
-            const double u = u_rel(d, r, x, y, z, mx - x, my - y, mz - z);
-            if (u != 0.0) uq += u * q[at(d, mx, my, mz) * L3 + slot(r, ex, ey, ez)];
-          }
-          // (Q U)_ij: m = i + e, Q_im in slot e of row i
-          const int nx = x + ex, ny = y + ey, nz = z + ez;
-          if (inside(d, nx, ny, nz)) {
-            const double qv = q[i * L3 + slot(r, ex, ey, ez)];
-            if (qv != 0.0) qu += qv * u_rel(d, r, nx, ny, nz, jx - nx, jy - ny, jz - nz);
+    __syncthreads();
+    // the box of row / column c: g(e) = Q_{c, c+e} or Q_{c-e, c}
+    for (int u = threadIdx.x; u < cnt * L3; u += 256) {
+      const int k = u / L3, t = u - k * L3;
+      const long long c = c0 + k;
+      double v = 0.0;
+      if constexpr (ROWS) {
+        v = q[c * L3 + t];
+      } else {
+        const OpComp& d = p.c[pos[k][3]];
+        const int x = pos[k][0], y = pos[k][1], z = pos[k][2];
+        const int mx = x - (t % L - R), my = y - ((t / L) % L - R), mz = z - (t / (L * L) - R);
+        if (inside(d, mx, my, mz)) v = q[at(d, mx, my, mz) * L3 + t];
+      }
+      g[u] = v;
+    }
+    __syncthreads();
+    // axis a: out(.., e'_a, ..) = sum_{e_a} U_a(c_a + sg e'_a, c_a + sg e_a) in(.., e_a, ..)
+    auto pass = [&](const double* in, double* o, int a) {
+      const int st = a == 0 ? 1 : a == 1 ? L : L * L;  // slot stride of axis a
+      for (int u = threadIdx.x; u < cnt * L3; u += 256) {
+        const int k = u / L3, t = u - k * L3;
+        const OpComp& d = p.c[pos[k][3]];
+        const int ca = pos[k][a];
+        const int e_out = (t / st) % L - R;
+        const int base = t - (e_out + R) * st;
+        const int pp = ca + sg * e_out;
+        double acc = 0.0;
+        if ((unsigned)pp < (unsigned)d.n[a]) {
+          const double* band = d.M2[a] + (long long)pp * L2 + 2 * R;
+#pragma unroll
+          for (int e = -R; e <= R; ++e) {
+            const int qq = ca + sg * e;
+            if ((unsigned)qq < (unsigned)d.n[a]) acc += band[qq - pp] * in[k * L3 + base + (e + R) * st];
           }
         }
-    double acc = d.sc * d.sc * (uq + qu);
-    const long long j = at(d, jx, jy, jz);
-    for (int k = 0; k < p.np; ++k) {
-      const long long o = (long long)k * p.n1;
-      acc += p.lam * (p.X[o + i] * p.W[o + j] + p.W[o + i] * p.Y[o + j]);
+        o[u] = acc;
+      }
+      __syncthreads();
+    };
+    pass(g, h, 0);
+    pass(h, g, 1);
+    pass(g, h, 2);
+    for (int u = threadIdx.x; u < cnt * L3; u += 256) {
+      const int k = u / L3, t = u - k * L3;
+      const long long c = c0 + k;
+      const OpComp& d = p.c[pos[k][3]];
+      const int x = pos[k][0], y = pos[k][1], z = pos[k][2];
+      const int dx = t % L - R, dy = (t / L) % L - R, dz = t / (L * L) - R;
+      const double v = d.sc * d.sc * h[u];
+      if constexpr (ROWS) {
+        const long long idx = c * L3 + t;
+        if (!inside(d, x + dx, y + dy, z + dz) || m1_rel(d, R, x, y, z, dx, dy, dz) == 0.0) {
+          out[idx] = 0.0;
+          continue;
+        }
+        const long long j = at(d, x + dx, y + dy, z + dz);
+        double acc = v;
+        for (int kk = 0; kk < p.np; ++kk) {
+          const long long o = (long long)kk * p.n1;
+          acc += p.lam * (p.X[o + c] * p.W[o + j] + p.W[o + c] * p.Y[o + j]);
+        }
+        out[idx] = acc + p.eps * q[idx];
+      } else {
+        const int ix = x - dx, iy = y - dy, iz = z - dz;  // row i = j - e'
+        if (inside(d, ix, iy, iz) && m1_rel(d, R, ix, iy, iz, dx, dy, dz) != 0.0) out[at(d, ix, iy, iz) * L3 + t] += v;
+      }
     }
-    out[t] = acc + p.eps * q[t];
+    __syncthreads();  // h and g are refilled by the next boxes
+  }
+}
+
+template <int R>
+void launch_sylv(const SylvParams& p, const double* q, double* out, int ncu, hipStream_t s) {
+  constexpr int L3 = (2 * R + 1) * (2 * R + 1) * (2 * R + 1);
+  const int per = L3 >= 256 ? 1 : 256 / L3;
+  long long nb = (p.n1 + per - 1) / per;
+  if (nb > 8LL * ncu) nb = 8LL * ncu;
+  const size_t lds = sizeof(double) * 2 * per * L3;
+  hipLaunchKernelGGL((sylv_box<R, true>), dim3((int)nb), dim3(256), lds, s, p, q, out, per);
+  hipLaunchKernelGGL((sylv_box<R, false>), dim3((int)nb), dim3(256), lds, s, p, q, out, per);
+}
+
+// out = A q on S (+ eps q)
+void sylv_apply(const SylvParams& p, const double* q, double* out, int ncu, hipStream_t s) {
+  switch (p.r) {
+    case 1: launch_sylv<1>(p, q, out, ncu, s); break;
+    case 2: launch_sylv<2>(p, q, out, ncu, s); break;
+    case 3: launch_sylv<3>(p, q, out, ncu, s); break;
+    default: launch_sylv<4>(p, q, out, ncu, s); break;
   }
 }
 
@@ -341,7 +419,7 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
       hipLaunchKernelGGL(box_apply, dim3(nbr), dim3(256), 0, s, P, v, Wdev + (long long)k * n1, tmp, 1);
       hipLaunchKernelGGL(u_apply, dim3(nbr), dim3(256), 0, s, P, tmp, Y + (long long)k * n1);
     }
-    hipLaunchKernelGGL(sylv_apply, dim3(nb), dim3(256), 0, s, P, v, out);
+    sylv_apply(P, v, out, ncu, s);
   };
   auto dot = [&](const double* a, const double* b, double* res) {
     return eig_gram(a, 1, b, 1, nq, res, gw, nb, s);
