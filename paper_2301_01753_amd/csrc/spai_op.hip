@@ -246,12 +246,21 @@ __global__ void __launch_bounds__(256) sylv_setup(const SylvParams p, double* __
   }
 }
 
+// The stencil applies do (2r + 1)^3 or (4r + 1)^3 terms per row: one wave per
+// workgroup and one row per thread, so that a small mesh still spreads over
+// every CU.
+constexpr int kRowBT = 64;
+int row_grid(long long n) {
+  long long b = (n + kRowBT - 1) / kRowBT;
+  return (int)(b > 65536 ? 65536 : b < 1 ? 1 : b);
+}
+
 // y = Q x (transpose = 0) or Q^T x (transpose = 1), Q from the slots q
-__global__ void __launch_bounds__(256) box_apply(const SylvParams p, const double* __restrict__ q,
+__global__ void __launch_bounds__(kRowBT) box_apply(const SylvParams p, const double* __restrict__ q,
                                                  const double* __restrict__ xv, double* __restrict__ yv,
                                                  int transpose) {
   const int r = p.r, L = 2 * r + 1, L3 = L * L * L;
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < p.n1; i += (long long)gridDim.x * 256) {
+  for (long long i = (long long)blockIdx.x * kRowBT + threadIdx.x; i < p.n1; i += (long long)gridDim.x * kRowBT) {
     const OpComp& d = p.c[comp_of(p, i)];
     int x, y, z;
     decode(d, i, x, y, z);
@@ -270,10 +279,10 @@ __global__ void __launch_bounds__(256) box_apply(const SylvParams p, const doubl
 }
 
 // y = U x = M1^2 x
-__global__ void __launch_bounds__(256) u_apply(const SylvParams p, const double* __restrict__ xv,
+__global__ void __launch_bounds__(kRowBT) u_apply(const SylvParams p, const double* __restrict__ xv,
                                                double* __restrict__ yv) {
   const int r = p.r;
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < p.n1; i += (long long)gridDim.x * 256) {
+  for (long long i = (long long)blockIdx.x * kRowBT + threadIdx.x; i < p.n1; i += (long long)gridDim.x * kRowBT) {
     const OpComp& d = p.c[comp_of(p, i)];
     int x, y, z;
     decode(d, i, x, y, z);
@@ -410,14 +419,14 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
   P.Y = Y;
   P.lam = lam;
   P.eps = 1e-12 * dmax;
-  const int nbr = vec_grid(n1, ncu);
+  const int nbr = row_grid(n1);
   // A v for a slot vector v: X = U V W, Y = U V^T W, then the Sylvester operator
   auto apply = [&](const double* v, double* out) {
     for (int k = 0; k < np; ++k) {
-      hipLaunchKernelGGL(box_apply, dim3(nbr), dim3(256), 0, s, P, v, Wdev + (long long)k * n1, tmp, 0);
-      hipLaunchKernelGGL(u_apply, dim3(nbr), dim3(256), 0, s, P, tmp, X + (long long)k * n1);
-      hipLaunchKernelGGL(box_apply, dim3(nbr), dim3(256), 0, s, P, v, Wdev + (long long)k * n1, tmp, 1);
-      hipLaunchKernelGGL(u_apply, dim3(nbr), dim3(256), 0, s, P, tmp, Y + (long long)k * n1);
+      hipLaunchKernelGGL(box_apply, dim3(nbr), dim3(kRowBT), 0, s, P, v, Wdev + (long long)k * n1, tmp, 0);
+      hipLaunchKernelGGL(u_apply, dim3(nbr), dim3(kRowBT), 0, s, P, tmp, X + (long long)k * n1);
+      hipLaunchKernelGGL(box_apply, dim3(nbr), dim3(kRowBT), 0, s, P, v, Wdev + (long long)k * n1, tmp, 1);
+      hipLaunchKernelGGL(u_apply, dim3(nbr), dim3(kRowBT), 0, s, P, tmp, Y + (long long)k * n1);
     }
     sylv_apply(P, v, out, ncu, s);
   };
@@ -516,7 +525,7 @@ void launch_spai_op_apply(const SpaiOpQ1& Q, const double* x, double* y, int ncu
   }
   P.n1 = Q.n1;
   P.r = Q.r;
-  hipLaunchKernelGGL(box_apply, dim3(vec_grid(Q.n1, ncu)), dim3(256), 0, s, P, Q.q, x, y, 0);
+  hipLaunchKernelGGL(box_apply, dim3(row_grid(Q.n1)), dim3(kRowBT), 0, s, P, Q.q, x, y, 0);
 }
 
 void spai_op_free(SpaiOpQ1* Q) {
