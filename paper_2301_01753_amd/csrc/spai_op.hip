@@ -23,7 +23,6 @@
 #include <cmath>
 #include <vector>
 
-#include "eig.hpp"
 #include "gym_internal.hpp"
 #include "krylov.hpp"
 #include "spai.hpp"
@@ -278,24 +277,24 @@ __global__ void __launch_bounds__(kRowBT) box_apply(const SylvParams p, const do
   }
 }
 
-// y = U x = M1^2 x
-__global__ void __launch_bounds__(kRowBT) u_apply(const SylvParams p, const double* __restrict__ xv,
-                                               double* __restrict__ yv) {
-  const int r = p.r;
+// One factor of U = M1^2 = sc^2 (M_x^2 (x) M_y^2 (x) M_z^2) per component:
+// y = (M_a^2 along axis a) x, times sc^2 when `last`.  Three launches, one
+// per axis, apply U with 3 (4r + 1) terms per row.
+__global__ void __launch_bounds__(kRowBT) u_axis(const SylvParams p, const double* __restrict__ xv,
+                                              double* __restrict__ yv, int a, int last) {
+  const int r = p.r, L2 = 4 * r + 1;
   for (long long i = (long long)blockIdx.x * kRowBT + threadIdx.x; i < p.n1; i += (long long)gridDim.x * kRowBT) {
     const OpComp& d = p.c[comp_of(p, i)];
-    int x, y, z;
-    decode(d, i, x, y, z);
+    int xyz[3];
+    decode(d, i, xyz[0], xyz[1], xyz[2]);
+    const int pa = a == 0 ? xyz[0] : a == 1 ? xyz[1] : xyz[2];
+    const int na = d.n[a];
+    const long long st = a == 0 ? 1 : a == 1 ? (long long)d.n[0] : (long long)d.n[0] * d.n[1];
+    const double* band = d.M2[a] + (long long)pa * L2 + 2 * r;
     double acc = 0.0;
-    for (int ez = -2 * r; ez <= 2 * r; ++ez)
-      for (int ey = -2 * r; ey <= 2 * r; ++ey)
-        for (int ex = -2 * r; ex <= 2 * r; ++ex) {
-          const int nx = x + ex, ny = y + ey, nz = z + ez;
-          if (!inside(d, nx, ny, nz)) continue;
-          const double u = u_rel(d, r, x, y, z, ex, ey, ez);
-          if (u != 0.0) acc += u * xv[at(d, nx, ny, nz)];
-        }
-    yv[i] = d.sc * d.sc * acc;
+    for (int k = -2 * r; k <= 2 * r; ++k)
+      if ((unsigned)(pa + k) < (unsigned)na) acc += band[k] * xv[i + k * st];
+    yv[i] = last ? d.sc * d.sc * acc : acc;
   }
 }
 
@@ -374,16 +373,17 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
   // the first two allocations (tables, the solution q) outlive the call
   double* tab = alloc((long long)host.size());
   double* q = alloc(nq);
-  double* rv = alloc(2 * nq);  // r, then z = Pinv r: one Gram call gives r . r and r . z
+  double* rv = alloc(2 * nq);  // r, then z = Pinv r
   double* pv = alloc(nq);
   double* ap = alloc(nq);
   double* pinv = alloc(nq);
   double* X = alloc(std::max(1, np) * n1);
   double* Y = alloc(std::max(1, np) * n1);
   double* tmp = alloc(n1);
+  double* tmp2 = alloc(n1);
   const int nb = vec_grid(nq, ncu);
-  double* gw = alloc(eig_gram_work(nb));
-  if (!tab || !q || !rv || !pv || !ap || !pinv || !X || !Y || !tmp || !gw) {
+  double* gw = alloc(2LL * nb + 2);  // dot-product partials and results
+  if (!tab || !q || !rv || !pv || !ap || !pinv || !X || !Y || !tmp || !tmp2 || !gw) {
     release(false);
     return fail(GYM_E_OOM, "SPAI-OP: device allocation failed");
   }
@@ -420,19 +420,35 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
   P.lam = lam;
   P.eps = 1e-12 * dmax;
   const int nbr = row_grid(n1);
+  // out = U t, axis by axis: t -> tmp2 -> t -> out (t is overwritten)
+  auto u_apply = [&](double* t, double* out) {
+    hipLaunchKernelGGL(u_axis, dim3(nbr), dim3(kRowBT), 0, s, P, t, tmp2, 0, 0);
+    hipLaunchKernelGGL(u_axis, dim3(nbr), dim3(kRowBT), 0, s, P, tmp2, t, 1, 0);
+    hipLaunchKernelGGL(u_axis, dim3(nbr), dim3(kRowBT), 0, s, P, t, out, 2, 1);
+  };
   // A v for a slot vector v: X = U V W, Y = U V^T W, then the Sylvester operator
   auto apply = [&](const double* v, double* out) {
     for (int k = 0; k < np; ++k) {
+      double* xk = X + (long long)k * n1;
+      double* yk = Y + (long long)k * n1;
       hipLaunchKernelGGL(box_apply, dim3(nbr), dim3(kRowBT), 0, s, P, v, Wdev + (long long)k * n1, tmp, 0);
-      hipLaunchKernelGGL(u_apply, dim3(nbr), dim3(kRowBT), 0, s, P, tmp, X + (long long)k * n1);
+      u_apply(tmp, xk);
       hipLaunchKernelGGL(box_apply, dim3(nbr), dim3(kRowBT), 0, s, P, v, Wdev + (long long)k * n1, tmp, 1);
-      hipLaunchKernelGGL(u_apply, dim3(nbr), dim3(kRowBT), 0, s, P, tmp, Y + (long long)k * n1);
+      u_apply(tmp, yk);
     }
     sylv_apply(P, v, out, ncu, s);
   };
-  auto dot = [&](const double* a, const double* b, double* res) {
-    return eig_gram(a, 1, b, 1, nq, res, gw, nb, s);
+  // dot products a1 . b1 (and a2 . b2): deterministic two-stage sums into the
+  // work buffer, one copy to the host
+  auto dot2 = [&](const double* a1, const double* b1, const double* a2, const double* b2, double* res) {
+    double* part = gw;
+    double* dres = gw + 2LL * nb;
+    launch_norm2(a1, b1, nq, 1, nb, 2, part, dres, s);
+    if (a2) launch_norm2(a2, b2, nq, 1, nb, 2, part + nb, dres + 1, s);
+    if (hipMemcpyAsync(res, dres, sizeof(double) * (a2 ? 2 : 1), hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+    return hipStreamSynchronize(s) != hipSuccess ? -1 : 0;
   };
+  auto dot = [&](const double* a, const double* b, double* res) { return dot2(a, b, nullptr, nullptr, res); };
   // rhs into pv for now (pv is free until the first direction)
   hipLaunchKernelGGL(sylv_setup, dim3(nb), dim3(256), 0, s, P, pv, pinv);
   SpaiParams spp{};
@@ -453,7 +469,7 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
   // z = Pinv r, p = z
   launch_axpy_diag(zv, 0.0, 1.0, pinv, rv, nq, nb, s);
   launch_axpy_diag(pv, 0.0, 1.0, nullptr, zv, nq, nb, s);
-  if (!status && eig_gram(rv, 1, rv, 2, nq, rrz, gw, nb, s)) status = -1;
+  if (!status && dot2(rv, rv, zv, rv, rrz)) status = -1;
   double rz = rrz[1];
   const double bn = std::sqrt(bn2);
   double rel = bn > 0 ? std::sqrt(rrz[0]) / bn : 0.0;
@@ -472,9 +488,9 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
     launch_axpy_diag(q, 1.0, al, nullptr, pv, nq, nb, s);
     launch_axpy_diag(rv, 1.0, -al, nullptr, ap, nq, nb, s);
     ++it;
-    // z = Pinv r; r . r and r . z in one reduction; p = z + beta p
+    // z = Pinv r; r . r and r . z with one host round trip; p = z + beta p
     launch_axpy_diag(zv, 0.0, 1.0, pinv, rv, nq, nb, s);
-    if (eig_gram(rv, 1, rv, 2, nq, rrz, gw, nb, s)) {
+    if (dot2(rv, rv, zv, rv, rrz)) {
       status = -1;
       break;
     }
