@@ -391,6 +391,8 @@ def main():
                     help="skip the 64^3 degree-4 Poisson and perturbed 96^3 degree-3 Hodge rates")
     ap.add_argument("--profile-apply", type=int, default=0,
                     help="counter runs: copy calibration + this many MINRES steps, no JSON")
+    ap.add_argument("--profile-spai-q1", action="store_true",
+                    help="only the SPAI-Q1 time stepping (128^3 degree 1, 32^3 degree 2), for a kernel trace")
     ap.add_argument("--profile-spai-op", action="store_true",
                     help="only the SPAI-OP builds (degree 1 and 2) and stepping, for a kernel trace")
     ap.add_argument("--profile-maxwell", action="store_true",
@@ -412,6 +414,11 @@ def main():
     dev = torch.device("cuda:0")
     nel, r = (args.nel,) * 3, args.degree
     ctx = gym.gym_create(0)
+    if args.profile_spai_q1:
+        for N, deg, steps in ((128, 1, 200), (32, 2, 500)):
+            log(f"SPAI-Q1 time stepping {N}^3 degree {deg}: {maxwell_rates(gym, ctx, N, deg, 'spai', steps)}")
+        gym.gym_destroy(ctx)
+        return
     if args.profile_spai_op:
         for nel, deg in (((24, 20, 16), 1), ((12, 10, 8), 2)):
             log(f"SPAI-OP {nel} degree {deg}: {spai_op_rates(gym, ctx, nel, (1.0, 1.3, 0.8), deg, 5e5, 500)}")

@@ -99,41 +99,24 @@ void spai1d(const std::vector<double>& A, int count, int r, int pattern, std::ve
   }
 }
 
-__global__ void __launch_bounds__(256) spai_apply_kernel(const SpaiParams p, const double* __restrict__ x,
-                                                         double* __restrict__ y) {
+// One 1-D factor of a Kronecker term of Q1: y = (Q_a or Q_a^T along axis a) x
+// over every block; `last` finishes the second term: y = scale (y + acc).
+__global__ void __launch_bounds__(256) spai_axis_kernel(const SpaiParams p, int t, int a, int last,
+                                                        const double* __restrict__ x, double* __restrict__ y) {
   for (long long g = (long long)blockIdx.x * 256 + threadIdx.x; g < p.n; g += (long long)gridDim.x * 256) {
     const int c = (g >= p.c[1].offset) + (g >= p.c[2].offset);
     const SpaiComp& d = p.c[c];
-    const long long loc = g - d.offset;
-    const int i = (int)(loc % d.count[0]);
-    const long long rest = loc / d.count[0];
-    const int j = (int)(rest % d.count[1]);
-    const int k = (int)(rest / d.count[1]);
+    // 32-bit position arithmetic: a block holds fewer than 2^31 unknowns
+    const unsigned loc = (unsigned)(g - d.offset);
+    const unsigned c0 = (unsigned)d.count[0], plane = c0 * (unsigned)d.count[1];
+    const int pos = a == 0 ? (int)(loc % c0) : a == 1 ? (int)((loc / c0) % (unsigned)d.count[1]) : (int)(loc / plane);
+    const long long st = a == 0 ? 1 : a == 1 ? (long long)c0 : (long long)plane;
     const int w = d.w, L = 2 * w + 1;
-    const double* __restrict__ xc = x + d.offset;
+    const double* __restrict__ band = d.band[t][a] + (long long)pos * L + w;
     double acc = 0.0;
-    for (int t = 0; t < 2; ++t) {
-      const double* bx = d.band[t][0] + (long long)i * L;
-      const double* by = d.band[t][1] + (long long)j * L;
-      const double* bz = d.band[t][2] + (long long)k * L;
-      for (int sz = -w; sz <= w; ++sz) {
-        const int kk = k + sz;
-        const double vz = bz[sz + w];
-        if (kk < 0 || kk >= d.count[2] || vz == 0.0) continue;
-        for (int sy = -w; sy <= w; ++sy) {
-          const int jj = j + sy;
-          const double vyz = vz * by[sy + w];
-          if (jj < 0 || jj >= d.count[1] || vyz == 0.0) continue;
-          const long long row = (long long)d.count[0] * (jj + (long long)d.count[1] * kk);
-          for (int sx = -w; sx <= w; ++sx) {
-            const int ii = i + sx;
-            if (ii < 0 || ii >= d.count[0]) continue;
-            acc += vyz * bx[sx + w] * xc[row + ii];
-          }
-        }
-      }
-    }
-    y[g] = d.scale * acc;
+    for (int k = -w; k <= w; ++k)
+      if ((unsigned)(pos + k) < (unsigned)d.count[a]) acc += band[k] * x[g + k * st];
+    y[g] = last ? d.scale * (y[g] + acc) : acc;
   }
 }
 
@@ -143,6 +126,7 @@ int build_spai_q1(const gym_space* s1, int pattern, SpaiParams* out, double** me
   const SpaceDesc& sd = s1->desc;
   const gym_mesh* m = s1->mesh;
   if (sd.ncomp != 3 || m->dim != 3) return fail(GYM_E_ARG, "SPAI Q1: 3-D Lambda^1 only");
+  if (sd.ndofs >= (1LL << 31)) return fail(GYM_E_ARG, "SPAI Q1: more than 2^31 unknowns");
   const int r = sd.r;
   const LumpedTables lt = lumped_tables_host(s1);  // sc[c]: the metric constants
   std::vector<double> host;
@@ -160,7 +144,7 @@ int build_spai_q1(const gym_space* s1, int pattern, SpaiParams* out, double** me
       host.insert(host.end(), QTb.begin(), QTb.end());
     }
   void* p = nullptr;
-  if (hipMalloc(&p, sizeof(double) * host.size()) != hipSuccess) {
+  if (hipMalloc(&p, sizeof(double) * (host.size() + 2 * (size_t)sd.ndofs)) != hipSuccess) {
     (void)hipGetLastError();
     return fail(GYM_E_OOM, "SPAI Q1: device allocation failed");
   }
@@ -179,12 +163,22 @@ int build_spai_q1(const gym_space* s1, int pattern, SpaiParams* out, double** me
       for (int a = 0; a < 3; ++a) sc.band[t][a] = d + off[c][t][a];
   }
   out->n = sd.ndofs;
+  out->tmp[0] = d + host.size();
+  out->tmp[1] = d + host.size() + sd.ndofs;
   *mem = d;
   return 0;
 }
 
 void launch_spai_apply(const SpaiParams& p, const double* x, double* y, int nb, hipStream_t s) {
-  hipLaunchKernelGGL(spai_apply_kernel, dim3(nb), dim3(256), 0, s, p, x, y);
+  // one row per thread: each pass has a single load chain per row, so the
+  // loads in flight come from the number of resident waves
+  const long long rows = (p.n + 255) / 256;
+  if (rows > nb) nb = (int)(rows < (1LL << 20) ? rows : (1LL << 20));
+  for (int t = 0; t < 2; ++t) {  // Q_x (x) Q_y (x) Q_z, then the transposed term
+    hipLaunchKernelGGL(spai_axis_kernel, dim3(nb), dim3(256), 0, s, p, t, 0, 0, x, p.tmp[0]);
+    hipLaunchKernelGGL(spai_axis_kernel, dim3(nb), dim3(256), 0, s, p, t, 1, 0, (const double*)p.tmp[0], p.tmp[1]);
+    hipLaunchKernelGGL(spai_axis_kernel, dim3(nb), dim3(256), 0, s, p, t, 2, t, (const double*)p.tmp[1], y);
+  }
 }
 
 }  // namespace gym

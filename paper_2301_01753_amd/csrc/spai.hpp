@@ -24,7 +24,8 @@ struct SpaiComp {
 };
 struct SpaiParams {
   SpaiComp c[3];
-  long long n;  // unknowns of Lambda^1
+  long long n;     // unknowns of Lambda^1
+  double* tmp[2];  // two n-vectors of scratch for the axis passes of the apply
 };
 
 // Builds Q1 = (Q + Q^T) / 2, Q the column-wise least-squares SPAI of M1 with
@@ -34,10 +35,12 @@ struct SpaiParams {
 // restricted to the kept positions), both patterns are Kronecker products
 // of 1-D patterns, and each column's normal equations are the Kronecker
 // product of 1-D normal equations: so Q's block is (1/s_c) Q_x (x) Q_y (x) Q_z
-// with Q_a the 1-D SPAI of M_a.  The bands go to one device allocation,
-// returned in *mem (the caller frees it).
+// with Q_a the 1-D SPAI of M_a.  The bands and the apply's scratch go to one
+// device allocation, returned in *mem (the caller frees it).
 int build_spai_q1(const gym_space* s1, int pattern, SpaiParams* out, double** mem);
-// y = Q1 x
+// y = Q1 x, as six 1-D band passes (three per Kronecker term) through the
+// scratch in p; x and y must not overlap, and applies sharing p must not
+// run concurrently.
 void launch_spai_apply(const SpaiParams& p, const double* x, double* y, int nb, hipStream_t s);
 
 // Assembled 1-D mass of nel elements of degree r on the reference element,
