@@ -1,22 +1,26 @@
 """Benchmark of the matrix-free FEEC hot path on one MI355X.
 
-Workload (default): 3-D unit cube, 32^3 hexahedra, degree-2 Hodge Laplacian
-on 1-forms (sigma in H1_0, u in H0(curl)), right-hand side = load vector of
-an 8-mode Fourier field with N(0, 1) coefficients (seed 0), FP64
-matrix-free operator inside block-Jacobi preconditioned MINRES.
+Headline workload: the unit cube, 96^3 hexahedra with seeded vertex
+perturbations (+-15% of h per coordinate, multilinear cells, so every cell has
+its own Jacobian field), degree-3 Hodge Laplacian on 1-forms (sigma in H1_0,
+u in H0(curl)), 8 right-hand sides per apply, FP64.  758.5 M unknowns per
+apply (94.8 M per right-hand side).
 
-A step is one whole solve (every Krylov iteration: incidence, sum-factorised
-masses, transposed incidence, deterministic reductions, vector updates) to a
-relative residual of 1e-10, starting from x = 0 with b already in HBM.
+A step is one FP64 operator apply y = A x of all 8 right-hand sides: the
+gather of the lattice closure, the incidence G, C (+-1 sums), the four mass
+applies (M0, M1 twice, M2) by sum-factorised contractions with the
+Gauss-point metrics of the curved cells, the transposed incidence and the
+deterministic scatter.  x is resident in HBM before the timed region.
 
-value = operator-apply throughput inside the solve:
-        (DoFs x MINRES iterations) summed over the timed solves / wall time,
-in GDoF/s.  Also printed: solves/s, the pure operator-apply rate, the
-relative error of each result against an FP64 reference solve (rtol 1e-13),
-the mixed-precision mode (FP32 inner solve inside FP64 refinement) and the
-batched mode (8 right-hand sides per launch) on the same operator.
+value = 8 x ndofs / (median HIP-event time of one apply), GDoF/s; the wall
+time of the K timed applies gives ms_per_step.  Also reported (extras): the
+FP32 apply of the same workload with its error against FP64; the 64^3
+degree-4 mixed Poisson workload: applies per precision and whole solves to
+relative residual 1e-8 in FP64 and in FP32 / bf16-operand refinement, each
+with its error against the FP64 solution; the 32^3 degree-2 Hodge solves; the
+serving loop; the time-stepping, eigen-solver and SPAI-OP rates.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-extras]
 """
 import argparse
 import json
@@ -32,6 +36,8 @@ METRIC = "operator-apply GDoF/s and solves/s to 1e-8 rel. err: FP64 vs mixed vs 
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 PEAK_FP64_TFLOPS = 78.6        # 256 CU x 64 FP64 FMA lanes x 2 x 2.4 GHz
 PEAK_FP32_TFLOPS = 157.3
+
+HEAD_N, HEAD_R, HEAD_PERTURB, HEAD_NRHS = 96, 3, 0.15, 8
 
 
 def log(msg):
@@ -54,24 +60,30 @@ def kron_comp_flops(n):
     return 2 * nx * ny * nz * (nx + ny + nz)
 
 
-def algorithmic_flops_per_element(problem, r, kron=False):
-    """Flops per element of one operator apply (no halo recomputation): the
-    Gauss-point sum factorisation (q = r + 1), or the Kronecker form that the
-    kernel evaluates on affine cells."""
+def algorithmic_flops_per_element(problem, r, kron=False, metric=False):
+    """Flops per element and right-hand side of one operator apply (no halo
+    recomputation): the Gauss-point sum factorisation (q = r + 1), or the
+    Kronecker form that the kernel evaluates on affine cells.  metric: add the
+    pointwise metric at the q^3 Gauss points of curved cells, 1 flop per point
+    for a scalar mass and 15 (symmetric 3x3 times a 3-vector) for a vector
+    mass."""
     q, N, E = r + 1, r + 1, r
     f = kron_comp_flops if kron else (lambda n: comp_flops(n, q))
     h1 = f((N, N, N))
     hcurl = sum(f(tuple(E if a == c else N for a in range(3))) for c in range(3))
     hdiv = sum(f(tuple(N if a == c else E for a in range(3))) for c in range(3))
     l2 = f((E, E, E))
+    pts = q ** 3 if metric else 0
     if problem == "hodge":
-        return h1 + 2 * hcurl + hdiv       # M0 sigma, M1 u, M1 G sigma, M2 C u
-    return hdiv + 2 * l2                   # M2 s, M3 p, M3 D s
+        return h1 + 2 * hcurl + hdiv + pts * (1 + 15 + 15 + 15)   # M0 sigma, M1 u, M1 G sigma, M2 C u
+    return hdiv + 2 * l2 + pts * (15 + 1 + 1)                     # M2 s, M3 p, M3 D s
 
 
-def cpu_baseline(nel, r, rtol):
-    """The CPU oracle (SciPy MINRES on the assembled operator) on a reduced
-    mesh of the same workload, single-threaded."""
+def cpu_baseline(N, r, nrhs, reps=20):
+    """The CPU oracle on a bounded sample of the headline workload: the same
+    perturbed-mesh recipe at N^3 cells, degree r, assembled by naive
+    quadrature (not timed in the rate), then the median of `reps` sparse
+    applies to nrhs right-hand sides, one thread."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -81,36 +93,168 @@ def cpu_baseline(nel, r, rtol):
 
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        P = problems.Hodge1(Mesh(synth.uniform_vertices(nel)), r)
-        coeffs = synth.fourier_coeffs(0, 8, 3)
-        _, _, f = problems.hodge_fields(coeffs, synth.modes_3d())
-        b = P.rhs(f)
+        P = problems.Hodge1(Mesh(synth.perturbed_vertices_counter((N, N, N), HEAD_PERTURB, 0)), r)
         t_asm = time.perf_counter() - t0
-        its = [0]
-
-        def cb(_):
-            its[0] += 1
-
-        import scipy.sparse as sp
-        import scipy.sparse.linalg as spla
-        Minv = sp.diags(1.0 / P.precond_diag())
-        t0 = time.perf_counter()
-        # SciPy's stopping test is looser than a true relative residual;
-        # a tighter internal tolerance brings the true residual near `rtol`
-        x, info = spla.minres(P.A, b, M=Minv, rtol=rtol * 1e-4, maxiter=20000, callback=cb)
-        t_solve = time.perf_counter() - t0
-    n = P.A.shape[0]
-    rel = float(np.linalg.norm(P.A @ x - b) / np.linalg.norm(b))
+        n = P.A.shape[0]
+        X = np.asarray(synth.random_vector(n, seed=3, nrhs=nrhs).reshape(nrhs, n).T, order="F")
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            P.A @ X
+            ts.append(time.perf_counter() - t0)
+    t = float(np.median(ts))
     return {
-        "value": n * its[0] / t_solve / 1e9,
+        "value": nrhs * n / t / 1e9,
         "unit": "GDoF/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"SciPy MINRES on the assembled {nel[0]}x{nel[1]}x{nel[2]} degree-{r} Hodge system "
-                   f"({n} DoFs, {its[0]} iterations, rel. residual {rel:.1e}) in {t_solve:.2f} s; "
-                   f"assembly {t_asm:.2f} s not counted; 1 thread of {os.cpu_count()} host cores"),
-        "solves_per_s_at_sample": 1.0 / t_solve,
+        "sample": (f"SciPy CSR apply of the assembled {N}^3 perturbed (15%) degree-{r} Hodge operator "
+                   f"({n} DoFs, {P.A.nnz} nonzeros) to {nrhs} right-hand sides, median of {reps}: "
+                   f"{t * 1e3:.2f} ms; assembly {t_asm:.1f} s not counted; 1 thread of {os.cpu_count()} host cores"),
     }
+
+
+def event_times(fn, reps, warmup):
+    """Run fn() warmup + reps times on the current stream; returns (per-call
+    HIP-event ms list, wall seconds of the timed calls)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) for a, b in ev], wall
+
+
+def median(v):
+    v = sorted(v)
+    k = len(v)
+    return 0.5 * (v[(k - 1) // 2] + v[k // 2])
+
+
+def apply_rates(gym, op, n, nrhs, precs, reps, warmup, seed):
+    """Median apply time per contraction precision and the relative error of
+    each lower-precision apply against the FP64 apply of the same vector."""
+    import torch
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(seed)
+    x = torch.randn(nrhs * n, dtype=torch.float64, device="cuda:0", generator=gen)
+    y64 = torch.empty_like(x)
+    out = {}
+    for name, prec in precs:
+        xi = x if prec == gym.GYM_F64 else x.float()
+        yi = y64 if prec == gym.GYM_F64 else torch.empty_like(xi)
+        ms, wall = event_times(lambda: gym.gym_op_apply(op, prec, nrhs, xi, yi), reps, warmup)
+        t = median(ms)
+        e = {"median_us": t * 1e3, "gdof_s": nrhs * n / t / 1e6, "applies": reps}
+        if prec != gym.GYM_F64:
+            e["rel_err_vs_f64_apply"] = float(torch.linalg.norm(yi.double() - y64) / torch.linalg.norm(y64))
+        out[name] = e
+        del yi
+    del x, y64
+    return out
+
+
+def poisson64_solves(gym, ctx, rtol, modes, reps):
+    """64^3 degree-4 mixed Poisson (67.3 M unknowns): whole solves from x = 0
+    to relative residual `rtol` (true FP64 residual) in FP64 and in
+    mixed-precision refinement; each result's relative error against the
+    FP64 solution.  Also the apply rates per precision."""
+    import torch
+    import synth
+    mesh = gym.gym_mesh_create(ctx, 3, (64, 64, 64))
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON, mesh, 4)
+    n = gym.gym_op_ndofs(op)
+    res = {"ndofs": n, "apply": apply_rates(gym, op, n, 1, (("f64", gym.GYM_F64), ("f32", gym.GYM_F32),
+                                                            ("bf16", gym.GYM_BF16)), 50, 3, 11)}
+    b = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    gym.gym_rhs_manufactured(op, synth.modes_3d(), synth.fourier_coeffs(0, 8, 1), b)
+    x64 = None
+    for name, mode, inner in modes:
+        o = gym.gym_solve_opts_default()
+        o.mode = mode
+        o.rtol = rtol
+        o.maxit = 200000
+        o.inner_rtol = inner
+        o.max_outer = 60
+        o.check_every = 50
+        x = torch.empty_like(b)
+        walls, infos = [], []
+        for k in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            inf = gym.gym_solve(op, o, 1, b, x)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+            infos.append(inf)
+            log(f"  poisson 64^3 r4 {name} solve {k}: {inf.iters} it, {inf.outer_iters} outer, "
+                f"rel_res {inf.rel_res:.2e}, {walls[-1]:.2f} s")
+        e = {"solves_per_s": reps / sum(walls), "seconds_per_solve": sum(walls) / reps,
+             "iters": infos[-1].iters, "outer_iters": infos[-1].outer_iters, "rel_res": infos[-1].rel_res,
+             "status": infos[-1].status}
+        if mode != gym.GYM_MODE_F64:
+            e["inner_rtol"] = inner
+        if x64 is None:
+            x64 = x.clone()
+        else:
+            e["rel_err_vs_fp64_solve"] = float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+        res[name] = e
+    f64 = res[modes[0][0]]["solves_per_s"]
+    for name, _, _ in modes[1:]:
+        res[name]["speedup_vs_fp64"] = res[name]["solves_per_s"] / f64
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+    del b, x, x64
+    torch.cuda.empty_cache()
+    return res
+
+
+def hodge32_solves(gym, ctx, steps, rtol):
+    """32^3 degree-2 Hodge (1.01 M unknowns, manufactured 8-mode field): FP64
+    solves to `rtol`, 8 right-hand sides per solve, and IR-FP32."""
+    import torch
+    import synth
+    mesh = gym.gym_mesh_create(ctx, 3, (32, 32, 32))
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, 2)
+    n = gym.gym_op_ndofs(op)
+    b = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    gym.gym_rhs_manufactured(op, synth.modes_3d(), synth.fourier_coeffs(0, 8, 3), b)
+    res = {"ndofs": n}
+
+    def run(mode, nrhs, bv, k):
+        o = gym.gym_solve_opts_default()
+        o.rtol, o.mode, o.timing = rtol, mode, 16
+        x = torch.empty_like(bv)
+        gym.gym_solve(op, o, nrhs, bv, x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, ap, ms = 0, 0, 0.0
+        for _ in range(k):
+            inf = gym.gym_solve(op, o, nrhs, bv, x)
+            its, ap, ms = its + inf.iters, ap + inf.applies, ms + inf.apply_ms
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return {"solves_per_s": nrhs * k / wall, "iters_per_solve": its / k, "rel_res": inf.rel_res,
+                "gdof_s_in_solve": nrhs * n * its / wall / 1e9,
+                "apply_us": ms / max(ap, 1) * 1e3}, x
+
+    res["f64"], x64 = run(gym.GYM_MODE_F64, 1, b, steps)
+    res["ir_f32"], x32 = run(gym.GYM_MODE_IR_F32, 1, b, max(1, steps // 2))
+    res["ir_f32"]["rel_err_vs_fp64_solve"] = float(torch.linalg.norm(x32 - x64) / torch.linalg.norm(x64))
+    B = torch.empty(8 * n, dtype=torch.float64, device="cuda:0")
+    for k in range(8):
+        gym.gym_rhs_manufactured(op, synth.modes_3d(), synth.fourier_coeffs(k, 8, 3), B[k * n:(k + 1) * n])
+    res["f64_8rhs"], _ = run(gym.GYM_MODE_F64, 8, B, max(1, steps // 4))
+    res["f64_8rhs"]["speedup_vs_fp64"] = res["f64_8rhs"]["solves_per_s"] / res["f64"]["solves_per_s"]
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+    return res
 
 
 def serving(gym, nreq, seed, max_slots, qps=None, budget=64 << 30):
@@ -154,67 +298,45 @@ def serving(gym, nreq, seed, max_slots, qps=None, budget=64 << 30):
             "mean_ndofs": float(np.mean([r.ndofs for r in done.values()]))}
 
 
-def workload_rates(gym, ctx, which, N, r, perturb, nrhs, steps, seed):
-    """Apply rates per contraction precision (with the error against the FP64
-    apply on the same vector), and MINRES step throughput over a fixed number
-    of steps: FP64, and FP32 / BF16 inner steps of the refinement."""
+def profile_workload(gym, ctx, which, applies):
+    """For kernel traces and HBM counters: a plain copy of known size (it
+    calibrates FETCH_SIZE / WRITE_SIZE per byte), then `applies` operator
+    applies of the workload per contraction precision, no timing of its own."""
     import torch
-    import synth
-    verts = synth.perturbed_vertices((N, N, N), perturb, seed=0) if perturb else None
-    mesh = gym.gym_mesh_create(ctx, 3, (N, N, N), vertices=verts)
-    op = gym.gym_op_create(ctx, gym.GYM_HODGE1 if which == "hodge" else gym.GYM_MIXED_POISSON, mesh, r)
+    dev = torch.device("cuda:0")
+    src = torch.empty(32 << 20, dtype=torch.float64, device=dev).normal_()
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    del src, dst
+    if which == "poisson_r4_64cube":
+        N, r, perturb, nrhs, prob = 64, 4, 0.0, 1, gym.GYM_MIXED_POISSON
+        precs = (("f64", gym.GYM_F64), ("f32", gym.GYM_F32), ("bf16", gym.GYM_BF16))
+    else:
+        N, r, perturb, nrhs, prob = 96, 3, 0.15, 8, gym.GYM_HODGE1
+        precs = (("f64", gym.GYM_F64), ("f32", gym.GYM_F32))
+    mesh = workload_mesh(gym, ctx, N, perturb)
+    op = gym.gym_op_create(ctx, prob, mesh, r)
     n = gym.gym_op_ndofs(op)
-    gen = torch.Generator(device="cuda:0")
-    gen.manual_seed(seed)
-    x = torch.randn(nrhs * n, dtype=torch.float64, device="cuda:0", generator=gen)
-    y64 = torch.empty_like(x)
-    res = {"ndofs": n, "nrhs": nrhs, "apply": {}, "minres_steps": {}}
-    precs = [("f64", gym.GYM_F64), ("f32", gym.GYM_F32)] + ([] if perturb else [("bf16", gym.GYM_BF16)])
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    x = torch.randn(nrhs * n, dtype=torch.float64, device=dev, generator=gen)
     for name, prec in precs:
         xi = x if prec == gym.GYM_F64 else x.float()
-        yi = y64 if prec == gym.GYM_F64 else torch.empty_like(xi)
-        gym.gym_op_apply(op, prec, nrhs, xi, yi)
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        reps = 5
-        e0.record()
-        for _ in range(reps):
+        yi = torch.empty_like(xi)
+        for k in range(applies):
             gym.gym_op_apply(op, prec, nrhs, xi, yi)
-        e1.record()
-        torch.cuda.synchronize()
-        us = e0.elapsed_time(e1) / reps * 1e3
-        entry = {"us_per_apply": us, "gdof_s": nrhs * n / us / 1e3}
-        if prec != gym.GYM_F64:
-            entry["rel_err_vs_f64_apply"] = float(torch.linalg.norm(yi.double() - y64) / torch.linalg.norm(y64))
-        res["apply"][name] = entry
-        del yi
-    b = torch.randn(nrhs * n, dtype=torch.float64, device="cuda:0", generator=gen)
-    xs = torch.empty_like(b)
-    modes = [("f64", gym.GYM_MODE_F64), ("ir_f32", gym.GYM_MODE_IR_F32)] + \
-        ([] if perturb else [("ir_bf16", gym.GYM_MODE_IR_BF16)])
-    for name, mode in modes:
-        o = gym.gym_solve_opts_default()
-        o.mode = mode
-        o.maxit = steps
-        o.max_outer = 1
-        o.inner_rtol = 1e-30
-        o.check_every = steps
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        inf = gym.gym_solve(op, o, nrhs, b, xs)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        res["minres_steps"][name] = {"steps": inf.iters, "wall_s": wall,
-                                     "gdof_s": nrhs * n * inf.iters / wall / 1e9, "rel_res": inf.rel_res}
-    res["minres_steps"]["note"] = ("fixed step count from x = 0 (one solve call, including its setup and the "
-                                   "final FP64 residual); a full solve to 1e-8 with the block-Jacobi "
-                                   "preconditioner takes thousands of steps at this size")
+            torch.cuda.synchronize()
+            log(f"profile-workload {which}: {name} apply {k + 1}/{applies} done")
+        del xi, yi
     gym.gym_op_destroy(op)
     gym.gym_mesh_destroy(mesh)
-    del x, y64, b, xs
-    torch.cuda.empty_cache()
-    return res
+
+
+def workload_mesh(gym, ctx, N, perturb):
+    """N^3 unit-cube mesh; perturb > 0: the library's seeded perturbed mesh
+    (SplitMix64 offsets, seed 0)."""
+    return gym.gym_mesh_structured(ctx, 3, (N, N, N), perturb, 0)
 
 
 def maxwell_rates(gym, ctx, N, r, q1, steps):
@@ -345,9 +467,9 @@ def cfl_rate(gym, ctx, N):
 # (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) is reported only while these are
 # unchanged since the counters were taken.
 KERNEL_SOURCES = ("paper_2301_01753_amd/csrc/op_kernel.hpp", "paper_2301_01753_amd/csrc/tile.hpp",
-                  "paper_2301_01753_amd/csrc/minres_step.hpp", "paper_2301_01753_amd/csrc/op_hodge.hip",
-                  "paper_2301_01753_amd/csrc/kernels.hpp")
-TRAFFIC_FILE = "profiles/op_kernel_hodge_r2_32cube_traffic.txt"
+                  "paper_2301_01753_amd/csrc/curved.hpp", "paper_2301_01753_amd/csrc/minres_step.hpp",
+                  "paper_2301_01753_amd/csrc/op_hodge.hip", "paper_2301_01753_amd/csrc/kernels.hpp")
+TRAFFIC_FILE = "profiles/op_kernel_hodge_r3_96cube_perturbed_traffic.txt"
 
 
 def kernel_source_hash():
@@ -359,7 +481,7 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(nel, r):
+def measured_traffic(workload):
     """HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE) of the operator
     kernel on this workload, or None when not measured for the current sources."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
@@ -371,8 +493,7 @@ def measured_traffic(nel, r):
             if "=" in line and not line.startswith("#"):
                 k, v = line.strip().split("=", 1)
                 kv[k] = v
-    if kv.get("source_hash") != kernel_source_hash() or int(kv.get("nel", -1)) != nel or \
-            int(kv.get("degree", -1)) != r:
+    if kv.get("source_hash") != kernel_source_hash() or kv.get("workload") != workload:
         return None
     return float(kv["fetch_bytes"]) + float(kv["write_bytes"])
 
@@ -380,17 +501,17 @@ def measured_traffic(nel, r):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--nel", type=int, default=32)
-    ap.add_argument("--degree", type=int, default=2)
-    ap.add_argument("--rtol", type=float, default=1e-10)
+    ap.add_argument("--steps", type=int, default=60, help="timed applies (>= 50 for the median)")
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-modes", action="store_true")
-    ap.add_argument("--no-extras", action="store_true",
-                    help="skip the 64^3 degree-4 Poisson and perturbed 96^3 degree-3 Hodge rates")
+    ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--no-solves", action="store_true", help="skip the 64^3 degree-4 Poisson solves")
     ap.add_argument("--profile-apply", type=int, default=0,
-                    help="counter runs: copy calibration + this many MINRES steps, no JSON")
+                    help="counter runs: copy calibration + this many MINRES steps of the 32^3 degree-2 Hodge "
+                         "workload, no JSON")
+    ap.add_argument("--profile-workload", choices=("poisson_r4_64cube", "hodge_r3_96cube_perturbed_8rhs"),
+                    help="counter/trace runs: copy calibration + K operator applies per precision of that "
+                         "workload, no JSON")
     ap.add_argument("--profile-spai-q1", action="store_true",
                     help="only the SPAI-Q1 time stepping (128^3 degree 1, 32^3 degree 2), for a kernel trace")
     ap.add_argument("--profile-spai-op", action="store_true",
@@ -402,17 +523,15 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the operator would shard).", file=sys.stderr)
+              "(DESIGN.md describes how the operator would shard).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
 
-    import synth
     from paper_2301_01753_amd import gym
 
     dev = torch.device("cuda:0")
-    nel, r = (args.nel,) * 3, args.degree
     ctx = gym.gym_create(0)
     if args.profile_spai_q1:
         for N, deg, steps in ((128, 1, 200), (32, 2, 500)):
@@ -424,28 +543,26 @@ def main():
             log(f"SPAI-OP {nel} degree {deg}: {spai_op_rates(gym, ctx, nel, (1.0, 1.3, 0.8), deg, 5e5, 500)}")
         gym.gym_destroy(ctx)
         return
+    if args.profile_workload:
+        profile_workload(gym, ctx, args.profile_workload, args.steps)
+        gym.gym_destroy(ctx)
+        return
     if args.profile_maxwell:
         for N, deg in ((128, 1), (32, 2)):
             log(f"lumped time stepping {N}^3 degree {deg}: {maxwell_rates(gym, ctx, N, deg, 'lumped', 2000)}")
         gym.gym_destroy(ctx)
         return
-    mesh = gym.gym_mesh_create(ctx, 3, nel)
-    op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, r)
-    n = gym.gym_op_ndofs(op)
-    modes = synth.modes_3d()
-    b = torch.empty(n, dtype=torch.float64, device=dev)
-    gym.gym_rhs_manufactured(op, modes, synth.fourier_coeffs(0, 8, 3), b)
-    log(f"workload: {nel} degree {r} Hodge, {n} DoFs")
-
     if args.profile_apply:
-        # counter runs: a plain copy of known size (calibrates FETCH_SIZE /
-        # WRITE_SIZE per byte), then operator applies on the bench workload
+        import synth
+        mesh = gym.gym_mesh_create(ctx, 3, (32, 32, 32))
+        op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, 2)
+        n = gym.gym_op_ndofs(op)
+        b = torch.empty(n, dtype=torch.float64, device=dev)
+        gym.gym_rhs_manufactured(op, synth.modes_3d(), synth.fourier_coeffs(0, 8, 3), b)
         src = torch.empty(32 << 20, dtype=torch.float64, device=dev).normal_()
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
-        # the operator kernel as the solve runs it: K MINRES steps (K fused
-        # applies, each followed by minres_step2)
         xv = torch.empty_like(b)
         o = gym.gym_solve_opts_default()
         o.maxit = args.profile_apply
@@ -454,71 +571,39 @@ def main():
         log(f"profile-apply: copy of {src.numel() * 8} bytes x3, {args.profile_apply} MINRES steps")
         return
 
-    # FP64 reference (untimed), tight tolerance
-    xref = torch.empty_like(b)
-    o = gym.gym_solve_opts_default()
-    o.rtol = 1e-13
-    info = gym.gym_solve(op, o, 1, b, xref)
-    log(f"reference solve: {info.iters} iterations, rel_res {info.rel_res:.2e}")
-
-    def run_mode(mode, nrhs, bvec, steps, warmup):
-        x = torch.empty_like(bvec)
-        o = gym.gym_solve_opts_default()
-        o.rtol = args.rtol
-        o.mode = mode
-        o.inner_rtol = 1e-4
-        o.timing = 16  # one apply in 16 bracketed by HIP events
-        for _ in range(warmup):
-            gym.gym_solve(op, o, nrhs, bvec, x)
-        torch.cuda.synchronize()
-        iters, applies, apply_ms, worst = 0, 0, 0.0, 0.0
-        t0 = time.perf_counter()
-        infos = []
-        for k in range(steps):
-            inf = gym.gym_solve(op, o, nrhs, bvec, x)
-            infos.append((inf.iters, inf.outer_iters, inf.rel_res, inf.applies, inf.apply_ms, inf.status))
-            log(f"  mode {mode} nrhs {nrhs} step {k}: {inf.iters} it, rel_res {inf.rel_res:.2e}")
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        for it, _, rr, na, ms, st in infos:
-            iters += it
-            applies += na
-            apply_ms += ms
-            worst = max(worst, rr)
-        return x, wall, iters, applies, apply_ms, worst, infos
-
-    def rel_err(x, ref):
-        return float(torch.linalg.norm(x - ref) / torch.linalg.norm(ref))
-
-    # ---- FP64 (the headline) ----
-    torch.cuda.synchronize()
-    x, wall, iters, applies, apply_ms, worst, infos = run_mode(gym.GYM_MODE_F64, 1, b, args.steps, args.warmup)
-    err64 = rel_err(x, xref)
-    value = n * iters / wall / 1e9
-    ms_per_step = wall / args.steps * 1e3
-    apply_avg_s = apply_ms / applies / 1e3
-    # The kernel evaluates the masses in the Kronecker form on these affine
-    # cells; its arithmetic intensity decides the binding roofline.
-    flops = algorithmic_flops_per_element("hodge", r, kron=True) * int(np.prod(nel))
-    flops_q = algorithmic_flops_per_element("hodge", r) * int(np.prod(nel))
-    bytes_ = 16.0 * n
-    ai = flops / bytes_
-    ridge = PEAK_FP64_TFLOPS * 1e12 / (PEAK_HBM_GBS * 1e9)
-    if ai > ridge:
-        roof = {"bound": "alu", "achieved": flops / apply_avg_s / 1e12, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": bytes_ / apply_avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    # ---- headline: perturbed 96^3 degree-3 Hodge, 8 rhs, FP64 apply ----
+    N, r, nrhs = HEAD_N, HEAD_R, HEAD_NRHS
+    t0 = time.perf_counter()
+    mesh = gym.gym_mesh_structured(ctx, 3, (N, N, N), HEAD_PERTURB, 0)
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, r)
+    n = gym.gym_op_ndofs(op)
+    log(f"workload: perturbed {N}^3 degree {r} Hodge, {n} DoFs x {nrhs} rhs (setup {time.perf_counter() - t0:.1f} s)")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(12)
+    x = torch.randn(nrhs * n, dtype=torch.float64, device=dev, generator=gen)
+    y = torch.empty_like(x)
+    ms, wall = event_times(lambda: gym.gym_op_apply(op, gym.GYM_F64, nrhs, x, y), args.steps, args.warmup)
+    t_med = median(ms) / 1e3
+    value = nrhs * n / t_med / 1e9
+    log(f"FP64 apply: median {t_med * 1e3:.3f} ms over {args.steps} applies ({min(ms):.3f} .. {max(ms):.3f} ms), "
+        f"wall {wall / args.steps * 1e3:.3f} ms per apply")
+    nel3 = N ** 3
+    flops = algorithmic_flops_per_element("hodge", r, metric=True) * nel3 * nrhs
+    # bytes: the vectors in and out once, and the 13 Gauss-point metric fields
+    # the Hodge operator reads (det J, the HCURL and HDIV metrics) once
+    qbytes = 13 * 8.0 * ((r + 1) * N) ** 3
+    bytes_ = 16.0 * n * nrhs + qbytes
+    roof = {"bound": "alu", "achieved": flops / t_med / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = measured_traffic(nel[0], r)
-    roof["kernel"] = "op_kernel<Hodge, r=%d, Kronecker, FP64, fused MINRES step>" % r
-    roof["avg_launch_us"] = apply_avg_s * 1e6
-    roof["algorithmic_bytes"] = bytes_
+    roof["traffic"] = measured_traffic("hodge_r3_96cube_perturbed_8rhs_f64")
+    roof["kernel"] = "op_kernel_rhs<Hodge, r=3, curved (Gauss-point metrics), FP64>"
+    roof["avg_launch_us"] = sum(ms) / len(ms) * 1e3
+    roof["median_launch_us"] = t_med * 1e6
     roof["algorithmic_flops"] = flops
-    roof["arithmetic_intensity"] = ai
-    roof["achieved_tflops"] = flops / apply_avg_s / 1e12
-    roof["algorithmic_flops_gauss_point_form"] = flops_q
-
+    roof["algorithmic_bytes"] = bytes_
+    roof["arithmetic_intensity"] = flops / bytes_
+    roof["achieved_hbm_gb_s"] = bytes_ / t_med / 1e9
+    roof["hbm_frac"] = roof["achieved_hbm_gb_s"] / PEAK_HBM_GBS
     out = {
         "metric": METRIC,
         "value": value,
@@ -526,74 +611,57 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": wall / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"3-D unit cube {nel[0]}^3 hex, degree-{r} Hodge Laplacian on 1-forms "
-                        f"(H1_0 x H0(curl)), FP64 matrix-free apply + block-Jacobi MINRES to rel. residual "
-                        f"{args.rtol:g}, 8-mode manufactured field (seed 0)",
-            "ndofs": n,
+            "workload": (f"unit cube {N}^3 hex, seeded vertex perturbation 15% of h (SplitMix64, seed 0), "
+                         f"degree-{r} Hodge Laplacian on 1-forms (H1_0 x H0(curl)), {nrhs} N(0,1) right-hand "
+                         f"sides, FP64 matrix-free operator apply"),
+            "ndofs_per_rhs": n,
+            "nrhs": nrhs,
             "parallelism": "single GPU",
         },
-        "solves_per_s": args.steps / wall,
-        "iters_per_solve": iters / args.steps,
-        "rel_err_vs_fp64_ref": err64,
-        "apply_gdof_s": n / apply_avg_s / 1e9,
+        "apply_median_ms": t_med * 1e3,
         "roofline": roof,
     }
-
-    if not args.no_modes:
-        # ---- mixed precision: FP32 inner MINRES inside FP64 refinement ----
-        xm, wall_m, it_m, ap_m, ms_m, worst_m, inf_m = run_mode(gym.GYM_MODE_IR_F32, 1, b, args.steps, 1)
-        out["mixed_ir_f32"] = {
-            "solves_per_s": args.steps / wall_m, "gdof_s": n * it_m / wall_m / 1e9,
-            "inner_iters_per_solve": it_m / args.steps, "outer_iters": inf_m[-1][1],
-            "rel_err_vs_fp64_ref": rel_err(xm, xref), "rel_res": worst_m,
-            "apply_gdof_s_f32": n / (ms_m / ap_m / 1e3) / 1e9,
-            "speedup_vs_fp64": (args.steps / wall_m) / (args.steps / wall),
-        }
-        # ---- batched: 8 right-hand sides per launch ----
-        nb = 8
-        B = torch.empty(nb * n, dtype=torch.float64, device=dev)
-        for k in range(nb):
-            gym.gym_rhs_manufactured(op, modes, synth.fourier_coeffs(k, 8, 3), B[k * n:(k + 1) * n])
-        xb, wall_b, it_b, ap_b, ms_b, worst_b, inf_b = run_mode(gym.GYM_MODE_F64, nb, B, max(2, args.steps // 4), 1)
-        steps_b = max(2, args.steps // 4)
-        out["batched_8rhs"] = {
-            "solves_per_s": nb * steps_b / wall_b, "gdof_s": nb * n * it_b / wall_b / 1e9,
-            "iters_per_solve": it_b / steps_b, "rel_res": worst_b,
-            "apply_gdof_s": nb * n / (ms_b / ap_b / 1e3) / 1e9,
-            "speedup_vs_fp64": (nb * steps_b / wall_b) / (args.steps / wall),
-        }
-
-    if args.serve_requests > 0:
-        # continuous batching vs one request at a time, same requests, same GPU
-        log("serving (batched) ...")
-        batched = serving(gym, args.serve_requests, 7, max_slots=32)
-        log("serving (one at a time) ...")
-        single = serving(gym, args.serve_requests, 7, max_slots=1)
-        log("serving (Poisson arrivals at half the batched rate) ...")
-        arrivals = serving(gym, args.serve_requests, 7, max_slots=32, qps=0.5 * batched["solves_per_s"])
-        out["serving"] = {
-            "workload": "mixed Poisson, N ~ U{8..48}^3 hex, degree ~ U{1,2,3}, N(0,1) rhs (seeded), "
-                        "rel. residual 1e-8",
-            "batched": batched, "one_at_a_time": single, "poisson_arrivals": arrivals,
-            "speedup_batched_vs_one_at_a_time": batched["solves_per_s"] / single["solves_per_s"],
-        }
+    extras = {}
+    if not args.no_extras:
+        log("FP32 apply of the headline workload ...")
+        del y
+        extras["hodge_r3_96cube_perturbed_8rhs_f32"] = apply_rates(
+            gym, op, n, nrhs, (("f64", gym.GYM_F64), ("f32", gym.GYM_F32)), 20, 2, 12)
+    del x
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+    torch.cuda.empty_cache()
 
     if not args.no_extras:
-        # the other two workloads: mixed precision at 64^3 degree 4 (Poisson) and
-        # perturbed 96^3 degree 3 (Hodge, 8 rhs)
-        log("extras: 64^3 degree-4 Poisson ...")
-        ext = {"poisson_r4_64cube": workload_rates(gym, ctx, "poisson", 64, 4, 0.0, 1, 200, 11)}
-        log("extras: perturbed 96^3 degree-3 Hodge, 8 rhs ...")
-        ext["hodge_r3_96cube_perturbed_8rhs"] = workload_rates(gym, ctx, "hodge", 96, 3, 0.15, 8, 30, 12)
-        log("extras: generalized Yee time stepping ...")
-        ext["gym_time_stepping"] = {
+        if not args.no_solves:
+            log("64^3 degree-4 mixed Poisson: applies and solves to 1e-8 ...")
+            extras["poisson_r4_64cube"] = poisson64_solves(
+                gym, ctx, 1e-8, (("f64", gym.GYM_MODE_F64, 0.0), ("ir_f32", gym.GYM_MODE_IR_F32, 1e-3),
+                                 ("ir_bf16", gym.GYM_MODE_IR_BF16, 1e-2)), 1)
+        log("32^3 degree-2 Hodge solves ...")
+        extras["hodge_r2_32cube"] = hodge32_solves(gym, ctx, 4, 1e-10)
+        if args.serve_requests > 0:
+            log("serving (batched) ...")
+            batched = serving(gym, args.serve_requests, 7, max_slots=32)
+            log("serving (one at a time) ...")
+            single = serving(gym, args.serve_requests, 7, max_slots=1)
+            log("serving (Poisson arrivals at half the batched rate) ...")
+            arrivals = serving(gym, args.serve_requests, 7, max_slots=32, qps=0.5 * batched["solves_per_s"])
+            extras["serving"] = {
+                "workload": "mixed Poisson, N ~ U{8..48}^3 hex, degree ~ U{1,2,3}, N(0,1) rhs (seeded), "
+                            "rel. residual 1e-8",
+                "batched": batched, "one_at_a_time": single, "poisson_arrivals": arrivals,
+                "speedup_batched_vs_one_at_a_time": batched["solves_per_s"] / single["solves_per_s"],
+            }
+        log("generalized Yee time stepping ...")
+        extras["gym_time_stepping"] = {
             "yee_r1_128cube_lumped": maxwell_rates(gym, ctx, 128, 1, "lumped", 2000),
             "r2_32cube_lumped": maxwell_rates(gym, ctx, 32, 2, "lumped", 2000),
             "r2_32cube_exact_q1_cg": maxwell_rates(gym, ctx, 32, 2, "exact", 20),
@@ -601,21 +669,18 @@ def main():
             "r2_32cube_spai_q1": maxwell_rates(gym, ctx, 32, 2, "spai", 500),
         }
         log("SPAI-OP ...")
-        ext["gym_spai_op"] = {"r1_24x20x16_box": spai_op_rates(gym, ctx, (24, 20, 16), (1.0, 1.3, 0.8), 1, 5e5, 500)}
+        extras["gym_spai_op"] = {"r1_24x20x16_box": spai_op_rates(gym, ctx, (24, 20, 16), (1.0, 1.3, 0.8), 1, 5e5, 500)}
         log("eigenmodes ...")
-        ext["gym_eigenmodes"] = {
+        extras["gym_eigenmodes"] = {
             "whitney_24cube_lowest5": eig_rates(gym, ctx, 24, 1, 5, 7),
-            "whitney_32cube_lowest5": eig_rates(gym, ctx, 32, 1, 5, 7),
             "yee_128cube_omega_max": cfl_rate(gym, ctx, 128),
         }
-        out["extras"] = ext
+        out["extras"] = extras
 
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline((10, 10, 10), r, args.rtol)
+        out["cpu_baseline"] = cpu_baseline(7, r, nrhs)
 
-    gym.gym_op_destroy(op)
-    gym.gym_mesh_destroy(mesh)
     gym.gym_destroy(ctx)
     print(json.dumps(out), flush=True)
 

@@ -62,7 +62,9 @@ extern "C" {
 
 #define GYM_F64   0   /* contractions and vectors in FP64                    */
 #define GYM_F32   1   /* contractions in FP32, vectors FP32                  */
-#define GYM_BF16  2   /* contractions BF16 on MFMA, FP32 accumulate/vectors  */
+#define GYM_BF16  2   /* contraction operands rounded to bf16 (round to
+                         nearest even), products accumulated in FP32 on the
+                         vector ALUs; FP32 vectors; affine meshes only      */
 
 #define GYM_MIXED_POISSON  0  /* H(div) x L2:  [M2, -D^T M3; -M3 D, 0]       */
 #define GYM_HODGE1         1  /* H1_0 x H0(curl): [-M0, G^T M1; M1 G, C^T M2 C] */
@@ -73,6 +75,15 @@ extern "C" {
 #define GYM_MODE_F64      0  /* plain FP64 Krylov                            */
 #define GYM_MODE_IR_F32   1  /* FP64 iterative refinement, FP32 inner solve   */
 #define GYM_MODE_IR_BF16  2  /* FP64 iterative refinement, BF16 contractions  */
+
+/* Preconditioners of gym_solve.  The paper preconditions only with a
+ * diagonal (section 5.1, its Sylvester PCG); the block operators take the
+ * diagonal of each block's own Gram-type operator:
+ *   Poisson: diag(M2 + D^T M3 D), diag(M3);
+ *   Hodge:   diag(M0 + G^T M1 G), diag(M1 + C^T M2 C)
+ * (gym_op_precond_diag).  NONE runs unpreconditioned MINRES. */
+#define GYM_PRECOND_JACOBI 0
+#define GYM_PRECOND_NONE   1
 
 typedef struct gym_ctx gym_ctx;
 typedef struct gym_mesh gym_mesh;
@@ -117,6 +128,30 @@ int gym_ctx_set(gym_ctx* ctx, int option, int value);
 int gym_mesh_create(gym_ctx* ctx, int dim, const int64_t nel[3],
                     const double* vertices, const double lo[3],
                     const double hi[3], gym_mesh** out);
+/* Structured mesh of the box [lo, hi] (NULL: the unit box) with seeded
+ * vertex perturbations, the perturbed-hexahedron workloads of the paper's
+ * unstructured-mesh experiments recast on a lattice (section 7; the shape
+ * of M_p on non-affine cells is section 2).  Vertex (i, j, k) moves by
+ * (2 u - 1) perturb_frac h_a along axis a, h_a = (hi_a - lo_a) / nel_a, with
+ * u = (z >> 11) 2^-53 and z the SplitMix64 word (Steele, Lea & Flood 2014)
+ *   z = mix(seed + (w + 1) 0x9E3779B97F4A7C15),  w = dim * v + a,
+ *   v = i + (nel_0 + 1) (j + (nel_1 + 1) k),
+ * the same word definition as the serving right-hand sides.  The offset is
+ * zero along a on the faces i_a = 0 and i_a = nel_a, so boundary vertices
+ * slide in their face or edge and corners stay fixed; the unperturbed
+ * coordinate is lo_a + ((hi_a - lo_a) i_a) / nel_a.  perturb_frac = 0 gives
+ * the affine box (gym_mesh_create with vertices = NULL); perturb_frac > 0 a
+ * curved mesh exactly as if its vertex array had been passed to
+ * gym_mesh_create.  Below 1/6 every cell is valid; larger values may return
+ * GYM_E_INVALID_MESH.  Errors: GYM_E_ARG (perturb_frac outside [0, 0.5)),
+ * and those of gym_mesh_create. */
+int gym_mesh_structured(gym_ctx* ctx, int dim, const int64_t nel[3],
+                        const double lo[3], const double hi[3],
+                        double perturb_frac, uint64_t seed, gym_mesh** out);
+/* Vertex coordinates of a mesh into the HOST array `vertices`
+ * ((nel_0+1)...(nel_{d-1}+1) x dim doubles, the layout of gym_mesh_create);
+ * for an affine mesh, the uniform lattice of [lo, hi]. */
+int gym_mesh_vertices(const gym_mesh* mesh, double* vertices);
 int gym_mesh_destroy(gym_mesh* mesh);
 
 /* ---- spaces (paper section 2: Lambda^p(T_h) with basis Lambda^p) ------ */
@@ -125,6 +160,29 @@ int gym_space_create(gym_ctx* ctx, const gym_mesh* mesh, int kind, int degree,
                      int bc, gym_space** out);
 int64_t gym_space_ndofs(const gym_space* space);
 int gym_space_destroy(gym_space* space);
+
+/* The canonical order of a space's vector (the only layout: every kernel
+ * reads and writes it directly, see the conventions above).  Component c
+ * occupies [offset[c], offset[c] + prod_a count[c][a]); its entry at kept
+ * lattice position (p_0, p_1, p_2) sits at
+ *   offset[c] + (p_0 - start[c][0]) + count[c][0] ((p_1 - start[c][1]) +
+ *   count[c][1] (p_2 - start[c][2])),
+ * with p_a in [start[c][a], start[c][a] + count[c][a]).  Bit a of
+ * nodal_mask[c] is set when the component is nodal along axis a (positions
+ * 0..m_a, m_a = r nel_a) and clear when it is an edge along a (cells
+ * 0..m_a-1).  Unused axes (2-D) have start 0, count 1. */
+typedef struct gym_layout {
+  int kind;             /* GYM_H1 .. GYM_L2                                */
+  int dim, degree, bc;
+  int ncomp;            /* 1 or dim                                        */
+  int nodal_mask[3];
+  int64_t m[3];         /* lattice cells per axis, r * nel                 */
+  int64_t start[3][3];  /* [component][axis]                               */
+  int64_t count[3][3];
+  int64_t offset[3];
+  int64_t ndofs;
+} gym_layout;
+int gym_space_layout(const gym_space* space, gym_layout* layout);
 
 /* ---- incidence (paper eq. discreteDeRham) ----------------------------- */
 /* y = d x (transpose = 0) or y = d^T x (transpose = 1) where d: from -> to is
@@ -185,6 +243,7 @@ typedef struct gym_solve_opts {
   int timing;         /* k > 0: bracket every k-th operator apply with HIP
                          events (1: every apply; a larger k keeps the
                          events' own cost out of the solve)                */
+  int precond;        /* GYM_PRECOND_JACOBI (default) or GYM_PRECOND_NONE  */
 } gym_solve_opts;
 
 typedef struct gym_solve_info {
@@ -198,7 +257,7 @@ typedef struct gym_solve_info {
 } gym_solve_info;
 
 /* Fill `opts` with defaults: MINRES, FP64, rtol 1e-10, maxit 20000,
- * inner_rtol 1e-4, max_outer 30, check_every 25, timing 0. */
+ * inner_rtol 1e-4, max_outer 30, check_every 25, timing 0, block Jacobi. */
 void gym_solve_opts_default(gym_solve_opts* opts);
 
 /* Solve A x = b for nrhs right-hand sides (device FP64 vectors, x is

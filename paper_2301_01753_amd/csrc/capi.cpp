@@ -2,12 +2,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
+#include "geom.hpp"
 #include "gym_internal.hpp"
 #include "kernels.hpp"
 #include "krylov.hpp"
@@ -198,7 +201,8 @@ int dalloc(void** p, size_t bytes) {
 }
 
 int check_mesh_jacobians(const gym_mesh* m) {
-  // det J > 0 at the corners and the 5-point Gauss points of every cell
+  // det J > 0 at the corners and the 5-point Gauss points of every cell;
+  // the cell layers are split over host threads
   std::vector<double> gx, gw;
   gauss_rule(5, gx, gw);
   std::vector<double> pts = {0.0};
@@ -210,10 +214,12 @@ int check_mesh_jacobians(const gym_mesh* m) {
   auto vtx = [&](int64_t i, int64_t j, int64_t k, int a) {
     return V[((k * (ny + 1) + j) * (nx + 1) + i) * d + a];
   };
-  for (int64_t k = 0; k < nz; ++k)
+  const std::vector<double> zpts = d == 3 ? pts : std::vector<double>{0.5};
+  // first bad cell (linear index), or -1
+  auto check_layer = [&](int64_t k) -> int64_t {
     for (int64_t j = 0; j < ny; ++j)
-      for (int64_t i = 0; i < nx; ++i) {
-        for (double z : (d == 3 ? pts : std::vector<double>{0.5}))
+      for (int64_t i = 0; i < nx; ++i)
+        for (double z : zpts)
           for (double y : pts)
             for (double x : pts) {
               double J[3][3] = {{0}};
@@ -234,11 +240,30 @@ int check_mesh_jacobians(const gym_mesh* m) {
                                   : J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                                         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                                         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
-              if (!(det > 0))
-                return fail(GYM_E_INVALID_MESH, "det J <= 0 in cell (" + std::to_string(i) + "," +
-                                                    std::to_string(j) + "," + std::to_string(k) + ")");
+              if (!(det > 0)) return i + nx * (j + ny * k);
             }
+    return -1;
+  };
+  const int nth = (int)std::max<int64_t>(1, std::min<int64_t>(nz, std::max(1u, std::thread::hardware_concurrency())));
+  std::atomic<int64_t> bad{-1};
+  std::atomic<int64_t> next{0};
+  auto worker = [&]() {
+    for (int64_t k; (k = next.fetch_add(1)) < nz && bad.load() < 0;) {
+      int64_t c = check_layer(k);
+      if (c >= 0) {
+        int64_t expect = -1;
+        bad.compare_exchange_strong(expect, c);
       }
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nth; ++t) th.emplace_back(worker);
+  worker();
+  for (auto& t : th) t.join();
+  const int64_t c = bad.load();
+  if (c >= 0)
+    return fail(GYM_E_INVALID_MESH, "det J <= 0 in cell (" + std::to_string(c % nx) + "," +
+                                        std::to_string((c / nx) % ny) + "," + std::to_string(c / (nx * ny)) + ")");
   return 0;
 }
 
@@ -248,7 +273,18 @@ void set_form(OpParams& p, const gym_ctx* ctx, const gym_mesh* m) {
   // small to give every CU one of them; decided at launch
   p.tile_budget = ctx->tile == 1 ? 0 : ctx->tile == 2 ? 1 : 2;
   p.curved = m->curved ? 1 : 0;
-  p.verts = m->d_vertices;
+}
+
+// Curved meshes: the Gauss-point metrics of degree r in the precision of the
+// contractions (FP32 also for the bf16-operand mode, which curved kernels
+// refuse anyway).
+int set_qdata(OpParams& p, const gym_mesh* m, int r, int prec) {
+  if (!m->curved || m->dim != 3) return 0;
+  const void* q = nullptr;
+  if (int rc = mesh_qdata(m, r, prec == GYM_F64 ? 0 : 1, &q)) return rc;
+  p.qd = q;
+  p.qfs = (long long)(r + 1) * m->nel[0] * (r + 1) * m->nel[1] * (r + 1) * m->nel[2];
+  return 0;
 }
 
 // On curved cells the metric is evaluated per Gauss point; the per-block
@@ -258,6 +294,28 @@ void curved_scales(OpParams& p) {
 }
 
 }  // namespace
+
+int mesh_qdata(const gym_mesh* m, int r, int f32, const void** out) {
+  *out = nullptr;
+  if (!m->curved || m->dim != 3 || r < 1 || r > kMaxR)
+    return fail(GYM_E_UNSUPPORTED, "Gauss-point metrics exist for curved 3-D meshes only");
+  void*& slot = m->qd[f32 ? 1 : 0][r];
+  if (!slot) {
+    const int q = r + 1;
+    const int nel[3] = {(int)m->nel[0], (int)m->nel[1], (int)m->nel[2]};
+    const long long fs = (long long)q * nel[0] * q * nel[1] * q * nel[2];
+    if (int rc = dalloc(&slot, (size_t)kQFields * fs * (f32 ? sizeof(float) : sizeof(double)))) return rc;
+    Tables1D t = make_tables(r, q);
+    if (launch_qdata(m->d_vertices, nel, q, t.gx.data(), slot, f32 ? 1 : 0, nullptr)) {
+      (void)hipFree(slot);
+      slot = nullptr;
+      return fail(GYM_E_HIP, "Gauss-point metric kernel launch failed");
+    }
+    GYM_HIP(hipDeviceSynchronize());
+  }
+  *out = slot;
+  return 0;
+}
 
 // Kernel parameters of a block operator apply (shared with the server).
 void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int& prob) {
@@ -294,6 +352,7 @@ int op_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipS
   OpParams p;
   int prob;
   build_op_params(op, x, y, p, prob);
+  if (int rc = set_qdata(p, op->mesh, op->r, prec)) return rc;
   if (prec == GYM_BF16) {
     p.bf16 = 1;  // FP32 vectors, bf16 contraction operands
     prec = GYM_F32;
@@ -339,6 +398,7 @@ int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, vo
   }
   for (int c = 0; c < sp->desc.ncomp; ++c) p.sc[c] = metric_const(sp->desc.kind, c, m);
   if (m->curved) curved_scales(p);
+  if (int rc = set_qdata(p, m, sp->desc.r, prec)) return rc;
   int prob = PROB_MASS_H1 + sp->desc.kind;
   if (prec == GYM_BF16) {
     p.bf16 = 1;
@@ -543,6 +603,7 @@ struct OpWork {
   MinresWork<float> m32;
   double *tmp = nullptr, *part = nullptr, *sums = nullptr, *r64 = nullptr, *d64 = nullptr, *scale = nullptr;
   float *r32 = nullptr, *x32 = nullptr;
+  double* ones = nullptr;  // the identity "diagonal" of GYM_PRECOND_NONE
   std::vector<void*> pool;
 };
 
@@ -744,9 +805,79 @@ int gym_mesh_create(gym_ctx* ctx, int dim, const int64_t nel[3], const double* v
   return GYM_OK;
 }
 
+int gym_mesh_structured(gym_ctx* ctx, int dim, const int64_t nel[3], const double lo[3], const double hi[3],
+                        double perturb_frac, uint64_t seed, gym_mesh** out) {
+  if (!ctx || !out || !nel) return fail(GYM_E_ARG, "NULL argument");
+  if (dim != 2 && dim != 3) return fail(GYM_E_ARG, "dim must be 2 or 3");
+  if (!(perturb_frac >= 0.0 && perturb_frac < 0.5)) return fail(GYM_E_ARG, "perturb_frac must be in [0, 0.5)");
+  if (perturb_frac == 0.0) return gym_mesh_create(ctx, dim, nel, nullptr, lo, hi, out);
+  int64_t n[3] = {1, 1, 1};
+  double L[3] = {0, 0, 0}, H[3] = {1, 1, 1};
+  int64_t nv = 1;
+  for (int a = 0; a < dim; ++a) {
+    n[a] = nel[a];
+    if (n[a] < 1 || n[a] > (1 << 20)) return fail(GYM_E_ARG, "nel out of range");
+    L[a] = lo ? lo[a] : 0.0;
+    H[a] = hi ? hi[a] : 1.0;
+    if (!(H[a] > L[a])) return fail(GYM_E_ARG, "hi must exceed lo");
+    nv *= n[a] + 1;
+  }
+  std::vector<double> v;
+  try {
+    v.resize((size_t)nv * dim);
+  } catch (const std::bad_alloc&) {
+    return fail(GYM_E_OOM, "host vertex array");
+  }
+  // SplitMix64 word w of stream `seed`, mapped to [0, 1) with 53 bits
+  auto uniform = [seed](uint64_t w) {
+    uint64_t z = seed + (w + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53;
+  };
+  for (int64_t k = 0; k < (dim == 3 ? n[2] + 1 : 1); ++k)
+    for (int64_t j = 0; j <= n[1]; ++j)
+      for (int64_t i = 0; i <= n[0]; ++i) {
+        const int64_t vid = i + (n[0] + 1) * (j + (n[1] + 1) * k);
+        const int64_t idx[3] = {i, j, k};
+        for (int a = 0; a < dim; ++a) {
+          double x = L[a] + ((H[a] - L[a]) * (double)idx[a]) / (double)n[a];
+          if (idx[a] > 0 && idx[a] < n[a]) {
+            const double h = (H[a] - L[a]) / (double)n[a];
+            x += (2.0 * uniform((uint64_t)(dim * vid + a)) - 1.0) * (perturb_frac * h);
+          }
+          v[(size_t)vid * dim + a] = x;
+        }
+      }
+  return gym_mesh_create(ctx, dim, n, v.data(), L, H, out);
+}
+
+int gym_mesh_vertices(const gym_mesh* m, double* out) {
+  if (!m || !out) return fail(GYM_E_ARG, "NULL argument");
+  const int d = m->dim;
+  if (m->curved) {
+    std::copy(m->vertices.begin(), m->vertices.end(), out);
+    return GYM_OK;
+  }
+  const int64_t nx = m->nel[0], ny = m->nel[1], nz = d == 3 ? m->nel[2] : 0;
+  for (int64_t k = 0; k <= nz; ++k)
+    for (int64_t j = 0; j <= ny; ++j)
+      for (int64_t i = 0; i <= nx; ++i) {
+        const int64_t idx[3] = {i, j, k};
+        const int64_t vid = i + (nx + 1) * (j + (ny + 1) * k);
+        for (int a = 0; a < d; ++a)
+          out[vid * d + a] = m->lo[a] + ((m->hi[a] - m->lo[a]) * (double)idx[a]) / (double)m->nel[a];
+      }
+  return GYM_OK;
+}
+
 int gym_mesh_destroy(gym_mesh* m) {
   if (!m) return GYM_OK;
   if (m->d_vertices) (void)hipFree(m->d_vertices);
+  for (auto& per_prec : m->qd)
+    for (void* q : per_prec)
+      if (q) (void)hipFree(q);
   delete m;
   return GYM_OK;
 }
@@ -765,6 +896,34 @@ int gym_space_create(gym_ctx* ctx, const gym_mesh* mesh, int kind, int degree, i
 }
 
 int64_t gym_space_ndofs(const gym_space* s) { return s ? s->desc.ndofs : -1; }
+
+int gym_space_layout(const gym_space* s, gym_layout* out) {
+  if (!s || !out) return fail(GYM_E_ARG, "NULL argument");
+  const SpaceDesc& d = s->desc;
+  gym_layout L{};
+  L.kind = d.kind;
+  L.dim = d.dim;
+  L.degree = d.r;
+  L.bc = d.bc;
+  L.ncomp = d.ncomp;
+  for (int a = 0; a < 3; ++a) L.m[a] = a < d.dim ? d.m[a] : 1;
+  for (int c = 0; c < 3; ++c) {
+    if (c < d.ncomp) {
+      L.nodal_mask[c] = d.comp[c].nodal_mask;
+      L.offset[c] = d.comp[c].offset;
+      for (int a = 0; a < 3; ++a) {
+        L.start[c][a] = a < d.dim ? d.comp[c].start[a] : 0;
+        L.count[c][a] = a < d.dim ? d.comp[c].count[a] : 1;
+      }
+    } else {
+      L.offset[c] = d.ndofs;
+      for (int a = 0; a < 3; ++a) L.count[c][a] = 0;
+    }
+  }
+  L.ndofs = d.ndofs;
+  *out = L;
+  return GYM_OK;
+}
 
 int gym_space_destroy(gym_space* s) {
   if (!s) return GYM_OK;
@@ -834,6 +993,14 @@ int gym_op_create(gym_ctx* ctx, int problem, const gym_mesh* mesh, int degree, g
   }
   op->na = op->sa.ndofs;
   op->nb = op->sb.ndofs;
+  if (mesh->curved && mesh->dim == 3) {
+    // the FP64 Gauss-point metrics now rather than inside the first apply
+    const void* q;
+    if (int rc = mesh_qdata(mesh, degree, 0, &q)) {
+      delete op;
+      return rc;
+    }
+  }
   std::vector<double> d = precond_diag_host(op);
   for (double& v : d) v = 1.0 / v;
   if (int rc = dalloc((void**)&op->d_prec, sizeof(double) * d.size())) {
@@ -964,6 +1131,7 @@ void gym_solve_opts_default(gym_solve_opts* o) {
   o->max_outer = 30;
   o->check_every = 25;
   o->timing = 0;
+  o->precond = GYM_PRECOND_JACOBI;
 }
 
 static int ensure_work(gym_op* op, int nrhs, OpWork** out) {
@@ -1006,6 +1174,55 @@ static int ensure_work32(gym_op* op, OpWork* w) {
   return 0;
 }
 
+// FP64 mode of gym_solve on the workspace w: preconditioned MINRES, then the
+// true FP64 residual; restarts on the residual while the preconditioned
+// estimate was optimistic.  Allocates no device memory.
+static int minres_f64(gym_op* op, const gym_solve_opts& opts, int nrhs, const double* b, double* x, OpWork& w,
+                      int npa, const double* dinv, ApplyTimer& timer, hipStream_t s, int* iters, int* status,
+                      std::vector<double>& rel) {
+  const long long n = w.n;
+  auto apply = [&](const double* in, double* out, const MrStep& m) {
+    if (int rc = timer.begin(s)) return rc;
+    if (int rc = launch_op_apply(op, GYM_F64, nrhs, in, out, s, &m)) return rc;
+    return timer.end(s);
+  };
+  double tol = opts.rtol;
+  int total = 0, flag = 0;
+  const double* rhs = b;
+  double* sol = x;
+  *status = GYM_OK;
+  for (int attempt = 0; attempt < 6; ++attempt) {
+    int it = 0;
+    if (int rc = run_minres<double>(apply, n, nrhs, w.nb, npa, rhs, sol, dinv, tol, opts.maxit - total,
+                                    opts.check_every, w.m64, s, &it, &flag))
+      return rc;
+    total += it;
+    if (flag < 0) {
+      *status = fail(GYM_E_BREAKDOWN, "MINRES breakdown (NaN or indefinite preconditioner)");
+      break;
+    }
+    if (sol != x) launch_add(sol, x, n * nrhs, w.nb, s);
+    if (int rc = relres_f64(op, nrhs, b, x, w.tmp, w.part, w.sums, w.nb, s, rel)) return rc;
+    double worst = *std::max_element(rel.begin(), rel.end());
+    if (worst <= opts.rtol) break;
+    if (total >= opts.maxit) {
+      *status = GYM_W_NOT_CONVERGED;
+      break;
+    }
+    // the preconditioned estimate was optimistic: restart on the true
+    // residual, A d = b - A x (zero for right-hand sides already within
+    // rtol), with the tolerance that brings the worst one below rtol
+    launch_sub(b, w.tmp, w.r64, n * nrhs, w.nb, s);
+    for (int r = 0; r < nrhs; ++r)
+      if (rel[r] <= opts.rtol) launch_fill(w.r64 + n * r, 0.0, n, w.nb, s);
+    tol = std::min(0.5, 0.3 * opts.rtol / worst);
+    rhs = w.r64;
+    sol = w.d64;
+  }
+  *iters = total;
+  return 0;
+}
+
 int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double* b, double* x,
               gym_solve_info* info, void* stream) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1016,55 +1233,31 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
   gym_solve_info inf{};
   hipStream_t s = (hipStream_t)stream;
   if (opts.method != GYM_MINRES) return fail(GYM_E_UNSUPPORTED, "block operators are indefinite: use MINRES");
+  if (opts.precond != GYM_PRECOND_JACOBI && opts.precond != GYM_PRECOND_NONE)
+    return fail(GYM_E_ARG, "unknown preconditioner");
   OpWork* w;
   if (int rc = ensure_work(op, nrhs, &w)) return rc;
   const long long n = w->n;
+  const double* dinv = op->d_prec;
+  if (opts.precond == GYM_PRECOND_NONE) {
+    if (!w->ones) {
+      void* p;
+      if (int rc = dalloc(&p, sizeof(double) * n)) return rc;
+      w->pool.push_back(p);
+      w->ones = (double*)p;
+      launch_fill(w->ones, 1.0, n, w->nb, s);
+    }
+    dinv = w->ones;
+  }
   std::vector<double> rel;
   int status = GYM_OK;
   ApplyTimer timer;
   timer.period = opts.timing > 0 ? opts.timing : 0;
   if (opts.mode == GYM_MODE_F64) {
-    auto apply = [&](const double* in, double* out, const MrStep& m) {
-      if (int rc = timer.begin(s)) return rc;
-      if (int rc = launch_op_apply(op, GYM_F64, nrhs, in, out, s, &m)) return rc;
-      return timer.end(s);
-    };
     int npa = 0;
     if (int rc = op_workgroups(op, GYM_F64, nrhs, &npa)) return rc;
     if (int rc = ensure_partials(w->pool, w->m64, npa, w->nb, nrhs)) return rc;
-    double tol = opts.rtol;
-    int total = 0, flag = 0;
-    const double* rhs = b;
-    double* sol = x;
-    for (int attempt = 0; attempt < 6; ++attempt) {
-      int it = 0;
-      if (int rc = run_minres<double>(apply, n, nrhs, w->nb, npa, rhs, sol, op->d_prec, tol, opts.maxit - total,
-                                      opts.check_every, w->m64, s, &it, &flag))
-        return rc;
-      total += it;
-      if (flag < 0) {
-        status = fail(GYM_E_BREAKDOWN, "MINRES breakdown (NaN or indefinite preconditioner)");
-        break;
-      }
-      if (sol != x) launch_add(sol, x, n * nrhs, w->nb, s);
-      if (int rc = relres_f64(op, nrhs, b, x, w->tmp, w->part, w->sums, w->nb, s, rel)) return rc;
-      double worst = *std::max_element(rel.begin(), rel.end());
-      if (worst <= opts.rtol) break;
-      if (total >= opts.maxit) {
-        status = GYM_W_NOT_CONVERGED;
-        break;
-      }
-      // the preconditioned estimate was optimistic: restart on the true
-      // residual, A d = b - A x (zero for right-hand sides already within
-      // rtol), with the tolerance that brings the worst one below rtol
-      launch_sub(b, w->tmp, w->r64, n * nrhs, w->nb, s);
-      for (int r = 0; r < nrhs; ++r)
-        if (rel[r] <= opts.rtol) GYM_HIP(hipMemsetAsync(w->r64 + n * r, 0, sizeof(double) * n, s));
-      tol = std::min(0.5, 0.3 * opts.rtol / worst);
-      rhs = w->r64;
-      sol = w->d64;
-    }
-    inf.iters = total;
+    if (int rc = minres_f64(op, opts, nrhs, b, x, *w, npa, dinv, timer, s, &inf.iters, &status, rel)) return rc;
   } else if (opts.mode == GYM_MODE_IR_F32 || opts.mode == GYM_MODE_IR_BF16) {
     if (int rc = ensure_work32(op, w)) return rc;
     const int prec = opts.mode == GYM_MODE_IR_BF16 ? GYM_BF16 : GYM_F32;
@@ -1097,7 +1290,7 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
       GYM_HIP(hipMemcpyAsync(w->scale, sc.data(), sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s));
       launch_to_f32_scaled(w->r64, w->r32, n, nrhs, w->nb, w->scale, s);
       int it = 0, flag = 0;
-      if (int rc = run_minres<float>(apply32, n, nrhs, w->nb, npa, w->r32, w->x32, op->d_prec, opts.inner_rtol,
+      if (int rc = run_minres<float>(apply32, n, nrhs, w->nb, npa, w->r32, w->x32, dinv, opts.inner_rtol,
                                      opts.maxit, opts.check_every, w->m32, s, &it, &flag))
         return rc;
       total += it;

@@ -95,7 +95,16 @@ struct gym_mesh {
   bool curved = false;              // vertex array given
   double* d_vertices = nullptr;     // device copy, (N+1)^d x d
   std::vector<double> vertices;     // host copy
+  // curved: Gauss-point metrics per degree r (q = r + 1), FP64 [0] and FP32
+  // [1], built on first use (geom.hpp) and kept until the mesh is destroyed
+  mutable void* qd[2][gym::kMaxR + 1] = {};
 };
+
+namespace gym {
+// The Gauss-point metrics of a curved mesh for degree r (f32: FP32 copy),
+// allocated and filled on first use (synchronously).
+int mesh_qdata(const gym_mesh* m, int r, int f32, const void** out);
+}  // namespace gym
 
 struct gym_space {
   gym_ctx* ctx = nullptr;

@@ -36,8 +36,9 @@ struct OpParams {
   int tiles_x, tiles_y, chunk, nchunks;
   int kron;         // 1: Kronecker (1-D element matrix) form of the masses
   int bf16;         // 1: contraction operands rounded to bf16 (FP32 accumulate)
-  int curved;       // 1: per-Gauss-point metric from the vertex array
-  const double* verts;  // (nel+1)^3 x 3 vertex coordinates (curved only)
+  int curved;       // 1: per-Gauss-point metric (curved cells)
+  const void* qd;   // curved: the Gauss-point metrics (geom.hpp), FP64 or FP32 as the contractions
+  long long qfs;    // values per metric field, (q nel_0)(q nel_1)(q nel_2)
   const int* gate;      // batched launches: skip when *gate != 0 (a solve's done flag)
   int tile_budget;  // 0: one 160 KB workgroup per CU, 1: 40 KB workgroups, 2: automatic
   double sc[8];     // constant pointwise metric factors (affine meshes)

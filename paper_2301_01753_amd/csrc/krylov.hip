@@ -423,6 +423,10 @@ __global__ void __launch_bounds__(kBT) add_kernel(const double* d, double* x, lo
     x[i] += d[i];
 }
 
+__global__ void __launch_bounds__(kBT) fill_kernel(double* y, double v, long long n) {
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) y[i] = v;
+}
+
 // y32 = scale[rhs] * a64 (rhs-wise scaling)
 __global__ void __launch_bounds__(kBT) to_f32_scaled(const double* a, float* y, long long n, const double* scale) {
   const int rhs = blockIdx.y;
@@ -504,6 +508,10 @@ void launch_axpy_diag(double* y, double beta, double alpha, const double* d, con
 
 void launch_add(const double* d, double* x, long long n, int nb, hipStream_t s) {
   GYM_LAUNCH(add_kernel, dim3(nb), s, d, x, n);
+}
+
+void launch_fill(double* y, double v, long long n, int nb, hipStream_t s) {
+  GYM_LAUNCH(fill_kernel, dim3(nb), s, y, v, n);
 }
 
 void launch_to_f32_scaled(const double* a, float* y, long long n, int nrhs, int nb, const double* scale,

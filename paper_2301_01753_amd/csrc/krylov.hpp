@@ -85,6 +85,8 @@ void launch_norm2(const double* a, const double* b, long long n, int nrhs, int n
                   double* out, hipStream_t s);
 void launch_sub(const double* a, const double* b, double* y, long long n, int nb, hipStream_t s);
 void launch_add(const double* d, double* x, long long n, int nb, hipStream_t s);
+// y = v (a fill kernel, not a memset, so that it may sit in a captured graph)
+void launch_fill(double* y, double v, long long n, int nb, hipStream_t s);
 // y = beta y + alpha (d .* x); d = NULL: ones
 void launch_axpy_diag(double* y, double beta, double alpha, const double* d, const double* x, long long n, int nb,
                       hipStream_t s);

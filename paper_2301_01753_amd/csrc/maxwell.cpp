@@ -120,6 +120,11 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
     return fail(GYM_E_ARG, "bad time-stepping options");
   if (mesh->curved && (o.q1 != GYM_Q1_EXACT || o.m2 == GYM_M2_LUMPED))
     return fail(GYM_E_UNSUPPORTED, "lumped masses and the SPAI need an affine mesh");
+  if (mesh->curved) {
+    // the Gauss-point metrics of the mass applies, before the first step
+    const void* qd;
+    if (int rc = mesh_qdata(mesh, degree, 0, &qd)) return rc;
+  }
   gym_maxwell* mx = new gym_maxwell;
   mx->ctx = ctx;
   mx->mesh = mesh;
@@ -510,6 +515,9 @@ int gym_maxwell_spai_op(gym_maxwell* mx, int nprobe, const double* probes, doubl
   spai_op_free(&mx->spai_op);
   mx->spai_op = Q;
   mx->o.q1 = GYM_Q1_SPAI_OP;
+  // the one-kernel stepping exists for lumped Q1 only: from now on the steps
+  // apply SPAI-OP Q1 (and the lumped M2~ still, if that was chosen)
+  mx->fused = false;
   return rc;
 }
 

@@ -21,6 +21,7 @@
 
 #include <type_traits>
 
+#include "curved.hpp"
 #include "gym_internal.hpp"
 #include "kernels.hpp"
 #include "tile.hpp"
@@ -125,8 +126,16 @@ __device__ __forceinline__ void static_for(Fn&& fn) {
 }
 
 // ---- LDS layout ------------------------------------------------------------
+// Per field: the input and output lattice closures of the layer, the carried
+// top plane (nodal-in-z fields), then the work arrays of the mass form:
+//   affine forms: A, B (and T2 for the Kronecker form), three lattice
+//     temporaries L for the incidence stages;
+//   curved form: the three lattice temporaries L, then per vector component
+//     an x-contracted array WA ([QX][ny][nz]) and an x-y-contracted one WB
+//     ([QX][QY][nz]).
 template <class C, class F, int FORM>
 struct Layout {
+  static constexpr bool CURVED = FORM == FORM_CURVED;
   static constexpr int lat(int f) { return C::lat(F::tm[f]); }
   static constexpr bool carries(int f) { return C::DIM == 3 && (F::tm[f] & 4); }
   static constexpr int in_off(int f) {
@@ -145,17 +154,17 @@ struct Layout {
     for (int t = 0; t < 8; ++t) m = C::lat(t) > m ? C::lat(t) : m;
     return m;
   }
-  static constexpr int nq() { return C::QX * C::QY * C::QZ; }
   static constexpr int A_off() { return car_off(F::NF); }
-  static constexpr int B_off() { return A_off() + (is_kron(FORM) ? maxlat() : C::tmpA()); }
+  static constexpr int B_off() { return A_off() + (CURVED ? 0 : is_kron(FORM) ? maxlat() : C::tmpA()); }
   // Kronecker form: a third lattice temporary (one per vector component)
-  static constexpr int T2_off() { return B_off() + (is_kron(FORM) ? maxlat() : C::tmpB()); }
+  static constexpr int T2_off() { return B_off() + (CURVED ? 0 : is_kron(FORM) ? maxlat() : C::tmpB()); }
   static constexpr int L_off(int k) { return T2_off() + (is_kron(FORM) ? maxlat() : 0) + k * maxlat(); }
-  // curved form: three Gauss-point arrays and the layer's vertex block
-  static constexpr int Q_off(int k) { return L_off(3) + k * nq(); }
-  static constexpr int nvert() { return 2 * (C::EX + 1) * (C::EY + 1) * 3; }
-  static constexpr int V_off() { return Q_off(3); }
-  static constexpr int total() { return FORM == FORM_CURVED ? V_off() + nvert() : L_off(3); }
+  // curved form: contraction work arrays per component
+  static constexpr int wa() { return C::QX * (C::R * C::EY + 1) * C::nz(7); }
+  static constexpr int wb() { return C::QX * C::QY * C::nz(7); }
+  static constexpr int WA_off(int k) { return L_off(3) + k * wa(); }
+  static constexpr int WB_off(int k) { return WA_off(3) + k * wb(); }
+  static constexpr int total() { return CURVED ? WB_off(3) : L_off(3); }
 };
 
 // extent of the lattice of mask TM along axis a
@@ -164,127 +173,63 @@ __device__ __forceinline__ int ext(int a) {
   return a == 0 ? C::nx(TM) : (a == 1 ? C::ny(TM) : C::nz(TM));
 }
 
-// ---- curved cells: Jacobian of the multilinear map at a Gauss point ----------
-// V: the layer's vertex block [2][EY+1][EX+1][3] (local element e spans
-// vertices e, e+1).  J[i][a] = dx_i / dxi_a.
-template <class C, typename TC>
-__device__ __forceinline__ void jac_at(const TC* V, int ex, int ey, TC xi, TC eta, TC zeta, TC J[3][3]) {
-  constexpr int SX = 3, SY = 3 * (C::EX + 1), SZ = 3 * (C::EX + 1) * (C::EY + 1);
-  const TC* v = V + ex * SX + ey * SY;
-  const TC wx[2] = {1 - xi, xi}, wy[2] = {1 - eta, eta}, wz[2] = {1 - zeta, zeta};
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    TC dx = 0, dy = 0, dz = 0;
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        // derivative along x: (X(1,b,c) - X(0,b,c)) weighted by the other two
-        dx += wy[b] * wz[c] * (v[SX + b * SY + c * SZ + i] - v[b * SY + c * SZ + i]);
-        dy += wx[b] * wz[c] * (v[b * SX + SY + c * SZ + i] - v[b * SX + c * SZ + i]);
-        dz += wx[b] * wy[c] * (v[b * SX + c * SY + SZ + i] - v[b * SX + c * SY + i]);
-      }
-    J[i][0] = dx;
-    J[i][1] = dy;
-    J[i][2] = dz;
-  }
-}
-
-// Pointwise metric of the mass of `KIND` applied in place to the Gauss-point
-// values (vector kinds: Q0..Q2 are the three reference components).  The
-// Gauss weights are already in the transposed tables.
-//   H1: det J   L2: 1/det J   HCURL: det J J^-1 J^-T = adj adj^T / det
-//   HDIV: J^T J / det J
-template <class C, int KIND, typename TC>
-__device__ __forceinline__ void pointwise_curved(TC* Q0, TC* Q1, TC* Q2, const TC* V, TC sign,
-                                                 const ElemRange& er) {
-  const TabSet<TC>& T = tabs<TC>(C::R);
-  constexpr int N = C::QX * C::QY * C::QZ;
-  for (int idx = threadIdx.x; idx < N; idx += C::NT) {
-    int qx = idx % C::QX, r = idx / C::QX;
-    int qy = r % C::QY, qz = r / C::QY;
-    int ex = qx / C::Q, ey = qy / C::Q;
-    if (ex < er.xlo || ex >= er.xhi || ey < er.ylo || ey >= er.yhi) {
-      Q0[idx] = 0;
-      if constexpr (KIND == GYM_HCURL || KIND == GYM_HDIV) {
-        Q1[idx] = 0;
-        Q2[idx] = 0;
-      }
-      continue;
-    }
-    TC J[3][3];
-    jac_at<C, TC>(V, ex, ey, T.gx[qx - ex * C::Q], T.gx[qy - ey * C::Q], T.gx[qz], J);
-    // cofactors: adj[a][i] = cof(J)[i][a], det = sum_i J[i][0] cof[i][0]
-    TC adj[3][3];
-    adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-    adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-    adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-    adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-    adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-    adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-    adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-    adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-    adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-    const TC det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-    if constexpr (KIND == GYM_H1) {
-      Q0[idx] *= sign * det;
-    } else if constexpr (KIND == GYM_L2) {
-      Q0[idx] *= sign / det;
-    } else {
-      TC G[3][3];
-      const TC s = sign / det;
-#pragma unroll
-      for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-          TC acc = 0;
-#pragma unroll
-          for (int i = 0; i < 3; ++i) acc += KIND == GYM_HCURL ? adj[a][i] * adj[b][i] : J[i][a] * J[i][b];
-          G[a][b] = acc * s;
-        }
-      const TC u0 = Q0[idx], u1 = Q1[idx], u2 = Q2[idx];
-      Q0[idx] = G[0][0] * u0 + G[0][1] * u1 + G[0][2] * u2;
-      Q1[idx] = G[1][0] * u0 + G[1][1] * u1 + G[1][2] * u2;
-      Q2[idx] = G[2][0] * u0 + G[2][1] * u1 + G[2][2] * u2;
-    }
-  }
-}
-
-template <class C, int TM, typename TC>
-__device__ __forceinline__ void to_gauss(const TC* in, TC* Q, TC* A, TC* B, const ElemRange& er) {
-  fwd_x<C, TM>(in, A, er);
-  __syncthreads();
-  fwd_y<C, TM>(A, B, er);
-  __syncthreads();
-  fwd_z<C, TM>(B, Q);
-  __syncthreads();
-}
-
-template <class C, int TM, bool ADD, typename TC>
-__device__ __forceinline__ void from_gauss(const TC* Q, TC* out, TC* A, TC* B) {
-  bwd_z<C, TM>(Q, B);
-  __syncthreads();
-  bwd_y<C, TM>(B, A);
-  __syncthreads();
-  bwd_x<C, TM, ADD>(A, out, TC(1));
-  __syncthreads();
-}
-
 // Work buffers of one layer.
 template <typename TC>
 struct Work {
-  TC *A, *B, *T2, *L[3], *Q[3], *V;
+  TC *A, *B, *T2, *L[3];
+  TC *WA[3], *WB[3];  // curved form
+  QGeom<TC> g;        // curved form: the layer's Gauss-point metrics
   ElemRange er;
 };
+
+// ---- curved cells (curved.hpp stages) -----------------------------------------
+template <class C, int TM, int KIND, bool ADD, typename TC>
+__device__ __forceinline__ void cmass_scalar(const TC* in, TC* out, TC sign, const Work<TC>& w) {
+  constexpr int NY = C::ny(TM), NZ = C::nz(TM);
+  for (int l = threadIdx.x; l < C::EX * NY * NZ; l += C::NT) cfwd_x<C, TM>(in, w.WA[0], l, w.er);
+  __syncthreads();
+  for (int l = threadIdx.x; l < C::QX * C::EY * NZ; l += C::NT) cfwd_y<C, TM>(w.WA[0], w.WB[0], l, w.er);
+  __syncthreads();
+  for (int p = threadIdx.x; p < C::QX * C::QY; p += C::NT) cz_scalar<C, TM, KIND>(w.WB[0], p, w.er, w.g, sign);
+  __syncthreads();
+  for (int l = threadIdx.x; l < C::QX * C::EY * NZ; l += C::NT) cbwd_y<C, TM>(w.WB[0], w.WA[0], l);
+  __syncthreads();
+  for (int l = threadIdx.x; l < C::EX * NY * NZ; l += C::NT) cbwd_x<C, TM, ADD>(w.WA[0], out, l);
+  __syncthreads();
+}
+
+// in == out is allowed: the inputs are consumed by the first stage.
+template <class C, int KIND, int T0, int T1, int T2, bool ADD, typename TC>
+__device__ __forceinline__ void cmass_vector(TC* const in[3], TC* const out[3], TC sign, const Work<TC>& w) {
+  constexpr int NT = C::NT;
+  constexpr int X0 = C::EX * C::ny(T0) * C::nz(T0), X1 = C::EX * C::ny(T1) * C::nz(T1),
+                X2 = C::EX * C::ny(T2) * C::nz(T2);
+  constexpr int Y0 = C::QX * C::EY * C::nz(T0), Y1 = C::QX * C::EY * C::nz(T1), Y2 = C::QX * C::EY * C::nz(T2);
+  stage3<NT, X0, X1, X2>([&](int l) { cfwd_x<C, T0>(in[0], w.WA[0], l, w.er); },
+                         [&](int l) { cfwd_x<C, T1>(in[1], w.WA[1], l, w.er); },
+                         [&](int l) { cfwd_x<C, T2>(in[2], w.WA[2], l, w.er); });
+  __syncthreads();
+  stage3<NT, Y0, Y1, Y2>([&](int l) { cfwd_y<C, T0>(w.WA[0], w.WB[0], l, w.er); },
+                         [&](int l) { cfwd_y<C, T1>(w.WA[1], w.WB[1], l, w.er); },
+                         [&](int l) { cfwd_y<C, T2>(w.WA[2], w.WB[2], l, w.er); });
+  __syncthreads();
+  for (int p = threadIdx.x; p < C::QX * C::QY; p += NT) cz_vector<C, KIND, T0, T1, T2>(w.WB, p, w.er, w.g, sign);
+  __syncthreads();
+  stage3<NT, Y0, Y1, Y2>([&](int l) { cbwd_y<C, T0>(w.WB[0], w.WA[0], l); },
+                         [&](int l) { cbwd_y<C, T1>(w.WB[1], w.WA[1], l); },
+                         [&](int l) { cbwd_y<C, T2>(w.WB[2], w.WA[2], l); });
+  __syncthreads();
+  stage3<NT, X0, X1, X2>([&](int l) { cbwd_x<C, T0, ADD>(w.WA[0], out[0], l); },
+                         [&](int l) { cbwd_x<C, T1, ADD>(w.WA[1], out[1], l); },
+                         [&](int l) { cbwd_x<C, T2, ADD>(w.WA[2], out[2], l); });
+  __syncthreads();
+}
 
 // Scalar mass apply of kind KIND on a field of mask TM.
 template <class C, int TM, int KIND, bool ADD, int FORM, typename TC>
 __device__ __forceinline__ void smass(const TC* in, TC* out, TC scale, const Work<TC>& w) {
   if constexpr (FORM == FORM_CURVED) {
-    to_gauss<C, TM>(in, w.Q[0], w.A, w.B, w.er);
-    pointwise_curved<C, KIND>(w.Q[0], w.Q[1], w.Q[2], w.V, scale, w.er);
-    __syncthreads();
-    from_gauss<C, TM, ADD>(w.Q[0], out, w.A, w.B);
+    cmass_scalar<C, TM, KIND, ADD>(in, out, scale, w);
   } else if constexpr (is_kron(FORM)) {
     TC* const i3[3] = {const_cast<TC*>(in), nullptr, nullptr};
     TC* const o3[3] = {out, nullptr, nullptr};
@@ -303,14 +248,7 @@ __device__ __forceinline__ void smass(const TC* in, TC* out, TC scale, const Wor
 template <class C, int KIND, int T0, int T1, int T2, bool ADD, int FORM, typename TC>
 __device__ __forceinline__ void vmass(TC* const in[3], TC* const out[3], const TC sc[3], const Work<TC>& w) {
   if constexpr (FORM == FORM_CURVED) {
-    to_gauss<C, T0>(in[0], w.Q[0], w.A, w.B, w.er);
-    to_gauss<C, T1>(in[1], w.Q[1], w.A, w.B, w.er);
-    to_gauss<C, T2>(in[2], w.Q[2], w.A, w.B, w.er);
-    pointwise_curved<C, KIND>(w.Q[0], w.Q[1], w.Q[2], w.V, sc[0], w.er);
-    __syncthreads();
-    from_gauss<C, T0, ADD>(w.Q[0], out[0], w.A, w.B);
-    from_gauss<C, T1, ADD>(w.Q[1], out[1], w.A, w.B);
-    from_gauss<C, T2, ADD>(w.Q[2], out[2], w.A, w.B);
+    cmass_vector<C, KIND, T0, T1, T2, ADD>(in, out, sc[0], w);
   } else if constexpr (is_kron(FORM)) {
     TC* const t3[3] = {w.A, w.B, w.T2};
     kron_cols<C, 3, T0, T1, T2, ADD, FORM == FORM_KRON_BF16>(in, out, sc, t3, w.er);
@@ -357,9 +295,10 @@ constexpr int max_per_thread() {
 }
 
 // ---- the kernel body -------------------------------------------------------
-// (bx, by, bz) = (tile, z-chunk, right-hand side) of this workgroup.
+// (bx, by, bz) = (tile, z-chunk, right-hand side) of this workgroup.  remap:
+// spread the tiles over the XCDs in contiguous runs (the launch did not).
 template <class C, int PROB, int FORM, typename TV, typename TC, bool MR>
-__device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int bz, TC* smem) {
+__device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int bz, TC* smem, bool remap = true) {
   using F = Fields<PROB, C::DIM>;
   using L = Layout<C, F, FORM>;
   constexpr int R = C::R;
@@ -369,7 +308,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
   // the 8 XCDs; remap so that each XCD receives a contiguous run of tiles.
   const int nt = p.tiles_x * p.tiles_y;
   int b = bx;
-  if (nt % 8 == 0) b = (b % 8) * (nt / 8) + b / 8;
+  if (remap && nt % 8 == 0) b = (b % 8) * (nt / 8) + b / 8;
   const int tx = b % p.tiles_x, ty = b / p.tiles_x;
   const int X0 = tx * C::BX, Y0 = ty * C::BY;
   const int rhs = bz;
@@ -390,11 +329,20 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
   w.T2 = smem + L::T2_off();
   for (int k = 0; k < 3; ++k) w.L[k] = smem + L::L_off(k);
   if constexpr (FORM == FORM_CURVED) {
-    for (int k = 0; k < 3; ++k) w.Q[k] = smem + L::Q_off(k);
-    w.V = smem + L::V_off();
+    for (int k = 0; k < 3; ++k) {
+      w.WA[k] = smem + L::WA_off(k);
+      w.WB[k] = smem + L::WB_off(k);
+    }
+    w.g.qd = static_cast<const TC*>(p.qd);
+    w.g.fs = p.qfs;
+    w.g.GX = C::Q * p.nel[0];
+    w.g.GY = C::Q * p.nel[1];
+    w.g.gx0 = C::Q * (X0 - 1);
+    w.g.gy0 = C::Q * (Y0 - 1);
+    w.g.gz0 = 0;
   } else {
-    for (int k = 0; k < 3; ++k) w.Q[k] = nullptr;
-    w.V = nullptr;
+    for (int k = 0; k < 3; ++k) w.WA[k] = w.WB[k] = nullptr;
+    w.g = QGeom<TC>{};
   }
   // local element e <-> global X0 - 1 + e
   w.er = ElemRange{max(0, 1 - X0), min(C::EX, p.nel[0] - X0 + 1), max(0, 1 - Y0), min(C::EY, p.nel[1] - Y0 + 1)};
@@ -491,20 +439,7 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
         }
       }
     });
-    if constexpr (FORM == FORM_CURVED) {
-      // vertices of the layer, clamped into the mesh (cells outside it are
-      // masked, their clamped geometry only has to stay finite)
-      constexpr int NVX = C::EX + 1, NVY = C::EY + 1;
-      for (int i = threadIdx.x; i < 2 * NVX * NVY * 3; i += C::NT) {
-        int a = i % 3, r = i / 3;
-        int lx = r % NVX, r2 = r / NVX;
-        int ly = r2 % NVY, lz = r2 / NVY;
-        int vx = min(max(X0 - 1 + lx, 0), p.nel[0]);
-        int vy = min(max(Y0 - 1 + ly, 0), p.nel[1]);
-        int vz = min(ez + lz, p.nel[2]);
-        w.V[i] = static_cast<TC>(p.verts[(((long long)vz * (p.nel[1] + 1) + vy) * (p.nel[0] + 1) + vx) * 3 + a]);
-      }
-    }
+    if constexpr (FORM == FORM_CURVED) w.g.gz0 = C::Q * ez;
     __syncthreads();
     if constexpr (PREFETCH) {
       if (ez + 1 < zend) prefetch(ez + 1);
@@ -736,6 +671,23 @@ __global__ void __launch_bounds__(C::NT) op_kernel(const OpParams p) {
   op_body<C, PROB, FORM, TV, TC, MR>(p, blockIdx.x, blockIdx.y, blockIdx.z, smem);
 }
 
+// Several right-hand sides sharing per-point data (the curved form's
+// Gauss-point metrics): a 1-D grid of tiles x chunks x nrhs workgroups,
+// numbered so that the nrhs workgroups of one tile and chunk run on the same
+// XCD (the hardware deals block b to XCD b mod 8) and are dispatched one after
+// another.  They then read the same metric values within a short time, and
+// all but the first find them in that XCD's L2.  The host checks that the
+// workgroup count is a multiple of 8.
+template <class C, int PROB, int FORM, typename TV, typename TC, bool MR>
+__global__ void __launch_bounds__(C::NT) op_kernel_rhs(const OpParams p, int nrhs) {
+  __shared__ __align__(16) TC smem[Layout<C, Fields<PROB, C::DIM>, FORM>::total()];
+  const int nt = p.tiles_x * p.tiles_y;
+  const int per_xcd = nt * p.nchunks * nrhs / 8;
+  const int slot = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);  // (tile, chunk, rhs), rhs fastest
+  const int rhs = slot % nrhs, tc = slot / nrhs;
+  op_body<C, PROB, FORM, TV, TC, MR>(p, tc % nt, tc / nt, rhs, smem, false);
+}
+
 // Ragged batch: one launch over the workgroups of several operators of the
 // same kind and degree (different meshes and vectors).  bstart holds the
 // prefix sums of the per-request workgroup counts (nreq + 1 entries).
@@ -882,8 +834,14 @@ int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
   else op_tiling(p, B, DIM, nrhs, ncu, kTileSmall);
   if (p0.wg_out) *p0.wg_out = p.tiles_x * p.tiles_y * p.nchunks;
   if (p0.dry) return 0;
-  dim3 grid(p.tiles_x * p.tiles_y, p.nchunks, nrhs);
-  hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC, MR>), grid, dim3(C::NT), 0, stream, p);
+  const long long nwg = (long long)p.tiles_x * p.tiles_y * p.nchunks * nrhs;
+  if (FORM == FORM_CURVED && nrhs > 1 && nwg % 8 == 0 && nwg < (1LL << 31)) {
+    hipLaunchKernelGGL((op_kernel_rhs<C, PROB, FORM, TV, TC, MR>), dim3((unsigned)nwg), dim3(C::NT), 0, stream, p,
+                       nrhs);
+  } else {
+    dim3 grid(p.tiles_x * p.tiles_y, p.nchunks, nrhs);
+    hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC, MR>), grid, dim3(C::NT), 0, stream, p);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

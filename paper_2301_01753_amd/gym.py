@@ -29,6 +29,7 @@ GYM_F64, GYM_F32, GYM_BF16 = 0, 1, 2
 GYM_MIXED_POISSON, GYM_HODGE1 = 0, 1
 GYM_MINRES, GYM_CG = 0, 1
 GYM_MODE_F64, GYM_MODE_IR_F32, GYM_MODE_IR_BF16 = 0, 1, 2
+GYM_PRECOND_JACOBI, GYM_PRECOND_NONE = 0, 1
 GYM_Q1_EXACT, GYM_Q1_LUMPED, GYM_Q1_SPAI_DIAG, GYM_Q1_SPAI, GYM_Q1_SPAI_OP = 0, 1, 2, 3, 4
 GYM_M2_EXACT, GYM_M2_LUMPED = 0, 1
 
@@ -44,7 +45,14 @@ class GymError(RuntimeError):
 class SolveOpts(ctypes.Structure):
     _fields_ = [("method", ctypes.c_int), ("mode", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("inner_rtol", ctypes.c_double), ("max_outer", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("timing", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("timing", ctypes.c_int), ("precond", ctypes.c_int)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("dim", ctypes.c_int), ("degree", ctypes.c_int), ("bc", ctypes.c_int),
+                ("ncomp", ctypes.c_int), ("nodal_mask", ctypes.c_int * 3), ("m", ctypes.c_int64 * 3),
+                ("start", (ctypes.c_int64 * 3) * 3), ("count", (ctypes.c_int64 * 3) * 3),
+                ("offset", ctypes.c_int64 * 3), ("ndofs", ctypes.c_int64)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -94,10 +102,14 @@ SIGNATURES = {
     "gym_last_error": (ctypes.c_char_p, []),
     "gym_ctx_set": (_I, [_P, _I, _I]),
     "gym_mesh_create": (_I, [_P, _I, ctypes.POINTER(_I64), _P, _P, _P, ctypes.POINTER(_P)]),
+    "gym_mesh_structured": (_I, [_P, _I, ctypes.POINTER(_I64), _P, _P, ctypes.c_double, ctypes.c_uint64,
+                                 ctypes.POINTER(_P)]),
+    "gym_mesh_vertices": (_I, [_P, _P]),
     "gym_mesh_destroy": (_I, [_P]),
     "gym_space_create": (_I, [_P, _P, _I, _I, _I, ctypes.POINTER(_P)]),
     "gym_space_ndofs": (_I64, [_P]),
     "gym_space_destroy": (_I, [_P]),
+    "gym_space_layout": (_I, [_P, ctypes.POINTER(Layout)]),
     "gym_d_apply": (_I, [_P, _P, _I, _P, _P, _P]),
     "gym_mass_apply": (_I, [_P, _I, _I, _P, _P, _P]),
     "gym_op_create": (_I, [_P, _I, _P, _I, ctypes.POINTER(_P)]),
@@ -213,6 +225,30 @@ def gym_mesh_create(ctx, dim, nel, vertices=None, lo=None, hi=None):
     return h
 
 
+def gym_mesh_structured(ctx, dim, nel, perturb_frac=0.0, seed=0, lo=None, hi=None):
+    """Box mesh with the library's seeded vertex perturbation (gym.h)."""
+    def pad3(v, fill):
+        v = list(v)[:3]
+        return v + [fill] * (3 - len(v))
+    n = (_I64 * 3)(*pad3(nel, 1))
+    lo_a = (ctypes.c_double * 3)(*pad3(lo if lo is not None else [0.0] * 3, 0.0))
+    hi_a = (ctypes.c_double * 3)(*pad3(hi if hi is not None else [1.0] * 3, 1.0))
+    h = _P()
+    _check(lib().gym_mesh_structured(ctx, dim, n, ctypes.cast(lo_a, _P), ctypes.cast(hi_a, _P), float(perturb_frac),
+                                     ctypes.c_uint64(seed), ctypes.byref(h)))
+    return h
+
+
+def gym_mesh_vertices(mesh, nel):
+    """Vertex coordinates as an array (N_1+1, ..., N_d+1, d), axis 0 first
+    (the layout synth.uniform_vertices returns)."""
+    dim = len(nel)
+    shape = [int(n) + 1 for n in nel][::-1] + [dim]
+    v = np.empty(shape, dtype=np.float64)
+    _check(lib().gym_mesh_vertices(mesh, v.ctypes.data_as(_P)))
+    return np.ascontiguousarray(np.transpose(v, list(range(dim))[::-1] + [dim]))
+
+
 def gym_mesh_destroy(mesh):
     _check(lib().gym_mesh_destroy(mesh))
 
@@ -227,6 +263,12 @@ def gym_space_create(ctx, mesh, kind, degree, bc=GYM_BC_NATURAL):
 
 def gym_space_ndofs(space):
     return int(lib().gym_space_ndofs(space))
+
+
+def gym_space_layout(space):
+    L = Layout()
+    _check(lib().gym_space_layout(space, ctypes.byref(L)))
+    return L
 
 
 def gym_space_destroy(space):

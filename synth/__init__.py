@@ -10,6 +10,10 @@ Recipes (stated in DESIGN.md as well):
     coordinate from numpy's PCG64 (``default_rng(seed)``); components normal
     to a boundary face are zeroed, so boundary-face vertices slide in their
     face, boundary-edge vertices along their edge, and corners stay fixed;
+  * counter-based perturbed meshes (``perturbed_vertices_counter``): the
+    same boundary rule with offsets (2u - 1)*frac*h, u = (z >> 11) 2^-53 from
+    SplitMix64 word z of index dim*v + a (v the vertex's lexicographic index,
+    axis 0 fastest), the definition the C library's mesh constructor uses;
   * Fourier coefficients and random right-hand sides: i.i.d. N(0, 1) from
     ``default_rng(seed)``.
 """
@@ -88,3 +92,36 @@ def counter_normal(seed, n, first=0):
     u2 = (z2 >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
     out[first:] = np.sqrt(-2.0 * np.log(1.0 - u1)) * np.cos(2.0 * np.pi * u2)
     return out
+
+
+def perturbed_vertices_counter(nel, frac, seed, lo=None, hi=None):
+    """Uniform vertices plus counter-based offsets: vertex v (lexicographic,
+    axis 0 fastest), coordinate a, moves by (2u - 1) * (frac * h_a) with u
+    from SplitMix64 word dim*v + a of stream `seed`; no offset along a on the
+    faces normal to a."""
+    v = uniform_vertices(nel, lo, hi)
+    nel = tuple(int(n) for n in nel)
+    dim = len(nel)
+    lo = np.zeros(dim) if lo is None else np.asarray(lo, float)
+    hi = np.ones(dim) if hi is None else np.asarray(hi, float)
+    # vertex index with axis 0 fastest, in the (N_1+1, ..., N_d+1) array order
+    vid = np.zeros(v.shape[:-1], dtype=np.uint64)
+    stride = 1
+    for a in range(dim):
+        shape = [1] * dim
+        shape[a] = nel[a] + 1
+        vid = vid + (np.arange(nel[a] + 1, dtype=np.uint64) * np.uint64(stride)).reshape(shape)
+        stride *= nel[a] + 1
+    off = np.zeros_like(v)
+    for a in range(dim):
+        h = (hi[a] - lo[a]) / float(nel[a])
+        with np.errstate(over="ignore"):
+            z = _splitmix64(seed, vid * np.uint64(dim) + np.uint64(a))
+        u = (z >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        off_a = (2.0 * u - 1.0) * (frac * h)
+        idx = [slice(None)] * dim
+        for end in (0, nel[a]):
+            idx[a] = end
+            off_a[tuple(idx)] = 0.0
+        off[..., a] = off_a
+    return np.ascontiguousarray(v + off)

@@ -40,24 +40,29 @@ def _t(a):
     return torch.tensor(np.ascontiguousarray(a), device=DEV)
 
 
-def _create(gym, ctx, nel, r, m2, c, hi):
+def _create(gym, ctx, nel, r, m2, c, hi, q1="exact"):
     mesh = gym.gym_mesh_create(ctx, 3, nel, hi=hi)
     o = gym.gym_maxwell_opts_default()
+    o.q1 = gym.GYM_Q1_EXACT if q1 == "exact" else gym.GYM_Q1_LUMPED
     o.m2 = gym.GYM_M2_EXACT if m2 == "exact" else gym.GYM_M2_LUMPED
     o.c = c
     return mesh, gym.gym_maxwell_create(ctx, mesh, r, o)
 
 
-CASES = [((4, 3, 4), 1, "exact", 1.0, (1.0, 1.2, 0.9), 0.0, 0),
-         ((4, 3, 4), 1, "exact", 0.9, (1.0, 1.2, 0.9), 1e3, 2),
-         ((3, 3, 2), 2, "lumped", 1.0, (1.0, 1.0, 1.0), 0.0, 0),
-         ((3, 3, 2), 2, "exact", 1.0, (1.0, 1.0, 1.0), 100.0, 2)]
+# The last two start from lumped Q1 and lumped M2~ (the one-kernel Yee
+# stepping): SPAI-OP then replaces Q1 and the steps must use it.
+CASES = [((4, 3, 4), 1, "exact", 1.0, (1.0, 1.2, 0.9), 0.0, 0, "exact"),
+         ((4, 3, 4), 1, "exact", 0.9, (1.0, 1.2, 0.9), 1e3, 2, "exact"),
+         ((3, 3, 2), 2, "lumped", 1.0, (1.0, 1.0, 1.0), 0.0, 0, "exact"),
+         ((3, 3, 2), 2, "exact", 1.0, (1.0, 1.0, 1.0), 100.0, 2, "exact"),
+         ((4, 3, 4), 1, "lumped", 1.0, (1.0, 1.2, 0.9), 0.0, 0, "lumped"),
+         ((3, 3, 2), 2, "lumped", 1.0, (1.0, 1.0, 1.0), 100.0, 2, "lumped")]
 
 
-@pytest.mark.parametrize("nel,r,m2,c,hi,lam,nprobe", CASES)
-def test_spai_op_steps_match_oracle(g, nel, r, m2, c, hi, lam, nprobe):
+@pytest.mark.parametrize("nel,r,m2,c,hi,lam,nprobe,q1", CASES)
+def test_spai_op_steps_match_oracle(g, nel, r, m2, c, hi, lam, nprobe, q1):
     gym, ctx = g
-    mesh, mx = _create(gym, ctx, nel, r, m2, c, hi)
+    mesh, mx = _create(gym, ctx, nel, r, m2, c, hi, q1)
     n = gym.gym_maxwell_ndofs(mx)
     verts = synth.uniform_vertices(nel, hi=hi)
     G0 = maxwell.Gym(Mesh(verts), r, q1="exact", m2=m2, c=c)
