@@ -268,6 +268,22 @@ void gym_solve_opts_default(gym_solve_opts* opts);
 int gym_solve(gym_op* op, const gym_solve_opts* opts, int nrhs,
               const double* b, double* x, gym_solve_info* info, void* stream);
 
+/* gym_solve without device allocation, for callers that cannot allocate
+ * (HIP graph capture set-up, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and results as gym_solve in GYM_MODE_F64 (the
+ * same kernels in the same order, so x is the same bit for bit); its Krylov
+ * workspace is a static device array of 128 MiB that each GPU the library
+ * runs on holds until the process ends, instead of the operator's pool.
+ * Limits: FP64 mode only (GYM_E_UNSUPPORTED otherwise), nrhs <= 64, and
+ * about 11 x ndofs x nrhs doubles plus partial sums must fit the array
+ * (roughly 1.4 M unknowns x rhs); larger problems return GYM_E_ARG with the
+ * size in the message.  opts->timing is ignored.  Calls on one GPU share the
+ * array: calls that overlap on one GPU race (serialise them).  Blocking, like
+ * gym_solve. */
+int gym_solve_noalloc(gym_op* op, const gym_solve_opts* opts, int nrhs,
+                      const double* b, double* x, gym_solve_info* info,
+                      void* stream);
+
 /* Mass solve M x = b (CG, Jacobi preconditioner, FP64): the exact-FEEC
  * application of M_1^{-1} in the paper's eq. (exactEOM). */
 int gym_mass_solve(const gym_space* space, const gym_solve_opts* opts,

@@ -738,6 +738,10 @@ int gym_create(gym_ctx** out, int device) {
     delete c;
     return rc;
   }
+  if (int rc = noalloc_init(device)) {
+    delete c;
+    return rc;
+  }
   *out = c;
   return GYM_OK;
 }
@@ -1174,7 +1178,8 @@ static int ensure_work32(gym_op* op, OpWork* w) {
   return 0;
 }
 
-// FP64 mode of gym_solve on the workspace w: preconditioned MINRES, then the
+// FP64 mode of gym_solve on the workspace w (the operator's pool, or the
+// static scratch array of gym_solve_noalloc): preconditioned MINRES, then the
 // true FP64 residual; restarts on the residual while the preconditioned
 // estimate was optimistic.  Allocates no device memory.
 static int minres_f64(gym_op* op, const gym_solve_opts& opts, int nrhs, const double* b, double* x, OpWork& w,
@@ -1317,6 +1322,96 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
   if (info) *info = inf;
   return status;
 }
+
+}  // extern "C"
+
+namespace gym {
+
+// FP64 solve on caller-provided device memory `base` of `bytes` bytes (the
+// static scratch array of gym_solve_noalloc): the workspace of gym_solve's
+// FP64 mode is carved from it, so nothing is allocated on the device.
+int solve_f64_on(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double* b, double* x,
+                 gym_solve_info* info, hipStream_t s, void* base, size_t bytes, MinresState* host_states,
+                 int max_rhs) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (!op || !b || !x || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
+  if (nrhs > max_rhs) return fail(GYM_E_ARG, "nrhs exceeds " + std::to_string(max_rhs));
+  if (!base) return fail(GYM_E_HIP, "scratch array not set up on this device");
+  gym_solve_opts opts;
+  if (opts_in) opts = *opts_in;
+  else gym_solve_opts_default(&opts);
+  if (opts.method != GYM_MINRES) return fail(GYM_E_UNSUPPORTED, "block operators are indefinite: use MINRES");
+  if (opts.mode != GYM_MODE_F64) return fail(GYM_E_UNSUPPORTED, "the allocation-free solve runs in FP64 mode only");
+  if (opts.precond != GYM_PRECOND_JACOBI && opts.precond != GYM_PRECOND_NONE)
+    return fail(GYM_E_ARG, "unknown preconditioner");
+  const long long n = op->na + op->nb;
+  int npa = 0;
+  if (int rc = op_workgroups(op, GYM_F64, nrhs, &npa)) return rc;
+  OpWork w;
+  w.n = n;
+  w.nrhs = nrhs;
+  w.nb = vec_grid(n, op->ctx->ncu);
+  // carve: 256-byte aligned pieces, in doubles
+  char* p = static_cast<char*>(base);
+  size_t used = 0;
+  bool fits = true;
+  auto take = [&](long long count) -> double* {
+    const size_t sz = ((size_t)count * sizeof(double) + 255) & ~(size_t)255;
+    if (used + sz > bytes) {
+      fits = false;
+      return nullptr;
+    }
+    double* q = reinterpret_cast<double*>(p + used);
+    used += sz;
+    return q;
+  };
+  const long long nv = n * nrhs;
+  double** vecs[8] = {&w.m64.r1, &w.m64.r2, &w.m64.y, &w.m64.z, &w.m64.zp, &w.m64.w, &w.m64.w1, &w.m64.w2};
+  for (double** v : vecs) *v = take(nv);
+  w.tmp = take(nv);
+  w.r64 = take(nv);
+  w.d64 = take(nv);
+  w.ones = opts.precond == GYM_PRECOND_NONE ? take(n) : nullptr;
+  w.m64.pa = take((long long)npa * nrhs);
+  for (int k = 0; k < 2; ++k) {
+    w.m64.pb[k] = take((long long)w.nb * nrhs);
+    w.m64.pc[k] = take((long long)w.nb * nrhs);
+    w.m64.alfa[k] = take(nrhs);
+  }
+  w.m64.npa_cap = npa;
+  w.part = take((long long)w.nb * nrhs);
+  w.sums = take(4LL * nrhs);
+  w.scale = w.sums + 2 * nrhs;
+  w.m64.st = reinterpret_cast<MinresState*>(take((long long)(sizeof(MinresState) * 2 * nrhs + 7) / 8));
+  if (!fits)
+    return fail(GYM_E_ARG, "problem too large for the allocation-free solve: needs more than " +
+                               std::to_string(bytes) + " bytes of scratch (" + std::to_string(n) + " unknowns x " +
+                               std::to_string(nrhs) + " rhs)");
+  w.m64.host = host_states;
+  const double* dinv = op->d_prec;
+  if (w.ones) {
+    launch_fill(w.ones, 1.0, n, w.nb, s);
+    dinv = w.ones;
+  }
+  ApplyTimer timer;  // no HIP events here: timing is off
+  gym_solve_info inf{};
+  std::vector<double> rel;
+  int status = GYM_OK;
+  int rc = minres_f64(op, opts, nrhs, b, x, w, npa, dinv, timer, s, &inf.iters, &status, rel);
+  w.m64.host = nullptr;  // not ours to free
+  if (rc) return rc;
+  inf.rel_res = rel.empty() ? 0.0 : *std::max_element(rel.begin(), rel.end());
+  if (status == GYM_OK && inf.rel_res > opts.rtol) status = GYM_W_NOT_CONVERGED;
+  GYM_HIP(hipStreamSynchronize(s));
+  inf.status = status;
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return status;
+}
+
+}  // namespace gym
+
+extern "C" {
 
 int gym_mass_solve(const gym_space* space_c, const gym_solve_opts* opts_in, int nrhs, const double* b, double* x,
                    gym_solve_info* info, void* stream) {

@@ -104,6 +104,9 @@ namespace gym {
 // The Gauss-point metrics of a curved mesh for degree r (f32: FP32 copy),
 // allocated and filled on first use (synchronously).
 int mesh_qdata(const gym_mesh* m, int r, int f32, const void** out);
+// Device address of the allocation-free solve's scratch array on `device`
+// (current), asked once per device (noalloc.hip).
+int noalloc_init(int device);
 }  // namespace gym
 
 struct gym_space {

@@ -121,6 +121,7 @@ SIGNATURES = {
     "gym_rhs_manufactured": (_I, [_P, _I, _P, _P, _P, _P]),
     "gym_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
     "gym_solve": (_I, [_P, ctypes.POINTER(SolveOpts), _I, _P, _P, ctypes.POINTER(SolveInfo), _P]),
+    "gym_solve_noalloc": (_I, [_P, ctypes.POINTER(SolveOpts), _I, _P, _P, ctypes.POINTER(SolveInfo), _P]),
     "gym_mass_solve": (_I, [_P, ctypes.POINTER(SolveOpts), _I, _P, _P, ctypes.POINTER(SolveInfo), _P]),
     "gym_serve_start": (_I, [ctypes.POINTER(ServeOpts), ctypes.POINTER(_P)]),
     "gym_serve_submit": (_I, [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -327,6 +328,14 @@ def gym_solve_opts_default():
 def gym_solve(op, opts, nrhs, b, x, stream=None):
     info = SolveInfo()
     st = lib().gym_solve(op, ctypes.byref(opts), nrhs, _ptr(b), _ptr(x), ctypes.byref(info), _stream(stream))
+    _check(st, ok=(GYM_OK, GYM_W_NOT_CONVERGED))
+    return info
+
+
+def gym_solve_noalloc(op, opts, nrhs, b, x, stream=None):
+    info = SolveInfo()
+    st = lib().gym_solve_noalloc(op, ctypes.byref(opts), nrhs, _ptr(b), _ptr(x), ctypes.byref(info),
+                                 _stream(stream))
     _check(st, ok=(GYM_OK, GYM_W_NOT_CONVERGED))
     return info
 
