@@ -26,6 +26,15 @@
 
 namespace gym {
 
+// The x Gauss-point dimension of the work arrays (QX = Q EX entries) is stored
+// point-major: Gauss point t of local element e at t EX + e.  The x stages give
+// consecutive lanes consecutive elements, so their LDS accesses are
+// consecutive words (element-major, Q words apart, they collide in banks).
+template <class C>
+__device__ __forceinline__ constexpr int xq(int e, int t) {
+  return t * C::EX + e;
+}
+
 // Where a layer's Gauss points sit in the metric lattice of geom.hpp.
 template <typename TC>
 struct QGeom {
@@ -41,30 +50,31 @@ __device__ __forceinline__ void cfwd_x(const TC* __restrict__ in, TC* __restrict
   constexpr int NX = C::nx(TM), R = C::R, Q = C::Q;
   constexpr bool N = TM & 1;
   constexpr int n = N ? R + 1 : R;
-  const TabSet<TC>& T = tabs<TC>(R);
+  const TabSet<TC>& T = stage_tabs<TC>(R);
   const int e = l % C::EX, rest = l / C::EX;
   const TC* s = in + rest * NX + R * e;
   TC v[n];
 #pragma unroll
   for (int i = 0; i < n; ++i) v[i] = s[i];
   const bool ok = e >= er.xlo && e < er.xhi;
-  TC* o = out + rest * C::QX + Q * e;
+  TC* o = out + rest * C::QX + e;
 #pragma unroll
   for (int t = 0; t < Q; ++t) {
     TC acc = 0;
 #pragma unroll
     for (int i = 0; i < n; ++i) acc += tab<TC, N, false>(T, t, i) * v[i];
-    o[t] = ok ? acc : TC(0);
+    o[xq<C>(0, t)] = ok ? acc : TC(0);
   }
 }
 
-// y: in [QX][NY][NZ] -> out [QX][QY][NZ]; line l = (qx, element, z row)
+// y: in [QX][NY][NZ] -> out [QX][QY][NZ]; line l = (qx, element, z row), qx
+// the stored x index (xq)
 template <class C, int TM, typename TC>
 __device__ __forceinline__ void cfwd_y(const TC* __restrict__ in, TC* __restrict__ out, int l, const ElemRange& er) {
   constexpr int NY = C::ny(TM), R = C::R, Q = C::Q, QX = C::QX;
   constexpr bool N = TM & 2;
   constexpr int n = N ? R + 1 : R;
-  const TabSet<TC>& T = tabs<TC>(R);
+  const TabSet<TC>& T = stage_tabs<TC>(R);
   const int qx = l % QX, r2 = l / QX;
   const int e = r2 % C::EY, k = r2 / C::EY;
   const TC* s = in + qx + QX * (R * e + NY * k);
@@ -88,7 +98,7 @@ __device__ __forceinline__ void cz_fwd(const TC* __restrict__ B, int p, TC (&u)[
   constexpr int P = C::QX * C::QY, R = C::R, Q = C::Q;
   constexpr bool N = TM & 4;
   constexpr int n = N ? R + 1 : R;
-  const TabSet<TC>& T = tabs<TC>(R);
+  const TabSet<TC>& T = stage_tabs<TC>(R);
   TC v[n];
 #pragma unroll
   for (int i = 0; i < n; ++i) v[i] = B[p + P * i];
@@ -107,7 +117,7 @@ __device__ __forceinline__ void cz_bwd(TC* __restrict__ B, int p, const TC (&u)[
   constexpr int P = C::QX * C::QY, R = C::R, Q = C::Q;
   constexpr bool N = TM & 4;
   constexpr int NZ = C::nz(TM);
-  const TabSet<TC>& T = tabs<TC>(R);
+  const TabSet<TC>& T = stage_tabs<TC>(R);
 #pragma unroll
   for (int k = 0; k < NZ; ++k) {
     TC acc = 0;
@@ -121,10 +131,10 @@ __device__ __forceinline__ void cz_bwd(TC* __restrict__ B, int p, const TC (&u)[
 // or -1 when the column belongs to an element outside the mesh
 template <class C, typename TC>
 __device__ __forceinline__ long long cz_base(int p, const ElemRange& er, const QGeom<TC>& g) {
-  const int qx = p % C::QX, qy = p / C::QX;
-  const int ex = qx / C::Q, ey = qy / C::Q;
+  const int qxs = p % C::QX, qy = p / C::QX;
+  const int ex = qxs % C::EX, tx = qxs / C::EX, ey = qy / C::Q;
   if (ex < er.xlo || ex >= er.xhi || ey < er.ylo || ey >= er.yhi) return -1;
-  return (long long)(g.gx0 + qx) + (long long)g.GX * ((long long)(g.gy0 + qy) + (long long)g.GY * g.gz0);
+  return (long long)(g.gx0 + C::Q * ex + tx) + (long long)g.GX * ((long long)(g.gy0 + qy) + (long long)g.GY * g.gz0);
 }
 
 // z stage of a scalar mass (H1: det J, L2: 1/det J) on column p, in place
@@ -182,7 +192,7 @@ template <class C, int TM, typename TC>
 __device__ __forceinline__ void cbwd_y(const TC* __restrict__ in, TC* __restrict__ out, int l) {
   constexpr int NY = C::ny(TM), R = C::R, Q = C::Q, QX = C::QX;
   constexpr bool N = TM & 2;
-  const TabSet<TC>& T = tabs<TC>(R);
+  const TabSet<TC>& T = stage_tabs<TC>(R);
   const int qx = l % QX, r2 = l / QX;
   const int e = r2 % C::EY, k = r2 / C::EY;
   const TC* s = in + qx + QX * (Q * e + C::QY * k);
@@ -226,12 +236,12 @@ template <class C, int TM, bool ADD, typename TC>
 __device__ __forceinline__ void cbwd_x(const TC* __restrict__ in, TC* __restrict__ out, int l) {
   constexpr int NX = C::nx(TM), R = C::R, Q = C::Q;
   constexpr bool N = TM & 1;
-  const TabSet<TC>& T = tabs<TC>(R);
+  const TabSet<TC>& T = stage_tabs<TC>(R);
   const int e = l % C::EX, rest = l / C::EX;
-  const TC* s = in + rest * C::QX + Q * e;
+  const TC* s = in + rest * C::QX + e;
   TC c[Q];
 #pragma unroll
-  for (int t = 0; t < Q; ++t) c[t] = s[t];
+  for (int t = 0; t < Q; ++t) c[t] = s[xq<C>(0, t)];
   TC* o = out + rest * NX + R * e;
   auto put = [&](int i, TC v) {
     if constexpr (ADD) o[i] += v;
@@ -241,7 +251,7 @@ __device__ __forceinline__ void cbwd_x(const TC* __restrict__ in, TC* __restrict
     TC lower = 0;
     if (e > 0) {
 #pragma unroll
-      for (int t = 0; t < Q; ++t) lower += tab<TC, N, true>(T, t, R) * s[t - Q];
+      for (int t = 0; t < Q; ++t) lower += tab<TC, N, true>(T, t, R) * s[xq<C>(0, t) - 1];
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {

@@ -835,13 +835,15 @@ int launch_op_b(const OpParams& p0, int nrhs, int ncu, hipStream_t stream) {
   if (p0.wg_out) *p0.wg_out = p.tiles_x * p.tiles_y * p.nchunks;
   if (p0.dry) return 0;
   const long long nwg = (long long)p.tiles_x * p.tiles_y * p.nchunks * nrhs;
-  if (FORM == FORM_CURVED && nrhs > 1 && nwg % 8 == 0 && nwg < (1LL << 31)) {
-    hipLaunchKernelGGL((op_kernel_rhs<C, PROB, FORM, TV, TC, MR>), dim3((unsigned)nwg), dim3(C::NT), 0, stream, p,
-                       nrhs);
-  } else {
-    dim3 grid(p.tiles_x * p.tiles_y, p.nchunks, nrhs);
-    hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC, MR>), grid, dim3(C::NT), 0, stream, p);
+  if constexpr (FORM == FORM_CURVED) {
+    if (nrhs > 1 && nwg % 8 == 0 && nwg < (1LL << 31)) {
+      hipLaunchKernelGGL((op_kernel_rhs<C, PROB, FORM, TV, TC, MR>), dim3((unsigned)nwg), dim3(C::NT), 0, stream, p,
+                         nrhs);
+      return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
   }
+  dim3 grid(p.tiles_x * p.tiles_y, p.nchunks, nrhs);
+  hipLaunchKernelGGL((op_kernel<C, PROB, FORM, TV, TC, MR>), grid, dim3(C::NT), 0, stream, p);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

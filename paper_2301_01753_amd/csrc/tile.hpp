@@ -80,6 +80,19 @@ __device__ __forceinline__ const TabSet<double>& tabs<double>(int r) { return c_
 template <>
 __device__ __forceinline__ const TabSet<float>& tabs<float>(int r) { return c_tab_f[r - 1]; }
 
+// The same tables, looked up afresh at the call: the index passes through an
+// empty asm, so the scalar loads of the entries cannot be hoisted out of the
+// enclosing loops.  Hoisted, every table a kernel touches would stay live in
+// scalar registers at once and spill to VGPR lanes; fetched here, only the
+// entries of one contraction are live.
+template <typename TC>
+__device__ __forceinline__ const TabSet<TC>& stage_tabs(int r) {
+  int k = r - 1;
+  asm volatile("" : "+s"(k));
+  if constexpr (sizeof(TC) == 8) return c_tab_d[k];
+  else return c_tab_f[k];
+}
+
 template <bool BF, typename TC>
 __device__ __forceinline__ const TabSet<TC>& ktabs(int r) {
   if constexpr (BF) return c_tab_b[r - 1];
