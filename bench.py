@@ -164,8 +164,10 @@ def apply_rates(gym, op, n, nrhs, precs, reps, warmup, seed):
 def poisson64_solves(gym, ctx, rtol, modes, reps):
     """64^3 degree-4 mixed Poisson (67.3 M unknowns): whole solves from x = 0
     to relative residual `rtol` (true FP64 residual) in FP64 and in
-    mixed-precision refinement; each result's relative error against the
-    FP64 solution.  Also the apply rates per precision."""
+    mixed-precision refinement, MINRES with the block preconditioner
+    diag(diag(M2), M3 D diag(M2)^-1 D^T M3); each result's relative error
+    against the FP64 solution.  Also the apply rates per precision and the
+    preconditioner's own time."""
     import torch
     import synth
     mesh = gym.gym_mesh_create(ctx, 3, (64, 64, 64))
@@ -175,6 +177,11 @@ def poisson64_solves(gym, ctx, rtol, modes, reps):
                                                             ("bf16", gym.GYM_BF16)), 50, 3, 11)}
     b = torch.empty(n, dtype=torch.float64, device="cuda:0")
     gym.gym_rhs_manufactured(op, synth.modes_3d(), synth.fourier_coeffs(0, 8, 1), b)
+    zt = torch.empty_like(b)
+    gym.gym_op_precond_apply(op, gym.GYM_PRECOND_SCHUR, 1, b, zt)  # set-up (host eigenproblems), not timed
+    ms, _ = event_times(lambda: gym.gym_op_precond_apply(op, gym.GYM_PRECOND_SCHUR, 1, b, zt), 10, 1)
+    res["schur_precond_apply_us"] = median(ms) * 1e3
+    del zt
     x64 = None
     for name, mode, inner in modes:
         o = gym.gym_solve_opts_default()
@@ -183,7 +190,8 @@ def poisson64_solves(gym, ctx, rtol, modes, reps):
         o.maxit = 200000
         o.inner_rtol = inner
         o.max_outer = 60
-        o.check_every = 50
+        o.check_every = 10
+        o.precond = gym.GYM_PRECOND_SCHUR
         x = torch.empty_like(b)
         walls, infos = [], []
         for k in range(reps):
@@ -644,7 +652,7 @@ def main():
             log("64^3 degree-4 mixed Poisson: applies and solves to 1e-8 ...")
             extras["poisson_r4_64cube"] = poisson64_solves(
                 gym, ctx, 1e-8, (("f64", gym.GYM_MODE_F64, 0.0), ("ir_f32", gym.GYM_MODE_IR_F32, 1e-3),
-                                 ("ir_bf16", gym.GYM_MODE_IR_BF16, 1e-2)), 1)
+                                 ("ir_bf16", gym.GYM_MODE_IR_BF16, 1e-3)), 3)
         log("32^3 degree-2 Hodge solves ...")
         extras["hodge_r2_32cube"] = hodge32_solves(gym, ctx, 4, 1e-10)
         if args.serve_requests > 0:

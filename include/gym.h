@@ -81,9 +81,16 @@ extern "C" {
  * diagonal of each block's own Gram-type operator:
  *   Poisson: diag(M2 + D^T M3 D), diag(M3);
  *   Hodge:   diag(M0 + G^T M1 G), diag(M1 + C^T M2 C)
- * (gym_op_precond_diag).  NONE runs unpreconditioned MINRES. */
+ * (gym_op_precond_diag).  NONE runs unpreconditioned MINRES.
+ * SCHUR (mixed Poisson on affine 3-D boxes): diag(diag(M2), S) with
+ * S = M3 D diag(M2)^-1 D^T M3, the Schur complement of the block system with
+ * M2 replaced by its diagonal; S is inverted exactly by simultaneous
+ * diagonalisation of its per-axis factors (dense 1-D transforms along the
+ * three axes).  Its set-up (three symmetric eigenproblems of size r N_a on
+ * the host) runs on first use. */
 #define GYM_PRECOND_JACOBI 0
 #define GYM_PRECOND_NONE   1
+#define GYM_PRECOND_SCHUR  2
 
 typedef struct gym_ctx gym_ctx;
 typedef struct gym_mesh gym_mesh;
@@ -215,6 +222,12 @@ int gym_op_destroy(gym_op* op);
 /* y = A x, nrhs vectors; precisions as for gym_mass_apply (incidence exact). */
 int gym_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y,
                  void* stream);
+/* z = M^-1 y for the preconditioner `precond` of gym_solve (GYM_PRECOND_JACOBI
+ * or GYM_PRECOND_SCHUR), nrhs FP64 device vectors.  Stream-ordered; the
+ * Schur set-up on first use is blocking.  Errors: GYM_E_ARG,
+ * GYM_E_UNSUPPORTED (SCHUR on a Hodge operator, a 2-D or a curved mesh). */
+int gym_op_precond_apply(gym_op* op, int precond, int nrhs, const double* y,
+                         double* z, void* stream);
 /* Diagonal of the block-Jacobi preconditioner (FP64, op ndofs entries):
  * diag(M2 + D^T M3 D), diag(M3) for Poisson; diag(M0 + G^T M1 G),
  * diag(M1 + C^T M2 C) for Hodge. */
@@ -243,7 +256,7 @@ typedef struct gym_solve_opts {
   int timing;         /* k > 0: bracket every k-th operator apply with HIP
                          events (1: every apply; a larger k keeps the
                          events' own cost out of the solve)                */
-  int precond;        /* GYM_PRECOND_JACOBI (default) or GYM_PRECOND_NONE  */
+  int precond;        /* GYM_PRECOND_JACOBI (default), _NONE or _SCHUR     */
 } gym_solve_opts;
 
 typedef struct gym_solve_info {

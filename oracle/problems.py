@@ -202,3 +202,37 @@ def mass_cg(M, b, rtol=1e-14, maxiter=10000):
     Minv = sp.diags(1.0 / M.diagonal())
     x, info = spla.cg(M, b, M=Minv, rtol=rtol, maxiter=maxiter)
     return x, info
+
+
+def schur_preconditioner(P):
+    """Block preconditioner of the mixed Poisson system (a reading: the paper
+    preconditions only with a diagonal, section 5.1).  With A's blocks M2 and
+    B = -M3 D, the preconditioner is diag(diag(M2), S), S = B diag(M2)^-1 B^T
+    = M3 D diag(M2)^-1 D^T M3: the Schur complement of the system whose flux
+    block is replaced by its diagonal.  Returns (apply, S, d): apply(y) =
+    [y_s / d; S^-1 y_p] by a sparse direct solve, d = diag(M2)."""
+    d = P.M2.diagonal().copy()
+    B = -(P.M3 @ P.D)
+    S = (B @ sp.diags(1.0 / d) @ B.T).tocsc()
+    lu = spla.splu(S)
+    ns = d.size
+
+    def apply(y):
+        y = np.asarray(y, dtype=float)
+        return np.concatenate([y[:ns] / d, lu.solve(y[ns:])])
+
+    return apply, S, d
+
+
+def solve_minres_prec(A, b, apply, rtol=1e-13, maxiter=100000):
+    """SciPy MINRES with a preconditioner given as a function z = M^-1 y;
+    returns (x, info, iterations)."""
+    n = A.shape[0]
+    M = spla.LinearOperator((n, n), matvec=apply, dtype=float)
+    its = [0]
+
+    def cb(_):
+        its[0] += 1
+
+    x, info = spla.minres(A, b, M=M, rtol=rtol, maxiter=maxiter, callback=cb)
+    return x, info, its[0]

@@ -42,15 +42,30 @@ def _compile(src, obj):
     return obj
 
 
-def build(verbose=True, jobs=None):
+def _stale(src, obj, headers):
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    return os.path.getmtime(src) > t or any(os.path.getmtime(h) > t for h in headers)
+
+
+def build(verbose=True, jobs=None, incremental=False):
+    """Compile every source (incremental=True: only those whose object is
+    older than the source or any header) and link lib/libgym.so."""
     os.makedirs(LIBDIR, exist_ok=True)
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
     srcs = sources()
     objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in srcs]
-    jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
+    if incremental:
+        headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+        headers.append(os.path.join(HERE, "..", "include", "gym.h"))
+        todo = [(s, o) for s, o in zip(srcs, objs) if _stale(s, o, headers)]
+    else:
+        todo = list(zip(srcs, objs))
+    jobs = jobs or min(max(1, len(todo)), max(1, (os.cpu_count() or 4)))
     with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
-        list(ex.map(_compile, srcs, objs))
+        list(ex.map(lambda so: _compile(*so), todo))
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + COMMON + ["-shared", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -63,5 +78,5 @@ def build(verbose=True, jobs=None):
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)
     sys.exit(0)

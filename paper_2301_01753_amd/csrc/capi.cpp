@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <thread>
 #include <vector>
@@ -14,6 +15,8 @@
 #include "gym_internal.hpp"
 #include "kernels.hpp"
 #include "krylov.hpp"
+#include "poisson_mfma.hpp"
+#include "schur.hpp"
 
 namespace gym {
 
@@ -347,8 +350,77 @@ void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int&
 }
 
 namespace {
+
+// bf16 element products on the matrix cores: mixed Poisson, affine 3-D, r >= 3
+bool mfma_path(const gym_op* op, int prec) {
+  return prec == GYM_BF16 && op->problem == GYM_MIXED_POISSON && op->mesh->dim == 3 && !op->mesh->curved &&
+         op->r >= 3;
+}
+
+struct MfmaState {
+  uint16_t* frag = nullptr;
+  float* yel = nullptr;
+  int nrhs = 0;
+};
+
+int mfma_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t s, const MrStep* mr, int* wg_out) {
+  const gym_mesh* m = op->mesh;
+  const long long E = m->nel[0] * m->nel[1] * m->nel[2];
+  const int rows = poisson_mfma_rows(op->r);
+  PoissonMfmaParams q{};
+  q.ndofs = op->na + op->nb;
+  q.gather_blocks = poisson_mfma_gather_blocks(q.ndofs, op->ctx->ncu);
+  if (wg_out) {
+    *wg_out = q.gather_blocks;
+    return 0;
+  }
+  gym_op* mop = const_cast<gym_op*>(op);  // lazily built apply state
+  MfmaState* st = static_cast<MfmaState*>(mop->mfma);
+  if (!st) {
+    st = new MfmaState;
+    std::vector<double> mn, me;
+    element_masses_1d(op->r, mn, me);
+    const double s3 = metric_const(GYM_L2, 0, m);
+    std::vector<uint16_t> f = poisson_mfma_fragments(op->r, mn, me, s3);
+    if (int rc = dalloc((void**)&st->frag, sizeof(uint16_t) * f.size())) {
+      delete st;
+      return rc;
+    }
+    if (hipMemcpy(st->frag, f.data(), sizeof(uint16_t) * f.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(st->frag);
+      delete st;
+      return fail(GYM_E_HIP, "upload of the element fragments");
+    }
+    mop->mfma = st;
+  }
+  if (st->nrhs < nrhs) {
+    if (st->yel) (void)hipFree(st->yel);
+    st->yel = nullptr;
+    st->nrhs = 0;
+    if (int rc = dalloc((void**)&st->yel, sizeof(float) * (size_t)rows * E * nrhs)) return rc;
+    st->nrhs = nrhs;
+  }
+  q.x = x;
+  q.y = y;
+  q.yel = st->yel;
+  q.np_off = op->na;
+  q.el_rows = E;
+  q.el_stride = (long long)rows * E;
+  for (int a = 0; a < 3; ++a) {
+    q.nel[a] = (int)m->nel[a];
+    q.m[a] = (int)(op->r * m->nel[a]);
+    q.s2[a] = (float)metric_const(GYM_HDIV, a, m);
+  }
+  q.s = to_dev(op->sa, 0);
+  if (mr) q.mr = *mr;
+  if (launch_poisson_mfma(q, st->frag, op->r, nrhs, mr != nullptr, op->ctx->ncu, s))
+    return fail(GYM_E_HIP, "matrix-core operator launch failed");
+  return 0;
+}
+
 int op_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s, const MrStep* mr,
               int* wg_out) {
+  if (mfma_path(op, prec)) return mfma_launch(op, nrhs, x, y, s, mr, wg_out);
   OpParams p;
   int prob;
   build_op_params(op, x, y, p, prob);
@@ -465,14 +537,25 @@ int ensure_partials(std::vector<void*>& pool, MinresWork<TV>& w, int npa, int nb
 // host reads the states every check_every steps; on exit x is complete (a
 // step still pending at the iteration cap is finished by minres_finish).
 // npa = workgroups per rhs of the fused apply.
+// A non-diagonal preconditioner: out = M^-1 in for all right-hand sides.
+template <typename TV>
+using PrecFn = std::function<int(const TV*, TV*)>;
+
 template <typename TV, typename Apply>
 int run_minres(Apply&& apply, long long n, int nrhs, int nb, int npa, const TV* b, TV* x, const double* dinv,
                double tol, int maxit, int check_every, MinresWork<TV>& wk, hipStream_t s, int* iters_out,
-               int* flag_out) {
+               int* flag_out, const PrecFn<TV>* ext = nullptr) {
   if (npa > wk.npa_cap) return fail(GYM_E_HIP, "MINRES partial-sum buffer too small for this launch");
   // init: r1 = r2 = b, z = M^-1 b (into wk.z), beta_1 in slot 0
   MinresVecs<TV> V{b, x, wk.r1, wk.r2, wk.z, wk.y, wk.w, wk.w1, wk.w2};
-  minres_launch_init<TV>(V, dinv, n, nrhs, nb, wk.pb[0], wk.st, tol, s);
+  if (ext) {
+    minres_launch_init_vecs<TV>(V, n, nrhs, nb, s);
+    if (int rc = (*ext)(b, wk.z)) return rc;
+    minres_launch_dot2<TV>(b, wk.z, nullptr, n, nrhs, nb, wk.pb[0], nullptr, s);
+    minres_launch_init_state<TV>(V, n, nrhs, nb, wk.pb[0], wk.st, tol, s);
+  } else {
+    minres_launch_init<TV>(V, dinv, n, nrhs, nb, wk.pb[0], wk.st, tol, s);
+  }
   int par = 0;  // set of step2 partials written last
   if (check_every < 1) check_every = 1;
   int it = 0, slot = 0;
@@ -484,8 +567,14 @@ int run_minres(Apply&& apply, long long n, int nrhs, int nb, int npa, const TV* 
     if (int rc = apply(wk.z, wk.y, m)) return rc;
     const MrVecs<TV> mv{wk.y, wk.r1, wk.r2, wk.zp, x, wk.w2, wk.w, wk.w1};
     const Step2Io io{cur, next, pending ? 0 : 1, npa, nb, wk.pa, wk.pb[par], wk.pc[par], wk.alfa[par],
-                     wk.pb[par ^ 1], wk.pc[par ^ 1], wk.alfa[par ^ 1]};
+                     wk.pb[par ^ 1], wk.pc[par ^ 1], wk.alfa[par ^ 1], ext ? 1 : 0};
     minres_launch_step2<TV>(mv, dinv, n, nrhs, nb, io, s);
+    if (ext) {
+      // z_{k+1} = M^-1 y over zp (read by step2 already), and the partial
+      // sums step2 leaves to us: y . z_{k+1}, z_{k+1} . r2
+      if (int rc = (*ext)(wk.y, wk.zp)) return rc;
+      minres_launch_dot2<TV>(wk.y, wk.zp, wk.r2, n, nrhs, nb, io.pb, io.pc, s);
+    }
     par ^= 1;
     if (pending) {  // the newest w was written over the oldest
       TV *ow = wk.w, *ow1 = wk.w1, *ow2 = wk.w2;
@@ -606,6 +695,23 @@ struct OpWork {
   double* ones = nullptr;  // the identity "diagonal" of GYM_PRECOND_NONE
   std::vector<void*> pool;
 };
+
+// The block preconditioner of a mixed Poisson operator on an affine box,
+// set up on first use and kept with the operator; work vectors for nrhs.
+static int ensure_schur(gym_op* op, int nrhs, SchurPrec** out) {
+  if (!op->schur) {
+    SchurPrec* P = new SchurPrec;
+    if (int rc = schur_build(op, P)) {
+      delete P;
+      return rc;
+    }
+    op->schur = P;
+  }
+  SchurPrec* P = static_cast<SchurPrec*>(op->schur);
+  if (int rc = schur_reserve(P, nrhs, sizeof(double))) return rc;
+  *out = P;
+  return 0;
+}
 
 // Workspace of CG mass solves, cached on the space.
 struct MassWork {
@@ -1044,6 +1150,16 @@ static void free_work(gym_op* op) {
 int gym_op_destroy(gym_op* op) {
   if (!op) return GYM_OK;
   free_work(op);
+  if (op->schur) {
+    schur_free(static_cast<SchurPrec*>(op->schur));
+    delete static_cast<SchurPrec*>(op->schur);
+  }
+  if (op->mfma) {
+    MfmaState* st = static_cast<MfmaState*>(op->mfma);
+    if (st->frag) (void)hipFree(st->frag);
+    if (st->yel) (void)hipFree(st->yel);
+    delete st;
+  }
   if (op->d_prec) (void)hipFree(op->d_prec);
   delete op;
   return GYM_OK;
@@ -1053,6 +1169,23 @@ int gym_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, v
   if (!op || !x || !y || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
   if (prec != GYM_F64 && prec != GYM_F32 && prec != GYM_BF16) return fail(GYM_E_ARG, "unknown precision");
   return launch_op_apply(op, prec, nrhs, x, y, (hipStream_t)stream);
+}
+
+int gym_op_precond_apply(gym_op* op, int precond, int nrhs, const double* y, double* z, void* stream) {
+  if (!op || !y || !z || nrhs < 1) return fail(GYM_E_ARG, "bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  const long long n = op->na + op->nb;
+  const int nb = vec_grid(n, op->ctx->ncu);
+  if (precond == GYM_PRECOND_JACOBI) {
+    for (int r = 0; r < nrhs; ++r) launch_axpy_diag(z + n * r, 0.0, 1.0, op->d_prec, y + n * r, n, nb, s);
+    GYM_HIP(hipGetLastError());
+    return GYM_OK;
+  }
+  if (precond != GYM_PRECOND_SCHUR) return fail(GYM_E_ARG, "unknown preconditioner");
+  SchurPrec* P;
+  if (int rc = ensure_schur(op, nrhs, &P)) return rc;
+  if (launch_schur_apply<double>(*P, y, z, nrhs, nb, s)) return fail(GYM_E_HIP, "preconditioner launch");
+  return GYM_OK;
 }
 
 int gym_op_precond_diag(const gym_op* op, double* diag, void* stream) {
@@ -1184,7 +1317,7 @@ static int ensure_work32(gym_op* op, OpWork* w) {
 // estimate was optimistic.  Allocates no device memory.
 static int minres_f64(gym_op* op, const gym_solve_opts& opts, int nrhs, const double* b, double* x, OpWork& w,
                       int npa, const double* dinv, ApplyTimer& timer, hipStream_t s, int* iters, int* status,
-                      std::vector<double>& rel) {
+                      std::vector<double>& rel, const PrecFn<double>* ext = nullptr) {
   const long long n = w.n;
   auto apply = [&](const double* in, double* out, const MrStep& m) {
     if (int rc = timer.begin(s)) return rc;
@@ -1199,7 +1332,7 @@ static int minres_f64(gym_op* op, const gym_solve_opts& opts, int nrhs, const do
   for (int attempt = 0; attempt < 6; ++attempt) {
     int it = 0;
     if (int rc = run_minres<double>(apply, n, nrhs, w.nb, npa, rhs, sol, dinv, tol, opts.maxit - total,
-                                    opts.check_every, w.m64, s, &it, &flag))
+                                    opts.check_every, w.m64, s, &it, &flag, ext))
       return rc;
     total += it;
     if (flag < 0) {
@@ -1238,10 +1371,20 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
   gym_solve_info inf{};
   hipStream_t s = (hipStream_t)stream;
   if (opts.method != GYM_MINRES) return fail(GYM_E_UNSUPPORTED, "block operators are indefinite: use MINRES");
-  if (opts.precond != GYM_PRECOND_JACOBI && opts.precond != GYM_PRECOND_NONE)
+  if (opts.precond != GYM_PRECOND_JACOBI && opts.precond != GYM_PRECOND_NONE && opts.precond != GYM_PRECOND_SCHUR)
     return fail(GYM_E_ARG, "unknown preconditioner");
   OpWork* w;
   if (int rc = ensure_work(op, nrhs, &w)) return rc;
+  SchurPrec* schur = nullptr;
+  if (opts.precond == GYM_PRECOND_SCHUR)
+    if (int rc = ensure_schur(op, nrhs, &schur)) return rc;
+  const PrecFn<double> ext64 = [&](const double* in, double* out) {
+    return launch_schur_apply<double>(*schur, in, out, nrhs, w->nb, s) ? fail(GYM_E_HIP, "preconditioner launch")
+                                                                      : 0;
+  };
+  const PrecFn<float> ext32 = [&](const float* in, float* out) {
+    return launch_schur_apply<float>(*schur, in, out, nrhs, w->nb, s) ? fail(GYM_E_HIP, "preconditioner launch") : 0;
+  };
   const long long n = w->n;
   const double* dinv = op->d_prec;
   if (opts.precond == GYM_PRECOND_NONE) {
@@ -1262,7 +1405,9 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
     int npa = 0;
     if (int rc = op_workgroups(op, GYM_F64, nrhs, &npa)) return rc;
     if (int rc = ensure_partials(w->pool, w->m64, npa, w->nb, nrhs)) return rc;
-    if (int rc = minres_f64(op, opts, nrhs, b, x, *w, npa, dinv, timer, s, &inf.iters, &status, rel)) return rc;
+    if (int rc = minres_f64(op, opts, nrhs, b, x, *w, npa, schur ? nullptr : dinv, timer, s, &inf.iters, &status,
+                            rel, schur ? &ext64 : nullptr))
+      return rc;
   } else if (opts.mode == GYM_MODE_IR_F32 || opts.mode == GYM_MODE_IR_BF16) {
     if (int rc = ensure_work32(op, w)) return rc;
     const int prec = opts.mode == GYM_MODE_IR_BF16 ? GYM_BF16 : GYM_F32;
@@ -1295,8 +1440,9 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
       GYM_HIP(hipMemcpyAsync(w->scale, sc.data(), sizeof(double) * 2 * nrhs, hipMemcpyHostToDevice, s));
       launch_to_f32_scaled(w->r64, w->r32, n, nrhs, w->nb, w->scale, s);
       int it = 0, flag = 0;
-      if (int rc = run_minres<float>(apply32, n, nrhs, w->nb, npa, w->r32, w->x32, dinv, opts.inner_rtol,
-                                     opts.maxit, opts.check_every, w->m32, s, &it, &flag))
+      if (int rc = run_minres<float>(apply32, n, nrhs, w->nb, npa, w->r32, w->x32, schur ? nullptr : dinv,
+                                     opts.inner_rtol, opts.maxit, opts.check_every, w->m32, s, &it, &flag,
+                                     schur ? &ext32 : nullptr))
         return rc;
       total += it;
       if (flag < 0) {
@@ -1342,6 +1488,8 @@ int solve_f64_on(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const doub
   else gym_solve_opts_default(&opts);
   if (opts.method != GYM_MINRES) return fail(GYM_E_UNSUPPORTED, "block operators are indefinite: use MINRES");
   if (opts.mode != GYM_MODE_F64) return fail(GYM_E_UNSUPPORTED, "the allocation-free solve runs in FP64 mode only");
+  if (opts.precond == GYM_PRECOND_SCHUR)
+    return fail(GYM_E_UNSUPPORTED, "the allocation-free solve takes the diagonal preconditioners only");
   if (opts.precond != GYM_PRECOND_JACOBI && opts.precond != GYM_PRECOND_NONE)
     return fail(GYM_E_ARG, "unknown preconditioner");
   const long long n = op->na + op->nb;

@@ -22,27 +22,69 @@
 #include "krylov.hpp"
 
 namespace gym {
-namespace {
 
-// Cholesky factor L (lower, row-major m x m) of G; false if a pivot is not
-// positive or falls below rel times the largest diagonal entry.
-bool cholesky(const std::vector<double>& G, int m, std::vector<double>& L, double rel) {
-  L.assign((size_t)m * m, 0.0);
-  double dmax = 0.0;
-  for (int i = 0; i < m; ++i) dmax = std::max(dmax, G[(size_t)i * m + i]);
-  for (int j = 0; j < m; ++j) {
-    double d = G[(size_t)j * m + j];
-    for (int k = 0; k < j; ++k) d -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
-    if (!(d > rel * dmax)) return false;
-    const double ljj = std::sqrt(d);
-    L[(size_t)j * m + j] = ljj;
-    for (int i = j + 1; i < m; ++i) {
-      double v = G[(size_t)i * m + j];
-      for (int k = 0; k < j; ++k) v -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
-      L[(size_t)i * m + j] = v / ljj;
+// Eigenvalues (ascending, w) and orthonormal eigenvectors (columns of V,
+// n x n row-major) of the symmetric tridiagonal matrix with diagonal d and
+// off-diagonal e (e[i] couples rows i and i + 1) by the QL iteration with
+// implicit Wilkinson shifts (Bowdler, Martin, Reinsch & Wilkinson 1968),
+// accumulating the plane rotations.
+void tridiag_eig(std::vector<double> d, std::vector<double> e, int n, std::vector<double>& w, std::vector<double>& V) {
+  std::vector<double> Z((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Z[(size_t)i * n + i] = 1.0;
+  e.resize(n, 0.0);
+  e[n - 1] = 0.0;
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0; iter < 64; ++iter) {
+      int m = l;
+      for (; m < n - 1; ++m) {
+        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= 2.2e-16 * dd) break;
+      }
+      if (m == l) break;
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + std::copysign(r, g));
+      double s = 1.0, c = 1.0, p = 0.0;
+      bool deflated = false;
+      for (int i = m - 1; i >= l; --i) {
+        double f = s * e[i];
+        const double b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          deflated = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        for (int k = 0; k < n; ++k) {
+          f = Z[(size_t)k * n + i + 1];
+          Z[(size_t)k * n + i + 1] = s * Z[(size_t)k * n + i] + c * f;
+          Z[(size_t)k * n + i] = c * Z[(size_t)k * n + i] - s * f;
+        }
+      }
+      if (deflated) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
     }
   }
-  return true;
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return d[a] < d[b]; });
+  w.resize(n);
+  V.assign((size_t)n * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    w[j] = d[ord[j]];
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + j] = Z[(size_t)i * n + ord[j]];
+  }
 }
 
 // Eigenvalues (ascending) and eigenvectors (columns of V, row-major) of the
@@ -92,6 +134,29 @@ void jacobi_eig(std::vector<double> H, int m, std::vector<double>& w, std::vecto
     for (int i = 0; i < m; ++i) Vs[(size_t)i * m + j] = V[(size_t)i * m + order[j]];
   }
   V.swap(Vs);
+}
+
+namespace {
+
+// Cholesky factor L (lower, row-major m x m) of G; false if a pivot is not
+// positive or falls below rel times the largest diagonal entry.
+bool cholesky(const std::vector<double>& G, int m, std::vector<double>& L, double rel) {
+  L.assign((size_t)m * m, 0.0);
+  double dmax = 0.0;
+  for (int i = 0; i < m; ++i) dmax = std::max(dmax, G[(size_t)i * m + i]);
+  for (int j = 0; j < m; ++j) {
+    double d = G[(size_t)j * m + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * m + k] * L[(size_t)j * m + k];
+    if (!(d > rel * dmax)) return false;
+    const double ljj = std::sqrt(d);
+    L[(size_t)j * m + j] = ljj;
+    for (int i = j + 1; i < m; ++i) {
+      double v = G[(size_t)i * m + j];
+      for (int k = 0; k < j; ++k) v -= L[(size_t)i * m + k] * L[(size_t)j * m + k];
+      L[(size_t)i * m + j] = v / ljj;
+    }
+  }
+  return true;
 }
 
 // Rayleigh-Ritz on the m columns with Gram matrices GA = S^T A S, GB = S^T B S:

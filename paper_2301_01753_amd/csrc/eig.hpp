@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <functional>
+#include <vector>
 
 namespace gym {
 
@@ -38,5 +39,12 @@ struct EigResult {
 // status on error, or 1 when the iteration cap was reached first.
 int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int maxit, double* X, double* lam,
            EigResult* res, int ncu, hipStream_t s);
+
+// Eigenvalues (ascending, w) and eigenvectors (columns of V, m x m row-major)
+// of the symmetric m x m row-major matrix H by cyclic Jacobi rotations.
+void jacobi_eig(std::vector<double> H, int m, std::vector<double>& w, std::vector<double>& V);
+// The same for a symmetric tridiagonal matrix (diagonal d, off-diagonal e,
+// e[i] coupling rows i and i + 1) by implicit-shift QL.
+void tridiag_eig(std::vector<double> d, std::vector<double> e, int n, std::vector<double>& w, std::vector<double>& V);
 
 }  // namespace gym

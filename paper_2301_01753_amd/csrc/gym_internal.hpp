@@ -35,6 +35,9 @@ struct Tables1D {
   std::vector<double> edge;     // q x r
 };
 Tables1D make_tables(int r, int q);
+// 1-D element masses of degree r from the q = r + 1 Gauss rule: nodal
+// (r+1)^2 and edge r^2 entries, row-major.
+void element_masses_1d(int r, std::vector<double>& mn, std::vector<double>& me);
 std::vector<double> gll_nodes(int r);
 void gauss_rule(int q, std::vector<double>& x, std::vector<double>& w);
 
@@ -129,4 +132,6 @@ struct gym_op {
   std::vector<void*> work;           // Krylov workspace
   int work_nrhs = 0;
   size_t work_bytes = 0;
+  void* schur = nullptr;             // gym::SchurPrec, built on first use
+  void* mfma = nullptr;              // bf16 matrix-core apply state, built on first use
 };

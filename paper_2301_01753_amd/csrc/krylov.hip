@@ -96,6 +96,41 @@ __global__ void __launch_bounds__(kBT) minres_init_b(MinresVecs<TV> v, long long
     v.v[off + i] = static_cast<TV>(todbl(v.y[off + i]) * inv);
 }
 
+// Non-diagonal preconditioner: r1 = r2 = b, x = w = w1 = w2 = 0
+template <typename TV>
+__global__ void __launch_bounds__(kBT) minres_init_vecs(MinresVecs<TV> v, long long n) {
+  const long long off = (long long)blockIdx.y * n;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    const TV bi = v.b[off + i];
+    v.r1[off + i] = bi;
+    v.r2[off + i] = bi;
+    v.x[off + i] = 0;
+    v.w[off + i] = 0;
+    v.w1[off + i] = 0;
+    v.w2[off + i] = 0;
+  }
+}
+
+// per block: pb = y . z, pc = z . r (r may be null)
+template <typename TV>
+__global__ void __launch_bounds__(kBT) minres_dot2(const TV* __restrict__ y, const TV* __restrict__ z,
+                                                   const TV* __restrict__ r, long long n, double* pb, double* pc) {
+  __shared__ double sh[2 * kBT];
+  const long long off = (long long)blockIdx.y * n;
+  double a = 0.0, c = 0.0;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
+    const double zi = todbl(z[off + i]);
+    a += todbl(y[off + i]) * zi;
+    if (r) c += zi * todbl(r[off + i]);
+  }
+  double t[2] = {a, c};
+  wg_sums<kBT, 2>(t, sh);
+  if (threadIdx.x == 0) {
+    pb[(long long)blockIdx.y * gridDim.x + blockIdx.x] = t[0];
+    if (pc) pc[(long long)blockIdx.y * gridDim.x + blockIdx.x] = t[1];
+  }
+}
+
 // Second kernel of a fused MINRES step.  The operator kernel left
 // y = A z_k and per-workgroup partial sums pa of z_k . A z_k.  Every block:
 //   1. closes step k-1 (unless `first`): scalar update of state cur with
@@ -113,7 +148,7 @@ struct Step2Coef {
   double ys, c1, c, vpinv, phi, denom, oldeps, delta;
 };
 
-template <typename TV, bool UPD>
+template <typename TV, bool UPD, bool EXT>
 __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* __restrict__ dinv, long long n,
                                             long long off, const Step2Coef& k, int blk, int nblk, double& ab,
                                             double& ac) {
@@ -134,16 +169,18 @@ __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* _
                  double xv) {
     const TV ys = static_cast<TV>(k.ys * yv - k.c1 * r1v - k.c * r2v);
     y[i] = ys;
-    const TV zs = static_cast<TV>(dv * todbl(ys));
     if constexpr (UPD) {
       const double vp = todbl(static_cast<TV>(zpv * k.vpinv));
       const TV ws = static_cast<TV>((vp - k.oldeps * wav - k.delta * wbv) * k.denom);
       wo[i] = ws;
       x[i] = static_cast<TV>(xv + k.phi * todbl(ws));
     }
-    zp[i] = zs;
-    ab += todbl(ys) * todbl(zs);
-    ac += todbl(zs) * r2v;
+    if constexpr (!EXT) {
+      const TV zs = static_cast<TV>(dv * todbl(ys));
+      zp[i] = zs;
+      ab += todbl(ys) * todbl(zs);
+      ac += todbl(zs) * r2v;
+    }
   };
   for (; i0 + (U - 1) * stride < n; i0 += U * stride) {
     double yv[U], r1v[U], r2v[U], dv[U], zpv[U], wav[U], wbv[U], xv[U];
@@ -153,7 +190,7 @@ __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* _
       yv[u] = todbl(y[i]);
       r1v[u] = todbl(r1[i]);
       r2v[u] = todbl(r2[i]);
-      dv[u] = dinv[i];
+      dv[u] = EXT ? 0.0 : dinv[i];
       if constexpr (UPD) {
         zpv[u] = todbl(zp[i]);
         wav[u] = todbl(wa[i]);
@@ -168,10 +205,10 @@ __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* _
   }
   for (; i0 < n; i0 += stride) {
     if constexpr (UPD)
-      one(i0, todbl(y[i0]), todbl(r1[i0]), todbl(r2[i0]), dinv[i0], todbl(zp[i0]), todbl(wa[i0]), todbl(wb[i0]),
-          todbl(x[i0]));
+      one(i0, todbl(y[i0]), todbl(r1[i0]), todbl(r2[i0]), EXT ? 0.0 : dinv[i0], todbl(zp[i0]), todbl(wa[i0]),
+          todbl(wb[i0]), todbl(x[i0]));
     else
-      one(i0, todbl(y[i0]), todbl(r1[i0]), todbl(r2[i0]), dinv[i0], 0.0, 0.0, 0.0, 0.0);
+      one(i0, todbl(y[i0]), todbl(r1[i0]), todbl(r2[i0]), EXT ? 0.0 : dinv[i0], 0.0, 0.0, 0.0, 0.0);
   }
 }
 
@@ -216,8 +253,15 @@ __device__ __forceinline__ void step2_body(const MrVecs<TV>& v, const double* __
   k.c = alfa * vinv;
   const long long off = (long long)rhs * n;
   double ab = 0.0, ac = 0.0;
-  if (io.first) step2_sweep<TV, false>(v, dinv, n, off, k, blk, nblk, ab, ac);
-  else step2_sweep<TV, true>(v, dinv, n, off, k, blk, nblk, ab, ac);
+  if (io.ext) {
+    // y and the w, x updates only: z_{k+1} = M^-1 y and its partial sums
+    // follow in the caller's kernels
+    if (io.first) step2_sweep<TV, false, true>(v, dinv, n, off, k, blk, nblk, ab, ac);
+    else step2_sweep<TV, true, true>(v, dinv, n, off, k, blk, nblk, ab, ac);
+    return;
+  }
+  if (io.first) step2_sweep<TV, false, false>(v, dinv, n, off, k, blk, nblk, ab, ac);
+  else step2_sweep<TV, true, false>(v, dinv, n, off, k, blk, nblk, ab, ac);
   double t2[2] = {ab, ac};
   wg_sums<kBT, 2>(t2, sh);
   if (threadIdx.x == 0) {
@@ -464,6 +508,23 @@ void minres_launch_init(const MinresVecs<TV>& v, const double* dinv, long long n
 }
 
 template <typename TV>
+void minres_launch_init_vecs(const MinresVecs<TV>& v, long long n, int nrhs, int nb, hipStream_t s) {
+  GYM_LAUNCH(minres_init_vecs<TV>, dim3(nb, nrhs), s, v, n);
+}
+
+template <typename TV>
+void minres_launch_dot2(const TV* y, const TV* z, const TV* r, long long n, int nrhs, int nb, double* pb,
+                        double* pc, hipStream_t s) {
+  GYM_LAUNCH(minres_dot2<TV>, dim3(nb, nrhs), s, y, z, r, n, pb, pc);
+}
+
+template <typename TV>
+void minres_launch_init_state(const MinresVecs<TV>& v, long long n, int nrhs, int nb, const double* part,
+                              MinresState* st0, double tol, hipStream_t s) {
+  GYM_LAUNCH(minres_init_b<TV>, dim3(nb, nrhs), s, v, n, part, nb, st0, tol);
+}
+
+template <typename TV>
 void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, const Step2Io& io,
                          hipStream_t s) {
   GYM_LAUNCH(minres_step2<TV>, dim3(nb, nrhs), s, v, dinv, n, io);
@@ -528,6 +589,16 @@ template void minres_launch_init<double>(const MinresVecs<double>&, const double
                                          MinresState*, double, hipStream_t);
 template void minres_launch_init<float>(const MinresVecs<float>&, const double*, long long, int, int, double*,
                                         MinresState*, double, hipStream_t);
+template void minres_launch_init_vecs<double>(const MinresVecs<double>&, long long, int, int, hipStream_t);
+template void minres_launch_init_vecs<float>(const MinresVecs<float>&, long long, int, int, hipStream_t);
+template void minres_launch_dot2<double>(const double*, const double*, const double*, long long, int, int, double*,
+                                         double*, hipStream_t);
+template void minres_launch_dot2<float>(const float*, const float*, const float*, long long, int, int, double*,
+                                        double*, hipStream_t);
+template void minres_launch_init_state<double>(const MinresVecs<double>&, long long, int, int, const double*,
+                                               MinresState*, double, hipStream_t);
+template void minres_launch_init_state<float>(const MinresVecs<float>&, long long, int, int, const double*,
+                                              MinresState*, double, hipStream_t);
 template void minres_launch_step2<double>(const MrVecs<double>&, const double*, long long, int, int, const Step2Io&,
                                           hipStream_t);
 template void minres_launch_step2<float>(const MrVecs<float>&, const double*, long long, int, int, const Step2Io&,

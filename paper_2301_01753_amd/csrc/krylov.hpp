@@ -52,11 +52,27 @@ struct Step2Io {
   const double* alfa_prev; // alfa_{k-1} per rhs
   double *pb, *pc;         // out: this pass's partials
   double* alfa;            // out: alfa_k per rhs
+  int ext;                 // 1: the preconditioner runs after the kernel
+                           // (z_{k+1} and the partials pb, pc come from
+                           // the caller: minres_launch_dot2)
 };
 
 template <typename TV>
 void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, int nrhs, int nb, const Step2Io& io,
                          hipStream_t s);
+// A non-diagonal preconditioner M: the initialisation without z (r1 = r2 = b,
+// x = w = w1 = w2 = 0), and after z = M^-1 y the per-block partial sums
+// pb = y . z and, if r is not null, pc = z . r, in the layout of
+// minres_step2's (nb blocks per rhs).
+template <typename TV>
+void minres_launch_init_vecs(const MinresVecs<TV>& v, long long n, int nrhs, int nb, hipStream_t s);
+template <typename TV>
+void minres_launch_dot2(const TV* y, const TV* z, const TV* r, long long n, int nrhs, int nb, double* pb,
+                        double* pc, hipStream_t s);
+// beta_1 from the partials of b . M^-1 b (as minres_launch_init's second half)
+template <typename TV>
+void minres_launch_init_state(const MinresVecs<TV>& v, long long n, int nrhs, int nb, const double* part,
+                              MinresState* st0, double tol, hipStream_t s);
 
 // One request of a ragged batch of fused MINRES steps (FP64, one rhs).
 struct MrItem {

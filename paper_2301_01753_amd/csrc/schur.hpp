@@ -1,0 +1,54 @@
+// Block preconditioner of the mixed Poisson operator on affine boxes:
+// diag(diag(M2), M3 D diag(M2)^-1 D^T M3) applied exactly, the cell block by
+// simultaneous diagonalisation of its per-axis factors (schur.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+struct gym_op;
+
+namespace gym {
+
+struct SchurPrec {
+  long long ns = 0, np = 0;     // unknowns of the flux block and of the cell block
+  int m[3] = {1, 1, 1};         // cells per axis
+  double* dsinv = nullptr;      // ns: 1 / diag(M2)
+  double* lam = nullptr;        // m0 + m1 + m2: lam_a / s2_a per axis
+  double scale = 1.0;           // 1 / s3^2
+  double* fwd64[3] = {};        // Vt_a^T, row-major m_a x m_a (forward transforms)
+  double* bwd64[3] = {};        // Vt_a
+  float* fwd32[3] = {};
+  float* bwd32[3] = {};
+  void* work = nullptr;         // two cell-block vectors per right-hand side
+  int work_nrhs = 0;
+  size_t work_bytes = 0;
+  void* mem = nullptr;          // the factors
+
+  template <typename T>
+  const T* const* fwd() const {
+    if constexpr (sizeof(T) == 8) return fwd64;
+    else return fwd32;
+  }
+  template <typename T>
+  const T* const* bwd() const {
+    if constexpr (sizeof(T) == 8) return bwd64;
+    else return bwd32;
+  }
+  // k-th work vector (np x nrhs of T)
+  template <typename T>
+  T* work_vec(int k) const {
+    return static_cast<T*>(work) + (size_t)k * (size_t)np * (size_t)work_nrhs;
+  }
+};
+
+// Set-up for the operator (mixed Poisson, 3-D, affine): GYM_E_UNSUPPORTED
+// otherwise.  Host work: three symmetric eigenproblems of size m_a.
+int schur_build(const gym_op* op, SchurPrec* out);
+// Work vectors for nrhs right-hand sides (grown on demand; the caller
+// allocates outside its hot loop).
+int schur_reserve(SchurPrec* P, int nrhs, size_t elem_bytes);
+void schur_free(SchurPrec* P);
+// z = P^-1 y for nrhs vectors in the operator's layout [s; p] (stride ns + np).
+template <typename T>
+int launch_schur_apply(const SchurPrec& P, const T* y, T* z, int nrhs, int nb, hipStream_t s);
+
+}  // namespace gym

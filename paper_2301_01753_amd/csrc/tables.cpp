@@ -154,4 +154,17 @@ SpaceDesc make_space_desc(int kind, int dim, const int64_t nel[3], int r, int bc
   return s;
 }
 
+void element_masses_1d(int r, std::vector<double>& mn, std::vector<double>& me) {
+  Tables1D t = make_tables(r, r + 1);
+  const int q = r + 1;
+  mn.assign((r + 1) * (r + 1), 0.0);
+  me.assign(r * r, 0.0);
+  for (int k = 0; k < q; ++k) {
+    for (int i = 0; i <= r; ++i)
+      for (int j = 0; j <= r; ++j) mn[i * (r + 1) + j] += t.gw[k] * t.phi[k * (r + 1) + i] * t.phi[k * (r + 1) + j];
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) me[i * r + j] += t.gw[k] * t.edge[k * r + i] * t.edge[k * r + j];
+  }
+}
+
 }  // namespace gym

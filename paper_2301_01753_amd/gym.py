@@ -29,7 +29,7 @@ GYM_F64, GYM_F32, GYM_BF16 = 0, 1, 2
 GYM_MIXED_POISSON, GYM_HODGE1 = 0, 1
 GYM_MINRES, GYM_CG = 0, 1
 GYM_MODE_F64, GYM_MODE_IR_F32, GYM_MODE_IR_BF16 = 0, 1, 2
-GYM_PRECOND_JACOBI, GYM_PRECOND_NONE = 0, 1
+GYM_PRECOND_JACOBI, GYM_PRECOND_NONE, GYM_PRECOND_SCHUR = 0, 1, 2
 GYM_Q1_EXACT, GYM_Q1_LUMPED, GYM_Q1_SPAI_DIAG, GYM_Q1_SPAI, GYM_Q1_SPAI_OP = 0, 1, 2, 3, 4
 GYM_M2_EXACT, GYM_M2_LUMPED = 0, 1
 
@@ -117,6 +117,7 @@ SIGNATURES = {
     "gym_op_block_sizes": (_I, [_P, ctypes.POINTER(_I64)]),
     "gym_op_destroy": (_I, [_P]),
     "gym_op_apply": (_I, [_P, _I, _I, _P, _P, _P]),
+    "gym_op_precond_apply": (_I, [_P, _I, _I, _P, _P, _P]),
     "gym_op_precond_diag": (_I, [_P, _P, _P]),
     "gym_rhs_manufactured": (_I, [_P, _I, _P, _P, _P, _P]),
     "gym_solve_opts_default": (None, [ctypes.POINTER(SolveOpts)]),
@@ -306,6 +307,10 @@ def gym_op_destroy(op):
 
 def gym_op_apply(op, prec, nrhs, x, y, stream=None):
     _check(lib().gym_op_apply(op, prec, nrhs, _ptr(x), _ptr(y), _stream(stream)))
+
+
+def gym_op_precond_apply(op, precond, nrhs, y, z, stream=None):
+    _check(lib().gym_op_precond_apply(op, precond, nrhs, _ptr(y), _ptr(z), _stream(stream)))
 
 
 def gym_op_precond_diag(op, diag, stream=None):

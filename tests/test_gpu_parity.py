@@ -583,6 +583,52 @@ def test_operator_apply_bf16(g, which, nel, r):
     gym.gym_mesh_destroy(mesh)
 
 
+@pytest.mark.parametrize("nel,r", [((4, 5, 3), 4), ((3, 2, 4), 3), ((5, 3, 3), 4)])
+def test_poisson_bf16_matrix_core_apply_error_bound(g, nel, r):
+    # Mixed Poisson at degree >= 3 applies each element operator
+    # A_e = [[M2_e, B_e^T], [B_e, 0]], B_e = -M3_e D_e, as one bf16 product with
+    # FP32 accumulation, then sums at most two element results per unknown in
+    # FP32.  Entries of A_e and of x are rounded to bf16 (unit round-off
+    # u = 2^-8), so per output row
+    #   |y - A x|_i <= (2 u + u^2 + 2 * 2^-24 K) (sum_e P_e^T |A_e| |P_e x|)_i,
+    # K the element row length.  Checked row by row with the oracle's element
+    # matrices (x rounded to FP32 first, as the caller passes it).
+    gym, ctx = g
+    mesh = _mesh(gym, ctx, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON, mesh, r)
+    P = _oracle_problem("poisson", nel, r)
+    n = P.A.shape[0]
+    x32 = synth.random_vector(n, seed=13).astype(np.float32)
+    y = torch.empty(n, dtype=torch.float32, device=DEV)
+    gym.gym_op_apply(op, gym.GYM_BF16, 1, torch.tensor(x32, device=DEV), y)
+    torch.cuda.synchronize()
+    x = x32.astype(np.float64)
+    M = P.mesh
+    m2 = assembly.local_mass(P.sdiv, M)
+    m3 = assembly.local_mass(P.sl2, M)
+    ei = M.element_multi_index()
+    dd = P.sdiv.element_dofs(ei)
+    dc = P.sl2.element_dofs(ei)
+    D = P.D.tocsr()
+    bound_vec = np.zeros(n)
+    ns = P.sdiv.ndofs
+    for e in range(dd.shape[0]):
+        Be = -m3[e] @ D[dc[e]][:, dd[e]].toarray()
+        xs, xp = np.abs(x[dd[e]]), np.abs(x[ns + dc[e]])
+        bound_vec[dd[e]] += np.abs(m2[e]) @ xs + np.abs(Be.T) @ xp
+        bound_vec[ns + dc[e]] += np.abs(Be) @ xs
+    K = 3 * (r + 1) * r * r + r ** 3
+    u = 2.0 ** -8
+    tol = (2 * u + u * u + 2 * 2.0 ** -24 * K) * bound_vec + 1e-30
+    err = np.abs(y.cpu().numpy().astype(np.float64) - P.A @ x)
+    ratio = (err / tol).max()
+    print(f"nel={nel} r={r}: max |y - Ax| / bound = {ratio:.3f}, rel err {_rel(y.cpu().numpy(), P.A @ x):.2e}",
+          flush=True)
+    assert ratio <= 1.0
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
 @pytest.mark.parametrize("which,nel,r", [("poisson", (4, 4, 3), 3), ("hodge", (4, 3, 4), 2)])
 def test_solve_mixed_precision_bf16(g, which, nel, r):
     gym, ctx = g

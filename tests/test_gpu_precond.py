@@ -1,0 +1,194 @@
+"""The mixed Poisson block preconditioner on the GPU (GYM_PRECOND_SCHUR)
+against the oracle's plain definition (oracle.problems.schur_preconditioner:
+diag(M2) and a sparse direct solve with S = M3 D diag(M2)^-1 D^T M3), and the
+solves it drives.
+
+* gym_op_precond_apply vs the oracle, several boxes (non-cubic, non-unit
+  extents), degrees 1-4, two right-hand sides: <= 1e-11 of the max norm (the
+  GPU inverts S through per-axis eigenvectors; the error is S's condition
+  number, at most ~1e4 here, times the rounding of the transforms).
+* Solves with it: FP64 against SuperLU <= 1e-10; FP32 / bf16-operand
+  refinement <= 1e-8; the iteration count stays small.
+* The full 64^3 degree-4 workload (67.3 M unknowns, whole-CU tiles, the
+  benchmark's launch configuration): FP64, IR-FP32 and IR-BF16 solves of the
+  manufactured right-hand side to 1e-8, each checked on sampled oracle rows
+  of A x = b (patch rows, tests/patch_rows.py) against its global residual,
+  and the mixed-precision solutions against the FP64 one.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import problems
+from oracle.lattice import Mesh
+from patch_rows import origins, patch_rows
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def g():
+    from paper_2301_01753_amd import gym
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = gym.gym_create(0)
+    yield gym, ctx
+    gym.gym_destroy(ctx)
+
+
+CASES = [((3, 4, 2), 1, None), ((3, 4, 2), 2, (1.0, 1.3, 0.7)), ((2, 3, 2), 3, None), ((2, 2, 3), 4, None),
+         ((5, 3, 4), 2, (2.0, 1.0, 0.5))]
+
+
+@pytest.mark.parametrize("nel,r,hi", CASES)
+def test_schur_apply_matches_oracle(g, nel, r, hi):
+    gym, ctx = g
+    mesh = gym.gym_mesh_create(ctx, 3, nel, hi=hi)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON, mesh, r)
+    P = problems.MixedPoisson(Mesh(synth.uniform_vertices(nel, hi=hi)), r)
+    apply, S, d = problems.schur_preconditioner(P)
+    n = P.A.shape[0]
+    assert gym.gym_op_ndofs(op) == n
+    y = synth.random_vector(n, seed=8, nrhs=2)
+    z = torch.empty(2 * n, dtype=torch.float64, device=DEV)
+    gym.gym_op_precond_apply(op, gym.GYM_PRECOND_SCHUR, 2, torch.tensor(y, device=DEV), z)
+    got = z.cpu().numpy().reshape(2, n)
+    for k in range(2):
+        ref = apply(y.reshape(2, n)[k])
+        err = np.abs(got[k] - ref).max() / np.abs(ref).max()
+        print(f"nel={nel} r={r}: rhs {k} rel err {err:.2e}", flush=True)
+        assert err < 1e-11, err
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
+@pytest.mark.parametrize("mode,tol", [("F64", 1e-10), ("IR_F32", 1e-8), ("IR_BF16", 1e-8)])
+@pytest.mark.parametrize("nel,r", [((4, 3, 5), 2), ((3, 3, 3), 4)])
+def test_schur_solve_matches_direct(g, nel, r, mode, tol):
+    gym, ctx = g
+    mesh = gym.gym_mesh_create(ctx, 3, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON, mesh, r)
+    P = problems.MixedPoisson(Mesh(synth.uniform_vertices(nel)), r)
+    n = P.A.shape[0]
+    b = synth.random_vector(n, seed=12, nrhs=2)
+    x = torch.empty(2 * n, dtype=torch.float64, device=DEV)
+    o = gym.gym_solve_opts_default()
+    o.mode = {"F64": gym.GYM_MODE_F64, "IR_F32": gym.GYM_MODE_IR_F32, "IR_BF16": gym.GYM_MODE_IR_BF16}[mode]
+    o.rtol = 1e-12 if mode == "F64" else 1e-10
+    o.inner_rtol = 1e-3
+    o.precond = gym.GYM_PRECOND_SCHUR
+    info = gym.gym_solve(op, o, 2, torch.tensor(b, device=DEV), x)
+    print(f"{mode} nel={nel} r={r}: {info.iters} iterations ({info.outer_iters} outer), "
+          f"rel_res {info.rel_res:.1e}", flush=True)
+    assert info.status == gym.GYM_OK
+    assert info.iters < (200 if mode == "F64" else 600)
+    got = x.cpu().numpy().reshape(2, n)
+    for k in range(2):
+        ref = problems.solve_direct(P.A, b.reshape(2, n)[k])
+        err = np.linalg.norm(got[k] - ref) / np.linalg.norm(ref)
+        assert err < tol, (k, err)
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
+@pytest.mark.parametrize("maxit", [1, 2, 7])
+def test_schur_iteration_cap_matches_minres_iterate(g, maxit):
+    # The external-preconditioner MINRES step (z = M^-1 y after the step's
+    # vector pass, then its partial sums) against SciPy's MINRES with the
+    # oracle's preconditioner, k steps: the k-th iterates agree.
+    import scipy.sparse.linalg as spla
+    gym, ctx = g
+    nel, r = (4, 3, 5), 2
+    mesh = gym.gym_mesh_create(ctx, 3, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON, mesh, r)
+    P = problems.MixedPoisson(Mesh(synth.uniform_vertices(nel)), r)
+    apply, S, d = problems.schur_preconditioner(P)
+    n = P.A.shape[0]
+    b = synth.random_vector(n, seed=12, nrhs=2)
+    x = torch.empty(2 * n, dtype=torch.float64, device=DEV)
+    o = gym.gym_solve_opts_default()
+    o.rtol, o.maxit, o.check_every, o.precond = 1e-14, maxit, 3, gym.GYM_PRECOND_SCHUR
+    info = gym.gym_solve(op, o, 2, torch.tensor(b, device=DEV), x)
+    assert info.iters == maxit
+    M = spla.LinearOperator((n, n), matvec=apply, dtype=float)
+    got = x.cpu().numpy().reshape(2, n)
+    for k in range(2):
+        ref, _ = spla.minres(P.A, b.reshape(2, n)[k], M=M, rtol=1e-30, maxiter=maxit)
+        err = np.linalg.norm(got[k] - ref) / np.linalg.norm(ref)
+        assert err < 1e-10, (k, err)
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
+def test_schur_refused_where_not_built(g):
+    gym, ctx = g
+    mesh = gym.gym_mesh_create(ctx, 3, (3, 3, 3))
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, 1)
+    n = gym.gym_op_ndofs(op)
+    y = torch.zeros(n, dtype=torch.float64, device=DEV)
+    z = torch.empty_like(y)
+    with pytest.raises(gym.GymError) as e:
+        gym.gym_op_precond_apply(op, gym.GYM_PRECOND_SCHUR, 1, y, z)
+    assert e.value.status == gym.GYM_E_UNSUPPORTED
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+    mesh = gym.gym_mesh_structured(ctx, 3, (3, 3, 3), 0.1, 2)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON, mesh, 1)
+    n = gym.gym_op_ndofs(op)
+    y = torch.zeros(n, dtype=torch.float64, device=DEV)
+    z = torch.empty_like(y)
+    with pytest.raises(gym.GymError) as e:
+        gym.gym_op_precond_apply(op, gym.GYM_PRECOND_SCHUR, 1, y, z)
+    assert e.value.status == gym.GYM_E_UNSUPPORTED
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
+
+
+def test_poisson_r4_64cube_solves_on_rows(g):
+    # The 64^3 degree-4 workload end to end with the block preconditioner:
+    # FP64, IR-FP32 and IR-BF16 to relative residual 1e-8 from the
+    # manufactured right-hand side.  On sampled oracle rows, |b_i - (A x)_i|
+    # is bounded by the global residual rel_res ||b||_2 (plus the rounding of
+    # the row sum); the mixed-precision solutions agree with the FP64 one to
+    # the accuracy the residual allows (condition number x 1e-8).
+    gym, ctx = g
+    nel, r = (64, 64, 64), 4
+    mesh = gym.gym_mesh_create(ctx, 3, nel)
+    op = gym.gym_op_create(ctx, gym.GYM_MIXED_POISSON, mesh, r)
+    n = gym.gym_op_ndofs(op)
+    b = torch.empty(n, dtype=torch.float64, device=DEV)
+    gym.gym_rhs_manufactured(op, synth.modes_3d(), synth.fourier_coeffs(0, 8, 1), b)
+    vg = synth.uniform_vertices(nel)
+    rng = np.random.default_rng(17)
+    samples = [patch_rows("poisson", vg, nel, r, o, m) for o, m in origins(nel, rng)]
+    bnorm = float(torch.linalg.vector_norm(b))
+    sols = {}
+    for mode in ("F64", "IR_F32", "IR_BF16"):
+        o = gym.gym_solve_opts_default()
+        o.mode = {"F64": gym.GYM_MODE_F64, "IR_F32": gym.GYM_MODE_IR_F32, "IR_BF16": gym.GYM_MODE_IR_BF16}[mode]
+        o.rtol = 1e-8
+        o.inner_rtol = 1e-3
+        o.precond = gym.GYM_PRECOND_SCHUR
+        x = torch.empty_like(b)
+        info = gym.gym_solve(op, o, 1, b, x)
+        torch.cuda.synchronize()
+        print(f"64^3 r=4 Poisson {mode}: {info.iters} iterations ({info.outer_iters} outer), "
+              f"rel_res {info.rel_res:.2e}, {info.seconds:.2f} s", flush=True)
+        assert info.status == gym.GYM_OK and info.rel_res <= 1e-8
+        bound = 1.01 * info.rel_res * bnorm
+        for A, gmap, rows in samples:
+            idx = torch.as_tensor(gmap, device=DEV)
+            xp = x.index_select(0, idx).cpu().numpy()
+            bp = b.index_select(0, idx).cpu().numpy()[rows]
+            err = np.abs(bp - (A @ xp)[rows])
+            scale = (abs(A) @ np.abs(xp))[rows]
+            assert (err <= bound + 1e-12 * scale).all(), err.max()
+        sols[mode] = x
+    for mode in ("IR_F32", "IR_BF16"):
+        e = float(torch.linalg.vector_norm(sols[mode] - sols["F64"]) / torch.linalg.vector_norm(sols["F64"]))
+        print(f"{mode} vs FP64 solution: rel err {e:.2e}", flush=True)
+        assert e < 1e-5
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
