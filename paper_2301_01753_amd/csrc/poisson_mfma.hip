@@ -69,7 +69,7 @@ __device__ inline bf16x8 ld_frag(const uint16_t* p, int lane) {
 
 // Element products of a batch of 32 elements; one wavefront per batch.
 template <int R, bool MR>
-__global__ void __launch_bounds__(64) elem_kernel(const float* __restrict__ x, float* __restrict__ yel,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) elem_kernel(const float* __restrict__ x, float* __restrict__ yel,
                                                   const uint16_t* __restrict__ frag, PoissonMfmaParams q) {
   using D = Dims<R>;
   const int lane = threadIdx.x;
@@ -87,31 +87,9 @@ __global__ void __launch_bounds__(64) elem_kernel(const float* __restrict__ x, f
     ec[2] = (int)(e / ((long long)q.nel[0] * q.nel[1]));
   }
   const int kh = 8 * (lane / 32);  // this lane's first k within a 16-step
-  // B fragments: the element's flux components and cell values, bf16
-  bf16x8 bs[3][D::KF], bp[D::KC];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-    const DevComp& cd = q.s.c[c];
-#pragma unroll
-    for (int kt = 0; kt < D::KF; ++kt) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = 16 * kt + kh + j;
-        float v = 0.f;
-        if (live && k < D::NF) {
-          const int i_n = k % (R + 1), t = k / (R + 1);
-          const int i_1 = t % R, i_2 = t / R;
-          int p[3];
-          p[c] = R * ec[c] + i_n;
-          p[a1] = R * ec[a1] + i_1;
-          p[a2] = R * ec[a2] + i_2;
-          v = xr[cd.offset + p[0] + (long long)cd.count[0] * (p[1] + (long long)cd.count[1] * p[2])];
-        }
-        bs[c][kt][j] = (__bf16)v;
-      }
-    }
-  }
+  // B fragments of the cell values, bf16 (those of a flux component are
+  // gathered inside the component loop, so only one component is live)
+  bf16x8 bp[D::KC];
   {
     const long long base = q.np_off;
     const long long m0 = q.m[0], m1 = q.m[1];
@@ -141,6 +119,29 @@ __global__ void __launch_bounds__(64) elem_kernel(const float* __restrict__ x, f
   const int rq = 4 * (lane / 32);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    bf16x8 bs[D::KF];
+    {
+      const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
+      const DevComp& cd = q.s.c[c];
+#pragma unroll
+      for (int kt = 0; kt < D::KF; ++kt) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int k = 16 * kt + kh + j;
+          float v = 0.f;
+          if (live && k < D::NF) {
+            const int i_n = k % (R + 1), t = k / (R + 1);
+            const int i_1 = t % R, i_2 = t / R;
+            int p[3];
+            p[c] = R * ec[c] + i_n;
+            p[a1] = R * ec[a1] + i_1;
+            p[a2] = R * ec[a2] + i_2;
+            v = xr[cd.offset + p[0] + (long long)cd.count[0] * (p[1] + (long long)cd.count[1] * p[2])];
+          }
+          bs[kt][j] = (__bf16)v;
+        }
+      }
+    }
     floatx16 a1[D::TF], a2[D::TF];
 #pragma unroll
     for (int t = 0; t < D::TF; ++t) {
@@ -149,7 +150,7 @@ __global__ void __launch_bounds__(64) elem_kernel(const float* __restrict__ x, f
 #pragma unroll
       for (int kt = 0; kt < D::KF; ++kt)
         a1[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ld_frag(fM2 + (size_t)(t * D::KF + kt) * 512, lane),
-                                                       bs[c][kt], a1[t], 0, 0, 0);
+                                                       bs[kt], a1[t], 0, 0, 0);
 #pragma unroll
       for (int kt = 0; kt < D::KC; ++kt)
         a2[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
@@ -160,7 +161,7 @@ __global__ void __launch_bounds__(64) elem_kernel(const float* __restrict__ x, f
 #pragma unroll
       for (int kt = 0; kt < D::KF; ++kt)
         accp[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            ld_frag(fB + (size_t)((c * D::TC + t) * D::KF + kt) * 512, lane), bs[c][kt], accp[t], 0, 0, 0);
+            ld_frag(fB + (size_t)((c * D::TC + t) * D::KF + kt) * 512, lane), bs[kt], accp[t], 0, 0, 0);
     // y_s,c = s2_c (M2ref s_c) + B_c^T p, rows c NF + local
     if (live) {
       const float s2 = q.s2[c];
@@ -184,9 +185,13 @@ __global__ void __launch_bounds__(64) elem_kernel(const float* __restrict__ x, f
   }
 }
 
-// Sum the element contributions of every global unknown (flux: at most two
-// elements, lower one first; cell: one) into y; with MR also partial sums of
-// z . (A z) per block.
+// Sum the element contributions of every global unknown into y: one thread
+// per (element-local row, element), elements contiguous, so every read of the
+// element buffer is coalesced.  A flux row on an element's lower face (normal
+// index 0) adds the lower neighbour's upper-face row first, then its own; a
+// row on the upper face is written only at the domain's upper boundary (the
+// next element's lower-face thread writes it otherwise); every other row is
+// the only contribution.  With MR also partial sums of z . (A z) per block.
 template <int R, bool MR>
 __global__ void __launch_bounds__(256) gather_kernel(const float* __restrict__ x, float* __restrict__ y,
                                                      const float* __restrict__ yel, PoissonMfmaParams q) {
@@ -194,46 +199,53 @@ __global__ void __launch_bounds__(256) gather_kernel(const float* __restrict__ x
   const int rhs = blockIdx.y;
   const float* yr = yel + (long long)rhs * q.el_stride;
   const long long off = (long long)rhs * q.ndofs;
+  const long long E = q.el_rows;
+  const long long total = (long long)D::ROWS * E;
   double acc = 0.0;
-  for (long long g = (long long)blockIdx.x * 256 + threadIdx.x; g < q.ndofs; g += (long long)gridDim.x * 256) {
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
+    const int row = (int)(t / E);
+    const long long e = t - (long long)row * E;
+    const int ex = (int)(e % q.nel[0]);
+    const long long et = e / q.nel[0];
+    const int ey = (int)(et % q.nel[1]), ez = (int)(et / q.nel[1]);
+    const int ec[3] = {ex, ey, ez};
+    long long g;
     float v;
-    if (g >= q.np_off) {
-      const long long cidx = g - q.np_off;
-      const int px = (int)(cidx % q.m[0]);
-      const long long t = cidx / q.m[0];
-      const int py = (int)(t % q.m[1]), pz = (int)(t / q.m[1]);
-      const long long el = px / R + (long long)q.nel[0] * (py / R + (long long)q.nel[1] * (pz / R));
-      const int row = 3 * D::NF + (px % R) + R * ((py % R) + R * (pz % R));
-      v = yr[(long long)row * q.el_rows + el];
+    if (row >= 3 * D::NF) {
+      const int k = row - 3 * D::NF;
+      const int ix = k % R, iy = (k / R) % R, iz = k / (R * R);
+      g = q.np_off + (R * ex + ix) + (long long)q.m[0] * ((R * ey + iy) + (long long)q.m[1] * (R * ez + iz));
+      v = yr[(long long)row * E + e];
     } else {
-      int c = 0;
-      while (c < 2 && g >= q.s.c[c + 1].offset) ++c;
-      const DevComp& cd = q.s.c[c];
-      const long long li = g - cd.offset;
-      int p[3];
-      p[0] = (int)(li % cd.count[0]);
-      const long long t = li / cd.count[0];
-      p[1] = (int)(t % cd.count[1]);
-      p[2] = (int)(t / cd.count[1]);
+      const int c = row / D::NF, k = row - c * D::NF;
+      const int i_n = k % (R + 1), tt = k / (R + 1);
+      const int i_1 = tt % R, i_2 = tt / R;
+      const int nc = c == 0 ? q.nel[0] : (c == 1 ? q.nel[1] : q.nel[2]);
+      const int ecc = c == 0 ? ex : (c == 1 ? ey : ez);
+      if (i_n == R && ecc != nc - 1) continue;
+      const long long se = c == 0 ? 1 : (c == 1 ? (long long)q.nel[0] : (long long)q.nel[0] * q.nel[1]);
+      v = yr[(long long)row * E + e];
+      if (i_n == 0 && ecc > 0) v = yr[(long long)(row + R) * E + (e - se)] + v;
       const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-      int ec[3], ii[3];
-      for (int a = 0; a < 3; ++a) {
-        ec[a] = p[a] / R;
-        ii[a] = p[a] % R;
+      int p[3];
+      p[0] = p[1] = p[2] = 0;
+      // lattice position of this row (nodal along c, edge along a1, a2)
+      const int pc = R * ecc + i_n, p1 = R * ec[a1] + i_1, p2 = R * ec[a2] + i_2;
+      if (c == 0) {
+        p[0] = pc;
+        p[1] = p1;
+        p[2] = p2;
+      } else if (c == 1) {
+        p[1] = pc;
+        p[2] = p1;
+        p[0] = p2;
+      } else {
+        p[2] = pc;
+        p[0] = p1;
+        p[1] = p2;
       }
-      const int rbase = c * D::NF;
-      const int tang = R + 1;  // stride of the first tangential axis in the local order
-      auto at = [&](int enorm, int inorm) {
-        int e3[3] = {ec[0], ec[1], ec[2]};
-        e3[c] = enorm;
-        const long long el = e3[0] + (long long)q.nel[0] * (e3[1] + (long long)q.nel[1] * e3[2]);
-        const int row = rbase + inorm + tang * (ii[a1] + R * ii[a2]);
-        return yr[(long long)row * q.el_rows + el];
-      };
-      float s = 0.f;
-      if (ii[c] == 0 && ec[c] > 0) s = at(ec[c] - 1, R);
-      if (ec[c] < q.nel[c]) s = s + at(ec[c], ii[c]);
-      v = s;
+      const DevComp& cd = q.s.c[c];
+      g = cd.offset + p[0] + (long long)cd.count[0] * (p[1] + (long long)cd.count[1] * p[2]);
     }
     y[off + g] = v;
     if constexpr (MR) acc += (double)x[off + g] * (double)v;
