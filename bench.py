@@ -265,7 +265,7 @@ def hodge32_solves(gym, ctx, steps, rtol):
     return res
 
 
-def serving(gym, nreq, seed, max_slots, qps=None, budget=64 << 30):
+def serving(gym, nreq, seed, max_slots, qps=None, budget=32 << 30, precond=None):
     """Run `nreq` mixed-Poisson requests (N ~ U{8..48}, r ~ U{1,2,3}, seeded
     N(0,1) right-hand sides) through the serving loop.  qps=None submits
     everything at t = 0; otherwise arrivals are a Poisson process."""
@@ -273,7 +273,9 @@ def serving(gym, nreq, seed, max_slots, qps=None, budget=64 << 30):
     rng = np.random.default_rng(seed)
     reqs = [(int(rng.integers(8, 49)), int(rng.integers(1, 4)), 1000 + k) for k in range(nreq)]
     gaps = rng.exponential(1.0 / qps, nreq) if qps else np.zeros(nreq)
-    o = gym.ServeOpts(device=0, mem_budget=budget, max_slots=max_slots, rtol=1e-8, maxit=100000)
+    if precond is None:
+        precond = gym.GYM_PRECOND_SCHUR
+    o = gym.ServeOpts(device=0, mem_budget=budget, max_slots=max_slots, rtol=1e-8, maxit=100000, precond=precond)
     srv = gym.gym_serve_start(o)
     t0 = time.perf_counter()
     due = t0 + np.cumsum(gaps)
@@ -300,7 +302,10 @@ def serving(gym, nreq, seed, max_slots, qps=None, budget=64 << 30):
     lat = np.array([r.latency_s for r in done.values()])
     dof_it = sum(r.ndofs * r.iters for r in done.values())
     bad = sum(1 for r in done.values() if r.status != 0)
+    its = np.array([r.iters for r in done.values()])
     return {"requests": nreq, "max_slots": max_slots, "qps": qps, "solves_per_s": nreq / wall,
+            "precond": {gym.GYM_PRECOND_SCHUR: "block (Schur)", gym.GYM_PRECOND_JACOBI: "Jacobi"}[precond],
+            "median_iters": float(np.median(its)), "max_iters": int(its.max()),
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "gdof_s": dof_it / wall / 1e9, "wall_s": wall, "not_converged": bad,
             "mean_ndofs": float(np.mean([r.ndofs for r in done.values()]))}
@@ -312,11 +317,17 @@ def profile_workload(gym, ctx, which, applies):
     applies of the workload per contraction precision, no timing of its own."""
     import torch
     dev = torch.device("cuda:0")
-    src = torch.empty(32 << 20, dtype=torch.float64, device=dev).normal_()
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    del src, dst
+    # calibration: 256 MiB and 2 GiB moved by a blit copy and by an
+    # elementwise kernel (plain vector loads and stores, like the operator's)
+    for words in (32 << 20, 256 << 20):
+        src = torch.empty(words, dtype=torch.float64, device=dev).normal_()
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"profile-workload: calibration copies of {words * 8} bytes done")
+        del src, dst
     if which == "poisson_r4_64cube":
         N, r, perturb, nrhs, prob = 64, 4, 0.0, 1, gym.GYM_MIXED_POISSON
         precs = (("f64", gym.GYM_F64), ("f32", gym.GYM_F32), ("bf16", gym.GYM_BF16))
@@ -476,7 +487,8 @@ def cfl_rate(gym, ctx, N):
 # unchanged since the counters were taken.
 KERNEL_SOURCES = ("paper_2301_01753_amd/csrc/op_kernel.hpp", "paper_2301_01753_amd/csrc/tile.hpp",
                   "paper_2301_01753_amd/csrc/curved.hpp", "paper_2301_01753_amd/csrc/minres_step.hpp",
-                  "paper_2301_01753_amd/csrc/op_hodge.hip", "paper_2301_01753_amd/csrc/kernels.hpp")
+                  "paper_2301_01753_amd/csrc/op_hodge.hip", "paper_2301_01753_amd/csrc/kernels.hpp",
+                  "paper_2301_01753_amd/csrc/gen/gen_tables.cpp", "paper_2301_01753_amd/csrc/tables.cpp")
 TRAFFIC_FILE = "profiles/op_kernel_hodge_r3_96cube_perturbed_traffic.txt"
 
 
@@ -526,7 +538,7 @@ def main():
                     help="only the SPAI-OP builds (degree 1 and 2) and stepping, for a kernel trace")
     ap.add_argument("--profile-maxwell", action="store_true",
                     help="profiling runs: only the lumped time-stepping rates (Yee 128^3, degree 2 on 32^3), no JSON")
-    ap.add_argument("--serve-requests", type=int, default=24,
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests in the serving sample (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -656,16 +668,19 @@ def main():
         log("32^3 degree-2 Hodge solves ...")
         extras["hodge_r2_32cube"] = hodge32_solves(gym, ctx, 4, 1e-10)
         if args.serve_requests > 0:
-            log("serving (batched) ...")
-            batched = serving(gym, args.serve_requests, 7, max_slots=32)
+            nreq = args.serve_requests
+            log(f"serving {nreq} requests (batched) ...")
+            batched = serving(gym, nreq, 7, max_slots=32)
             log("serving (one at a time) ...")
-            single = serving(gym, args.serve_requests, 7, max_slots=1)
-            log("serving (Poisson arrivals at half the batched rate) ...")
-            arrivals = serving(gym, args.serve_requests, 7, max_slots=32, qps=0.5 * batched["solves_per_s"])
+            single = serving(gym, nreq, 7, max_slots=1)
+            sweep = {}
+            for f in (0.5, 1.0, 2.0):
+                log(f"serving (Poisson arrivals at {f} x the batched rate) ...")
+                sweep[f"{f}x"] = serving(gym, nreq, 7, max_slots=32, qps=f * batched["solves_per_s"])
             extras["serving"] = {
-                "workload": "mixed Poisson, N ~ U{8..48}^3 hex, degree ~ U{1,2,3}, N(0,1) rhs (seeded), "
-                            "rel. residual 1e-8",
-                "batched": batched, "one_at_a_time": single, "poisson_arrivals": arrivals,
+                "workload": f"{nreq} mixed Poisson solves, N ~ U{{8..48}}^3 hex, degree ~ U{{1,2,3}}, "
+                            "N(0,1) rhs (seeded), rel. residual 1e-8, block preconditioner",
+                "batched": batched, "one_at_a_time": single, "poisson_arrivals": sweep,
                 "speedup_batched_vs_one_at_a_time": batched["solves_per_s"] / single["solves_per_s"],
             }
         log("generalized Yee time stepping ...")

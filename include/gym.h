@@ -414,6 +414,10 @@ typedef struct gym_serve_opts {
   int max_slots;         /* requests resident at once                        */
   double rtol;           /* per-request relative residual target             */
   int maxit;             /* per-request iteration cap                        */
+  int precond;           /* GYM_PRECOND_JACOBI (0) or GYM_PRECOND_SCHUR; the
+                            latter serves GYM_MIXED_POISSON requests only
+                            (others are refused at submit) and is set up
+                            once per operator                              */
 } gym_serve_opts;
 
 typedef struct gym_request {
@@ -441,7 +445,12 @@ typedef struct gym_result {
  * requests while fewer than max_slots are active and their device memory
  * (vectors + operator) fits mem_budget, runs one batched MINRES step of all
  * active requests per turn, and retires converged ones (rel. residual <=
- * rtol, true FP64 residual) so that queued requests enter the mix. */
+ * rtol, true FP64 residual) so that queued requests enter the mix.
+ * mem_budget bytes are reserved on the device here, as the pool that holds
+ * every request's vectors (GYM_E_OOM if they cannot be); operators are set
+ * up outside the pool on first use of a (problem, nel, degree), count
+ * against the same budget and stay resident; one that no active request
+ * uses is freed only when an admission needs its room. */
 int gym_serve_start(const gym_serve_opts* opts, gym_server** out);
 /* Enqueue a request; returns its id.  Errors: GYM_E_OOM if one request
  * alone exceeds the memory budget. */

@@ -42,6 +42,32 @@ def _compile(src, obj):
     return obj
 
 
+def gen_tables(objdir):
+    """Build step: compile csrc/gen/gen_tables.cpp with the library's own
+    table code and let it write csrc/gen/tables_const.hpp (the contraction
+    tables as compile-time constants).  The header is rewritten only when its
+    text changes, so incremental builds keep their objects."""
+    exe = os.path.join(objdir, "gen_tables")
+    cmd = [hipcc()] + COMMON + [os.path.join(CSRC, "gen", "gen_tables.cpp"), os.path.join(CSRC, "tables.cpp"),
+                                "-o", exe]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"table generator build failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    out = os.path.join(CSRC, "gen", "tables_const.hpp")
+    tmp = out + ".new"
+    res = subprocess.run([exe, tmp], capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"table generator failed\n{res.stdout}\n{res.stderr}")
+    with open(tmp) as f:
+        new = f.read()
+    old = open(out).read() if os.path.exists(out) else None
+    if new != old:
+        os.replace(tmp, out)
+    else:
+        os.remove(tmp)
+    return out
+
+
 def _stale(src, obj, headers):
     if not os.path.exists(obj):
         return True
@@ -55,10 +81,12 @@ def build(verbose=True, jobs=None, incremental=False):
     os.makedirs(LIBDIR, exist_ok=True)
     objdir = os.path.join(LIBDIR, "obj")
     os.makedirs(objdir, exist_ok=True)
+    gen_tables(objdir)
     srcs = sources()
     objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in srcs]
     if incremental:
         headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))]
+        headers.append(os.path.join(CSRC, "gen", "tables_const.hpp"))
         headers.append(os.path.join(HERE, "..", "include", "gym.h"))
         todo = [(s, o) for s, o in zip(srcs, objs) if _stale(s, o, headers)]
     else:

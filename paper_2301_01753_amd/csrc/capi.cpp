@@ -537,9 +537,10 @@ int ensure_partials(std::vector<void*>& pool, MinresWork<TV>& w, int npa, int nb
 // host reads the states every check_every steps; on exit x is complete (a
 // step still pending at the iteration cap is finished by minres_finish).
 // npa = workgroups per rhs of the fused apply.
-// A non-diagonal preconditioner: out = M^-1 in for all right-hand sides.
+// A non-diagonal preconditioner: out = M^-1 in for all right-hand sides,
+// leaving those whose Krylov state in gate (if not null) has converged.
 template <typename TV>
-using PrecFn = std::function<int(const TV*, TV*)>;
+using PrecFn = std::function<int(const TV*, TV*, const MinresState*)>;
 
 template <typename TV, typename Apply>
 int run_minres(Apply&& apply, long long n, int nrhs, int nb, int npa, const TV* b, TV* x, const double* dinv,
@@ -550,7 +551,7 @@ int run_minres(Apply&& apply, long long n, int nrhs, int nb, int npa, const TV* 
   MinresVecs<TV> V{b, x, wk.r1, wk.r2, wk.z, wk.y, wk.w, wk.w1, wk.w2};
   if (ext) {
     minres_launch_init_vecs<TV>(V, n, nrhs, nb, s);
-    if (int rc = (*ext)(b, wk.z)) return rc;
+    if (int rc = (*ext)(b, wk.z, nullptr)) return rc;
     minres_launch_dot2<TV>(b, wk.z, nullptr, n, nrhs, nb, wk.pb[0], nullptr, s);
     minres_launch_init_state<TV>(V, n, nrhs, nb, wk.pb[0], wk.st, tol, s);
   } else {
@@ -572,8 +573,8 @@ int run_minres(Apply&& apply, long long n, int nrhs, int nb, int npa, const TV* 
     if (ext) {
       // z_{k+1} = M^-1 y over zp (read by step2 already), and the partial
       // sums step2 leaves to us: y . z_{k+1}, z_{k+1} . r2
-      if (int rc = (*ext)(wk.y, wk.zp)) return rc;
-      minres_launch_dot2<TV>(wk.y, wk.zp, wk.r2, n, nrhs, nb, io.pb, io.pc, s);
+      if (int rc = (*ext)(wk.y, wk.zp, cur)) return rc;
+      minres_launch_dot2<TV>(wk.y, wk.zp, wk.r2, n, nrhs, nb, io.pb, io.pc, s, cur);
     }
     par ^= 1;
     if (pending) {  // the newest w was written over the oldest
@@ -696,9 +697,7 @@ struct OpWork {
   std::vector<void*> pool;
 };
 
-// The block preconditioner of a mixed Poisson operator on an affine box,
-// set up on first use and kept with the operator; work vectors for nrhs.
-static int ensure_schur(gym_op* op, int nrhs, SchurPrec** out) {
+int ensure_schur(gym_op* op, int nrhs, SchurPrec** out) {
   if (!op->schur) {
     SchurPrec* P = new SchurPrec;
     if (int rc = schur_build(op, P)) {
@@ -1378,12 +1377,14 @@ int gym_solve(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const double*
   SchurPrec* schur = nullptr;
   if (opts.precond == GYM_PRECOND_SCHUR)
     if (int rc = ensure_schur(op, nrhs, &schur)) return rc;
-  const PrecFn<double> ext64 = [&](const double* in, double* out) {
-    return launch_schur_apply<double>(*schur, in, out, nrhs, w->nb, s) ? fail(GYM_E_HIP, "preconditioner launch")
-                                                                      : 0;
+  const PrecFn<double> ext64 = [&](const double* in, double* out, const MinresState* gate) {
+    return launch_schur_apply<double>(*schur, in, out, nrhs, w->nb, s, gate)
+               ? fail(GYM_E_HIP, "preconditioner launch")
+               : 0;
   };
-  const PrecFn<float> ext32 = [&](const float* in, float* out) {
-    return launch_schur_apply<float>(*schur, in, out, nrhs, w->nb, s) ? fail(GYM_E_HIP, "preconditioner launch") : 0;
+  const PrecFn<float> ext32 = [&](const float* in, float* out, const MinresState* gate) {
+    return launch_schur_apply<float>(*schur, in, out, nrhs, w->nb, s, gate) ? fail(GYM_E_HIP, "preconditioner launch")
+                                                                            : 0;
   };
   const long long n = w->n;
   const double* dinv = op->d_prec;

@@ -45,50 +45,49 @@ struct QGeom {
 };
 
 // x: in [NX][NY][NZ] lattice -> out [QX][NY][NZ]; line l = (element, row)
+// Gauss-point values of elements outside the mesh are not masked here: the z
+// stage (cz_scalar, cz_vector) replaces every column of such an element by
+// zeros, so whatever these stages computed for it is never used.
 template <class C, int TM, typename TC>
-__device__ __forceinline__ void cfwd_x(const TC* __restrict__ in, TC* __restrict__ out, int l, const ElemRange& er) {
+__device__ __forceinline__ void cfwd_x(const TC* __restrict__ in, TC* __restrict__ out, int l) {
   constexpr int NX = C::nx(TM), R = C::R, Q = C::Q;
   constexpr bool N = TM & 1;
   constexpr int n = N ? R + 1 : R;
-  const TabSet<TC>& T = stage_tabs<TC>(R);
   const int e = l % C::EX, rest = l / C::EX;
   const TC* s = in + rest * NX + R * e;
   TC v[n];
 #pragma unroll
   for (int i = 0; i < n; ++i) v[i] = s[i];
-  const bool ok = e >= er.xlo && e < er.xhi;
   TC* o = out + rest * C::QX + e;
 #pragma unroll
   for (int t = 0; t < Q; ++t) {
     TC acc = 0;
 #pragma unroll
-    for (int i = 0; i < n; ++i) acc += tab<TC, N, false>(T, t, i) * v[i];
-    o[xq<C>(0, t)] = ok ? acc : TC(0);
+    for (int i = 0; i < n; ++i) acc += ctab<TC, R, N, false>(t, i) * v[i];
+    o[xq<C>(0, t)] = acc;
   }
 }
 
 // y: in [QX][NY][NZ] -> out [QX][QY][NZ]; line l = (qx, element, z row), qx
 // the stored x index (xq)
 template <class C, int TM, typename TC>
-__device__ __forceinline__ void cfwd_y(const TC* __restrict__ in, TC* __restrict__ out, int l, const ElemRange& er) {
+__device__ __forceinline__ void cfwd_y(const TC* __restrict__ in, TC* __restrict__ out, int l) {
   constexpr int NY = C::ny(TM), R = C::R, Q = C::Q, QX = C::QX;
   constexpr bool N = TM & 2;
   constexpr int n = N ? R + 1 : R;
-  const TabSet<TC>& T = stage_tabs<TC>(R);
   const int qx = l % QX, r2 = l / QX;
   const int e = r2 % C::EY, k = r2 / C::EY;
   const TC* s = in + qx + QX * (R * e + NY * k);
   TC v[n];
 #pragma unroll
   for (int i = 0; i < n; ++i) v[i] = s[QX * i];
-  const bool ok = e >= er.ylo && e < er.yhi;
   TC* o = out + qx + QX * (Q * e + C::QY * k);
 #pragma unroll
   for (int t = 0; t < Q; ++t) {
     TC acc = 0;
 #pragma unroll
-    for (int i = 0; i < n; ++i) acc += tab<TC, N, false>(T, t, i) * v[i];
-    o[QX * t] = ok ? acc : TC(0);
+    for (int i = 0; i < n; ++i) acc += ctab<TC, R, N, false>(t, i) * v[i];
+    o[QX * t] = acc;
   }
 }
 
@@ -98,7 +97,6 @@ __device__ __forceinline__ void cz_fwd(const TC* __restrict__ B, int p, TC (&u)[
   constexpr int P = C::QX * C::QY, R = C::R, Q = C::Q;
   constexpr bool N = TM & 4;
   constexpr int n = N ? R + 1 : R;
-  const TabSet<TC>& T = stage_tabs<TC>(R);
   TC v[n];
 #pragma unroll
   for (int i = 0; i < n; ++i) v[i] = B[p + P * i];
@@ -106,7 +104,7 @@ __device__ __forceinline__ void cz_fwd(const TC* __restrict__ B, int p, TC (&u)[
   for (int t = 0; t < Q; ++t) {
     TC acc = 0;
 #pragma unroll
-    for (int i = 0; i < n; ++i) acc += tab<TC, N, false>(T, t, i) * v[i];
+    for (int i = 0; i < n; ++i) acc += ctab<TC, R, N, false>(t, i) * v[i];
     u[t] = acc;
   }
 }
@@ -117,12 +115,11 @@ __device__ __forceinline__ void cz_bwd(TC* __restrict__ B, int p, const TC (&u)[
   constexpr int P = C::QX * C::QY, R = C::R, Q = C::Q;
   constexpr bool N = TM & 4;
   constexpr int NZ = C::nz(TM);
-  const TabSet<TC>& T = stage_tabs<TC>(R);
 #pragma unroll
   for (int k = 0; k < NZ; ++k) {
     TC acc = 0;
 #pragma unroll
-    for (int t = 0; t < Q; ++t) acc += tab<TC, N, true>(T, t, k) * u[t];
+    for (int t = 0; t < Q; ++t) acc += ctab<TC, R, N, true>(t, k) * u[t];
     B[p + P * k] = acc;
   }
 }
@@ -192,7 +189,6 @@ template <class C, int TM, typename TC>
 __device__ __forceinline__ void cbwd_y(const TC* __restrict__ in, TC* __restrict__ out, int l) {
   constexpr int NY = C::ny(TM), R = C::R, Q = C::Q, QX = C::QX;
   constexpr bool N = TM & 2;
-  const TabSet<TC>& T = stage_tabs<TC>(R);
   const int qx = l % QX, r2 = l / QX;
   const int e = r2 % C::EY, k = r2 / C::EY;
   const TC* s = in + qx + QX * (Q * e + C::QY * k);
@@ -204,19 +200,19 @@ __device__ __forceinline__ void cbwd_y(const TC* __restrict__ in, TC* __restrict
     TC lower = 0;  // the lower element's contribution to the shared position R e
     if (e > 0) {
 #pragma unroll
-      for (int t = 0; t < Q; ++t) lower += tab<TC, N, true>(T, t, R) * s[QX * (t - Q)];
+      for (int t = 0; t < Q; ++t) lower += ctab<TC, R, N, true>(t, R) * s[QX * (t - Q)];
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       TC acc = 0;
 #pragma unroll
-      for (int t = 0; t < Q; ++t) acc += tab<TC, N, true>(T, t, i) * c[t];
+      for (int t = 0; t < Q; ++t) acc += ctab<TC, R, N, true>(t, i) * c[t];
       o[QX * i] = i == 0 ? lower + acc : acc;
     }
     if (e == C::EY - 1) {
       TC acc = 0;
 #pragma unroll
-      for (int t = 0; t < Q; ++t) acc += tab<TC, N, true>(T, t, R) * c[t];
+      for (int t = 0; t < Q; ++t) acc += ctab<TC, R, N, true>(t, R) * c[t];
       o[QX * R] = acc;
     }
   } else {
@@ -224,7 +220,7 @@ __device__ __forceinline__ void cbwd_y(const TC* __restrict__ in, TC* __restrict
     for (int i = 0; i < R; ++i) {
       TC acc = 0;
 #pragma unroll
-      for (int t = 0; t < Q; ++t) acc += tab<TC, N, true>(T, t, i) * c[t];
+      for (int t = 0; t < Q; ++t) acc += ctab<TC, R, N, true>(t, i) * c[t];
       o[QX * i] = acc;
     }
   }
@@ -236,7 +232,6 @@ template <class C, int TM, bool ADD, typename TC>
 __device__ __forceinline__ void cbwd_x(const TC* __restrict__ in, TC* __restrict__ out, int l) {
   constexpr int NX = C::nx(TM), R = C::R, Q = C::Q;
   constexpr bool N = TM & 1;
-  const TabSet<TC>& T = stage_tabs<TC>(R);
   const int e = l % C::EX, rest = l / C::EX;
   const TC* s = in + rest * C::QX + e;
   TC c[Q];
@@ -251,19 +246,19 @@ __device__ __forceinline__ void cbwd_x(const TC* __restrict__ in, TC* __restrict
     TC lower = 0;
     if (e > 0) {
 #pragma unroll
-      for (int t = 0; t < Q; ++t) lower += tab<TC, N, true>(T, t, R) * s[xq<C>(0, t) - 1];
+      for (int t = 0; t < Q; ++t) lower += ctab<TC, R, N, true>(t, R) * s[xq<C>(0, t) - 1];
     }
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       TC acc = 0;
 #pragma unroll
-      for (int t = 0; t < Q; ++t) acc += tab<TC, N, true>(T, t, i) * c[t];
+      for (int t = 0; t < Q; ++t) acc += ctab<TC, R, N, true>(t, i) * c[t];
       put(i, i == 0 ? lower + acc : acc);
     }
     if (e == C::EX - 1) {
       TC acc = 0;
 #pragma unroll
-      for (int t = 0; t < Q; ++t) acc += tab<TC, N, true>(T, t, R) * c[t];
+      for (int t = 0; t < Q; ++t) acc += ctab<TC, R, N, true>(t, R) * c[t];
       put(R, acc);
     }
   } else {
@@ -271,17 +266,27 @@ __device__ __forceinline__ void cbwd_x(const TC* __restrict__ in, TC* __restrict
     for (int i = 0; i < R; ++i) {
       TC acc = 0;
 #pragma unroll
-      for (int t = 0; t < Q; ++t) acc += tab<TC, N, true>(T, t, i) * c[t];
+      for (int t = 0; t < Q; ++t) acc += ctab<TC, R, N, true>(t, i) * c[t];
       put(i, acc);
     }
   }
+}
+
+// The thread index, passed through an empty asm: the loop predicates of the
+// stages (thread index < item count) are then evaluated where the stage runs,
+// instead of being hoisted out of the layer loop, where dozens of them would
+// stay live as 64-bit lane masks and spill to VGPR lanes.
+__device__ __forceinline__ int stage_tid() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
 }
 
 // One stage over up to three components: items [0, n0) go to f0, then n1
 // items to f1, n2 to f2, spread over the workgroup.
 template <int NT, int N0, int N1, int N2, class F0, class F1, class F2>
 __device__ __forceinline__ void stage3(F0&& f0, F1&& f1, F2&& f2) {
-  for (int idx = threadIdx.x; idx < N0 + N1 + N2; idx += NT) {
+  for (int idx = stage_tid(); idx < N0 + N1 + N2; idx += NT) {
     if (idx < N0) f0(idx);
     else if (N1 > 0 && idx < N0 + N1) f1(idx - N0);
     else if (N2 > 0) f2(idx - N0 - N1);

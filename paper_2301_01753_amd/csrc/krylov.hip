@@ -111,11 +111,14 @@ __global__ void __launch_bounds__(kBT) minres_init_vecs(MinresVecs<TV> v, long l
   }
 }
 
-// per block: pb = y . z, pc = z . r (r may be null)
+// per block: pb = y . z, pc = z . r (r may be null); nothing for a
+// right-hand side whose state in gate (if given) has converged
 template <typename TV>
 __global__ void __launch_bounds__(kBT) minres_dot2(const TV* __restrict__ y, const TV* __restrict__ z,
-                                                   const TV* __restrict__ r, long long n, double* pb, double* pc) {
+                                                   const TV* __restrict__ r, long long n, double* pb, double* pc,
+                                                   const MinresState* gate) {
   __shared__ double sh[2 * kBT];
+  if (gate && gate[blockIdx.y].done) return;
   const long long off = (long long)blockIdx.y * n;
   double a = 0.0, c = 0.0;
   for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT) {
@@ -514,8 +517,8 @@ void minres_launch_init_vecs(const MinresVecs<TV>& v, long long n, int nrhs, int
 
 template <typename TV>
 void minres_launch_dot2(const TV* y, const TV* z, const TV* r, long long n, int nrhs, int nb, double* pb,
-                        double* pc, hipStream_t s) {
-  GYM_LAUNCH(minres_dot2<TV>, dim3(nb, nrhs), s, y, z, r, n, pb, pc);
+                        double* pc, hipStream_t s, const MinresState* gate) {
+  GYM_LAUNCH(minres_dot2<TV>, dim3(nb, nrhs), s, y, z, r, n, pb, pc, gate);
 }
 
 template <typename TV>
@@ -592,9 +595,9 @@ template void minres_launch_init<float>(const MinresVecs<float>&, const double*,
 template void minres_launch_init_vecs<double>(const MinresVecs<double>&, long long, int, int, hipStream_t);
 template void minres_launch_init_vecs<float>(const MinresVecs<float>&, long long, int, int, hipStream_t);
 template void minres_launch_dot2<double>(const double*, const double*, const double*, long long, int, int, double*,
-                                         double*, hipStream_t);
+                                         double*, hipStream_t, const MinresState*);
 template void minres_launch_dot2<float>(const float*, const float*, const float*, long long, int, int, double*,
-                                        double*, hipStream_t);
+                                        double*, hipStream_t, const MinresState*);
 template void minres_launch_init_state<double>(const MinresVecs<double>&, long long, int, int, const double*,
                                                MinresState*, double, hipStream_t);
 template void minres_launch_init_state<float>(const MinresVecs<float>&, long long, int, int, const double*,

@@ -66,9 +66,10 @@ void minres_launch_step2(const MrVecs<TV>& v, const double* dinv, long long n, i
 // minres_step2's (nb blocks per rhs).
 template <typename TV>
 void minres_launch_init_vecs(const MinresVecs<TV>& v, long long n, int nrhs, int nb, hipStream_t s);
+// gate (optional): leave right-hand sides whose state there has converged.
 template <typename TV>
 void minres_launch_dot2(const TV* y, const TV* z, const TV* r, long long n, int nrhs, int nb, double* pb,
-                        double* pc, hipStream_t s);
+                        double* pc, hipStream_t s, const MinresState* gate = nullptr);
 // beta_1 from the partials of b . M^-1 b (as minres_launch_init's second half)
 template <typename TV>
 void minres_launch_init_state(const MinresVecs<TV>& v, long long n, int nrhs, int nb, const double* part,

@@ -12,35 +12,35 @@ struct MinresState {
   int pad;
 };
 
-// Sums over a workgroup of NT threads of N values per thread, returned in
-// every thread: a tree in LDS over all N values at once (one barrier per
-// level).  When NT is not a power of two the threads above the largest power
-// of two P are first folded onto the first NT - P.  The order is fixed, so
-// results are reproducible.  sh holds N * NT doubles.
+// Sums over a workgroup of NT threads (a multiple of 64) of N values per
+// thread, returned in every thread: a butterfly across the 64 lanes of each
+// wavefront (cross-lane moves, no LDS, no barrier), then one LDS exchange of
+// the per-wavefront sums, which every thread adds up in wavefront order.  The
+// order is fixed, so results are reproducible.  sh holds N * NT / 64 doubles
+// (any buffer of N * NT doubles is large enough).
 template <int NT, int N>
 __device__ __forceinline__ void wg_sums(double (&v)[N], double* sh) {
-  constexpr int P = NT >= 1024 ? 1024 : NT >= 512 ? 512 : NT >= 256 ? 256 : NT >= 128 ? 128 : 64;
-  static_assert(NT <= 2 * P && NT >= 64, "workgroup size");
+  static_assert(NT % 64 == 0 && NT >= 64 && NT <= 1024, "workgroup size");
+  constexpr int NW = NT / 64;
   const int t = threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < N; ++k) sh[k * NT + t] = v[k];
-  __syncthreads();
-  if constexpr (NT > P) {
-    if (t < NT - P)
+  for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
-      for (int k = 0; k < N; ++k) sh[k * NT + t] += sh[k * NT + t + P];
+    for (int k = 0; k < N; ++k) v[k] += __shfl_xor(v[k], off, 64);
+  if constexpr (NW > 1) {
+    if ((t & 63) == 0)
+#pragma unroll
+      for (int k = 0; k < N; ++k) sh[k * NW + (t >> 6)] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a = sh[k * NW];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) a += sh[k * NW + w];
+      v[k] = a;
+    }
     __syncthreads();
   }
-#pragma unroll
-  for (int s = P / 2; s > 0; s >>= 1) {
-    if (t < s)
-#pragma unroll
-      for (int k = 0; k < N; ++k) sh[k * NT + t] += sh[k * NT + t + s];
-    __syncthreads();
-  }
-#pragma unroll
-  for (int k = 0; k < N; ++k) v[k] = sh[k * NT];
-  __syncthreads();
 }
 
 // Lanczos/Givens scalar recurrence of one MINRES step (Paige & Saunders),

@@ -186,15 +186,15 @@ struct Work {
 template <class C, int TM, int KIND, bool ADD, typename TC>
 __device__ __forceinline__ void cmass_scalar(const TC* in, TC* out, TC sign, const Work<TC>& w) {
   constexpr int NY = C::ny(TM), NZ = C::nz(TM);
-  for (int l = threadIdx.x; l < C::EX * NY * NZ; l += C::NT) cfwd_x<C, TM>(in, w.WA[0], l, w.er);
+  for (int l = stage_tid(); l < C::EX * NY * NZ; l += C::NT) cfwd_x<C, TM>(in, w.WA[0], l);
   __syncthreads();
-  for (int l = threadIdx.x; l < C::QX * C::EY * NZ; l += C::NT) cfwd_y<C, TM>(w.WA[0], w.WB[0], l, w.er);
+  for (int l = stage_tid(); l < C::QX * C::EY * NZ; l += C::NT) cfwd_y<C, TM>(w.WA[0], w.WB[0], l);
   __syncthreads();
-  for (int p = threadIdx.x; p < C::QX * C::QY; p += C::NT) cz_scalar<C, TM, KIND>(w.WB[0], p, w.er, w.g, sign);
+  for (int p = stage_tid(); p < C::QX * C::QY; p += C::NT) cz_scalar<C, TM, KIND>(w.WB[0], p, w.er, w.g, sign);
   __syncthreads();
-  for (int l = threadIdx.x; l < C::QX * C::EY * NZ; l += C::NT) cbwd_y<C, TM>(w.WB[0], w.WA[0], l);
+  for (int l = stage_tid(); l < C::QX * C::EY * NZ; l += C::NT) cbwd_y<C, TM>(w.WB[0], w.WA[0], l);
   __syncthreads();
-  for (int l = threadIdx.x; l < C::EX * NY * NZ; l += C::NT) cbwd_x<C, TM, ADD>(w.WA[0], out, l);
+  for (int l = stage_tid(); l < C::EX * NY * NZ; l += C::NT) cbwd_x<C, TM, ADD>(w.WA[0], out, l);
   __syncthreads();
 }
 
@@ -205,15 +205,15 @@ __device__ __forceinline__ void cmass_vector(TC* const in[3], TC* const out[3], 
   constexpr int X0 = C::EX * C::ny(T0) * C::nz(T0), X1 = C::EX * C::ny(T1) * C::nz(T1),
                 X2 = C::EX * C::ny(T2) * C::nz(T2);
   constexpr int Y0 = C::QX * C::EY * C::nz(T0), Y1 = C::QX * C::EY * C::nz(T1), Y2 = C::QX * C::EY * C::nz(T2);
-  stage3<NT, X0, X1, X2>([&](int l) { cfwd_x<C, T0>(in[0], w.WA[0], l, w.er); },
-                         [&](int l) { cfwd_x<C, T1>(in[1], w.WA[1], l, w.er); },
-                         [&](int l) { cfwd_x<C, T2>(in[2], w.WA[2], l, w.er); });
+  stage3<NT, X0, X1, X2>([&](int l) { cfwd_x<C, T0>(in[0], w.WA[0], l); },
+                         [&](int l) { cfwd_x<C, T1>(in[1], w.WA[1], l); },
+                         [&](int l) { cfwd_x<C, T2>(in[2], w.WA[2], l); });
   __syncthreads();
-  stage3<NT, Y0, Y1, Y2>([&](int l) { cfwd_y<C, T0>(w.WA[0], w.WB[0], l, w.er); },
-                         [&](int l) { cfwd_y<C, T1>(w.WA[1], w.WB[1], l, w.er); },
-                         [&](int l) { cfwd_y<C, T2>(w.WA[2], w.WB[2], l, w.er); });
+  stage3<NT, Y0, Y1, Y2>([&](int l) { cfwd_y<C, T0>(w.WA[0], w.WB[0], l); },
+                         [&](int l) { cfwd_y<C, T1>(w.WA[1], w.WB[1], l); },
+                         [&](int l) { cfwd_y<C, T2>(w.WA[2], w.WB[2], l); });
   __syncthreads();
-  for (int p = threadIdx.x; p < C::QX * C::QY; p += NT) cz_vector<C, KIND, T0, T1, T2>(w.WB, p, w.er, w.g, sign);
+  for (int p = stage_tid(); p < C::QX * C::QY; p += NT) cz_vector<C, KIND, T0, T1, T2>(w.WB, p, w.er, w.g, sign);
   __syncthreads();
   stage3<NT, Y0, Y1, Y2>([&](int l) { cbwd_y<C, T0>(w.WB[0], w.WA[0], l); },
                          [&](int l) { cbwd_y<C, T1>(w.WB[1], w.WA[1], l); },

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gym_internal.hpp"
+#include "minres_step.hpp"
 #include "schur.hpp"
 
 namespace gym {
@@ -33,13 +34,16 @@ constexpr int kGT = 256; // threads
 // out[line][i] = sum_l A[i][l] in[line][l] along axis AX of an m0 x m1 x m2
 // lattice (x fastest), A row-major m_a x m_a.  blockIdx.z: right-hand side.
 // A thread computes 4 lines x 4 outputs; lanes run along the outputs for the
-// x axis (contiguous in memory) and along the lines for y and z.
+// x axis (contiguous in memory) and along the lines for y and z.  Every
+// kernel here does nothing for a right-hand side whose Krylov state in `gate`
+// (if given) has converged.
 template <int AX, typename T>
 __global__ void __launch_bounds__(kGT) axis_gemm(const T* __restrict__ in, T* __restrict__ out,
                                                  const T* __restrict__ A, int m0, int m1, int m2, long long vin,
-                                                 long long vout) {
+                                                 long long vout, const MinresState* gate) {
   __shared__ T s_in[kTK][kTL + 4];
   __shared__ T sa[kTK][kTI + 4];
+  if (gate && gate[blockIdx.z].done) return;
   const int ma = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
   const long long nlines = (long long)m0 * m1 * m2 / ma;
   const long long stride = AX == 0 ? 1 : (AX == 1 ? (long long)m0 : (long long)m0 * m1);
@@ -112,7 +116,8 @@ __global__ void __launch_bounds__(kGT) axis_gemm(const T* __restrict__ in, T* __
 // y[i, j, k] *= scale / (lam0[i] + lam1[j] + lam2[k]) on the cell lattice
 template <typename T>
 __global__ void __launch_bounds__(256) lam_scale(T* __restrict__ y, const double* __restrict__ lam, int m0, int m1,
-                                                 int m2, double scale, long long vstride) {
+                                                 int m2, double scale, long long vstride, const MinresState* gate) {
+  if (gate && gate[blockIdx.y].done) return;
   const long long n = (long long)m0 * m1 * m2;
   y += (long long)blockIdx.y * vstride;
   for (long long g = (long long)blockIdx.x * 256 + threadIdx.x; g < n; g += (long long)gridDim.x * 256) {
@@ -126,7 +131,9 @@ __global__ void __launch_bounds__(256) lam_scale(T* __restrict__ y, const double
 // z = d .* y on the flux block
 template <typename T>
 __global__ void __launch_bounds__(256) diag_scale(const T* __restrict__ y, T* __restrict__ z,
-                                                  const double* __restrict__ d, long long n, long long vstride) {
+                                                  const double* __restrict__ d, long long n, long long vstride,
+                                                  const MinresState* gate) {
+  if (gate && gate[blockIdx.y].done) return;
   y += (long long)blockIdx.y * vstride;
   z += (long long)blockIdx.y * vstride;
   for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
@@ -135,16 +142,17 @@ __global__ void __launch_bounds__(256) diag_scale(const T* __restrict__ y, T* __
 
 template <int AX, typename T>
 void axis_launch(const T* in, long long vin, T* out, long long vout, const T* A, const int m[3], int nrhs,
-                 hipStream_t s) {
+                 const MinresState* gate, hipStream_t s) {
   const long long nlines = (long long)m[0] * m[1] * m[2] / m[AX];
   dim3 grid((unsigned)((nlines + kTL - 1) / kTL), (unsigned)((m[AX] + kTI - 1) / kTI), (unsigned)nrhs);
-  hipLaunchKernelGGL((axis_gemm<AX, T>), grid, dim3(kGT), 0, s, in, out, A, m[0], m[1], m[2], vin, vout);
+  hipLaunchKernelGGL((axis_gemm<AX, T>), grid, dim3(kGT), 0, s, in, out, A, m[0], m[1], m[2], vin, vout, gate);
 }
 
 }  // namespace
 
 template <typename T>
-int launch_schur_apply(const SchurPrec& P, const T* y, T* z, int nrhs, int nb, hipStream_t s) {
+int launch_schur_apply(const SchurPrec& P, const T* y, T* z, int nrhs, int nb, hipStream_t s,
+                       const MinresState* gate) {
   const T* const* F = P.template fwd<T>();
   const T* const* B = P.template bwd<T>();
   if (nrhs > P.work_nrhs) return -1;
@@ -152,22 +160,24 @@ int launch_schur_apply(const SchurPrec& P, const T* y, T* z, int nrhs, int nb, h
   T* w1 = P.template work_vec<T>(1);
   const long long n = P.ns + P.np, np = P.np;
   // flux block
-  hipLaunchKernelGGL((diag_scale<T>), dim3(nb, nrhs), dim3(256), 0, s, y, z, P.dsinv, P.ns, n);
+  hipLaunchKernelGGL((diag_scale<T>), dim3(nb, nrhs), dim3(256), 0, s, y, z, P.dsinv, P.ns, n, gate);
   // cell block: forward transforms, division, backward transforms
   const T* yp = y + P.ns;
   T* zp = z + P.ns;
-  axis_launch<0, T>(yp, n, w0, np, F[0], P.m, nrhs, s);
-  axis_launch<1, T>(w0, np, w1, np, F[1], P.m, nrhs, s);
-  axis_launch<2, T>(w1, np, w0, np, F[2], P.m, nrhs, s);
+  axis_launch<0, T>(yp, n, w0, np, F[0], P.m, nrhs, gate, s);
+  axis_launch<1, T>(w0, np, w1, np, F[1], P.m, nrhs, gate, s);
+  axis_launch<2, T>(w1, np, w0, np, F[2], P.m, nrhs, gate, s);
   hipLaunchKernelGGL((lam_scale<T>), dim3(nb, nrhs), dim3(256), 0, s, w0, P.lam, P.m[0], P.m[1], P.m[2], P.scale,
-                     np);
-  axis_launch<2, T>(w0, np, w1, np, B[2], P.m, nrhs, s);
-  axis_launch<1, T>(w1, np, w0, np, B[1], P.m, nrhs, s);
-  axis_launch<0, T>(w0, np, zp, n, B[0], P.m, nrhs, s);
+                     np, gate);
+  axis_launch<2, T>(w0, np, w1, np, B[2], P.m, nrhs, gate, s);
+  axis_launch<1, T>(w1, np, w0, np, B[1], P.m, nrhs, gate, s);
+  axis_launch<0, T>(w0, np, zp, n, B[0], P.m, nrhs, gate, s);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template int launch_schur_apply<double>(const SchurPrec&, const double*, double*, int, int, hipStream_t);
-template int launch_schur_apply<float>(const SchurPrec&, const float*, float*, int, int, hipStream_t);
+template int launch_schur_apply<double>(const SchurPrec&, const double*, double*, int, int, hipStream_t,
+                                        const MinresState*);
+template int launch_schur_apply<float>(const SchurPrec&, const float*, float*, int, int, hipStream_t,
+                                       const MinresState*);
 
 }  // namespace gym

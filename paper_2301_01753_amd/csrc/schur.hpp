@@ -4,6 +4,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "minres_step.hpp"
+
 struct gym_op;
 
 namespace gym {
@@ -47,8 +49,14 @@ int schur_build(const gym_op* op, SchurPrec* out);
 // allocates outside its hot loop).
 int schur_reserve(SchurPrec* P, int nrhs, size_t elem_bytes);
 void schur_free(SchurPrec* P);
+// The operator's preconditioner, set up on first use and kept with the
+// operator (freed with it), with work vectors for nrhs right-hand sides.
+int ensure_schur(gym_op* op, int nrhs, SchurPrec** out);
 // z = P^-1 y for nrhs vectors in the operator's layout [s; p] (stride ns + np).
+// gate (optional, one Krylov state per right-hand side): right-hand sides
+// whose state has converged are left untouched.
 template <typename T>
-int launch_schur_apply(const SchurPrec& P, const T* y, T* z, int nrhs, int nb, hipStream_t s);
+int launch_schur_apply(const SchurPrec& P, const T* y, T* z, int nrhs, int nb, hipStream_t s,
+                       const MinresState* gate = nullptr);
 
 }  // namespace gym

@@ -2,15 +2,21 @@
 //
 // A persistent host thread owns the device work.  Each turn it
 //   1. admits queued requests while slots and the memory budget allow
-//      (device buffers are allocated here, never inside a step), builds or
-//      reuses the request's operator and starts its MINRES state;
+//      (request vectors are carved from one pool allocated when the server
+//      starts, so admission and retirement never allocate or free device
+//      memory), builds or reuses the request's operator (set up once per
+//      problem, mesh and degree, then kept resident) and starts its MINRES
+//      state;
 //   2. runs ONE MINRES step for every active request: one ragged operator
 //      launch per (problem, degree) group carrying the first half of the
 //      fused step, then one ragged launch of the second half over all active
 //      requests;
 //   3. every few steps reads all Krylov states back, retires converged
 //      requests (true FP64 residual, optional copy of the solution) and
-//      frees their memory, so queued requests can enter the mix.
+//      returns their vectors to the pool, so queued requests can enter the
+//      mix.
+// With the block preconditioner (mixed Poisson) each request's step adds its
+// preconditioner launches after the batched second half.
 // Every request keeps its own blocks, partial sums and scalar state, so its
 // iterates are the same whether it runs alone or in any mix.
 #include <hip/hip_runtime.h>
@@ -30,6 +36,7 @@
 #include "gym_internal.hpp"
 #include "kernels.hpp"
 #include "krylov.hpp"
+#include "schur.hpp"
 
 using namespace gym;
 
@@ -43,8 +50,63 @@ constexpr int kMaxGroups = 8;   // (problem, degree) pairs
 struct OpEntry {
   gym_mesh* mesh = nullptr;
   gym_op* op = nullptr;
+  SchurPrec* schur = nullptr;  // set up on the first request that needs it
   int refs = 0;
   size_t bytes = 0;
+};
+
+// First-fit pool over one device allocation: blocks are carved at admission
+// and given back at retirement (adjacent free blocks merge), so the loop
+// thread allocates and frees no device memory for requests (hipFree would
+// synchronise the device under the running mix).
+class Pool {
+ public:
+  static constexpr size_t kAlign = 256;
+  void reset(char* base, size_t size) {
+    base_ = base;
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  char* base() const { return base_; }
+  static size_t round(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+  bool fits(size_t bytes) const {
+    bytes = round(bytes);
+    for (const auto& f : free_)
+      if (f.second >= bytes) return true;
+    return false;
+  }
+  char* take(size_t bytes) {
+    bytes = round(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < bytes) continue;
+      const size_t off = it->first, left = it->second - bytes;
+      free_.erase(it);
+      if (left) free_[off + bytes] = left;
+      return base_ + off;
+    }
+    return nullptr;
+  }
+  void give(char* p, size_t bytes) {
+    size_t off = (size_t)(p - base_);
+    bytes = round(bytes);
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + bytes == next->first) {
+      bytes += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+
+ private:
+  char* base_ = nullptr;
+  std::map<size_t, size_t> free_;  // offset -> size
 };
 
 struct Pending {
@@ -53,7 +115,8 @@ struct Pending {
   std::vector<double> rhs;
   Clock::time_point t0;
   int64_t n;
-  size_t bytes;
+  size_t bytes;       // vectors + operator (budget check)
+  size_t slot_bytes;  // vectors (pool block)
 };
 
 struct Slot {
@@ -66,6 +129,7 @@ struct Slot {
   int nb;   // blocks of the vector kernel
   int npa;  // operator workgroups of the last step
   size_t bytes;
+  SchurPrec* schur;  // block preconditioner, or null (Jacobi)
   double *b, *x;
   double *r1, *r2, *y, *z, *zp, *w, *w1, *w2;  // current roles
   double *pa, *pb[2], *pc[2], *alfa[2];         // step partials (two alternating sets)
@@ -141,6 +205,8 @@ struct gym_server {
   int* ibst_d[kStages] = {};
   hipEvent_t ev[kStages] = {};
   int stage = 0;
+  void* pool_mem = nullptr;
+  Pool pool;
   int fatal = 0;
   std::string fatal_msg;
 };
@@ -182,7 +248,7 @@ void evict_ops(gym_server* s, size_t need) {
     OpEntry* e = it->second;
     if (e->refs == 0) {
       s->bytes_used -= e->bytes;
-      gym_op_destroy(e->op);
+      gym_op_destroy(e->op);  // frees the preconditioner kept with it
       gym_mesh_destroy(e->mesh);
       delete e;
       it = s->ops.erase(it);
@@ -192,11 +258,28 @@ void evict_ops(gym_server* s, size_t need) {
   }
 }
 
+// device bytes of a preconditioner's factors and work vectors
+size_t schur_bytes(const SchurPrec& P) {
+  size_t f = 0;
+  for (int a = 0; a < 3; ++a) f += (size_t)P.m[a] * P.m[a];
+  return sizeof(double) * ((size_t)P.ns + P.m[0] + P.m[1] + P.m[2] + 2 * f) + sizeof(float) * 2 * f + P.work_bytes;
+}
+
 int admit(gym_server* s, Pending& p) {
   int rc = 0;
   OpEntry* e = get_op(s, p.req.problem, p.req.nel, p.req.degree, &rc);
   if (!e) return rc;
+  if (s->opts.precond == GYM_PRECOND_SCHUR && !e->schur) {
+    if (int rc2 = ensure_schur(e->op, 1, &e->schur)) return rc2;
+    const size_t b = schur_bytes(*e->schur);
+    e->bytes += b;
+    s->bytes_used += b;
+  }
+  char* mem = s->pool.take(p.slot_bytes);
+  if (!mem) return fail(GYM_E_OOM, "serving: request pool exhausted at admission");
   Slot* sl = new Slot{};
+  sl->schur = e->schur;
+  sl->mem = mem;
   sl->id = p.id;
   sl->problem = p.req.problem;
   sl->degree = p.req.degree;
@@ -205,12 +288,7 @@ int admit(gym_server* s, Pending& p) {
   sl->op = e;
   sl->n = p.n;
   sl->nb = vec_grid(p.n, s->ctx->ncu);
-  sl->bytes = sizeof(double) * slot_doubles(p.n, p.req.nel, sl->nb);
-  if (hipMalloc(&sl->mem, sl->bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    delete sl;
-    return fail(GYM_E_OOM, "serving: device allocation failed at admission");
-  }
+  sl->bytes = p.slot_bytes;
   double* base = (double*)sl->mem;
   double** vecs[10] = {&sl->b, &sl->x, &sl->r1, &sl->r2, &sl->y, &sl->z, &sl->zp, &sl->w, &sl->w1, &sl->w2};
   for (int k = 0; k < 10; ++k) *vecs[k] = base + (size_t)k * p.n;
@@ -247,8 +325,23 @@ int admit(gym_server* s, Pending& p) {
   }
   // init: r1 = r2 = b, z = M^-1 b, beta_1 (y receives v_1, unused)
   MinresVecs<double> V{sl->b, sl->x, sl->r1, sl->r2, sl->z, sl->y, sl->w, sl->w1, sl->w2};
-  minres_launch_init<double>(V, e->op->d_prec, p.n, 1, sl->nb, sl->scratch, s->d_states + 2 * sl->sidx,
-                             s->opts.rtol, s->stream);
+  if (sl->schur) {
+    minres_launch_init_vecs<double>(V, p.n, 1, sl->nb, s->stream);
+    if (launch_schur_apply<double>(*sl->schur, sl->b, sl->z, 1, sl->nb, s->stream)) {
+      s->pool.give((char*)sl->mem, sl->bytes);
+      s->bytes_used -= sl->bytes;
+      e->refs -= 1;
+      s->free_sidx.push_back(sl->sidx);
+      delete sl;
+      return fail(GYM_E_HIP, "serving: preconditioner launch failed");
+    }
+    minres_launch_dot2<double>(sl->b, sl->z, nullptr, p.n, 1, sl->nb, sl->scratch, nullptr, s->stream);
+    minres_launch_init_state<double>(V, p.n, 1, sl->nb, sl->scratch, s->d_states + 2 * sl->sidx, s->opts.rtol,
+                                     s->stream);
+  } else {
+    minres_launch_init<double>(V, e->op->d_prec, p.n, 1, sl->nb, sl->scratch, s->d_states + 2 * sl->sidx,
+                               s->opts.rtol, s->stream);
+  }
   s->active.push_back(sl);
   return 0;
 }
@@ -292,8 +385,9 @@ int step(gym_server* s) {
     MinresState* cur = s->d_states + 2 * sl->sidx + (sl->it & 1);
     MinresState* next = s->d_states + 2 * sl->sidx + ((sl->it + 1) & 1);
     const int pr = sl->par;
-    it.io = Step2Io{cur, next, sl->pending ? 0 : 1, sl->npa, sl->nb, sl->pa, sl->pb[pr], sl->pc[pr],
-                    sl->alfa[pr], sl->pb[pr ^ 1], sl->pc[pr ^ 1], sl->alfa[pr ^ 1]};
+    it.io = Step2Io{cur,          next,           sl->pending ? 0 : 1, sl->npa,       sl->nb,
+                    sl->pa,       sl->pb[pr],     sl->pc[pr],          sl->alfa[pr],  sl->pb[pr ^ 1],
+                    sl->pc[pr ^ 1], sl->alfa[pr ^ 1], sl->schur ? 1 : 0};
     s->ibst_h[st][i] = nblocks;
     nblocks += sl->nb;
   }
@@ -301,6 +395,17 @@ int step(gym_server* s) {
   GYM_HIP(hipMemcpyAsync(s->items_d[st], s->items_h[st], sizeof(MrItem) * na, hipMemcpyHostToDevice, s->stream));
   GYM_HIP(hipMemcpyAsync(s->ibst_d[st], s->ibst_h[st], sizeof(int) * (na + 1), hipMemcpyHostToDevice, s->stream));
   launch_batch_step2(s->items_d[st], s->ibst_d[st], na, nblocks, s->stream);
+  // block-preconditioned requests: z_{k+1} = P^-1 y over zp and the partial
+  // sums the second half left out (nothing once the request has converged:
+  // its buffers must stay as they were for a resumed recurrence)
+  for (Slot* sl : s->active) {
+    if (!sl->schur) continue;
+    const MinresState* cur = s->d_states + 2 * sl->sidx + (sl->it & 1);
+    if (launch_schur_apply<double>(*sl->schur, sl->y, sl->zp, 1, sl->nb, s->stream, cur))
+      return fail(GYM_E_HIP, "serving: preconditioner launch failed");
+    minres_launch_dot2<double>(sl->y, sl->zp, sl->r2, sl->n, 1, sl->nb, sl->pb[sl->par ^ 1], sl->pc[sl->par ^ 1],
+                               s->stream, cur);
+  }
   GYM_HIP(hipEventRecord(s->ev[st], s->stream));
   GYM_HIP(hipGetLastError());
   // the same rotation as the single-request driver
@@ -365,7 +470,7 @@ int retire(gym_server* s, Slot* sl, const MinresState& ms, double rel) {
   d.res.ndofs = sl->n;
   d.res.status = ms.flag < 0 ? GYM_E_BREAKDOWN : (d.res.rel_res <= s->opts.rtol ? GYM_OK : GYM_W_NOT_CONVERGED);
   d.res.latency_s = std::chrono::duration<double>(Clock::now() - sl->t0).count();
-  (void)hipFree(sl->mem);
+  s->pool.give((char*)sl->mem, sl->bytes);
   s->bytes_used -= sl->bytes;
   sl->op->refs -= 1;
   s->free_sidx.push_back(sl->sidx);
@@ -439,10 +544,11 @@ void loop(gym_server* s) {
         if (s->queue.empty() || (int)s->active.size() >= s->opts.max_slots) break;
         Pending& f = s->queue.front();
         size_t need = f.bytes;
+        const size_t block = f.slot_bytes;
         lk.unlock();
         if (s->bytes_used + need > (size_t)s->opts.mem_budget) evict_ops(s, need);
         lk.lock();
-        if (s->bytes_used + need > (size_t)s->opts.mem_budget) break;
+        if (s->bytes_used + need > (size_t)s->opts.mem_budget || !s->pool.fits(block)) break;
         p = std::move(s->queue.front());
         s->queue.pop_front();
       }
@@ -482,6 +588,8 @@ int gym_serve_start(const gym_serve_opts* opts, gym_server** out) {
   if (!opts || !out) return fail(GYM_E_ARG, "NULL argument");
   if (opts->max_slots < 1 || opts->max_slots > 4096 || opts->mem_budget <= 0 || opts->maxit < 1 || !(opts->rtol > 0))
     return fail(GYM_E_ARG, "bad serving options");
+  if (opts->precond != GYM_PRECOND_JACOBI && opts->precond != GYM_PRECOND_SCHUR)
+    return fail(GYM_E_ARG, "serving preconditioner must be GYM_PRECOND_JACOBI or GYM_PRECOND_SCHUR");
   gym_server* s = new gym_server;
   s->opts = *opts;
   if (int rc = gym_create(&s->ctx, opts->device)) {
@@ -489,6 +597,15 @@ int gym_serve_start(const gym_serve_opts* opts, gym_server** out) {
     return rc;
   }
   GYM_HIP(hipStreamCreate(&s->stream));
+  // the request pool: one allocation for the server's lifetime
+  if (hipMalloc(&s->pool_mem, (size_t)opts->mem_budget) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipStreamDestroy(s->stream);
+    gym_destroy(s->ctx);
+    delete s;
+    return fail(GYM_E_OOM, "serving: cannot reserve the memory budget on the device");
+  }
+  s->pool.reset((char*)s->pool_mem, (size_t)opts->mem_budget);
   const int maxs = opts->max_slots;
   GYM_HIP(hipMalloc(&s->d_states, sizeof(MinresState) * 2 * maxs));
   GYM_HIP(hipHostMalloc((void**)&s->h_states, sizeof(MinresState) * 2 * maxs, hipHostMallocDefault));
@@ -515,10 +632,13 @@ int gym_serve_submit(gym_server* s, const gym_request* req, uint64_t* id) {
   if ((req->problem != GYM_MIXED_POISSON && req->problem != GYM_HODGE1) || req->nel < 1 || req->nel > 1024 ||
       req->degree < 1 || req->degree > kMaxR)
     return fail(GYM_E_ARG, "bad request");
+  if (s->opts.precond == GYM_PRECOND_SCHUR && req->problem != GYM_MIXED_POISSON)
+    return fail(GYM_E_UNSUPPORTED, "the block preconditioner serves mixed Poisson requests only");
   Pending p;
   p.req = *req;
   p.n = request_ndofs(*req);
   p.bytes = request_bytes(p.n, req->nel, s->ctx->ncu);
+  p.slot_bytes = sizeof(double) * slot_doubles(p.n, req->nel, vec_grid(p.n, s->ctx->ncu));
   if (p.bytes > (size_t)s->opts.mem_budget) return fail(GYM_E_OOM, "request exceeds the server's memory budget");
   if (req->rhs) p.rhs.assign(req->rhs, req->rhs + p.n);
   p.req.rhs = nullptr;
@@ -562,10 +682,7 @@ int gym_serve_stop(gym_server* s) {
   s->cv.notify_all();
   if (s->th.joinable()) s->th.join();
   int rc = s->fatal;
-  for (Slot* sl : s->active) {
-    (void)hipFree(sl->mem);
-    delete sl;
-  }
+  for (Slot* sl : s->active) delete sl;
   for (auto& kv : s->ops) {
     gym_op_destroy(kv.second->op);
     gym_mesh_destroy(kv.second->mesh);
@@ -583,6 +700,7 @@ int gym_serve_stop(gym_server* s) {
     (void)hipEventDestroy(s->ev[k]);
   }
   (void)hipFree(s->d_states);
+  (void)hipFree(s->pool_mem);
   (void)hipHostFree(s->h_states);
   (void)hipStreamDestroy(s->stream);
   gym_destroy(s->ctx);

@@ -20,6 +20,7 @@
 
 #include <cstdint>
 
+#include "gen/tables_const.hpp"
 #include "kernels.hpp"
 
 namespace gym {
@@ -80,19 +81,6 @@ __device__ __forceinline__ const TabSet<double>& tabs<double>(int r) { return c_
 template <>
 __device__ __forceinline__ const TabSet<float>& tabs<float>(int r) { return c_tab_f[r - 1]; }
 
-// The same tables, looked up afresh at the call: the index passes through an
-// empty asm, so the scalar loads of the entries cannot be hoisted out of the
-// enclosing loops.  Hoisted, every table a kernel touches would stay live in
-// scalar registers at once and spill to VGPR lanes; fetched here, only the
-// entries of one contraction are live.
-template <typename TC>
-__device__ __forceinline__ const TabSet<TC>& stage_tabs(int r) {
-  int k = r - 1;
-  asm volatile("" : "+s"(k));
-  if constexpr (sizeof(TC) == 8) return c_tab_d[k];
-  else return c_tab_f[k];
-}
-
 template <bool BF, typename TC>
 __device__ __forceinline__ const TabSet<TC>& ktabs(int r) {
   if constexpr (BF) return c_tab_b[r - 1];
@@ -119,6 +107,17 @@ struct Cfg {
   static constexpr int tmpB() { return QX * QY * (DIM == 3 ? R + 1 : 1); }
 };
 
+// The contraction tables of degree R (q = R + 1) as compile-time constants,
+// generated at build time from the same make_tables() as the run-time copies:
+// with the loops unrolled every entry is a literal, so no scalar-memory load
+// (and no wait on one) sits in a contraction.
+template <typename TC, int R, bool NODAL, bool WEIGHTED>
+__device__ __forceinline__ constexpr TC ctab(int q, int i) {
+  using T = ctabs::Tab<R>;
+  if constexpr (NODAL) return static_cast<TC>(WEIGHTED ? T::phiw[q][i] : T::phi[q][i]);
+  else return static_cast<TC>(WEIGHTED ? T::edgew[q][i] : T::edge[q][i]);
+}
+
 template <typename TC, bool NODAL, bool WEIGHTED>
 __device__ __forceinline__ TC tab(const TabSet<TC>& t, int q, int i) {
   if constexpr (NODAL) return WEIGHTED ? t.phiw[q][i] : t.phi[q][i];
@@ -140,14 +139,13 @@ __device__ __forceinline__ void fwd_x(const TC* __restrict__ in, TC* __restrict_
   constexpr int NX = C::nx(TM), NY = C::ny(TM), NZ = C::nz(TM);
   constexpr bool N = TM & 1;
   constexpr int n = N ? C::R + 1 : C::R;
-  const TabSet<TC>& T = tabs<TC>(C::R);
   for (int idx = threadIdx.x; idx < C::QX * NY * NZ; idx += C::NT) {
     int qx = idx % C::QX, rest = idx / C::QX;
     int e = qx / C::Q, t = qx - e * C::Q;
     const TC* s = in + rest * NX + C::R * e;
     TC acc = 0;
 #pragma unroll
-    for (int i = 0; i < n; ++i) acc += tab<TC, N, false>(T, t, i) * s[i];
+    for (int i = 0; i < n; ++i) acc += ctab<TC, C::R, N, false>(t, i) * s[i];
     out[idx] = (e >= er.xlo && e < er.xhi) ? acc : TC(0);
   }
 }
@@ -158,7 +156,6 @@ __device__ __forceinline__ void fwd_y(const TC* __restrict__ in, TC* __restrict_
   constexpr int NY = C::ny(TM), NZ = C::nz(TM);
   constexpr bool N = TM & 2;
   constexpr int n = N ? C::R + 1 : C::R;
-  const TabSet<TC>& T = tabs<TC>(C::R);
   for (int idx = threadIdx.x; idx < C::QX * C::QY * NZ; idx += C::NT) {
     int qx = idx % C::QX, r2 = idx / C::QX;
     int qy = r2 % C::QY, k = r2 / C::QY;
@@ -166,7 +163,7 @@ __device__ __forceinline__ void fwd_y(const TC* __restrict__ in, TC* __restrict_
     const TC* s = in + qx + C::QX * (C::R * e + NY * k);
     TC acc = 0;
 #pragma unroll
-    for (int i = 0; i < n; ++i) acc += tab<TC, N, false>(T, t, i) * s[C::QX * i];
+    for (int i = 0; i < n; ++i) acc += ctab<TC, C::R, N, false>(t, i) * s[C::QX * i];
     out[idx] = (e >= er.ylo && e < er.yhi) ? acc : TC(0);
   }
 }
@@ -180,12 +177,11 @@ __device__ __forceinline__ void fwd_z(const TC* __restrict__ in, TC* __restrict_
   } else {
     constexpr bool N = TM & 4;
     constexpr int n = N ? C::R + 1 : C::R;
-    const TabSet<TC>& T = tabs<TC>(C::R);
     for (int idx = threadIdx.x; idx < P * C::Q; idx += C::NT) {
       int p = idx % P, t = idx / P;
       TC acc = 0;
 #pragma unroll
-      for (int i = 0; i < n; ++i) acc += tab<TC, N, false>(T, t, i) * in[p + P * i];
+      for (int i = 0; i < n; ++i) acc += ctab<TC, C::R, N, false>(t, i) * in[p + P * i];
       out[idx] = acc;
     }
   }
@@ -201,12 +197,11 @@ __device__ __forceinline__ void bwd_z(const TC* __restrict__ in, TC* __restrict_
   } else {
     constexpr bool N = TM & 4;
     constexpr int NZ = C::nz(TM);
-    const TabSet<TC>& T = tabs<TC>(C::R);
     for (int idx = threadIdx.x; idx < P * NZ; idx += C::NT) {
       int p = idx % P, k = idx / P;
       TC acc = 0;
 #pragma unroll
-      for (int t = 0; t < C::Q; ++t) acc += tab<TC, N, true>(T, t, k) * in[p + P * t];
+      for (int t = 0; t < C::Q; ++t) acc += ctab<TC, C::R, N, true>(t, k) * in[p + P * t];
       out[idx] = acc;
     }
   }
@@ -233,11 +228,12 @@ template <class C, int TM, typename TC>
 __device__ __forceinline__ void bwd_y(const TC* __restrict__ in, TC* __restrict__ out) {
   constexpr int NY = C::ny(TM), NZ = C::nz(TM);
   constexpr bool N = TM & 2;
-  const TabSet<TC>& T = tabs<TC>(C::R);
   for (int idx = threadIdx.x; idx < C::QX * NY * NZ; idx += C::NT) {
     int qx = idx % C::QX, r2 = idx / C::QX;
     int j = r2 % NY, k = r2 / NY;
     const TC* base = in + qx + C::QX * C::QY * k;
+    // i varies over the lanes: a table lookup, not a literal
+    const TabSet<TC>& T = tabs<TC>(C::R);
     out[idx] = gather1d<C::R, C::EY, N>(j, [&](int e, int i) {
       TC acc = 0;
 #pragma unroll
@@ -253,10 +249,10 @@ template <class C, int TM, bool ADD, typename TC>
 __device__ __forceinline__ void bwd_x(const TC* __restrict__ in, TC* __restrict__ out, TC scale) {
   constexpr int NX = C::nx(TM), NY = C::ny(TM), NZ = C::nz(TM);
   constexpr bool N = TM & 1;
-  const TabSet<TC>& T = tabs<TC>(C::R);
   for (int idx = threadIdx.x; idx < NX * NY * NZ; idx += C::NT) {
     int j = idx % NX, rest = idx / NX;
     const TC* base = in + C::QX * rest;
+    const TabSet<TC>& T = tabs<TC>(C::R);  // i varies over the lanes
     TC v = gather1d<C::R, C::EX, N>(j, [&](int e, int i) {
       TC acc = 0;
 #pragma unroll

@@ -63,7 +63,7 @@ class SolveInfo(ctypes.Structure):
 
 class ServeOpts(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("mem_budget", ctypes.c_int64), ("max_slots", ctypes.c_int),
-                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int)]
+                ("rtol", ctypes.c_double), ("maxit", ctypes.c_int), ("precond", ctypes.c_int)]
 
 
 class Request(ctypes.Structure):

@@ -31,8 +31,8 @@ REQS = [(0, 4, 1, 101), (0, 6, 2, 102), (0, 3, 3, 103), (1, 4, 2, 104), (0, 9, 1
         (1, 3, 3, 106), (0, 5, 2, 107), (1, 5, 1, 108), (0, 4, 4, 109), (1, 2, 2, 110)]
 
 
-def _serve(gym, reqs, max_slots, stagger=False, budget=4 << 30, rtol=1e-12):
-    o = gym.ServeOpts(device=0, mem_budget=budget, max_slots=max_slots, rtol=rtol, maxit=50000)
+def _serve(gym, reqs, max_slots, stagger=False, budget=4 << 30, rtol=1e-12, precond=0):
+    o = gym.ServeOpts(device=0, mem_budget=budget, max_slots=max_slots, rtol=rtol, maxit=50000, precond=precond)
     srv = gym.gym_serve_start(o)
     ids = []
     half = len(reqs) // 2
@@ -124,3 +124,61 @@ def test_host_rhs_and_admission_budget(gym):
         assert res.status == 0
         ref = problems.solve_direct(P.A, b)
         assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-8
+
+
+# mixed Poisson requests of uneven sizes and degrees (problem, nel, r, seed)
+PREQS = [(0, 4, 1, 201), (0, 7, 2, 202), (0, 3, 3, 203), (0, 9, 1, 204), (0, 5, 2, 205), (0, 4, 3, 206),
+         (0, 6, 1, 207), (0, 2, 2, 208)]
+
+
+def test_block_preconditioned_serving_alone_and_in_the_mix(gym):
+    """With the block preconditioner every request takes its own
+    preconditioner launches after the batched step; results stay bitwise
+    the same alone and in the mix, converge in a mesh-independent number of
+    steps and match the oracle's direct solve."""
+    alone = _serve(gym, PREQS, max_slots=1, precond=gym.GYM_PRECOND_SCHUR, rtol=1e-11)
+    mix = _serve(gym, PREQS, max_slots=8, stagger=True, precond=gym.GYM_PRECOND_SCHUR, rtol=1e-11)
+    jac = _serve(gym, PREQS[:4], max_slots=4, rtol=1e-11)
+    for (ra, xa), (rm, xm), req in zip(alone, mix, PREQS):
+        assert ra.status == 0 and rm.status == 0, req
+        assert ra.iters == rm.iters, req
+        assert np.array_equal(xa, xm), (req, np.abs(xa - xm).max())
+        assert rm.rel_res <= 1e-11
+        assert rm.iters <= 120, (req, rm.iters)
+    # fewer steps than the Jacobi-preconditioned recurrence on the larger meshes
+    assert mix[1][0].iters < jac[1][0].iters and mix[3][0].iters < jac[3][0].iters
+    for (res, x), (prob, nel, r, seed) in zip(mix[:4], PREQS[:4]):
+        mesh = Mesh(synth.uniform_vertices((nel,) * 3))
+        P = problems.MixedPoisson(mesh, r)
+        b = synth.counter_normal(seed, P.A.shape[0], first=P.n[0])
+        ref = problems.solve_direct(P.A, b)
+        assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-9, (prob, nel, r)
+
+
+def test_block_preconditioner_refuses_other_problems_and_bad_options(gym):
+    o = gym.ServeOpts(device=0, mem_budget=1 << 28, max_slots=2, rtol=1e-8, maxit=1000,
+                      precond=gym.GYM_PRECOND_SCHUR)
+    srv = gym.gym_serve_start(o)
+    with pytest.raises(gym.GymError):
+        gym.gym_serve_submit(srv, gym.Request(problem=1, nel=3, degree=1, seed=1, rhs=None, want_solution=0))
+    gym.gym_serve_stop(srv)
+    o = gym.ServeOpts(device=0, mem_budget=1 << 28, max_slots=2, rtol=1e-8, maxit=1000,
+                      precond=gym.GYM_PRECOND_NONE)
+    with pytest.raises(gym.GymError):
+        gym.gym_serve_start(o)
+
+
+def test_pool_reuse_over_many_requests(gym):
+    """Forty requests through a pool with room for about three at a time:
+    blocks are returned and carved again, every request completes, and each
+    result equals the same request served alone."""
+    prob, nel, r = 0, 5, 2
+    n = _ndofs(prob, nel, r)
+    per_req = 8 * (10 * n) + 8 * 4096
+    reqs = [(prob, nel if k % 3 else nel - 1, r, 300 + k) for k in range(40)]
+    mix = _serve(gym, reqs, max_slots=16, budget=int(3.5 * per_req), precond=gym.GYM_PRECOND_SCHUR, rtol=1e-10)
+    for k in (0, 1, 17, 39):
+        (ra, xa), = _serve(gym, [reqs[k]], max_slots=1, precond=gym.GYM_PRECOND_SCHUR, rtol=1e-10)
+        rm, xm = mix[k]
+        assert rm.status == 0 and ra.iters == rm.iters
+        assert np.array_equal(xa, xm)
