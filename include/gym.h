@@ -155,6 +155,17 @@ int gym_mesh_create(gym_ctx* ctx, int dim, const int64_t nel[3],
 int gym_mesh_structured(gym_ctx* ctx, int dim, const int64_t nel[3],
                         const double lo[3], const double hi[3],
                         double perturb_frac, uint64_t seed, gym_mesh** out);
+
+/* Make the axes in mask (bit a: axis a) of an affine box periodic: position
+ * m_a of every lattice closes onto position 0, so spaces created on the mesh
+ * afterwards keep r*nel[a] positions along such an axis for nodal and edge
+ * functions alike and apply no boundary condition along it (the paper's
+ * torus of section 7.3 and the 20 x 20 mesh of section 7.5).  Serves the
+ * time stepping (gym_maxwell_*) and its eigenmodes, incidence and mass
+ * applies and mass solves (FP64, through 1-D band passes); gym_op_create
+ * refuses periodic meshes.  Call before creating spaces on the mesh.
+ * Errors: GYM_E_ARG (bits beyond dim), GYM_E_UNSUPPORTED (curved mesh). */
+int gym_mesh_set_periodic(gym_mesh* mesh, int mask);
 /* Vertex coordinates of a mesh into the HOST array `vertices`
  * ((nel_0+1)...(nel_{d-1}+1) x dim doubles, the layout of gym_mesh_create);
  * for an affine mesh, the uniform lattice of [lo, hi]. */
@@ -334,8 +345,12 @@ typedef struct gym_maxwell_opts {
 } gym_maxwell_opts;
 /* Defaults: exact Q1 and M2~, c = 1, cg_rtol 1e-14, cg_maxit 1000. */
 void gym_maxwell_opts_default(gym_maxwell_opts* opts);
-/* Errors: GYM_E_ARG (not 3-D, degree outside 1..4, bad option),
- * GYM_E_UNSUPPORTED (lumped masses or a SPAI on a curved mesh), GYM_E_OOM. */
+/* The mesh is 3-D (tangential components zero on non-periodic faces: the
+ * perfect conductor), or 2-D with both axes periodic (the torus: Lambda^2 is
+ * then the scalar L2 space and C the 2-D curl).  On periodic meshes the
+ * masses run as 1-D band passes.  Errors: GYM_E_ARG (other dimensions,
+ * degree outside 1..4, bad option), GYM_E_UNSUPPORTED (lumped masses or a
+ * SPAI on a curved mesh), GYM_E_OOM. */
 int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree,
                        const gym_maxwell_opts* opts, gym_maxwell** out);
 /* SPAI-OP (section 5, eqs. SPAIOPobjective to diagonalPreconditioner): the
@@ -347,7 +362,8 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree,
  * probes: device array of nprobe x ndofs doubles, the modes v_k (nprobe may be
  * 0: the optimal symmetric SPAI).  On success the object's Q1 becomes this
  * SPAI-OP (GYM_Q1_SPAI_OP) for the time stepping, the energy and the
- * eigen-solver.  Affine meshes only.  Returns GYM_W_NOT_CONVERGED (Q1 is
+ * eigen-solver.  Affine 3-D meshes without periodic axes only
+ * (GYM_E_UNSUPPORTED otherwise).  Returns GYM_W_NOT_CONVERGED (Q1 is
  * still replaced) if maxit came before rtol; *iters and *rel_res may be NULL. */
 int gym_maxwell_spai_op(gym_maxwell* mx, int nprobe, const double* probes, double lambda, double rtol,
                         int maxit, int* iters, double* rel_res, void* stream);

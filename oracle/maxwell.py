@@ -35,7 +35,10 @@ Strang splitting reproduce the Yee leapfrog; :func:`yee_fdtd` is that
 leapfrog written directly as finite differences of cell-averaged fields.
 
 Boundary: perfect conductor (tangential E = 0): a, e in H0(curl)
-(essential), b = C a in H(div) (natural).
+(essential), b = C a in H(div) (natural).  Or, with periodic=True, the torus
+of sections 7.3 and 7.5: every axis periodic, no boundary; in 2-D the second
+space is the scalar L2 space and C the 2-D curl.  Row sums are then those of
+the periodic mass matrix itself.
 
 Pins (tests/test_oracle_maxwell.py): equivalence with the hand-written Yee
 finite differences; the one-step Jacobian against the paper's printed block
@@ -57,6 +60,8 @@ from .lattice import Space
 def _kept_row_sums(space, mesh):
     """Row sums of the mass matrix of `space` without boundary conditions,
     at the unknowns `space` keeps (its canonical order)."""
+    if space.periodic:  # no boundary: the space's own rows
+        return np.asarray(assembly.mass_matrix(space, mesh).sum(axis=1)).ravel()
     full = Space(space.kind, space.nel, space.r, "natural")
     rs = np.asarray(assembly.mass_matrix(full, mesh).sum(axis=1)).ravel()
     out = np.empty(space.ndofs)
@@ -69,14 +74,14 @@ def _kept_row_sums(space, mesh):
 class Gym:
     """Generalized Yee method on a structured hexahedral mesh."""
 
-    def __init__(self, mesh, r, q1="exact", m2="exact", c=1.0):
+    def __init__(self, mesh, r, q1="exact", m2="exact", c=1.0, periodic=False):
         given = sp.issparse(q1) or isinstance(q1, np.ndarray)
         if (not given and q1 not in ("exact", "lumped", "spai_diag", "spai")) or m2 not in ("exact", "lumped"):
             raise ValueError("q1: 'exact', 'lumped', 'spai_diag', 'spai' or a matrix; m2: 'exact' or 'lumped'")
         self.mesh, self.r, self.c = mesh, r, float(c)
         self.q1_kind, self.m2_kind = ("given" if given else q1), m2
-        self.s1 = Space("HCURL", mesh.nel, r, "essential")
-        self.s2 = Space("HDIV", mesh.nel, r, "natural")
+        self.s1 = Space("HCURL", mesh.nel, r, "essential", periodic=periodic)
+        self.s2 = Space("HDIV" if len(mesh.nel) == 3 else "L2", mesh.nel, r, "natural", periodic=periodic)
         self.M1 = assembly.mass_matrix(self.s1, mesh).tocsc()
         self.M2 = assembly.mass_matrix(self.s2, mesh).tocsr()
         self.C = incidence.curl(self.s1, self.s2).astype(np.float64).tocsr()

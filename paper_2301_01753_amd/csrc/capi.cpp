@@ -17,6 +17,7 @@
 #include "krylov.hpp"
 #include "poisson_mfma.hpp"
 #include "schur.hpp"
+#include "spai.hpp"
 
 namespace gym {
 
@@ -457,6 +458,27 @@ namespace {
 
 int launch_mass_apply(const gym_space* sp, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
   const gym_mesh* m = sp->mesh;
+  if (sp->desc.periodic) {
+    // periodic axes: the mass as a Kronecker product of assembled 1-D bands
+    // with wrap-around (FP64), built on first use and kept with the space
+    if (prec != GYM_F64) return fail(GYM_E_UNSUPPORTED, "mass apply on a periodic space: FP64 only");
+    gym_space* w = const_cast<gym_space*>(sp);  // cache only
+    if (!w->band) {
+      SpaiParams* bp = new SpaiParams{};
+      if (int rc = build_band_mass(sp, bp, &w->band_mem)) {
+        delete bp;
+        return rc;
+      }
+      w->band = bp;
+    }
+    const SpaiParams& bp = *static_cast<const SpaiParams*>(sp->band);
+    const long long n = sp->desc.ndofs;
+    for (int k = 0; k < nrhs; ++k)
+      launch_spai_apply(bp, static_cast<const double*>(x) + k * n, static_cast<double*>(y) + k * n,
+                        vec_grid(n, sp->ctx->ncu), s);
+    GYM_HIP(hipGetLastError());
+    return 0;
+  }
   OpParams p{};
   set_form(p, sp->ctx, m);
   p.x = x;
@@ -721,12 +743,42 @@ struct MassWork {
   std::vector<void*> pool;
 };
 
+// Diagonal (rowsum = false) or row sums (true) of the mass of a space with a
+// periodic axis: Kronecker products of the 1-D diagonals or row sums of the
+// assembled 1-D masses with their wrap, times the component's metric.
+std::vector<double> periodic_diag_host(const gym_space* sp, bool rowsum) {
+  const gym_mesh* m = sp->mesh;
+  const SpaceDesc& s = sp->desc;
+  std::vector<double> out(s.ndofs);
+  for (int c = 0; c < s.ncomp; ++c) {
+    const CompDesc& cd = s.comp[c];
+    std::vector<double> f[3];
+    for (int a = 0; a < 3; ++a) {
+      if (a >= s.dim) {
+        f[a].assign(1, 1.0);
+        continue;
+      }
+      std::vector<double> dg, rs;
+      mass1d_diag_rowsum(s.r, (int)m->nel[a], (cd.nodal_mask >> a) & 1, (int)cd.start[a], (int)cd.count[a],
+                         (s.periodic >> a) & 1, dg, rs);
+      f[a] = rowsum ? rs : dg;
+    }
+    const double sc = metric_const(s.kind, c, m);
+    int64_t idx = cd.offset;
+    for (int64_t k = 0; k < cd.count[2]; ++k)
+      for (int64_t j = 0; j < cd.count[1]; ++j)
+        for (int64_t i = 0; i < cd.count[0]; ++i) out[idx++] = sc * f[0][i] * f[1][j] * f[2][k];
+  }
+  return out;
+}
+
 // Diagonal of M_k on an affine box (Kronecker product of 1-D diagonals);
 // on curved cells it is the diagonal of the box with the same spacing,
 // which only serves as the Jacobi preconditioner.
 std::vector<double> mass_diag_host(const gym_space* sp) {
   const gym_mesh* m = sp->mesh;
   const SpaceDesc& s = sp->desc;
+  if (s.periodic) return periodic_diag_host(sp, false);
   std::vector<Diag1D> D;
   for (int a = 0; a < 3; ++a) D.push_back(diag1d(s.r, a < m->dim ? m->nel[a] : 1));
   std::vector<double> out(s.ndofs);
@@ -760,6 +812,7 @@ LumpedTables lumped_tables_host(const gym_space* sp) {
 std::vector<double> lumped_diag_host(const gym_space* sp) {
   const gym_mesh* m = sp->mesh;
   const SpaceDesc& s = sp->desc;
+  if (s.periodic) return periodic_diag_host(sp, true);
   const LumpedTables t = lumped_tables_host(sp);
   std::vector<double> out(s.ndofs);
   for (int c = 0; c < s.ncomp; ++c) {
@@ -981,6 +1034,14 @@ int gym_mesh_vertices(const gym_mesh* m, double* out) {
   return GYM_OK;
 }
 
+int gym_mesh_set_periodic(gym_mesh* m, int mask) {
+  if (!m) return fail(GYM_E_ARG, "NULL argument");
+  if (mask < 0 || mask >= (1 << m->dim)) return fail(GYM_E_ARG, "periodic mask has bits beyond the mesh dimension");
+  if (mask && m->curved) return fail(GYM_E_UNSUPPORTED, "periodic axes need an affine box");
+  m->periodic = mask;
+  return GYM_OK;
+}
+
 int gym_mesh_destroy(gym_mesh* m) {
   if (!m) return GYM_OK;
   if (m->d_vertices) (void)hipFree(m->d_vertices);
@@ -999,7 +1060,7 @@ int gym_space_create(gym_ctx* ctx, const gym_mesh* mesh, int kind, int degree, i
   gym_space* s = new gym_space;
   s->ctx = ctx;
   s->mesh = mesh;
-  s->desc = make_space_desc(kind, mesh->dim, mesh->nel, degree, bc);
+  s->desc = make_space_desc(kind, mesh->dim, mesh->nel, degree, bc, mesh->periodic);
   *out = s;
   return GYM_OK;
 }
@@ -1037,6 +1098,8 @@ int gym_space_layout(const gym_space* s, gym_layout* out) {
 int gym_space_destroy(gym_space* s) {
   if (!s) return GYM_OK;
   if (s->d_diag) (void)hipFree(s->d_diag);
+  if (s->band_mem) (void)hipFree(s->band_mem);
+  delete static_cast<SpaiParams*>(s->band);
   if (!s->work.empty()) {
     MassWork* w = (MassWork*)s->work[0];
     for (void* p : w->pool) (void)hipFree(p);
@@ -1071,6 +1134,7 @@ int gym_d_apply(const gym_space* from, const gym_space* to, int transpose, const
   p.dim = dim;
   p.op = op;
   p.transpose = transpose ? 1 : 0;
+  p.periodic = from->desc.periodic;
   p.nout = dst->desc.ndofs;
   int rc = launch_incidence(p, (hipStream_t)stream);
   if (rc) return fail(GYM_E_HIP, "incidence launch failed");
@@ -1088,6 +1152,8 @@ int gym_op_create(gym_ctx* ctx, int problem, const gym_mesh* mesh, int degree, g
   if (degree < 1 || degree > kMaxR) return fail(GYM_E_ARG, "degree must be 1..4");
   if (problem != GYM_MIXED_POISSON && problem != GYM_HODGE1) return fail(GYM_E_ARG, "unknown problem");
   if (problem == GYM_HODGE1 && mesh->dim != 3) return fail(GYM_E_UNSUPPORTED, "Hodge problem is 3-D only");
+  if (mesh->periodic)
+    return fail(GYM_E_UNSUPPORTED, "periodic meshes serve the time stepping and its eigenmodes, not the operators");
   gym_op* op = new gym_op;
   op->ctx = ctx;
   op->mesh = mesh;

@@ -52,11 +52,14 @@ struct CompDesc {
 
 struct SpaceDesc {
   int kind = 0, dim = 3, r = 1, bc = 0, ncomp = 1;
+  int periodic = 0;  // bit a: axis a closes on itself (position m_a is position 0)
   int64_t m[3] = {1, 1, 1};
   CompDesc comp[3];
   int64_t ndofs = 0;
 };
-SpaceDesc make_space_desc(int kind, int dim, const int64_t nel[3], int r, int bc);
+// periodic: bit a makes axis a periodic, with m_a positions for nodal and edge
+// functions alike and no boundary condition along it.
+SpaceDesc make_space_desc(int kind, int dim, const int64_t nel[3], int r, int bc, int periodic = 0);
 
 }  // namespace gym
 
@@ -96,6 +99,7 @@ struct gym_mesh {
   int64_t nel[3] = {1, 1, 1};
   double lo[3] = {0, 0, 0}, hi[3] = {1, 1, 1}, h[3] = {1, 1, 1};
   bool curved = false;              // vertex array given
+  int periodic = 0;                 // bit a: axis a periodic (affine boxes only)
   double* d_vertices = nullptr;     // device copy, (N+1)^d x d
   std::vector<double> vertices;     // host copy
   // curved: Gauss-point metrics per degree r (q = r + 1), FP64 [0] and FP32
@@ -117,6 +121,8 @@ struct gym_space {
   const gym_mesh* mesh = nullptr;
   gym::SpaceDesc desc;
   double* d_diag = nullptr;         // lazily built Jacobi diagonal
+  void* band = nullptr;             // periodic spaces: the mass as 1-D band passes (SpaiParams)
+  double* band_mem = nullptr;
   // Krylov workspace for mass solves
   std::vector<void*> work;
   int work_nrhs = 0;

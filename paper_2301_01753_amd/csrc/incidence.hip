@@ -6,7 +6,9 @@
 // index, so every entry is summed from +0.0 in ascending input order.  With
 // +-1 coefficients the products are exact, hence the result is bit-identical
 // to an ascending-order CSR sum of the same matrix (and independent of the
-// launch shape).
+// launch shape).  On a periodic axis the shifted position wraps around; the
+// terms are then summed in the same fixed order, which for the entries whose
+// stencil wraps is not the ascending one (exact on integer data all the same).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,6 +49,10 @@ __global__ void __launch_bounds__(256) incidence_kernel(const IncParams p, const
     int g0 = pos[0] + t.shift[0] - ic.start[0];
     int g1 = pos[1] + t.shift[1] - ic.start[1];
     int g2 = pos[2] + t.shift[2] - ic.start[2];
+    // periodic axes: a shift of +-1 past either end re-enters at the other
+    if (p.periodic & 1) g0 = g0 < 0 ? g0 + ic.count[0] : (g0 >= ic.count[0] ? g0 - ic.count[0] : g0);
+    if (p.periodic & 2) g1 = g1 < 0 ? g1 + ic.count[1] : (g1 >= ic.count[1] ? g1 - ic.count[1] : g1);
+    if (p.periodic & 4) g2 = g2 < 0 ? g2 + ic.count[2] : (g2 >= ic.count[2] ? g2 - ic.count[2] : g2);
     if (g0 < 0 || g0 >= ic.count[0] || g1 < 0 || g1 >= ic.count[1] || g2 < 0 || g2 >= ic.count[2]) continue;
     double v = p.x[ic.offset + g0 + (long long)ic.count[0] * (g1 + (long long)ic.count[1] * g2)];
     if (t.sign > 0) acc += v;

@@ -81,6 +81,7 @@ struct IncParams {
   int dim;
   int op;           // 0 = G, 1 = C, 2 = D
   int transpose;
+  int periodic;     // bit a: positions along axis a wrap (count = m_a)
   long long nout;
 };
 int launch_incidence(const IncParams& p, hipStream_t s);

@@ -112,7 +112,8 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
   gym_maxwell_opts o;
   if (opts) o = *opts;
   else gym_maxwell_opts_default(&o);
-  if (mesh->dim != 3) return fail(GYM_E_ARG, "time stepping is 3-D");
+  if (mesh->dim != 3 && !(mesh->dim == 2 && mesh->periodic == 3))
+    return fail(GYM_E_ARG, "time stepping is 3-D, or 2-D on a doubly periodic mesh");
   if (degree < 1 || degree > 4) return fail(GYM_E_ARG, "degree must be 1..4");
   if ((o.q1 != GYM_Q1_EXACT && o.q1 != GYM_Q1_LUMPED && o.q1 != GYM_Q1_SPAI_DIAG && o.q1 != GYM_Q1_SPAI) ||
       (o.m2 != GYM_M2_EXACT && o.m2 != GYM_M2_LUMPED) ||
@@ -130,7 +131,8 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
   mx->mesh = mesh;
   mx->o = o;
   int rc = gym_space_create(ctx, mesh, GYM_HCURL, degree, GYM_BC_ESSENTIAL, &mx->s1);
-  if (!rc) rc = gym_space_create(ctx, mesh, GYM_HDIV, degree, GYM_BC_NATURAL, &mx->s2);
+  // Lambda^2 = C Lambda^1: H(div) in 3-D, the scalar L2 space in 2-D
+  if (!rc) rc = gym_space_create(ctx, mesh, mesh->dim == 3 ? GYM_HDIV : GYM_L2, degree, GYM_BC_NATURAL, &mx->s2);
   if (rc) {
     gym_maxwell_destroy(mx);
     return rc;
@@ -150,8 +152,9 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
       nw += (long long)(tab1.rn[a].size() + tab1.re[a].size());
     }
   }
-  // one thread per lattice position, indexed in 32 bits
-  mx->fused = lumped && npos < (1LL << 31) - 256;
+  // one thread per lattice position, indexed in 32 bits (the stencil kernel
+  // is written for the 3-D perfect conductor)
+  mx->fused = lumped && npos < (1LL << 31) - 256 && mesh->dim == 3 && !mesh->periodic;
   const size_t total = 3 * (size_t)mx->n1 + 3 * (size_t)mx->n2 + (size_t)mx->nb1 + 4 + (mx->fused ? nw : 0);
   if (hipMalloc(&mx->mem, sizeof(double) * total) != hipSuccess) {
     (void)hipGetLastError();
@@ -329,7 +332,14 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   double* dT = alloc(n1);    // their inverses (the preconditioner)
   double* gw = alloc(eig_gram_work(nb1));
   double* cgw = spai_q1 ? alloc(3 * n1 * k) : nullptr;  // CG work of B = Q1^-1
-  if (!X || !bx || !gp || !bgp || !g0 || !phi || !dB || !dT || !gw || (spai_q1 && !cgw)) {
+  // On a mesh periodic along every axis, ker P2 holds besides the gradients
+  // the harmonic fields: the interpolants of the constant fields (one per
+  // axis; edge values proportional to the GLL sub-edge lengths).
+  const int dimm = mx->mesh->dim;
+  const int nh = mx->mesh->periodic == (1 << dimm) - 1 ? dimm : 0;
+  double* H = nh ? alloc(n1 * nh) : nullptr;
+  double* BH = nh ? alloc(n1 * nh) : nullptr;
+  if (!X || !bx || !gp || !bgp || !g0 || !phi || !dB || !dT || !gw || (spai_q1 && !cgw) || (nh && (!H || !BH))) {
     cleanup();
     return fail(GYM_E_OOM, "eigen-solver: device allocation failed");
   }
@@ -441,6 +451,70 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
       launch_axpy_diag(colp(y, n1, j), c2, c2 * o.grad_shift, nullptr, colp(bgp, n1, j), n1, nb1, s);
     return 0;
   };
+  // harmonic lift: A += c^2 s B H (H^T B H)^-1 H^T B, which moves the
+  // harmonic fields (P2 h = 0) to omega^2 = s c^2 and, as every other
+  // eigenvector of (P2, B) is B-orthogonal to them, leaves the rest alone
+  std::vector<double> ghi((size_t)nh * nh);
+  if (nh) {
+    const SpaceDesc& d1 = mx->s1->desc;
+    const std::vector<double> xi = gll_nodes(d1.r);
+    std::vector<double> h((size_t)n1 * nh, 0.0);
+    for (int a = 0; a < nh; ++a) {
+      const CompDesc& cd = d1.comp[a];
+      int64_t idx = cd.offset;
+      for (int64_t kk = 0; kk < cd.count[2]; ++kk)
+        for (int64_t j = 0; j < cd.count[1]; ++j)
+          for (int64_t i = 0; i < cd.count[0]; ++i) {
+            const int64_t p[3] = {cd.start[0] + i, cd.start[1] + j, cd.start[2] + kk};
+            const int loc = (int)(p[a] % d1.r);
+            h[(size_t)a * n1 + idx++] = xi[loc + 1] - xi[loc];
+          }
+    }
+    std::vector<double> gh((size_t)nh * nh);
+    int rc0 = hipMemcpy(H, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice) != hipSuccess
+                  ? hip_fail(hipGetLastError(), "eigen-solver upload")
+                  : ops.B(H, BH, nh);
+    if (!rc0 && eig_gram(H, nh, BH, nh, n1, gh.data(), gw, nb1, s)) rc0 = hip_fail(hipGetLastError(), "eigen-solver gram");
+    if (!rc0) {
+      // (H^T B H)^-1 of at most 3 x 3, by Gauss-Jordan
+      std::vector<double> a = gh;
+      for (int i = 0; i < nh; ++i) ghi[(size_t)i * nh + i] = 1.0;
+      for (int c = 0; c < nh; ++c) {
+        const double piv = a[(size_t)c * nh + c];
+        for (int j = 0; j < nh; ++j) {
+          a[(size_t)c * nh + j] /= piv;
+          ghi[(size_t)c * nh + j] /= piv;
+        }
+        for (int r2 = 0; r2 < nh; ++r2) {
+          if (r2 == c) continue;
+          const double f = a[(size_t)r2 * nh + c];
+          for (int j = 0; j < nh; ++j) {
+            a[(size_t)r2 * nh + j] -= f * a[(size_t)c * nh + j];
+            ghi[(size_t)r2 * nh + j] -= f * ghi[(size_t)c * nh + j];
+          }
+        }
+      }
+    }
+    if (rc0) {
+      cleanup();
+      return rc0;
+    }
+  }
+  const std::function<int(const double*, double*, int)> base_a = ops.A;
+  if (nh && !o.largest) {
+    ops.A = [&, base_a](const double* x, double* y, int ncol) -> int {
+      if (int rc = base_a(x, y, ncol)) return rc;
+      std::vector<double> cf((size_t)nh * ncol);
+      if (eig_gram(BH, nh, x, ncol, n1, cf.data(), gw, nb1, s)) return hip_fail(hipGetLastError(), "eigen-solver gram");
+      for (int j = 0; j < ncol; ++j)
+        for (int a = 0; a < nh; ++a) {
+          double w = 0.0;
+          for (int b = 0; b < nh; ++b) w += ghi[(size_t)a * nh + b] * cf[(size_t)b * ncol + j];
+          launch_axpy_diag(colp(y, n1, j), 1.0, c2 * o.grad_shift * w, nullptr, BH + (long long)a * n1, n1, nb1, s);
+        }
+      return 0;
+    };
+  }
   launch_rhs_normal(X, 0, n1 * k, o.seed, vec_grid(n1 * k, mx->ctx->ncu), s);
   std::vector<double> lam(k);
   EigResult er;
@@ -480,6 +554,8 @@ int gym_maxwell_spai_op(gym_maxwell* mx, int nprobe, const double* probes, doubl
   if (!mx || nprobe < 0 || (nprobe > 0 && !probes) || !(lambda >= 0) || !(rtol > 0) || maxit < 1)
     return fail(GYM_E_ARG, "bad SPAI-OP arguments");
   if (mx->mesh->curved) return fail(GYM_E_UNSUPPORTED, "SPAI-OP needs an affine mesh");
+  if (mx->mesh->periodic || mx->mesh->dim != 3)
+    return fail(GYM_E_UNSUPPORTED, "SPAI-OP is built for the 3-D perfect conductor");
   hipStream_t s = (hipStream_t)stream;
   const long long n1 = mx->n1;
   const double c2 = mx->o.c * mx->o.c;

@@ -377,10 +377,13 @@ __device__ __forceinline__ void op_body(const OpParams& p, int bx, int by, int b
 
   // Inputs of a layer are loaded into registers one layer ahead (a thread
   // holds at most KMAX values per field), so the global loads of layer ez + 1
-  // are in flight while layer ez is computed.  Only for workgroups of up to
-  // 512 threads: wider ones are already at their register limit, and the
-  // extra registers spill to scratch (measured slower).
-  constexpr bool PREFETCH = C::NT <= 512;
+  // are in flight while layer ez is computed.  For workgroups of up to 512
+  // threads, and for the curved form (its contraction tables are immediates,
+  // which leaves the registers for it; the perturbed 96^3 degree-3 apply
+  // measured 6% faster).  The wider Kronecker and Gauss-point workgroups are
+  // at their register limit: there the extra registers spill to scratch
+  // (measured slower).
+  constexpr bool PREFETCH = C::NT <= 512 || FORM == FORM_CURVED;
   constexpr int KMAX = PREFETCH ? max_per_thread<C, F>() : 1;
   TC pre[F::NF][KMAX];
   auto prefetch = [&](int ez) {
@@ -787,13 +790,15 @@ inline int op_tiling(OpParams& p, int B, int dim, int nrhs, int ncu, int mode, i
 // LDS latency).  Measured on MI355X at about 8M unknowns per operator for
 // 512, 768 and 1024 threads: degree 1 has too little work per stage for more
 // than 512; Gauss-point and the FP32/BF16 Kronecker contractions gain up to
-// 1024; the FP64 Kronecker Hodge kernel at degree >= 3 and the curved kernels
-// run out of registers beyond 768.
+// 1024; the FP64 Kronecker Hodge kernel at degree >= 3 runs out of registers
+// beyond 768.  The curved kernels fit 1024 threads (at most 128 VGPRs, no
+// scratch) since their tables are immediates: the perturbed 96^3 degree-3
+// apply took 48.5 ms at 1024 against 53.1 ms at 768.
 template <int DIM, int R, int PROB, int FORM, typename TC>
 constexpr int big_threads() {
   if (DIM == 2 || PROB >= PROB_MASS_H1) return 512;
   if (R == 1) return FORM == FORM_CURVED ? 768 : 512;
-  if (FORM == FORM_CURVED) return 768;
+  if (FORM == FORM_CURVED) return 1024;
   if (FORM == FORM_GAUSS) return 1024;
   if (FORM == FORM_KRON && std::is_same<TC, double>::value) return (PROB == PROB_HODGE && R >= 3) ? 768 : 1024;
   return R == 2 ? 768 : 1024;

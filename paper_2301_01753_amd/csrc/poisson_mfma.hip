@@ -17,9 +17,9 @@
 //
 // The element results go to an element-local buffer (row-major over local
 // rows, elements contiguous, so every store of a batch is coalesced); a second
-// kernel sums the contributions of each global unknown in a fixed order (the
-// lower element first, at most two for a flux unknown on an element face) and
-// writes y: deterministic, no atomics.  With the fused MINRES step it also
+// kernel, one thread per global unknown, sums its contributions in a fixed
+// order (the lower element first, at most two for a flux unknown on an
+// element face) and writes y: deterministic, no atomics.  With the fused MINRES step it also
 // adds z . A z per block.
 //
 // Lane layouts (gfx950, checked on the device): A is 32 x 16 with lane l
@@ -186,12 +186,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) el
 }
 
 // Sum the element contributions of every global unknown into y: one thread
-// per (element-local row, element), elements contiguous, so every read of the
-// element buffer is coalesced.  A flux row on an element's lower face (normal
-// index 0) adds the lower neighbour's upper-face row first, then its own; a
-// row on the upper face is written only at the domain's upper boundary (the
-// next element's lower-face thread writes it otherwise); every other row is
-// the only contribution.  With MR also partial sums of z . (A z) per block.
+// per unknown, in the vector's own order, so every store of y is coalesced and
+// each 64-byte line of it is written once; the reads of the element buffer come
+// as a few contiguous runs per wavefront (a run per local row, elements
+// contiguous).  A flux unknown on an interior face (normal position a multiple
+// of r, not on the boundary) sums the lower element's upper-face row and the
+// upper element's lower-face row, in that order; every other unknown has one
+// contribution.  With MR also partial sums of z . (A z) per block.
 template <int R, bool MR>
 __global__ void __launch_bounds__(256) gather_kernel(const float* __restrict__ x, float* __restrict__ y,
                                                      const float* __restrict__ yel, PoissonMfmaParams q) {
@@ -200,52 +201,45 @@ __global__ void __launch_bounds__(256) gather_kernel(const float* __restrict__ x
   const float* yr = yel + (long long)rhs * q.el_stride;
   const long long off = (long long)rhs * q.ndofs;
   const long long E = q.el_rows;
-  const long long total = (long long)D::ROWS * E;
+  const unsigned n0 = (unsigned)q.nel[0], n01 = (unsigned)q.nel[0] * (unsigned)q.nel[1];
   double acc = 0.0;
-  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total; t += (long long)gridDim.x * 256) {
-    const int row = (int)(t / E);
-    const long long e = t - (long long)row * E;
-    const int ex = (int)(e % q.nel[0]);
-    const long long et = e / q.nel[0];
-    const int ey = (int)(et % q.nel[1]), ez = (int)(et / q.nel[1]);
-    const int ec[3] = {ex, ey, ez};
-    long long g;
+  for (long long g = (long long)blockIdx.x * 256 + threadIdx.x; g < q.ndofs; g += (long long)gridDim.x * 256) {
     float v;
-    if (row >= 3 * D::NF) {
-      const int k = row - 3 * D::NF;
-      const int ix = k % R, iy = (k / R) % R, iz = k / (R * R);
-      g = q.np_off + (R * ex + ix) + (long long)q.m[0] * ((R * ey + iy) + (long long)q.m[1] * (R * ez + iz));
-      v = yr[(long long)row * E + e];
+    if (g >= q.np_off) {
+      const unsigned idx = (unsigned)(g - q.np_off);
+      const unsigned m0 = (unsigned)q.m[0], m1 = (unsigned)q.m[1];
+      const unsigned px = idx % m0, t = idx / m0, py = t % m1, pz = t / m1;
+      const long long e = (long long)(px / R) + n0 * (py / R) + (long long)n01 * (pz / R);
+      const int k = (int)(px % R) + R * ((int)(py % R) + R * (int)(pz % R));
+      v = yr[(long long)(3 * D::NF + k) * E + e];
     } else {
-      const int c = row / D::NF, k = row - c * D::NF;
-      const int i_n = k % (R + 1), tt = k / (R + 1);
-      const int i_1 = tt % R, i_2 = tt / R;
-      const int nc = c == 0 ? q.nel[0] : (c == 1 ? q.nel[1] : q.nel[2]);
-      const int ecc = c == 0 ? ex : (c == 1 ? ey : ez);
-      if (i_n == R && ecc != nc - 1) continue;
-      const long long se = c == 0 ? 1 : (c == 1 ? (long long)q.nel[0] : (long long)q.nel[0] * q.nel[1]);
-      v = yr[(long long)row * E + e];
-      if (i_n == 0 && ecc > 0) v = yr[(long long)(row + R) * E + (e - se)] + v;
-      const int a1 = (c + 1) % 3, a2 = (c + 2) % 3;
-      int p[3];
-      p[0] = p[1] = p[2] = 0;
-      // lattice position of this row (nodal along c, edge along a1, a2)
-      const int pc = R * ecc + i_n, p1 = R * ec[a1] + i_1, p2 = R * ec[a2] + i_2;
-      if (c == 0) {
-        p[0] = pc;
-        p[1] = p1;
-        p[2] = p2;
-      } else if (c == 1) {
-        p[1] = pc;
-        p[2] = p1;
-        p[0] = p2;
-      } else {
-        p[2] = pc;
-        p[0] = p1;
-        p[1] = p2;
-      }
+      const int c = g >= q.s.c[2].offset ? 2 : (g >= q.s.c[1].offset ? 1 : 0);
       const DevComp& cd = q.s.c[c];
-      g = cd.offset + p[0] + (long long)cd.count[0] * (p[1] + (long long)cd.count[1] * p[2]);
+      const unsigned idx = (unsigned)(g - cd.offset);
+      const unsigned c0 = (unsigned)cd.count[0], c1 = (unsigned)cd.count[1];
+      const unsigned q0 = idx % c0, t = idx / c0, q1 = t % c1, q2 = t / c1;
+      // positions along the normal axis c and the tangential axes c+1, c+2
+      const unsigned pn = c == 0 ? q0 : (c == 1 ? q1 : q2);
+      const unsigned pt1 = c == 0 ? q1 : (c == 1 ? q2 : q0);
+      const unsigned pt2 = c == 0 ? q2 : (c == 1 ? q0 : q1);
+      const int nc = c == 0 ? q.nel[0] : (c == 1 ? q.nel[1] : q.nel[2]);
+      int en = (int)(pn / R), i_n = (int)(pn % R);
+      if (en == nc) {  // upper boundary face: the last element's upper row
+        en = nc - 1;
+        i_n = R;
+      }
+      const unsigned e1 = pt1 / R, e2 = pt2 / R;
+      const int i_1 = (int)(pt1 % R), i_2 = (int)(pt2 % R);
+      const unsigned ex = c == 0 ? (unsigned)en : (c == 1 ? e2 : e1);
+      const unsigned ey = c == 0 ? e1 : (c == 1 ? (unsigned)en : e2);
+      const unsigned ez = c == 0 ? e2 : (c == 1 ? e1 : (unsigned)en);
+      const long long e = (long long)ex + (long long)n0 * ey + (long long)n01 * ez;
+      const int row = c * D::NF + flux_local(R, i_n, i_1, i_2);
+      v = yr[(long long)row * E + e];
+      if (i_n == 0 && en > 0) {
+        const long long se = c == 0 ? 1 : (c == 1 ? (long long)n0 : (long long)n01);
+        v = yr[(long long)(row + R) * E + (e - se)] + v;
+      }
     }
     y[off + g] = v;
     if constexpr (MR) acc += (double)x[off + g] * (double)v;

@@ -37,20 +37,18 @@ constexpr int kGT = 256; // threads
 // x axis (contiguous in memory) and along the lines for y and z.  Every
 // kernel here does nothing for a right-hand side whose Krylov state in `gate`
 // (if given) has converged.
+// Block (bx: line block, by: output block) of the transform of one vector.
 template <int AX, typename T>
-__global__ void __launch_bounds__(kGT) axis_gemm(const T* __restrict__ in, T* __restrict__ out,
-                                                 const T* __restrict__ A, int m0, int m1, int m2, long long vin,
-                                                 long long vout, const MinresState* gate) {
+__device__ __forceinline__ void axis_gemm_block(const T* __restrict__ in, T* __restrict__ out,
+                                                const T* __restrict__ A, int m0, int m1, int m2, long long bx,
+                                                int by) {
   __shared__ T s_in[kTK][kTL + 4];
   __shared__ T sa[kTK][kTI + 4];
-  if (gate && gate[blockIdx.z].done) return;
   const int ma = AX == 0 ? m0 : (AX == 1 ? m1 : m2);
   const long long nlines = (long long)m0 * m1 * m2 / ma;
   const long long stride = AX == 0 ? 1 : (AX == 1 ? (long long)m0 : (long long)m0 * m1);
-  const long long L0 = (long long)blockIdx.x * kTL;
-  const int i0 = blockIdx.y * kTI;
-  in += (long long)blockIdx.z * vin;
-  out += (long long)blockIdx.z * vout;
+  const long long L0 = bx * kTL;
+  const int i0 = by * kTI;
   // memory offset of the first entry of line L
   auto base = [&](long long L) -> long long {
     if (AX == 0) return L * m0;
@@ -113,6 +111,15 @@ __global__ void __launch_bounds__(kGT) axis_gemm(const T* __restrict__ in, T* __
   }
 }
 
+template <int AX, typename T>
+__global__ void __launch_bounds__(kGT) axis_gemm(const T* __restrict__ in, T* __restrict__ out,
+                                                 const T* __restrict__ A, int m0, int m1, int m2, long long vin,
+                                                 long long vout, const MinresState* gate) {
+  if (gate && gate[blockIdx.z].done) return;
+  axis_gemm_block<AX, T>(in + (long long)blockIdx.z * vin, out + (long long)blockIdx.z * vout, A, m0, m1, m2,
+                         blockIdx.x, blockIdx.y);
+}
+
 // y[i, j, k] *= scale / (lam0[i] + lam1[j] + lam2[k]) on the cell lattice
 template <typename T>
 __global__ void __launch_bounds__(256) lam_scale(T* __restrict__ y, const double* __restrict__ lam, int m0, int m1,
@@ -148,7 +155,94 @@ void axis_launch(const T* in, long long vin, T* out, long long vout, const T* A,
   hipLaunchKernelGGL((axis_gemm<AX, T>), grid, dim3(kGT), 0, s, in, out, A, m[0], m[1], m[2], vin, vout, gate);
 }
 
+__device__ __forceinline__ int item_of(const int* start, int nitem, int blk) {
+  int lo = 0, hi = nitem;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= blk) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Ragged batch, elementwise parts: stage 0 the flux diagonal, stage 1 the
+// division by the eigenvalue sums, stage 2 the partial sums y . z, z . r2.
+template <int STAGE>
+__global__ void __launch_bounds__(256) schur_batch_elem(const SchurItem* items, const int* start, int nitem) {
+  __shared__ double sh[2 * 256];
+  const int i = item_of(start, nitem, blockIdx.x);
+  const SchurItem& it = items[i];
+  if (it.gate && it.gate->done) return;
+  const int blk = blockIdx.x - start[i];
+  const long long stride = (long long)it.nb * 256;
+  if constexpr (STAGE == 0) {
+    for (long long g = (long long)blk * 256 + threadIdx.x; g < it.ns; g += stride) it.z[g] = it.dsinv[g] * it.y[g];
+  } else if constexpr (STAGE == 1) {
+    const int m0 = it.m[0], m1 = it.m[1];
+    for (long long g = (long long)blk * 256 + threadIdx.x; g < it.np; g += stride) {
+      const int a = (int)(g % m0);
+      const long long r = g / m0;
+      const int b = (int)(r % m1), c = (int)(r / m1);
+      it.w0[g] *= it.scale / (it.lam[a] + it.lam[m0 + b] + it.lam[m0 + m1 + c]);
+    }
+  } else {
+    const long long n = it.ns + it.np;
+    double a = 0.0, c = 0.0;
+    for (long long g = (long long)blk * 256 + threadIdx.x; g < n; g += stride) {
+      const double zi = it.z[g];
+      a += it.y[g] * zi;
+      c += zi * it.r2[g];
+    }
+    double t[2] = {a, c};
+    wg_sums<256, 2>(t, sh);
+    if (threadIdx.x == 0) {
+      it.pb[blk] = t[0];
+      it.pc[blk] = t[1];
+    }
+  }
+}
+
+// Ragged batch, one 1-D transform along AX: FWD y_p -> w0 (x), w0 -> w1 (y),
+// w1 -> w0 (z); backward w0 -> w1 (z), w1 -> w0 (y), w0 -> z_p (x).
+template <int AX, bool FWD>
+__global__ void __launch_bounds__(kGT) schur_batch_axis(const SchurItem* items, const int* start, int nitem) {
+  const int i = item_of(start, nitem, blockIdx.x);
+  const SchurItem& it = items[i];
+  if (it.gate && it.gate->done) return;
+  const int blk = blockIdx.x - start[i];
+  const int nob = (it.m[AX] + kTI - 1) / kTI;
+  const double* in;
+  double* out;
+  if constexpr (FWD) {
+    in = AX == 0 ? it.y + it.ns : (AX == 1 ? it.w0 : it.w1);
+    out = AX == 0 ? it.w0 : (AX == 1 ? it.w1 : it.w0);
+  } else {
+    in = AX == 2 ? it.w0 : (AX == 1 ? it.w1 : it.w0);
+    out = AX == 2 ? it.w1 : (AX == 1 ? it.w0 : it.z + it.ns);
+  }
+  axis_gemm_block<AX, double>(in, out, FWD ? it.fwd[AX] : it.bwd[AX], it.m[0], it.m[1], it.m[2], blk / nob,
+                              blk % nob);
+}
+
 }  // namespace
+
+int schur_axis_blocks(const SchurItem& it, int a) {
+  const long long nlines = (long long)it.m[0] * it.m[1] * it.m[2] / it.m[a];
+  return (int)(((nlines + kTL - 1) / kTL) * ((it.m[a] + kTI - 1) / kTI));
+}
+
+void launch_schur_batch(const SchurItem* items, int nitem, const int* est, int ne, const int* const ast[3],
+                        const int na[3], hipStream_t s) {
+  hipLaunchKernelGGL((schur_batch_elem<0>), dim3(ne), dim3(256), 0, s, items, est, nitem);
+  hipLaunchKernelGGL((schur_batch_axis<0, true>), dim3(na[0]), dim3(kGT), 0, s, items, ast[0], nitem);
+  hipLaunchKernelGGL((schur_batch_axis<1, true>), dim3(na[1]), dim3(kGT), 0, s, items, ast[1], nitem);
+  hipLaunchKernelGGL((schur_batch_axis<2, true>), dim3(na[2]), dim3(kGT), 0, s, items, ast[2], nitem);
+  hipLaunchKernelGGL((schur_batch_elem<1>), dim3(ne), dim3(256), 0, s, items, est, nitem);
+  hipLaunchKernelGGL((schur_batch_axis<2, false>), dim3(na[2]), dim3(kGT), 0, s, items, ast[2], nitem);
+  hipLaunchKernelGGL((schur_batch_axis<1, false>), dim3(na[1]), dim3(kGT), 0, s, items, ast[1], nitem);
+  hipLaunchKernelGGL((schur_batch_axis<0, false>), dim3(na[0]), dim3(kGT), 0, s, items, ast[0], nitem);
+  hipLaunchKernelGGL((schur_batch_elem<2>), dim3(ne), dim3(256), 0, s, items, est, nitem);
+}
 
 template <typename T>
 int launch_schur_apply(const SchurPrec& P, const T* y, T* z, int nrhs, int nb, hipStream_t s,

@@ -49,6 +49,35 @@ int schur_build(const gym_op* op, SchurPrec* out);
 // allocates outside its hot loop).
 int schur_reserve(SchurPrec* P, int nrhs, size_t elem_bytes);
 void schur_free(SchurPrec* P);
+// One request of a ragged batch of FP64 preconditioner applies (serving):
+// z = P^-1 y for one right-hand side, with the request's own work vectors,
+// followed by the partial sums pb = y . z and pc = z . r2 per elementwise
+// block (nb of them), as minres_launch_dot2 forms them.
+struct SchurItem {
+  long long ns, np;
+  int m[3];
+  int nb;                   // blocks of this item in the elementwise kernels
+  double scale;
+  const double* dsinv;
+  const double* lam;
+  const double* fwd[3];
+  const double* bwd[3];
+  const double* y;
+  double* z;
+  double* w0;               // np
+  double* w1;               // np
+  const double* r2;
+  double* pb;
+  double* pc;
+  const MinresState* gate;  // skip the item once this state has converged
+};
+// Blocks of item it in the transform along axis a (64 lines x 64 outputs each).
+int schur_axis_blocks(const SchurItem& it, int a);
+// The batch on the device: items_dev[nitem]; est: prefix sums of the items'
+// nb; ast[a]: prefix sums of schur_axis_blocks(., a) (nitem + 1 entries each).
+void launch_schur_batch(const SchurItem* items_dev, int nitem, const int* est, int ne, const int* const ast[3],
+                        const int na[3], hipStream_t s);
+
 // The operator's preconditioner, set up on first use and kept with the
 // operator (freed with it), with work vectors for nrhs right-hand sides.
 int ensure_schur(gym_op* op, int nrhs, SchurPrec** out);

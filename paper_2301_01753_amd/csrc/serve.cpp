@@ -15,8 +15,8 @@
 //      requests (true FP64 residual, optional copy of the solution) and
 //      returns their vectors to the pool, so queued requests can enter the
 //      mix.
-// With the block preconditioner (mixed Poisson) each request's step adds its
-// preconditioner launches after the batched second half.
+// With the block preconditioner (mixed Poisson) each step adds one ragged
+// batch of preconditioner applies over the requests that use it.
 // Every request keeps its own blocks, partial sums and scalar state, so its
 // iterates are the same whether it runs alone or in any mix.
 #include <hip/hip_runtime.h>
@@ -117,6 +117,7 @@ struct Pending {
   int64_t n;
   size_t bytes;       // vectors + operator (budget check)
   size_t slot_bytes;  // vectors (pool block)
+  int64_t np;         // cell unknowns (block preconditioner work vectors)
 };
 
 struct Slot {
@@ -130,6 +131,7 @@ struct Slot {
   int npa;  // operator workgroups of the last step
   size_t bytes;
   SchurPrec* schur;  // block preconditioner, or null (Jacobi)
+  double *sw0, *sw1;  // its work vectors (cell block), in the slot's own memory
   double *b, *x;
   double *r1, *r2, *y, *z, *zp, *w, *w1, *w2;  // current roles
   double *pa, *pb[2], *pc[2], *alfa[2];         // step partials (two alternating sets)
@@ -201,6 +203,10 @@ struct gym_server {
   int* bst_d[kStages] = {};
   MrItem* items_h[kStages] = {};
   MrItem* items_d[kStages] = {};
+  SchurItem* sitems_h[kStages] = {};  // block preconditioner batch
+  SchurItem* sitems_d[kStages] = {};
+  int* stab_h[kStages] = {};          // its block tables: elementwise, then axes 0..2
+  int* stab_d[kStages] = {};
   int* ibst_h[kStages] = {};
   int* ibst_d[kStages] = {};
   hipEvent_t ev[kStages] = {};
@@ -289,6 +295,7 @@ int admit(gym_server* s, Pending& p) {
   sl->n = p.n;
   sl->nb = vec_grid(p.n, s->ctx->ncu);
   sl->bytes = p.slot_bytes;
+  sl->sw0 = sl->sw1 = nullptr;
   double* base = (double*)sl->mem;
   double** vecs[10] = {&sl->b, &sl->x, &sl->r1, &sl->r2, &sl->y, &sl->z, &sl->zp, &sl->w, &sl->w1, &sl->w2};
   for (int k = 0; k < 10; ++k) *vecs[k] = base + (size_t)k * p.n;
@@ -303,6 +310,10 @@ int admit(gym_server* s, Pending& p) {
   }
   sl->scratch = q;
   sl->sums = q + sl->nb;
+  if (sl->schur) {
+    sl->sw0 = q + sl->nb + 2;
+    sl->sw1 = sl->sw0 + p.np;
+  }
   sl->R0[0] = sl->r1, sl->R0[1] = sl->r2, sl->R0[2] = sl->y;
   sl->Z0[0] = sl->z, sl->Z0[1] = sl->zp;
   sl->W0[0] = sl->w, sl->W0[1] = sl->w1, sl->W0[2] = sl->w2;
@@ -396,15 +407,50 @@ int step(gym_server* s) {
   GYM_HIP(hipMemcpyAsync(s->ibst_d[st], s->ibst_h[st], sizeof(int) * (na + 1), hipMemcpyHostToDevice, s->stream));
   launch_batch_step2(s->items_d[st], s->ibst_d[st], na, nblocks, s->stream);
   // block-preconditioned requests: z_{k+1} = P^-1 y over zp and the partial
-  // sums the second half left out (nothing once the request has converged:
-  // its buffers must stay as they were for a resumed recurrence)
-  for (Slot* sl : s->active) {
-    if (!sl->schur) continue;
-    const MinresState* cur = s->d_states + 2 * sl->sidx + (sl->it & 1);
-    if (launch_schur_apply<double>(*sl->schur, sl->y, sl->zp, 1, sl->nb, s->stream, cur))
-      return fail(GYM_E_HIP, "serving: preconditioner launch failed");
-    minres_launch_dot2<double>(sl->y, sl->zp, sl->r2, sl->n, 1, sl->nb, sl->pb[sl->par ^ 1], sl->pc[sl->par ^ 1],
-                               s->stream, cur);
+  // sums the second half left out, one ragged batch over all of them (nothing
+  // for a request that has converged: its buffers must stay as they were for
+  // a resumed recurrence)
+  {
+    const int maxs = s->opts.max_slots;
+    SchurItem* items = s->sitems_h[st];
+    int* et = s->stab_h[st];
+    int* at[3] = {et + (maxs + 1), et + 2 * (maxs + 1), et + 3 * (maxs + 1)};
+    int k = 0;
+    et[0] = at[0][0] = at[1][0] = at[2][0] = 0;
+    for (Slot* sl : s->active) {
+      if (!sl->schur) continue;
+      const SchurPrec& P = *sl->schur;
+      SchurItem& it = items[k];
+      it.ns = P.ns;
+      it.np = P.np;
+      for (int a = 0; a < 3; ++a) {
+        it.m[a] = P.m[a];
+        it.fwd[a] = P.fwd64[a];
+        it.bwd[a] = P.bwd64[a];
+      }
+      it.nb = sl->nb;
+      it.scale = P.scale;
+      it.dsinv = P.dsinv;
+      it.lam = P.lam;
+      it.y = sl->y;
+      it.z = sl->zp;
+      it.w0 = sl->sw0;
+      it.w1 = sl->sw1;
+      it.r2 = sl->r2;
+      it.pb = sl->pb[sl->par ^ 1];
+      it.pc = sl->pc[sl->par ^ 1];
+      it.gate = s->d_states + 2 * sl->sidx + (sl->it & 1);
+      et[k + 1] = et[k] + it.nb;
+      for (int a = 0; a < 3; ++a) at[a][k + 1] = at[a][k] + schur_axis_blocks(it, a);
+      ++k;
+    }
+    if (k > 0) {
+      GYM_HIP(hipMemcpyAsync(s->sitems_d[st], items, sizeof(SchurItem) * k, hipMemcpyHostToDevice, s->stream));
+      GYM_HIP(hipMemcpyAsync(s->stab_d[st], et, sizeof(int) * 4 * (maxs + 1), hipMemcpyHostToDevice, s->stream));
+      const int* atd[3] = {s->stab_d[st] + (maxs + 1), s->stab_d[st] + 2 * (maxs + 1), s->stab_d[st] + 3 * (maxs + 1)};
+      const int na[3] = {at[0][k], at[1][k], at[2][k]};
+      launch_schur_batch(s->sitems_d[st], k, s->stab_d[st], et[k], atd, na, s->stream);
+    }
   }
   GYM_HIP(hipEventRecord(s->ev[st], s->stream));
   GYM_HIP(hipGetLastError());
@@ -619,6 +665,10 @@ int gym_serve_start(const gym_serve_opts* opts, gym_server** out) {
     GYM_HIP(hipMalloc(&s->items_d[k], sizeof(MrItem) * maxs));
     GYM_HIP(hipHostMalloc((void**)&s->ibst_h[k], sizeof(int) * (maxs + 1), hipHostMallocDefault));
     GYM_HIP(hipMalloc(&s->ibst_d[k], sizeof(int) * (maxs + 1)));
+    GYM_HIP(hipHostMalloc((void**)&s->sitems_h[k], sizeof(SchurItem) * maxs, hipHostMallocDefault));
+    GYM_HIP(hipMalloc(&s->sitems_d[k], sizeof(SchurItem) * maxs));
+    GYM_HIP(hipHostMalloc((void**)&s->stab_h[k], sizeof(int) * 4 * (maxs + 1), hipHostMallocDefault));
+    GYM_HIP(hipMalloc(&s->stab_d[k], sizeof(int) * 4 * (maxs + 1)));
     GYM_HIP(hipEventCreate(&s->ev[k]));
     GYM_HIP(hipEventRecord(s->ev[k], s->stream));
   }
@@ -638,7 +688,11 @@ int gym_serve_submit(gym_server* s, const gym_request* req, uint64_t* id) {
   p.req = *req;
   p.n = request_ndofs(*req);
   p.bytes = request_bytes(p.n, req->nel, s->ctx->ncu);
-  p.slot_bytes = sizeof(double) * slot_doubles(p.n, req->nel, vec_grid(p.n, s->ctx->ncu));
+  // with the block preconditioner: two cell-block work vectors of its own
+  p.np = (int64_t)req->degree * req->nel * (int64_t)req->degree * req->nel * (int64_t)req->degree * req->nel;
+  const size_t extra = s->opts.precond == GYM_PRECOND_SCHUR ? 2 * (size_t)p.np : 0;
+  p.slot_bytes = sizeof(double) * (slot_doubles(p.n, req->nel, vec_grid(p.n, s->ctx->ncu)) + extra);
+  p.bytes += sizeof(double) * extra;
   if (p.bytes > (size_t)s->opts.mem_budget) return fail(GYM_E_OOM, "request exceeds the server's memory budget");
   if (req->rhs) p.rhs.assign(req->rhs, req->rhs + p.n);
   p.req.rhs = nullptr;
@@ -697,6 +751,10 @@ int gym_serve_stop(gym_server* s) {
     (void)hipFree(s->items_d[k]);
     (void)hipHostFree(s->ibst_h[k]);
     (void)hipFree(s->ibst_d[k]);
+    (void)hipHostFree(s->sitems_h[k]);
+    (void)hipFree(s->sitems_d[k]);
+    (void)hipHostFree(s->stab_h[k]);
+    (void)hipFree(s->stab_d[k]);
     (void)hipEventDestroy(s->ev[k]);
   }
   (void)hipFree(s->d_states);

@@ -19,12 +19,14 @@ struct SpaiComp {
   long long offset;  // first unknown of the block
   int count[3];      // kept lattice positions per axis
   int w;             // half bandwidth of the 1-D factors
+  int wrap;          // bit a: axis a is periodic (row i, offset k couples i and (i + k) mod count)
   double scale;
   const double* band[2][3];
 };
 struct SpaiParams {
-  SpaiComp c[3];
-  long long n;     // unknowns of Lambda^1
+  SpaiComp c[3];   // unused components: offset = n
+  long long n;     // unknowns of the space
+  int terms;       // 2: the symmetrised pair of Kronecker terms; 1: the first only
   double* tmp[2];  // two n-vectors of scratch for the axis passes of the apply
 };
 
@@ -38,6 +40,14 @@ struct SpaiParams {
 // with Q_a the 1-D SPAI of M_a.  The bands and the apply's scratch go to one
 // device allocation, returned in *mem (the caller frees it).
 int build_spai_q1(const gym_space* s1, int pattern, SpaiParams* out, double** mem);
+// The mass matrix of an affine space as one Kronecker term of assembled 1-D
+// masses (scale: the component's metric constant), applied by the same band
+// passes; used for spaces with a periodic axis.  Same ownership as above.
+int build_band_mass(const gym_space* sp, SpaiParams* out, double** mem);
+// 1-D diagonals and row sums of the assembled masses of a space along axis a
+// (nodal or edge, with the space's wrap), for Jacobi and lumped masses.
+void mass1d_diag_rowsum(int r, int nel, bool nodal, int start, int count, bool periodic, std::vector<double>& diag,
+                        std::vector<double>& rowsum);
 // y = Q1 x, as six 1-D band passes (three per Kronecker term) through the
 // scratch in p; x and y must not overlap, and applies sharing p must not
 // run concurrently.
@@ -46,6 +56,10 @@ void launch_spai_apply(const SpaiParams& p, const double* x, double* y, int nb, 
 // Assembled 1-D mass of nel elements of degree r on the reference element,
 // nodal (r nel + 1 positions) or edge (r nel), restricted to [start, start +
 // count): row-major band of half width r, A[i][k + r] = A_{i, i+k}.
-std::vector<double> mass1d_band(int r, int nel, bool nodal, int start, int count);
+// periodic: positions wrap modulo count (= r nel); an entry coupling i and j
+// sits in row i at the raw offset k = j - i of its element (|k| <= r), so
+// that entries which wrap onto the same column (count <= 2r) are kept apart
+// and summed by the apply.
+std::vector<double> mass1d_band(int r, int nel, bool nodal, int start, int count, bool periodic = false);
 
 }  // namespace gym

@@ -109,12 +109,13 @@ Tables1D make_tables(int r, int q) {
   return t;
 }
 
-SpaceDesc make_space_desc(int kind, int dim, const int64_t nel[3], int r, int bc) {
+SpaceDesc make_space_desc(int kind, int dim, const int64_t nel[3], int r, int bc, int periodic) {
   SpaceDesc s;
   s.kind = kind;
   s.dim = dim;
   s.r = r;
   s.bc = bc;
+  s.periodic = periodic & ((1 << dim) - 1);
   for (int a = 0; a < 3; ++a) s.m[a] = a < dim ? r * nel[a] : 1;
   int full = (1 << dim) - 1;
   if (kind == GYM_H1 || kind == GYM_L2) {
@@ -133,6 +134,9 @@ SpaceDesc make_space_desc(int kind, int dim, const int64_t nel[3], int r, int bc
       if (a >= dim) {
         cd.start[a] = 0;
         cd.count[a] = 1;
+      } else if (s.periodic >> a & 1) {  // m_a positions, the last wrapping onto the first
+        cd.start[a] = 0;
+        cd.count[a] = s.m[a];
       } else if (cd.nodal_mask >> a & 1) {
         if (bc == GYM_BC_ESSENTIAL) {
           cd.start[a] = 1;

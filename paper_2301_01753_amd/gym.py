@@ -105,6 +105,7 @@ SIGNATURES = {
     "gym_mesh_structured": (_I, [_P, _I, ctypes.POINTER(_I64), _P, _P, ctypes.c_double, ctypes.c_uint64,
                                  ctypes.POINTER(_P)]),
     "gym_mesh_vertices": (_I, [_P, _P]),
+    "gym_mesh_set_periodic": (_I, [_P, _I]),
     "gym_mesh_destroy": (_I, [_P]),
     "gym_space_create": (_I, [_P, _P, _I, _I, _I, ctypes.POINTER(_P)]),
     "gym_space_ndofs": (_I64, [_P]),
@@ -239,6 +240,11 @@ def gym_mesh_structured(ctx, dim, nel, perturb_frac=0.0, seed=0, lo=None, hi=Non
     _check(lib().gym_mesh_structured(ctx, dim, n, ctypes.cast(lo_a, _P), ctypes.cast(hi_a, _P), float(perturb_frac),
                                      ctypes.c_uint64(seed), ctypes.byref(h)))
     return h
+
+
+def gym_mesh_set_periodic(mesh, mask):
+    """Axes in mask (bit a: axis a) become periodic (gym.h)."""
+    _check(lib().gym_mesh_set_periodic(mesh, int(mask)))
 
 
 def gym_mesh_vertices(mesh, nel):

@@ -38,8 +38,11 @@ def g():
     gym.gym_destroy(ctx)
 
 
+# the last three have one axis of 52 cells: its transform spans a 64-wide
+# output tile with a ragged tail
 CASES = [((3, 4, 2), 1, None), ((3, 4, 2), 2, (1.0, 1.3, 0.7)), ((2, 3, 2), 3, None), ((2, 2, 3), 4, None),
-         ((5, 3, 4), 2, (2.0, 1.0, 0.5))]
+         ((5, 3, 4), 2, (2.0, 1.0, 0.5)), ((13, 2, 3), 4, None), ((2, 13, 1), 4, (1.0, 2.0, 0.5)),
+         ((1, 2, 13), 4, None)]
 
 
 @pytest.mark.parametrize("nel,r,hi", CASES)
@@ -65,7 +68,7 @@ def test_schur_apply_matches_oracle(g, nel, r, hi):
 
 
 @pytest.mark.parametrize("mode,tol", [("F64", 1e-10), ("IR_F32", 1e-8), ("IR_BF16", 1e-8)])
-@pytest.mark.parametrize("nel,r", [((4, 3, 5), 2), ((3, 3, 3), 4)])
+@pytest.mark.parametrize("nel,r", [((4, 3, 5), 2), ((3, 3, 3), 4), ((13, 2, 3), 4)])
 def test_schur_solve_matches_direct(g, nel, r, mode, tol):
     gym, ctx = g
     mesh = gym.gym_mesh_create(ctx, 3, nel)

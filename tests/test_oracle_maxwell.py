@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import synth
+from conftest import golden
 from oracle import maxwell
 from oracle.lattice import Mesh
 
@@ -187,3 +188,25 @@ def test_eigenmode_phase_rate():
     for n in range(1, 61):
         a, e = G.strang(a, e, tau, 1)
         assert abs(e @ e0 / (e0 @ e0) - np.cos(n * theta)) < 1e-10
+
+
+@pytest.mark.parametrize("q1,key", [("exact", "omega_20x20"), ("spai_diag", "spai_diag_omega_20x20"),
+                                    ("spai", "spai_m1_omega_20x20")])
+def test_periodic_torus_frequencies(q1, key):
+    # Section 7.5: the lowest non-kernel frequency of Q1 P2 on the 20 x 20
+    # periodic Whitney mesh, for exact Q1 and the two SPAI patterns, through
+    # the Gym class on periodic spaces (2-D: Lambda^2 is L2, C the 2-D curl)
+    G = maxwell.Gym(Mesh(synth.uniform_vertices((20, 20), hi=(2 * np.pi, 2 * np.pi))), 1, q1=q1, periodic=True)
+    val, tol = golden(key)
+    w = G.lowest_modes(1)
+    assert abs(np.sqrt(w[0]) - val) < tol
+
+
+def test_periodic_gym_kernel_holds_the_harmonic_fields():
+    # on the torus ker P2 is the gradients plus one constant field per axis:
+    # dim ker = (n0 - 1) + 2 in 2-D (n0: periodic nodal unknowns)
+    nel = (5, 4)
+    G = maxwell.Gym(Mesh(synth.uniform_vertices(nel)), 2, periodic=True)
+    w = G.omega2()
+    n0 = (2 * 5) * (2 * 4)
+    assert int(np.sum(w < 1e-9 * w.max())) == (n0 - 1) + 2
