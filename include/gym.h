@@ -362,8 +362,8 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree,
  * probes: device array of nprobe x ndofs doubles, the modes v_k (nprobe may be
  * 0: the optimal symmetric SPAI).  On success the object's Q1 becomes this
  * SPAI-OP (GYM_Q1_SPAI_OP) for the time stepping, the energy and the
- * eigen-solver.  Affine 3-D meshes without periodic axes only
- * (GYM_E_UNSUPPORTED otherwise).  Returns GYM_W_NOT_CONVERGED (Q1 is
+ * eigen-solver.  Affine meshes only; a periodic axis needs more than 4r
+ * lattice positions (GYM_E_UNSUPPORTED otherwise).  Returns GYM_W_NOT_CONVERGED (Q1 is
  * still replaced) if maxit came before rtol; *iters and *rel_res may be NULL. */
 int gym_maxwell_spai_op(gym_maxwell* mx, int nprobe, const double* probes, double lambda, double rtol,
                         int maxit, int* iters, double* rel_res, void* stream);

@@ -554,8 +554,6 @@ int gym_maxwell_spai_op(gym_maxwell* mx, int nprobe, const double* probes, doubl
   if (!mx || nprobe < 0 || (nprobe > 0 && !probes) || !(lambda >= 0) || !(rtol > 0) || maxit < 1)
     return fail(GYM_E_ARG, "bad SPAI-OP arguments");
   if (mx->mesh->curved) return fail(GYM_E_UNSUPPORTED, "SPAI-OP needs an affine mesh");
-  if (mx->mesh->periodic || mx->mesh->dim != 3)
-    return fail(GYM_E_UNSUPPORTED, "SPAI-OP is built for the 3-D perfect conductor");
   hipStream_t s = (hipStream_t)stream;
   const long long n1 = mx->n1;
   const double c2 = mx->o.c * mx->o.c;

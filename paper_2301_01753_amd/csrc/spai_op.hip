@@ -33,6 +33,7 @@ namespace {
 struct OpComp {
   long long off;         // first row of the block
   int n[3];              // kept positions per axis
+  int wrap;              // bit a: axis a periodic (positions taken modulo n[a]; n[a] > 4r)
   double sc;             // M1 block = sc (x)_a M_a
   const double* M[3];    // n[a] x (2r + 1): M_a band
   const double* M2[3];   // n[a] x (4r + 1): (M_a^2) band
@@ -62,23 +63,43 @@ __device__ __forceinline__ void decode(const OpComp& d, long long g, int& x, int
   z = (int)(rest / d.n[1]);
 }
 
+// A position along axis a brought back into [0, n[a]) on a periodic axis
+// (shifts here are at most 2r < n[a]); unchanged otherwise.
+__device__ __forceinline__ int wrap_pos(const OpComp& d, int a, int v) {
+  if (!((d.wrap >> a) & 1)) return v;
+  const int n = d.n[a];
+  return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
 __device__ __forceinline__ long long at(const OpComp& d, int x, int y, int z) {
+  x = wrap_pos(d, 0, x);
+  y = wrap_pos(d, 1, y);
+  z = wrap_pos(d, 2, z);
   return d.off + x + (long long)d.n[0] * (y + (long long)d.n[1] * z);
 }
 
+// every position of a periodic axis is inside
 __device__ __forceinline__ bool inside(const OpComp& d, int x, int y, int z) {
-  return (unsigned)x < (unsigned)d.n[0] && (unsigned)y < (unsigned)d.n[1] && (unsigned)z < (unsigned)d.n[2];
+  return ((d.wrap & 1) || (unsigned)x < (unsigned)d.n[0]) && ((d.wrap & 2) || (unsigned)y < (unsigned)d.n[1]) &&
+         ((d.wrap & 4) || (unsigned)z < (unsigned)d.n[2]);
 }
 
-// M1_ij / sc for j = i + (dx, dy, dz) (zero off the pattern)
+// M1_ij / sc for j = i + (dx, dy, dz) (zero off the pattern); the bands hold
+// raw offsets, so on a periodic axis only the row position wraps
 __device__ __forceinline__ double m1_rel(const OpComp& d, int r, int x, int y, int z, int dx, int dy, int dz) {
   const int L = 2 * r + 1;
+  x = wrap_pos(d, 0, x);
+  y = wrap_pos(d, 1, y);
+  z = wrap_pos(d, 2, z);
   return d.M[0][(long long)x * L + dx + r] * d.M[1][(long long)y * L + dy + r] * d.M[2][(long long)z * L + dz + r];
 }
 
 // U_ij / sc^2 for j = i + (dx, dy, dz), |d_a| <= 2r
 __device__ __forceinline__ double u_rel(const OpComp& d, int r, int x, int y, int z, int dx, int dy, int dz) {
   const int L2 = 4 * r + 1;
+  x = wrap_pos(d, 0, x);
+  y = wrap_pos(d, 1, y);
+  z = wrap_pos(d, 2, z);
   return d.M2[0][(long long)x * L2 + dx + 2 * r] * d.M2[1][(long long)y * L2 + dy + 2 * r] *
          d.M2[2][(long long)z * L2 + dz + 2 * r];
 }
@@ -143,13 +164,14 @@ __global__ void __launch_bounds__(256) sylv_box(const SylvParams p, const double
         const int e_out = (t / st) % L - R;
         const int base = t - (e_out + R) * st;
         const int pp = ca + sg * e_out;
+        const bool wa = (d.wrap >> a) & 1;
         double acc = 0.0;
-        if ((unsigned)pp < (unsigned)d.n[a]) {
-          const double* band = d.M2[a] + (long long)pp * L2 + 2 * R;
+        if (wa || (unsigned)pp < (unsigned)d.n[a]) {
+          const double* band = d.M2[a] + (long long)wrap_pos(d, a, pp) * L2 + 2 * R;
 #pragma unroll
           for (int e = -R; e <= R; ++e) {
             const int qq = ca + sg * e;
-            if ((unsigned)qq < (unsigned)d.n[a]) acc += band[qq - pp] * in[k * L3 + base + (e + R) * st];
+            if (wa || (unsigned)qq < (unsigned)d.n[a]) acc += band[qq - pp] * in[k * L3 + base + (e + R) * st];
           }
         }
         o[u] = acc;
@@ -289,11 +311,12 @@ __global__ void __launch_bounds__(kRowBT) u_axis(const SylvParams p, const doubl
     decode(d, i, xyz[0], xyz[1], xyz[2]);
     const int pa = a == 0 ? xyz[0] : a == 1 ? xyz[1] : xyz[2];
     const int na = d.n[a];
+    const bool wa = (d.wrap >> a) & 1;
     const long long st = a == 0 ? 1 : a == 1 ? (long long)d.n[0] : (long long)d.n[0] * d.n[1];
     const double* band = d.M2[a] + (long long)pa * L2 + 2 * r;
     double acc = 0.0;
     for (int k = -2 * r; k <= 2 * r; ++k)
-      if ((unsigned)(pa + k) < (unsigned)na) acc += band[k] * xv[i + k * st];
+      if (wa || (unsigned)(pa + k) < (unsigned)na) acc += band[k] * xv[i + (long long)(wrap_pos(d, a, pa + k) - pa) * st];
     yv[i] = last ? d.sc * d.sc * acc : acc;
   }
 }
@@ -329,29 +352,40 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
                   int maxit, int ncu, hipStream_t s, SpaiOpQ1* out, int* iters, double* rel_res) {
   const SpaceDesc& sd = s1->desc;
   const gym_mesh* m = s1->mesh;
-  if (sd.ncomp != 3 || m->dim != 3) return fail(GYM_E_ARG, "SPAI-OP: 3-D Lambda^1 only");
+  if (sd.kind != GYM_HCURL || sd.ncomp != m->dim) return fail(GYM_E_ARG, "SPAI-OP: Lambda^1 only");
   const int r = sd.r, L = 2 * r + 1, L2 = 4 * r + 1, L3 = L * L * L;
+  for (int a = 0; a < sd.dim; ++a)
+    if (((sd.periodic >> a) & 1) && sd.m[a] <= 4 * r)
+      return fail(GYM_E_UNSUPPORTED, "SPAI-OP: a periodic axis needs more than 4r positions");
   const long long n1 = sd.ndofs, nq = n1 * L3;
   const LumpedTables lt = lumped_tables_host(s1);
   // 1-D bands of M_a and M_a^2 per component and axis
   std::vector<double> host;
-  size_t offM[3][3], offM2[3][3];
-  for (int c = 0; c < 3; ++c)
+  size_t offM[3][3] = {}, offM2[3][3] = {};
+  for (int c = 0; c < sd.ncomp; ++c)
     for (int a = 0; a < 3; ++a) {
       const CompDesc& cd = sd.comp[c];
       const int cnt = (int)cd.count[a];
-      const std::vector<double> A = mass1d_band(r, (int)m->nel[a], (cd.nodal_mask >> a) & 1, (int)cd.start[a], cnt);
-      std::vector<double> A2((size_t)cnt * L2, 0.0);
-      for (int i = 0; i < cnt; ++i)
-        for (int k = -r; k <= r; ++k) {
-          const int mm = i + k;
-          if (mm < 0 || mm >= cnt) continue;
-          for (int k2 = -r; k2 <= r; ++k2) {
-            const int j = mm + k2;
-            if (j < 0 || j >= cnt) continue;
-            A2[(size_t)i * L2 + (j - i + 2 * r)] += A[(size_t)i * L + k + r] * A[(size_t)mm * L + k2 + r];
+      const bool per = (sd.periodic >> a) & 1;
+      std::vector<double> A, A2((size_t)cnt * L2, 0.0);
+      if (a >= sd.dim) {  // no such axis: the identity (one position)
+        A.assign(L, 0.0);
+        A[r] = 1.0;
+        A2[2 * r] = 1.0;
+      } else {
+        A = mass1d_band(r, (int)m->nel[a], (cd.nodal_mask >> a) & 1, (int)cd.start[a], cnt, per);
+        for (int i = 0; i < cnt; ++i)
+          for (int k = -r; k <= r; ++k) {
+            int mm = i + k;
+            if (per) mm = mm < 0 ? mm + cnt : (mm >= cnt ? mm - cnt : mm);
+            else if (mm < 0 || mm >= cnt) continue;
+            for (int k2 = -r; k2 <= r; ++k2) {
+              // raw offset k + k2 (on a periodic axis, cnt > 4r keeps them apart)
+              if (!per && (mm + k2 < 0 || mm + k2 >= cnt)) continue;
+              A2[(size_t)i * L2 + (k + k2 + 2 * r)] += A[(size_t)i * L + k + r] * A[(size_t)mm * L + k2 + r];
+            }
           }
-        }
+      }
       offM[c][a] = host.size();
       host.insert(host.end(), A.begin(), A.end());
       offM2[c][a] = host.size();
@@ -395,7 +429,17 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
   double dmax = 0.0;  // largest diagonal of U, for the Tikhonov shift
   for (int c = 0; c < 3; ++c) {
     OpComp& d = P.c[c];
+    if (c >= sd.ncomp) {  // 2-D: no third component (never selected)
+      d.off = n1;
+      for (int a = 0; a < 3; ++a) {
+        d.n[a] = 1;
+        d.M[a] = tab + offM[0][a];
+        d.M2[a] = tab + offM2[0][a];
+      }
+      continue;
+    }
     d.off = sd.comp[c].offset;
+    d.wrap = sd.periodic;
     for (int a = 0; a < 3; ++a) {
       d.n[a] = (int)sd.comp[c].count[a];
       d.M[a] = tab + offM[c][a];
@@ -514,6 +558,7 @@ int spai_op_build(const gym_space* s1, const double* Wdev, const double* MWdev, 
   out->q = q;
   out->r = r;
   out->n1 = n1;
+  out->wrap = sd.periodic;
   for (int c = 0; c < 3; ++c) {
     out->off[c] = P.c[c].off;
     for (int a = 0; a < 3; ++a) {
@@ -532,6 +577,7 @@ void launch_spai_op_apply(const SpaiOpQ1& Q, const double* x, double* y, int ncu
   SylvParams P{};
   for (int c = 0; c < 3; ++c) {
     P.c[c].off = Q.off[c];
+    P.c[c].wrap = Q.off[c] < Q.n1 ? Q.wrap : 0;
     for (int a = 0; a < 3; ++a) {
       P.c[c].n[a] = Q.n[c][a];
       P.c[c].M[a] = Q.M[c][a];

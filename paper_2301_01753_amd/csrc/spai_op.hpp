@@ -14,6 +14,7 @@ struct SpaiOpQ1 {
   double* params_tab = nullptr;  // the 1-D bands of M_a and M_a^2
   long long n1 = 0;
   int r = 0;
+  int wrap = 0;                  // periodic axes of the space
   long long off[3] = {0, 0, 0};
   int n[3][3] = {};
   double sc[3] = {0, 0, 0};

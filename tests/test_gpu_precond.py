@@ -38,11 +38,11 @@ def g():
     gym.gym_destroy(ctx)
 
 
-# the last three have one axis of 52 cells: its transform spans a 64-wide
-# output tile with a ragged tail
+# then three with one axis of 52 cells (its transform spans a 64-wide output
+# tile with a ragged tail) and three with one of 132 (three tiles, ragged)
 CASES = [((3, 4, 2), 1, None), ((3, 4, 2), 2, (1.0, 1.3, 0.7)), ((2, 3, 2), 3, None), ((2, 2, 3), 4, None),
          ((5, 3, 4), 2, (2.0, 1.0, 0.5)), ((13, 2, 3), 4, None), ((2, 13, 1), 4, (1.0, 2.0, 0.5)),
-         ((1, 2, 13), 4, None)]
+         ((1, 2, 13), 4, None), ((33, 1, 2), 4, None), ((2, 33, 1), 4, (1.0, 3.0, 0.5)), ((1, 2, 33), 4, None)]
 
 
 @pytest.mark.parametrize("nel,r,hi", CASES)
