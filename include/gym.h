@@ -324,7 +324,7 @@ int gym_mass_solve(const gym_space* space, const gym_solve_opts* opts,
  * strangSplit).  Stable iff tau <= 2 / omega_max, omega_max^2 the largest
  * eigenvalue of Q1 P2 (Proposition Stability). */
 #define GYM_Q1_EXACT  0  /* Q1 = M1^-1, applied by a CG mass solve           */
-#define GYM_Q1_LUMPED 1  /* inverse row sums of M1 (section 4.3; affine only) */
+#define GYM_Q1_LUMPED 1  /* inverse row sums of M1 (section 4.3)            */
 #define GYM_Q1_SPAI_DIAG 2 /* symmetrised SPAI of M1, diagonal pattern S(1)
                               (section 5; affine only)                       */
 #define GYM_Q1_SPAI_OP 4 /* SPAI-OP (set by gym_maxwell_spai_op only)        */
@@ -332,7 +332,7 @@ int gym_mass_solve(const gym_space* space, const gym_solve_opts* opts,
                             q_l = argmin ||M1[:, I_l] q - e_l||_2, then
                             (Q + Q^T)/2 (section 5; affine only)            */
 #define GYM_M2_EXACT  0  /* M2~ = M2                                         */
-#define GYM_M2_LUMPED 1  /* row sums of M2 (affine only)                     */
+#define GYM_M2_LUMPED 1  /* row sums of M2                                   */
 /* Lumped row sums are those of the mass matrix without boundary conditions,
  * at the kept unknowns; with Whitney forms (degree 1) on a box, lumped Q1 and
  * M2~ give Yee's leapfrog (section 4). */
@@ -349,8 +349,10 @@ void gym_maxwell_opts_default(gym_maxwell_opts* opts);
  * perfect conductor), or 2-D with both axes periodic (the torus: Lambda^2 is
  * then the scalar L2 space and C the 2-D curl).  On periodic meshes the
  * masses run as 1-D band passes.  Errors: GYM_E_ARG (other dimensions,
- * degree outside 1..4, bad option), GYM_E_UNSUPPORTED (lumped masses or a
- * SPAI on a curved mesh), GYM_E_OOM. */
+ * degree outside 1..4, bad option), GYM_E_UNSUPPORTED (a SPAI on a curved
+ * mesh; lumped masses whose row sums are not all positive, which on curved
+ * cells of degree >= 2 can happen), GYM_E_OOM.  On curved meshes the lumped
+ * row sums are those of the curved mass matrix (one device apply). */
 int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree,
                        const gym_maxwell_opts* opts, gym_maxwell** out);
 /* SPAI-OP (section 5, eqs. SPAIOPobjective to diagonalPreconditioner): the

@@ -809,10 +809,49 @@ LumpedTables lumped_tables_host(const gym_space* sp) {
   return t;
 }
 
-std::vector<double> lumped_diag_host(const gym_space* sp) {
+// Row sums of the mass matrix without boundary conditions on curved cells:
+// the natural-BC space's mass (the curved kernel, FP64) applied to ones on the
+// device, then restricted to the unknowns `sp` keeps.  Empty on failure.
+std::vector<double> curved_rowsums(const gym_space* sp) {
+  const SpaceDesc& s = sp->desc;
+  std::vector<double> out;
+  gym_space* full = nullptr;
+  if (gym_space_create(sp->ctx, sp->mesh, s.kind, s.r, GYM_BC_NATURAL, &full)) return out;
+  const SpaceDesc& f = full->desc;
+  const std::vector<double> ones(f.ndofs, 1.0);
+  std::vector<double> rs(f.ndofs);
+  void* d = nullptr;
+  bool ok = hipMalloc(&d, sizeof(double) * 2 * f.ndofs) == hipSuccess;
+  double* x = static_cast<double*>(d);
+  ok = ok && hipMemcpy(x, ones.data(), sizeof(double) * f.ndofs, hipMemcpyHostToDevice) == hipSuccess;
+  ok = ok && launch_mass_apply(full, GYM_F64, 1, x, x + f.ndofs, nullptr) == 0;
+  ok = ok && hipMemcpy(rs.data(), x + f.ndofs, sizeof(double) * f.ndofs, hipMemcpyDeviceToHost) == hipSuccess;
+  if (d) (void)hipFree(d);
+  if (!ok) (void)hipGetLastError();
+  if (ok) {
+    out.resize(s.ndofs);
+    for (int c = 0; c < s.ncomp; ++c) {
+      const CompDesc& cd = s.comp[c];
+      const CompDesc& fd = f.comp[c];
+      int64_t idx = cd.offset;
+      for (int64_t k = 0; k < cd.count[2]; ++k)
+        for (int64_t j = 0; j < cd.count[1]; ++j)
+          for (int64_t i = 0; i < cd.count[0]; ++i) {
+            const int64_t p[3] = {cd.start[0] + i - fd.start[0], cd.start[1] + j - fd.start[1],
+                                  cd.start[2] + k - fd.start[2]};
+            out[idx++] = rs[fd.offset + p[0] + fd.count[0] * (p[1] + fd.count[1] * p[2])];
+          }
+    }
+  }
+  gym_space_destroy(full);
+  return out;
+}
+
+std::vector<double> lumped_diag_host(const gym_space* sp, bool curved_exact) {
   const gym_mesh* m = sp->mesh;
   const SpaceDesc& s = sp->desc;
   if (s.periodic) return periodic_diag_host(sp, true);
+  if (m->curved && curved_exact) return curved_rowsums(sp);
   const LumpedTables t = lumped_tables_host(sp);
   std::vector<double> out(s.ndofs);
   for (int c = 0; c < s.ncomp; ++c) {

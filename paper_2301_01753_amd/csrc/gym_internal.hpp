@@ -68,9 +68,11 @@ namespace gym {
 struct OpParams;
 // Parameters of one block-operator apply (capi.cpp), and the apply itself.
 void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int& prob);
-// Row sums of the mass matrix of an affine space without boundary
-// conditions, at its kept unknowns (canonical order).
-std::vector<double> lumped_diag_host(const gym_space* sp);
+// Row sums of the mass matrix without boundary conditions at the kept
+// unknowns.  On curved cells they come from a device apply of the curved
+// mass (curved_exact), or, as a preconditioner only, from the box with the
+// same spacing.
+std::vector<double> lumped_diag_host(const gym_space* sp, bool curved_exact = true);
 // The same row sums in factored form: at lattice position p, component c has
 // sc[c] prod_a w_a(p_a), w_a = rn[a] (nodal along axis a, r N_a + 1 values)
 // or re[a] (edge, r N_a values); the product is taken in axis order.

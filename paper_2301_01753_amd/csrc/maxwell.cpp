@@ -49,6 +49,16 @@ struct gym_maxwell {
 
 namespace {
 
+// Lumped masses: one positive row sum per unknown (on curved cells they come
+// from a device apply, which may fail; high-order curved rows need not sum
+// positive).
+int check_rowsums(const std::vector<double>& d, long long n) {
+  if ((long long)d.size() != n) return fail(GYM_E_HIP, "lumped masses: the row sums could not be formed");
+  for (double v : d)
+    if (!(v > 0)) return fail(GYM_E_UNSUPPORTED, "lumped masses: a row sum of the mass matrix is not positive");
+  return 0;
+}
+
 // q = Q1 e
 bool sparse_q1(const gym_maxwell* mx) {
   return mx->o.q1 == GYM_Q1_SPAI_DIAG || mx->o.q1 == GYM_Q1_SPAI || mx->o.q1 == GYM_Q1_SPAI_OP;
@@ -119,8 +129,8 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
       (o.m2 != GYM_M2_EXACT && o.m2 != GYM_M2_LUMPED) ||
       !(o.c > 0) || !(o.cg_rtol > 0) || o.cg_maxit < 1)
     return fail(GYM_E_ARG, "bad time-stepping options");
-  if (mesh->curved && (o.q1 != GYM_Q1_EXACT || o.m2 == GYM_M2_LUMPED))
-    return fail(GYM_E_UNSUPPORTED, "lumped masses and the SPAI need an affine mesh");
+  if (mesh->curved && (o.q1 == GYM_Q1_SPAI_DIAG || o.q1 == GYM_Q1_SPAI))
+    return fail(GYM_E_UNSUPPORTED, "the SPAI needs an affine mesh");
   if (mesh->curved) {
     // the Gauss-point metrics of the mass applies, before the first step
     const void* qd;
@@ -154,7 +164,7 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
   }
   // one thread per lattice position, indexed in 32 bits (the stencil kernel
   // is written for the 3-D perfect conductor)
-  mx->fused = lumped && npos < (1LL << 31) - 256 && mesh->dim == 3 && !mesh->periodic;
+  mx->fused = lumped && npos < (1LL << 31) - 256 && mesh->dim == 3 && !mesh->periodic && !mesh->curved;
   const size_t total = 3 * (size_t)mx->n1 + 3 * (size_t)mx->n2 + (size_t)mx->nb1 + 4 + (mx->fused ? nw : 0);
   if (hipMalloc(&mx->mem, sizeof(double) * total) != hipSuccess) {
     (void)hipGetLastError();
@@ -199,6 +209,10 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
   }
   if (o.q1 == GYM_Q1_LUMPED) {
     std::vector<double> d = lumped_diag_host(mx->s1);
+    if (int rc2 = check_rowsums(d, mx->n1)) {
+      gym_maxwell_destroy(mx);
+      return rc2;
+    }
     for (double& v : d) v = 1.0 / v;
     if (hipMemcpy(mx->q1d, d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice) != hipSuccess) {
       gym_maxwell_destroy(mx);
@@ -213,6 +227,10 @@ int gym_maxwell_create(gym_ctx* ctx, const gym_mesh* mesh, int degree, const gym
   }
   if (o.m2 == GYM_M2_LUMPED) {
     std::vector<double> d = lumped_diag_host(mx->s2);
+    if (int rc2 = check_rowsums(d, mx->n2)) {
+      gym_maxwell_destroy(mx);
+      return rc2;
+    }
     if (hipMemcpy(mx->m2d, d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice) != hipSuccess) {
       gym_maxwell_destroy(mx);
       return fail(GYM_E_HIP, "time stepping: upload failed");
@@ -344,7 +362,12 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
     return fail(GYM_E_OOM, "eigen-solver: device allocation failed");
   }
   {
-    std::vector<double> d = lumped_diag_host(mx->s1), di(d.size());
+    // B itself when Q1 is lumped; otherwise only the preconditioner T
+    std::vector<double> d = lumped_diag_host(mx->s1, lumped), di(d.size());
+    if (int rc2 = check_rowsums(d, n1)) {
+      cleanup();
+      return rc2;
+    }
     for (size_t i = 0; i < d.size(); ++i) di[i] = 1.0 / d[i];
     if (hipMemcpy(dB, d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dT, di.data(), sizeof(double) * di.size(), hipMemcpyHostToDevice) != hipSuccess) {

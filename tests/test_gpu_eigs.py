@@ -49,7 +49,9 @@ CASES = [((3, 4, 3), 1, "exact", "exact", 1.0, (1.0, 1.2, 0.9), 0.0, 4),
          ((3, 3, 2), 2, "exact", "exact", 1.3, (1.0, 1.0, 1.0), 0.0, 4),
          ((4, 3, 3), 1, "lumped", "lumped", 1.0, (1.0, 1.0, 1.0), 0.0, 4),
          ((2, 3, 2), 3, "lumped", "exact", 0.8, (1.0, 1.0, 1.0), 0.0, 3),
-         ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15, 3)]
+         ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15, 3),
+         ((3, 3, 3), 1, "lumped", "lumped", 1.0, (1.0, 1.0, 1.0), 0.15, 3),
+         ((3, 2, 3), 2, "lumped", "exact", 1.0, (1.0, 1.0, 1.0), 0.15, 3)]
 
 
 @pytest.mark.parametrize("nel,r,q1,m2,c,hi,perturb,nev", CASES)
@@ -98,7 +100,8 @@ def test_whitney_24cube_closed_form(g):
 
 LARGEST = [((3, 4, 3), 1, "exact", "exact", 1.0, (1.0, 1.2, 0.9), 0.0),
            ((3, 3, 2), 2, "lumped", "lumped", 1.3, (1.0, 1.0, 1.0), 0.0),
-           ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15)]
+           ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15),
+           ((3, 3, 2), 2, "lumped", "lumped", 1.0, (1.0, 1.0, 1.0), 0.15)]
 
 
 @pytest.mark.parametrize("nel,r,q1,m2,c,hi,perturb", LARGEST)

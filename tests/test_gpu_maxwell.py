@@ -5,7 +5,9 @@ the oracle applies every half step literally.  With both masses lumped a
 whole step is one stencil kernel; those cases run every degree, odd and
 even step counts, and the full 128^3 Yee lattice.  Lumped masses: the two differ
 by rounding only (1e-13 of the state's scale).  Exact Q1: every M1 solve is a
-CG solve to 1e-14, so the trajectories agree to 1e-10 after a few steps.
+CG solve to 1e-14, so the trajectories agree to 1e-10 after a few steps.  Lumped masses on
+curved cells are the row sums of the curved mass matrices (the GPU forms them
+by one mass apply to ones, the oracle from its assembled matrices).
 """
 import numpy as np
 import pytest
@@ -57,6 +59,10 @@ CASES = [((4, 3, 5), 1, "lumped", "lumped", 1.3, (1.0, 0.9, 1.3), 0.0, 1e-13),
          ((3, 2, 3), 2, "lumped", "exact", 0.7, (1.0, 1.2, 1.0), 0.0, 1e-13),
          ((2, 3, 2), 3, "exact", "lumped", 1.0, (1.0, 1.0, 1.0), 0.0, 1e-10),
          ((3, 3, 3), 1, "exact", "exact", 1.0, (1.0, 1.0, 1.0), 0.15, 1e-10),
+         # lumped masses on curved cells: row sums of the curved mass matrices
+         ((3, 3, 3), 1, "lumped", "lumped", 1.0, (1.0, 1.0, 1.0), 0.15, 1e-12),
+         ((3, 2, 3), 2, "lumped", "exact", 1.1, (1.0, 1.0, 1.0), 0.15, 1e-12),
+         ((2, 3, 2), 2, "exact", "lumped", 1.0, (1.0, 1.0, 1.2), 0.1, 1e-10),
          # sparse approximate inverses of M1 (section 5): Kronecker-factored on the GPU,
          # column-wise least squares on the assembled M1 in the oracle
          ((3, 2, 3), 1, "spai", "exact", 1.0, (1.0, 1.1, 1.0), 0.0, 1e-12),
@@ -194,14 +200,27 @@ def test_eigenmode_phase_on_gpu(g):
     _close(gym, mesh, mx)
 
 
+def test_lumped_nonpositive_rowsum_refused(g):
+    # Degree 3 on a strongly perturbed mesh: some row sums of M1 and M2 are
+    # negative (checked with the oracle), so neither can be lumped.
+    gym, ctx = g
+    nel = (3, 3, 3)
+    verts = synth.perturbed_vertices(nel, 0.3, seed=5)
+    G = maxwell.Gym(Mesh(verts), 3)
+    assert G.rs1.min() < 0 and G.rs2.min() < 0
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts)
+    for q1, m2 in ((gym.GYM_Q1_LUMPED, gym.GYM_M2_EXACT), (gym.GYM_Q1_EXACT, gym.GYM_M2_LUMPED)):
+        o = gym.gym_maxwell_opts_default()
+        o.q1, o.m2 = q1, m2
+        with pytest.raises(gym.GymError, match="not positive"):
+            gym.gym_maxwell_create(ctx, mesh, 3, o)
+    gym.gym_mesh_destroy(mesh)
+
+
 def test_errors(g):
     gym, ctx = g
     verts = synth.perturbed_vertices((2, 2, 2), 0.1, seed=1)
     mesh = gym.gym_mesh_create(ctx, 3, (2, 2, 2), vertices=verts)
-    o = gym.gym_maxwell_opts_default()
-    o.q1 = gym.GYM_Q1_LUMPED
-    with pytest.raises(gym.GymError):
-        gym.gym_maxwell_create(ctx, mesh, 1, o)
     o = gym.gym_maxwell_opts_default()
     with pytest.raises(gym.GymError):
         gym.gym_maxwell_create(ctx, mesh, 5, o)
