@@ -118,9 +118,14 @@ const char* gym_last_error(void);
  * GYM_OPT_TILE: 0 = automatic (large tiles unless the mesh has fewer of
  *   them than the device has CUs), 1 = large tiles (one workgroup per CU),
  *   2 = small tiles (several workgroups per CU).
+ * GYM_OPT_CURVED_KERNEL: 0 = automatic (the FP64 Hodge apply of degree 3 on
+ *   curved cells runs its 1-D contractions on the matrix cores, one cell per
+ *   4 x 4 block; other curved applies use the tile kernel), 1 = always the
+ *   tile kernel.  Both compute the same operator up to rounding.
  * Errors: GYM_E_ARG for an unknown option or value. */
 #define GYM_OPT_MASS_FORM 0
 #define GYM_OPT_TILE      1
+#define GYM_OPT_CURVED_KERNEL 2
 int gym_ctx_set(gym_ctx* ctx, int option, int value);
 
 /* ---- mesh (paper section 2: the mesh T_h) ----------------------------- */

@@ -15,6 +15,7 @@
 #include "gym_internal.hpp"
 #include "kernels.hpp"
 #include "krylov.hpp"
+#include "hodge_mfma.hpp"
 #include "poisson_mfma.hpp"
 #include "schur.hpp"
 #include "spai.hpp"
@@ -419,9 +420,47 @@ int mfma_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t 
   return 0;
 }
 
+// Curved Hodge apply of degree 3 in FP64 on the matrix cores (not with the
+// fused MINRES step, which the tile kernel carries).
+bool hc_path(const gym_op* op, int prec, const MrStep* mr) {
+  const gym_mesh* m = op->mesh;
+  return prec == GYM_F64 && op->problem != GYM_MIXED_POISSON && m->curved && m->dim == 3 && !m->periodic &&
+         op->r == kHcDegree && !mr && op->ctx->curved_kernel == 0;
+}
+
+int hc_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t s) {
+  const gym_mesh* m = op->mesh;
+  HcParams q{};
+  q.x = static_cast<const double*>(x);
+  q.y = static_cast<double*>(y);
+  q.ndofs = op->na + op->nb;
+  const DevSpace a = to_dev(op->sa, 0), b = to_dev(op->sb, op->na);
+  q.f[0] = a.c[0];
+  for (int c = 0; c < 3; ++c) q.f[1 + c] = b.c[c];
+  for (int i = 0; i < 3; ++i) q.nel[i] = (int)m->nel[i];
+  const void* qd = nullptr;
+  if (int rc = mesh_qdata(m, op->r, 0, &qd)) return rc;
+  q.qd = static_cast<const double*>(qd);
+  q.qfs = (long long)(op->r + 1) * m->nel[0] * (op->r + 1) * m->nel[1] * (op->r + 1) * m->nel[2];
+  gym_op* mop = const_cast<gym_op*>(op);  // lazily sized apply state
+  const long long need = hodge_mfma_halo_doubles(q.nel, nrhs);
+  if (mop->hc_halo_n < need) {
+    if (mop->hc_halo) (void)hipFree(mop->hc_halo);
+    mop->hc_halo = nullptr;
+    mop->hc_halo_n = 0;
+    if (int rc = dalloc((void**)&mop->hc_halo, sizeof(double) * (size_t)std::max<long long>(need, 1))) return rc;
+    mop->hc_halo_n = need;
+  }
+  q.halo = mop->hc_halo;
+  q.chunk_mode = op->ctx->tile;  // large tiles: whole z columns; small: one layer per workgroup
+  if (launch_hodge_mfma(q, nrhs, op->ctx->ncu, s)) return fail(GYM_E_HIP, "matrix-core operator launch failed");
+  return 0;
+}
+
 int op_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s, const MrStep* mr,
               int* wg_out) {
   if (mfma_path(op, prec)) return mfma_launch(op, nrhs, x, y, s, mr, wg_out);
+  if (!wg_out && hc_path(op, prec, mr)) return hc_launch(op, nrhs, x, y, s);
   OpParams p;
   int prob;
   build_op_params(op, x, y, p, prob);
@@ -958,6 +997,10 @@ int gym_ctx_set(gym_ctx* ctx, int option, int value) {
     ctx->tile = value;
     return GYM_OK;
   }
+  if (option == GYM_OPT_CURVED_KERNEL && (value == 0 || value == 1)) {
+    ctx->curved_kernel = value;
+    return GYM_OK;
+  }
   return fail(GYM_E_ARG, "unknown option or value");
 }
 
@@ -1264,6 +1307,7 @@ int gym_op_destroy(gym_op* op) {
     if (st->yel) (void)hipFree(st->yel);
     delete st;
   }
+  if (op->hc_halo) (void)hipFree(op->hc_halo);
   if (op->d_prec) (void)hipFree(op->d_prec);
   delete op;
   return GYM_OK;

@@ -93,6 +93,7 @@ struct gym_ctx {
   int ncu = 0;
   int mass_form = 0;  // GYM_OPT_MASS_FORM
   int tile = 0;       // GYM_OPT_TILE
+  int curved_kernel = 0;  // GYM_OPT_CURVED_KERNEL
 };
 
 struct gym_mesh {
@@ -142,4 +143,6 @@ struct gym_op {
   size_t work_bytes = 0;
   void* schur = nullptr;             // gym::SchurPrec, built on first use
   void* mfma = nullptr;              // bf16 matrix-core apply state, built on first use
+  double* hc_halo = nullptr;         // curved Hodge matrix-core apply: tile-boundary sums
+  long long hc_halo_n = 0;
 };

@@ -203,7 +203,7 @@ def gym_destroy(ctx):
     _check(lib().gym_destroy(ctx))
 
 
-GYM_OPT_MASS_FORM, GYM_OPT_TILE = 0, 1
+GYM_OPT_MASS_FORM, GYM_OPT_TILE, GYM_OPT_CURVED_KERNEL = 0, 1, 2
 
 
 def gym_ctx_set(ctx, option, value):
