@@ -32,6 +32,12 @@
 // w_r T(r, c).  The z contractions and the metric are FMAs in registers with
 // the table entries as compile-time constants.
 //
+// Metric: per Gauss point 1/det J and the HCURL metric G1 are read (7 of the
+// 14 precomputed fields); det J = det G1 and the HDIV metric G1^-1 =
+// adj(G1) / det J follow in registers.  A wavefront loads its cells' values
+// for the next layer straight into its own LDS rows (global-to-LDS loads,
+// no registers, no barrier) while it computes the current one.
+//
 // Sums over cells: a workgroup owns a TX x TY tile of cells and marches
 // through a chunk of layers in z.  The top z plane of a cell is carried in
 // registers into the cell above (the layer below a chunk is recomputed to
@@ -155,9 +161,21 @@ __device__ __forceinline__ long long kept_index(const DevComp& d, int g0, int g1
   return d.offset + l0 + (long long)d.count[0] * (l1 + (long long)d.count[1] * l2);
 }
 
+// Metric fields read per Gauss point: 1/det J and the six HCURL entries
+// G1 = det J J^-1 J^-T (fields QF_INVDET .. QF_HCURL + 5, consecutive).  The
+// other two follow from G1: det G1 = det J, and the HDIV metric
+// J^T J / det J = G1^-1 = adj(G1) / det J.
+constexpr int kQF = 7;
+constexpr int kQRows = kQF * 4 * 4;
+static_assert(QF_HCURL == QF_INVDET + 1, "1/det J and the HCURL metric are consecutive fields");
+
 // Workgroup tile of cells: TX x TY, four cells (a row of four along x) per
 // wavefront.
-constexpr int kTX = 8, kTY = 4;
+// Workgroup tile: 16 x 2 cells, 8 wavefronts.  Tile boundaries across x cost
+// the second kernel a read-modify-write of y one row apart per position; across
+// y they are contiguous rows: 16 x 2 took 13.8 ms on the 96^3 workload (second
+// kernel 1.4 ms) against 14.5 ms (1.7 ms) for 8 x 4.
+constexpr int kTX = 16, kTY = 2;
 
 // LDS slots of the values a cell hands to a neighbour in its layer, per
 // z plane: x senders [field][cell y][cell x][b][plane], y senders
@@ -173,13 +191,21 @@ struct Slots {
 // Roles of a lane for one field in the x-y sums (3 bits), and the
 // neighbours it receives from (3 bits: x, y, xy).
 enum { ROLE_NONE = 0, ROLE_SX = 1, ROLE_SY = 2, ROLE_SXY = 3, ROLE_Y = 4, ROLE_HX = 5, ROLE_HY = 6, ROLE_HXY = 7 };
+constexpr int kCodeBits = 6;  // per field: role (3 bits), then the neighbours received from (3 bits)
 
-template <int TX, int TY>
-__global__ void __launch_bounds__(TX * TY * 16) hodge_mfma_kernel(HcParams p) {
+// WPE: wavefronts per SIMD the registers are budgeted for (2: about 250
+// VGPRs; 3 and 4 spill and measured slower).
+template <int TX, int TY, int WPE>
+__global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams p) {
   static_assert(TX % 4 == 0, "four cells per wavefront along x");
   constexpr int WX = TX / 4;
   using SL = Slots<TX, TY>;
+  constexpr int NW = TX * TY / 4;
   __shared__ double lds[SL::kN];
+  // per wavefront: the metric of its four cells for one layer, rows
+  // (field, k, j) of 16 x points (4 cells x 4 Gauss points), filled by
+  // direct global-to-LDS loads one layer ahead
+  __shared__ double qm[NW][kQRows * 16];
 
   // blocks b, b + 8, ... run on one XCD: the right-hand sides of an item
   // are consecutive there, so its metric is read from HBM about once
@@ -208,9 +234,24 @@ __global__ void __launch_bounds__(TX * TY * 16) hodge_mfma_kernel(HcParams p) {
   double* __restrict__ hxy = hy + p.hy_n;
   const int LX = R * Nx + 1, LY = R * Ny + 1, LZ = R * Nz + 1;
 
-  // metric lattice: Gauss point (i, j) = (c, r) of the cell
+  // metric lattice: the wavefront's rows of 16 x points start at cell x0w
   const long long GX = (long long)Q * Nx, GY = (long long)Q * Ny;
-  const long long qcol = (Q * min(ex, Nx - 1) + c) + GX * (Q * min(ey, Ny - 1) + r);
+  const int x0w = tx * TX + 4 * (wv % WX);
+  double* qw = &qm[wv][0];
+  auto prefetch_metric = [&](int ezq) {
+    // lane L of instruction t: row 8 t + L / 8, points 2 (L % 8), + 1 (cells
+    // beyond the mesh read the last cell: their inputs are zero)
+    const int half = lane & 7, rsub = lane >> 3;
+    const long long xoff = (long long)Q * min(x0w + (half >> 1), Nx - 1) + 2 * (half & 1);
+    const long long yrow = (long long)Q * min(ey, Ny - 1);
+#pragma unroll
+    for (int t = 0; t < kQRows / 8; ++t) {
+      const int row = 8 * t + rsub;
+      const int f = row >> 4, kk = (row >> 2) & 3, j = row & 3;
+      const double* src = p.qd + (long long)(QF_INVDET + f) * p.qfs + ((long long)(Q * ezq + kk) * GY + yrow + j) * GX + xoff;
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(qw + 128 * t), 16, 0, 0);
+    }
+  };
 
   const int zfirst = chunk * p.chunk;
   const int zend = min(zfirst + p.chunk, Nz);
@@ -260,11 +301,12 @@ __global__ void __launch_bounds__(TX * TY * 16) hodge_mfma_kernel(HcParams p) {
         if (kNX[F] && kNY[F] && a == 0 && bb == 0 && lx > 0 && ly > 0) rm |= 4;
       }
     }
-    code |= (role | rm << 3) << (6 * F);
+    code |= (role | rm << 3) << (kCodeBits * F);
   }
 
   double cS = 0, cX = 0, cY = 0;  // top planes carried into the cell above
 
+  prefetch_metric(zbeg);
   for (int ez = zbeg; ez < zend; ++ez) {
     // ---- inputs: the cell's coefficients, planes along z (branch-free: a
     // position outside the kept set loads element 0 and is replaced by zero)
@@ -340,31 +382,38 @@ __global__ void __launch_bounds__(TX * TY * 16) hodge_mfma_kernel(HcParams p) {
       zf<3, SUB>(K, ZDN, cy);   // -d/dx u_z
     }
 
-    // ---- pointwise metric
+    // ---- pointwise metric (this wavefront's LDS rows, loaded a layer ahead)
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the global-to-LDS loads have landed
+    asm volatile("" ::: "memory");
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      double m[6], n[6];
-      const double* q = p.qd + qcol + GX * GY * (long long)(Q * ez + k);
-      const double det = q[QF_DET * p.qfs];
-#pragma unroll
-      for (int s = 0; s < 6; ++s) {
-        m[s] = q[(QF_HCURL + s) * p.qfs];
-        n[s] = q[(QF_HDIV + s) * p.qfs];
-      }
+      auto q = [&](int f) { return qw[((f * 4 + k) * 4 + r) * 16 + 4 * blk + c]; };
+      const double inv = q(0);
+      const double m00 = q(1), m01 = q(2), m02 = q(3), m11 = q(4), m12 = q(5), m22 = q(6);
+      // cofactors of the symmetric G1: adj(G1) = det J G1^-1
+      const double c00 = m11 * m22 - m12 * m12, c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11;
+      const double c11 = m00 * m22 - m02 * m02, c12 = m01 * m02 - m00 * m12, c22 = m00 * m11 - m01 * m01;
+      const double det = m00 * c00 + m01 * c01 + m02 * c02;
+      const double n00 = c00 * inv, n01 = c01 * inv, n02 = c02 * inv, n11 = c11 * inv, n12 = c12 * inv,
+                   n22 = c22 * inv;
       sg[k] = -det * sg[k];
       double t0 = ux[k], t1 = uy[k], t2 = uz[k];
-      ux[k] = m[0] * t0 + m[1] * t1 + m[2] * t2;
-      uy[k] = m[1] * t0 + m[3] * t1 + m[4] * t2;
-      uz[k] = m[2] * t0 + m[4] * t1 + m[5] * t2;
+      ux[k] = m00 * t0 + m01 * t1 + m02 * t2;
+      uy[k] = m01 * t0 + m11 * t1 + m12 * t2;
+      uz[k] = m02 * t0 + m12 * t1 + m22 * t2;
       t0 = gx[k], t1 = gy[k], t2 = gz[k];
-      gx[k] = m[0] * t0 + m[1] * t1 + m[2] * t2;
-      gy[k] = m[1] * t0 + m[3] * t1 + m[4] * t2;
-      gz[k] = m[2] * t0 + m[4] * t1 + m[5] * t2;
+      gx[k] = m00 * t0 + m01 * t1 + m02 * t2;
+      gy[k] = m01 * t0 + m11 * t1 + m12 * t2;
+      gz[k] = m02 * t0 + m12 * t1 + m22 * t2;
       t0 = cx[k], t1 = cy[k], t2 = cz[k];
-      cx[k] = n[0] * t0 + n[1] * t1 + n[2] * t2;
-      cy[k] = n[1] * t0 + n[3] * t1 + n[4] * t2;
-      cz[k] = n[2] * t0 + n[4] * t1 + n[5] * t2;
+      cx[k] = n00 * t0 + n01 * t1 + n02 * t2;
+      cy[k] = n01 * t0 + n11 * t1 + n12 * t2;
+      cz[k] = n02 * t0 + n12 * t1 + n22 * t2;
     }
+    // the rows are read: load the next layer's behind them
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
+    asm volatile("" ::: "memory");
+    if (ez + 1 < zend) prefetch_metric(ez + 1);
 
     // ---- backward: p = sg, h = u, g = grad, v = curl (metric applied).
     // z contractions (weighted tables) grouped by the (x, y) tables of a term:
@@ -427,7 +476,7 @@ __global__ void __launch_bounds__(TX * TY * 16) hodge_mfma_kernel(HcParams p) {
     const int nout4 = top ? R + 1 : R;
     auto send = [&](auto fc, const double(&o)[4]) {
       constexpr int F = decltype(fc)::value;
-      const int role = (code >> (6 * F)) & 7;
+      const int role = (code >> (kCodeBits * F)) & 7;
       if (role < ROLE_SX || role > ROLE_SXY) return;
       int off = 0;
       if constexpr (kSX[F] >= 0) {
@@ -446,7 +495,7 @@ __global__ void __launch_bounds__(TX * TY * 16) hodge_mfma_kernel(HcParams p) {
     };
     auto collect = [&](auto fc, const double(&o)[4]) {
       constexpr int F = decltype(fc)::value;
-      const int role = (code >> (6 * F)) & 7, rm = (code >> (6 * F + 3)) & 7;
+      const int role = (code >> (kCodeBits * F)) & 7, rm = (code >> (kCodeBits * F + 3)) & 7;
       if (role < ROLE_Y) return;
       const int nout = kNZ[F] ? nout4 : R;
       double v[4];
@@ -527,57 +576,54 @@ __device__ __forceinline__ const DevComp& field_comp(const HcParams& p, int f) {
   }
 }
 
-// Tile-boundary sums: y(p) += halo values of p, in the order x, y, xy.
-// Part A: positions on x boundaries of the fields nodal in x (sigma, u_y,
-// u_z); part B: positions on y boundaries of the fields nodal in y (sigma,
-// u_x, u_z) that part A did not take.
-__global__ void __launch_bounds__(256) hodge_mfma_fixup(HcParams p, int TX, int TY, long long nA, long long nB) {
+// Tile-boundary sums of one right-hand side (blockIdx.y), in the order own,
+// x, y, xy; positions are numbered line by line (line length LM), lines:
+// Part A: the x boundary planes of the fields nodal in x (sigma, u_y, u_z),
+// lines along y: y += HX (+ HY + HXY where the position is on a y boundary
+// too).  Part B: the y boundary planes of the fields nodal in y (sigma, u_x,
+// u_z), lines along x: y += HY, except where part A adds.
+__global__ void __launch_bounds__(256) hodge_mfma_fixup(HcParams p, int TX, int TY) {
   const int Nx = p.nel[0], Ny = p.nel[1], Nz = p.nel[2];
-  const int LX = R * Nx + 1, LY = R * Ny + 1, LZ = R * Nz + 1;
-  const long long total = (long long)p.nrhs * (nA + nB);
-  for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int rhs = (int)(t / (nA + nB));
-    long long u = t - (long long)rhs * (nA + nB);
-    double* y = p.y + (long long)rhs * p.ndofs;
-    const double* hx = p.halo + (long long)rhs * (p.hx_n + p.hy_n + p.hxy_n);
-    const double* hy = hx + p.hx_n;
-    const double* hxy = hy + p.hy_n;
-    if (u < nA) {
-      const long long per = (long long)(p.tiles_x - 1) * LZ * LY;
-      const int fs = (int)(u / per);
-      long long v = u - fs * per;
-      const int gy = (int)(v % LY);
-      v /= LY;
-      const int gz = (int)(v % LZ);
-      const int bx = (int)(v / LZ);
+  const int LX = R * Nx + 1, LY = R * Ny + 1, LZ = R * Nz + 1, LM = max(LX, LY);
+  const int bxn = p.tiles_x - 1, byn = p.tiles_y - 1;
+  const int ra = 3 * bxn * LZ, rb = 3 * byn * LZ;
+  const int rhs = blockIdx.y;
+  double* y = p.y + (long long)rhs * p.ndofs;
+  const double* hx = p.halo + (long long)rhs * (p.hx_n + p.hy_n + p.hxy_n);
+  const double* hy = hx + p.hx_n;
+  const double* hxy = hy + p.hy_n;
+  const int total = (ra + rb) * LM;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const int row = t / LM, g = t - row * LM;
+    if (row < ra) {
+      const int fs = row / (bxn * LZ), rem = row - fs * bxn * LZ;
+      const int bx = rem / LZ, gz = rem - bx * LZ;
+      const int gy = g;
+      if (gy >= LY) continue;
       const int F = fs == 0 ? 0 : fs + 1;  // sigma, u_y, u_z
       const int gx = R * TX * (bx + 1);
       const long long id = kept_index(field_comp(p, F), gx, gy, gz);
       if (id < 0) continue;
-      double val = y[id] + hx[(((long long)fs * (p.tiles_x - 1) + bx) * LZ + gz) * LY + gy];
+      double val = y[id] + hx[((long long)(fs * bxn + bx) * LZ + gz) * LY + gy];
       if (F != 2 && gy % (R * TY) == 0 && gy > 0 && gy < R * Ny) {
         const int by = gy / (R * TY) - 1;
         const int fy = F == 0 ? 0 : 2, fxy = F == 0 ? 0 : 1;
-        val += hy[(((long long)fy * (p.tiles_y - 1) + by) * LZ + gz) * LX + gx];
-        val += hxy[(((long long)fxy * (p.tiles_x - 1) + bx) * (p.tiles_y - 1) + by) * LZ + gz];
+        val += hy[((long long)(fy * byn + by) * LZ + gz) * LX + gx];
+        val += hxy[((long long)(fxy * bxn + bx) * byn + by) * LZ + gz];
       }
       y[id] = val;
     } else {
-      u -= nA;
-      const long long per = (long long)(p.tiles_y - 1) * LZ * LX;
-      const int fs = (int)(u / per);
-      long long v = u - fs * per;
-      const int gx = (int)(v % LX);
-      v /= LX;
-      const int gz = (int)(v % LZ);
-      const int by = (int)(v / LZ);
+      const int r2 = row - ra;
+      const int fs = r2 / (byn * LZ), rem = r2 - fs * byn * LZ;
+      const int by = rem / LZ, gz = rem - by * LZ;
+      const int gx = g;
+      if (gx >= LX) continue;
       const int F = fs == 0 ? 0 : (fs == 1 ? 1 : 3);  // sigma, u_x, u_z
       if (F != 1 && gx % (R * TX) == 0 && gx > 0 && gx < R * Nx) continue;  // part A's
       const int gy = R * TY * (by + 1);
       const long long id = kept_index(field_comp(p, F), gx, gy, gz);
       if (id < 0) continue;
-      y[id] += hy[(((long long)fs * (p.tiles_y - 1) + by) * LZ + gz) * LX + gx];
+      y[id] += hy[((long long)(fs * byn + by) * LZ + gz) * LX + gx];
     }
   }
 }
@@ -634,15 +680,15 @@ int launch_hodge_mfma(const HcParams& p0, int nrhs, int ncu, hipStream_t s) {
   p.nitems = ntiles * p.nchunks;
   const long long nblk = (long long)((p.nitems + 7) / 8) * 8 * nrhs;
   if (nblk >= (1LL << 31)) return -1;
-  hipLaunchKernelGGL((hodge_mfma_kernel<kTX, kTY>), dim3((unsigned)nblk), dim3(kTX * kTY * 16), 0, s, p);
+  hipLaunchKernelGGL((hodge_mfma_kernel<kTX, kTY, 2>), dim3((unsigned)nblk), dim3(kTX * kTY * 16), 0, s, p);
   if (hipGetLastError() != hipSuccess) return -1;
-  const long long LX = R * (long long)p.nel[0] + 1, LY = R * (long long)p.nel[1] + 1,
-                  LZ = R * (long long)p.nel[2] + 1;
-  const long long nA = 3LL * (p.tiles_x - 1) * LZ * LY, nB = 3LL * (p.tiles_y - 1) * LZ * LX;
-  const long long total = (long long)nrhs * (nA + nB);
+  const int LX = R * p.nel[0] + 1, LY = R * p.nel[1] + 1, LZ = R * p.nel[2] + 1;
+  const long long rows = 3LL * (p.tiles_x - 1) * LZ + 3LL * (p.tiles_y - 1) * LZ;
+  const long long total = rows * std::max(LX, LY);
+  if (total >= (1LL << 31)) return -1;
   if (total > 0) {
-    const long long nb = std::min<long long>((total + 255) / 256, 8LL * ncu * 8);
-    hipLaunchKernelGGL(hodge_mfma_fixup, dim3((unsigned)nb), dim3(256), 0, s, p, kTX, kTY, nA, nB);
+    const dim3 grid((unsigned)std::min<long long>((total + 255) / 256, 4LL * ncu), (unsigned)nrhs);
+    hipLaunchKernelGGL(hodge_mfma_fixup, grid, dim3(256), 0, s, p, kTX, kTY);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   return 0;
