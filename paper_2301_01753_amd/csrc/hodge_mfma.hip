@@ -178,14 +178,23 @@ static_assert(QF_HCURL == QF_INVDET + 1, "1/det J and the HCURL metric are conse
 constexpr int kTX = 16, kTY = 2;
 
 // LDS slots of the values a cell hands to a neighbour in its layer, per
-// z plane: x senders [field][cell y][cell x][b][plane], y senders
-// [field][cell y][cell x][a][plane], xy senders [field][cell y][cell x][plane].
+// cell (cell-major, 87 doubles): x senders (sigma b 0-3, u_y b 0-2, u_z b 0-3),
+// y senders (sigma a 0-3, u_x a 0-2, u_z a 0-3), xy senders (sigma, u_z),
+// each by z plane (4 planes, 3 for u_z).  Two copies, used by alternate
+// layers, so one barrier per layer separates the senders from the collectors.
 template <int TX, int TY>
 struct Slots {
-  static constexpr int kX = 0, kY = 3 * TY * TX * 16, kXY = 6 * TY * TX * 16, kN = kXY + 2 * TY * TX * 4;
-  static __device__ __forceinline__ int sx(int f, int ly, int lx, int b) { return kX + (((f * TY + ly) * TX + lx) * 4 + b) * 4; }
-  static __device__ __forceinline__ int sy(int f, int ly, int lx, int a) { return kY + (((f * TY + ly) * TX + lx) * 4 + a) * 4; }
-  static __device__ __forceinline__ int sxy(int f, int ly, int lx) { return kXY + ((f * TY + ly) * TX + lx) * 4; }
+  static constexpr int kCell = 87, kN = kCell * TX * TY;
+  static constexpr int kBX[4] = {0, -1, 16, 28}, kBY[4] = {40, 56, -1, 68};
+  static constexpr int kBXY[4] = {80, -1, -1, 84};
+  static constexpr int kNZP[4] = {4, 4, 4, 3};
+  static __device__ __forceinline__ int cell(int ly, int lx) { return (ly * TX + lx) * kCell; }
+  template <int F>
+  static __device__ __forceinline__ int sx(int ly, int lx, int b) { return cell(ly, lx) + kBX[F] + b * kNZP[F]; }
+  template <int F>
+  static __device__ __forceinline__ int sy(int ly, int lx, int a) { return cell(ly, lx) + kBY[F] + a * kNZP[F]; }
+  template <int F>
+  static __device__ __forceinline__ int sxy(int ly, int lx) { return cell(ly, lx) + kBXY[F]; }
 };
 
 // Roles of a lane for one field in the x-y sums (3 bits), and the
@@ -201,7 +210,7 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
   constexpr int WX = TX / 4;
   using SL = Slots<TX, TY>;
   constexpr int NW = TX * TY / 4;
-  __shared__ double lds[SL::kN];
+  __shared__ double slots[2][SL::kN];
   // per wavefront: the metric of its four cells for one layer, rows
   // (field, k, j) of 16 x points (4 cells x 4 Gauss points), filled by
   // direct global-to-LDS loads one layer ahead
@@ -474,19 +483,20 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
     // ---- x-y sums: senders to LDS, then collectors (planes of this layer:
     // 0 .. R - 1, and R for nodal-z fields at the top of the mesh)
     const int nout4 = top ? R + 1 : R;
+    double* lds = slots[ez & 1];
     auto send = [&](auto fc, const double(&o)[4]) {
       constexpr int F = decltype(fc)::value;
       const int role = (code >> (kCodeBits * F)) & 7;
       if (role < ROLE_SX || role > ROLE_SXY) return;
       int off = 0;
       if constexpr (kSX[F] >= 0) {
-        if (role == ROLE_SX) off = SL::sx(kSX[F], ly, lx, bb);
+        if (role == ROLE_SX) off = SL::template sx<F>(ly, lx, bb);
       }
       if constexpr (kSY[F] >= 0) {
-        if (role == ROLE_SY) off = SL::sy(kSY[F], ly, lx, a);
+        if (role == ROLE_SY) off = SL::template sy<F>(ly, lx, a);
       }
       if constexpr (kSXY[F] >= 0) {
-        if (role == ROLE_SXY) off = SL::sxy(kSXY[F], ly, lx);
+        if (role == ROLE_SXY) off = SL::template sxy<F>(ly, lx);
       }
       const int nout = kNZ[F] ? nout4 : R;
 #pragma unroll
@@ -503,7 +513,7 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
       for (int k = 0; k < 4; ++k) v[k] = o[k];
       if constexpr (kSX[F] >= 0) {
         if (rm & 1) {
-          const int off = SL::sx(kSX[F], ly, lx - 1, bb);
+          const int off = SL::template sx<F>(ly, lx - 1, bb);
 #pragma unroll
           for (int k = 0; k < 4; ++k)
             if (k < nout) v[k] += lds[off + k];
@@ -511,7 +521,7 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
       }
       if constexpr (kSY[F] >= 0) {
         if (rm & 2) {
-          const int off = SL::sy(kSY[F], ly - 1, lx, a);
+          const int off = SL::template sy<F>(ly - 1, lx, a);
 #pragma unroll
           for (int k = 0; k < 4; ++k)
             if (k < nout) v[k] += lds[off + k];
@@ -519,7 +529,7 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
       }
       if constexpr (kSXY[F] >= 0) {
         if (rm & 4) {
-          const int off = SL::sxy(kSXY[F], ly - 1, lx - 1);
+          const int off = SL::template sxy<F>(ly - 1, lx - 1);
 #pragma unroll
           for (int k = 0; k < 4; ++k)
             if (k < nout) v[k] += lds[off + k];
@@ -563,7 +573,6 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
     collect(std::integral_constant<int, 1>{}, oX);
     collect(std::integral_constant<int, 2>{}, oY);
     collect(std::integral_constant<int, 3>{}, oZ);
-    __syncthreads();
   }
 }
 
