@@ -448,10 +448,17 @@ int hc_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t s)
     if (mop->hc_halo) (void)hipFree(mop->hc_halo);
     mop->hc_halo = nullptr;
     mop->hc_halo_n = 0;
-    if (int rc = dalloc((void**)&mop->hc_halo, sizeof(double) * (size_t)std::max<long long>(need, 1))) return rc;
+    // the halo slots, then one zero that the kernel only reads
+    if (int rc = dalloc((void**)&mop->hc_halo, sizeof(double) * (size_t)(need + 1))) return rc;
+    if (hipMemset(mop->hc_halo + need, 0, sizeof(double)) != hipSuccess) {
+      (void)hipFree(mop->hc_halo);
+      mop->hc_halo = nullptr;
+      return fail(GYM_E_HIP, "matrix-core operator: workspace set-up failed");
+    }
     mop->hc_halo_n = need;
   }
   q.halo = mop->hc_halo;
+  q.zero = mop->hc_halo + mop->hc_halo_n;
   q.chunk_mode = op->ctx->tile;  // large tiles: whole z columns; small: one layer per workgroup
   if (launch_hodge_mfma(q, nrhs, op->ctx->ncu, s)) return fail(GYM_E_HIP, "matrix-core operator launch failed");
   return 0;

@@ -282,12 +282,17 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
     fok[F] = ev && a < na && bb < nb && l0 >= 0 && l0 < d.count[0] && l1 >= 0 && l1 < d.count[1];
     fbase[F] = d.offset + l0 + (long long)d.count[0] * (l1 - (long long)d.count[1] * d.start[2]);
   }
-  // index of position gz of field F in the lane's column, or -1
-  auto zidx = [&](int F, int gz) -> long long {
-    const DevComp& d = p.f[F];
-    const bool ok = fok[F] && gz >= d.start[2] && gz < d.start[2] + d.count[2];
-    return ok ? fbase[F] + (long long)d.count[0] * d.count[1] * gz : -1;
-  };
+  // the lane's input column: position gz at xcol[F][zsl[F] gz]; a lane
+  // outside the kept set reads the zero (stride 0)
+  const double* xcol[4];
+  int zsl[4];
+#pragma unroll
+  for (int F = 0; F < 4; ++F) {
+    xcol[F] = fok[F] ? x + fbase[F] : p.zero;
+    zsl[F] = fok[F] ? p.f[F].count[0] * p.f[F].count[1] : 0;
+  }
+  // is lattice plane gz of field F kept (uniform)
+  auto zkept = [&](int F, int gz) { return gz >= p.f[F].start[2] && gz < p.f[F].start[2] + p.f[F].count[2]; };
 
   // roles in the x-y sums, 6 bits per field
   int code = 0;
@@ -317,20 +322,14 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
 
   prefetch_metric(zbeg);
   for (int ez = zbeg; ez < zend; ++ez) {
-    // ---- inputs: the cell's coefficients, planes along z (branch-free: a
-    // position outside the kept set loads element 0 and is replaced by zero)
+    // ---- inputs: the cell's coefficients, planes along z
     double iS[4], iX[4], iY[4], iZ[4];
     {
       auto load = [&](int F, int nz, double(&v)[4]) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-          if (k < nz) {
-            const long long id = zidx(F, R * ez + k);
-            const double t = x[id >= 0 ? id : 0];
-            v[k] = id >= 0 ? t : 0.0;
-          } else {
-            v[k] = 0;
-          }
+          const int gz = R * ez + k;
+          v[k] = (k < nz && zkept(F, gz)) ? xcol[F][(long long)zsl[F] * gz] : 0.0;
         }
       };
       load(0, 4, iS);
@@ -538,9 +537,9 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
       // destination column: the vector, or a halo slot of the next tile
       double* dst;
       int zs, zlo, zhi;
-      if (role == ROLE_Y) {
+      if (role == ROLE_Y) {  // a kept column: the input's, in y
         const DevComp& d = p.f[F];
-        dst = y + fbase[F];
+        dst = y + (xcol[F] - x);
         zs = d.count[0] * d.count[1];
         zlo = d.start[2];
         zhi = d.start[2] + d.count[2];

@@ -16,6 +16,7 @@ struct HcParams {
   const double* qd;  // Gauss-point metrics (geom.hpp), FP64
   long long qfs;     // values per metric field
   double* halo;      // tile-boundary partial sums (hodge_mfma_halo_doubles)
+  const double* zero;  // one 0.0 in device memory (read by lanes outside the kept set)
   int chunk_mode;    // z chunks: 0 automatic, 1 whole columns, 2 one layer each
   // filled by the launch
   int tiles_x, tiles_y, chunk, nchunks, nitems, nrhs;
