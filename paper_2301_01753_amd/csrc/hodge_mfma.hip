@@ -51,6 +51,7 @@
 #include "hodge_mfma.hpp"
 
 #include <algorithm>
+#include <utility>
 
 #include "gen/tables_const.hpp"
 #include "geom.hpp"
@@ -100,21 +101,26 @@ __device__ __forceinline__ double mma(double a, double b, double c) {
 
 enum { SET = 0, ADD = 1, SUB = 2, NSET = 3 };
 
-// A table as 16 scalar-register constants, materialised where it is used:
-// the empty asm keeps the compiler from hoisting all tables out of the
-// layer loop (they do not fit the scalar registers together and would spill).
-__device__ __forceinline__ double opaque(double v) {
-  asm volatile("" : "+s"(v));
-  return v;
+// A table as 16 scalar-register constants, materialised where it is used.
+// Each entry is written by two s_mov_b32 of its bit pattern inside volatile
+// asm: the compiler can then neither hoist the entries out of the layer loop
+// (all tables together do not fit the scalar registers and would be spilled
+// and reloaded lane by lane) nor keep them across the loop.
+template <int T, bool W, int t, int i>
+__device__ __forceinline__ double kconst() {
+  constexpr unsigned long long b = __builtin_bit_cast(unsigned long long, tab<T, W>(t, i));
+  unsigned lo, hi;
+  asm volatile("s_mov_b32 %0, %1" : "=s"(lo) : "i"((unsigned)(b & 0xffffffffu)));
+  asm volatile("s_mov_b32 %0, %1" : "=s"(hi) : "i"((unsigned)(b >> 32)));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 template <int T, bool W>
 struct KTab {
   double k[4][4];
-  __device__ __forceinline__ KTab() {
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) k[t][i] = (T == TE && i == R) ? 0.0 : opaque(tab<T, W>(t, i));
+  __device__ __forceinline__ KTab() { fill(std::make_integer_sequence<int, 16>{}); }
+  template <int... I>
+  __device__ __forceinline__ void fill(std::integer_sequence<int, I...>) {
+    ((k[I / 4][I % 4] = (T == TE && I % 4 == R) ? 0.0 : kconst<T, W, I / 4, I % 4>()), ...);
   }
 };
 // z forward: g[k] (=, +=, -=, = -) sum_{c < NC} T(k, c) y[c]
@@ -295,7 +301,7 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
   auto zkept = [&](int F, int gz) { return gz >= p.f[F].start[2] && gz < p.f[F].start[2] + p.f[F].count[2]; };
 
   // roles in the x-y sums, 6 bits per field
-  int code = 0;
+  int code0 = 0;
 #pragma unroll
   for (int F = 0; F < 4; ++F) {
     const int na = kNX[F] ? R + 1 : R, nb = kNY[F] ? R + 1 : R;
@@ -315,7 +321,7 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
         if (kNX[F] && kNY[F] && a == 0 && bb == 0 && lx > 0 && ly > 0) rm |= 4;
       }
     }
-    code |= (role | rm << 3) << (kCodeBits * F);
+    code0 |= (role | rm << 3) << (kCodeBits * F);
   }
 
   double cS = 0, cX = 0, cY = 0;  // top planes carried into the cell above
@@ -483,6 +489,10 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
     // 0 .. R - 1, and R for nodal-z fields at the top of the mesh)
     const int nout4 = top ? R + 1 : R;
     double* lds = slots[ez & 1];
+    // the roles, re-read each layer: their lane masks would otherwise be
+    // hoisted out of the loop and spilled
+    int code = code0;
+    asm volatile("" : "+v"(code));
     auto send = [&](auto fc, const double(&o)[4]) {
       constexpr int F = decltype(fc)::value;
       const int role = (code >> (kCodeBits * F)) & 7;
