@@ -6,11 +6,13 @@ its own Jacobian field), degree-3 Hodge Laplacian on 1-forms (sigma in H1_0,
 u in H0(curl)), 8 right-hand sides per apply, FP64.  758.5 M unknowns per
 apply (94.8 M per right-hand side).
 
-A step is one FP64 operator apply y = A x of all 8 right-hand sides: the
-gather of the lattice closure, the incidence G, C (+-1 sums), the four mass
-applies (M0, M1 twice, M2) by sum-factorised contractions with the
-Gauss-point metrics of the curved cells, the transposed incidence and the
-deterministic scatter.  x is resident in HBM before the timed region.
+A step is one FP64 operator apply y = A x of all 8 right-hand sides: per
+cell, the sum-factorised contractions of the four mass terms (M0, M1 twice,
+M2; the gradient and curl through the nodal-derivative tables) with the
+Gauss-point metrics of the curved cells, the x and y contractions on the
+matrix cores; the deterministic sums over shared positions (LDS within a
+tile, a second kernel across tiles).  x is resident in HBM before the timed
+region.
 
 value = 8 x ndofs / (median HIP-event time of one apply), GDoF/s; the wall
 time of the K timed applies gives ms_per_step.  Also reported (extras): the
@@ -488,9 +490,8 @@ def cfl_rate(gym, ctx, N):
 # Sources of the operator kernel: the HBM traffic recorded under profiles/
 # (rocprofv3 FETCH_SIZE / WRITE_SIZE runs) is reported only while these are
 # unchanged since the counters were taken.
-KERNEL_SOURCES = ("paper_2301_01753_amd/csrc/op_kernel.hpp", "paper_2301_01753_amd/csrc/tile.hpp",
-                  "paper_2301_01753_amd/csrc/curved.hpp", "paper_2301_01753_amd/csrc/minres_step.hpp",
-                  "paper_2301_01753_amd/csrc/op_hodge.hip", "paper_2301_01753_amd/csrc/kernels.hpp",
+KERNEL_SOURCES = ("paper_2301_01753_amd/csrc/hodge_mfma.hip", "paper_2301_01753_amd/csrc/hodge_mfma.hpp",
+                  "paper_2301_01753_amd/csrc/kernels.hpp", "paper_2301_01753_amd/csrc/geom.hpp",
                   "paper_2301_01753_amd/csrc/gen/gen_tables.cpp", "paper_2301_01753_amd/csrc/tables.cpp")
 TRAFFIC_FILE = "profiles/op_kernel_hodge_r3_96cube_perturbed_traffic.txt"
 
@@ -613,14 +614,16 @@ def main():
         f"wall {wall / args.steps * 1e3:.3f} ms per apply")
     nel3 = N ** 3
     flops = algorithmic_flops_per_element("hodge", r, metric=True) * nel3 * nrhs
-    # bytes: the vectors in and out once, and the 13 Gauss-point metric fields
-    # the Hodge operator reads (det J, the HCURL and HDIV metrics) once
-    qbytes = 13 * 8.0 * ((r + 1) * N) ** 3
+    # bytes: the vectors in and out once, and the Gauss-point metric fields the
+    # kernel reads once (1/det J and the six HCURL entries; det J and the HDIV
+    # metric follow from them)
+    qbytes = 7 * 8.0 * ((r + 1) * N) ** 3
     bytes_ = 16.0 * n * nrhs + qbytes
     roof = {"bound": "alu", "achieved": flops / t_med / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic("hodge_r3_96cube_perturbed_8rhs_f64")
-    roof["kernel"] = "op_kernel_rhs<Hodge, r=3, curved (Gauss-point metrics), FP64>"
+    roof["kernel"] = ("hodge_mfma_kernel<16, 2> + hodge_mfma_fixup (one apply: the matrix-core element kernel "
+                      "and its tile-boundary sums)")
     roof["avg_launch_us"] = sum(ms) / len(ms) * 1e3
     roof["median_launch_us"] = t_med * 1e6
     roof["algorithmic_flops"] = flops
