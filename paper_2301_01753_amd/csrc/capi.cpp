@@ -438,10 +438,7 @@ int hc_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t s)
   q.f[0] = a.c[0];
   for (int c = 0; c < 3; ++c) q.f[1 + c] = b.c[c];
   for (int i = 0; i < 3; ++i) q.nel[i] = (int)m->nel[i];
-  const void* qd = nullptr;
-  if (int rc = mesh_qdata(m, op->r, 0, &qd)) return rc;
-  q.qd = static_cast<const double*>(qd);
-  q.qfs = (long long)(op->r + 1) * m->nel[0] * (op->r + 1) * m->nel[1] * (op->r + 1) * m->nel[2];
+  q.verts = m->d_vertices;
   gym_op* mop = const_cast<gym_op*>(op);  // lazily sized apply state
   const long long need = hodge_mfma_halo_doubles(q.nel, nrhs);
   if (mop->hc_halo_n < need) {
@@ -1041,11 +1038,14 @@ int gym_mesh_create(gym_ctx* ctx, int dim, const int64_t nel[3], const double* v
       delete m;
       return rc;
     }
-    if (int rc = dalloc((void**)&m->d_vertices, sizeof(double) * nv * dim)) {
+    // 16 doubles of zero padding: the matrix-core Hodge kernel reads vertex
+    // rows in 128-byte pieces that may run past the last vertex
+    if (int rc = dalloc((void**)&m->d_vertices, sizeof(double) * (nv * dim + 16))) {
       delete m;
       return rc;
     }
     hipError_t e = hipMemcpy(m->d_vertices, vertices, sizeof(double) * nv * dim, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(m->d_vertices + nv * dim, 0, sizeof(double) * 16);
     if (e != hipSuccess) {
       (void)hipFree(m->d_vertices);
       delete m;

@@ -44,6 +44,9 @@ int main(int argc, char** argv) {
     emit(f, "phiw", t.phi, r + 1, r + 1, r + 1, r + 1, true, t.gw);
     emit(f, "edge", t.edge, r + 1, r, r + 1, r, false, t.gw);
     emit(f, "edgew", t.edge, r + 1, r, r + 1, r, true, t.gw);
+    std::fprintf(f, "  static constexpr double gx[%d] = {", r + 1);
+    for (int s = 0; s <= r; ++s) std::fprintf(f, "%s%a", s ? ", " : "", t.gx[s]);
+    std::fprintf(f, "};  // Gauss points on [0, 1]\n");
     std::fprintf(f, "};\n\n");
   }
   std::fprintf(f, "}  // namespace ctabs\n}  // namespace gym\n");

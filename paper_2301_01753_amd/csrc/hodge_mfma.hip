@@ -32,11 +32,11 @@
 // w_r T(r, c).  The z contractions and the metric are FMAs in registers with
 // the table entries as compile-time constants.
 //
-// Metric: per Gauss point 1/det J and the HCURL metric G1 are read (7 of the
-// 14 precomputed fields); det J = det G1 and the HDIV metric G1^-1 =
-// adj(G1) / det J follow in registers.  A wavefront loads its cells' values
-// for the next layer straight into its own LDS rows (global-to-LDS loads,
-// no registers, no barrier) while it computes the current one.
+// Metric: computed in registers from the cell's 8 vertices (J, adj J, det J,
+// G1, G2 at each Gauss point); a wavefront loads its cells' vertex rows for
+// the next layer straight into its own LDS rows (global-to-LDS loads, no
+// registers, no barrier).  No per-Gauss-point metric is read from memory:
+// read per right-hand side, it cost more than the rest of the kernel.
 //
 // Sums over cells: a workgroup owns a TX x TY tile of cells and marches
 // through a chunk of layers in z.  The top z plane of a cell is carried in
@@ -167,13 +167,8 @@ __device__ __forceinline__ long long kept_index(const DevComp& d, int g0, int g1
   return d.offset + l0 + (long long)d.count[0] * (l1 + (long long)d.count[1] * l2);
 }
 
-// Metric fields read per Gauss point: 1/det J and the six HCURL entries
-// G1 = det J J^-1 J^-T (fields QF_INVDET .. QF_HCURL + 5, consecutive).  The
-// other two follow from G1: det G1 = det J, and the HDIV metric
-// J^T J / det J = G1^-1 = adj(G1) / det J.
-constexpr int kQF = 7;
-constexpr int kQRows = kQF * 4 * 4;
-static_assert(QF_HCURL == QF_INVDET + 1, "1/det J and the HCURL metric are consecutive fields");
+// Gauss points on [0, 1] of the rule the tables use
+__host__ __device__ constexpr double gpt(int t) { return Tab::gx[t]; }
 
 // Workgroup tile of cells: TX x TY, four cells (a row of four along x) per
 // wavefront.
@@ -217,13 +212,13 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
   using SL = Slots<TX, TY>;
   constexpr int NW = TX * TY / 4;
   __shared__ double slots[2][SL::kN];
-  // per wavefront: the metric of its four cells for one layer, rows
-  // (field, k, j) of 16 x points (4 cells x 4 Gauss points), filled by
-  // direct global-to-LDS loads one layer ahead
-  __shared__ double qm[NW][kQRows * 16];
+  // per wavefront, two layers: the vertices of its four cells, rows (z, y) of
+  // 16 doubles from the first cell's low x vertex (5 vertices, 3
+  // coordinates each), filled by direct global-to-LDS loads a layer ahead
+  __shared__ double vrow[NW][2][64];
 
   // blocks b, b + 8, ... run on one XCD: the right-hand sides of an item
-  // are consecutive there, so its metric is read from HBM about once
+  // are consecutive there
   const int blk_id = blockIdx.x;
   const int rhs = (blk_id >> 3) % p.nrhs;
   const int item = (blk_id & 7) + 8 * (blk_id / (8 * p.nrhs));
@@ -249,24 +244,27 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
   double* __restrict__ hxy = hy + p.hy_n;
   const int LX = R * Nx + 1, LY = R * Ny + 1, LZ = R * Nz + 1;
 
-  // metric lattice: the wavefront's rows of 16 x points start at cell x0w
-  const long long GX = (long long)Q * Nx, GY = (long long)Q * Ny;
+  // vertex rows of the wavefront's cells: x from vertex xs (a cell beyond
+  // the mesh uses the last cell's vertices: its inputs are zero), y from ey'
   const int x0w = tx * TX + 4 * (wv % WX);
-  double* qw = &qm[wv][0];
-  auto prefetch_metric = [&](int ezq) {
-    // lane L of instruction t: row 8 t + L / 8, points 2 (L % 8), + 1 (cells
-    // beyond the mesh read the last cell: their inputs are zero)
-    const int half = lane & 7, rsub = lane >> 3;
-    const long long xoff = (long long)Q * min(x0w + (half >> 1), Nx - 1) + 2 * (half & 1);
-    const long long yrow = (long long)Q * min(ey, Ny - 1);
-#pragma unroll
-    for (int t = 0; t < kQRows / 8; ++t) {
-      const int row = 8 * t + rsub;
-      const int f = row >> 4, kk = (row >> 2) & 3, j = row & 3;
-      const double* src = p.qd + (long long)(QF_INVDET + f) * p.qfs + ((long long)(Q * ezq + kk) * GY + yrow + j) * GX + xoff;
-      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)(qw + 128 * t), 16, 0, 0);
+  const int xs = min(x0w, Nx - 1), eyv = min(ey, Ny - 1);
+  const int vx = min(ex, Nx - 1) - xs;  // the lane's cell, 0..3, within the rows
+  auto prefetch_verts = [&](int ezq) {
+    // lanes 0-31: row L / 8 = (z, y) bits, doubles 2 (L % 8), + 1
+    if (lane < 32) {
+      const int row = lane >> 3, b2 = row >> 1, b1 = row & 1;
+      const double* src =
+          p.verts + (((long long)(ezq + b2) * (Ny + 1) + (eyv + b1)) * (Nx + 1) + xs) * 3 + 2 * (lane & 7);
+      __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)&vrow[wv][ezq & 1][0], 16, 0, 0);
     }
   };
+  // Gauss points of the lane's (i, j) = (c, r)
+  double xi1 = 0, xi2 = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (c == t) xi1 = gpt(t);
+    if (r == t) xi2 = gpt(t);
+  }
 
   const int zfirst = chunk * p.chunk;
   const int zend = min(zfirst + p.chunk, Nz);
@@ -326,8 +324,11 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
 
   double cS = 0, cX = 0, cY = 0;  // top planes carried into the cell above
 
-  prefetch_metric(zbeg);
+  prefetch_verts(zbeg);
   for (int ez = zbeg; ez < zend; ++ez) {
+    // the next layer's vertices, issued before this layer's inputs (whose
+    // wait then covers them)
+    if (ez + 1 < zend) prefetch_verts(ez + 1);
     // ---- inputs: the cell's coefficients, planes along z
     double iS[4], iX[4], iY[4], iZ[4];
     {
@@ -396,38 +397,85 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
       zf<3, SUB>(K, ZDN, cy);   // -d/dx u_z
     }
 
-    // ---- pointwise metric (this wavefront's LDS rows, loaded a layer ahead)
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the global-to-LDS loads have landed
+    // ---- pointwise metric, from the cell's vertices (paper section 2: the
+    // masses pulled back through the multilinear cell map with Jacobian J):
+    // det J, G1 = adj(J) adj(J)^T / det J (HCURL), G2 = J^T J / det J (HDIV,
+    // applied as J^T (J v) / det J).
+    // Column d of J is the derivative along reference axis d, a bilinear
+    // interpolation of the cell's edge vectors along d in the other two
+    // coordinates; with (xi1, xi2) fixed per lane, columns 0 and 1 are linear
+    // in xi3 and column 2 is constant over the lane's z column.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the vertex rows have landed
     asm volatile("" ::: "memory");
+    {
+      const double* V = &vrow[wv][ez & 1][0];
+      auto vtx = [&](int b0, int b1, int b2, int comp) { return V[(b2 * 2 + b1) * 16 + (vx + b0) * 3 + comp]; };
+      double A0[3], dA[3], B0[3], dB[3], Cc[3];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      auto q = [&](int f) { return qw[((f * 4 + k) * 4 + r) * 16 + 4 * blk + c]; };
-      const double inv = q(0);
-      const double m00 = q(1), m01 = q(2), m02 = q(3), m11 = q(4), m12 = q(5), m22 = q(6);
-      // cofactors of the symmetric G1: adj(G1) = det J G1^-1
-      const double c00 = m11 * m22 - m12 * m12, c01 = m02 * m12 - m01 * m22, c02 = m01 * m12 - m02 * m11;
-      const double c11 = m00 * m22 - m02 * m02, c12 = m01 * m02 - m00 * m12, c22 = m00 * m11 - m01 * m01;
-      const double det = m00 * c00 + m01 * c01 + m02 * c02;
-      const double n00 = c00 * inv, n01 = c01 * inv, n02 = c02 * inv, n11 = c11 * inv, n12 = c12 * inv,
-                   n22 = c22 * inv;
-      sg[k] = -det * sg[k];
-      double t0 = ux[k], t1 = uy[k], t2 = uz[k];
-      ux[k] = m00 * t0 + m01 * t1 + m02 * t2;
-      uy[k] = m01 * t0 + m11 * t1 + m12 * t2;
-      uz[k] = m02 * t0 + m12 * t1 + m22 * t2;
-      t0 = gx[k], t1 = gy[k], t2 = gz[k];
-      gx[k] = m00 * t0 + m01 * t1 + m02 * t2;
-      gy[k] = m01 * t0 + m11 * t1 + m12 * t2;
-      gz[k] = m02 * t0 + m12 * t1 + m22 * t2;
-      t0 = cx[k], t1 = cy[k], t2 = cz[k];
-      cx[k] = n00 * t0 + n01 * t1 + n02 * t2;
-      cy[k] = n01 * t0 + n11 * t1 + n12 * t2;
-      cz[k] = n02 * t0 + n12 * t1 + n22 * t2;
+      for (int i = 0; i < 3; ++i) {
+        // d/dxi1: edges along x at (y, z) corners, interpolated in xi2, then xi3
+        const double e00 = vtx(1, 0, 0, i) - vtx(0, 0, 0, i), e10 = vtx(1, 1, 0, i) - vtx(0, 1, 0, i);
+        const double e01 = vtx(1, 0, 1, i) - vtx(0, 0, 1, i), e11 = vtx(1, 1, 1, i) - vtx(0, 1, 1, i);
+        const double a0 = e00 + xi2 * (e10 - e00), a1 = e01 + xi2 * (e11 - e01);
+        A0[i] = a0;
+        dA[i] = a1 - a0;
+        // d/dxi2: edges along y at (x, z) corners, interpolated in xi1, then xi3
+        const double f00 = vtx(0, 1, 0, i) - vtx(0, 0, 0, i), f10 = vtx(1, 1, 0, i) - vtx(1, 0, 0, i);
+        const double f01 = vtx(0, 1, 1, i) - vtx(0, 0, 1, i), f11 = vtx(1, 1, 1, i) - vtx(1, 0, 1, i);
+        const double b0 = f00 + xi1 * (f10 - f00), b1 = f01 + xi1 * (f11 - f01);
+        B0[i] = b0;
+        dB[i] = b1 - b0;
+        // d/dxi3: edges along z at (x, y) corners, interpolated in xi1, xi2
+        const double g00 = vtx(0, 0, 1, i) - vtx(0, 0, 0, i), g10 = vtx(1, 0, 1, i) - vtx(1, 0, 0, i);
+        const double g01 = vtx(0, 1, 1, i) - vtx(0, 1, 0, i), g11 = vtx(1, 1, 1, i) - vtx(1, 1, 0, i);
+        const double c0 = g00 + xi1 * (g10 - g00), c1 = g01 + xi1 * (g11 - g01);
+        Cc[i] = c0 + xi2 * (c1 - c0);
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double xi3 = gpt(k);
+        double J[3][3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          J[i][0] = A0[i] + xi3 * dA[i];
+          J[i][1] = B0[i] + xi3 * dB[i];
+          J[i][2] = Cc[i];
+        }
+        // adj[a][i] = cofactor of J[i][a]
+        const double a00 = J[1][1] * J[2][2] - J[1][2] * J[2][1], a01 = J[0][2] * J[2][1] - J[0][1] * J[2][2],
+                     a02 = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        const double a10 = J[1][2] * J[2][0] - J[1][0] * J[2][2], a11 = J[0][0] * J[2][2] - J[0][2] * J[2][0],
+                     a12 = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        const double a20 = J[1][0] * J[2][1] - J[1][1] * J[2][0], a21 = J[0][1] * J[2][0] - J[0][0] * J[2][1],
+                     a22 = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        const double det = J[0][0] * a00 + J[0][1] * a10 + J[0][2] * a20;
+        // 1 / det J: hardware reciprocal and two Newton steps (error about
+        // one ulp; the division sequence cost three times the instructions)
+        double inv = __builtin_amdgcn_rcp(det);
+        inv = __builtin_fma(inv, __builtin_fma(-det, inv, 1.0), inv);
+        inv = __builtin_fma(inv, __builtin_fma(-det, inv, 1.0), inv);
+        const double m00 = (a00 * a00 + a01 * a01 + a02 * a02) * inv, m01 = (a00 * a10 + a01 * a11 + a02 * a12) * inv,
+                     m02 = (a00 * a20 + a01 * a21 + a02 * a22) * inv, m11 = (a10 * a10 + a11 * a11 + a12 * a12) * inv,
+                     m12 = (a10 * a20 + a11 * a21 + a12 * a22) * inv, m22 = (a20 * a20 + a21 * a21 + a22 * a22) * inv;
+        sg[k] = -det * sg[k];
+        double t0 = ux[k], t1 = uy[k], t2 = uz[k];
+        ux[k] = m00 * t0 + m01 * t1 + m02 * t2;
+        uy[k] = m01 * t0 + m11 * t1 + m12 * t2;
+        uz[k] = m02 * t0 + m12 * t1 + m22 * t2;
+        t0 = gx[k], t1 = gy[k], t2 = gz[k];
+        gx[k] = m00 * t0 + m01 * t1 + m02 * t2;
+        gy[k] = m01 * t0 + m11 * t1 + m12 * t2;
+        gz[k] = m02 * t0 + m12 * t1 + m22 * t2;
+        // G2 v = J^T (J v) / det J: two matrix-vector products
+        t0 = cx[k], t1 = cy[k], t2 = cz[k];
+        const double w0 = (J[0][0] * t0 + J[0][1] * t1 + J[0][2] * t2) * inv,
+                     w1 = (J[1][0] * t0 + J[1][1] * t1 + J[1][2] * t2) * inv,
+                     w2 = (J[2][0] * t0 + J[2][1] * t1 + J[2][2] * t2) * inv;
+        cx[k] = J[0][0] * w0 + J[1][0] * w1 + J[2][0] * w2;
+        cy[k] = J[0][1] * w0 + J[1][1] * w1 + J[2][1] * w2;
+        cz[k] = J[0][2] * w0 + J[1][2] * w1 + J[2][2] * w2;
+      }
     }
-    // the rows are read: load the next layer's behind them
-    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
-    asm volatile("" ::: "memory");
-    if (ez + 1 < zend) prefetch_metric(ez + 1);
 
     // ---- backward: p = sg, h = u, g = grad, v = curl (metric applied).
     // z contractions (weighted tables) grouped by the (x, y) tables of a term:

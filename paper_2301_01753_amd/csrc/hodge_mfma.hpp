@@ -13,8 +13,7 @@ struct HcParams {
   long long ndofs;   // stride between right-hand sides
   DevComp f[4];      // sigma (H1_0), u_x, u_y, u_z (H0(curl)), kept positions
   int nel[3];
-  const double* qd;  // Gauss-point metrics (geom.hpp), FP64
-  long long qfs;     // values per metric field
+  const double* verts;  // (nel+1)^3 x 3 cell vertices (x fastest), 16 doubles of padding after
   double* halo;      // tile-boundary partial sums (hodge_mfma_halo_doubles)
   const double* zero;  // one 0.0 in device memory (read by lanes outside the kept set)
   int chunk_mode;    // z chunks: 0 automatic, 1 whole columns, 2 one layer each
