@@ -614,10 +614,9 @@ def main():
         f"wall {wall / args.steps * 1e3:.3f} ms per apply")
     nel3 = N ** 3
     flops = algorithmic_flops_per_element("hodge", r, metric=True) * nel3 * nrhs
-    # bytes: the vectors in and out once, and the Gauss-point metric fields the
-    # kernel reads once (1/det J and the six HCURL entries; det J and the HDIV
-    # metric follow from them)
-    qbytes = 7 * 8.0 * ((r + 1) * N) ** 3
+    # bytes: the vectors in and out once, and the cell vertices once (the
+    # kernel computes the Piola metrics at the Gauss points from them)
+    qbytes = 3 * 8.0 * (N + 1) ** 3
     bytes_ = 16.0 * n * nrhs + qbytes
     roof = {"bound": "alu", "achieved": flops / t_med / 1e12, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
