@@ -420,19 +420,20 @@ int mfma_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t 
   return 0;
 }
 
-// Curved Hodge apply of degree 3 in FP64 on the matrix cores (not with the
-// fused MINRES step, which the tile kernel carries).
+// Curved Hodge apply of degree 3 on the matrix cores, FP64 arithmetic with
+// FP64 or FP32 vectors (not with the fused MINRES step, which the tile
+// kernel carries).
 bool hc_path(const gym_op* op, int prec, const MrStep* mr) {
   const gym_mesh* m = op->mesh;
-  return prec == GYM_F64 && op->problem != GYM_MIXED_POISSON && m->curved && m->dim == 3 && !m->periodic &&
-         op->r == kHcDegree && !mr && op->ctx->curved_kernel == 0;
+  return (prec == GYM_F64 || prec == GYM_F32) && op->problem != GYM_MIXED_POISSON && m->curved && m->dim == 3 &&
+         !m->periodic && op->r == kHcDegree && !mr && op->ctx->curved_kernel == 0;
 }
 
-int hc_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t s) {
+int hc_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
   const gym_mesh* m = op->mesh;
   HcParams q{};
-  q.x = static_cast<const double*>(x);
-  q.y = static_cast<double*>(y);
+  q.x = x;
+  q.y = y;
   q.ndofs = op->na + op->nb;
   const DevSpace a = to_dev(op->sa, 0), b = to_dev(op->sb, op->na);
   q.f[0] = a.c[0];
@@ -457,14 +458,15 @@ int hc_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t s)
   q.halo = mop->hc_halo;
   q.zero = mop->hc_halo + mop->hc_halo_n;
   q.chunk_mode = op->ctx->tile;  // large tiles: whole z columns; small: one layer per workgroup
-  if (launch_hodge_mfma(q, nrhs, op->ctx->ncu, s)) return fail(GYM_E_HIP, "matrix-core operator launch failed");
+  if (launch_hodge_mfma(q, nrhs, op->ctx->ncu, s, prec == GYM_F32))
+    return fail(GYM_E_HIP, "matrix-core operator launch failed");
   return 0;
 }
 
 int op_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s, const MrStep* mr,
               int* wg_out) {
   if (mfma_path(op, prec)) return mfma_launch(op, nrhs, x, y, s, mr, wg_out);
-  if (!wg_out && hc_path(op, prec, mr)) return hc_launch(op, nrhs, x, y, s);
+  if (!wg_out && hc_path(op, prec, mr)) return hc_launch(op, prec, nrhs, x, y, s);
   OpParams p;
   int prob;
   build_op_params(op, x, y, p, prob);

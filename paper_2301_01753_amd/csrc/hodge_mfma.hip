@@ -205,7 +205,8 @@ constexpr int kCodeBits = 6;  // per field: role (3 bits), then the neighbours r
 
 // WPE: wavefronts per SIMD the registers are budgeted for (2: about 250
 // VGPRs; 3 and 4 spill and measured slower).
-template <int TX, int TY, int WPE>
+// TV: the vectors' type (the arithmetic is FP64 either way).
+template <int TX, int TY, int WPE, typename TV>
 __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams p) {
   static_assert(TX % 4 == 0, "four cells per wavefront along x");
   constexpr int WX = TX / 4;
@@ -237,8 +238,8 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
   const double fN = lane_tab<TN, false>(c, r), fD = lane_tab<TD, false>(c, r), fE = lane_tab<TE, false>(c, r);
   const double bN = lane_tab<TN, true>(r, c), bD = lane_tab<TD, true>(r, c), bE = lane_tab<TE, true>(r, c);
 
-  const double* __restrict__ x = p.x + (long long)rhs * p.ndofs;
-  double* __restrict__ y = p.y + (long long)rhs * p.ndofs;
+  const TV* __restrict__ x = static_cast<const TV*>(p.x) + (long long)rhs * p.ndofs;
+  TV* __restrict__ y = static_cast<TV*>(p.y) + (long long)rhs * p.ndofs;
   double* __restrict__ hx = p.halo + (long long)rhs * (p.hx_n + p.hy_n + p.hxy_n);
   double* __restrict__ hy = hx + p.hx_n;
   double* __restrict__ hxy = hy + p.hy_n;
@@ -288,11 +289,11 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
   }
   // the lane's input column: position gz at xcol[F][zsl[F] gz]; a lane
   // outside the kept set reads the zero (stride 0)
-  const double* xcol[4];
+  const TV* xcol[4];
   int zsl[4];
 #pragma unroll
   for (int F = 0; F < 4; ++F) {
-    xcol[F] = fok[F] ? x + fbase[F] : p.zero;
+    xcol[F] = fok[F] ? x + fbase[F] : static_cast<const TV*>(p.zero);
     zsl[F] = fok[F] ? p.f[F].count[0] * p.f[F].count[1] : 0;
   }
   // is lattice plane gz of field F kept (uniform)
@@ -336,7 +337,7 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int gz = R * ez + k;
-          v[k] = (k < nz && zkept(F, gz)) ? xcol[F][(long long)zsl[F] * gz] : 0.0;
+          v[k] = (k < nz && zkept(F, gz)) ? static_cast<double>(xcol[F][(long long)zsl[F] * gz]) : 0.0;
         }
       };
       load(0, 4, iS);
@@ -592,33 +593,34 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
             if (k < nout) v[k] += lds[off + k];
         }
       }
-      // destination column: the vector, or a halo slot of the next tile
-      double* dst;
-      int zs, zlo, zhi;
+      // destination column: the vector, or a halo slot of the next tile (FP64)
       if (role == ROLE_Y) {  // a kept column: the input's, in y
         const DevComp& d = p.f[F];
-        dst = y + (xcol[F] - x);
-        zs = d.count[0] * d.count[1];
-        zlo = d.start[2];
-        zhi = d.start[2] + d.count[2];
-      } else {
-        zlo = 0;
-        zhi = LZ;
-        if (role == ROLE_HX) {
-          dst = hx + ((kSX[F] * (p.tiles_x - 1) + tx) * LZ) * LY + gb;
-          zs = LY;
-        } else if (role == ROLE_HY) {
-          dst = hy + ((kSY[F] * (p.tiles_y - 1) + ty) * LZ) * LX + ga;
-          zs = LX;
-        } else {
-          dst = hxy + ((kSXY[F] * (p.tiles_x - 1) + tx) * (p.tiles_y - 1) + ty) * LZ;
-          zs = 1;
+        TV* dst = y + (xcol[F] - x);
+        const int zs = d.count[0] * d.count[1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int gz = R * ez + k;
+          if (k < nout && gz >= d.start[2] && gz < d.start[2] + d.count[2]) dst[(long long)zs * gz] = static_cast<TV>(v[k]);
         }
+        return;
+      }
+      double* dst;
+      int zs;
+      if (role == ROLE_HX) {
+        dst = hx + ((kSX[F] * (p.tiles_x - 1) + tx) * LZ) * LY + gb;
+        zs = LY;
+      } else if (role == ROLE_HY) {
+        dst = hy + ((kSY[F] * (p.tiles_y - 1) + ty) * LZ) * LX + ga;
+        zs = LX;
+      } else {
+        dst = hxy + ((kSXY[F] * (p.tiles_x - 1) + tx) * (p.tiles_y - 1) + ty) * LZ;
+        zs = 1;
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int gz = R * ez + k;
-        if (k < nout && gz >= zlo && gz < zhi) dst[(long long)zs * gz] = v[k];
+        if (k < nout) dst[(long long)zs * gz] = v[k];
       }
     };
     send(std::integral_constant<int, 0>{}, oS);
@@ -648,13 +650,14 @@ __device__ __forceinline__ const DevComp& field_comp(const HcParams& p, int f) {
 // lines along y: y += HX (+ HY + HXY where the position is on a y boundary
 // too).  Part B: the y boundary planes of the fields nodal in y (sigma, u_x,
 // u_z), lines along x: y += HY, except where part A adds.
+template <typename TV>
 __global__ void __launch_bounds__(256) hodge_mfma_fixup(HcParams p, int TX, int TY) {
   const int Nx = p.nel[0], Ny = p.nel[1], Nz = p.nel[2];
   const int LX = R * Nx + 1, LY = R * Ny + 1, LZ = R * Nz + 1, LM = max(LX, LY);
   const int bxn = p.tiles_x - 1, byn = p.tiles_y - 1;
   const int ra = 3 * bxn * LZ, rb = 3 * byn * LZ;
   const int rhs = blockIdx.y;
-  double* y = p.y + (long long)rhs * p.ndofs;
+  TV* y = static_cast<TV*>(p.y) + (long long)rhs * p.ndofs;
   const double* hx = p.halo + (long long)rhs * (p.hx_n + p.hy_n + p.hxy_n);
   const double* hy = hx + p.hx_n;
   const double* hxy = hy + p.hy_n;
@@ -670,14 +673,14 @@ __global__ void __launch_bounds__(256) hodge_mfma_fixup(HcParams p, int TX, int 
       const int gx = R * TX * (bx + 1);
       const long long id = kept_index(field_comp(p, F), gx, gy, gz);
       if (id < 0) continue;
-      double val = y[id] + hx[((long long)(fs * bxn + bx) * LZ + gz) * LY + gy];
+      double val = static_cast<double>(y[id]) + hx[((long long)(fs * bxn + bx) * LZ + gz) * LY + gy];
       if (F != 2 && gy % (R * TY) == 0 && gy > 0 && gy < R * Ny) {
         const int by = gy / (R * TY) - 1;
         const int fy = F == 0 ? 0 : 2, fxy = F == 0 ? 0 : 1;
         val += hy[((long long)(fy * byn + by) * LZ + gz) * LX + gx];
         val += hxy[((long long)(fxy * bxn + bx) * byn + by) * LZ + gz];
       }
-      y[id] = val;
+      y[id] = static_cast<TV>(val);
     } else {
       const int r2 = row - ra;
       const int fs = r2 / (byn * LZ), rem = r2 - fs * byn * LZ;
@@ -689,7 +692,7 @@ __global__ void __launch_bounds__(256) hodge_mfma_fixup(HcParams p, int TX, int 
       const int gy = R * TY * (by + 1);
       const long long id = kept_index(field_comp(p, F), gx, gy, gz);
       if (id < 0) continue;
-      y[id] += hy[((long long)(fs * byn + by) * LZ + gz) * LX + gx];
+      y[id] = static_cast<TV>(static_cast<double>(y[id]) + hy[((long long)(fs * byn + by) * LZ + gz) * LX + gx]);
     }
   }
 }
@@ -716,7 +719,7 @@ long long hodge_mfma_halo_doubles(const int nel[3], int nrhs) {
   return (long long)nrhs * (h.hx + h.hy + h.hxy);
 }
 
-int launch_hodge_mfma(const HcParams& p0, int nrhs, int ncu, hipStream_t s) {
+int launch_hodge_mfma(const HcParams& p0, int nrhs, int ncu, hipStream_t s, bool f32) {
   HcParams p = p0;
   const HaloDims h = halo_dims(p.nel);
   p.nrhs = nrhs;
@@ -746,7 +749,10 @@ int launch_hodge_mfma(const HcParams& p0, int nrhs, int ncu, hipStream_t s) {
   p.nitems = ntiles * p.nchunks;
   const long long nblk = (long long)((p.nitems + 7) / 8) * 8 * nrhs;
   if (nblk >= (1LL << 31)) return -1;
-  hipLaunchKernelGGL((hodge_mfma_kernel<kTX, kTY, 2>), dim3((unsigned)nblk), dim3(kTX * kTY * 16), 0, s, p);
+  if (f32)
+    hipLaunchKernelGGL((hodge_mfma_kernel<kTX, kTY, 2, float>), dim3((unsigned)nblk), dim3(kTX * kTY * 16), 0, s, p);
+  else
+    hipLaunchKernelGGL((hodge_mfma_kernel<kTX, kTY, 2, double>), dim3((unsigned)nblk), dim3(kTX * kTY * 16), 0, s, p);
   if (hipGetLastError() != hipSuccess) return -1;
   const int LX = R * p.nel[0] + 1, LY = R * p.nel[1] + 1, LZ = R * p.nel[2] + 1;
   const long long rows = 3LL * (p.tiles_x - 1) * LZ + 3LL * (p.tiles_y - 1) * LZ;
@@ -754,7 +760,10 @@ int launch_hodge_mfma(const HcParams& p0, int nrhs, int ncu, hipStream_t s) {
   if (total >= (1LL << 31)) return -1;
   if (total > 0) {
     const dim3 grid((unsigned)std::min<long long>((total + 255) / 256, 4LL * ncu), (unsigned)nrhs);
-    hipLaunchKernelGGL(hodge_mfma_fixup, grid, dim3(256), 0, s, p, kTX, kTY);
+    if (f32)
+      hipLaunchKernelGGL(hodge_mfma_fixup<float>, grid, dim3(256), 0, s, p, kTX, kTY);
+    else
+      hipLaunchKernelGGL(hodge_mfma_fixup<double>, grid, dim3(256), 0, s, p, kTX, kTY);
     if (hipGetLastError() != hipSuccess) return -1;
   }
   return 0;

@@ -8,14 +8,14 @@
 namespace gym {
 
 struct HcParams {
-  const double* x;
-  double* y;
+  const void* x;     // FP64 or FP32 (the launch's f32), as y
+  void* y;
   long long ndofs;   // stride between right-hand sides
   DevComp f[4];      // sigma (H1_0), u_x, u_y, u_z (H0(curl)), kept positions
   int nel[3];
   const double* verts;  // (nel+1)^3 x 3 cell vertices (x fastest), 16 doubles of padding after
   double* halo;      // tile-boundary partial sums (hodge_mfma_halo_doubles)
-  const double* zero;  // one 0.0 in device memory (read by lanes outside the kept set)
+  const void* zero;  // 8 zero bytes in device memory (read by lanes outside the kept set)
   int chunk_mode;    // z chunks: 0 automatic, 1 whole columns, 2 one layer each
   // filled by the launch
   int tiles_x, tiles_y, chunk, nchunks, nitems, nrhs;
@@ -29,6 +29,8 @@ long long hodge_mfma_halo_doubles(const int nel[3], int nrhs);
 // y = A x for nrhs right-hand sides (x, y in the operator's canonical layout,
 // stride ndofs).  Two launches on s: the element kernel, then the sums over
 // tile boundaries.  Returns 0, or -1 on a launch failure.
-int launch_hodge_mfma(const HcParams& p, int nrhs, int ncu, hipStream_t s);
+// f32: x and y are FP32 (the arithmetic stays FP64; only the vectors are
+// stored in FP32).
+int launch_hodge_mfma(const HcParams& p, int nrhs, int ncu, hipStream_t s, bool f32 = false);
 
 }  // namespace gym

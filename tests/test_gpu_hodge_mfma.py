@@ -96,3 +96,34 @@ def test_hodge_mfma_repeat_and_second_operator(g):
         outs.append(op)
         gym.gym_op_destroy(op)
         gym.gym_mesh_destroy(mesh)
+
+
+@pytest.mark.parametrize("nel,nrhs", [((10, 9, 5), 2), ((9, 5, 2), 3)])
+def test_hodge_mfma_fp32_vectors(g, nel, nrhs):
+    # FP32 vectors, FP64 arithmetic: the FP32 result is the FP64 apply of the
+    # FP32-rounded input, rounded (two roundings plus the tile-boundary pass's
+    # third, each half an FP32 ulp: 1e-6 of the output's max norm), and it
+    # meets the oracle within the input rounding.
+    gym, ctx = g
+    print(f"hodge mfma fp32 nel={nel} nrhs={nrhs}", flush=True)
+    verts = synth.perturbed_vertices(nel, 0.15, seed=8)
+    mesh = gym.gym_mesh_create(ctx, 3, nel, vertices=verts)
+    op = gym.gym_op_create(ctx, gym.GYM_HODGE1, mesh, 3)
+    P = problems.Hodge1(Mesh(verts), 3)
+    n = gym.gym_op_ndofs(op)
+    x = synth.random_vector(n, seed=16, nrhs=nrhs)
+    x32 = torch.tensor(x, dtype=torch.float32, device=DEV)
+    y32 = torch.full((nrhs * n,), float("nan"), dtype=torch.float32, device=DEV)
+    gym.gym_op_apply(op, gym.GYM_F32, nrhs, x32, y32)
+    y64 = torch.empty(nrhs * n, dtype=torch.float64, device=DEV)
+    gym.gym_op_apply(op, gym.GYM_F64, nrhs, x32.double(), y64)
+    torch.cuda.synchronize()
+    got = y32.cpu().numpy().astype(np.float64).reshape(nrhs, -1)
+    ref64 = y64.cpu().numpy().reshape(nrhs, -1)
+    xr = x32.cpu().numpy().astype(np.float64).reshape(nrhs, -1)
+    for k in range(nrhs):
+        assert _rel(got[k], ref64[k]) < 1e-6, k
+        assert _rel(got[k], P.A @ xr[k]) < 1e-6, k
+        assert _rel(got[k], P.A @ x.reshape(nrhs, -1)[k]) < 1e-5, k
+    gym.gym_op_destroy(op)
+    gym.gym_mesh_destroy(mesh)
