@@ -393,9 +393,11 @@ int gym_maxwell_destroy(gym_maxwell* mx);
  * M1 (lumped) and P2 = c^2 C^T M2~ C.  The eigenvalues set the stability
  * bound tau <= 2 / omega_max (Proposition Stability) and the numerical
  * dispersion of the scheme (section 5).  P2 vanishes on gradients G Lambda^0;
- * the solver works on P2 + c^2 s Q1^-1 G M0^-1 G^T Q1^-1 instead, which lifts
- * the gradients to c^2 s times the eigenvalues of the Lambda^0 Laplacian and
- * leaves every other eigenpair unchanged, s = grad_shift.  Method: LOBPCG
+ * the solver works on P2 + c^2 s Q1^-1 G D0^-1 G^T Q1^-1 instead (D0 the
+ * diagonal of the Lambda^0 mass matrix M0), which lifts the gradients to
+ * c^2 s times the eigenvalues of the Lambda^0 Laplacian G^T Q1^-1 G taken
+ * against D0 and leaves every other eigenpair unchanged, s = grad_shift.
+ * Method: LOBPCG
  * (Knyazev 2001) with block size `block`, preconditioned by the inverse row
  * sums of M1, from a seeded N(0,1) block. */
 typedef struct gym_eig_opts {

@@ -239,10 +239,40 @@ int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int
   }
   double* fdev = cdev + kEigMaxCols * kEigMaxCols;
   auto col = [&](double* base, int j) { return base + (long long)j * n; };
-  // small host arrays go over synchronously: the source vectors are short-lived
+  // Small host arrays go over asynchronously from a ring of pinned slots; a
+  // slot is written again only after a stream synchronisation (every Gram
+  // matrix brings one; otherwise the ring waits for its oldest copy).
+  constexpr int kRing = 16;
+  constexpr size_t kSlot = (size_t)kEigMaxCols * kEigMaxCols + kEigMaxCols;
+  double* ring = nullptr;
+  if (hipHostMalloc((void**)&ring, sizeof(double) * kRing * kSlot) != hipSuccess) {
+    (void)hipGetLastError();
+    release();
+    return fail(GYM_E_OOM, "eigen-solver: pinned staging allocation failed");
+  }
+  int ring_pos = 0, since_sync = 0;
   auto upload = [&](const std::vector<double>& v, double* dst) {
-    if (hipMemcpyAsync(dst, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, s) != hipSuccess) return -1;
-    return hipStreamSynchronize(s) == hipSuccess ? 0 : -1;
+    if (v.size() > kSlot) return -1;
+    if (since_sync == kRing) {
+      if (hipStreamSynchronize(s) != hipSuccess) return -1;
+      since_sync = 0;
+    }
+    double* h = ring + (size_t)ring_pos * kSlot;
+    std::copy(v.begin(), v.end(), h);
+    ring_pos = (ring_pos + 1) % kRing;
+    ++since_sync;
+    return hipMemcpyAsync(dst, h, sizeof(double) * v.size(), hipMemcpyHostToDevice, s) == hipSuccess ? 0 : -1;
+  };
+  auto gram = [&](const double* U, int p, const double* V, int q, double* G) {
+    const int rc = eig_gram(U, p, V, q, n, G, gw, nb, s);
+    since_sync = 0;
+    return rc;
+  };
+  auto gram2 = [&](const double* U1, int p1, const double* V1, int q1, double* G1, const double* U2, int p2,
+                   const double* V2, int q2, double* G2) {
+    const int rc = eig_gram2(U1, p1, V1, q1, G1, U2, p2, V2, q2, G2, n, gw, nb, s);
+    since_sync = 0;
+    return rc;
   };
   auto copy = [&](double* dst, const double* src, long long cnt) {
     return hipMemcpyAsync(dst, src, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s) == hipSuccess ? 0 : -1;
@@ -251,7 +281,7 @@ int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int
   // the nc columns of (U, AU, BU) scaled to unit B-norm
   auto normalize = [&](double* U, double* AU, double* BU, int nc) -> int {
     std::vector<double> G((size_t)nc * nc);
-    if (eig_gram(U, nc, BU, nc, n, G.data(), gw, nb, s)) return -1;
+    if (gram(U, nc, BU, nc, G.data())) return -1;
     std::vector<double> f(nc);
     for (int j = 0; j < nc; ++j) {
       const double d = G[(size_t)j * nc + j];
@@ -277,7 +307,7 @@ int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int
     if ((status = ops.A(S, AS, k))) break;
     {
       std::vector<double> GA((size_t)k * k), GB((size_t)k * k);
-      if (eig_gram(S, k, AS, k, n, GA.data(), gw, nb, s) || eig_gram(S, k, BS, k, n, GB.data(), gw, nb, s)) {
+      if (gram2(S, k, AS, k, GA.data(), S, k, BS, k, GB.data())) {
         status = -1;
         break;
       }
@@ -329,7 +359,7 @@ int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int
           eig_combine(NP, 2 * k, cdev, k, n, R, nb, s);
         }
         std::vector<double> GR((size_t)k * k), GX((size_t)k * k);
-        if (eig_gram(R, k, R, k, n, GR.data(), gw, nb, s) || eig_gram(BS, k, BS, k, n, GX.data(), gw, nb, s)) {
+        if (gram2(R, k, R, k, GR.data(), BS, k, BS, k, GX.data())) {
           status = -1;
           break;
         }
@@ -379,7 +409,7 @@ int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int
       // converging residual is otherwise nearly in the span of X
       {
         std::vector<double> GXW((size_t)k * ka);
-        if (eig_gram(S, k, col(BS, k), ka, n, GXW.data(), gw, nb, s)) { status = -1; break; }
+        if (gram(S, k, col(BS, k), ka, GXW.data())) { status = -1; break; }
         std::vector<double> Co((size_t)(k + ka) * ka, 0.0);  // [X W] -> W - X GXW
         for (int i = 0; i < k; ++i)
           for (int j = 0; j < ka; ++j) Co[(size_t)i * ka + j] = -GXW[(size_t)i * ka + j];
@@ -396,7 +426,7 @@ int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int
       bool ok = false;
       while (!ok) {
         std::vector<double> GA((size_t)m * m), GB((size_t)m * m);
-        if (eig_gram(S, m, AS, m, n, GA.data(), gw, nb, s) || eig_gram(S, m, BS, m, n, GB.data(), gw, nb, s)) break;
+        if (gram2(S, m, AS, m, GA.data(), S, m, BS, m, GB.data())) break;
         ok = rayleigh_ritz(GA, GB, m, k, lam, C);
         if (!ok) {
           if (m == k + 2 * ka) m = k + ka;
@@ -439,6 +469,7 @@ int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int
   }
   if (status == -1) status = hip_fail(hipGetLastError(), "eigen-solver");
   (void)hipStreamSynchronize(s);
+  (void)hipHostFree(ring);
   release();
   return status;
 }

@@ -91,19 +91,37 @@ __global__ void __launch_bounds__(kET) scale_kernel(double* __restrict__ X, cons
 
 }  // namespace
 
-long long eig_gram_work(int nb) { return (long long)nb * kEigMaxCols * kEigMaxCols + kEigMaxCols * kEigMaxCols; }
+namespace {
+// one Gram matrix into work slot `slot` (partials and result), copied to the
+// host asynchronously on s
+int gram_async(const double* U, int p, const double* V, int q, long long n, double* G_host, double* work, int slot,
+               int nb, hipStream_t s) {
+  if (p < 1 || q < 1 || p > kEigMaxCols || q > kEigMaxCols) return -1;
+  const int npair = p * q;
+  const long long per = (long long)nb * kEigMaxCols * kEigMaxCols + kEigMaxCols * kEigMaxCols;
+  double* part = work + slot * per;
+  double* G = part + (long long)nb * kEigMaxCols * kEigMaxCols;
+  hipLaunchKernelGGL(gram_partial, dim3(nb), dim3(kET), 0, s, U, p, V, q, n, part);
+  hipLaunchKernelGGL(gram_reduce, dim3((npair + kET - 1) / kET), dim3(kET), 0, s, part, npair, nb, G);
+  return hipMemcpyAsync(G_host, G, sizeof(double) * npair, hipMemcpyDeviceToHost, s) == hipSuccess ? 0 : -1;
+}
+}  // namespace
+
+long long eig_gram_work(int nb) {
+  return 2 * ((long long)nb * kEigMaxCols * kEigMaxCols + kEigMaxCols * kEigMaxCols);
+}
 
 int eig_gram(const double* U, int p, const double* V, int q, long long n, double* G_host, double* work, int nb,
              hipStream_t s) {
-  if (p < 1 || q < 1 || p > kEigMaxCols || q > kEigMaxCols) return -1;
-  const int npair = p * q;
-  double* part = work;
-  double* G = work + (long long)nb * kEigMaxCols * kEigMaxCols;
-  hipLaunchKernelGGL(gram_partial, dim3(nb), dim3(kET), 0, s, U, p, V, q, n, part);
-  hipLaunchKernelGGL(gram_reduce, dim3((npair + kET - 1) / kET), dim3(kET), 0, s, part, npair, nb, G);
-  if (hipMemcpyAsync(G_host, G, sizeof(double) * npair, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
-  if (hipStreamSynchronize(s) != hipSuccess) return -1;
-  return 0;
+  if (gram_async(U, p, V, q, n, G_host, work, 0, nb, s)) return -1;
+  return hipStreamSynchronize(s) == hipSuccess ? 0 : -1;
+}
+
+int eig_gram2(const double* U1, int p1, const double* V1, int q1, double* G1_host, const double* U2, int p2,
+              const double* V2, int q2, double* G2_host, long long n, double* work, int nb, hipStream_t s) {
+  if (gram_async(U1, p1, V1, q1, n, G1_host, work, 0, nb, s)) return -1;
+  if (gram_async(U2, p2, V2, q2, n, G2_host, work, 1, nb, s)) return -1;
+  return hipStreamSynchronize(s) == hipSuccess ? 0 : -1;
 }
 
 void eig_combine(const double* U, int m, const double* C_dev, int q, long long n, double* Y, int nb, hipStream_t s) {

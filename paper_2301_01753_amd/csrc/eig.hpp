@@ -19,7 +19,11 @@ int eig_gram(const double* U, int p, const double* V, int q, long long n, double
 void eig_combine(const double* U, int m, const double* C_dev, int q, long long n, double* Y, int nb, hipStream_t s);
 // Column j of X (n x k) scaled by f[j] (device array).
 void eig_scale(double* X, const double* f_dev, int k, long long n, int nb, hipStream_t s);
-// Partial-sum slots eig_gram needs in `work`.
+// Two Gram matrices G1 = U1^T V1 and G2 = U2^T V2 with one host
+// synchronisation (same summation order as eig_gram).
+int eig_gram2(const double* U1, int p1, const double* V1, int q1, double* G1_host, const double* U2, int p2,
+              const double* V2, int q2, double* G2_host, long long n, double* work, int nb, hipStream_t s);
+// Partial-sum slots eig_gram and eig_gram2 need in `work`.
 long long eig_gram_work(int nb);
 
 // Generalized symmetric-definite eigenproblem A x = lambda B x, lowest k

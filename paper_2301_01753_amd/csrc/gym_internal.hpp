@@ -73,6 +73,9 @@ void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int&
 // mass (curved_exact), or, as a preconditioner only, from the box with the
 // same spacing.
 std::vector<double> lumped_diag_host(const gym_space* sp, bool curved_exact = true);
+// Diagonal of the mass matrix at the kept unknowns (on curved cells that of
+// the box with the same spacing).
+std::vector<double> mass_diag_host(const gym_space* sp);
 // The same row sums in factored form: at lattice position p, component c has
 // sc[c] prod_a w_a(p_a), w_a = rn[a] (nodal along axis a, r N_a + 1 values)
 // or re[a] (edge, r N_a values); the product is taken in axis order.

@@ -326,6 +326,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   if (int rc = gym_space_create(mx->ctx, mx->mesh, GYM_H1, mx->s1->desc.r, GYM_BC_ESSENTIAL, &s0)) return rc;
   const long long n0 = gym_space_ndofs(s0);
   const int nb1 = mx->nb1;
+  const int nb0 = vec_grid(std::max(1LL, n0), mx->ctx->ncu);
   std::vector<void*> pool;
   auto alloc = [&](long long cnt) -> double* {
     void* p = nullptr;
@@ -348,6 +349,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   double* phi = alloc(std::max(1LL, n0) * k);
   double* dB = alloc(n1);    // lumped: the row sums of M1 (B itself)
   double* dT = alloc(n1);    // their inverses (the preconditioner)
+  double* d0i = alloc(std::max(1LL, n0));  // inverse diagonal of M0 (the gradient shift's X)
   double* gw = alloc(eig_gram_work(nb1));
   double* cgw = spai_q1 ? alloc(3 * n1 * k) : nullptr;  // CG work of B = Q1^-1
   // On a mesh periodic along every axis, ker P2 holds besides the gradients
@@ -357,7 +359,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   const int nh = mx->mesh->periodic == (1 << dimm) - 1 ? dimm : 0;
   double* H = nh ? alloc(n1 * nh) : nullptr;
   double* BH = nh ? alloc(n1 * nh) : nullptr;
-  if (!X || !bx || !gp || !bgp || !g0 || !phi || !dB || !dT || !gw || (spai_q1 && !cgw) || (nh && (!H || !BH))) {
+  if (!X || !bx || !gp || !bgp || !g0 || !phi || !dB || !dT || !d0i || !gw || (spai_q1 && !cgw) || (nh && (!H || !BH))) {
     cleanup();
     return fail(GYM_E_OOM, "eigen-solver: device allocation failed");
   }
@@ -369,8 +371,11 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
       return rc2;
     }
     for (size_t i = 0; i < d.size(); ++i) di[i] = 1.0 / d[i];
+    std::vector<double> d0 = mass_diag_host(s0);
+    for (double& v : d0) v = 1.0 / v;
     if (hipMemcpy(dB, d.data(), sizeof(double) * d.size(), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(dT, di.data(), sizeof(double) * di.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(dT, di.data(), sizeof(double) * di.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        (n0 > 0 && hipMemcpy(d0i, d0.data(), sizeof(double) * n0, hipMemcpyHostToDevice) != hipSuccess)) {
       cleanup();
       return fail(GYM_E_HIP, "eigen-solver: upload failed");
     }
@@ -439,9 +444,12 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
       launch_axpy_diag(colp(y, n1, j), 0.0, 1.0, dT, colp(const_cast<double*>(x), n1, j), n1, nb1, s);
     return 0;
   };
-  // A = c^2 (C^T M2~ C + s B G M0^-1 G^T B): P2 plus a multiple of the
-  // gradient-space operator, which lifts the gradients (the kernel of P2)
-  // above the wanted modes and leaves every other eigenpair of (P2, B) alone
+  // A = c^2 (C^T M2~ C + s B G D0^-1 G^T B), D0 the diagonal of M0: P2 plus
+  // a multiple of a gradient-space operator.  For any SPD X in place of
+  // D0^-1 the term vanishes on fields with G^T B v = 0 and maps gradients to
+  // B times gradients, so it lifts the gradients (the kernel of P2) above the
+  // wanted modes and leaves every other eigenpair of (P2, B) alone; the
+  // diagonal makes it a handful of launches instead of a mass solve.
   ops.A = [&](const double* x, double* y, int ncol) -> int {
     if (o.largest) {  // -P2: its lowest pairs are the largest of P2
       for (int j = 0; j < ncol; ++j) {
@@ -456,19 +464,11 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
         return hip_fail(hipGetLastError(), "eigen-solver copy");
     }
     if (int rc = ops.B(x, bx, ncol)) return rc;
-    for (int j = 0; j < ncol; ++j)
+    for (int j = 0; j < ncol; ++j) {
       if (int rc = gym_d_apply(s0, mx->s1, 1, colp(bx, n1, j), colp(g0, n0, j), s)) return rc;
-    gym_solve_opts so;
-    gym_solve_opts_default(&so);
-    so.method = GYM_CG;
-    so.rtol = 1e-13;
-    so.maxit = 5000;
-    gym_solve_info si{};
-    int rc = gym_mass_solve(s0, &so, ncol, g0, phi, &si, s);
-    if (rc == GYM_W_NOT_CONVERGED) warn = 1;
-    else if (rc) return rc;
-    for (int j = 0; j < ncol; ++j)
-      if (int rc2 = gym_d_apply(s0, mx->s1, 0, colp(phi, n0, j), colp(gp, n1, j), s)) return rc2;
+      launch_axpy_diag(colp(phi, n0, j), 0.0, 1.0, d0i, colp(g0, n0, j), n0, nb0, s);
+      if (int rc = gym_d_apply(s0, mx->s1, 0, colp(phi, n0, j), colp(gp, n1, j), s)) return rc;
+    }
     if (int rc2 = ops.B(gp, bgp, ncol)) return rc2;
     for (int j = 0; j < ncol; ++j)
       launch_axpy_diag(colp(y, n1, j), c2, c2 * o.grad_shift, nullptr, colp(bgp, n1, j), n1, nb1, s);
