@@ -421,12 +421,11 @@ int mfma_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t 
 }
 
 // Curved Hodge apply of degree 3 on the matrix cores, FP64 arithmetic with
-// FP64 or FP32 vectors (not with the fused MINRES step, which the tile
-// kernel carries).
-bool hc_path(const gym_op* op, int prec, const MrStep* mr) {
+// FP64 or FP32 vectors.
+bool hc_path(const gym_op* op, int prec) {
   const gym_mesh* m = op->mesh;
   return (prec == GYM_F64 || prec == GYM_F32) && op->problem != GYM_MIXED_POISSON && m->curved && m->dim == 3 &&
-         !m->periodic && op->r == kHcDegree && !mr && op->ctx->curved_kernel == 0;
+         !m->periodic && op->r == kHcDegree && op->ctx->curved_kernel == 0;
 }
 
 int hc_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s) {
@@ -463,10 +462,33 @@ int hc_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipS
   return 0;
 }
 
+// matrix_core: the curved Hodge apply may take the matrix-core kernel, whose
+// tile-boundary buffer is allocated on first use (callers that must not
+// allocate pass false and get the tile kernel).
 int op_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s, const MrStep* mr,
-              int* wg_out) {
+              int* wg_out, bool matrix_core) {
   if (mfma_path(op, prec)) return mfma_launch(op, nrhs, x, y, s, mr, wg_out);
-  if (!wg_out && hc_path(op, prec, mr)) return hc_launch(op, prec, nrhs, x, y, s);
+  if (matrix_core && hc_path(op, prec)) {
+    // With a MINRES step the apply is followed by the step's first half as a
+    // kernel of its own: partial sums of z . A z over vec_grid blocks per
+    // right-hand side, skipping converged ones (the layout minres_step2 reads).
+    const long long n = op->na + op->nb;
+    const int np = vec_grid(n, op->ctx->ncu);
+    if (wg_out) {
+      *wg_out = np;
+      return 0;
+    }
+    if (int rc = hc_launch(op, prec, nrhs, x, y, s)) return rc;
+    if (mr) {
+      if (prec == GYM_F64)
+        minres_launch_dot2<double>(static_cast<const double*>(x), static_cast<const double*>(y), nullptr, n, nrhs,
+                                   np, mr->pa, nullptr, s, mr->cur);
+      else
+        minres_launch_dot2<float>(static_cast<const float*>(x), static_cast<const float*>(y), nullptr, n, nrhs, np,
+                                  mr->pa, nullptr, s, mr->cur);
+    }
+    return 0;
+  }
   OpParams p;
   int prob;
   build_op_params(op, x, y, p, prob);
@@ -488,14 +510,14 @@ int op_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipS
 }
 }  // namespace
 
-int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s,
-                    const MrStep* mr) {
-  return op_launch(op, prec, nrhs, x, y, s, mr, nullptr);
+int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s, const MrStep* mr,
+                    bool matrix_core) {
+  return op_launch(op, prec, nrhs, x, y, s, mr, nullptr, matrix_core);
 }
 
-int op_workgroups(const gym_op* op, int prec, int nrhs, int* wg) {
+int op_workgroups(const gym_op* op, int prec, int nrhs, int* wg, bool matrix_core) {
   *wg = 0;
-  if (int rc = op_launch(op, prec, nrhs, nullptr, nullptr, nullptr, nullptr, wg)) return rc;
+  if (int rc = op_launch(op, prec, nrhs, nullptr, nullptr, nullptr, nullptr, wg, matrix_core)) return rc;
   return *wg > 0 ? 0 : fail(GYM_E_HIP, "operator tiling query failed");
 }
 
@@ -685,9 +707,10 @@ int run_minres(Apply&& apply, long long n, int nrhs, int nb, int npa, const TV* 
 }
 
 int relres_f64(const gym_op* op, int nrhs, const double* b, const double* x, double* tmp, double* part,
-               double* sums, int nb, hipStream_t s, std::vector<double>& rel, std::vector<double>* rnorm = nullptr) {
+               double* sums, int nb, hipStream_t s, std::vector<double>& rel, std::vector<double>* rnorm = nullptr,
+               bool matrix_core = true) {
   long long n = op->na + op->nb;
-  if (int rc = launch_op_apply(op, GYM_F64, nrhs, x, tmp, s)) return rc;
+  if (int rc = launch_op_apply(op, GYM_F64, nrhs, x, tmp, s, nullptr, matrix_core)) return rc;
   launch_norm2(tmp, b, n, nrhs, nb, 1, part, sums, s);
   launch_norm2(b, nullptr, n, nrhs, nb, 0, part, sums + nrhs, s);
   std::vector<double> h(2 * nrhs);
@@ -762,6 +785,7 @@ struct OpWork {
   float *r32 = nullptr, *x32 = nullptr;
   double* ones = nullptr;  // the identity "diagonal" of GYM_PRECOND_NONE
   std::vector<void*> pool;
+  bool matrix_core = true;  // false: applies that allocate nothing (launch_op_apply)
 };
 
 int ensure_schur(gym_op* op, int nrhs, SchurPrec** out) {
@@ -1478,7 +1502,7 @@ static int minres_f64(gym_op* op, const gym_solve_opts& opts, int nrhs, const do
   const long long n = w.n;
   auto apply = [&](const double* in, double* out, const MrStep& m) {
     if (int rc = timer.begin(s)) return rc;
-    if (int rc = launch_op_apply(op, GYM_F64, nrhs, in, out, s, &m)) return rc;
+    if (int rc = launch_op_apply(op, GYM_F64, nrhs, in, out, s, &m, w.matrix_core)) return rc;
     return timer.end(s);
   };
   double tol = opts.rtol;
@@ -1497,7 +1521,7 @@ static int minres_f64(gym_op* op, const gym_solve_opts& opts, int nrhs, const do
       break;
     }
     if (sol != x) launch_add(sol, x, n * nrhs, w.nb, s);
-    if (int rc = relres_f64(op, nrhs, b, x, w.tmp, w.part, w.sums, w.nb, s, rel)) return rc;
+    if (int rc = relres_f64(op, nrhs, b, x, w.tmp, w.part, w.sums, w.nb, s, rel, nullptr, w.matrix_core)) return rc;
     double worst = *std::max_element(rel.begin(), rel.end());
     if (worst <= opts.rtol) break;
     if (total >= opts.maxit) {
@@ -1653,8 +1677,9 @@ int solve_f64_on(gym_op* op, const gym_solve_opts* opts_in, int nrhs, const doub
     return fail(GYM_E_ARG, "unknown preconditioner");
   const long long n = op->na + op->nb;
   int npa = 0;
-  if (int rc = op_workgroups(op, GYM_F64, nrhs, &npa)) return rc;
+  if (int rc = op_workgroups(op, GYM_F64, nrhs, &npa, false)) return rc;
   OpWork w;
+  w.matrix_core = false;
   w.n = n;
   w.nrhs = nrhs;
   w.nb = vec_grid(n, op->ctx->ncu);

@@ -84,11 +84,13 @@ struct LumpedTables {
   double sc[3];
 };
 LumpedTables lumped_tables_host(const gym_space* sp);
-// y = A x; with `mr` the launch also carries that fused MINRES step.
+// y = A x; with `mr` the launch also carries the first half of that MINRES
+// step (partial sums of x . A x, op_workgroups of them per rhs).
+// matrix_core = false keeps to kernels that allocate nothing on first use.
 int launch_op_apply(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s,
-                    const MrStep* mr = nullptr);
-// Workgroups per rhs of the operator launch for this precision and nrhs.
-int op_workgroups(const gym_op* op, int prec, int nrhs, int* wg);
+                    const MrStep* mr = nullptr, bool matrix_core = true);
+// Partial sums per rhs of the launch above for this precision and nrhs.
+int op_workgroups(const gym_op* op, int prec, int nrhs, int* wg, bool matrix_core = true);
 }  // namespace gym
 
 struct gym_ctx {
