@@ -635,12 +635,15 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
   }
 }
 
-__device__ __forceinline__ const DevComp& field_comp(const HcParams& p, int f) {
+// kept_index of field f (runtime f): each case reads its own kernel-argument
+// fields, so the argument block is not copied to per-thread memory for a
+// dynamically indexed reference
+__device__ __forceinline__ long long field_index(const HcParams& p, int f, int g0, int g1, int g2) {
   switch (f) {
-    case 0: return p.f[0];
-    case 1: return p.f[1];
-    case 2: return p.f[2];
-    default: return p.f[3];
+    case 0: return kept_index(p.f[0], g0, g1, g2);
+    case 1: return kept_index(p.f[1], g0, g1, g2);
+    case 2: return kept_index(p.f[2], g0, g1, g2);
+    default: return kept_index(p.f[3], g0, g1, g2);
   }
 }
 
@@ -671,7 +674,7 @@ __global__ void __launch_bounds__(256) hodge_mfma_fixup(HcParams p, int TX, int 
       if (gy >= LY) continue;
       const int F = fs == 0 ? 0 : fs + 1;  // sigma, u_y, u_z
       const int gx = R * TX * (bx + 1);
-      const long long id = kept_index(field_comp(p, F), gx, gy, gz);
+      const long long id = field_index(p, F, gx, gy, gz);
       if (id < 0) continue;
       double val = static_cast<double>(y[id]) + hx[((long long)(fs * bxn + bx) * LZ + gz) * LY + gy];
       if (F != 2 && gy % (R * TY) == 0 && gy > 0 && gy < R * Ny) {
@@ -690,7 +693,7 @@ __global__ void __launch_bounds__(256) hodge_mfma_fixup(HcParams p, int TX, int 
       const int F = fs == 0 ? 0 : (fs == 1 ? 1 : 3);  // sigma, u_x, u_z
       if (F != 1 && gx % (R * TX) == 0 && gx > 0 && gx < R * Nx) continue;  // part A's
       const int gy = R * TY * (by + 1);
-      const long long id = kept_index(field_comp(p, F), gx, gy, gz);
+      const long long id = field_index(p, F, gx, gy, gz);
       if (id < 0) continue;
       y[id] = static_cast<TV>(static_cast<double>(y[id]) + hy[((long long)(fs * byn + by) * LZ + gz) * LX + gx]);
     }
