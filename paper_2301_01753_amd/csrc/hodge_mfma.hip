@@ -333,12 +333,19 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
     // ---- inputs: the cell's coefficients, planes along z
     double iS[4], iX[4], iY[4], iZ[4];
     {
+      // unconditional loads (a plane outside the kept set reads the zero
+      // slot), converted after all of them: a load under a branch with its
+      // conversion would be waited for on the spot
+      const TV* zero = static_cast<const TV*>(p.zero);
       auto load = [&](int F, int nz, double(&v)[4]) {
+        TV raw[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int gz = R * ez + k;
-          v[k] = (k < nz && zkept(F, gz)) ? static_cast<double>(xcol[F][(long long)zsl[F] * gz]) : 0.0;
+          raw[k] = *((k < nz && zkept(F, gz)) ? xcol[F] + (long long)zsl[F] * gz : zero);
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = static_cast<double>(raw[k]);
       };
       load(0, 4, iS);
       load(1, 4, iX);
