@@ -1227,7 +1227,16 @@ int gym_space_destroy(gym_space* s) {
 
 int gym_d_apply(const gym_space* from, const gym_space* to, int transpose, const double* x, double* y,
                 void* stream) {
-  if (!from || !to || !x || !y) return fail(GYM_E_ARG, "NULL argument");
+  return d_apply_n(from, to, transpose, 1, x, y, (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+namespace gym {
+
+int d_apply_n(const gym_space* from, const gym_space* to, int transpose, int nrhs, const double* x, double* y,
+              hipStream_t stream) {
+  if (!from || !to || !x || !y || nrhs < 1) return fail(GYM_E_ARG, "NULL argument or nrhs < 1");
   if (from->mesh != to->mesh || from->desc.r != to->desc.r)
     return fail(GYM_E_ARG, "spaces on different meshes or degrees");
   const int dim = from->desc.dim;
@@ -1251,10 +1260,17 @@ int gym_d_apply(const gym_space* from, const gym_space* to, int transpose, const
   p.transpose = transpose ? 1 : 0;
   p.periodic = from->desc.periodic;
   p.nout = dst->desc.ndofs;
-  int rc = launch_incidence(p, (hipStream_t)stream);
+  p.nrhs = nrhs;
+  p.in_stride = src->desc.ndofs;
+  p.out_stride = dst->desc.ndofs;
+  int rc = launch_incidence(p, stream);
   if (rc) return fail(GYM_E_HIP, "incidence launch failed");
   return GYM_OK;
 }
+
+}  // namespace gym
+
+extern "C" {
 
 int gym_mass_apply(const gym_space* space, int prec, int nrhs, const void* x, void* y, void* stream) {
   if (!space || !x || !y || nrhs < 1) return fail(GYM_E_ARG, "bad argument");

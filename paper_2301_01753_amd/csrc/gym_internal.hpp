@@ -73,6 +73,10 @@ void build_op_params(const gym_op* op, const void* x, void* y, OpParams& p, int&
 // mass (curved_exact), or, as a preconditioner only, from the box with the
 // same spacing.
 std::vector<double> lumped_diag_host(const gym_space* sp, bool curved_exact = true);
+// y = d x or d^T x (gym_d_apply) for nrhs contiguous vectors (strides: the
+// spaces' ndofs), one launch.
+int d_apply_n(const gym_space* from, const gym_space* to, int transpose, int nrhs, const double* x, double* y,
+              hipStream_t stream);
 // Diagonal of the mass matrix at the kept unknowns (on curved cells that of
 // the box with the same spacing).
 std::vector<double> mass_diag_host(const gym_space* sp);

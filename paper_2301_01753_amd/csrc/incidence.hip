@@ -33,6 +33,7 @@ struct IncTerms {
 __global__ void __launch_bounds__(256) incidence_kernel(const IncParams p, const IncTerms terms) {
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.nout) return;
+  const double* x = p.x + p.in_stride * blockIdx.y;  // right-hand side blockIdx.y
   int c = 0;
   while (c + 1 < p.out_ncomp && i >= p.out.c[c + 1].offset) ++c;
   const DevComp& oc = p.out.c[c];
@@ -54,11 +55,11 @@ __global__ void __launch_bounds__(256) incidence_kernel(const IncParams p, const
     if (p.periodic & 2) g1 = g1 < 0 ? g1 + ic.count[1] : (g1 >= ic.count[1] ? g1 - ic.count[1] : g1);
     if (p.periodic & 4) g2 = g2 < 0 ? g2 + ic.count[2] : (g2 >= ic.count[2] ? g2 - ic.count[2] : g2);
     if (g0 < 0 || g0 >= ic.count[0] || g1 < 0 || g1 >= ic.count[1] || g2 < 0 || g2 >= ic.count[2]) continue;
-    double v = p.x[ic.offset + g0 + (long long)ic.count[0] * (g1 + (long long)ic.count[1] * g2)];
+    double v = x[ic.offset + g0 + (long long)ic.count[0] * (g1 + (long long)ic.count[1] * g2)];
     if (t.sign > 0) acc += v;
     else acc -= v;
   }
-  p.y[i] = acc;
+  p.y[p.out_stride * blockIdx.y + i] = acc;
 }
 
 namespace {
@@ -137,9 +138,9 @@ int launch_incidence(const IncParams& p, hipStream_t s) {
     terms.nterm[c] = (int)list.size();
     for (size_t k = 0; k < list.size(); ++k) terms.t[c][k] = list[k];
   }
-  if (p.nout == 0) return 0;
+  if (p.nout == 0 || p.nrhs < 1) return 0;
   long long blocks = (p.nout + 255) / 256;
-  hipLaunchKernelGGL(incidence_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, terms);
+  hipLaunchKernelGGL(incidence_kernel, dim3((unsigned)blocks, (unsigned)p.nrhs), dim3(256), 0, s, p, terms);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

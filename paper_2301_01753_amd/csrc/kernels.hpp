@@ -83,6 +83,8 @@ struct IncParams {
   int transpose;
   int periodic;     // bit a: positions along axis a wrap (count = m_a)
   long long nout;
+  int nrhs = 1;     // right-hand sides (grid y), x and y strides below
+  long long in_stride = 0, out_stride = 0;
 };
 int launch_incidence(const IncParams& p, hipStream_t s);
 

@@ -104,6 +104,19 @@ int apply_p2(gym_maxwell* mx, const double* a, hipStream_t s) {
   return gym_d_apply(mx->s1, mx->s2, 1, mx->mb, mx->t, s);
 }
 
+// y = C^T M2~ C x for ncol contiguous columns, in one launch per stage
+// (b, mb: n2 x ncol work).
+int apply_p2_n(gym_maxwell* mx, const double* x, double* y, int ncol, double* b, double* mb, hipStream_t s) {
+  if (int rc = d_apply_n(mx->s1, mx->s2, 0, ncol, x, b, s)) return rc;
+  if (mx->o.m2 == GYM_M2_LUMPED) {
+    for (int j = 0; j < ncol; ++j)
+      launch_axpy_diag(mb + mx->n2 * j, 0.0, 1.0, mx->m2d, b + mx->n2 * j, mx->n2, mx->nb2, s);
+  } else if (int rc = gym_mass_apply(mx->s2, GYM_F64, ncol, b, mb, s)) {
+    return rc;
+  }
+  return d_apply_n(mx->s1, mx->s2, 1, ncol, mb, y, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -347,6 +360,8 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   double* bgp = alloc(n1 * k);
   double* g0 = alloc(std::max(1LL, n0) * k);
   double* phi = alloc(std::max(1LL, n0) * k);
+  double* b2 = alloc(mx->n2 * k);   // C x, then M2~ C x, for the columns of an A apply
+  double* mb2 = alloc(mx->n2 * k);
   double* dB = alloc(n1);    // lumped: the row sums of M1 (B itself)
   double* dT = alloc(n1);    // their inverses (the preconditioner)
   double* d0i = alloc(std::max(1LL, n0));  // inverse diagonal of M0 (the gradient shift's X)
@@ -359,7 +374,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   const int nh = mx->mesh->periodic == (1 << dimm) - 1 ? dimm : 0;
   double* H = nh ? alloc(n1 * nh) : nullptr;
   double* BH = nh ? alloc(n1 * nh) : nullptr;
-  if (!X || !bx || !gp || !bgp || !g0 || !phi || !dB || !dT || !d0i || !gw || (spai_q1 && !cgw) || (nh && (!H || !BH))) {
+  if (!X || !bx || !gp || !bgp || !g0 || !phi || !b2 || !mb2 || !dB || !dT || !d0i || !gw || (spai_q1 && !cgw) || (nh && (!H || !BH))) {
     cleanup();
     return fail(GYM_E_OOM, "eigen-solver: device allocation failed");
   }
@@ -451,27 +466,17 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   // wanted modes and leaves every other eigenpair of (P2, B) alone; the
   // diagonal makes it a handful of launches instead of a mass solve.
   ops.A = [&](const double* x, double* y, int ncol) -> int {
+    if (int rc = apply_p2_n(mx, x, y, ncol, b2, mb2, s)) return rc;
     if (o.largest) {  // -P2: its lowest pairs are the largest of P2
-      for (int j = 0; j < ncol; ++j) {
-        if (int rc = apply_p2(mx, colp(const_cast<double*>(x), n1, j), s)) return rc;
-        launch_axpy_diag(colp(y, n1, j), 0.0, -c2, nullptr, mx->t, n1, nb1, s);
-      }
+      launch_axpy_diag(y, 0.0, -c2, nullptr, y, n1 * ncol, nb1, s);
       return 0;
     }
-    for (int j = 0; j < ncol; ++j) {
-      if (int rc = apply_p2(mx, colp(const_cast<double*>(x), n1, j), s)) return rc;
-      if (hipMemcpyAsync(colp(y, n1, j), mx->t, sizeof(double) * n1, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        return hip_fail(hipGetLastError(), "eigen-solver copy");
-    }
     if (int rc = ops.B(x, bx, ncol)) return rc;
-    for (int j = 0; j < ncol; ++j) {
-      if (int rc = gym_d_apply(s0, mx->s1, 1, colp(bx, n1, j), colp(g0, n0, j), s)) return rc;
-      launch_axpy_diag(colp(phi, n0, j), 0.0, 1.0, d0i, colp(g0, n0, j), n0, nb0, s);
-      if (int rc = gym_d_apply(s0, mx->s1, 0, colp(phi, n0, j), colp(gp, n1, j), s)) return rc;
-    }
-    if (int rc2 = ops.B(gp, bgp, ncol)) return rc2;
-    for (int j = 0; j < ncol; ++j)
-      launch_axpy_diag(colp(y, n1, j), c2, c2 * o.grad_shift, nullptr, colp(bgp, n1, j), n1, nb1, s);
+    if (int rc = d_apply_n(s0, mx->s1, 1, ncol, bx, g0, s)) return rc;
+    for (int j = 0; j < ncol; ++j) launch_axpy_diag(colp(phi, n0, j), 0.0, 1.0, d0i, colp(g0, n0, j), n0, nb0, s);
+    if (int rc = d_apply_n(s0, mx->s1, 0, ncol, phi, gp, s)) return rc;
+    if (int rc = ops.B(gp, bgp, ncol)) return rc;
+    launch_axpy_diag(y, c2, c2 * o.grad_shift, nullptr, bgp, n1 * ncol, nb1, s);
     return 0;
   };
   // harmonic lift: A += c^2 s B H (H^T B H)^-1 H^T B, which moves the
