@@ -209,7 +209,7 @@ bool rayleigh_ritz(std::vector<double> GA, std::vector<double> GB, int m, int k,
 int lobpcg(const EigOperators& ops, long long n, int k, int nev, double tol, int maxit, double* X, double* lam_out,
            EigResult* res, int ncu, hipStream_t s) {
   if (k < 1 || 3 * k > kEigMaxCols || nev < 1 || nev > k || n < 3 * k) return GYM_E_ARG;
-  const int nb = vec_grid(n, ncu);
+  const int nb = eig_grid(n, ncu);
   const long long nk = n * k;
   // S, AS, BS (3k columns each), the residual, new X / AX / BX, new P / AP / BP
   std::vector<double*> bufs;

@@ -1,17 +1,19 @@
 // Block kernels of the generalized eigen-solver (LOBPCG, eig.cpp).
 //
 // Blocks hold up to kEigMaxCols column vectors of length n, column after
-// column.  The Gram kernel stages 32 rows of both blocks in LDS and gives
+// column.  The Gram kernel stages 64 rows of both blocks in LDS and gives
 // every thread up to three (row of U^T, column of V) pairs; per-block
 // partials are summed by a second kernel in block order, so the result does
 // not depend on timing.
+#include <algorithm>
+
 #include "eig.hpp"
 
 namespace gym {
 namespace {
 
 constexpr int kET = 256;  // threads per block
-constexpr int kER = 32;   // rows per LDS tile of the Gram kernel
+constexpr int kER = 64;   // rows per LDS tile of the Gram kernel
 constexpr int kEP = (kEigMaxCols * kEigMaxCols + kET - 1) / kET;  // pairs per thread
 
 __global__ void __launch_bounds__(kET) gram_partial(const double* __restrict__ U, int p, const double* __restrict__ V,
@@ -106,6 +108,12 @@ int gram_async(const double* U, int p, const double* V, int q, long long n, doub
   return hipMemcpyAsync(G_host, G, sizeof(double) * npair, hipMemcpyDeviceToHost, s) == hipSuccess ? 0 : -1;
 }
 }  // namespace
+
+int eig_grid(long long n, int ncu) {
+  long long b = (n + kET - 1) / kET;
+  const long long cap = 8LL * ncu;
+  return (int)std::max(1LL, std::min(b, cap));
+}
 
 long long eig_gram_work(int nb) {
   return 2 * ((long long)nb * kEigMaxCols * kEigMaxCols + kEigMaxCols * kEigMaxCols);

@@ -464,6 +464,13 @@ __global__ void __launch_bounds__(kBT) axpy_diag_kernel(double* y, double beta, 
   }
 }
 
+// y_j = d .* x_j for the columns j = blockIdx.y of n rows each (all FP64)
+__global__ void __launch_bounds__(kBT) diag_cols_kernel(double* y, const double* d, const double* x, long long n) {
+  const long long off = n * blockIdx.y;
+  for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
+    y[off + i] = d[i] * x[off + i];
+}
+
 // x += d (all FP64)
 __global__ void __launch_bounds__(kBT) add_kernel(const double* d, double* x, long long n) {
   for (long long i = (long long)blockIdx.x * kBT + threadIdx.x; i < n; i += (long long)gridDim.x * kBT)
@@ -568,6 +575,11 @@ void launch_sub(const double* a, const double* b, double* y, long long n, int nb
 void launch_axpy_diag(double* y, double beta, double alpha, const double* d, const double* x, long long n, int nb,
                       hipStream_t s) {
   GYM_LAUNCH(axpy_diag_kernel, dim3(nb), s, y, beta, alpha, d, x, n);
+}
+
+void launch_diag_cols(double* y, const double* d, const double* x, long long n, int ncol, int nb, hipStream_t s) {
+  if (n < 1 || ncol < 1) return;
+  hipLaunchKernelGGL(diag_cols_kernel, dim3(nb, ncol), dim3(kBT), 0, s, y, d, x, n);
 }
 
 void launch_add(const double* d, double* x, long long n, int nb, hipStream_t s) {

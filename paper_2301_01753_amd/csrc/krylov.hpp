@@ -107,6 +107,8 @@ void launch_fill(double* y, double v, long long n, int nb, hipStream_t s);
 // y = beta y + alpha (d .* x); d = NULL: ones
 void launch_axpy_diag(double* y, double beta, double alpha, const double* d, const double* x, long long n, int nb,
                       hipStream_t s);
+// y_j = d .* x_j for ncol contiguous columns of n rows (one launch)
+void launch_diag_cols(double* y, const double* d, const double* x, long long n, int ncol, int nb, hipStream_t s);
 void launch_to_f32_scaled(const double* a, float* y, long long n, int nrhs, int nb, const double* scale,
                           hipStream_t s);
 void launch_axpy_f32(const float* d, double* x, long long n, int nrhs, int nb, const double* scale,

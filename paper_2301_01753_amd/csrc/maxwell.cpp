@@ -444,8 +444,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
   ops.B = [&](const double* x, double* y, int ncol) -> int {
     if (spai_q1) return spai_inverse(x, y, ncol);
     if (!lumped) return gym_mass_apply(mx->s1, GYM_F64, ncol, x, y, s);
-    for (int j = 0; j < ncol; ++j)
-      launch_axpy_diag(colp(y, n1, j), 0.0, 1.0, dB, colp(const_cast<double*>(x), n1, j), n1, nb1, s);
+    launch_diag_cols(y, dB, x, n1, ncol, nb1, s);
     return 0;
   };
   // T: Q1 itself for a SPAI (it approximates B^-1 = Q1 exactly); otherwise
@@ -455,8 +454,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
       for (int j = 0; j < ncol; ++j) apply_sparse_q1(mx, colp(const_cast<double*>(x), n1, j), colp(y, n1, j), s);
       return 0;
     }
-    for (int j = 0; j < ncol; ++j)
-      launch_axpy_diag(colp(y, n1, j), 0.0, 1.0, dT, colp(const_cast<double*>(x), n1, j), n1, nb1, s);
+    launch_diag_cols(y, dT, x, n1, ncol, nb1, s);
     return 0;
   };
   // A = c^2 (C^T M2~ C + s B G D0^-1 G^T B), D0 the diagonal of M0: P2 plus
@@ -473,7 +471,7 @@ int gym_maxwell_eigs(gym_maxwell* mx, const gym_eig_opts* opts, double* omega2, 
     }
     if (int rc = ops.B(x, bx, ncol)) return rc;
     if (int rc = d_apply_n(s0, mx->s1, 1, ncol, bx, g0, s)) return rc;
-    for (int j = 0; j < ncol; ++j) launch_axpy_diag(colp(phi, n0, j), 0.0, 1.0, d0i, colp(g0, n0, j), n0, nb0, s);
+    launch_diag_cols(phi, d0i, g0, n0, ncol, nb0, s);
     if (int rc = d_apply_n(s0, mx->s1, 0, ncol, phi, gp, s)) return rc;
     if (int rc = ops.B(gp, bgp, ncol)) return rc;
     launch_axpy_diag(y, c2, c2 * o.grad_shift, nullptr, bgp, n1 * ncol, nb1, s);
