@@ -111,7 +111,7 @@ int gram_async(const double* U, int p, const double* V, int q, long long n, doub
 
 int eig_grid(long long n, int ncu) {
   long long b = (n + kET - 1) / kET;
-  const long long cap = 8LL * ncu;
+  const long long cap = 4LL * ncu;
   return (int)std::max(1LL, std::min(b, cap));
 }
 

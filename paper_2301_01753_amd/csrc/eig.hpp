@@ -25,9 +25,10 @@ int eig_gram2(const double* U1, int p1, const double* V1, int q1, double* G1_hos
               const double* V2, int q2, double* G2_host, long long n, double* work, int nb, hipStream_t s);
 // Partial-sum slots eig_gram and eig_gram2 need in `work`.
 long long eig_gram_work(int nb);
-// Workgroups of the block kernels for n rows: one per 256 rows, at most 8 per
-// CU (the blocks are short: k <= 8 columns of a few 10^5 rows leave the GPU
-// idle unless the rows are spread over every CU).
+// Workgroups of the block kernels for n rows: one per 256 rows, at most 4 per
+// CU (short blocks, k <= 8 columns of a few 10^5 rows, leave the GPU idle
+// unless the rows are spread over every CU; on long ones more workgroups only
+// lengthen the serial sum over their Gram partials).
 int eig_grid(long long n, int ncu);
 
 // Generalized symmetric-definite eigenproblem A x = lambda B x, lowest k
