@@ -156,7 +156,11 @@ __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* _
                                             long long off, const Step2Coef& k, int blk, int nblk, double& ab,
                                             double& ac) {
   // restrict-qualified locals let the compiler issue every load of an
-  // unrolled group before the stores of the previous one
+  // unrolled group before the stores of the previous one.  The stores are
+  // non-temporal: the four written vectors are read again only in the next
+  // step, after the whole sweep, far beyond what the caches hold (measured
+  // on a 95M-unknown Hodge solve: 2% faster per step at 1 rhs, 3.7% at 8;
+  // non-temporal loads helped at 1 rhs and hurt at 8)
   TV* __restrict__ y = v.y + off;
   const TV* __restrict__ r1 = v.r1 + off;
   const TV* __restrict__ r2 = v.r2 + off;
@@ -171,16 +175,16 @@ __device__ __forceinline__ void step2_sweep(const MrVecs<TV>& v, const double* _
   auto one = [&](long long i, double yv, double r1v, double r2v, double dv, double zpv, double wav, double wbv,
                  double xv) {
     const TV ys = static_cast<TV>(k.ys * yv - k.c1 * r1v - k.c * r2v);
-    y[i] = ys;
+    __builtin_nontemporal_store(ys, &y[i]);
     if constexpr (UPD) {
       const double vp = todbl(static_cast<TV>(zpv * k.vpinv));
       const TV ws = static_cast<TV>((vp - k.oldeps * wav - k.delta * wbv) * k.denom);
-      wo[i] = ws;
-      x[i] = static_cast<TV>(xv + k.phi * todbl(ws));
+      __builtin_nontemporal_store(ws, &wo[i]);
+      __builtin_nontemporal_store(static_cast<TV>(xv + k.phi * todbl(ws)), &x[i]);
     }
     if constexpr (!EXT) {
       const TV zs = static_cast<TV>(dv * todbl(ys));
-      zp[i] = zs;
+      __builtin_nontemporal_store(zs, &zp[i]);
       ab += todbl(ys) * todbl(zs);
       ac += todbl(zs) * r2v;
     }
