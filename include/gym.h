@@ -423,8 +423,9 @@ void gym_eig_opts_default(gym_eig_opts* opts);
  * then the solver runs on -P2, without the gradient shift, which the
  * largest pairs never meet).  vecs: NULL or a device array
  * of nev x ndofs doubles receiving the Q1^-1-orthonormal eigenvectors, one
- * after another.  Allocates its work space (device, about 16 block vectors)
- * per call and synchronises the stream.  Returns GYM_W_NOT_CONVERGED if the
+ * after another.  Allocates its work space (device, about 18 block vectors,
+ * and 16 small pinned host slots for its uploads) per call and synchronises
+ * the stream.  Returns GYM_W_NOT_CONVERGED if the
  * cap came first, or if a wanted pair is a gradient (grad_shift too small,
  * info->gradient_modes > 0); GYM_E_ARG for bad options; GYM_E_BREAKDOWN if
  * the search space lost rank (or a SPAI Q1 is not positive definite);
