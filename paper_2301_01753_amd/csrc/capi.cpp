@@ -421,11 +421,12 @@ int mfma_launch(const gym_op* op, int nrhs, const void* x, void* y, hipStream_t 
 }
 
 // Curved Hodge apply of degree 3 on the matrix cores, FP64 arithmetic with
-// FP64 or FP32 vectors.
+// FP64 or FP32 vectors (fewer than 2^31 unknowns: the kernel's z offsets are
+// 32-bit).
 bool hc_path(const gym_op* op, int prec) {
   const gym_mesh* m = op->mesh;
   return (prec == GYM_F64 || prec == GYM_F32) && op->problem != GYM_MIXED_POISSON && m->curved && m->dim == 3 &&
-         !m->periodic && op->r == kHcDegree && op->ctx->curved_kernel == 0;
+         !m->periodic && op->r == kHcDegree && op->ctx->curved_kernel == 0 && op->na + op->nb < (1LL << 31);
 }
 
 int hc_launch(const gym_op* op, int prec, int nrhs, const void* x, void* y, hipStream_t s) {

@@ -334,23 +334,31 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
     double iS[4], iX[4], iY[4], iZ[4];
     {
       // unconditional loads (a plane outside the kept set reads the zero
-      // slot), converted after all of them: a load under a branch with its
-      // conversion would be waited for on the spot
+      // slot), all issued before the first conversion (the scheduling
+      // barrier keeps them from being interleaved with their conversions
+      // field by field, each group waited for in turn); z offsets in 32 bits
+      // (operators of fewer than 2^31 unknowns), advanced by additions
       const TV* zero = static_cast<const TV*>(p.zero);
-      auto load = [&](int F, int nz, double(&v)[4]) {
-        TV raw[4];
+      TV raw[4][4];
+#pragma unroll
+      for (int F = 0; F < 4; ++F) {
+        const int nz = F == 3 ? 3 : 4;
+        unsigned o = (unsigned)zsl[F] * (unsigned)(R * ez);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int gz = R * ez + k;
-          raw[k] = *((k < nz && zkept(F, gz)) ? xcol[F] + (long long)zsl[F] * gz : zero);
+          raw[F][k] = *((k < nz && zkept(F, gz)) ? xcol[F] + o : zero);
+          o += (unsigned)zsl[F];
         }
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) v[k] = static_cast<double>(raw[k]);
-      };
-      load(0, 4, iS);
-      load(1, 4, iX);
-      load(2, 4, iY);
-      load(3, 3, iZ);
+      for (int k = 0; k < 4; ++k) {
+        iS[k] = static_cast<double>(raw[0][k]);
+        iX[k] = static_cast<double>(raw[1][k]);
+        iY[k] = static_cast<double>(raw[2][k]);
+        iZ[k] = static_cast<double>(raw[3][k]);
+      }
     }
 
     // ---- forward: x and y contractions on the matrix cores, all fields
@@ -624,10 +632,11 @@ __global__ void __launch_bounds__(TX * TY * 16, WPE) hodge_mfma_kernel(HcParams 
         dst = hxy + ((kSXY[F] * (p.tiles_x - 1) + tx) * (p.tiles_y - 1) + ty) * LZ;
         zs = 1;
       }
+      unsigned zo = (unsigned)zs * (unsigned)(R * ez);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int gz = R * ez + k;
-        if (k < nout) dst[(long long)zs * gz] = v[k];
+        if (k < nout) dst[zo] = v[k];
+        zo += (unsigned)zs;
       }
     };
     send(std::integral_constant<int, 0>{}, oS);
